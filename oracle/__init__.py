@@ -1,0 +1,206 @@
+"""ORACLE — test infrastructure only.
+
+A plain CPU statement of the seeding path (see ``oracle.c`` for the paper passages each function
+follows).  Only the tests, ``__graft_entry__.smoke()`` and the benchmark's ``cpu_baseline`` leg
+may import this package; the product library never does, and the two share no code.
+
+Two oracles:
+  * method 0 (O1): full suffix array by sorting; intervals, SMEMs and positions from their
+    definitions (Section 2.1).
+  * method 1 (O2): FM-index with Algorithm 1, serial Algorithm 3, Algorithm 2 LocateSlow over
+    a sampled SA; counts the index lines a given line layout would touch.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Opts(C.Structure):
+    _fields_ = [("min_len", C.c_int), ("min_occ", C.c_int), ("max_occ", C.c_int), ("reseed", C.c_int),
+                ("reseed_len", C.c_int), ("reseed_occ", C.c_int), ("bs_role", C.c_int),
+                ("method", C.c_int), ("kmer_k", C.c_int), ("bases_per_line", C.c_int)]
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    build()
+    L = C.CDLL(_LIB)
+    u64, i32, vp, u8 = C.c_uint64, C.c_int, C.c_void_p, C.c_uint8
+    L.orc_build.restype = vp
+    L.orc_build.argtypes = [vp, u64, i32, i32]
+    L.orc_free.argtypes = [vp]
+    for f in ("orc_n", "orc_primary"):
+        getattr(L, f).restype = u64
+        getattr(L, f).argtypes = [vp]
+    for f in ("orc_copy_text", "orc_copy_sa", "orc_copy_bwt", "orc_copy_c"):
+        getattr(L, f).argtypes = [vp, vp]
+    L.orc_interval_ascii.argtypes = [vp, vp, u64, vp]
+    L.orc_seed.restype = vp
+    L.orc_seed.argtypes = [vp, vp, vp, u64, C.POINTER(_Opts), i32]
+    L.orc_result_nseeds.restype = u64
+    L.orc_result_nseeds.argtypes = [vp]
+    L.orc_result_npos.restype = u64
+    L.orc_result_npos.argtypes = [vp]
+    L.orc_result_copy.argtypes = [vp] + [vp] * 10
+    L.orc_result_lines.argtypes = [vp, vp]
+    L.orc_result_free.argtypes = [vp]
+    L.orc_backward.argtypes = [vp, vp, u8]
+    L.orc_forward.argtypes = [vp, vp, u8]
+    L.orc_pi.restype = u64
+    L.orc_pi.argtypes = [vp, u8, u64]
+    L.orc_locate_slow.restype = u64
+    L.orc_locate_slow.argtypes = [vp, u64]
+    _lib = L
+    return L
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+# oracle symbol codes: $ = 0, A..T = 1..4
+SYM = {"$": 0, "A": 1, "C": 2, "G": 3, "T": 4}
+
+
+@dataclass
+class SeedResult:
+    """Seeds sorted by (read_id, qbeg, qend); positions of seed t are pos[pos_off[t] : pos_off[t] + npos[t]],
+    ascending.  flags bit 0: occurrence count above max_occ, so not located."""
+    read_id: np.ndarray
+    qbeg: np.ndarray
+    qend: np.ndarray
+    k: np.ndarray
+    kr: np.ndarray
+    s: np.ndarray
+    npos: np.ndarray
+    flags: np.ndarray
+    pos_off: np.ndarray
+    pos: np.ndarray
+    lines: dict = field(default_factory=dict)
+
+    def __len__(self):
+        return int(self.read_id.size)
+
+
+class OracleIndex:
+    """T = R . revcomp(R) . $ (or the four-copy bisulfite text) with its full SA, BWT and an
+    FM-index sampled every ``sa_rate`` rows."""
+
+    def __init__(self, ref_codes: np.ndarray, bisulfite: bool = False, sa_rate: int = 8):
+        L = _load()
+        self._ref = np.ascontiguousarray(ref_codes, dtype=np.uint8)
+        self.len_r = int(self._ref.size)
+        self.bisulfite = bool(bisulfite)
+        self.sa_rate = int(sa_rate)
+        self._h = L.orc_build(_p(self._ref), self.len_r, int(bisulfite), int(sa_rate))
+        self.n = int(L.orc_n(self._h))
+        self.primary = int(L.orc_primary(self._h))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.orc_free(h)
+            self._h = None
+
+    # raw structures (tests) -------------------------------------------------------------
+    def text(self) -> np.ndarray:
+        out = np.empty(self.n, np.uint8)
+        _lib.orc_copy_text(self._h, _p(out))
+        return out
+
+    def sa(self) -> np.ndarray:
+        out = np.empty(self.n, np.uint64)
+        _lib.orc_copy_sa(self._h, _p(out))
+        return out
+
+    def bwt(self) -> np.ndarray:
+        out = np.empty(self.n, np.uint8)
+        _lib.orc_copy_bwt(self._h, _p(out))
+        return out
+
+    def C(self) -> np.ndarray:
+        out = np.empty(6, np.uint64)
+        _lib.orc_copy_c(self._h, _p(out))
+        return out
+
+    def interval(self, pattern: str | bytes):
+        """ds-interval (lo(P), lo(revcomp P), occ(P)) of an ASCII pattern, by definition."""
+        b = pattern.encode() if isinstance(pattern, str) else bytes(pattern)
+        a = np.frombuffer(b, dtype=np.uint8).copy() if b else np.zeros(1, np.uint8)
+        out = np.zeros(3, np.uint64)
+        _lib.orc_interval_ascii(self._h, _p(a), len(b), _p(out))
+        return tuple(int(x) for x in out)
+
+    def backward(self, iv, a: int):
+        v = np.array(iv, dtype=np.uint64)
+        _lib.orc_backward(self._h, _p(v), int(a))
+        return tuple(int(x) for x in v)
+
+    def forward(self, iv, a: int):
+        v = np.array(iv, dtype=np.uint64)
+        _lib.orc_forward(self._h, _p(v), int(a))
+        return tuple(int(x) for x in v)
+
+    def pi(self, a: int, k: int) -> int:
+        return int(_lib.orc_pi(self._h, int(a), int(k)))
+
+    def locate_slow(self, k: int) -> int:
+        return int(_lib.orc_locate_slow(self._h, int(k)))
+
+    # seeding ------------------------------------------------------------------------------
+    def seed(self, seq: np.ndarray, offsets: np.ndarray, min_len: int = 19, min_occ: int = 1,
+             max_occ: int = 500, reseed: bool = True, reseed_len: int = 38, reseed_occ: int = 10,
+             bs_role: int = 0, method: int = 0, kmer_k: int = 0, bases_per_line: int = 0,
+             threads: int = 0) -> SeedResult:
+        seq = np.ascontiguousarray(seq, dtype=np.uint8)
+        if seq.size == 0:
+            seq = np.zeros(1, np.uint8)
+        offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+        nr = offsets.size - 1
+        o = _Opts(int(min_len), int(min_occ), int(max_occ), int(bool(reseed)), int(reseed_len),
+                  int(reseed_occ), int(bs_role), int(method), int(kmer_k), int(bases_per_line))
+        h = _lib.orc_seed(self._h, _p(seq), _p(offsets), nr, C.byref(o), int(threads))
+        try:
+            ns = int(_lib.orc_result_nseeds(h))
+            np_ = int(_lib.orc_result_npos(h))
+            a = dict(read_id=np.empty(ns, np.uint32), qbeg=np.empty(ns, np.uint32), qend=np.empty(ns, np.uint32),
+                     k=np.empty(ns, np.uint64), kr=np.empty(ns, np.uint64), s=np.empty(ns, np.uint64),
+                     npos=np.empty(ns, np.uint32), flags=np.empty(ns, np.uint32),
+                     pos_off=np.empty(ns, np.uint64), pos=np.empty(np_, np.uint64))
+            bufs = [a[x] if a[x].size else np.zeros(1, a[x].dtype) for x in
+                    ("read_id", "qbeg", "qend", "k", "kr", "s", "npos", "flags", "pos_off", "pos")]
+            _lib.orc_result_copy(h, *[_p(b) for b in bufs])
+            for name, b in zip(("read_id", "qbeg", "qend", "k", "kr", "s", "npos", "flags", "pos_off", "pos"), bufs):
+                a[name] = b[: a[name].size]
+            ln = np.zeros(5, np.uint64)
+            _lib.orc_result_lines(h, _p(ln))
+            lines = dict(lines=int(ln[0]), kmer_lookups=int(ln[1]), sa_reads=int(ln[2]), steps=int(ln[3]),
+                         lf_steps=int(ln[4]))
+        finally:
+            _lib.orc_result_free(h)
+        return SeedResult(lines=lines, **a)
+
+
+def seed_reads(index: OracleIndex, reads, **kw) -> SeedResult:
+    """Convenience: seed a ``synth.ReadSet``-like object (``seq``, ``offsets``)."""
+    return index.seed(reads.seq, reads.offsets, **kw)

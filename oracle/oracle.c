@@ -1,0 +1,545 @@
+/*
+ * ORACLE — test infrastructure only.
+ *
+ * A plain, slow CPU statement of what the seeding path computes, used to check the GPU library
+ * element by element.  Only the test-suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load this code; the product library never does.  It shares no code, header, table or
+ * helper with the GPU path.
+ *
+ * Paper: "Fast genomic read alignment with minibwa" (arXiv 2606.15357).
+ *
+ *   Definitions (Section 2.1):
+ *     T = R . revcomp(R) . $,  n = |T|, $ smaller than A<C<G<T            -> build_text()
+ *     S(i) = start of the i-th smallest suffix (suffix array)              -> sort_suffixes()
+ *     B[i] = T[S(i) - 1], with T[-1] = $                                   -> orc_build()
+ *     pi(a, k) = |{i : B[i] < a}| + |{i < k : B[i] = a}|                   -> fm_pi()
+ *     ds-interval (lo(P), lo(revcomp P), occ(P)), lo(P) = |{i : T[i,n) < P}|,
+ *       occ(P) = |{i : T[i, i+|P|) = P}|                                    -> def_interval()
+ *     (l,c)-match / (l,c)-SMEM (containment-maximal matches)              -> def_smems()
+ *   Algorithm 1 (BackwardExt / ForwardExt)                                 -> fm_backward(), fm_forward()
+ *   Algorithm 2 (LocateSlow over an SA sampled at multiples of r)          -> fm_locate_slow()
+ *   Algorithm 3 (BatchFindSMEM stages 1-3 with BackStep), one query at a time -> alg3_smems()
+ *   Section 2.6 (two seeding rounds: re-seed long, rare SMEMs)             -> seed_query()
+ *   Section 2.9 (bisulfite: 3-base index of C->T(R) . G->A(R), read conversion, strand filter)
+ *
+ * Two oracles live here:
+ *   O1 ("definition"): full suffix array by comparison sort; intervals by binary search over the
+ *       full SA; SMEMs from the definition via e(i) = max{ j : occ(P[i,j)) >= c }; positions read
+ *       straight from the full SA.
+ *   O2 ("paper algorithm"): an FM-index (one byte per BWT symbol, counts every 64 symbols) with
+ *       Algorithm 1, a serial Algorithm 3, and Algorithm 2's LocateSlow over a sampled SA.  It also
+ *       counts the index lines a given line layout would touch (the algorithmic traffic).
+ *
+ * Symbol coding inside the oracle: $ = 0, A = 1, C = 2, G = 3, T = 4; a read byte outside ACGT
+ * becomes 5, which equals no text symbol (so no match ever spans it).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <stdio.h>
+#include <omp.h>
+
+typedef struct {
+  uint64_t n;        /* |T| */
+  uint64_t len_r;    /* |R| of the original reference */
+  int bisulfite;     /* 1: T built from C->T(R) . G->A(R) */
+  uint8_t *T;        /* n symbols, T[n-1] = $ */
+  uint64_t *SA;      /* full suffix array (O1) */
+  uint8_t *B;        /* BWT */
+  uint64_t C[6];     /* C[a] = |{i : B[i] < a}| */
+  uint64_t primary;  /* the row whose BWT symbol is $ (S(primary) = 0) */
+  uint64_t *occ64;   /* O2: occ64[5*(x/64) + a] = |{i < 64*(x/64) : B[i] = a}| */
+  int r;             /* O2: SA sampling rate */
+  uint64_t *ssa;     /* O2: ssa[x/r] = S(x) for x % r == 0 */
+} orc_index;
+
+/* ------------------------------------------------------------------------------------------ */
+/* T = R . revcomp(R) . $   (Section 2.1).  In bisulfite mode R is first replaced by
+ * C->T(R) . G->A(R)  (Section 2.9), so T holds the four converted copies.                    */
+static uint8_t *build_text(const uint8_t *R, uint64_t len_r, int bisulfite, uint64_t *n_out) {
+  uint64_t lr = bisulfite ? 2 * len_r : len_r;
+  uint64_t n = 2 * lr + 1;
+  uint8_t *T = (uint8_t *)malloc(n);
+  for (uint64_t i = 0; i < len_r; ++i) {
+    uint8_t a = (uint8_t)(R[i] + 1);                 /* 0..3 -> A..T = 1..4 */
+    if (bisulfite) {
+      T[i] = a == 2 ? 4 : a;                          /* C -> T */
+      T[len_r + i] = a == 3 ? 1 : a;                  /* G -> A */
+    } else {
+      T[i] = a;
+    }
+  }
+  for (uint64_t i = 0; i < lr; ++i) T[lr + i] = (uint8_t)(5 - T[lr - 1 - i]); /* complement: A<->T, C<->G */
+  T[n - 1] = 0;
+  *n_out = n;
+  return T;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Suffix array by sorting (definition of S in Section 2.1): positions ordered by the suffix
+ * T[i,n).  Suffixes are first bucketed by their first 8 symbols (base-5 digits, $ = 0, padding
+ * after $ = 0: distinct suffixes that reach $ inside the window get distinct keys because $
+ * occurs once), buckets are visited in key order, and each bucket is sorted by direct suffix
+ * comparison.  memcmp never returns 0 for i != j since $ is unique and smallest.               */
+static const uint8_t *g_T;
+static uint64_t g_n;
+static int cmp_suffix(const void *pa, const void *pb) {
+  uint64_t i = *(const uint64_t *)pa, j = *(const uint64_t *)pb;
+  uint64_t li = g_n - i, lj = g_n - j;
+  int c = memcmp(g_T + i, g_T + j, li < lj ? li : lj);
+  return c < 0 ? -1 : c > 0 ? 1 : (li < lj ? -1 : 1);
+}
+#define BK 8
+static uint32_t bucket_key(const uint8_t *T, uint64_t n, uint64_t i) {
+  uint32_t k = 0;
+  for (int t = 0; t < BK; ++t) k = k * 5 + (i + t < n ? T[i + t] : 0);
+  return k;
+}
+static uint64_t *sort_suffixes(const uint8_t *T, uint64_t n) {
+  uint64_t nb = 390625; /* 5^8 */
+  uint64_t *cnt = (uint64_t *)calloc(nb + 1, sizeof(uint64_t));
+  uint32_t *key = (uint32_t *)malloc(n * sizeof(uint32_t));
+  #pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < (int64_t)n; ++i) key[i] = bucket_key(T, n, (uint64_t)i);
+  for (uint64_t i = 0; i < n; ++i) cnt[key[i] + 1]++;
+  for (uint64_t b = 0; b < nb; ++b) cnt[b + 1] += cnt[b];
+  uint64_t *SA = (uint64_t *)malloc(n * sizeof(uint64_t));
+  uint64_t *fill = (uint64_t *)malloc(nb * sizeof(uint64_t));
+  memcpy(fill, cnt, nb * sizeof(uint64_t));
+  for (uint64_t i = 0; i < n; ++i) SA[fill[key[i]]++] = i;
+  free(fill); free(key);
+  g_T = T; g_n = n;
+  #pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t b = 0; b < (int64_t)nb; ++b) {
+    uint64_t lo = cnt[b], hi = cnt[b + 1];
+    if (hi - lo > 1) qsort(SA + lo, hi - lo, sizeof(uint64_t), cmp_suffix);
+  }
+  free(cnt);
+  return SA;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+orc_index *orc_build(const uint8_t *R, uint64_t len_r, int bisulfite, int sa_rate) {
+  orc_index *ix = (orc_index *)calloc(1, sizeof(orc_index));
+  ix->len_r = len_r; ix->bisulfite = bisulfite; ix->r = sa_rate > 0 ? sa_rate : 1;
+  ix->T = build_text(R, len_r, bisulfite, &ix->n);
+  uint64_t n = ix->n;
+  ix->SA = sort_suffixes(ix->T, n);
+  ix->B = (uint8_t *)malloc(n);
+  for (uint64_t x = 0; x < n; ++x) {                 /* B[x] = T[S(x) - 1], T[-1] = $ */
+    uint64_t s = ix->SA[x];
+    ix->B[x] = s ? ix->T[s - 1] : 0;
+    if (!s) ix->primary = x;
+  }
+  uint64_t tot[6] = {0};
+  for (uint64_t x = 0; x < n; ++x) tot[ix->B[x]]++;
+  ix->C[0] = 0;
+  for (int a = 1; a < 6; ++a) ix->C[a] = ix->C[a - 1] + tot[a - 1];
+  /* O2 structures: counts every 64 rows and the SA sampled at multiples of r */
+  uint64_t nblk = n / 64 + 2;
+  ix->occ64 = (uint64_t *)calloc(nblk * 5, sizeof(uint64_t));
+  uint64_t run[5] = {0};
+  for (uint64_t x = 0; x <= n; ++x) {
+    if (x % 64 == 0) memcpy(ix->occ64 + 5 * (x / 64), run, sizeof(run));
+    if (x < n) run[ix->B[x]]++;
+  }
+  uint64_t ns = (n + ix->r - 1) / ix->r;
+  ix->ssa = (uint64_t *)malloc(ns * sizeof(uint64_t));
+  for (uint64_t x = 0; x < n; x += ix->r) ix->ssa[x / ix->r] = ix->SA[x];
+  return ix;
+}
+
+void orc_free(orc_index *ix) {
+  if (!ix) return;
+  free(ix->T); free(ix->SA); free(ix->B); free(ix->occ64); free(ix->ssa); free(ix);
+}
+
+uint64_t orc_n(const orc_index *ix) { return ix->n; }
+uint64_t orc_primary(const orc_index *ix) { return ix->primary; }
+void orc_copy_text(const orc_index *ix, uint8_t *out) { memcpy(out, ix->T, ix->n); }
+void orc_copy_sa(const orc_index *ix, uint64_t *out) { memcpy(out, ix->SA, ix->n * 8); }
+void orc_copy_bwt(const orc_index *ix, uint8_t *out) { memcpy(out, ix->B, ix->n); }
+void orc_copy_c(const orc_index *ix, uint64_t *out) { memcpy(out, ix->C, sizeof(ix->C)); }
+
+/* ------------------------------------------------------------------------------------------ */
+/* O1: ds-interval by its definition (Section 2.1) using binary search over the full SA.       */
+
+/* compare suffix T[i,n) with pattern P[0,m) over the first m symbols:
+ * <0 if T[i,n) < P with a difference in the first m symbols (or $ reached), 0 if P is a prefix
+ * of T[i,n), >0 otherwise. */
+static int cmp_prefix(const orc_index *ix, uint64_t i, const uint8_t *P, uint64_t m) {
+  for (uint64_t t = 0; t < m; ++t) {
+    uint8_t a = ix->T[i + t], b = P[t];   /* T[n-1] = $ = 0 < b, so i+t never passes n-1 */
+    if (a != b) return a < b ? -1 : 1;
+  }
+  return 0;
+}
+/* first SA row whose suffix is >= P (strict=0) or > every suffix having prefix P (strict=1) */
+static uint64_t sa_bound(const orc_index *ix, const uint8_t *P, uint64_t m, int strict) {
+  uint64_t lo = 0, hi = ix->n;
+  while (lo < hi) {
+    uint64_t mid = lo + (hi - lo) / 2;
+    int c = cmp_prefix(ix, ix->SA[mid], P, m);
+    if (c < 0 || (strict && c == 0)) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+static void revcomp_sym(const uint8_t *P, uint64_t m, uint8_t *out) {
+  for (uint64_t t = 0; t < m; ++t) { uint8_t a = P[m - 1 - t]; out[t] = a >= 1 && a <= 4 ? (uint8_t)(5 - a) : a; }
+}
+/* (lo(P), lo(revcomp P), occ(P)) */
+static void def_interval(const orc_index *ix, const uint8_t *P, uint64_t m, uint64_t out[3]) {
+  uint8_t *Q = (uint8_t *)malloc(m + 1);
+  revcomp_sym(P, m, Q);
+  uint64_t a = sa_bound(ix, P, m, 0), b = sa_bound(ix, P, m, 1);
+  out[0] = a; out[1] = sa_bound(ix, Q, m, 0); out[2] = b - a;
+  free(Q);
+}
+
+/* exported: interval of an ASCII pattern (for tests) */
+static uint8_t enc_ascii(uint8_t ch) {
+  switch (ch) { case 'A': case 'a': return 1; case 'C': case 'c': return 2; case 'G': case 'g': return 3;
+                case 'T': case 't': return 4; default: return 5; }
+}
+void orc_interval_ascii(const orc_index *ix, const uint8_t *p, uint64_t m, uint64_t out[3]) {
+  uint8_t *P = (uint8_t *)malloc(m + 1);
+  for (uint64_t t = 0; t < m; ++t) P[t] = enc_ascii(p[t]);
+  def_interval(ix, P, m, out);
+  free(P);
+}
+
+/* Given the SA range [lo,hi) of P[0,len), narrow it to P[0,len+1) (all suffixes in the range
+ * share the prefix, so only the symbol at offset len is compared). */
+static void narrow(const orc_index *ix, uint64_t *lo, uint64_t *hi, uint64_t len, uint8_t b) {
+  uint64_t a = *lo, z = *hi;
+  while (a < z) { uint64_t mid = a + (z - a) / 2; if (ix->T[ix->SA[mid] + len] < b) a = mid + 1; else z = mid; }
+  uint64_t L = a; z = *hi;
+  while (a < z) { uint64_t mid = a + (z - a) / 2; if (ix->T[ix->SA[mid] + len] <= b) a = mid + 1; else z = mid; }
+  *lo = L; *hi = a;
+}
+
+typedef struct { uint32_t qbeg, qend; uint64_t k, kr, s; } smem_t;
+typedef struct { smem_t *v; uint64_t n, cap; } smem_vec;
+static void push_smem(smem_vec *V, smem_t x) {
+  if (V->n == V->cap) { V->cap = V->cap ? 2 * V->cap : 16; V->v = (smem_t *)realloc(V->v, V->cap * sizeof(smem_t)); }
+  V->v[V->n++] = x;
+}
+
+/* (l,c)-SMEMs of P[0,m) from the definition (Section 2.1): with e(i) = max{ j >= i :
+ * occ(P[i,j)) >= c } (occ of the empty string is n), the SMEMs are exactly the intervals
+ * [i, e(i)) with e(i) - i >= l and (i == 0 or e(i-1) < e(i)).  Coordinates are shifted by `base`. */
+static void def_smems(const orc_index *ix, const uint8_t *P, uint64_t m, int l, uint64_t c, uint32_t base, smem_vec *out) {
+  uint64_t eprev = 0;
+  for (uint64_t i = 0; i < m; ++i) {
+    uint64_t j = i > 0 && eprev > i ? eprev : i;
+    uint64_t lo, hi;
+    if (j > i) { lo = sa_bound(ix, P + i, j - i, 0); hi = sa_bound(ix, P + i, j - i, 1); }
+    else { lo = 0; hi = ix->n; }
+    if (hi - lo < c) { eprev = j; continue; } /* only when c > n */
+    while (j < m) {
+      uint64_t a = lo, z = hi;
+      narrow(ix, &a, &z, j - i, P[j]);
+      if (z - a < c) break;
+      lo = a; hi = z; ++j;
+    }
+    if ((i == 0 || eprev < j) && j - i >= (uint64_t)l) {
+      uint64_t iv[3];
+      def_interval(ix, P + i, j - i, iv);
+      smem_t s = {(uint32_t)(base + i), (uint32_t)(base + j), iv[0], iv[1], iv[2]};
+      push_smem(out, s);
+    }
+    eprev = j;
+  }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* O2: FM-index primitives and Algorithm 1.                                                    */
+
+typedef struct {             /* algorithmic line counting for a given index line layout */
+  uint64_t bases_per_line;   /* rows of B covered by one index line (0 = do not count) */
+  uint64_t lines;            /* extension + LF lines touched */
+  uint64_t kmer_lookups;     /* one line each */
+  uint64_t sa_reads;         /* one SA-sample read each */
+  uint64_t steps;            /* extension steps (Algorithm 1 calls) */
+  uint64_t lf_steps;         /* LF steps in locate */
+} line_ctr;
+
+/* Occ(a, k) = |{i < k : B[i] = a}| from the 64-row checkpoints and a scan of B. */
+static inline uint64_t fm_occ(const orc_index *ix, uint8_t a, uint64_t k) {
+  uint64_t v = ix->occ64[5 * (k / 64) + a];
+  for (uint64_t x = k & ~63ull; x < k; ++x) v += ix->B[x] == a;
+  return v;
+}
+/* pi(a, k) = |{i : B[i] < a}| + |{i < k : B[i] = a}|  (Section 2.1) */
+static inline uint64_t fm_pi(const orc_index *ix, uint8_t a, uint64_t k) { return ix->C[a] + fm_occ(ix, a, k); }
+
+static inline void count_step(line_ctr *lc, uint64_t x1, uint64_t x2) {
+  if (!lc) return;
+  lc->steps++;
+  if (!lc->bases_per_line) return;
+  lc->lines += (x1 / lc->bases_per_line == x2 / lc->bases_per_line) ? 1 : 2;
+}
+
+/* Algorithm 1, BackwardExt: ds-interval of aP from that of P.  Symbols b range over $ and the
+ * bases smaller than the complement of a; comp($) = $. */
+static void fm_backward(const orc_index *ix, uint64_t iv[3], uint8_t a, line_ctr *lc) {
+  uint64_t k = iv[0], kr = iv[1], s = iv[2];
+  if (a < 1 || a > 4) { iv[0] = 0; iv[1] = 0; iv[2] = 0; return; } /* a read symbol that matches nothing */
+  count_step(lc, k, k + s);
+  uint8_t abar = (uint8_t)(5 - a);
+  for (uint8_t b = 0; b < abar; ++b) {               /* b = $, A, ... (b < comp(a)) */
+    uint8_t bbar = b == 0 ? 0 : (uint8_t)(5 - b);
+    kr += fm_pi(ix, bbar, k + s) - fm_pi(ix, bbar, k);
+  }
+  uint64_t lo = fm_pi(ix, a, k);
+  s = fm_pi(ix, a, k + s) - lo;
+  iv[0] = lo; iv[1] = kr; iv[2] = s;
+}
+/* Algorithm 1, ForwardExt: ds-interval of Pa = BackwardExt on the swapped interval with comp(a). */
+static void fm_forward(const orc_index *ix, uint64_t iv[3], uint8_t a, line_ctr *lc) {
+  uint64_t sw[3] = {iv[1], iv[0], iv[2]};
+  uint8_t abar = a >= 1 && a <= 4 ? (uint8_t)(5 - a) : a;
+  fm_backward(ix, sw, abar, lc);
+  iv[0] = sw[1]; iv[1] = sw[0]; iv[2] = sw[2];
+}
+
+/* Optional k-mer shortcut (Section 2.5: the ds-intervals of all k-mers are precomputed so that
+ * the first k single steps of a backward run are replaced by one lookup).  The oracle computes
+ * the looked-up value with k BackwardExt calls but counts one line for it.  When the k-mer's
+ * occurrence count is below c the run falls back to single steps from the start, so the result
+ * never depends on the shortcut. */
+
+/* ------------------------------------------------------------------------------------------ */
+/* Algorithm 3 for one query string P[0,m).  The batched queue of the paper interleaves many
+ * queries; records of one query are processed in order, so running the queue for one query at
+ * a time yields the same SMEMs.  Records are (stage u, i, j, interval). */
+static void alg3_smems(const orc_index *ix, const uint8_t *P, uint64_t m, int l, uint64_t c, int kmer_k,
+                       uint32_t base, smem_vec *out, line_ctr *lc) {
+  if (!((uint64_t)(l - 1) < m)) return;              /* Alg. 3 initialisation: needs l-1 < |P| */
+  int u = 1;
+  int64_t i = 0, j = l - 1;
+  uint64_t iv[3] = {0, 0, ix->n};
+  int fresh = 1;                                      /* interval is the initial (0,0,|B|) */
+  for (;;) {
+    if (u == 1 || u == 3) {
+      if (u == 1 && j < i) { u = 2; j = i + l; fresh = 0; continue; }           /* stage 1 -> 2 */
+      if (u == 3 && j <= i) { u = 1; i = j + 1; j = j + l; iv[0] = 0; iv[1] = 0; iv[2] = ix->n; fresh = 1; continue; }
+      /* k-mer shortcut at the start of a backward run */
+      if (fresh && kmer_k > 0 && j - kmer_k + 1 >= (u == 1 ? i : i + 1)) {
+        uint64_t t[3] = {0, 0, ix->n};
+        for (int q = 0; q < kmer_k; ++q) fm_backward(ix, t, P[j - q], NULL);
+        if (lc) lc->kmer_lookups++;
+        if (t[2] >= c) { iv[0] = t[0]; iv[1] = t[1]; iv[2] = t[2]; j -= kmer_k; fresh = 0; continue; }
+      }
+      fresh = 0;
+      /* BackStep */
+      uint64_t nv[3] = {iv[0], iv[1], iv[2]};
+      fm_backward(ix, nv, P[j], lc);
+      if (nv[2] >= c) { iv[0] = nv[0]; iv[1] = nv[1]; iv[2] = nv[2]; j -= 1; continue; }
+      if ((uint64_t)(j + l) < m) { u = 1; i = j + 1; j = j + l; iv[0] = 0; iv[1] = 0; iv[2] = ix->n; fresh = 1; continue; }
+      return;
+    }
+    /* stage 2: forward extension to the SMEM end */
+    if ((uint64_t)j == m) {
+      smem_t s = {(uint32_t)(base + i), (uint32_t)(base + j), iv[0], iv[1], iv[2]};
+      push_smem(out, s);
+      return;
+    }
+    uint64_t nv[3] = {iv[0], iv[1], iv[2]};
+    fm_forward(ix, nv, P[j], lc);
+    if (nv[2] >= c) { iv[0] = nv[0]; iv[1] = nv[1]; iv[2] = nv[2]; j += 1; continue; }
+    smem_t s = {(uint32_t)(base + i), (uint32_t)(base + j), iv[0], iv[1], iv[2]};
+    push_smem(out, s);
+    u = 3; iv[0] = 0; iv[1] = 0; iv[2] = ix->n; fresh = 1;   /* j stays: the mismatching symbol */
+  }
+}
+
+/* Algorithm 2, LocateSlow for one row k: LF-walk until the row is a multiple of r, then add the
+ * number of steps to the sampled value.  LF of the $ row goes to row 0 (pi($, k) = 0), whose
+ * suffix starts at n-1, so the sum is taken mod n. */
+static uint64_t fm_locate_slow(const orc_index *ix, uint64_t k, line_ctr *lc) {
+  uint64_t i = 0;
+  while (k % ix->r != 0) {
+    if (lc) { lc->lf_steps++; if (lc->bases_per_line) lc->lines++; }
+    uint8_t b = ix->B[k];
+    k = fm_pi(ix, b, k);
+    ++i;
+  }
+  if (lc) lc->sa_reads++;
+  return (i + ix->ssa[k / ix->r]) % ix->n;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Seeding of one query (Section 2.6): round 1 = (l,c)-SMEMs; round 2: for every round-1 SMEM
+ * [i,j) with j-i >= reseed_len and occurrence s <= reseed_occ, the (floor((j-i)/2), s+1)-SMEMs of
+ * P[i,j).  Union with duplicates (same [qbeg,qend)) removed; sorted by (qbeg, qend). */
+typedef struct {
+  int min_len;         /* l */
+  int min_occ;         /* c */
+  int max_occ;         /* locate only seeds with s <= max_occ */
+  int reseed;          /* run round 2 */
+  int reseed_len;      /* 38 */
+  int reseed_occ;      /* 10 */
+  int bs_role;         /* 0 plain, 1 read-1 (C->T), 2 read-2 (G->A) */
+  int method;          /* 0 = O1 definition, 1 = O2 Algorithm 3 */
+  int kmer_k;          /* O2 only */
+  int bases_per_line;  /* O2 line counting, 0 = off */
+} orc_opts;
+
+static int cmp_smem(const void *a, const void *b) {
+  const smem_t *x = (const smem_t *)a, *y = (const smem_t *)b;
+  if (x->qbeg != y->qbeg) return x->qbeg < y->qbeg ? -1 : 1;
+  if (x->qend != y->qend) return x->qend < y->qend ? -1 : 1;
+  return 0;
+}
+static void find_smems(const orc_index *ix, const uint8_t *P, uint64_t m, int l, uint64_t c, const orc_opts *o,
+                       uint32_t base, smem_vec *out, line_ctr *lc) {
+  if (o->method == 0) def_smems(ix, P, m, l, c, base, out);
+  else alg3_smems(ix, P, m, l, c, o->kmer_k, base, out, lc);
+}
+static void seed_query(const orc_index *ix, const uint8_t *P, uint64_t m, const orc_opts *o, smem_vec *out, line_ctr *lc) {
+  out->n = 0;
+  find_smems(ix, P, m, o->min_len, (uint64_t)o->min_occ, o, 0, out, lc);
+  if (o->reseed) {
+    uint64_t n1 = out->n;
+    for (uint64_t t = 0; t < n1; ++t) {
+      smem_t s = out->v[t];
+      if (s.qend - s.qbeg >= (uint32_t)o->reseed_len && s.s <= (uint64_t)o->reseed_occ)
+        find_smems(ix, P + s.qbeg, s.qend - s.qbeg, (int)((s.qend - s.qbeg) / 2), s.s + 1, o, s.qbeg, out, lc);
+    }
+  }
+  qsort(out->v, out->n, sizeof(smem_t), cmp_smem);
+  uint64_t w = 0;
+  for (uint64_t t = 0; t < out->n; ++t)
+    if (w == 0 || cmp_smem(&out->v[w - 1], &out->v[t]) != 0) out->v[w++] = out->v[t];
+  out->n = w;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Batch driver: reads are ASCII, CSR (offsets[n_reads+1]).  Results are returned in a handle:
+ * seeds sorted by (read, qbeg, qend), each seed's positions ascending.                        */
+typedef struct {
+  uint64_t n_seeds, n_pos;
+  uint32_t *read_id, *qbeg, *qend, *npos, *flags;
+  uint64_t *k, *kr, *s, *pos_off, *pos;
+  line_ctr lines;
+} orc_result;
+
+static int cmp_u64(const void *a, const void *b) {
+  uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+  return x < y ? -1 : x > y;
+}
+
+/* segment of T (bisulfite index): 0 fwd C->T, 1 fwd G->A, 2 rev G->A, 3 rev C->T (Section 2.9) */
+static inline int bs_keep(const orc_index *ix, int role, uint64_t pos) {
+  uint64_t seg = pos / ix->len_r;
+  if (role == 1) return seg == 0 || seg == 2;
+  if (role == 2) return seg == 1 || seg == 3;
+  return 1;
+}
+
+orc_result *orc_seed(const orc_index *ix, const uint8_t *reads, const uint64_t *offsets, uint64_t n_reads,
+                     const orc_opts *o, int n_threads) {
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+  int nt = omp_get_max_threads();
+  smem_vec *per = (smem_vec *)calloc(n_reads, sizeof(smem_vec));
+  uint64_t **ppos = (uint64_t **)calloc(n_reads, sizeof(uint64_t *));   /* kept positions, seed by seed */
+  uint32_t **pcnt = (uint32_t **)calloc(n_reads, sizeof(uint32_t *));   /* kept count per seed */
+  line_ctr *tl = (line_ctr *)calloc((size_t)nt, sizeof(line_ctr));
+  #pragma omp parallel
+  {
+    int tid = omp_get_thread_num();
+    line_ctr *lc = &tl[tid];
+    lc->bases_per_line = (uint64_t)(o->bases_per_line > 0 ? o->bases_per_line : 0);
+    uint8_t *P = NULL; uint64_t pcap = 0;
+    #pragma omp for schedule(dynamic, 16)
+    for (int64_t r = 0; r < (int64_t)n_reads; ++r) {
+      uint64_t b = offsets[r], m = offsets[r + 1] - b;
+      if (pcap < m + 1) { free(P); pcap = m + 1; P = (uint8_t *)malloc(pcap); }
+      for (uint64_t t = 0; t < m; ++t) {
+        uint8_t a = enc_ascii(reads[b + t]);
+        if (o->bs_role == 1 && a == 2) a = 4;          /* read 1: C -> T */
+        if (o->bs_role == 2 && a == 3) a = 1;          /* read 2: G -> A */
+        P[t] = a;
+      }
+      seed_query(ix, P, m, o, &per[r], o->method == 1 ? lc : NULL);
+      uint64_t tot = 0;
+      for (uint64_t q = 0; q < per[r].n; ++q) if (per[r].v[q].s <= (uint64_t)o->max_occ) tot += per[r].v[q].s;
+      uint64_t *pp = (uint64_t *)malloc((tot ? tot : 1) * sizeof(uint64_t));
+      uint32_t *pc = (uint32_t *)calloc(per[r].n + 1, sizeof(uint32_t));
+      uint64_t w = 0;
+      for (uint64_t q = 0; q < per[r].n; ++q) {
+        smem_t *s = &per[r].v[q];
+        if (s->s > (uint64_t)o->max_occ) continue;
+        uint64_t w0 = w;
+        for (uint64_t x = s->k; x < s->k + s->s; ++x) {
+          uint64_t p = o->method == 0 ? ix->SA[x] : fm_locate_slow(ix, x, lc);
+          if (bs_keep(ix, o->bs_role, p)) pp[w++] = p;
+        }
+        qsort(pp + w0, w - w0, sizeof(uint64_t), cmp_u64);
+        pc[q] = (uint32_t)(w - w0);
+      }
+      ppos[r] = pp; pcnt[r] = pc;
+    }
+    free(P);
+  }
+  orc_result *res = (orc_result *)calloc(1, sizeof(orc_result));
+  uint64_t ns = 0, np = 0;
+  for (uint64_t r = 0; r < n_reads; ++r) { ns += per[r].n; for (uint64_t q = 0; q < per[r].n; ++q) np += pcnt[r][q]; }
+  res->n_seeds = ns; res->n_pos = np;
+  res->read_id = (uint32_t *)malloc((ns + 1) * 4); res->qbeg = (uint32_t *)malloc((ns + 1) * 4);
+  res->qend = (uint32_t *)malloc((ns + 1) * 4); res->npos = (uint32_t *)malloc((ns + 1) * 4);
+  res->flags = (uint32_t *)malloc((ns + 1) * 4);
+  res->k = (uint64_t *)malloc((ns + 1) * 8); res->kr = (uint64_t *)malloc((ns + 1) * 8);
+  res->s = (uint64_t *)malloc((ns + 1) * 8); res->pos_off = (uint64_t *)malloc((ns + 1) * 8);
+  res->pos = (uint64_t *)malloc((np + 1) * 8);
+  uint64_t si = 0, pw = 0;
+  for (uint64_t r = 0; r < n_reads; ++r) {
+    uint64_t rp = 0;
+    for (uint64_t q = 0; q < per[r].n; ++q) {
+      smem_t *s = &per[r].v[q];
+      res->read_id[si] = (uint32_t)r; res->qbeg[si] = s->qbeg; res->qend[si] = s->qend;
+      res->k[si] = s->k; res->kr[si] = s->kr; res->s[si] = s->s;
+      res->pos_off[si] = pw;
+      res->flags[si] = s->s > (uint64_t)o->max_occ ? 1u : 0u;   /* 1: not located (occurrence above max_occ) */
+      res->npos[si] = pcnt[r][q];
+      memcpy(res->pos + pw, ppos[r] + rp, (uint64_t)pcnt[r][q] * 8);
+      rp += pcnt[r][q]; pw += pcnt[r][q];
+      ++si;
+    }
+    free(per[r].v); free(ppos[r]); free(pcnt[r]);
+  }
+  for (int t = 0; t < nt; ++t) {
+    res->lines.lines += tl[t].lines; res->lines.kmer_lookups += tl[t].kmer_lookups;
+    res->lines.sa_reads += tl[t].sa_reads; res->lines.steps += tl[t].steps; res->lines.lf_steps += tl[t].lf_steps;
+  }
+  res->lines.bases_per_line = (uint64_t)o->bases_per_line;
+  free(per); free(ppos); free(pcnt); free(tl);
+  return res;
+}
+
+uint64_t orc_result_nseeds(const orc_result *r) { return r->n_seeds; }
+uint64_t orc_result_npos(const orc_result *r) { return r->n_pos; }
+void orc_result_copy(const orc_result *r, uint32_t *read_id, uint32_t *qbeg, uint32_t *qend, uint64_t *k,
+                     uint64_t *kr, uint64_t *s, uint32_t *npos, uint32_t *flags, uint64_t *pos_off, uint64_t *pos) {
+  uint64_t n = r->n_seeds;
+  memcpy(read_id, r->read_id, n * 4); memcpy(qbeg, r->qbeg, n * 4); memcpy(qend, r->qend, n * 4);
+  memcpy(k, r->k, n * 8); memcpy(kr, r->kr, n * 8); memcpy(s, r->s, n * 8);
+  memcpy(npos, r->npos, n * 4); memcpy(flags, r->flags, n * 4); memcpy(pos_off, r->pos_off, n * 8);
+  memcpy(pos, r->pos, r->n_pos * 8);
+}
+void orc_result_lines(const orc_result *r, uint64_t out[5]) {
+  out[0] = r->lines.lines; out[1] = r->lines.kmer_lookups; out[2] = r->lines.sa_reads;
+  out[3] = r->lines.steps; out[4] = r->lines.lf_steps;
+}
+void orc_result_free(orc_result *r) {
+  if (!r) return;
+  free(r->read_id); free(r->qbeg); free(r->qend); free(r->npos); free(r->flags);
+  free(r->k); free(r->kr); free(r->s); free(r->pos_off); free(r->pos); free(r);
+}
+
+/* Exported single-step primitives for tests (O2 Algorithm 1 on raw intervals). */
+void orc_backward(const orc_index *ix, uint64_t iv[3], uint8_t a) { fm_backward(ix, iv, a, NULL); }
+void orc_forward(const orc_index *ix, uint64_t iv[3], uint8_t a) { fm_forward(ix, iv, a, NULL); }
+uint64_t orc_pi(const orc_index *ix, uint8_t a, uint64_t k) { return fm_pi(ix, a, k); }
+uint64_t orc_locate_slow(const orc_index *ix, uint64_t k) { return fm_locate_slow(ix, k, NULL); }
