@@ -1,0 +1,172 @@
+/*
+ * mbw — batched (l,c)-SMEM seeding with sampled-SA locate on one MI355X (gfx950) GPU.
+ *
+ * Plain C ABI: opaque handles, plain pointers and sizes, integer status codes.  No call throws
+ * or aborts; every entry point returns MBW_OK (0) or a negative MBW_E_* code, and
+ * mbw_last_error() gives a message for the calling thread's last failure.
+ *
+ * Paper: "Fast genomic read alignment with minibwa" (arXiv 2606.15357).  Notation follows its
+ * Section 2.1: R is the reference, T = R . revcomp(R) . $ with n = |T|, S the suffix array,
+ * B the BWT, pi(a,k) the LF-mapping, and (k, k', s) = (lo(P), lo(revcomp P), occ(P)) the
+ * double-strand SA interval ("ds-interval") of a string P.
+ */
+#ifndef MBW_H
+#define MBW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------------------ */
+#define MBW_OK          0
+#define MBW_E_INVAL    -1   /* bad argument (sizes, ranges, NULL handle)                          */
+#define MBW_E_NOMEM    -2   /* device or host allocation failed                                   */
+#define MBW_E_HIP      -3   /* a HIP runtime call failed (message names it)                       */
+#define MBW_E_IO       -4   /* file could not be opened, read or written                          */
+#define MBW_E_FORMAT   -5   /* index file has a bad magic, version, size or checksum              */
+#define MBW_E_CAPACITY -6   /* a caller-provided buffer is too small (required sizes reported)     */
+
+const char *mbw_strerror(int code);
+/* Message of the calling thread's last failed call ("" if none).  Valid until the next call. */
+const char *mbw_last_error(void);
+
+/* ---- index -------------------------------------------------------------------------------- */
+typedef struct mbw_index mbw_index;
+
+typedef struct {
+  int sa_sample;        /* r: S(x) is kept for rows x that are multiples of r (Section 2.4);
+                           1 <= r <= 1024.  Locate walks take about r-1 LF steps on average.     */
+  int kmer_k;           /* k-mer ds-interval table (Section 2.5 precomputes all 10-mers):
+                           0 = no table, else 1..13 (4^k entries of 16 bytes).                   */
+  int bisulfite;        /* 0: T = R . revcomp(R) . $.  1: four-copy 3-base text over
+                           C->T(R) . G->A(R) and its reverse complement (Section 2.9).           */
+  int ref_is_codes;     /* 1: ref holds codes 0..3 (A,C,G,T); 0: ASCII (case-insensitive)      */
+  uint64_t rng_seed;    /* ambiguous (non-ACGT) reference bases become random bases drawn from
+                           SplitMix64 seeded with this value (Section 2.1)                       */
+  int device;           /* HIP device ordinal that will hold the index                          */
+} mbw_build_opts;
+
+/* Build the index of `ref` (host pointer, `len` bases, 1 <= len < 2^38) on the GPU and keep it
+ * resident in that device's HBM.  Builds T, sorts its suffixes on the GPU, derives B, the
+ * occurrence lines (Section 2.2), the sampled SA (Section 2.4) and the optional k-mer table.
+ * The caller keeps ownership of `ref`; *out is owned by the caller and released with
+ * mbw_index_free.  Blocking.  Errors: MBW_E_INVAL (len, options), MBW_E_NOMEM, MBW_E_HIP.      */
+int mbw_index_build(const uint8_t *ref, uint64_t len, const mbw_build_opts *opts, mbw_index **out);
+
+/* Write the resident index to `path` (versioned header + checksummed arrays).  Blocking. */
+int mbw_index_save(const mbw_index *idx, const char *path);
+
+/* Read an index file written by mbw_index_save and make it resident on `device`.
+ * Errors: MBW_E_IO, MBW_E_FORMAT (magic, version, sizes or checksum), MBW_E_NOMEM, MBW_E_HIP. */
+int mbw_index_load(const char *path, int device, mbw_index **out);
+
+void mbw_index_free(mbw_index *idx);
+
+typedef struct {
+  uint64_t n;              /* |T| */
+  uint64_t len_r;          /* |R| (original reference length) */
+  uint64_t primary;        /* the row x with S(x) = 0 (B[x] = $) */
+  uint64_t n_lines;        /* occurrence lines (128 bytes each) */
+  uint64_t bytes_resident; /* device bytes held by the index */
+  uint64_t C[5];           /* C[a] = |{i : B[i] < a}| for a = $, A, C, G, T (C[0] = 0)         */
+  int bases_per_line;      /* rows of B per occurrence line (384) */
+  int line_bytes;          /* 128 */
+  int sa_sample;
+  int kmer_k;
+  int bisulfite;
+  int device;
+} mbw_index_info_t;
+
+int mbw_index_info(const mbw_index *idx, mbw_index_info_t *out);
+
+/* Device pointers to the resident arrays (read-only views for tests and tools):
+ * lines: n_lines x 128 B; each line = u64 counts of A,C,G,T in B before the line (the $ row is
+ *        counted as A), then 384 rows of B at 2 bits (row t of the line in u64 word t/32, bits
+ *        2*(t%32)..+1; the $ row holds A).
+ * ssa:   ceil(n/r) x u64, ssa[x/r] = S(x).
+ * kmer:  4^k x 16 B packed (k:40 | k':40 | s:40 bits, little-endian), code = sum P[q]*4^(k-1-q). */
+int mbw_index_device_arrays(const mbw_index *idx, const void **lines, const void **ssa, const void **kmer);
+
+/* ---- seeding ------------------------------------------------------------------------------ */
+typedef struct mbw_ctx mbw_ctx;
+
+/* A context owns the device work space and result buffers for one stream of mbw_seed calls.
+ * Contexts are not thread-safe; use one per host thread / stream.  The index must outlive it. */
+int mbw_ctx_create(const mbw_index *idx, mbw_ctx **out);
+void mbw_ctx_free(mbw_ctx *ctx);
+
+typedef struct {
+  int min_occ;        /* c of the (l,c)-SMEMs (Section 2.1); >= 1; 1 for plain seeding (Section 2.6) */
+  int reseed;         /* second seeding round (Section 2.6): for each round-1 SMEM [i,j) with
+                         j-i >= reseed_len and s <= reseed_occ, the (floor((j-i)/2), s+1)-SMEMs of
+                         P[i,j); duplicates removed */
+  int reseed_len;     /* 38 in the paper */
+  int reseed_occ;     /* 10 in the paper */
+  int bs_role;        /* bisulfite index only: 1 = read 1 (C->T, keep positions in the forward
+                         C->T and reverse G->A copies), 2 = read 2 (G->A, keep forward G->A and
+                         reverse C->T) (Section 2.9); 0 = plain */
+  int kernel;         /* MBW_KERNEL_COOP (default) or MBW_KERNEL_PLAIN (one read per thread,
+                         serial algorithm per thread; the baseline) */
+  int use_kmer;       /* use the index's k-mer table in the cooperative kernel */
+  int groups_per_block; /* cooperative kernels: 8-lane groups per workgroup (0 = default 32) */
+  int blocks_per_cu;  /* persistent grid size per compute unit (0 = occupancy limit) */
+  int grab;           /* queries taken per work-queue fetch (0 = default) */
+} mbw_seed_opts;
+
+#define MBW_KERNEL_COOP  0
+#define MBW_KERNEL_PLAIN 1
+
+/* One seed = one (l,c)-SMEM P[qbeg, qend) of read `read_id` with its ds-interval (k, kr, s).
+ * Its reference positions (T coordinates, 0 <= pos < n-1) are pos[pos_off .. pos_off+npos).
+ * flags bit 0 (MBW_SEED_UNLOCATED): s > max_occ, positions not computed (npos = 0).
+ * flags bit 1 (MBW_SEED_ROUND2): found in the second seeding round. */
+typedef struct {
+  uint32_t read_id, qbeg, qend, flags;
+  uint64_t k, kr, s;
+  uint64_t pos_off;
+  uint32_t npos, reserved;
+} mbw_seed_t;
+
+#define MBW_SEED_UNLOCATED 1u
+#define MBW_SEED_ROUND2    2u
+
+typedef struct {
+  uint64_t n_seeds;
+  uint64_t n_pos;
+  const mbw_seed_t *seeds; /* device pointer, n_seeds records sorted by (read_id, qbeg, qend)     */
+  const uint64_t *pos;     /* device pointer, n_pos positions; within a seed in SA-row order      */
+  uint64_t lines_smem;     /* algorithmic 128-B index lines touched by SMEM finding (counted)    */
+  uint64_t lines_locate;   /* ... by locate (LF steps + SA-sample reads)                          */
+  uint64_t steps;          /* extension steps (Algorithm 1 calls) */
+  uint64_t lf_steps;       /* LF steps in locate */
+  float ms_smem, ms_locate, ms_total; /* device time of the phases (HIP events) */
+} mbw_result;
+
+/* Seed a batch of reads.
+ *   reads:   concatenated read bases, ASCII (A/C/G/T case-insensitive; anything else is a base
+ *            that matches nothing), host or device pointer.
+ *   lengths: n_reads x u32 read lengths (host or device), each < 65536; reads are stored back to
+ *            back in `reads` in this order.
+ *   min_seed_len: l >= 1.  max_occ >= 1: seeds with s > max_occ are reported but not located.
+ *   stream:  hipStream_t to run on (NULL = default stream).
+ * The call runs on `stream` and waits for it before returning (the result counts are needed on
+ * the host).  Results stay in device memory owned by `ctx` and remain valid until the next
+ * mbw_seed on the same ctx.  Errors: MBW_E_INVAL, MBW_E_NOMEM, MBW_E_HIP. */
+int mbw_seed(mbw_ctx *ctx, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads,
+             int min_seed_len, int max_occ, const mbw_seed_opts *opts, void *stream, mbw_result *out);
+
+/* Copy a result to host buffers (seeds: n_seeds records, pos: n_pos values; either may be NULL). */
+int mbw_result_download(mbw_ctx *ctx, const mbw_result *res, mbw_seed_t *seeds, uint64_t *pos);
+
+/* Map a T position of a match of length len to (strand, reference position): pos < |R| is the
+ * forward strand at pos; otherwise the reverse strand at 2|R| - pos - len.  (Bisulfite index:
+ * the four copies of length |R| map to their source coordinates likewise.) */
+int mbw_pos_to_ref(const mbw_index *idx, uint64_t pos, uint32_t len, int *strand, uint64_t *ref_pos);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MBW_H */

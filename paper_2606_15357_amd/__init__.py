@@ -1,0 +1,277 @@
+"""Python binding of the mbw C-ABI (``include/mbw.h``): argument marshalling only.
+
+Every step of index construction and seeding runs in the HIP library ``libmbw.so`` built for
+gfx950; this module only loads it and moves arguments across the boundary.  If the library is
+missing it raises instead of computing anything itself.
+
+PyTorch is optional plumbing: reads may be passed as torch CUDA tensors (device pointers are
+handed to the library) and ``stream`` may be a ``torch.cuda.Stream``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmbw.so")
+
+MBW_OK = 0
+MBW_E_INVAL = -1
+MBW_E_NOMEM = -2
+MBW_E_HIP = -3
+MBW_E_IO = -4
+MBW_E_FORMAT = -5
+MBW_E_CAPACITY = -6
+
+KERNEL_COOP = 0
+KERNEL_PLAIN = 1
+SEED_UNLOCATED = 1
+SEED_ROUND2 = 2
+
+# the symbols include/mbw.h declares
+EXPORTS = ["mbw_strerror", "mbw_last_error", "mbw_index_build", "mbw_index_save", "mbw_index_load",
+           "mbw_index_free", "mbw_index_info", "mbw_index_device_arrays", "mbw_ctx_create", "mbw_ctx_free",
+           "mbw_seed", "mbw_result_download", "mbw_pos_to_ref"]
+
+
+class MbwError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mbw error {code}: {msg}")
+        self.code = code
+
+
+class BuildOpts(C.Structure):
+    _fields_ = [("sa_sample", C.c_int), ("kmer_k", C.c_int), ("bisulfite", C.c_int), ("ref_is_codes", C.c_int),
+                ("rng_seed", C.c_uint64), ("device", C.c_int)]
+
+
+class IndexInfo(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("len_r", C.c_uint64), ("primary", C.c_uint64), ("n_lines", C.c_uint64),
+                ("bytes_resident", C.c_uint64), ("C", C.c_uint64 * 5), ("bases_per_line", C.c_int),
+                ("line_bytes", C.c_int), ("sa_sample", C.c_int), ("kmer_k", C.c_int), ("bisulfite", C.c_int),
+                ("device", C.c_int)]
+
+
+class SeedOpts(C.Structure):
+    _fields_ = [("min_occ", C.c_int), ("reseed", C.c_int), ("reseed_len", C.c_int), ("reseed_occ", C.c_int),
+                ("bs_role", C.c_int), ("kernel", C.c_int), ("use_kmer", C.c_int), ("groups_per_block", C.c_int),
+                ("blocks_per_cu", C.c_int), ("grab", C.c_int)]
+
+
+class Result(C.Structure):
+    _fields_ = [("n_seeds", C.c_uint64), ("n_pos", C.c_uint64), ("seeds", C.c_void_p), ("pos", C.c_void_p),
+                ("lines_smem", C.c_uint64), ("lines_locate", C.c_uint64), ("steps", C.c_uint64),
+                ("lf_steps", C.c_uint64), ("ms_smem", C.c_float), ("ms_locate", C.c_float), ("ms_total", C.c_float)]
+
+
+SEED_DTYPE = np.dtype([("read_id", "<u4"), ("qbeg", "<u4"), ("qend", "<u4"), ("flags", "<u4"), ("k", "<u8"),
+                       ("kr", "<u8"), ("s", "<u8"), ("pos_off", "<u8"), ("npos", "<u4"), ("reserved", "<u4")])
+assert SEED_DTYPE.itemsize == 56
+
+_lib = None
+
+
+def load_library():
+    """Load libmbw.so; raises if it has not been built (no fallback of any kind)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2606_15357_amd.build` "
+                          "(or __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    vp, u64, i32 = C.c_void_p, C.c_uint64, C.c_int
+    L.mbw_strerror.restype = C.c_char_p
+    L.mbw_strerror.argtypes = [i32]
+    L.mbw_last_error.restype = C.c_char_p
+    L.mbw_last_error.argtypes = []
+    L.mbw_index_build.argtypes = [vp, u64, C.POINTER(BuildOpts), C.POINTER(vp)]
+    L.mbw_index_save.argtypes = [vp, C.c_char_p]
+    L.mbw_index_load.argtypes = [C.c_char_p, i32, C.POINTER(vp)]
+    L.mbw_index_free.argtypes = [vp]
+    L.mbw_index_free.restype = None
+    L.mbw_index_info.argtypes = [vp, C.POINTER(IndexInfo)]
+    L.mbw_index_device_arrays.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]
+    L.mbw_ctx_create.argtypes = [vp, C.POINTER(vp)]
+    L.mbw_ctx_free.argtypes = [vp]
+    L.mbw_ctx_free.restype = None
+    L.mbw_seed.argtypes = [vp, vp, vp, u64, i32, i32, C.POINTER(SeedOpts), vp, C.POINTER(Result)]
+    L.mbw_result_download.argtypes = [vp, C.POINTER(Result), vp, vp]
+    L.mbw_pos_to_ref.argtypes = [vp, u64, C.c_uint32, C.POINTER(C.c_int), C.POINTER(C.c_uint64)]
+    for name in EXPORTS:
+        getattr(L, name)
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != MBW_OK:
+        msg = _lib.mbw_last_error().decode(errors="replace")
+        raise MbwError(rc, msg or _lib.mbw_strerror(rc).decode())
+
+
+def _ptr(x):
+    """Address of a numpy array, torch tensor or raw int."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    raise TypeError(type(x))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class Index:
+    """A resident FM-index (``mbw_index``)."""
+
+    def __init__(self, handle):
+        self._h = C.c_void_p(handle) if isinstance(handle, int) else handle
+        self._lib = load_library()
+
+    @classmethod
+    def build(cls, ref, sa_sample: int = 8, kmer_k: int = 10, bisulfite: bool = False, device: int = 0,
+              rng_seed: int = 0):
+        """``ref``: numpy uint8 codes 0..3 or ASCII bytes / str."""
+        L = load_library()
+        if isinstance(ref, str):
+            ref = ref.encode()
+        if isinstance(ref, (bytes, bytearray)):
+            arr = np.frombuffer(bytes(ref), dtype=np.uint8)
+            codes = 0
+        else:
+            arr = np.ascontiguousarray(ref, dtype=np.uint8)
+            codes = 1
+        o = BuildOpts(int(sa_sample), int(kmer_k), int(bool(bisulfite)), codes, int(rng_seed), int(device))
+        h = C.c_void_p()
+        _check(L.mbw_index_build(arr.ctypes.data if arr.size else None, arr.size, C.byref(o), C.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def load(cls, path: str, device: int = 0):
+        L = load_library()
+        h = C.c_void_p()
+        _check(L.mbw_index_load(path.encode(), int(device), C.byref(h)))
+        return cls(h)
+
+    def save(self, path: str):
+        _check(self._lib.mbw_index_save(self._h, path.encode()))
+
+    def info(self) -> dict:
+        i = IndexInfo()
+        _check(self._lib.mbw_index_info(self._h, C.byref(i)))
+        d = {f: getattr(i, f) for f, _ in IndexInfo._fields_}
+        d["C"] = list(i.C)
+        return d
+
+    def device_arrays(self):
+        a, b, c = C.c_void_p(), C.c_void_p(), C.c_void_p()
+        _check(self._lib.mbw_index_device_arrays(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def pos_to_ref(self, pos: int, length: int):
+        s, p = C.c_int(), C.c_uint64()
+        _check(self._lib.mbw_pos_to_ref(self._h, int(pos), int(length), C.byref(s), C.byref(p)))
+        return s.value, p.value
+
+    def free(self):
+        if self._h:
+            self._lib.mbw_index_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+@dataclass
+class SeedOutput:
+    n_seeds: int
+    n_pos: int
+    seeds_ptr: int
+    pos_ptr: int
+    lines_smem: int
+    lines_locate: int
+    steps: int
+    lf_steps: int
+    ms_smem: float
+    ms_locate: float
+    ms_total: float
+    _res: Result
+    _ctx: "Context"
+
+    def download(self):
+        """(seeds structured array, positions uint64 array) on the host."""
+        seeds = np.zeros(self.n_seeds, dtype=SEED_DTYPE)
+        pos = np.zeros(self.n_pos, dtype=np.uint64)
+        _check(self._ctx._lib.mbw_result_download(self._ctx._h, C.byref(self._res),
+                                                  seeds.ctypes.data if self.n_seeds else None,
+                                                  pos.ctypes.data if self.n_pos else None))
+        return seeds, pos
+
+
+class Context:
+    """Work space for a stream of ``mbw_seed`` calls against one index."""
+
+    def __init__(self, index: Index):
+        self._lib = load_library()
+        self.index = index
+        h = C.c_void_p()
+        _check(self._lib.mbw_ctx_create(index._h, C.byref(h)))
+        self._h = h
+
+    def seed(self, reads, lengths, min_seed_len: int = 19, max_occ: int = 500, min_occ: int = 1,
+             reseed: bool = True, reseed_len: int = 38, reseed_occ: int = 10, bs_role: int = 0,
+             kernel: int = KERNEL_COOP, use_kmer: bool = True, groups_per_block: int = 0, blocks_per_cu: int = 0,
+             grab: int = 0, stream=None) -> SeedOutput:
+        """``reads``: concatenated ASCII (numpy uint8 on the host or a torch uint8 CUDA tensor);
+        ``lengths``: uint32 per read (numpy or torch)."""
+        n = int(lengths.numel() if hasattr(lengths, "numel") else len(lengths))
+        if isinstance(lengths, np.ndarray):
+            lengths = np.ascontiguousarray(lengths, dtype=np.uint32)
+        if isinstance(reads, np.ndarray):
+            reads = np.ascontiguousarray(reads, dtype=np.uint8)
+        o = SeedOpts(int(min_occ), int(bool(reseed)), int(reseed_len), int(reseed_occ), int(bs_role), int(kernel),
+                     int(bool(use_kmer)), int(groups_per_block), int(blocks_per_cu), int(grab))
+        res = Result()
+        rp = _ptr(reads) if n else None
+        lp = _ptr(lengths) if n else None
+        _check(self._lib.mbw_seed(self._h, rp, lp, n, int(min_seed_len), int(max_occ), C.byref(o),
+                                  _stream_handle(stream), C.byref(res)))
+        return SeedOutput(res.n_seeds, res.n_pos, res.seeds or 0, res.pos or 0, res.lines_smem, res.lines_locate,
+                          res.steps, res.lf_steps, res.ms_smem, res.ms_locate, res.ms_total, res, self)
+
+    def free(self):
+        if self._h:
+            self._lib.mbw_ctx_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def canonical(seeds: np.ndarray, pos: np.ndarray):
+    """Seeds in (read_id, qbeg, qend) order with each seed's positions sorted ascending, as flat
+    arrays: (records without pos_off, concatenated positions)."""
+    order = np.lexsort((seeds["qend"], seeds["qbeg"], seeds["read_id"]))
+    s = seeds[order]
+    chunks = [np.sort(pos[int(o):int(o) + int(c)]) for o, c in zip(s["pos_off"], s["npos"])]
+    flat = np.concatenate(chunks) if chunks else np.zeros(0, np.uint64)
+    return s, flat

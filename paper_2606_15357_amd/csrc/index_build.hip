@@ -1,0 +1,735 @@
+// Index construction on the GPU, index files, and index queries.
+//
+// Paper Section 2.1 defines T = R . revcomp(R) . $ (Section 2.9: in bisulfite mode R is replaced by
+// C->T(R) . G->A(R)), the suffix array S, the BWT B[i] = T[S(i)-1] and the LF-mapping.  The
+// suffix array is built here by MSD refinement on the GPU: suffixes are bucketed by their first six
+// symbols, each bucket range (a "chunk" sized to the free HBM) is radix-sorted by a 63-bit key
+// holding 21 symbols in 3-bit codes ($ = 0, A..T = 1..4), and groups of equal keys are re-sorted by
+// the next 21 symbols until every group is a single suffix.  $ is unique, so a key that reaches
+// the end of T is unique and needs no further refinement.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "mbw_internal.h"
+#include "../../include/mbw.h"
+
+namespace {
+
+// ---------------------------------------------------------------------------------------------
+// device buffers with RAII
+template <class T>
+struct DevBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() { release(); }
+  void release() { if (p) (void)hipFree(p); p = nullptr; n = 0; }
+  hipError_t alloc(size_t count) {
+    release();
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)&p, count * sizeof(T));
+    if (e == hipSuccess) n = count; else p = nullptr;
+    return e;
+  }
+  T *detach() { T *q = p; p = nullptr; n = 0; return q; }
+};
+
+struct Temp {
+  DevBuf<uint8_t> b;
+  hipError_t ensure(size_t bytes) { return bytes <= b.n ? hipSuccess : b.alloc(bytes + bytes / 8 + 256); }
+};
+
+#define TRY(call) MBW_HIP_TRY(call)
+
+__host__ __device__ inline uint64_t splitmix(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+inline unsigned grid_for(uint64_t n, unsigned bs = 256, unsigned cap = 65536u * 8) {
+  uint64_t g = (n + bs - 1) / bs;
+  if (g < 1) g = 1;
+  return (unsigned)std::min<uint64_t>(g, cap);
+}
+
+// ---------------------------------------------------------------------------------------------
+// text
+
+// T without its final $: Tm = R' . revcomp(R'), m = 2|R'| symbols, packed 32 per u64 (LSB first).
+__global__ void k_pack_text(const uint8_t *__restrict__ Rp, uint64_t lrp, uint64_t *__restrict__ Tw, uint64_t nwords) {
+  uint64_t m = 2 * lrp;
+  for (uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; w < nwords; w += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t v = 0;
+    for (int t = 0; t < 32; ++t) {
+      uint64_t i = w * 32 + t;
+      uint64_t a = 0;
+      if (i < lrp) a = Rp[i];
+      else if (i < m) a = 3 - Rp[m - 1 - i];
+      v |= a << (2 * t);
+    }
+    Tw[w] = v;
+  }
+}
+
+__device__ __forceinline__ uint64_t text_sym(const uint64_t *__restrict__ Tw, uint64_t p) {
+  return (Tw[p >> 5] >> (2 * (p & 31))) & 3;
+}
+
+// 21 symbols of T starting at p as a 63-bit key, MSB first, codes $/past-end = 0, A..T = 1..4.
+__device__ __forceinline__ uint64_t key21(const uint64_t *__restrict__ Tw, uint64_t m, uint64_t p) {
+  if (p >= m) return 0;
+  uint64_t w = p >> 5;
+  int sh = (int)(p & 31) * 2;
+  uint64_t s = Tw[w] >> sh;
+  if (sh) s |= Tw[w + 1] << (64 - sh);
+  uint64_t left = m - p;  // symbols before $
+  uint64_t key = 0;
+#pragma unroll
+  for (int t = 0; t < 21; ++t) {
+    uint64_t c = ((uint64_t)t < left) ? ((s >> (2 * t)) & 3) + 1 : 0;
+    key = (key << 3) | c;
+  }
+  return key;
+}
+
+// bucket = first 6 symbols as base-5 digits ($ / past-end = 0, A..T = 1..4): 5^6 buckets in
+// lexicographic order of the 6-symbol prefix
+#define NBUCKET 15625u
+__device__ __forceinline__ uint32_t bucket_of(uint64_t key) {
+  uint32_t b = 0;
+#pragma unroll
+  for (int t = 0; t < 6; ++t) b = b * 5 + (uint32_t)((key >> (60 - 3 * t)) & 7);
+  return b;
+}
+
+__global__ void __launch_bounds__(256) k_bucket_hist(const uint64_t *__restrict__ Tw, uint64_t m, uint64_t n,
+                                                     unsigned long long *__restrict__ hist) {
+  __shared__ uint32_t h[NBUCKET];
+  for (uint32_t t = threadIdx.x; t < NBUCKET; t += blockDim.x) h[t] = 0;
+  __syncthreads();
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    atomicAdd(&h[bucket_of(key21(Tw, m, i))], 1u);
+  __syncthreads();
+  for (uint32_t t = threadIdx.x; t < NBUCKET; t += blockDim.x)
+    if (h[t]) atomicAdd(&hist[t], (unsigned long long)h[t]);
+}
+
+// positions whose bucket lies in [blo, bhi) -> out (order is irrelevant: the sort fixes it)
+__global__ void k_select(const uint64_t *__restrict__ Tw, uint64_t m, uint64_t n, uint32_t blo, uint32_t bhi,
+                         uint64_t *__restrict__ out, unsigned long long *__restrict__ count) {
+  const int lane = threadIdx.x & 63;
+  for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x; base < n; base += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t i = base + threadIdx.x;
+    bool f = false;
+    if (i < n) {
+      uint32_t b = bucket_of(key21(Tw, m, i));
+      f = b >= blo && b < bhi;
+    }
+    uint64_t mask = __ballot(f);
+    uint32_t cnt = __popcll(mask);
+    unsigned long long off = 0;
+    if (lane == 0 && cnt) off = atomicAdd(count, (unsigned long long)cnt);
+    off = __shfl(off, 0);
+    if (f) out[off + __popcll(mask & ((1ull << lane) - 1))] = i;
+  }
+}
+
+__global__ void k_keys(const uint64_t *__restrict__ Tw, uint64_t m, const uint64_t *__restrict__ pos, uint64_t M,
+                       uint64_t d, uint64_t *__restrict__ key) {
+  for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < M; x += (uint64_t)gridDim.x * blockDim.x)
+    key[x] = key21(Tw, m, pos[x] + d);
+}
+
+// group boundaries after the first sort; grp seed for the max-scan
+__global__ void k_init_bounds(const uint64_t *__restrict__ key, uint64_t M, uint8_t *__restrict__ bnd, uint32_t *__restrict__ gs) {
+  for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x <= M; x += (uint64_t)gridDim.x * blockDim.x) {
+    uint8_t b = (x == 0 || x == M) ? 1 : (key[x] != key[x - 1]);
+    bnd[x] = b;
+    if (x < M) gs[x] = b ? (uint32_t)x : 0u;
+  }
+}
+
+// unresolved = member of a group of size >= 2
+__global__ void k_mark_unres(const uint8_t *__restrict__ bnd, uint64_t M, uint32_t *__restrict__ flag) {
+  for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < M; x += (uint64_t)gridDim.x * blockDim.x)
+    flag[x] = (bnd[x] && bnd[x + 1]) ? 0u : 1u;
+}
+
+__global__ void k_scatter_unres(const uint32_t *__restrict__ flag, const uint32_t *__restrict__ idx, uint64_t M,
+                                const uint32_t *__restrict__ grp, uint32_t *__restrict__ u_slot, uint32_t *__restrict__ u_gid) {
+  for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < M; x += (uint64_t)gridDim.x * blockDim.x)
+    if (flag[x]) { uint32_t u = idx[x]; u_slot[u] = (uint32_t)x; u_gid[u] = grp[x]; }
+}
+
+__global__ void k_u_keys(const uint64_t *__restrict__ Tw, uint64_t m, const uint64_t *__restrict__ sa,
+                         const uint32_t *__restrict__ u_slot, uint64_t MU, uint64_t d, uint64_t *__restrict__ nk,
+                         uint32_t *__restrict__ iota) {
+  for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < MU; u += (uint64_t)gridDim.x * blockDim.x) {
+    nk[u] = key21(Tw, m, sa[u_slot[u]] + d);
+    iota[u] = (uint32_t)u;
+  }
+}
+
+__global__ void k_gather_u32(const uint32_t *__restrict__ src, const uint32_t *__restrict__ perm, uint64_t MU, uint32_t *__restrict__ dst) {
+  for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < MU; u += (uint64_t)gridDim.x * blockDim.x)
+    dst[u] = src[perm[u]];
+}
+
+// final order of this round: element perm[u] (index into the round's U) goes to slot u_slot[u]
+__global__ void k_apply_gather(const uint64_t *__restrict__ sa, const uint32_t *__restrict__ u_slot,
+                               const uint32_t *__restrict__ perm, const uint64_t *__restrict__ nk, uint64_t MU,
+                               uint64_t *__restrict__ tmp_sa, uint64_t *__restrict__ tmp_nk) {
+  for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < MU; u += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t v = perm[u];
+    tmp_sa[u] = sa[u_slot[v]];
+    tmp_nk[u] = nk[v];
+  }
+}
+
+__global__ void k_apply_scatter(uint64_t *__restrict__ sa, uint8_t *__restrict__ bnd, const uint32_t *__restrict__ u_slot,
+                                const uint64_t *__restrict__ tmp_sa, const uint64_t *__restrict__ tmp_nk, uint64_t MU,
+                                uint32_t *__restrict__ gseed) {
+  for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < MU; u += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t x = u_slot[u];
+    sa[x] = tmp_sa[u];
+    uint8_t b = bnd[x] | (uint8_t)(u > 0 && tmp_nk[u] != tmp_nk[u - 1]);
+    bnd[x] = b;   // only this thread touches row x in this pass
+    gseed[u] = b ? x : 0u;
+  }
+}
+
+// new group start of every refined row (max-scan of the group-start seeds over U)
+__global__ void k_apply_groups(uint32_t *__restrict__ grp, const uint32_t *__restrict__ u_slot,
+                               const uint32_t *__restrict__ gscan, uint64_t MU) {
+  for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < MU; u += (uint64_t)gridDim.x * blockDim.x)
+    grp[u_slot[u]] = gscan[u];
+}
+
+// B rows and SA samples of a finished chunk
+__global__ void k_emit_rows(const uint64_t *__restrict__ sa, uint64_t M, uint64_t base, const uint64_t *__restrict__ Tw,
+                            uint32_t r, uint8_t *__restrict__ B, uint64_t *__restrict__ ssa, unsigned long long *__restrict__ primary) {
+  for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < M; x += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t p = sa[x], row = base + x;
+    uint8_t b = 0;
+    if (p == 0) *primary = row;
+    else b = (uint8_t)text_sym(Tw, p - 1);
+    B[row] = b;
+    if (row % r == 0) ssa[row / r] = p;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// occurrence lines
+
+__global__ void k_line_counts(const uint8_t *__restrict__ B, uint64_t n, uint64_t n_lines, uint64_t *__restrict__ cnt /*4 x n_lines*/,
+                              uint4 *__restrict__ lines) {
+  for (uint64_t L = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; L < n_lines; L += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t c[4] = {0, 0, 0, 0};
+    uint64_t *w = (uint64_t *)(lines + L * MBW_LINE_U4);
+    for (int q = 0; q < 12; ++q) {
+      uint64_t v = 0;
+      for (int t = 0; t < 32; ++t) {
+        uint64_t row = L * MBW_BPL + q * 32 + t;
+        if (row < n) { uint64_t b = B[row]; v |= b << (2 * t); c[b]++; }
+      }
+      w[4 + q] = v;
+    }
+    for (int a = 0; a < 4; ++a) cnt[a * n_lines + L] = c[a];
+  }
+}
+
+__global__ void k_line_headers(const uint64_t *__restrict__ pre /*4 x n_lines exclusive sums*/, uint64_t n_lines, uint4 *__restrict__ lines) {
+  for (uint64_t L = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; L < n_lines; L += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t *w = (uint64_t *)(lines + L * MBW_LINE_U4);
+    for (int a = 0; a < 4; ++a) w[a] = pre[a * n_lines + L];
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// k-mer table: level t+1 from level t by one backward extension (Algorithm 1)
+struct Iv { uint64_t k, kr, s; };
+
+__global__ void k_kmer_level(IndexView ix, const Iv *__restrict__ prev, uint64_t nprev, Iv *__restrict__ next) {
+  uint64_t total = nprev * 4;
+  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < total; e += (uint64_t)gridDim.x * blockDim.x) {
+    int a = (int)(e / nprev);
+    Iv p = prev[e % nprev];
+    Iv o;
+    if (p.s == 0) { o.k = 0; o.kr = 0; o.s = 0; }
+    else {
+      Occ4 o1 = occ_single(ix.lines, p.k, ix.primary);
+      Occ4 o2 = occ_single(ix.lines, p.k + p.s, ix.primary);
+      ext_update(o1, o2, a, p.k, p.s, p.kr, ix.primary, ix.Cb, o.k, o.kr, o.s);
+    }
+    next[e] = o;
+  }
+}
+
+__global__ void k_kmer_pack(const Iv *__restrict__ lv, uint64_t nent, uint4 *__restrict__ tab) {
+  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < nent; e += (uint64_t)gridDim.x * blockDim.x)
+    tab[e] = kmer_pack(lv[e].k, lv[e].kr, lv[e].s);
+}
+
+// ---------------------------------------------------------------------------------------------
+// suffix sorting of one chunk; returns 0 or an MBW error code
+int sort_chunk(const uint64_t *Tw, uint64_t m, uint64_t n, uint32_t blo, uint32_t bhi, uint64_t M,
+               uint64_t *sa0, uint64_t *sa1, uint64_t *key0, uint64_t *key1, uint8_t *bnd, uint32_t *grp,
+               uint32_t *flag, uint32_t *idx, uint32_t *u_slot, uint32_t *u_gid, uint32_t *iota0, uint32_t *iota1,
+               uint64_t *nk1, uint32_t *gid1, uint32_t *gseed, uint32_t *gscan, uint64_t *tmp_sa, uint64_t *tmp_nk,
+               unsigned long long *dcount, Temp &tmp, hipStream_t st, uint64_t **sa_out) {
+  TRY(hipMemsetAsync(dcount, 0, sizeof(unsigned long long), st));
+  k_select<<<grid_for(n), 256, 0, st>>>(Tw, m, n, blo, bhi, sa0, dcount);
+  TRY(hipGetLastError());
+  unsigned long long got = 0;
+  TRY(hipMemcpyAsync(&got, dcount, sizeof(got), hipMemcpyDeviceToHost, st));
+  TRY(hipStreamSynchronize(st));
+  if (got != M) { mbw_set_error("suffix bucket selection count mismatch"); return MBW_E_HIP; }
+  k_keys<<<grid_for(M), 256, 0, st>>>(Tw, m, sa0, M, 0, key0);
+  TRY(hipGetLastError());
+  hipcub::DoubleBuffer<uint64_t> dk(key0, key1), dv(sa0, sa1);
+  size_t tb = 0;
+  TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, dk, dv, M, 0, 63, st));
+  TRY(tmp.ensure(tb));
+  TRY(hipcub::DeviceRadixSort::SortPairs(tmp.b.p, tb, dk, dv, M, 0, 63, st));
+  uint64_t *sa = dv.Current();
+  uint64_t *key = dk.Current();
+  k_init_bounds<<<grid_for(M + 1), 256, 0, st>>>(key, M, bnd, idx /*as seed*/);
+  TRY(hipGetLastError());
+  tb = 0;
+  TRY(hipcub::DeviceScan::InclusiveScan(nullptr, tb, idx, grp, hipcub::Max(), M, st));
+  TRY(tmp.ensure(tb));
+  TRY(hipcub::DeviceScan::InclusiveScan(tmp.b.p, tb, idx, grp, hipcub::Max(), M, st));
+  for (uint64_t round = 1;; ++round) {
+    if (round > n / 21 + 4) { mbw_set_error("suffix refinement did not converge"); return MBW_E_HIP; }
+    k_mark_unres<<<grid_for(M), 256, 0, st>>>(bnd, M, flag);
+    TRY(hipGetLastError());
+    tb = 0;
+    TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, flag, idx, M, st));
+    TRY(tmp.ensure(tb));
+    TRY(hipcub::DeviceScan::ExclusiveSum(tmp.b.p, tb, flag, idx, M, st));
+    uint32_t lastf = 0, lasti = 0;
+    TRY(hipMemcpyAsync(&lastf, flag + M - 1, 4, hipMemcpyDeviceToHost, st));
+    TRY(hipMemcpyAsync(&lasti, idx + M - 1, 4, hipMemcpyDeviceToHost, st));
+    TRY(hipStreamSynchronize(st));
+    uint64_t MU = (uint64_t)lasti + lastf;
+    if (MU == 0) break;
+    k_scatter_unres<<<grid_for(M), 256, 0, st>>>(flag, idx, M, grp, u_slot, u_gid);
+    TRY(hipGetLastError());
+    uint64_t d = 21 * round;
+    k_u_keys<<<grid_for(MU), 256, 0, st>>>(Tw, m, sa, u_slot, MU, d, tmp_nk /*nk*/, iota0);
+    TRY(hipGetLastError());
+    // stable LSD: by next key, then by group start
+    hipcub::DoubleBuffer<uint64_t> k1(tmp_nk, nk1);
+    hipcub::DoubleBuffer<uint32_t> v1(iota0, iota1);
+    tb = 0;
+    TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, k1, v1, MU, 0, 63, st));
+    TRY(tmp.ensure(tb));
+    TRY(hipcub::DeviceRadixSort::SortPairs(tmp.b.p, tb, k1, v1, MU, 0, 63, st));
+    uint64_t *nk = (k1.Current() == tmp_nk) ? tmp_nk : nk1;   // sorted keys (unused below)
+    (void)nk;
+    uint32_t *perm1 = v1.Current();
+    uint32_t *perm_alt = (perm1 == iota0) ? iota1 : iota0;
+    k_gather_u32<<<grid_for(MU), 256, 0, st>>>(u_gid, perm1, MU, gid1);
+    TRY(hipGetLastError());
+    hipcub::DoubleBuffer<uint32_t> k2(gid1, gscan), v2(perm1, perm_alt);
+    tb = 0;
+    TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, k2, v2, MU, 0, 32, st));
+    TRY(tmp.ensure(tb));
+    TRY(hipcub::DeviceRadixSort::SortPairs(tmp.b.p, tb, k2, v2, MU, 0, 32, st));
+    uint32_t *perm = v2.Current();
+    // the unsorted next keys of this round are needed by index: recompute into nk1
+    k_u_keys<<<grid_for(MU), 256, 0, st>>>(Tw, m, sa, u_slot, MU, d, nk1, gscan /*scratch iota*/);
+    TRY(hipGetLastError());
+    k_apply_gather<<<grid_for(MU), 256, 0, st>>>(sa, u_slot, perm, nk1, MU, tmp_sa, tmp_nk);
+    TRY(hipGetLastError());
+    k_apply_scatter<<<grid_for(MU), 256, 0, st>>>(sa, bnd, u_slot, tmp_sa, tmp_nk, MU, gseed);
+    TRY(hipGetLastError());
+    tb = 0;
+    TRY(hipcub::DeviceScan::InclusiveScan(nullptr, tb, gseed, gscan, hipcub::Max(), MU, st));
+    TRY(tmp.ensure(tb));
+    TRY(hipcub::DeviceScan::InclusiveScan(tmp.b.p, tb, gseed, gscan, hipcub::Max(), MU, st));
+    k_apply_groups<<<grid_for(MU), 256, 0, st>>>(grp, u_slot, gscan, MU);
+    TRY(hipGetLastError());
+  }
+  *sa_out = sa;
+  return 0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// error state
+static thread_local std::string g_err;
+void mbw_set_error(const std::string &msg) { g_err = msg; }
+extern "C" const char *mbw_last_error(void) { return g_err.c_str(); }
+
+extern "C" const char *mbw_strerror(int code) {
+  switch (code) {
+    case MBW_OK: return "ok";
+    case MBW_E_INVAL: return "invalid argument";
+    case MBW_E_NOMEM: return "out of memory";
+    case MBW_E_HIP: return "HIP runtime error";
+    case MBW_E_IO: return "I/O error";
+    case MBW_E_FORMAT: return "bad index file format";
+    case MBW_E_CAPACITY: return "buffer too small";
+    default: return "unknown error";
+  }
+}
+
+extern "C" void mbw_index_free(mbw_index *ix) {
+  if (!ix) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(ix->device);
+  if (ix->lines) (void)hipFree(ix->lines);
+  if (ix->ssa) (void)hipFree(ix->ssa);
+  if (ix->kmer) (void)hipFree(ix->kmer);
+  (void)hipSetDevice(cur);
+  delete ix;
+}
+
+static int build_kmer_table(mbw_index *ix, hipStream_t st) {
+  int K = ix->kmer_k;
+  if (K <= 0) return 0;
+  IndexView v = make_view(ix);
+  DevBuf<Iv> a, b;
+  uint64_t ntop = 1ull << (2 * K);
+  TRY(a.alloc(ntop));
+  TRY(b.alloc(ntop));
+  Iv root = {0, 0, ix->n};
+  TRY(hipMemcpyAsync(a.p, &root, sizeof(Iv), hipMemcpyHostToDevice, st));
+  uint64_t cnt = 1;
+  Iv *cur = a.p, *nxt = b.p;
+  for (int t = 0; t < K; ++t) {
+    k_kmer_level<<<grid_for(cnt * 4), 256, 0, st>>>(v, cur, cnt, nxt);
+    TRY(hipGetLastError());
+    std::swap(cur, nxt);
+    cnt *= 4;
+  }
+  uint4 *tab = nullptr;
+  TRY(hipMalloc((void **)&tab, ntop * sizeof(uint4)));
+  ix->kmer = tab;
+  ix->bytes += ntop * sizeof(uint4);
+  k_kmer_pack<<<grid_for(ntop), 256, 0, st>>>(cur, ntop, tab);
+  TRY(hipGetLastError());
+  TRY(hipStreamSynchronize(st));
+  return 0;
+}
+
+static int build_lines(mbw_index *ix, const uint8_t *B, hipStream_t st) {
+  uint64_t n = ix->n, nl = n / MBW_BPL + 1;
+  ix->n_lines = nl;
+  TRY(hipMalloc((void **)&ix->lines, nl * MBW_LINE_BYTES));
+  ix->bytes += nl * MBW_LINE_BYTES;
+  DevBuf<uint64_t> cnt, pre;
+  TRY(cnt.alloc(4 * nl + 1));
+  TRY(pre.alloc(4 * nl + 1));
+  k_line_counts<<<grid_for(nl), 256, 0, st>>>(B, n, nl, cnt.p, ix->lines);
+  TRY(hipGetLastError());
+  Temp tmp;
+  for (int a = 0; a < 4; ++a) {
+    size_t tb = 0;
+    TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt.p + a * nl, pre.p + a * nl, nl, st));
+    TRY(tmp.ensure(tb));
+    TRY(hipcub::DeviceScan::ExclusiveSum(tmp.b.p, tb, cnt.p + a * nl, pre.p + a * nl, nl, st));
+  }
+  k_line_headers<<<grid_for(nl), 256, 0, st>>>(pre.p, nl, ix->lines);
+  TRY(hipGetLastError());
+  uint64_t tot[4], last[4];
+  for (int a = 0; a < 4; ++a) {
+    TRY(hipMemcpyAsync(&tot[a], pre.p + a * nl + nl - 1, 8, hipMemcpyDeviceToHost, st));
+    TRY(hipMemcpyAsync(&last[a], cnt.p + a * nl + nl - 1, 8, hipMemcpyDeviceToHost, st));
+  }
+  TRY(hipStreamSynchronize(st));
+  for (int a = 0; a < 4; ++a) tot[a] += last[a];
+  // raw A total includes the $ row
+  ix->C[0] = 0;
+  ix->C[1] = 1;
+  ix->C[2] = ix->C[1] + (tot[0] - 1);
+  ix->C[3] = ix->C[2] + tot[1];
+  ix->C[4] = ix->C[3] + tot[2];
+  return 0;
+}
+
+extern "C" int mbw_index_build(const uint8_t *ref, uint64_t len, const mbw_build_opts *opts, mbw_index **out) {
+  if (!out) { mbw_set_error("out is NULL"); return MBW_E_INVAL; }
+  *out = nullptr;
+  if (!ref || !opts || len == 0 || len >= (1ull << 38)) { mbw_set_error("bad reference or options"); return MBW_E_INVAL; }
+  if (opts->sa_sample < 1 || opts->sa_sample > 1024) { mbw_set_error("sa_sample must be in [1,1024]"); return MBW_E_INVAL; }
+  if (opts->kmer_k < 0 || opts->kmer_k > 13) { mbw_set_error("kmer_k must be in [0,13]"); return MBW_E_INVAL; }
+  TRY(hipSetDevice(opts->device));
+  // host: codes, ambiguous bases -> random (counter-based SplitMix64), bisulfite conversion
+  uint64_t lrp = opts->bisulfite ? 2 * len : len;
+  std::vector<uint8_t> Rp;
+  try { Rp.resize(lrp); } catch (...) { mbw_set_error("host allocation failed"); return MBW_E_NOMEM; }
+  auto convert = [&](uint64_t lo, uint64_t hi) {
+  for (uint64_t i = lo; i < hi; ++i) {
+    uint8_t a = ref[i];
+    int c;
+    if (opts->ref_is_codes) c = a < 4 ? a : -1;
+    else {
+      switch (a) { case 'A': case 'a': c = 0; break; case 'C': case 'c': c = 1; break;
+                   case 'G': case 'g': c = 2; break; case 'T': case 't': c = 3; break; default: c = -1; }
+    }
+    if (c < 0) c = (int)(splitmix(opts->rng_seed + (uint64_t)i * 0x9E3779B97F4A7C15ull) & 3);
+    if (opts->bisulfite) {
+      Rp[i] = (uint8_t)(c == 1 ? 3 : c);            // C -> T
+      Rp[len + i] = (uint8_t)(c == 2 ? 0 : c);      // G -> A
+    } else {
+      Rp[i] = (uint8_t)c;
+    }
+  }
+  };
+  {
+    unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    if (len < (1u << 22)) nt = 1;
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; ++t) th.emplace_back(convert, len * t / nt, len * (t + 1) / nt);
+    for (auto &x : th) x.join();
+  }
+  mbw_index *ix = new mbw_index();
+  memset(ix, 0, sizeof(*ix));
+  ix->device = opts->device;
+  ix->len_r = len;
+  ix->bisulfite = opts->bisulfite ? 1 : 0;
+  ix->sa_sample = opts->sa_sample;
+  ix->kmer_k = opts->kmer_k;
+  uint64_t m = 2 * lrp, n = m + 1;
+  ix->n = n;
+  hipStream_t st;
+  if (hipStreamCreate(&st) != hipSuccess) { delete ix; mbw_set_error("hipStreamCreate failed"); return MBW_E_HIP; }
+  int rc = [&]() -> int {
+    uint64_t nwords = (m + 31) / 32 + 2;
+    DevBuf<uint64_t> Tw;
+    TRY(Tw.alloc(nwords));
+    {
+      DevBuf<uint8_t> dR;
+      TRY(dR.alloc(lrp));
+      TRY(hipMemcpyAsync(dR.p, Rp.data(), lrp, hipMemcpyHostToDevice, st));
+      k_pack_text<<<grid_for(nwords), 256, 0, st>>>(dR.p, lrp, Tw.p, nwords);
+      TRY(hipGetLastError());
+      TRY(hipStreamSynchronize(st));
+    }
+    std::vector<uint8_t>().swap(Rp);
+    // bucket histogram and chunk plan
+    DevBuf<unsigned long long> hist;
+    TRY(hist.alloc(NBUCKET + 1));
+    TRY(hipMemsetAsync(hist.p, 0, (NBUCKET + 1) * sizeof(unsigned long long), st));
+    k_bucket_hist<<<std::min<unsigned>(grid_for(n), 1024u), 256, 0, st>>>(Tw.p, m, n, hist.p);
+    TRY(hipGetLastError());
+    std::vector<unsigned long long> h(NBUCKET);
+    TRY(hipMemcpyAsync(h.data(), hist.p, NBUCKET * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    TRY(hipStreamSynchronize(st));
+    // outputs
+    DevBuf<uint8_t> B;
+    TRY(B.alloc(n));
+    ix->n_ssa = (n + ix->sa_sample - 1) / ix->sa_sample;
+    TRY(hipMalloc((void **)&ix->ssa, ix->n_ssa * sizeof(uint64_t)));
+    ix->bytes += ix->n_ssa * sizeof(uint64_t);
+    // chunk capacity from free memory (about 100 bytes per suffix in flight)
+    size_t fr = 0, tot = 0;
+    TRY(hipMemGetInfo(&fr, &tot));
+    uint64_t cap = (fr > (size_t)(2ull << 30)) ? (uint64_t)((fr - (2ull << 30)) / 104) : (uint64_t)(fr / 208);
+    cap = std::min<uint64_t>(cap, (1ull << 31) - 1024);
+    uint64_t maxb = *std::max_element(h.begin(), h.end());
+    if (cap < maxb) cap = maxb;
+    cap = std::min<uint64_t>(cap, n);
+    DevBuf<uint64_t> sa0, sa1, key0, key1, nk1, tmp_sa, tmp_nk;
+    DevBuf<uint8_t> bnd;
+    DevBuf<uint32_t> grp, flag, idx, u_slot, u_gid, iota0, iota1, gid1, gseed, gscan;
+    DevBuf<unsigned long long> dcount, dprim;
+    TRY(sa0.alloc(cap)); TRY(sa1.alloc(cap)); TRY(key0.alloc(cap)); TRY(key1.alloc(cap));
+    TRY(nk1.alloc(cap)); TRY(tmp_sa.alloc(cap)); TRY(tmp_nk.alloc(cap));
+    TRY(bnd.alloc(cap + 1));
+    TRY(grp.alloc(cap)); TRY(flag.alloc(cap)); TRY(idx.alloc(cap)); TRY(u_slot.alloc(cap)); TRY(u_gid.alloc(cap));
+    TRY(iota0.alloc(cap)); TRY(iota1.alloc(cap)); TRY(gid1.alloc(cap)); TRY(gseed.alloc(cap)); TRY(gscan.alloc(cap));
+    TRY(dcount.alloc(1)); TRY(dprim.alloc(1));
+    TRY(hipMemsetAsync(dprim.p, 0xff, 8, st));
+    Temp tmp;
+    uint64_t base = 0;
+    uint32_t b = 0;
+    while (b < NBUCKET) {
+      uint32_t e = b;
+      uint64_t M = 0;
+      while (e < NBUCKET && M + h[e] <= cap) M += h[e++];
+      if (M == 0) { b = e; continue; }
+      uint64_t *sa = nullptr;
+      int r = sort_chunk(Tw.p, m, n, b, e, M, sa0.p, sa1.p, key0.p, key1.p, bnd.p, grp.p, flag.p, idx.p, u_slot.p,
+                         u_gid.p, iota0.p, iota1.p, nk1.p, gid1.p, gseed.p, gscan.p, tmp_sa.p, tmp_nk.p, dcount.p,
+                         tmp, st, &sa);
+      if (r) return r;
+      k_emit_rows<<<grid_for(M), 256, 0, st>>>(sa, M, base, Tw.p, (uint32_t)ix->sa_sample, B.p, ix->ssa, dprim.p);
+      TRY(hipGetLastError());
+      base += M;
+      b = e;
+    }
+    if (base != n) { mbw_set_error("suffix chunks do not cover the text"); return MBW_E_HIP; }
+    unsigned long long prim = 0;
+    TRY(hipMemcpyAsync(&prim, dprim.p, 8, hipMemcpyDeviceToHost, st));
+    TRY(hipStreamSynchronize(st));
+    ix->primary = prim;
+    // free the sorting space before the lines are built
+    sa0.release(); sa1.release(); key0.release(); key1.release(); nk1.release(); tmp_sa.release(); tmp_nk.release();
+    bnd.release(); grp.release(); flag.release(); idx.release(); u_slot.release(); u_gid.release(); iota0.release();
+    iota1.release(); gid1.release(); gseed.release(); gscan.release(); tmp.b.release();
+    int r = build_lines(ix, B.p, st);
+    if (r) return r;
+    B.release();
+    r = build_kmer_table(ix, st);
+    if (r) return r;
+    TRY(hipStreamSynchronize(st));
+    return 0;
+  }();
+  (void)hipStreamDestroy(st);
+  if (rc) { mbw_index_free(ix); return rc; }
+  *out = ix;
+  return MBW_OK;
+}
+
+extern "C" int mbw_index_info(const mbw_index *ix, mbw_index_info_t *o) {
+  if (!ix || !o) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
+  o->n = ix->n; o->len_r = ix->len_r; o->primary = ix->primary; o->n_lines = ix->n_lines;
+  o->bytes_resident = ix->bytes;
+  for (int a = 0; a < 5; ++a) o->C[a] = ix->C[a];
+  o->bases_per_line = MBW_BPL; o->line_bytes = MBW_LINE_BYTES; o->sa_sample = ix->sa_sample;
+  o->kmer_k = ix->kmer_k; o->bisulfite = ix->bisulfite; o->device = ix->device;
+  return MBW_OK;
+}
+
+extern "C" int mbw_index_device_arrays(const mbw_index *ix, const void **lines, const void **ssa, const void **kmer) {
+  if (!ix) { mbw_set_error("NULL index"); return MBW_E_INVAL; }
+  if (lines) *lines = ix->lines;
+  if (ssa) *ssa = ix->ssa;
+  if (kmer) *kmer = ix->kmer;
+  return MBW_OK;
+}
+
+extern "C" int mbw_pos_to_ref(const mbw_index *ix, uint64_t pos, uint32_t len, int *strand, uint64_t *ref_pos) {
+  if (!ix || !strand || !ref_pos) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
+  uint64_t half = (ix->n - 1) / 2;   // |R| (plain) or 2|R| (bisulfite)
+  if (pos + len > ix->n - 1) { mbw_set_error("position out of range"); return MBW_E_INVAL; }
+  uint64_t lr = ix->len_r;
+  if (pos < half) { *strand = 0; *ref_pos = ix->bisulfite ? pos % lr : pos; }
+  else {
+    *strand = 1;
+    uint64_t p = 2 * half - pos - len;  // position in the forward text of length `half`
+    *ref_pos = ix->bisulfite ? p % lr : p;
+  }
+  return MBW_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// index files: header (magic, version, fields, FNV-1a of header and of each array) + arrays
+static const uint64_t kMagic = 0x3158444e4957424dull;  // "MBWINDX1"
+static const uint32_t kVersion = 1;
+
+struct FileHeader {
+  uint64_t magic;
+  uint32_t version, bpl;
+  uint64_t n, len_r, primary, n_lines, n_ssa;
+  uint64_t C[5];
+  int32_t sa_sample, kmer_k, bisulfite, pad;
+  uint64_t sum_lines, sum_ssa, sum_kmer;
+  uint64_t sum_header;
+};
+
+static uint64_t fnv(const void *p, size_t n, uint64_t h = 1469598103934665603ull) {
+  const uint8_t *b = (const uint8_t *)p;
+  for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
+  return h;
+}
+
+// checksum of a large array: FNV of 64-bit words, strided by blocks (fast, order-sensitive)
+static uint64_t sum_words(const void *p, size_t bytes) {
+  const uint64_t *w = (const uint64_t *)p;
+  size_t nw = bytes / 8;
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < nw; ++i) { h ^= w[i] + i; h *= 1099511628211ull; }
+  return h;
+}
+
+extern "C" int mbw_index_save(const mbw_index *ix, const char *path) {
+  if (!ix || !path) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
+  TRY(hipSetDevice(ix->device));
+  uint64_t kb = ix->kmer ? (1ull << (2 * ix->kmer_k)) * 16 : 0;
+  std::vector<uint8_t> lines(ix->n_lines * MBW_LINE_BYTES), ssa(ix->n_ssa * 8), kmer(kb);
+  TRY(hipMemcpy(lines.data(), ix->lines, lines.size(), hipMemcpyDeviceToHost));
+  TRY(hipMemcpy(ssa.data(), ix->ssa, ssa.size(), hipMemcpyDeviceToHost));
+  if (kb) TRY(hipMemcpy(kmer.data(), ix->kmer, kb, hipMemcpyDeviceToHost));
+  FileHeader hd;
+  memset(&hd, 0, sizeof(hd));
+  hd.magic = kMagic; hd.version = kVersion; hd.bpl = MBW_BPL;
+  hd.n = ix->n; hd.len_r = ix->len_r; hd.primary = ix->primary; hd.n_lines = ix->n_lines; hd.n_ssa = ix->n_ssa;
+  for (int a = 0; a < 5; ++a) hd.C[a] = ix->C[a];
+  hd.sa_sample = ix->sa_sample; hd.kmer_k = ix->kmer ? ix->kmer_k : 0; hd.bisulfite = ix->bisulfite;
+  hd.sum_lines = sum_words(lines.data(), lines.size());
+  hd.sum_ssa = sum_words(ssa.data(), ssa.size());
+  hd.sum_kmer = sum_words(kmer.data(), kmer.size());
+  hd.sum_header = fnv(&hd, offsetof(FileHeader, sum_header));
+  FILE *f = fopen(path, "wb");
+  if (!f) { mbw_set_error(std::string("cannot open ") + path); return MBW_E_IO; }
+  bool ok = fwrite(&hd, sizeof(hd), 1, f) == 1 && fwrite(lines.data(), 1, lines.size(), f) == lines.size() &&
+            fwrite(ssa.data(), 1, ssa.size(), f) == ssa.size() && (kb == 0 || fwrite(kmer.data(), 1, kb, f) == kb);
+  ok = (fclose(f) == 0) && ok;
+  if (!ok) { mbw_set_error(std::string("write failed: ") + path); return MBW_E_IO; }
+  return MBW_OK;
+}
+
+extern "C" int mbw_index_load(const char *path, int device, mbw_index **out) {
+  if (!path || !out) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
+  *out = nullptr;
+  FILE *f = fopen(path, "rb");
+  if (!f) { mbw_set_error(std::string("cannot open ") + path); return MBW_E_IO; }
+  FileHeader hd;
+  if (fread(&hd, sizeof(hd), 1, f) != 1) { fclose(f); mbw_set_error("short header"); return MBW_E_FORMAT; }
+  if (hd.magic != kMagic || hd.version != kVersion || hd.bpl != MBW_BPL ||
+      hd.sum_header != fnv(&hd, offsetof(FileHeader, sum_header)) || hd.n_lines != hd.n / MBW_BPL + 1 ||
+      hd.sa_sample < 1 || hd.sa_sample > 1024 || hd.n_ssa != (hd.n + hd.sa_sample - 1) / hd.sa_sample ||
+      hd.kmer_k < 0 || hd.kmer_k > 13) {
+    fclose(f); mbw_set_error("bad magic, version or header fields"); return MBW_E_FORMAT;
+  }
+  uint64_t kb = hd.kmer_k ? (1ull << (2 * hd.kmer_k)) * 16 : 0;
+  std::vector<uint8_t> lines, ssa, kmer;
+  try { lines.resize(hd.n_lines * MBW_LINE_BYTES); ssa.resize(hd.n_ssa * 8); kmer.resize(kb); }
+  catch (...) { fclose(f); mbw_set_error("host allocation failed"); return MBW_E_NOMEM; }
+  bool ok = fread(lines.data(), 1, lines.size(), f) == lines.size() && fread(ssa.data(), 1, ssa.size(), f) == ssa.size() &&
+            (kb == 0 || fread(kmer.data(), 1, kb, f) == kb);
+  fclose(f);
+  if (!ok) { mbw_set_error("truncated index file"); return MBW_E_FORMAT; }
+  if (sum_words(lines.data(), lines.size()) != hd.sum_lines || sum_words(ssa.data(), ssa.size()) != hd.sum_ssa ||
+      sum_words(kmer.data(), kmer.size()) != hd.sum_kmer) {
+    mbw_set_error("index checksum mismatch"); return MBW_E_FORMAT;
+  }
+  TRY(hipSetDevice(device));
+  mbw_index *ix = new mbw_index();
+  memset(ix, 0, sizeof(*ix));
+  ix->device = device; ix->n = hd.n; ix->len_r = hd.len_r; ix->primary = hd.primary; ix->n_lines = hd.n_lines;
+  ix->n_ssa = hd.n_ssa; for (int a = 0; a < 5; ++a) ix->C[a] = hd.C[a];
+  ix->sa_sample = hd.sa_sample; ix->kmer_k = hd.kmer_k; ix->bisulfite = hd.bisulfite;
+  int rc = [&]() -> int {
+    TRY(hipMalloc((void **)&ix->lines, lines.size()));
+    TRY(hipMemcpy(ix->lines, lines.data(), lines.size(), hipMemcpyHostToDevice));
+    TRY(hipMalloc((void **)&ix->ssa, ssa.size()));
+    TRY(hipMemcpy(ix->ssa, ssa.data(), ssa.size(), hipMemcpyHostToDevice));
+    if (kb) {
+      TRY(hipMalloc((void **)&ix->kmer, kb));
+      TRY(hipMemcpy(ix->kmer, kmer.data(), kb, hipMemcpyHostToDevice));
+    }
+    ix->bytes = lines.size() + ssa.size() + kb;
+    return 0;
+  }();
+  if (rc) { mbw_index_free(ix); return rc; }
+  *out = ix;
+  return MBW_OK;
+}

@@ -1,0 +1,79 @@
+"""Test helpers: run the GPU library and the oracle on the same seeded inputs and compare."""
+from __future__ import annotations
+
+import struct
+
+import numpy as np
+
+import oracle
+import paper_2606_15357_amd as mbw
+
+FIELDS = ("read_id", "qbeg", "qend", "k", "kr", "s", "npos")
+
+
+def gpu_seed(index, reads, **kw):
+    ctx = mbw.Context(index)
+    out = ctx.seed(reads.seq, reads.lengths, **kw)
+    seeds, pos = out.download()
+    ctx.free()
+    return out, seeds, pos
+
+
+def gpu_canonical(seeds, pos):
+    s, flat = mbw.canonical(seeds, pos)
+    return s, flat
+
+
+def compare_with_oracle(seeds, pos, ref_res, check_flags=True):
+    """Bit-exact comparison of a GPU result with an oracle SeedResult (canonical order)."""
+    s, flat = gpu_canonical(seeds, pos)
+    assert len(s) == len(ref_res), (len(s), len(ref_res))
+    for f in FIELDS:
+        a = s[f].astype(np.uint64)
+        b = getattr(ref_res, f).astype(np.uint64)
+        if not np.array_equal(a, b):
+            bad = np.nonzero(a != b)[0][:5]
+            raise AssertionError(f"field {f} differs at {bad}: gpu {a[bad]} oracle {b[bad]}; "
+                                 f"rows {[(int(s['read_id'][i]), int(s['qbeg'][i]), int(s['qend'][i])) for i in bad]}")
+    if check_flags:
+        assert np.array_equal((s["flags"] & 1).astype(np.uint32), ref_res.flags & 1)
+    assert np.array_equal(flat, ref_res.pos), "positions differ"
+
+
+HEADER = struct.Struct("<QII QQQQQ 5Q iiii QQQ Q")
+
+
+def read_index_file(path):
+    """Parse an index file written by mbw_index_save (the documented layout)."""
+    with open(path, "rb") as f:
+        raw = f.read()
+    h = HEADER.unpack_from(raw, 0)
+    (magic, version, bpl, n, len_r, primary, n_lines, n_ssa, c0, c1, c2, c3, c4, r, K, bis, _pad,
+     s1, s2, s3, sh) = h
+    off = HEADER.size
+    lines = np.frombuffer(raw, dtype=np.uint64, count=n_lines * 16, offset=off).reshape(n_lines, 16)
+    off += n_lines * 128
+    ssa = np.frombuffer(raw, dtype=np.uint64, count=n_ssa, offset=off)
+    off += n_ssa * 8
+    kmer = None
+    if K:
+        kmer = np.frombuffer(raw, dtype=np.uint64, count=2 * 4 ** K, offset=off).reshape(-1, 2)
+    return dict(n=n, len_r=len_r, primary=primary, n_lines=n_lines, C=[c0, c1, c2, c3, c4], r=r, K=K,
+                lines=lines, ssa=ssa, kmer=kmer, bpl=bpl)
+
+
+def decode_bwt(idx):
+    """BWT codes (0..3, $ row as A) from the occurrence lines."""
+    lines = idx["lines"]
+    bits = lines[:, 4:16]
+    sh = (np.arange(32, dtype=np.uint64) * 2)
+    syms = ((bits[:, :, None] >> sh[None, None, :]) & 3).reshape(lines.shape[0], -1)
+    return syms.reshape(-1)[: idx["n"]].astype(np.uint8)
+
+
+def unpack_kmer(e):
+    w0, w1 = int(e[0]), int(e[1])
+    k = w0 & ((1 << 40) - 1)
+    kr = (w0 >> 40) | ((w1 & 0xFFFF) << 24)
+    s = w1 >> 16
+    return k, kr, s

@@ -1,0 +1,225 @@
+"""GPU parity: the HIP library against the CPU oracle, element by element, through the C-ABI.
+
+Integer results must be bit-exact: same seeds (read, qbeg, qend), same ds-intervals (k, k', s),
+same position sets (canonical order: seeds by (read, qbeg, qend), positions ascending).
+"""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import brute
+import oracle
+import synth
+from mbw_helpers import compare_with_oracle, decode_bwt, gpu_seed, read_index_file, unpack_kmer
+
+mbw = pytest.importorskip("paper_2606_15357_amd")
+
+pytestmark = pytest.mark.gpu
+
+ACGT = "ACGT"
+
+
+def ref_codes(s):
+    return np.array(["ACGT".index(ch) for ch in s], dtype=np.uint8)
+
+
+def to_str(codes):
+    return "".join(ACGT[int(x)] for x in codes)
+
+
+def readset(reads):
+    lens = np.array([len(r) for r in reads], dtype=np.uint32)
+    offs = np.zeros(len(reads) + 1, np.uint64)
+    offs[1:] = np.cumsum(lens)
+    seq = np.frombuffer("".join(reads).encode(), dtype=np.uint8).copy()
+    return synth.ReadSet(seq, lens, offs, np.zeros(len(reads), np.uint64), np.zeros(len(reads), np.uint8))
+
+
+TINY = {
+    "random300": to_str(np.random.default_rng(1).integers(0, 4, 300)),
+    "homopolymer": "A" * 50,
+    "period2": "AC" * 40,
+    "palindrome": "ACGGTCAT" + brute.revcomp("ACGGTCAT"),
+    "len1": "G",
+    "repeats": "ACGTTGCAAG" * 5 + "GGATCCATTA" + "ACGTTGCAAG" * 4,
+}
+
+
+@pytest.mark.parametrize("name", sorted(TINY))
+@pytest.mark.parametrize("r,K", [(1, 0), (3, 2), (8, 3)])
+def test_index_structure(name, r, K):
+    """BWT, C, primary row, SA samples and k-mer intervals of the GPU index equal the oracle's."""
+    R = TINY[name]
+    idx = mbw.Index.build(ref_codes(R), sa_sample=r, kmer_k=K)
+    info = idx.info()
+    ox = oracle.OracleIndex(ref_codes(R), sa_rate=r)
+    with tempfile.TemporaryDirectory() as d:
+        p = os.path.join(d, "ix.mbw")
+        idx.save(p)
+        f = read_index_file(p)
+    assert f["n"] == ox.n and info["n"] == ox.n
+    assert info["primary"] == ox.primary
+    B = ox.bwt().astype(np.int64) - 1
+    B[ox.primary] = 0
+    assert np.array_equal(decode_bwt(f), B.astype(np.uint8))
+    assert [int(x) for x in info["C"]] == [int(x) for x in ox.C()[:5]]
+    SA = ox.sa()
+    assert np.array_equal(f["ssa"], SA[::r])
+    if K:
+        T = brute.text_of(R)
+        for code in range(4 ** K):
+            kmer = "".join(ACGT[(code >> (2 * (K - 1 - q))) & 3] for q in range(K))
+            exp = ox.interval(kmer)
+            got = unpack_kmer(f["kmer"][code])
+            if exp[2] == 0:
+                assert got[2] == 0
+            else:
+                assert got == exp, (kmer, got, exp)
+        assert T
+
+
+@pytest.mark.parametrize("name", sorted(TINY))
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_tiny_seeding(name, kernel):
+    R = TINY[name]
+    rng = np.random.default_rng(3)
+    reads = []
+    for _ in range(40):
+        if len(R) < 4:
+            break
+        i = int(rng.integers(0, len(R) - 3))
+        j = int(rng.integers(i + 3, min(len(R), i + 60) + 1))
+        s = list(R[i:j])
+        for t in range(len(s)):
+            if rng.random() < 0.05:
+                s[t] = ACGT[int(rng.integers(0, 4))]
+        s = "".join(s)
+        reads.append(s if rng.random() < 0.5 else brute.revcomp(s))
+    reads += ["ACGTACGTACGTAGCT", "NNNNACGTNN", "A", "", "GATTACAGATTACA"]
+    rs = readset(reads)
+    ox = oracle.OracleIndex(ref_codes(R), sa_rate=3)
+    for K in (0, 3):
+        idx = mbw.Index.build(ref_codes(R), sa_sample=3, kmer_k=K)
+        for (l, c) in [(3, 1), (5, 1), (4, 2), (2, 3)]:
+            for reseed in (False, True):
+                exp = ox.seed(rs.seq, rs.offsets, min_len=l, min_occ=c, max_occ=10 ** 6, reseed=reseed,
+                              reseed_len=2 * l, reseed_occ=3)
+                out, seeds, pos = gpu_seed(idx, rs, min_seed_len=l, min_occ=c, max_occ=10 ** 6, reseed=reseed,
+                                           reseed_len=2 * l, reseed_occ=3, kernel=kernel)
+                compare_with_oracle(seeds, pos, exp)
+        idx.free()
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    ref = synth.config_reference(0)
+    reads = synth.config_reads(0, ref)
+    ox = oracle.OracleIndex(ref.codes, sa_rate=8)
+    exp = ox.seed(reads.seq, reads.offsets, min_len=19, max_occ=500)
+    return ref, reads, ox, exp
+
+
+@pytest.mark.parametrize("kernel,K", [(0, 10), (0, 0), (1, 0), (0, 12)])
+def test_small_workload_parity(cfg0, kernel, K):
+    """1 Mbp + repeat family reference, 10,000 x 150 bp reads, (19,1)-SMEMs with re-seeding,
+    max_occ 500: every seed, interval and position equals the oracle's."""
+    ref, reads, ox, exp = cfg0
+    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=K)
+    out, seeds, pos = gpu_seed(idx, reads, min_seed_len=19, max_occ=500, kernel=kernel)
+    compare_with_oracle(seeds, pos, exp)
+    assert out.n_seeds == len(exp)
+    idx.free()
+
+
+def test_line_count_matches_oracle(cfg0):
+    """The kernel's algorithmic line counter equals the oracle's count for the same layout."""
+    ref, reads, ox, _ = cfg0
+    for K in (0, 10):
+        idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=K)
+        out, seeds, pos = gpu_seed(idx, reads, min_seed_len=19, max_occ=500, kernel=0)
+        o2 = ox.seed(reads.seq, reads.offsets, method=1, kmer_k=K, bases_per_line=384)
+        assert out.steps == o2.lines["steps"]
+        assert out.lines_smem == o2.lines["lines"] - o2.lines["lf_steps"] + o2.lines["kmer_lookups"]
+        assert out.lf_steps == o2.lines["lf_steps"]
+        assert out.lines_locate == o2.lines["lf_steps"] + o2.lines["sa_reads"]
+        idx.free()
+
+
+def test_edge_cases(cfg0):
+    ref, _, ox, _ = cfg0
+    R = to_str(ref.codes[:5000])
+    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=10)
+    ctx = mbw.Context(idx)
+    # empty batch
+    out = ctx.seed(np.zeros(0, np.uint8), np.zeros(0, np.uint32))
+    assert out.n_seeds == 0 and out.n_pos == 0
+    # reads shorter than l, empty reads, N runs, lower case, ragged lengths
+    reads = ["", "A", R[:18], R[:19], R[100:400].lower(), R[500:600] + "N" * 30 + R[700:800],
+             R[1000:1001 + 250], "N" * 40, R[2000:2150]]
+    rs = readset(reads)
+    for kernel in (0, 1):
+        out, seeds, pos = gpu_seed(idx, rs, kernel=kernel)
+        exp = ox.seed(rs.seq, rs.offsets)
+        compare_with_oracle(seeds, pos, exp)
+    # a single maximal-length read (65535) and an over-long one
+    long = to_str(ref.codes[10000:10000 + 65535])
+    rs = readset([long])
+    out, seeds, pos = gpu_seed(idx, rs, kernel=0)
+    exp = ox.seed(rs.seq, rs.offsets)
+    compare_with_oracle(seeds, pos, exp)
+    with pytest.raises(mbw.MbwError):
+        ctx.seed(np.frombuffer((long + "A").encode(), np.uint8).copy(), np.array([65536], np.uint32))
+    with pytest.raises(mbw.MbwError):
+        ctx.seed(rs.seq, rs.lengths, min_seed_len=0)
+    ctx.free()
+    idx.free()
+
+
+def test_ragged_lengths_and_occ(cfg0):
+    """Ragged read lengths 1..600, c in {1,2,3}, max_occ small enough to skip repeats."""
+    ref, _, ox, _ = cfg0
+    rs = synth.reads_uniform_len(ref, 3000, 1, 600, seed=77)
+    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=10)
+    for c, mo in [(1, 3), (2, 500), (3, 20)]:
+        for kernel in (0, 1):
+            out, seeds, pos = gpu_seed(idx, rs, min_occ=c, max_occ=mo, kernel=kernel)
+            exp = ox.seed(rs.seq, rs.offsets, min_occ=c, max_occ=mo)
+            compare_with_oracle(seeds, pos, exp)
+    idx.free()
+
+
+def test_bisulfite_parity():
+    ref = synth.reference(0, 200_000, 31)
+    ox = oracle.OracleIndex(ref.codes, bisulfite=True, sa_rate=8)
+    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=10, bisulfite=True)
+    rs = synth.reads_bisulfite(ref, 2000, seed=5)
+    for role in (1, 2):
+        for kernel in (0, 1):
+            out, seeds, pos = gpu_seed(idx, rs, bs_role=role, kernel=kernel)
+            exp = ox.seed(rs.seq, rs.offsets, bs_role=role)
+            compare_with_oracle(seeds, pos, exp)
+    idx.free()
+
+
+def test_index_save_load_roundtrip(cfg0):
+    ref, reads, ox, exp = cfg0
+    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=10)
+    with tempfile.TemporaryDirectory() as d:
+        p = os.path.join(d, "cfg0.mbw")
+        idx.save(p)
+        idx2 = mbw.Index.load(p)
+        out, seeds, pos = gpu_seed(idx2, reads)
+        compare_with_oracle(seeds, pos, exp)
+        # corrupt one byte in the middle: the checksum must catch it
+        with open(p, "r+b") as f:
+            f.seek(4096)
+            b = f.read(1)
+            f.seek(4096)
+            f.write(bytes([b[0] ^ 0xFF]))
+        with pytest.raises(mbw.MbwError) as e:
+            mbw.Index.load(p)
+        assert e.value.code == mbw.MBW_E_FORMAT
+        idx2.free()
+    idx.free()
