@@ -113,8 +113,14 @@ typedef struct {
   int use_kmer;       /* use the index's k-mer table in the cooperative kernel */
   int groups_per_block; /* cooperative kernels: 8-lane groups per workgroup (0 = default 32) */
   int blocks_per_cu;  /* persistent grid size per compute unit (0 = occupancy limit) */
-  int grab;           /* queries taken per work-queue fetch (0 = default) */
+  int grab;           /* queries taken per work-queue fetch (0 = default 8) */
+  int grab_locate;    /* SA rows taken per locate work-queue fetch (0 = default 64) */
+  int schedule;       /* cooperative kernels: MBW_SCHED_WAVE (default: one query per lane, lines
+                         fetched by the whole wave) or MBW_SCHED_GROUP8 (eight lanes per query) */
 } mbw_seed_opts;
+
+#define MBW_SCHED_WAVE   0
+#define MBW_SCHED_GROUP8 1
 
 #define MBW_KERNEL_COOP  0
 #define MBW_KERNEL_PLAIN 1
@@ -142,7 +148,10 @@ typedef struct {
   uint64_t lines_locate;   /* ... by locate (LF steps + SA-sample reads)                          */
   uint64_t steps;          /* extension steps (Algorithm 1 calls) */
   uint64_t lf_steps;       /* LF steps in locate */
-  float ms_smem, ms_locate, ms_total; /* device time of the phases (HIP events) */
+  float ms_smem;            /* device time of the SMEM kernel launches (HIP events around each) */
+  float ms_locate;          /* device time of the locate kernel launch */
+  float ms_total;           /* device time of the whole call */
+  int n_smem_launches;      /* SMEM kernel launches in this call (round 1, round 2) */
 } mbw_result;
 
 /* Seed a batch of reads.

@@ -65,7 +65,8 @@ void mbw_set_error(const std::string &msg);
 // ---------------------------------------------------------------------------------------------
 // device helpers
 
-__device__ __forceinline__ uint64_t line_of(uint64_t x) { return x / MBW_BPL; }
+// x / 384 = (x >> 7) / 3, the division by 3 as a multiply-high by ceil(2^65 / 3)
+__device__ __forceinline__ uint64_t line_of(uint64_t x) { return __umul64hi(x >> 7, 0xAAAAAAAAAAAAAAABull) >> 1; }
 
 #define M55 0x5555555555555555ull
 
@@ -122,6 +123,10 @@ __device__ __forceinline__ void group_header(uint4 d, uint64_t hdr[4]) {
   hdr[3] = __shfl(hi, 1, MBW_GROUP);
 }
 
+__device__ __forceinline__ uint64_t sel4(uint64_t a0, uint64_t a1, uint64_t a2, uint64_t a3, int c) {
+  return c == 0 ? a0 : (c == 1 ? a1 : (c == 2 ? a2 : a3));
+}
+
 // Algorithm 1 as one unified step.  (x, y, s) is the interval with x the side that is LF-mapped
 // (backward: (k, k'), forward: (k', k)) and c the symbol mapped (backward: a, forward: comp(a)).
 //   s'  = Occ(c, x+s) - Occ(c, x)
@@ -132,14 +137,71 @@ __device__ __forceinline__ void group_header(uint4 d, uint64_t hdr[4]) {
 __device__ __forceinline__ void ext_update(const Occ4 &o1, const Occ4 &o2, int c, uint64_t x, uint64_t s,
                                            uint64_t y, uint64_t primary, const uint64_t Cb[4],
                                            uint64_t &nx, uint64_t &ny, uint64_t &ns) {
-  uint64_t a1 = o1.v[c], a2 = o2.v[c];
-  uint64_t gt = 0;
-#pragma unroll
-  for (int d = 0; d < 4; ++d) gt += (d > c) ? (o2.v[d] - o1.v[d]) : 0;
+  uint64_t a1 = sel4(o1.v[0], o1.v[1], o1.v[2], o1.v[3], c);
+  uint64_t a2 = sel4(o2.v[0], o2.v[1], o2.v[2], o2.v[3], c);
+  uint64_t gt = (c < 1 ? o2.v[1] - o1.v[1] : 0) + (c < 2 ? o2.v[2] - o1.v[2] : 0) + (c < 3 ? o2.v[3] - o1.v[3] : 0);
   uint64_t dol = (x <= primary && primary < x + s) ? 1 : 0;
   ns = a2 - a1;
-  nx = Cb[c] + a1;
+  nx = sel4(Cb[0], Cb[1], Cb[2], Cb[3], c) + a1;
   ny = y + dol + gt;
+}
+
+// ---- cooperative rank: eight lanes, one 16-byte slice of a 128-byte line each ----------------
+
+// DPP exchanges inside each group of eight lanes (quad_perm [1,0,3,2], [2,3,0,1], row_half_mirror)
+__device__ __forceinline__ uint32_t dpp_x1(uint32_t v) { return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false); }
+__device__ __forceinline__ uint32_t dpp_x2(uint32_t v) { return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false); }
+__device__ __forceinline__ uint32_t dpp_hm(uint32_t v) { return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false); }
+__device__ __forceinline__ uint64_t dpp64(uint64_t v, int which) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  if (which == 0) { lo = dpp_x1(lo); hi = dpp_x1(hi); }
+  else if (which == 1) { lo = dpp_x2(lo); hi = dpp_x2(hi); }
+  else { lo = dpp_hm(lo); hi = dpp_hm(hi); }
+  return ((uint64_t)hi << 32) | lo;
+}
+// sum over the eight lanes of the group, result in every lane
+__device__ __forceinline__ uint64_t grp_sum64(uint64_t v) {
+  v += dpp64(v, 0);
+  v += dpp64(v, 1);
+  v += dpp64(v, 2);
+  return v;
+}
+__device__ __forceinline__ uint32_t grp_sum32(uint32_t v) {
+  v += dpp_x1(v);
+  v += dpp_x2(v);
+  v += dpp_hm(v);
+  return v;
+}
+
+// rows of symbol c (eq) and of symbols greater than c (gt) among the first m (0..32) rows of a word
+__device__ __forceinline__ void word_eq_gt(uint64_t w, int m, int c, uint32_t &eq, uint32_t &gt) {
+  uint64_t mask = m >= 32 ? M55 : (((1ull << (2 * m)) - 1) & M55);
+  uint64_t hi = (w >> 1) & M55, lo = w & M55;
+  uint64_t e = c == 0 ? ~(hi | lo) : (c == 1 ? (~hi & lo) : (c == 2 ? (hi & ~lo) : (hi & lo)));
+  uint64_t g = c == 0 ? (hi | lo) : (c == 1 ? hi : (c == 2 ? (hi & lo) : 0ull));
+  eq = __popcll(e & mask);
+  gt = __popcll(g & mask);
+}
+
+// This lane's share of Occ(c, x) (E) and of sum_{d>c} Occ(d, x) (G), x at offset o of the line
+// whose slice q is d: slices 0/1 contribute the line's prefix counts, slices 2..7 their rows < o.
+__device__ __forceinline__ void slice_eg(uint4 d, int q, int o, int c, uint64_t &E, uint64_t &G) {
+  uint64_t w0 = ((uint64_t)d.y << 32) | d.x, w1 = ((uint64_t)d.w << 32) | d.z;
+  if (q == 0) {            // counts of A, C
+    E = c == 0 ? w0 : (c == 1 ? w1 : 0);
+    G = c == 0 ? w1 : 0;
+  } else if (q == 1) {     // counts of G, T
+    E = c == 2 ? w0 : (c == 3 ? w1 : 0);
+    G = (c <= 1 ? w0 : 0) + (c <= 2 ? w1 : 0);
+  } else {
+    int m = o - (q - 2) * 64;
+    m = m < 0 ? 0 : (m > 64 ? 64 : m);
+    uint32_t e0, g0, e1, g1;
+    word_eq_gt(w0, m < 32 ? m : 32, c, e0, g0);
+    word_eq_gt(w1, m > 32 ? m - 32 : 0, c, e1, g1);
+    E = e0 + e1;
+    G = g0 + g1;
+  }
 }
 
 // unpack a k-mer table entry (k:40 | k':40 | s:40)

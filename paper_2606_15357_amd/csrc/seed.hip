@@ -32,6 +32,7 @@
 namespace {
 
 struct Query { uint32_t read_id, qbeg, qend, l, c; };
+#define INVALID_READ 0xFFFFFFFFu   // unused slot of a per-wave output chunk
 struct SeedRec { uint32_t read_id, qbeg, qend, flags; uint64_t k, kr, s; };
 
 // control block (device): counters shared by the kernels of one call
@@ -53,9 +54,21 @@ struct SeedParams {
   unsigned long long *__restrict__ ctl;
 };
 
+// Append one seed (and, in round 1, its re-seeding query) from whatever lanes are active here:
+// one atomic per group of simultaneously emitting lanes.
+__device__ __forceinline__ uint64_t active_slot(unsigned long long *counter) {
+  const uint64_t m = __ballot(1);
+  const int lane = (int)(threadIdx.x & 63);
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  unsigned long long b0 = 0;
+  if (lane == leader) b0 = atomicAdd(counter, (unsigned long long)__popcll(m));
+  b0 = __shfl(b0, leader);
+  return b0 + __popcll(m & ((1ull << lane) - 1));
+}
+
 __device__ __forceinline__ void emit_seed(const SeedParams &P, uint32_t read_id, int i, int j, uint64_t k, uint64_t kr,
                                           uint64_t s) {
-  unsigned long long slot = atomicAdd(&P.ctl[C_NSEEDS], 1ull);
+  const uint64_t slot = active_slot(&P.ctl[C_NSEEDS]);
   if (slot < P.seed_cap) {
     SeedRec r;
     r.read_id = read_id; r.qbeg = (uint32_t)i; r.qend = (uint32_t)j; r.flags = P.round == 2 ? MBW_SEED_ROUND2 : 0u;
@@ -63,7 +76,7 @@ __device__ __forceinline__ void emit_seed(const SeedParams &P, uint32_t read_id,
     P.seeds[slot] = r;
   }
   if (P.round == 1 && P.reseed && j - i >= P.reseed_len && s <= (uint64_t)P.reseed_occ) {
-    unsigned long long qs = atomicAdd(&P.ctl[C_NSUBQ], 1ull);
+    const uint64_t qs = active_slot(&P.ctl[C_NSUBQ]);
     if (qs < P.subq_cap) {
       Query q; q.read_id = read_id; q.qbeg = (uint32_t)i; q.qend = (uint32_t)j; q.l = (uint32_t)((j - i) / 2);
       q.c = (uint32_t)(s + 1);
@@ -151,7 +164,7 @@ __global__ void __launch_bounds__(256) k_smem_coop(IndexView ix, SeedParams P) {
       }
       uint64_t qi = qnext++;
       load_query(P, qi, read_id, qbeg, qend, l, c);
-      if (!(l >= 1 && l - 1 < qend - qbeg)) continue;   // Algorithm 3 queues a string only if l-1 < |P|
+      if (read_id == INVALID_READ || !(l >= 1 && l - 1 < qend - qbeg)) continue;   // Algorithm 3 queues a string only if l-1 < |P|
       rb = P.codes + P.offs[read_id];
       if (SLOT > 0) {
         int len = (int)(qend - qbeg);
@@ -222,14 +235,21 @@ __global__ void __launch_bounds__(256) k_smem_coop(IndexView ix, SeedParams P) {
     if (L2 != L1) d2 = ix.lines[L2 * MBW_LINE_U4 + q];
     n_lines += (L2 != L1) ? 2 : 1;
     ++n_steps;
-    uint64_t h1[4], h2[4];
-    group_header(d1, h1);
-    group_header(d2, h2);
-    uint64_t in1 = group_sum(slice_counts(d1, q, (int)(x - L1 * MBW_BPL)));
-    uint64_t in2 = group_sum(slice_counts(d2, q, (int)(x2 - L2 * MBW_BPL)));
-    Occ4 o1 = occ_from(h1, in1, x, ix.primary), o2 = occ_from(h2, in2, x2, ix.primary);
-    uint64_t nx, ny, ns;
-    ext_update(o1, o2, cc, x, s, y, ix.primary, ix.Cb, nx, ny, ns);
+    uint64_t E1, G1, E2, G2;
+    slice_eg(d1, q, (int)(x - L1 * MBW_BPL), cc, E1, G1);
+    slice_eg(d2, q, (int)(x2 - L2 * MBW_BPL), cc, E2, G2);
+    uint64_t sE1 = grp_sum64(E1);
+    uint64_t dE = grp_sum64(E2 - E1);
+    uint64_t dG = grp_sum64(G2 - G1);
+    if (cc == 0) {                      // the $ row is stored as A
+      uint64_t c1 = x > ix.primary ? 1 : 0, c2 = x2 > ix.primary ? 1 : 0;
+      sE1 -= c1;
+      dE -= c2 - c1;
+    }
+    const uint64_t dol = (x <= ix.primary && ix.primary < x2) ? 1 : 0;
+    const uint64_t ns = dE;
+    const uint64_t nx = sel4(ix.Cb[0], ix.Cb[1], ix.Cb[2], ix.Cb[3], cc) + sE1;
+    const uint64_t ny = y + dol + dG;
     if (ns >= c) {
       if (bwd) { k = nx; kr = ny; s = ns; j -= 1; }
       else { kr = nx; k = ny; s = ns; j += 1; }
@@ -248,6 +268,289 @@ __global__ void __launch_bounds__(256) k_smem_coop(IndexView ix, SeedParams P) {
     atomicAdd(&P.ctl[C_STEPS], (unsigned long long)n_steps);
     atomicAdd(&P.ctl[C_KMER], (unsigned long long)n_kmer);
   }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Wave-cooperative fetch (default schedule): every lane owns one query (or one locate walk).  Each
+// step the wave gathers the lines its lanes need with eight 16-byte loads per lane: in load t, the
+// eight lanes 8g..8g+7 fetch the eight slices of the line wanted by lane 8t+g, so one instruction
+// moves eight whole 128-byte lines.  The slices land in LDS (8 KB per wave, rotated by lane to
+// spread banks) and each lane then ranks its own line without any cross-lane reduction.
+#define WAVE_U4 (64 * MBW_LINE_U4)
+
+__device__ __forceinline__ int slot_of(int r, int j) { return r * MBW_LINE_U4 + ((j + r) & 7); }
+
+#define WF_LOAD(t)                                                                             \
+  {                                                                                            \
+    const int src = 8 * (t) + (lane >> 3);                                                     \
+    const uint32_t Ls = (uint32_t)__shfl((int)myL, src);                                       \
+    if (__shfl((int)myneed, src)) d##t = lines[(uint64_t)Ls * MBW_LINE_U4 + (lane & 7)];       \
+  }
+#define WF_STORE(t) buf[slot_of(8 * (t) + (lane >> 3), lane & 7)] = d##t;
+
+// Slices of lanes that need nothing are stored too (stale data in slots nobody reads).
+__device__ __forceinline__ void wave_fetch(const uint4 *__restrict__ lines, uint32_t myL, bool myneed, uint4 *buf, int lane) {
+  uint4 d0 = make_uint4(0, 0, 0, 0), d1 = d0, d2 = d0, d3 = d0, d4 = d0, d5 = d0, d6 = d0, d7 = d0;
+  WF_LOAD(0) WF_LOAD(1) WF_LOAD(2) WF_LOAD(3) WF_LOAD(4) WF_LOAD(5) WF_LOAD(6) WF_LOAD(7)
+  WF_STORE(0) WF_STORE(1) WF_STORE(2) WF_STORE(3) WF_STORE(4) WF_STORE(5) WF_STORE(6) WF_STORE(7)
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ uint64_t pmask(int m) { return m >= 32 ? M55 : (((1ull << (2 * (m < 0 ? 0 : m))) - 1) & M55); }
+__device__ __forceinline__ uint64_t eq_bits(uint64_t w, int c) {
+  uint64_t hi = (w >> 1) & M55, lo = w & M55;
+  return c == 0 ? (~(hi | lo) & M55) : (c == 1 ? (~hi & lo) : (c == 2 ? (hi & ~lo) : (hi & lo)));
+}
+__device__ __forceinline__ uint64_t gt_bits(uint64_t w, int c) {
+  uint64_t hi = (w >> 1) & M55, lo = w & M55;
+  return c == 0 ? (hi | lo) : (c == 1 ? hi : (c == 2 ? (hi & lo) : 0ull));
+}
+
+// Occ(c, .) (E) and sum_{d>c} Occ(d, .) (G) at offsets o1 and o2 (o2 < 0: not needed) of the line
+// staged for this lane; $ not corrected.
+__device__ __forceinline__ void lane_eg(const uint4 *buf, int lane, int c, int o1, int o2, uint64_t &E1, uint64_t &G1,
+                                        uint64_t &E2, uint64_t &G2) {
+  const uint4 h0 = buf[slot_of(lane, 0)], h1 = buf[slot_of(lane, 1)];
+  const uint64_t cA = ((uint64_t)h0.y << 32) | h0.x, cC = ((uint64_t)h0.w << 32) | h0.z;
+  const uint64_t cG = ((uint64_t)h1.y << 32) | h1.x, cT = ((uint64_t)h1.w << 32) | h1.z;
+  const uint64_t he = sel4(cA, cC, cG, cT, c);
+  const uint64_t hg = (c < 1 ? cC : 0) + (c < 2 ? cG : 0) + (c < 3 ? cT : 0);
+  uint32_t e1 = 0, g1 = 0, e2 = 0, g2 = 0;
+  const int omax = o1 > o2 ? o1 : o2;
+#pragma unroll
+  for (int sl = 2; sl < 8; ++sl) {
+    const int base = (sl - 2) * 64;
+    if (base < omax) {
+      const uint4 d = buf[slot_of(lane, sl)];
+      const uint64_t w0 = ((uint64_t)d.y << 32) | d.x, w1 = ((uint64_t)d.w << 32) | d.z;
+      const uint64_t ea = eq_bits(w0, c), eb = eq_bits(w1, c), ga = gt_bits(w0, c), gb = gt_bits(w1, c);
+      const int m1 = o1 - base, m2 = o2 - base;
+      const uint64_t p1a = pmask(m1), p1b = pmask(m1 - 32), p2a = pmask(m2), p2b = pmask(m2 - 32);
+      e1 += __popcll(ea & p1a) + __popcll(eb & p1b);
+      g1 += __popcll(ga & p1a) + __popcll(gb & p1b);
+      e2 += __popcll(ea & p2a) + __popcll(eb & p2b);
+      g2 += __popcll(ga & p2a) + __popcll(gb & p2b);
+    }
+  }
+  E1 = he + e1; G1 = hg + g1; E2 = he + e2; G2 = hg + g2;
+}
+
+struct Emit { uint32_t i, j; uint64_t k, kr, s; };
+
+// Work and output are handed out in chunks per wave so that hot counters see one atomic per chunk
+// (device-scope atomics on a single address serialise).  All 64 lanes must call these together.
+#define WORK_CHUNK 256
+#define OUT_CHUNK 256
+
+// Give each lane with `want` the next item of the wave's current chunk (grabbing new chunks as
+// needed); returns the item or ~0 when the queue is exhausted.
+__device__ __forceinline__ uint64_t wave_take(bool want, uint64_t &cb, uint64_t &ce, unsigned long long *counter,
+                                              uint64_t total, int lane) {
+  uint64_t m = __ballot(want);
+  uint64_t res = ~0ull;
+  const uint64_t below = (1ull << lane) - 1;
+  while (m) {
+    if (cb >= ce) {
+      unsigned long long b0 = 0;
+      if (lane == 0) b0 = atomicAdd(counter, (unsigned long long)WORK_CHUNK);
+      b0 = __shfl(b0, 0);
+      if (b0 >= total) { cb = ce = total; break; }
+      cb = b0;
+      ce = b0 + WORK_CHUNK < total ? b0 + WORK_CHUNK : total;
+    }
+    const uint64_t avail = ce - cb;
+    const uint32_t rank = __popcll(m & below);
+    const bool mine = ((m >> lane) & 1) && rank < avail;
+    if (mine) res = cb + rank;
+    const uint64_t got = __ballot(mine);
+    cb += __popcll(got);
+    m &= ~got;
+  }
+  return res;
+}
+
+// Reserve one output slot for every lane with `em`, from the wave's current output chunk.
+// Slots past `cap` are reported as ~0 (the host grows the buffer and runs again).
+__device__ __forceinline__ uint64_t wave_slot(bool em, uint64_t &ob, uint64_t &oe, unsigned long long *counter, int lane) {
+  uint64_t m = __ballot(em);
+  uint64_t res = ~0ull;
+  const uint64_t below = (1ull << lane) - 1;
+  while (m) {
+    if (ob >= oe) {
+      unsigned long long b0 = 0;
+      if (lane == 0) b0 = atomicAdd(counter, (unsigned long long)OUT_CHUNK);
+      b0 = __shfl(b0, 0);
+      ob = b0;
+      oe = b0 + OUT_CHUNK;
+    }
+    const uint64_t avail = oe - ob;
+    const uint32_t rank = __popcll(m & below);
+    const bool mine = ((m >> lane) & 1) && rank < avail;
+    if (mine) res = ob + rank;
+    const uint64_t got = __ballot(mine);
+    ob += __popcll(got);
+    m &= ~got;
+  }
+  return res;
+}
+
+struct WaveOut { uint64_t sb, se, qb, qe; };
+
+__device__ __forceinline__ void wave_emit(const SeedParams &P, int lane, bool em, uint32_t read_id, const Emit &e, WaveOut &wo) {
+  if (!__ballot(em)) return;
+  const uint64_t slot = wave_slot(em, wo.sb, wo.se, &P.ctl[C_NSEEDS], lane);
+  if (em && slot < P.seed_cap) {
+    SeedRec r;
+    r.read_id = read_id; r.qbeg = e.i; r.qend = e.j; r.flags = P.round == 2 ? MBW_SEED_ROUND2 : 0u;
+    r.k = e.k; r.kr = e.kr; r.s = e.s;
+    P.seeds[slot] = r;
+  }
+  const bool rq = em && P.round == 1 && P.reseed && (int)(e.j - e.i) >= P.reseed_len && e.s <= (uint64_t)P.reseed_occ;
+  if (!__ballot(rq)) return;
+  const uint64_t qs = wave_slot(rq, wo.qb, wo.qe, &P.ctl[C_NSUBQ], lane);
+  if (rq && qs < P.subq_cap) {
+    Query q; q.read_id = read_id; q.qbeg = e.i; q.qend = e.j; q.l = (e.j - e.i) / 2; q.c = (uint32_t)(e.s + 1);
+    P.subq[qs] = q;
+  }
+}
+
+// mark the unused tail of the wave's output chunks invalid
+__device__ __forceinline__ void wave_close(const SeedParams &P, int lane, const WaveOut &wo) {
+  for (uint64_t t = wo.sb + lane; t < wo.se; t += 64)
+    if (t < P.seed_cap) { SeedRec r; r.read_id = INVALID_READ; r.qbeg = r.qend = r.flags = 0; r.k = r.kr = r.s = 0; P.seeds[t] = r; }
+  for (uint64_t t = wo.qb + lane; t < wo.qe; t += 64)
+    if (t < P.subq_cap) { Query q; q.read_id = INVALID_READ; q.qbeg = q.qend = q.l = 0; q.c = 1; P.subq[t] = q; }
+}
+
+__global__ void __launch_bounds__(256) k_smem_wave(IndexView ix, SeedParams P) {
+  __shared__ uint4 lbuf[4 * WAVE_U4];
+  const int lane = threadIdx.x & 63;
+  uint4 *buf = lbuf + (threadIdx.x >> 6) * WAVE_U4;
+  const int K = (P.use_kmer && ix.kmer) ? ix.K : 0;
+  const uint8_t *rb = nullptr;
+  uint32_t read_id = 0, qbeg = 0, qend = 0, l = 0, c = 1;
+  int u = 0, i = 0, j = 0;
+  uint64_t k = 0, kr = 0, s = 0, budget = 0;
+  bool fresh = false, active = false, drained = false;
+  uint64_t n_lines = 0, n_steps = 0, n_kmer = 0;
+  uint64_t cb = 0, ce = 0;
+  WaveOut wo = {0, 0, 0, 0};
+  for (;;) {
+    // ---- refill idle lanes from the wave's work chunk
+    const bool want = !active && !drained;
+    if (__ballot(want)) {
+      const uint64_t qi = wave_take(want, cb, ce, &P.ctl[C_WORK], P.n_queries, lane);
+      if (want) {
+        if (qi == ~0ull) drained = true;
+        else {
+          load_query(P, qi, read_id, qbeg, qend, l, c);
+          if (read_id != INVALID_READ && l >= 1 && l - 1 < qend - qbeg) {
+            rb = P.codes + P.offs[read_id];
+            u = 1; i = (int)qbeg; j = (int)(qbeg + l - 1);
+            k = 0; kr = 0; s = ix.n; fresh = true; active = true;
+            budget = 8ull * (qend - qbeg) * (qend - qbeg) + 64;
+          }
+        }
+      }
+    }
+    if (__ballot(active) == 0) {
+      if (__ballot(!drained) == 0) break;
+      continue;
+    }
+    // ---- per-lane stage transitions up to the next memory action
+    int act = ACT_DONE, a = 0;
+    uint32_t code = 0;
+    bool em = false;
+    Emit e;
+    e.i = 0; e.j = 0; e.k = 0; e.kr = 0; e.s = 0;
+    if (active) {
+      if (--budget == 0) { atomicOr(&P.ctl[C_ERR], 1ull); active = false; }
+    }
+    if (active) {
+      for (;;) {
+        if (u == 2) {
+          if (j == (int)qend) { em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s; act = ACT_DONE; break; }
+          a = rb[j];
+          if (a > 3) {
+            em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s;
+            u = 3; k = 0; kr = 0; s = ix.n; fresh = true;
+            continue;
+          }
+          act = ACT_FWD; break;
+        }
+        if (u == 1 && j < i) { u = 2; j = i + (int)l; fresh = false; continue; }
+        if (u == 3 && j <= i) { u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; continue; }
+        if (fresh && K > 0 && j - K + 1 >= (u == 1 ? i : i + 1)) {
+          bool ok = true;
+          code = 0;
+          for (int t = j - K + 1; t <= j; ++t) { int b = rb[t]; ok = ok && b < 4; code = code * 4 + (uint32_t)(b & 3); }
+          fresh = false;
+          if (ok) { act = ACT_KMER; break; }
+        }
+        fresh = false;
+        a = rb[j];
+        if (a > 3) {
+          if (j + (int)l < (int)qend) { u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; continue; }
+          act = ACT_DONE; break;
+        }
+        act = ACT_BWD; break;
+      }
+      if (act == ACT_DONE) active = false;
+    }
+    // ---- k-mer lookups (one 16-byte load per lane)
+    if (act == ACT_KMER) {
+      uint64_t ek, ekr, es;
+      kmer_unpack(ix.kmer[code], ek, ekr, es);
+      ++n_kmer;
+      if (es >= c) { k = ek; kr = ekr; s = es; j -= K; }
+    }
+    // ---- extension steps (Algorithm 1) with the wave-cooperative fetch
+    const bool ext = act == ACT_BWD || act == ACT_FWD;
+    const bool bwd = act == ACT_BWD;
+    const uint64_t x1 = bwd ? k : kr, y = bwd ? kr : k;
+    const int cc = bwd ? a : 3 - a;
+    const uint64_t x2 = x1 + s;
+    const uint32_t L1 = ext ? (uint32_t)line_of(x1) : 0u, L2 = ext ? (uint32_t)line_of(x2) : 0u;
+    if (__ballot(ext)) {
+      wave_fetch(ix.lines, L1, ext, buf, lane);
+      const bool same = L1 == L2;
+      uint64_t E1 = 0, G1 = 0, E2 = 0, G2 = 0;
+      if (ext) lane_eg(buf, lane, cc, (int)(x1 - (uint64_t)L1 * MBW_BPL), same ? (int)(x2 - (uint64_t)L2 * MBW_BPL) : -1,
+                       E1, G1, E2, G2);
+      const bool two = ext && !same;
+      if (__ballot(two)) {
+        wave_fetch(ix.lines, L2, two, buf, lane);
+        if (two) {
+          uint64_t t1, t2;
+          lane_eg(buf, lane, cc, (int)(x2 - (uint64_t)L2 * MBW_BPL), -1, E2, G2, t1, t2);
+        }
+      }
+      if (ext) {
+        n_lines += two ? 2 : 1;
+        ++n_steps;
+        if (cc == 0) { E1 -= x1 > ix.primary ? 1 : 0; E2 -= x2 > ix.primary ? 1 : 0; }
+        const uint64_t dol = (x1 <= ix.primary && ix.primary < x2) ? 1 : 0;
+        const uint64_t ns = E2 - E1;
+        const uint64_t nx = sel4(ix.Cb[0], ix.Cb[1], ix.Cb[2], ix.Cb[3], cc) + E1;
+        const uint64_t ny = y + dol + (G2 - G1);
+        if (ns >= c) {
+          if (bwd) { k = nx; kr = ny; s = ns; j -= 1; }
+          else { kr = nx; k = ny; s = ns; j += 1; }
+        } else if (bwd) {
+          if (j + (int)l < (int)qend) { u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; }
+          else active = false;
+        } else {
+          em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s;
+          u = 3; k = 0; kr = 0; s = ix.n; fresh = true;
+        }
+      }
+    }
+    wave_emit(P, lane, em, read_id, e, wo);
+  }
+  wave_close(P, lane, wo);
+  atomicAdd(&P.ctl[C_LINES], (unsigned long long)(n_lines + n_kmer));
+  atomicAdd(&P.ctl[C_STEPS], (unsigned long long)n_steps);
+  atomicAdd(&P.ctl[C_KMER], (unsigned long long)n_kmer);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -341,17 +644,20 @@ __global__ void __launch_bounds__(256) k_smem_plain(IndexView ix, SeedParams P) 
 
 // ---------------------------------------------------------------------------------------------
 // seeds: sort keys, dedup, counts
-__global__ void k_seed_keys(const SeedRec *__restrict__ raw, uint64_t ns, uint64_t *__restrict__ key, uint32_t *__restrict__ val) {
+// sort key (read, qbeg, qend); unused slots (read_id INVALID_READ) get key n_reads << 32, after all
+__global__ void k_seed_keys(const SeedRec *__restrict__ raw, uint64_t ns, uint64_t n_reads, uint64_t *__restrict__ key,
+                            uint32_t *__restrict__ val) {
   for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < ns; t += (uint64_t)gridDim.x * blockDim.x) {
     SeedRec r = raw[t];
-    key[t] = ((uint64_t)r.read_id << 32) | ((uint64_t)r.qbeg << 16) | (uint64_t)r.qend;
+    key[t] = r.read_id == INVALID_READ ? (n_reads << 32)
+                                       : (((uint64_t)r.read_id << 32) | ((uint64_t)r.qbeg << 16) | (uint64_t)r.qend);
     val[t] = (uint32_t)t;
   }
 }
 
-__global__ void k_dedup_mark(const uint64_t *__restrict__ key, uint64_t ns, uint32_t *__restrict__ flag) {
+__global__ void k_dedup_mark(const uint64_t *__restrict__ key, uint64_t ns, uint64_t n_reads, uint32_t *__restrict__ flag) {
   for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < ns; t += (uint64_t)gridDim.x * blockDim.x)
-    flag[t] = (t == 0 || key[t] != key[t - 1]) ? 1u : 0u;
+    flag[t] = (key[t] < (n_reads << 32) && (t == 0 || key[t] != key[t - 1])) ? 1u : 0u;
 }
 
 __global__ void k_seed_emit(const SeedRec *__restrict__ raw, const uint32_t *__restrict__ val, const uint32_t *__restrict__ flag,
@@ -385,10 +691,14 @@ __global__ void k_seed_posoff(mbw_seed_t *__restrict__ out, const uint64_t *__re
 __device__ __forceinline__ bool sampled(uint64_t x, uint32_t r, uint32_t rmask) {
   return rmask ? (x & rmask) == 0 : (x % r) == 0;
 }
+// x / r for a sampled row (r a power of two: shift)
+__device__ __forceinline__ uint64_t sample_index(uint64_t x, uint32_t r, int rshift) {
+  return rshift >= 0 ? (x >> rshift) : x / r;
+}
 
 // plain: one thread = one seed, LocateSlow for each of its rows
 __global__ void __launch_bounds__(256) k_locate_plain(IndexView ix, const mbw_seed_t *__restrict__ seeds, uint64_t ns,
-                                                      uint64_t *__restrict__ pos, uint32_t rmask,
+                                                      uint64_t *__restrict__ pos, uint32_t rmask, int rshift,
                                                       unsigned long long *__restrict__ ctl) {
   uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (t >= ns) return;
@@ -404,7 +714,7 @@ __global__ void __launch_bounds__(256) k_locate_plain(IndexView ix, const mbw_se
       x = ix.Cb[b] + o.v[b];
       ++steps; ++lines; ++lf;
     }
-    uint64_t p = steps + ix.ssa[x / ix.r];
+    uint64_t p = steps + ix.ssa[sample_index(x, ix.r, rshift)];
     if (p >= ix.n) p -= ix.n;
     pos[sd.pos_off + w] = p;
     ++lines;
@@ -419,7 +729,7 @@ __global__ void __launch_bounds__(256) k_locate_plain(IndexView ix, const mbw_se
 // of all (seed, row) pairs (BatchLocate's refill of finished walks).
 __global__ void __launch_bounds__(256) k_locate_coop(IndexView ix, const mbw_seed_t *__restrict__ seeds,
                                                      const uint32_t *__restrict__ sid, uint64_t n_pos,
-                                                     uint64_t *__restrict__ pos, uint32_t rmask, int grab,
+                                                     uint64_t *__restrict__ pos, uint32_t rmask, int rshift, int grab,
                                                      unsigned long long *__restrict__ ctl) {
   const int q = threadIdx.x & (MBW_GROUP - 1);
   uint64_t wnext = 0, wlast = 0, w = 0, x = 0, steps = 0;
@@ -442,7 +752,7 @@ __global__ void __launch_bounds__(256) k_locate_coop(IndexView ix, const mbw_see
       active = true;
     }
     if (sampled(x, ix.r, rmask)) {
-      uint64_t p = steps + ix.ssa[x / ix.r];
+      uint64_t p = steps + ix.ssa[sample_index(x, ix.r, rshift)];
       if (p >= ix.n) p -= ix.n;
       if (q == 0) pos[w] = p;
       ++lines;
@@ -456,22 +766,100 @@ __global__ void __launch_bounds__(256) k_locate_coop(IndexView ix, const mbw_see
     const uint64_t L = line_of(x);
     const int o = (int)(x - L * MBW_BPL);
     uint4 d = ix.lines[L * MBW_LINE_U4 + q];
-    // B[x] from the slice that holds row o
-    const int qs = 2 + (o >> 6);
-    uint64_t wsel = ((o & 63) < 32) ? (((uint64_t)d.y << 32) | d.x) : (((uint64_t)d.w << 32) | d.z);
-    int bmine = (int)((wsel >> (2 * (o & 31))) & 3);
-    int b = __shfl(bmine, qs, MBW_GROUP);
-    uint64_t hdr[4];
-    group_header(d, hdr);
-    uint64_t inl = group_sum(slice_counts(d, q, o));
-    Occ4 oc = occ_from(hdr, inl, x, ix.primary);
-    x = ix.Cb[b] + oc.v[b];
+    const uint64_t w0 = ((uint64_t)d.y << 32) | d.x, w1 = ((uint64_t)d.w << 32) | d.z;
+    // one reduction carries the in-line counts of A, C, G (16 bits each) and B[x] + 1 (top 16 bits,
+    // from the slice holding row o); a second one the line's prefix count of B[x]
+    uint64_t pk = 0;
+    if (q >= 2) {
+      pk = slice_counts(d, q, o) & 0xFFFFFFFFFFFFull;
+      if (q == 2 + (o >> 6)) {
+        uint64_t wsel = (o & 63) < 32 ? w0 : w1;
+        pk |= (((wsel >> (2 * (o & 31))) & 3) + 1) << 48;
+      }
+    }
+    pk = grp_sum64(pk);
+    const int b = (int)(pk >> 48) - 1;
+    uint64_t hv = 0;
+    if (q == 0) hv = b == 0 ? w0 : (b == 1 ? w1 : 0);
+    else if (q == 1) hv = b == 2 ? w0 : (b == 3 ? w1 : 0);
+    hv = grp_sum64(hv);
+    const uint64_t nA = pk & 0xffff, nC = (pk >> 16) & 0xffff, nG = (pk >> 32) & 0xffff;
+    const uint64_t inl = b == 0 ? nA : (b == 1 ? nC : (b == 2 ? nG : (uint64_t)o - nA - nC - nG));
+    const uint64_t occ = hv + inl - ((b == 0 && x > ix.primary) ? 1 : 0);
+    x = sel4(ix.Cb[0], ix.Cb[1], ix.Cb[2], ix.Cb[3], b) + occ;
     ++steps; ++lines; ++lf;
   }
   if (q == 0 && lines) {
     atomicAdd(&ctl[C_LINES_LOC], (unsigned long long)lines);
     atomicAdd(&ctl[C_LFSTEPS], (unsigned long long)lf);
   }
+}
+
+// wave-cooperative locate: every lane walks one SA row; idle lanes refill from the queue of all
+// (seed, row) pairs (one atomic per wave); lines are fetched with the wave-cooperative loads.
+__global__ void __launch_bounds__(256) k_locate_wave(IndexView ix, const mbw_seed_t *__restrict__ seeds,
+                                                     const uint32_t *__restrict__ sid, uint64_t n_pos,
+                                                     uint64_t *__restrict__ pos, uint32_t rmask, int rshift,
+                                                     unsigned long long *__restrict__ ctl) {
+  __shared__ uint4 lbuf[4 * WAVE_U4];
+  const int lane = threadIdx.x & 63;
+  uint4 *buf = lbuf + (threadIdx.x >> 6) * WAVE_U4;
+  uint64_t w = 0, x = 0, steps = 0, lines = 0, lf = 0;
+  uint64_t cb = 0, ce = 0;
+  bool active = false, drained = false;
+  for (;;) {
+    const bool want = !active && !drained;
+    if (__ballot(want)) {
+      const uint64_t wi = wave_take(want, cb, ce, &ctl[C_WORK2], n_pos, lane);
+      if (want) {
+        w = wi;
+        if (w == ~0ull) drained = true;
+        else {
+          const uint32_t t = sid[w];
+          x = seeds[t].k + (w - seeds[t].pos_off);
+          steps = 0;
+          active = true;
+        }
+      }
+    }
+    if (__ballot(active) == 0) {
+      if (__ballot(!drained) == 0) break;
+      continue;
+    }
+    bool need = false;
+    if (active) {
+      if (sampled(x, ix.r, rmask)) {
+        uint64_t p = steps + ix.ssa[sample_index(x, ix.r, rshift)];
+        if (p >= ix.n) p -= ix.n;
+        pos[w] = p;
+        ++lines;
+        active = false;
+      } else if (x == ix.primary || steps > ix.n) {   // LF of the $ row is row 0 (the cap guards a corrupt index)
+        if (steps > ix.n) atomicOr(&ctl[C_ERR], 2ull);
+        x = 0;
+        ++steps;
+      } else {
+        need = true;
+      }
+    }
+    const uint32_t L = need ? (uint32_t)line_of(x) : 0u;
+    if (__ballot(need)) {
+      wave_fetch(ix.lines, L, need, buf, lane);
+      if (need) {
+        const int o = (int)(x - (uint64_t)L * MBW_BPL);
+        const uint4 bd = buf[slot_of(lane, 2 + (o >> 6))];
+        const uint64_t wsel = (o & 63) < 32 ? (((uint64_t)bd.y << 32) | bd.x) : (((uint64_t)bd.w << 32) | bd.z);
+        const int b = (int)((wsel >> (2 * (o & 31))) & 3);
+        uint64_t E, G, t1, t2;
+        lane_eg(buf, lane, b, o, -1, E, G, t1, t2);
+        if (b == 0 && x > ix.primary) E -= 1;
+        x = sel4(ix.Cb[0], ix.Cb[1], ix.Cb[2], ix.Cb[3], b) + E;
+        ++steps; ++lines; ++lf;
+      }
+    }
+  }
+  atomicAdd(&ctl[C_LINES_LOC], (unsigned long long)lines);
+  atomicAdd(&ctl[C_LFSTEPS], (unsigned long long)lf);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -516,8 +904,10 @@ struct mbw_ctx {
   struct Buf { void *p = nullptr; size_t bytes = 0; };
   Buf codes, ascii, lens, offs, raw, subq, keys0, keys1, vals0, vals1, flag, idx, seeds, npos, posoff, sid, pos, pos2,
       keep, kidx, temp, ctl;
-  hipEvent_t ev[4];
+  hipEvent_t ev[8];
   unsigned long long host_ctl[C_COUNT];
+  float ms_smem;
+  int n_smem_launches;
 };
 
 static int grow(mbw_ctx::Buf &b, size_t bytes) {
@@ -542,7 +932,7 @@ extern "C" int mbw_ctx_create(const mbw_index *ix, mbw_ctx **out) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, ix->device) != hipSuccess) { delete c; mbw_set_error("hipGetDeviceProperties failed"); return MBW_E_HIP; }
   c->n_cu = prop.multiProcessorCount;
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < 8; ++t)
     if (hipEventCreate(&c->ev[t]) != hipSuccess) { delete c; mbw_set_error("hipEventCreate failed"); return MBW_E_HIP; }
   if (grow(c->ctl, C_COUNT * sizeof(unsigned long long))) { delete c; return MBW_E_NOMEM; }
   *out = c;
@@ -556,7 +946,7 @@ extern "C" void mbw_ctx_free(mbw_ctx *c) {
                         &c->vals1, &c->flag, &c->idx, &c->seeds, &c->npos, &c->posoff, &c->sid, &c->pos, &c->pos2,
                         &c->keep, &c->kidx, &c->temp, &c->ctl};
   for (auto *b : bs) if (b->p) (void)hipFree(b->p);
-  for (int t = 0; t < 4; ++t) (void)hipEventDestroy(c->ev[t]);
+  for (int t = 0; t < 8; ++t) (void)hipEventDestroy(c->ev[t]);
   delete c;
 }
 
@@ -583,10 +973,30 @@ static int persistent_grid(const void *kern, int block, size_t lds, int n_cu, in
   return per * n_cu;
 }
 
+static int launch_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const mbw_seed_opts &o, int maxlen, hipStream_t st);
 static int run_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const mbw_seed_opts &o, int maxlen, hipStream_t st) {
   if (P.n_queries == 0) return 0;
+  TRY(hipEventRecord(c->ev[1], st));
+  int r = launch_smem(c, v, P, o, maxlen, st);
+  if (r) return r;
+  TRY(hipEventRecord(c->ev[2], st));
+  TRY(hipEventSynchronize(c->ev[2]));
+  float ms = 0;
+  TRY(hipEventElapsedTime(&ms, c->ev[1], c->ev[2]));
+  c->ms_smem += ms;
+  c->n_smem_launches++;
+  return 0;
+}
+
+static int launch_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const mbw_seed_opts &o, int maxlen, hipStream_t st) {
   if (o.kernel == MBW_KERNEL_PLAIN) {
     k_smem_plain<<<grid_for(P.n_queries, 256), 256, 0, st>>>(v, P);
+    TRY(hipGetLastError());
+    return 0;
+  }
+  if (o.schedule == MBW_SCHED_WAVE) {
+    int grid = persistent_grid((const void *)k_smem_wave, 256, 0, c->n_cu, o.blocks_per_cu);
+    k_smem_wave<<<grid, 256, 0, st>>>(v, P);
     TRY(hipGetLastError());
     return 0;
   }
@@ -618,13 +1028,16 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   if (o.min_occ < 1) { mbw_set_error("min_occ must be >= 1"); return MBW_E_INVAL; }
   if (o.bs_role && !c->ix->bisulfite) { mbw_set_error("bs_role needs a bisulfite index"); return MBW_E_INVAL; }
   if (o.bs_role < 0 || o.bs_role > 2) { mbw_set_error("bs_role must be 0, 1 or 2"); return MBW_E_INVAL; }
-  if (o.grab <= 0) o.grab = 1;
+  if (o.grab <= 0) o.grab = 8;
+  if (o.grab_locate <= 0) o.grab_locate = 64;
   TRY(hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
   const mbw_index *ix = c->ix;
   IndexView v = make_view(ix);
   unsigned long long *ctl = (unsigned long long *)c->ctl.p;
   TRY(hipMemsetAsync(ctl, 0, C_COUNT * sizeof(unsigned long long), st));
+  c->ms_smem = 0;
+  c->n_smem_launches = 0;
   TRY(hipEventRecord(c->ev[0], st));
   if (n_reads == 0) {
     TRY(hipStreamSynchronize(st));
@@ -661,11 +1074,12 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   }
   k_encode<<<grid_for(total), 256, 0, st>>>(dreads, total, o.bs_role, (uint8_t *)c->codes.p);
   TRY(hipGetLastError());
-  TRY(hipEventRecord(c->ev[1], st));
   // SMEM rounds
-  uint64_t seed_cap = std::max<uint64_t>(1 << 16, n_reads * 6);
+  // per-wave output chunks leave up to one partly used chunk per wave of the persistent grid
+  const uint64_t chunk_slack = (uint64_t)c->n_cu * 32 * OUT_CHUNK;
+  uint64_t seed_cap = std::max<uint64_t>(1 << 16, n_reads * 4) + chunk_slack;
   if (c->raw.bytes / sizeof(SeedRec) > seed_cap) seed_cap = c->raw.bytes / sizeof(SeedRec);
-  uint64_t subq_cap = std::max<uint64_t>(1 << 14, n_reads / 2);
+  uint64_t subq_cap = std::max<uint64_t>(1 << 14, n_reads / 2) + chunk_slack;
   if (c->subq.bytes / sizeof(Query) > subq_cap) subq_cap = c->subq.bytes / sizeof(Query);
   SeedParams P;
   memset(&P, 0, sizeof(P));
@@ -718,17 +1132,16 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
       c->raw = nb;
     }
   }
-  TRY(hipEventRecord(c->ev[2], st));
   // sort by (read, qbeg, qend), dedup, counts
   uint64_t ns = ntot;
   GROW(c->keys0, ns * 8); GROW(c->keys1, ns * 8); GROW(c->vals0, ns * 4); GROW(c->vals1, ns * 4);
   GROW(c->flag, ns * 4 + 8); GROW(c->idx, ns * 4 + 8);
   if (ns) {
-    k_seed_keys<<<grid_for(ns), 256, 0, st>>>((const SeedRec *)c->raw.p, ns, (uint64_t *)c->keys0.p, (uint32_t *)c->vals0.p);
+    k_seed_keys<<<grid_for(ns), 256, 0, st>>>((const SeedRec *)c->raw.p, ns, n_reads, (uint64_t *)c->keys0.p, (uint32_t *)c->vals0.p);
     TRY(hipGetLastError());
   }
-  int hibit = 32;
-  while (hibit < 64 && (1ull << (hibit - 32)) < n_reads) ++hibit;
+  int hibit = 33;   // key < (n_reads + 1) << 32
+  while (hibit < 64 && (1ull << (hibit - 32)) <= n_reads) ++hibit;
   hipcub::DoubleBuffer<uint64_t> dk((uint64_t *)c->keys0.p, (uint64_t *)c->keys1.p);
   // (ns may be 0: every step below is skipped then)
   hipcub::DoubleBuffer<uint32_t> dv((uint32_t *)c->vals0.p, (uint32_t *)c->vals1.p);
@@ -739,7 +1152,7 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   uint32_t *flag = (uint32_t *)c->flag.p, *idx = (uint32_t *)c->idx.p;
   uint64_t nu = 0;
   if (ns) {
-    k_dedup_mark<<<grid_for(ns), 256, 0, st>>>(dk.Current(), ns, flag);
+    k_dedup_mark<<<grid_for(ns), 256, 0, st>>>(dk.Current(), ns, n_reads, flag);
     TRY(hipGetLastError());
     r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, flag, idx, ns, st); });
     if (r) return r;
@@ -779,28 +1192,38 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     k_seed_posoff<<<grid_for(nu), 256, 0, st>>>(seeds, posoff, nu, coop && n_pos ? (uint32_t *)c->keep.p : nullptr);
     TRY(hipGetLastError());
   }
-  TRY(hipEventRecord(c->ev[3], st));
   // locate
   uint32_t rmask = (ix->sa_sample & (ix->sa_sample - 1)) == 0 ? (uint32_t)(ix->sa_sample - 1) : 0u;
   if (ix->sa_sample == 1) rmask = 0;   // every row sampled: x % 1 == 0 path
+  int rshift = -1;
+  if ((ix->sa_sample & (ix->sa_sample - 1)) == 0) { rshift = 0; while ((1 << rshift) < ix->sa_sample) ++rshift; }
+  TRY(hipEventRecord(c->ev[3], st));   // re-recorded right before the locate launch below
   if (n_pos) {
     if (!coop) {
-      k_locate_plain<<<grid_for(nu), 256, 0, st>>>(v, seeds, nu, (uint64_t *)c->pos.p, rmask, ctl);
+      TRY(hipEventRecord(c->ev[3], st));
+      k_locate_plain<<<grid_for(nu), 256, 0, st>>>(v, seeds, nu, (uint64_t *)c->pos.p, rmask, rshift, ctl);
       TRY(hipGetLastError());
     } else {
       uint32_t *seedmark = (uint32_t *)c->keep.p;
       r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::InclusiveScan(tp, tb, seedmark, sid, hipcub::Max(), n_pos, st); });
       if (r) return r;
+      if (o.schedule == MBW_SCHED_WAVE) {
+        int grid = persistent_grid((const void *)k_locate_wave, 256, 0, c->n_cu, o.blocks_per_cu);
+        TRY(hipEventRecord(c->ev[3], st));
+        k_locate_wave<<<grid, 256, 0, st>>>(v, seeds, sid, n_pos, (uint64_t *)c->pos.p, rmask, rshift, ctl);
+        TRY(hipGetLastError());
+      } else {
       int gpb = o.groups_per_block > 0 ? std::min(o.groups_per_block, 32) : 32;
       int block = gpb * MBW_GROUP;
       int grid = persistent_grid((const void *)k_locate_coop, block, 0, c->n_cu, o.blocks_per_cu);
-      k_locate_coop<<<grid, block, 0, st>>>(v, seeds, sid, n_pos, (uint64_t *)c->pos.p, rmask, o.grab, ctl);
+      TRY(hipEventRecord(c->ev[3], st));
+      k_locate_coop<<<grid, block, 0, st>>>(v, seeds, sid, n_pos, (uint64_t *)c->pos.p, rmask, rshift,
+                                             o.grab_locate, ctl);
       TRY(hipGetLastError());
+      }
     }
   }
-  hipEvent_t ev_loc;
-  TRY(hipEventCreate(&ev_loc));
-  (void)hipEventRecord(ev_loc, st);
+  TRY(hipEventRecord(c->ev[4], st));
   // bisulfite strand filter
   const uint64_t *final_pos = (const uint64_t *)c->pos.p;
   if (o.bs_role && n_pos) {
@@ -829,11 +1252,11 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     mbw_set_error(std::string("kernel guard tripped (") + std::to_string(c->host_ctl[C_ERR]) + "): corrupt index or internal error");
     return MBW_E_HIP;
   }
-  float t_smem = 0, t_loc = 0, t_tot = 0;
-  (void)hipEventElapsedTime(&t_smem, c->ev[1], c->ev[2]);
-  (void)hipEventElapsedTime(&t_loc, c->ev[3], ev_loc);
-  (void)hipEventElapsedTime(&t_tot, c->ev[0], ev_loc);
-  (void)hipEventDestroy(ev_loc);
+  TRY(hipEventRecord(c->ev[5], st));
+  TRY(hipEventSynchronize(c->ev[5]));
+  float t_loc = 0, t_tot = 0;
+  (void)hipEventElapsedTime(&t_loc, c->ev[3], c->ev[4]);
+  (void)hipEventElapsedTime(&t_tot, c->ev[0], c->ev[5]);
   out->n_seeds = nu;
   out->n_pos = n_pos;
   out->seeds = seeds;
@@ -842,7 +1265,8 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   out->lines_locate = c->host_ctl[C_LINES_LOC];
   out->steps = c->host_ctl[C_STEPS];
   out->lf_steps = c->host_ctl[C_LFSTEPS];
-  out->ms_smem = t_smem; out->ms_locate = t_loc; out->ms_total = t_tot;
+  out->ms_smem = c->ms_smem; out->ms_locate = t_loc; out->ms_total = t_tot;
+  out->n_smem_launches = c->n_smem_launches;
   return MBW_OK;
 }
 
