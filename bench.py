@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of batched (19,1)-SMEM seeding + sampled-SA locate on one MI355X.
+
+Workload (default): a synthetic 3.1 Gbp reference (55% random sequence, 35% interspersed repeat
+families of 300 bp / 6 kbp copies at 2-20% divergence, 10% tandem arrays of 171 bp units at 1-3%
+divergence), indexed on the GPU (T = R . revcomp(R) . $, n = 6.2 G; 128-byte occurrence lines of
+384 rows; SA sampled every 8 rows; 12-mer interval table), and 10,000,000 read pairs of 150 bp
+(20,000,000 reads) at 0.5% substitutions + 0.05% 1-3 bp indels, 5% of pairs drawn from satellite
+arrays.  One step = one ``mbw_seed`` call over the whole batch with the reads already resident in
+HBM: encode, both SMEM rounds, sort/dedup, locate of every seed with s <= 500.
+
+The JSON line reports reads/s of the default (wave-cooperative) path, the plain one-read-per-thread
+kernel on the same index and reads, the roofline of the dominant kernel (the SMEM kernel: 128-byte
+index lines it touches, counted by the kernel itself, over its HIP-event time), and the CPU oracle
+(paper algorithms, OpenMP) timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "150bp reads seeded/s on 3.1 Gbp ref vs plain GPU kernel; serve p50/p99 ms"
+HBM_PEAK_GBS = 8000.0
+LINE_BYTES = 128
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("seed.hip", "mbw_internal.h", "index_build.hip"):
+        with open(os.path.join(ROOT, "paper_2606_15357_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel: str, launches_bytes: float):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if it was taken on the
+    current kernel sources (else None)."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(ref_codes, n_pairs: int, window: int, threads: int):
+    """The oracle (Algorithm 3 + LocateSlow + 10-mer shortcut, OpenMP over reads) on a bounded
+    sample: an oracle index over the first `window` bases of the same reference and read pairs
+    from that window drawn with the workload's read model."""
+    import oracle
+    import synth
+    sub = synth.Reference(np.ascontiguousarray(ref_codes[:window]), np.zeros((0, 2), np.uint64), 1, 0)
+    t0 = time.time()
+    ox = oracle.OracleIndex(sub.codes, sa_rate=8)
+    t_build = time.time() - t0
+    rs = synth.reads_fixed(sub, n_pairs, 150, True, p_sub=0.005, p_indel=0.0005, seed=4003)
+    t0 = time.time()
+    res = ox.seed(rs.seq, rs.offsets, min_len=19, max_occ=500, method=1, kmer_k=10, threads=threads)
+    dt = time.time() - t0
+    return dict(value=len(rs) / dt, unit="reads/s", cores=threads, kind="oracle",
+                sample=f"{len(rs)} x 150 bp reads ({n_pairs} pairs, workload read model) against an oracle index "
+                       f"of the first {window / 1e6:.0f} Mbp of the same 3.1 Gbp reference (index build "
+                       f"{t_build:.1f} s excluded); oracle = serial Algorithm 3 + LocateSlow with the 10-mer "
+                       f"shortcut per read, OpenMP over reads; {len(res)} seeds, {res.pos.size} positions; "
+                       f"{dt:.1f} s wall")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--ref-len", type=int, default=3_100_000_000)
+    ap.add_argument("--pairs", type=int, default=10_000_000)
+    ap.add_argument("--sa-sample", type=int, default=8)
+    ap.add_argument("--kmer", type=int, default=12)
+    ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the plain kernel (0 = skip)")
+    ap.add_argument("--cpu-pairs", type=int, default=250_000)
+    ap.add_argument("--cpu-window", type=int, default=16_000_000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--schedule", type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the seeding path is "
+              "data-parallel over reads with a replicated index; multi-GPU runs are not part of this build.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2606_15357_amd as mbw
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    ref = synth.reference(1, args.ref_len, synth.REF_SEED + 3)
+    log(f"reference {len(ref)} bases generated in {time.time() - t0:.1f} s")
+    t0 = time.time()
+    idx = mbw.Index.build(ref.codes, sa_sample=args.sa_sample, kmer_k=args.kmer)
+    info = idx.info()
+    log(f"index built on the GPU in {time.time() - t0:.1f} s: n={info['n']} lines={info['n_lines']} "
+        f"resident={info['bytes_resident'] / 1e9:.2f} GB")
+    t0 = time.time()
+    reads = synth.reads_fixed(ref, args.pairs, 150, True, p_sub=0.005, p_indel=0.0005, sat_frac=0.05,
+                              seed=synth.READ_SEED + 3)
+    n_reads = len(reads)
+    log(f"{n_reads} reads generated in {time.time() - t0:.1f} s")
+    dseq = torch.from_numpy(reads.seq).to(dev)
+    dlen = torch.from_numpy(reads.lengths.view(np.int32)).to(dev)
+    torch.cuda.synchronize()
+    ctx = mbw.Context(idx)
+    stream = torch.cuda.current_stream()
+
+    def step(kernel):
+        return ctx.seed(dseq, dlen, min_seed_len=19, max_occ=500, kernel=kernel, schedule=args.schedule,
+                        stream=stream)
+
+    for _ in range(args.warmup):
+        out = step(mbw.KERNEL_COOP)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = []
+    for _ in range(args.steps):
+        outs.append(step(mbw.KERNEL_COOP))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    out = outs[-1]
+    value = n_reads * args.steps / elapsed
+    ms_smem = sum(o.ms_smem for o in outs) / len(outs)
+    ms_loc = sum(o.ms_locate for o in outs) / len(outs)
+    launches = out.n_smem_launches
+    lines_smem = out.lines_smem
+    lines_loc = out.lines_locate
+    log(f"wave path: {value / 1e6:.2f} M reads/s, {elapsed / args.steps * 1e3:.1f} ms/step; seeds {out.n_seeds} "
+        f"positions {out.n_pos}; smem {ms_smem:.1f} ms ({launches} launches, {lines_smem} lines), "
+        f"locate {ms_loc:.1f} ms ({lines_loc} lines)")
+
+    plain = None
+    if args.plain_steps > 0:
+        step(mbw.KERNEL_PLAIN)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pouts = [step(mbw.KERNEL_PLAIN) for _ in range(args.plain_steps)]
+        torch.cuda.synchronize()
+        pel = time.perf_counter() - t0
+        po = pouts[-1]
+        plain = dict(value=n_reads * args.plain_steps / pel, unit="reads/s",
+                     ms_smem=round(po.ms_smem, 2), ms_locate=round(po.ms_locate, 2),
+                     same_result=bool(po.n_seeds == out.n_seeds and po.n_pos == out.n_pos))
+        log(f"plain kernel: {plain['value'] / 1e6:.2f} M reads/s")
+
+    # roofline of the dominant kernel (SMEM): algorithmic 128-byte lines over its event time
+    smem_bytes = lines_smem * LINE_BYTES
+    achieved = smem_bytes / (ms_smem * 1e-3) / 1e9
+    traffic = traffic_from_profile("smem", smem_bytes / max(launches, 1))
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                    kernel="k_smem_wave (both SMEM rounds)",
+                    lines_per_read=round(lines_smem / n_reads, 1),
+                    locate=dict(achieved=round(lines_loc * LINE_BYTES / (ms_loc * 1e-3) / 1e9, 1),
+                                lines_per_read=round(lines_loc / n_reads, 1)),
+                    whole_path=round((lines_smem + lines_loc) * LINE_BYTES / (elapsed / args.steps) / 1e9, 1))
+
+    cpu = None
+    if not args.no_cpu:
+        threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+        threads = max(1, min(threads, int(os.environ.get("OMP_NUM_THREADS", threads))))
+        cpu = cpu_baseline(ref.codes, args.cpu_pairs, args.cpu_window, threads)
+        cpu["value"] = round(cpu["value"], 1)
+        log(f"cpu oracle: {cpu['value']:.0f} reads/s on {cpu['cores']} threads")
+
+    line = dict(metric=METRIC, value=round(value, 1), unit="reads/s", n_gpus=1, steps=args.steps,
+                warmup=args.warmup, ms_per_step=round(elapsed / args.steps * 1e3, 2), higher_is_better=True,
+                scaling="weak", vs_baseline=None, dtype="u64", data="synthetic",
+                config=dict(workload=f"configs[3]: {args.ref_len / 1e9:.1f} Gbp synthetic reference, "
+                                     f"{args.pairs} paired 150 bp reads ({n_reads} reads), 0.5% error, 5% from "
+                                     f"satellites; (19,1)-SMEMs + re-seeding, max_occ 500",
+                            min_seed_len=19, max_occ=500, sa_sample=args.sa_sample, kmer_k=args.kmer,
+                            bases_per_line=384, line_bytes=LINE_BYTES, index_gb=round(info["bytes_resident"] / 1e9, 2)),
+                plain_gpu=plain, roofline=roofline, cpu_baseline=cpu)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
