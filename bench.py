@@ -98,7 +98,6 @@ def main():
     ap.add_argument("--cpu-pairs", type=int, default=250_000)
     ap.add_argument("--cpu-window", type=int, default=16_000_000)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--schedule", type=int, default=0)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -133,7 +132,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step(kernel):
-        return ctx.seed(dseq, dlen, min_seed_len=19, max_occ=500, kernel=kernel, schedule=args.schedule,
+        return ctx.seed(dseq, dlen, min_seed_len=19, max_occ=500, kernel=kernel,
                         stream=stream)
 
     for _ in range(args.warmup):
@@ -176,7 +175,7 @@ def main():
     traffic = traffic_from_profile("smem", smem_bytes / max(launches, 1))
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                    kernel="k_smem_wave (both SMEM rounds)",
+                    kernel="k_smem_wave<staged> (both SMEM rounds)",
                     lines_per_read=round(lines_smem / n_reads, 1),
                     locate=dict(achieved=round(lines_loc * LINE_BYTES / (ms_loc * 1e-3) / 1e9, 1),
                                 lines_per_read=round(lines_loc / n_reads, 1)),

@@ -83,11 +83,13 @@ typedef struct {
 int mbw_index_info(const mbw_index *idx, mbw_index_info_t *out);
 
 /* Device pointers to the resident arrays (read-only views for tests and tools):
- * lines: n_lines x 128 B; each line = u64 counts of A,C,G,T in B before the line (the $ row is
- *        counted as A), then 384 rows of B at 2 bits (row t of the line in u64 word t/32, bits
- *        2*(t%32)..+1; the $ row holds A).
+ * lines: n_lines x 128 B; each line = u32 counts of A,C,G,T in B from the start of its superblock
+ *        (2^23 lines) to the line (the $ row counted as A), three u32 sub-checkpoints (A, C, G
+ *        counts in 10-bit fields for the line's first 96/192/288 rows), one unused u32, then the
+ *        line's 384 rows of B at 2 bits (row t in u64 word 4 + t/32, bits 2*(t%32)..+1; the $ row
+ *        holds A).
  * ssa:   ceil(n/r) x u64, ssa[x/r] = S(x).
- * kmer:  4^k x 16 B packed (k:40 | k':40 | s:40 bits, little-endian), code = sum P[q]*4^(k-1-q). */
+ * kmer:  4^k x 16 B packed (k:40 | k':40 | s:40 bits, little-endian), code = sum P[q]*4^q. */
 int mbw_index_device_arrays(const mbw_index *idx, const void **lines, const void **ssa, const void **kmer);
 
 /* ---- seeding ------------------------------------------------------------------------------ */
@@ -108,19 +110,13 @@ typedef struct {
   int bs_role;        /* bisulfite index only: 1 = read 1 (C->T, keep positions in the forward
                          C->T and reverse G->A copies), 2 = read 2 (G->A, keep forward G->A and
                          reverse C->T) (Section 2.9); 0 = plain */
-  int kernel;         /* MBW_KERNEL_COOP (default) or MBW_KERNEL_PLAIN (one read per thread,
-                         serial algorithm per thread; the baseline) */
-  int use_kmer;       /* use the index's k-mer table in the cooperative kernel */
-  int groups_per_block; /* cooperative kernels: 8-lane groups per workgroup (0 = default 32) */
+  int kernel;         /* MBW_KERNEL_COOP (default: persistent wave kernels) or MBW_KERNEL_PLAIN
+                         (one read per thread running the serial algorithm; the baseline) */
+  int use_kmer;       /* use the index's k-mer table (wave kernels) */
   int blocks_per_cu;  /* persistent grid size per compute unit (0 = occupancy limit) */
-  int grab;           /* queries taken per work-queue fetch (0 = default 8) */
-  int grab_locate;    /* SA rows taken per locate work-queue fetch (0 = default 64) */
-  int schedule;       /* cooperative kernels: MBW_SCHED_WAVE (default: one query per lane, lines
-                         fetched by the whole wave) or MBW_SCHED_GROUP8 (eight lanes per query) */
+  int no_stage;       /* 1: do not stage reads of <= 160 bases in LDS */
 } mbw_seed_opts;
 
-#define MBW_SCHED_WAVE   0
-#define MBW_SCHED_GROUP8 1
 
 #define MBW_KERNEL_COOP  0
 #define MBW_KERNEL_PLAIN 1

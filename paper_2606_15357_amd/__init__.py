@@ -28,8 +28,6 @@ MBW_E_CAPACITY = -6
 
 KERNEL_COOP = 0
 KERNEL_PLAIN = 1
-SCHED_WAVE = 0
-SCHED_GROUP8 = 1
 SEED_UNLOCATED = 1
 SEED_ROUND2 = 2
 
@@ -59,9 +57,8 @@ class IndexInfo(C.Structure):
 
 class SeedOpts(C.Structure):
     _fields_ = [("min_occ", C.c_int), ("reseed", C.c_int), ("reseed_len", C.c_int), ("reseed_occ", C.c_int),
-                ("bs_role", C.c_int), ("kernel", C.c_int), ("use_kmer", C.c_int), ("groups_per_block", C.c_int),
-                ("blocks_per_cu", C.c_int), ("grab", C.c_int), ("grab_locate", C.c_int),
-                ("schedule", C.c_int)]
+                ("bs_role", C.c_int), ("kernel", C.c_int), ("use_kmer", C.c_int), ("blocks_per_cu", C.c_int),
+                ("no_stage", C.c_int)]
 
 
 class Result(C.Structure):
@@ -241,8 +238,8 @@ class Context:
 
     def seed(self, reads, lengths, min_seed_len: int = 19, max_occ: int = 500, min_occ: int = 1,
              reseed: bool = True, reseed_len: int = 38, reseed_occ: int = 10, bs_role: int = 0,
-             kernel: int = KERNEL_COOP, use_kmer: bool = True, groups_per_block: int = 0, blocks_per_cu: int = 0,
-             grab: int = 0, grab_locate: int = 0, schedule: int = 0, stream=None) -> SeedOutput:
+             kernel: int = KERNEL_COOP, use_kmer: bool = True, blocks_per_cu: int = 0, stage: bool = True,
+             stream=None) -> SeedOutput:
         """``reads``: concatenated ASCII (numpy uint8 on the host or a torch uint8 CUDA tensor);
         ``lengths``: uint32 per read (numpy or torch)."""
         n = int(lengths.numel() if hasattr(lengths, "numel") else len(lengths))
@@ -251,8 +248,7 @@ class Context:
         if isinstance(reads, np.ndarray):
             reads = np.ascontiguousarray(reads, dtype=np.uint8)
         o = SeedOpts(int(min_occ), int(bool(reseed)), int(reseed_len), int(reseed_occ), int(bs_role), int(kernel),
-                     int(bool(use_kmer)), int(groups_per_block), int(blocks_per_cu), int(grab), int(grab_locate),
-                     int(schedule))
+                     int(bool(use_kmer)), int(blocks_per_cu), int(not stage))
         res = Result()
         rp = _ptr(reads) if n else None
         lp = _ptr(lengths) if n else None

@@ -232,12 +232,16 @@ __global__ void k_emit_rows(const uint64_t *__restrict__ sa, uint64_t M, uint64_
 // ---------------------------------------------------------------------------------------------
 // occurrence lines
 
+// rows of the line at 2 bits, sub-checkpoints (A, C, G in the first 96/192/288 rows), per-line totals
 __global__ void k_line_counts(const uint8_t *__restrict__ B, uint64_t n, uint64_t n_lines, uint64_t *__restrict__ cnt /*4 x n_lines*/,
                               uint4 *__restrict__ lines) {
   for (uint64_t L = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; L < n_lines; L += (uint64_t)gridDim.x * blockDim.x) {
     uint64_t c[4] = {0, 0, 0, 0};
+    uint32_t *w32 = (uint32_t *)(lines + L * MBW_LINE_U4);
     uint64_t *w = (uint64_t *)(lines + L * MBW_LINE_U4);
     for (int q = 0; q < 12; ++q) {
+      if (q % 3 == 0 && q > 0)   // sub-checkpoint after 96 (q/3) rows
+        w32[4 + q / 3 - 1] = (uint32_t)c[0] | ((uint32_t)c[1] << 10) | ((uint32_t)c[2] << 20);
       uint64_t v = 0;
       for (int t = 0; t < 32; ++t) {
         uint64_t row = L * MBW_BPL + q * 32 + t;
@@ -245,14 +249,18 @@ __global__ void k_line_counts(const uint8_t *__restrict__ B, uint64_t n, uint64_
       }
       w[4 + q] = v;
     }
+    w32[7] = 0;
     for (int a = 0; a < 4; ++a) cnt[a * n_lines + L] = c[a];
   }
 }
 
-__global__ void k_line_headers(const uint64_t *__restrict__ pre /*4 x n_lines exclusive sums*/, uint64_t n_lines, uint4 *__restrict__ lines) {
+// line header: counts before the line, relative to the start of its superblock
+__global__ void k_line_headers(const uint64_t *__restrict__ pre /*4 x n_lines exclusive sums*/, uint64_t n_lines,
+                               const uint64_t *__restrict__ sbtab, uint4 *__restrict__ lines) {
   for (uint64_t L = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; L < n_lines; L += (uint64_t)gridDim.x * blockDim.x) {
-    uint64_t *w = (uint64_t *)(lines + L * MBW_LINE_U4);
-    for (int a = 0; a < 4; ++a) w[a] = pre[a * n_lines + L];
+    uint32_t *w = (uint32_t *)(lines + L * MBW_LINE_U4);
+    const uint64_t *t = sbtab + 8 * (L >> MBW_SB_SHIFT);
+    for (int a = 0; a < 4; ++a) w[a] = (uint32_t)(pre[a * n_lines + L] - t[a]);
   }
 }
 
@@ -260,17 +268,19 @@ __global__ void k_line_headers(const uint64_t *__restrict__ pre /*4 x n_lines ex
 // k-mer table: level t+1 from level t by one backward extension (Algorithm 1)
 struct Iv { uint64_t k, kr, s; };
 
+// level t+1 from level t: code(aP) = a + 4 code(P) (the first base is the least significant digit)
 __global__ void k_kmer_level(IndexView ix, const Iv *__restrict__ prev, uint64_t nprev, Iv *__restrict__ next) {
   uint64_t total = nprev * 4;
   for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < total; e += (uint64_t)gridDim.x * blockDim.x) {
-    int a = (int)(e / nprev);
-    Iv p = prev[e % nprev];
+    const int a = (int)(e & 3);
+    Iv p = prev[e >> 2];
     Iv o;
     if (p.s == 0) { o.k = 0; o.kr = 0; o.s = 0; }
     else {
-      Occ4 o1 = occ_single(ix.lines, p.k, ix.primary);
-      Occ4 o2 = occ_single(ix.lines, p.k + p.s, ix.primary);
-      ext_update(o1, o2, a, p.k, p.s, p.kr, ix.primary, ix.Cb, o.k, o.kr, o.s);
+      uint64_t E1, G1, E2, G2;
+      rank_global(ix, p.k, a, E1, G1);
+      rank_global(ix, p.k + p.s, a, E2, G2);
+      ext_update(E1, G1, E2, G2, a, p.k, p.s, p.kr, ix.primary, ix.Cb, o.k, o.kr, o.s);
     }
     next[e] = o;
   }
@@ -395,6 +405,7 @@ extern "C" void mbw_index_free(mbw_index *ix) {
   if (ix->lines) (void)hipFree(ix->lines);
   if (ix->ssa) (void)hipFree(ix->ssa);
   if (ix->kmer) (void)hipFree(ix->kmer);
+  if (ix->sbtab) (void)hipFree(ix->sbtab);
   (void)hipSetDevice(cur);
   delete ix;
 }
@@ -430,6 +441,8 @@ static int build_kmer_table(mbw_index *ix, hipStream_t st) {
 static int build_lines(mbw_index *ix, const uint8_t *B, hipStream_t st) {
   uint64_t n = ix->n, nl = n / MBW_BPL + 1;
   ix->n_lines = nl;
+  ix->n_sb = (int)(((nl - 1) >> MBW_SB_SHIFT) + 1);
+  if (ix->n_sb > MBW_MAX_SB) { mbw_set_error("reference too large for the superblock table"); return MBW_E_INVAL; }
   TRY(hipMalloc((void **)&ix->lines, nl * MBW_LINE_BYTES));
   ix->bytes += nl * MBW_LINE_BYTES;
   DevBuf<uint64_t> cnt, pre;
@@ -444,13 +457,26 @@ static int build_lines(mbw_index *ix, const uint8_t *B, hipStream_t st) {
     TRY(tmp.ensure(tb));
     TRY(hipcub::DeviceScan::ExclusiveSum(tmp.b.p, tb, cnt.p + a * nl, pre.p + a * nl, nl, st));
   }
-  k_line_headers<<<grid_for(nl), 256, 0, st>>>(pre.p, nl, ix->lines);
-  TRY(hipGetLastError());
   uint64_t tot[4], last[4];
   for (int a = 0; a < 4; ++a) {
     TRY(hipMemcpyAsync(&tot[a], pre.p + a * nl + nl - 1, 8, hipMemcpyDeviceToHost, st));
     TRY(hipMemcpyAsync(&last[a], cnt.p + a * nl + nl - 1, 8, hipMemcpyDeviceToHost, st));
+    for (int sb = 0; sb < ix->n_sb; ++sb)
+      TRY(hipMemcpyAsync(&ix->sb_host[8 * sb + a], pre.p + a * nl + ((uint64_t)sb << MBW_SB_SHIFT), 8,
+                         hipMemcpyDeviceToHost, st));
   }
+  TRY(hipStreamSynchronize(st));
+  for (int sb = 0; sb < ix->n_sb; ++sb)
+    for (int c = 0; c < 4; ++c) {
+      uint64_t g = 0;
+      for (int d = c + 1; d < 4; ++d) g += ix->sb_host[8 * sb + d];
+      ix->sb_host[8 * sb + 4 + c] = g;
+    }
+  TRY(hipMalloc((void **)&ix->sbtab, MBW_MAX_SB * 8 * sizeof(uint64_t)));
+  ix->bytes += MBW_MAX_SB * 8 * sizeof(uint64_t);
+  TRY(hipMemcpyAsync(ix->sbtab, ix->sb_host, MBW_MAX_SB * 8 * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+  k_line_headers<<<grid_for(nl), 256, 0, st>>>(pre.p, nl, ix->sbtab, ix->lines);
+  TRY(hipGetLastError());
   TRY(hipStreamSynchronize(st));
   for (int a = 0; a < 4; ++a) tot[a] += last[a];
   // raw A total includes the $ row
@@ -632,14 +658,15 @@ extern "C" int mbw_pos_to_ref(const mbw_index *ix, uint64_t pos, uint32_t len, i
 // ---------------------------------------------------------------------------------------------
 // index files: header (magic, version, fields, FNV-1a of header and of each array) + arrays
 static const uint64_t kMagic = 0x3158444e4957424dull;  // "MBWINDX1"
-static const uint32_t kVersion = 1;
+static const uint32_t kVersion = 2;
 
 struct FileHeader {
   uint64_t magic;
   uint32_t version, bpl;
   uint64_t n, len_r, primary, n_lines, n_ssa;
   uint64_t C[5];
-  int32_t sa_sample, kmer_k, bisulfite, pad;
+  int32_t sa_sample, kmer_k, bisulfite, n_sb;
+  uint64_t sb[MBW_MAX_SB * 8];
   uint64_t sum_lines, sum_ssa, sum_kmer;
   uint64_t sum_header;
 };
@@ -673,6 +700,8 @@ extern "C" int mbw_index_save(const mbw_index *ix, const char *path) {
   hd.n = ix->n; hd.len_r = ix->len_r; hd.primary = ix->primary; hd.n_lines = ix->n_lines; hd.n_ssa = ix->n_ssa;
   for (int a = 0; a < 5; ++a) hd.C[a] = ix->C[a];
   hd.sa_sample = ix->sa_sample; hd.kmer_k = ix->kmer ? ix->kmer_k : 0; hd.bisulfite = ix->bisulfite;
+  hd.n_sb = ix->n_sb;
+  memcpy(hd.sb, ix->sb_host, sizeof(hd.sb));
   hd.sum_lines = sum_words(lines.data(), lines.size());
   hd.sum_ssa = sum_words(ssa.data(), ssa.size());
   hd.sum_kmer = sum_words(kmer.data(), kmer.size());
@@ -696,7 +725,7 @@ extern "C" int mbw_index_load(const char *path, int device, mbw_index **out) {
   if (hd.magic != kMagic || hd.version != kVersion || hd.bpl != MBW_BPL ||
       hd.sum_header != fnv(&hd, offsetof(FileHeader, sum_header)) || hd.n_lines != hd.n / MBW_BPL + 1 ||
       hd.sa_sample < 1 || hd.sa_sample > 1024 || hd.n_ssa != (hd.n + hd.sa_sample - 1) / hd.sa_sample ||
-      hd.kmer_k < 0 || hd.kmer_k > 13) {
+      hd.kmer_k < 0 || hd.kmer_k > 13 || hd.n_sb != (int)(((hd.n_lines - 1) >> MBW_SB_SHIFT) + 1)) {
     fclose(f); mbw_set_error("bad magic, version or header fields"); return MBW_E_FORMAT;
   }
   uint64_t kb = hd.kmer_k ? (1ull << (2 * hd.kmer_k)) * 16 : 0;
@@ -717,7 +746,11 @@ extern "C" int mbw_index_load(const char *path, int device, mbw_index **out) {
   ix->device = device; ix->n = hd.n; ix->len_r = hd.len_r; ix->primary = hd.primary; ix->n_lines = hd.n_lines;
   ix->n_ssa = hd.n_ssa; for (int a = 0; a < 5; ++a) ix->C[a] = hd.C[a];
   ix->sa_sample = hd.sa_sample; ix->kmer_k = hd.kmer_k; ix->bisulfite = hd.bisulfite;
+  ix->n_sb = hd.n_sb;
+  memcpy(ix->sb_host, hd.sb, sizeof(hd.sb));
   int rc = [&]() -> int {
+    TRY(hipMalloc((void **)&ix->sbtab, sizeof(hd.sb)));
+    TRY(hipMemcpy(ix->sbtab, hd.sb, sizeof(hd.sb), hipMemcpyHostToDevice));
     TRY(hipMalloc((void **)&ix->lines, lines.size()));
     TRY(hipMemcpy(ix->lines, lines.data(), lines.size(), hipMemcpyHostToDevice));
     TRY(hipMalloc((void **)&ix->ssa, ssa.size()));
@@ -726,7 +759,7 @@ extern "C" int mbw_index_load(const char *path, int device, mbw_index **out) {
       TRY(hipMalloc((void **)&ix->kmer, kb));
       TRY(hipMemcpy(ix->kmer, kmer.data(), kb, hipMemcpyHostToDevice));
     }
-    ix->bytes = lines.size() + ssa.size() + kb;
+    ix->bytes = lines.size() + ssa.size() + kb + sizeof(hd.sb);
     return 0;
   }();
   if (rc) { mbw_index_free(ix); return rc; }

@@ -1,7 +1,8 @@
 // Batched (l,c)-SMEM seeding and sampled-SA locate (paper Sections 2.1, 2.4, 2.5, 2.6, 2.9).
 //
 // Pipeline of one mbw_seed call (all on one stream):
-//   encode      ASCII -> codes 0..3 (4 = matches nothing), bisulfite read conversion (Section 2.9)
+//   encode      ASCII -> codes 0..3 (4 = matches nothing), bisulfite read conversion (Section 2.9),
+//               then 2-bit packing (32 bases per word + one N bit per base)
 //   smem        round 1: (l,c)-SMEMs of every read (Algorithm 3), appended to a seed list; SMEMs that
 //               qualify for re-seeding are appended to a sub-query list
 //   smem        round 2 (Section 2.6): (floor(len/2), s+1)-SMEMs of each sub-query
@@ -10,12 +11,14 @@
 //   locate      Algorithm 2: LF-walk every SA row of every located seed to a sampled row
 //   filter      bisulfite strand filter on positions (Section 2.9)
 //
-// Two kernel families do the smem and locate steps:
-//   * cooperative (default): persistent work queues; eight lanes hold one query (or one locate walk)
-//     and fetch each 128-byte occurrence line with a single 16-byte load per lane; the read is staged
-//     in LDS; the first k backward steps of a run come from the k-mer table (Section 2.5).
-//   * plain (baseline): one thread runs the serial algorithm for one read (round 2 inline), one
-//     thread locates one seed; ranks read the line header and the needed 16-byte slices.
+// Two kernel families run the smem and locate steps:
+//   * wave (default): persistent kernels in which every lane owns one query (or one locate walk)
+//     and each iteration has exactly one memory phase: the wave fetches all occurrence lines it
+//     needs cooperatively (eight lanes per 128-byte line, straight into LDS), together with k-mer
+//     table entries, the records of new queries and the words of reads being staged; then each
+//     lane ranks its own line from LDS.  Reads of up to 160 bases are staged in LDS.
+//   * plain (the baseline): one thread runs the serial algorithm for one read (round 2 inline) and
+//     one thread locates one seed; ranks read their line straight from global memory.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
@@ -31,7 +34,8 @@
 
 namespace {
 
-struct Query { uint32_t read_id, qbeg, qend, l, c; };
+// a query string: read_id's bases [qbeg, qend) with its own (l, c); rlen / woff locate the packed read
+struct Query { uint32_t read_id, qbeg, qend, l, c, rlen, woff_lo, woff_hi; };
 #define INVALID_READ 0xFFFFFFFFu   // unused slot of a per-wave output chunk
 struct SeedRec { uint32_t read_id, qbeg, qend, flags; uint64_t k, kr, s; };
 
@@ -40,13 +44,13 @@ enum { C_WORK = 0, C_NSEEDS = 1, C_NSUBQ = 2, C_LINES = 3, C_STEPS = 4, C_KMER =
        C_LINES_LOC = 8, C_WORK2 = 9, C_MAXLEN = 10, C_ERR = 11, C_COUNT = 16 };
 
 struct SeedParams {
-  const uint8_t *__restrict__ codes;
-  const uint64_t *__restrict__ offs;
+  const uint8_t *__restrict__ codes;   // one code per base (plain kernel)
+  const uint64_t *__restrict__ offs;   // read offsets (n_reads + 1)
   const Query *__restrict__ queries;   // round 2; nullptr in round 1
   uint64_t n_queries;
   int l, c;                            // round 1 parameters
   int reseed, reseed_len, reseed_occ, round;
-  int use_kmer, grab;
+  int use_kmer;
   SeedRec *__restrict__ seeds;
   uint64_t seed_cap;
   Query *__restrict__ subq;
@@ -54,49 +58,20 @@ struct SeedParams {
   unsigned long long *__restrict__ ctl;
 };
 
-// Append one seed (and, in round 1, its re-seeding query) from whatever lanes are active here:
-// one atomic per group of simultaneously emitting lanes.
-__device__ __forceinline__ uint64_t active_slot(unsigned long long *counter) {
-  const uint64_t m = __ballot(1);
-  const int lane = (int)(threadIdx.x & 63);
-  const int leader = __ffsll((unsigned long long)m) - 1;
-  unsigned long long b0 = 0;
-  if (lane == leader) b0 = atomicAdd(counter, (unsigned long long)__popcll(m));
-  b0 = __shfl(b0, leader);
-  return b0 + __popcll(m & ((1ull << lane) - 1));
-}
+struct ReadWords {
+  const uint64_t *__restrict__ pw;     // packed bases, 2 bits each, 32 per word (read-aligned)
+  const uint32_t *__restrict__ pn;     // one N bit per base, 32 per word
+  const uint64_t *__restrict__ woff;   // first word of each read (n_reads + 1)
+};
 
-__device__ __forceinline__ void emit_seed(const SeedParams &P, uint32_t read_id, int i, int j, uint64_t k, uint64_t kr,
-                                          uint64_t s) {
-  const uint64_t slot = active_slot(&P.ctl[C_NSEEDS]);
-  if (slot < P.seed_cap) {
-    SeedRec r;
-    r.read_id = read_id; r.qbeg = (uint32_t)i; r.qend = (uint32_t)j; r.flags = P.round == 2 ? MBW_SEED_ROUND2 : 0u;
-    r.k = k; r.kr = kr; r.s = s;
-    P.seeds[slot] = r;
-  }
-  if (P.round == 1 && P.reseed && j - i >= P.reseed_len && s <= (uint64_t)P.reseed_occ) {
-    const uint64_t qs = active_slot(&P.ctl[C_NSUBQ]);
-    if (qs < P.subq_cap) {
-      Query q; q.read_id = read_id; q.qbeg = (uint32_t)i; q.qend = (uint32_t)j; q.l = (uint32_t)((j - i) / 2);
-      q.c = (uint32_t)(s + 1);
-      P.subq[qs] = q;
-    }
-  }
-}
-
-__device__ __forceinline__ void load_query(const SeedParams &P, uint64_t qi, uint32_t &read_id, uint32_t &qbeg,
-                                           uint32_t &qend, uint32_t &l, uint32_t &c) {
-  if (P.queries) {
-    Query q = P.queries[qi];
-    read_id = q.read_id; qbeg = q.qbeg; qend = q.qend; l = q.l; c = q.c;
-  } else {
-    read_id = (uint32_t)qi; qbeg = 0; qend = (uint32_t)(P.offs[qi + 1] - P.offs[qi]); l = (uint32_t)P.l; c = (uint32_t)P.c;
-  }
+inline unsigned grid_for(uint64_t n, unsigned bs = 256, unsigned cap = 65536u * 8) {
+  uint64_t g = (n + bs - 1) / bs;
+  if (g < 1) g = 1;
+  return (unsigned)std::min<uint64_t>(g, cap);
 }
 
 // ---------------------------------------------------------------------------------------------
-// encode
+// encode / pack
 __global__ void k_encode(const uint8_t *__restrict__ in, uint64_t total, int role, uint8_t *__restrict__ out) {
   for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < total; t += (uint64_t)gridDim.x * blockDim.x) {
     uint8_t ch = in[t], c;
@@ -124,221 +99,35 @@ __global__ void k_widen(const uint32_t *__restrict__ len, uint64_t n, uint64_t *
   atomicMax(maxlen, (unsigned long long)mx);
 }
 
-// ---------------------------------------------------------------------------------------------
-// cooperative SMEM kernel (Algorithm 3 per 8-lane group; persistent work queue)
-//
-// Each group holds one query's record (u, i, j, (k, k', s)) in registers (all eight lanes hold the
-// same values) and advances it by one memory action per iteration: a k-mer table lookup, a
-// backward step or a forward step.  Stage changes that need no memory are taken in between.
-enum { ACT_DONE = 0, ACT_KMER = 1, ACT_BWD = 2, ACT_FWD = 3 };
+__global__ void k_read_words(const uint64_t *__restrict__ offs, uint64_t n, uint64_t *__restrict__ nwords) {
+  for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r <= n; r += (uint64_t)gridDim.x * blockDim.x)
+    nwords[r] = r < n ? (offs[r + 1] - offs[r] + 31) / 32 : 0;
+}
 
-template <int SLOT>
-__global__ void __launch_bounds__(256) k_smem_coop(IndexView ix, SeedParams P) {
-  extern __shared__ uint8_t lds[];
-  const int q = threadIdx.x & (MBW_GROUP - 1);
-  uint8_t *slot = lds + (threadIdx.x / MBW_GROUP) * (SLOT > 0 ? SLOT : 1);
-  const uint8_t *rb = nullptr;
-  uint32_t read_id = 0, qbeg = 0, qend = 0, l = 0, c = 1;
-  int u = 0, i = 0, j = 0;
-  uint64_t k = 0, kr = 0, s = 0;
-  bool fresh = false, active = false;
-  uint64_t n_lines = 0, n_steps = 0, n_kmer = 0;
-  uint64_t qnext = 0, qlast = 0;
-  uint64_t budget = 0;   // iterations left for the current query (guards against a runaway state)
-  const int K = (P.use_kmer && ix.kmer) ? ix.K : 0;
-
-  auto base_at = [&](int p) -> int {
-    if (SLOT > 0) return slot[p - (int)qbeg];
-    return rb[p];
-  };
-
-  for (;;) {
-    if (!active) {
-      if (qnext >= qlast) {
-        unsigned long long b0 = 0;
-        if (q == 0) b0 = atomicAdd(&P.ctl[C_WORK], (unsigned long long)P.grab);
-        b0 = __shfl(b0, 0, MBW_GROUP);
-        if (b0 >= P.n_queries) break;
-        qnext = b0;
-        qlast = b0 + (uint64_t)P.grab < P.n_queries ? b0 + (uint64_t)P.grab : P.n_queries;
-      }
-      uint64_t qi = qnext++;
-      load_query(P, qi, read_id, qbeg, qend, l, c);
-      if (read_id == INVALID_READ || !(l >= 1 && l - 1 < qend - qbeg)) continue;   // Algorithm 3 queues a string only if l-1 < |P|
-      rb = P.codes + P.offs[read_id];
-      if (SLOT > 0) {
-        int len = (int)(qend - qbeg);
-        for (int t = q; t < len; t += MBW_GROUP) slot[t] = rb[qbeg + t];
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      }
-      u = 1; i = (int)qbeg; j = (int)(qbeg + l - 1);
-      k = 0; kr = 0; s = ix.n; fresh = true; active = true;
-      budget = 8ull * (qend - qbeg) * (qend - qbeg) + 64;
-    }
-    if (--budget == 0) {
-      if (q == 0) atomicOr(&P.ctl[C_ERR], 1ull);
-      active = false;
-      continue;
-    }
-    // ---- stage transitions without memory traffic
-    int act = ACT_DONE;
-    int a = 0;
-    uint32_t code = 0;
-    for (;;) {
-      if (u == 2) {
-        if (j == (int)qend) {                         // reached the end of P: report the SMEM
-          if (q == 0) emit_seed(P, read_id, i, j, k, kr, s);
-          act = ACT_DONE; break;
+__global__ void k_pack_reads(const uint8_t *__restrict__ codes, const uint64_t *__restrict__ offs, const uint64_t *__restrict__ woff,
+                             uint64_t n, uint64_t *__restrict__ pw, uint32_t *__restrict__ pn) {
+  for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < n; r += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t b = offs[r], len = offs[r + 1] - b, w0 = woff[r];
+    for (uint64_t w = 0; w * 32 < len; ++w) {
+      uint64_t v = 0;
+      uint32_t nb = 0;
+      for (int t = 0; t < 32; ++t) {
+        const uint64_t p = w * 32 + t;
+        if (p < len) {
+          const uint8_t cd = codes[b + p];
+          if (cd > 3) nb |= 1u << t;
+          else v |= (uint64_t)cd << (2 * t);
         }
-        a = base_at(j);
-        if (a > 3) {                                  // forward extension fails on a non-ACGT base
-          if (q == 0) emit_seed(P, read_id, i, j, k, kr, s);
-          u = 3; k = 0; kr = 0; s = ix.n; fresh = true;
-          continue;
-        }
-        act = ACT_FWD; break;
       }
-      if (u == 1 && j < i) { u = 2; j = i + (int)l; fresh = false; continue; }
-      if (u == 3 && j <= i) { u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; continue; }
-      if (fresh && K > 0 && j - K + 1 >= (u == 1 ? i : i + 1)) {
-        bool ok = true;
-        code = 0;
-        for (int t = j - K + 1; t <= j; ++t) { int b = base_at(t); ok = ok && b < 4; code = code * 4 + (uint32_t)(b & 3); }
-        fresh = false;
-        if (ok) { act = ACT_KMER; break; }
-      }
-      fresh = false;
-      a = base_at(j);
-      if (a > 3) {                                     // BackStep fails on a non-ACGT base
-        if (j + (int)l < (int)qend) { u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; continue; }
-        act = ACT_DONE; break;
-      }
-      act = ACT_BWD; break;
+      pw[w0 + w] = v;
+      pn[w0 + w] = nb;
     }
-    if (act == ACT_DONE) { active = false; continue; }
-    if (act == ACT_KMER) {
-      uint4 e = ix.kmer[code];
-      uint64_t ek, ekr, es;
-      kmer_unpack(e, ek, ekr, es);
-      ++n_kmer;
-      if (es >= c) { k = ek; kr = ekr; s = es; j -= K; }
-      continue;
-    }
-    // ---- one extension step (Algorithm 1), one or two lines
-    const bool bwd = act == ACT_BWD;
-    const uint64_t x = bwd ? k : kr, y = bwd ? kr : k;
-    const int cc = bwd ? a : 3 - a;
-    const uint64_t x2 = x + s;
-    const uint64_t L1 = line_of(x), L2 = line_of(x2);
-    uint4 d1 = ix.lines[L1 * MBW_LINE_U4 + q];
-    uint4 d2 = d1;
-    if (L2 != L1) d2 = ix.lines[L2 * MBW_LINE_U4 + q];
-    n_lines += (L2 != L1) ? 2 : 1;
-    ++n_steps;
-    uint64_t E1, G1, E2, G2;
-    slice_eg(d1, q, (int)(x - L1 * MBW_BPL), cc, E1, G1);
-    slice_eg(d2, q, (int)(x2 - L2 * MBW_BPL), cc, E2, G2);
-    uint64_t sE1 = grp_sum64(E1);
-    uint64_t dE = grp_sum64(E2 - E1);
-    uint64_t dG = grp_sum64(G2 - G1);
-    if (cc == 0) {                      // the $ row is stored as A
-      uint64_t c1 = x > ix.primary ? 1 : 0, c2 = x2 > ix.primary ? 1 : 0;
-      sE1 -= c1;
-      dE -= c2 - c1;
-    }
-    const uint64_t dol = (x <= ix.primary && ix.primary < x2) ? 1 : 0;
-    const uint64_t ns = dE;
-    const uint64_t nx = sel4(ix.Cb[0], ix.Cb[1], ix.Cb[2], ix.Cb[3], cc) + sE1;
-    const uint64_t ny = y + dol + dG;
-    if (ns >= c) {
-      if (bwd) { k = nx; kr = ny; s = ns; j -= 1; }
-      else { kr = nx; k = ny; s = ns; j += 1; }
-      continue;
-    }
-    if (bwd) {                                        // BackStep failure: jump past j
-      if (j + (int)l < (int)qend) { u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; }
-      else active = false;
-    } else {                                          // forward failure: report, then stage 3 from j
-      if (q == 0) emit_seed(P, read_id, i, j, k, kr, s);
-      u = 3; k = 0; kr = 0; s = ix.n; fresh = true;
-    }
-  }
-  if (q == 0) {
-    atomicAdd(&P.ctl[C_LINES], (unsigned long long)(n_lines + n_kmer));
-    atomicAdd(&P.ctl[C_STEPS], (unsigned long long)n_steps);
-    atomicAdd(&P.ctl[C_KMER], (unsigned long long)n_kmer);
   }
 }
 
 // ---------------------------------------------------------------------------------------------
-// Wave-cooperative fetch (default schedule): every lane owns one query (or one locate walk).  Each
-// step the wave gathers the lines its lanes need with eight 16-byte loads per lane: in load t, the
-// eight lanes 8g..8g+7 fetch the eight slices of the line wanted by lane 8t+g, so one instruction
-// moves eight whole 128-byte lines.  The slices land in LDS (8 KB per wave, rotated by lane to
-// spread banks) and each lane then ranks its own line without any cross-lane reduction.
-#define WAVE_U4 (64 * MBW_LINE_U4)
-
-__device__ __forceinline__ int slot_of(int r, int j) { return r * MBW_LINE_U4 + ((j + r) & 7); }
-
-#define WF_LOAD(t)                                                                             \
-  {                                                                                            \
-    const int src = 8 * (t) + (lane >> 3);                                                     \
-    const uint32_t Ls = (uint32_t)__shfl((int)myL, src);                                       \
-    if (__shfl((int)myneed, src)) d##t = lines[(uint64_t)Ls * MBW_LINE_U4 + (lane & 7)];       \
-  }
-#define WF_STORE(t) buf[slot_of(8 * (t) + (lane >> 3), lane & 7)] = d##t;
-
-// Slices of lanes that need nothing are stored too (stale data in slots nobody reads).
-__device__ __forceinline__ void wave_fetch(const uint4 *__restrict__ lines, uint32_t myL, bool myneed, uint4 *buf, int lane) {
-  uint4 d0 = make_uint4(0, 0, 0, 0), d1 = d0, d2 = d0, d3 = d0, d4 = d0, d5 = d0, d6 = d0, d7 = d0;
-  WF_LOAD(0) WF_LOAD(1) WF_LOAD(2) WF_LOAD(3) WF_LOAD(4) WF_LOAD(5) WF_LOAD(6) WF_LOAD(7)
-  WF_STORE(0) WF_STORE(1) WF_STORE(2) WF_STORE(3) WF_STORE(4) WF_STORE(5) WF_STORE(6) WF_STORE(7)
-  __builtin_amdgcn_wave_barrier();
-}
-
-__device__ __forceinline__ uint64_t pmask(int m) { return m >= 32 ? M55 : (((1ull << (2 * (m < 0 ? 0 : m))) - 1) & M55); }
-__device__ __forceinline__ uint64_t eq_bits(uint64_t w, int c) {
-  uint64_t hi = (w >> 1) & M55, lo = w & M55;
-  return c == 0 ? (~(hi | lo) & M55) : (c == 1 ? (~hi & lo) : (c == 2 ? (hi & ~lo) : (hi & lo)));
-}
-__device__ __forceinline__ uint64_t gt_bits(uint64_t w, int c) {
-  uint64_t hi = (w >> 1) & M55, lo = w & M55;
-  return c == 0 ? (hi | lo) : (c == 1 ? hi : (c == 2 ? (hi & lo) : 0ull));
-}
-
-// Occ(c, .) (E) and sum_{d>c} Occ(d, .) (G) at offsets o1 and o2 (o2 < 0: not needed) of the line
-// staged for this lane; $ not corrected.
-__device__ __forceinline__ void lane_eg(const uint4 *buf, int lane, int c, int o1, int o2, uint64_t &E1, uint64_t &G1,
-                                        uint64_t &E2, uint64_t &G2) {
-  const uint4 h0 = buf[slot_of(lane, 0)], h1 = buf[slot_of(lane, 1)];
-  const uint64_t cA = ((uint64_t)h0.y << 32) | h0.x, cC = ((uint64_t)h0.w << 32) | h0.z;
-  const uint64_t cG = ((uint64_t)h1.y << 32) | h1.x, cT = ((uint64_t)h1.w << 32) | h1.z;
-  const uint64_t he = sel4(cA, cC, cG, cT, c);
-  const uint64_t hg = (c < 1 ? cC : 0) + (c < 2 ? cG : 0) + (c < 3 ? cT : 0);
-  uint32_t e1 = 0, g1 = 0, e2 = 0, g2 = 0;
-  const int omax = o1 > o2 ? o1 : o2;
-#pragma unroll
-  for (int sl = 2; sl < 8; ++sl) {
-    const int base = (sl - 2) * 64;
-    if (base < omax) {
-      const uint4 d = buf[slot_of(lane, sl)];
-      const uint64_t w0 = ((uint64_t)d.y << 32) | d.x, w1 = ((uint64_t)d.w << 32) | d.z;
-      const uint64_t ea = eq_bits(w0, c), eb = eq_bits(w1, c), ga = gt_bits(w0, c), gb = gt_bits(w1, c);
-      const int m1 = o1 - base, m2 = o2 - base;
-      const uint64_t p1a = pmask(m1), p1b = pmask(m1 - 32), p2a = pmask(m2), p2b = pmask(m2 - 32);
-      e1 += __popcll(ea & p1a) + __popcll(eb & p1b);
-      g1 += __popcll(ga & p1a) + __popcll(gb & p1b);
-      e2 += __popcll(ea & p2a) + __popcll(eb & p2b);
-      g2 += __popcll(ga & p2a) + __popcll(gb & p2b);
-    }
-  }
-  E1 = he + e1; G1 = hg + g1; E2 = he + e2; G2 = hg + g2;
-}
-
-struct Emit { uint32_t i, j; uint64_t k, kr, s; };
-
-// Work and output are handed out in chunks per wave so that hot counters see one atomic per chunk
-// (device-scope atomics on a single address serialise).  All 64 lanes must call these together.
+// wave-level work and output distribution.  Hot counters see one atomic per chunk (device-scope
+// atomics on a single address serialise).  All 64 lanes of a wave call these together.
 #define WORK_CHUNK 256
 #define OUT_CHUNK 256
 
@@ -370,7 +159,6 @@ __device__ __forceinline__ uint64_t wave_take(bool want, uint64_t &cb, uint64_t 
 }
 
 // Reserve one output slot for every lane with `em`, from the wave's current output chunk.
-// Slots past `cap` are reported as ~0 (the host grows the buffer and runs again).
 __device__ __forceinline__ uint64_t wave_slot(bool em, uint64_t &ob, uint64_t &oe, unsigned long long *counter, int lane) {
   uint64_t m = __ballot(em);
   uint64_t res = ~0ull;
@@ -394,9 +182,12 @@ __device__ __forceinline__ uint64_t wave_slot(bool em, uint64_t &ob, uint64_t &o
   return res;
 }
 
+struct Emit { uint32_t i, j; uint64_t k, kr, s; };
 struct WaveOut { uint64_t sb, se, qb, qe; };
 
-__device__ __forceinline__ void wave_emit(const SeedParams &P, int lane, bool em, uint32_t read_id, const Emit &e, WaveOut &wo) {
+// this iteration's SMEMs (at most one per lane) and, in round 1, their re-seeding queries
+__device__ __forceinline__ void wave_emit(const SeedParams &P, int lane, bool em, uint32_t read_id, const Emit &e, WaveOut &wo,
+                                          uint32_t rlen, uint64_t woff) {
   if (!__ballot(em)) return;
   const uint64_t slot = wave_slot(em, wo.sb, wo.se, &P.ctl[C_NSEEDS], lane);
   if (em && slot < P.seed_cap) {
@@ -409,7 +200,9 @@ __device__ __forceinline__ void wave_emit(const SeedParams &P, int lane, bool em
   if (!__ballot(rq)) return;
   const uint64_t qs = wave_slot(rq, wo.qb, wo.qe, &P.ctl[C_NSUBQ], lane);
   if (rq && qs < P.subq_cap) {
-    Query q; q.read_id = read_id; q.qbeg = e.i; q.qend = e.j; q.l = (e.j - e.i) / 2; q.c = (uint32_t)(e.s + 1);
+    Query q;
+    q.read_id = read_id; q.qbeg = e.i; q.qend = e.j; q.l = (e.j - e.i) / 2; q.c = (uint32_t)(e.s + 1);
+    q.rlen = rlen; q.woff_lo = (uint32_t)woff; q.woff_hi = (uint32_t)(woff >> 32);
     P.subq[qs] = q;
   }
 }
@@ -419,59 +212,106 @@ __device__ __forceinline__ void wave_close(const SeedParams &P, int lane, const 
   for (uint64_t t = wo.sb + lane; t < wo.se; t += 64)
     if (t < P.seed_cap) { SeedRec r; r.read_id = INVALID_READ; r.qbeg = r.qend = r.flags = 0; r.k = r.kr = r.s = 0; P.seeds[t] = r; }
   for (uint64_t t = wo.qb + lane; t < wo.qe; t += 64)
-    if (t < P.subq_cap) { Query q; q.read_id = INVALID_READ; q.qbeg = q.qend = q.l = 0; q.c = 1; P.subq[t] = q; }
+    if (t < P.subq_cap) {
+      Query q; q.read_id = INVALID_READ; q.qbeg = q.qend = q.l = q.rlen = q.woff_lo = q.woff_hi = 0; q.c = 1;
+      P.subq[t] = q;
+    }
 }
 
-__global__ void __launch_bounds__(256) k_smem_wave(IndexView ix, SeedParams P) {
-  __shared__ uint4 lbuf[4 * WAVE_U4];
-  const int lane = threadIdx.x & 63;
-  uint4 *buf = lbuf + (threadIdx.x >> 6) * WAVE_U4;
+// ---------------------------------------------------------------------------------------------
+// wave-cooperative line fetch, straight into LDS (global_load_lds, 16 bytes per lane).  Load t of
+// lane L writes buf[64 t + L] (the hardware places lane L's 16 bytes at base + 16 L) and fetches
+// slice ((L & 7) + (L >> 3)) & 7 of the line wanted by lane r = 8 t + (L >> 3); so slice j of
+// lane r's line sits at buf[8 r + ((j - r) & 7)], rotated by r to spread the LDS banks.
+#define WAVE_U4 (64 * MBW_LINE_U4)
+typedef __attribute__((address_space(3))) void lds_void;
+
+__device__ __forceinline__ void fetch_lines_lds(const uint4 *__restrict__ lines, uint32_t myL, bool myneed, uint4 *buf, int lane) {
+  const int g = lane >> 3, j = ((lane & 7) + g) & 7;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int src = 8 * t + g;
+    const uint32_t Ls = (uint32_t)__shfl((int)myL, src);
+    if (__shfl((int)myneed, src))
+      __builtin_amdgcn_global_load_lds((const void *)(lines + (uint64_t)Ls * MBW_LINE_U4 + j), (lds_void *)(buf + 64 * t), 16, 0, 0);
+  }
+}
+
+__device__ __forceinline__ uint4 lds_slice(const uint4 *buf, int lane, int j) { return buf[8 * lane + ((j - lane) & 7)]; }
+
+// (E, G) at offsets o1 and, if o2 >= 0, o2 of the line staged for this lane
+__device__ __forceinline__ void rank_lds(const uint4 *buf, int lane, int c, const SymMasks &sm, uint64_t sbe, uint64_t sbg,
+                                         int o1, int o2, uint64_t &E1, uint64_t &G1, uint64_t &E2, uint64_t &G2) {
+  const uint4 h0 = lds_slice(buf, lane, 0), h1 = lds_slice(buf, lane, 1);
+  const int s1 = block_slice(o1);
+  rank_eg(h0, h1, lds_slice(buf, lane, s1), lds_slice(buf, lane, s1 + 1), o1, c, sm, sbe, sbg, E1, G1);
+  if (o2 >= 0) {
+    const int s2 = block_slice(o2);
+    rank_eg(h0, h1, lds_slice(buf, lane, s2), lds_slice(buf, lane, s2 + 1), o2, c, sm, sbe, sbg, E2, G2);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// SMEM kernel, wave schedule (Algorithm 3 per lane; persistent).
+//
+// Lane states: IDLE (takes a query), REC (the query's record is loaded in this iteration's memory
+// phase), STAGE (the read's packed words are loaded; STAGED only), ACTIVE (one memory action per
+// iteration: a k-mer table lookup or a backward/forward extension), DRAINED.  Stage changes that
+// need no memory are taken before the memory phase.
+#define STAGE_WORDS 5   // staged reads of up to 160 bases
+enum { ACT_DONE = 0, ACT_KMER = 1, ACT_BWD = 2, ACT_FWD = 3 };
+enum { ST_IDLE = 0, ST_REC = 1, ST_STAGE = 2, ST_ACTIVE = 3, ST_DRAINED = 4 };
+
+template <bool STAGED>
+__global__ void __launch_bounds__(128) k_smem_wave(IndexView ix, SeedParams P, ReadWords R) {
+  __shared__ uint4 lbuf[2][2 * WAVE_U4];                        // per wave: first and second lines
+  __shared__ uint64_t sw[2][STAGED ? STAGE_WORDS * 64 : 1];     // staged bases, word w of lane L at [64 w + L]
+  __shared__ uint32_t sn[2][STAGED ? STAGE_WORDS * 64 : 1];     // staged N bits
+  __shared__ uint64_t sbt[MBW_MAX_SB * 8];
+  for (int t = threadIdx.x; t < 8 * ix.n_sb; t += blockDim.x) sbt[t] = ix.sbtab[t];
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint4 *bufA = lbuf[wv], *bufB = lbuf[wv] + WAVE_U4;
+  uint64_t *mw = sw[wv];
+  uint32_t *mn = sn[wv];
   const int K = (P.use_kmer && ix.kmer) ? ix.K : 0;
-  const uint8_t *rb = nullptr;
+  int st = ST_IDLE;
+  uint64_t qi = 0, wo = 0;
+  uint32_t nw = 0, rlen = 0;
+  auto word_at = [&](int w) -> uint64_t { return STAGED ? mw[64 * w + lane] : R.pw[wo + w]; };
+  auto nbits_at = [&](int w) -> uint32_t { return STAGED ? mn[64 * w + lane] : R.pn[wo + w]; };
+  auto base_at = [&](int p) -> int {
+    const int w = p >> 5, b = p & 31;
+    return ((nbits_at(w) >> b) & 1) ? 4 : (int)((word_at(w) >> (2 * b)) & 3);
+  };
   uint32_t read_id = 0, qbeg = 0, qend = 0, l = 0, c = 1;
   int u = 0, i = 0, j = 0;
   uint64_t k = 0, kr = 0, s = 0, budget = 0;
-  bool fresh = false, active = false, drained = false;
+  bool fresh = false;
   uint64_t n_lines = 0, n_steps = 0, n_kmer = 0;
   uint64_t cb = 0, ce = 0;
-  WaveOut wo = {0, 0, 0, 0};
+  WaveOut wout = {0, 0, 0, 0};
   for (;;) {
-    // ---- refill idle lanes from the wave's work chunk
-    const bool want = !active && !drained;
+    // ---- idle lanes take a query (its record is loaded in this iteration's memory phase)
+    const bool want = st == ST_IDLE;
     if (__ballot(want)) {
-      const uint64_t qi = wave_take(want, cb, ce, &P.ctl[C_WORK], P.n_queries, lane);
-      if (want) {
-        if (qi == ~0ull) drained = true;
-        else {
-          load_query(P, qi, read_id, qbeg, qend, l, c);
-          if (read_id != INVALID_READ && l >= 1 && l - 1 < qend - qbeg) {
-            rb = P.codes + P.offs[read_id];
-            u = 1; i = (int)qbeg; j = (int)(qbeg + l - 1);
-            k = 0; kr = 0; s = ix.n; fresh = true; active = true;
-            budget = 8ull * (qend - qbeg) * (qend - qbeg) + 64;
-          }
-        }
-      }
+      const uint64_t t = wave_take(want, cb, ce, &P.ctl[C_WORK], P.n_queries, lane);
+      if (want) { if (t == ~0ull) st = ST_DRAINED; else { qi = t; st = ST_REC; } }
     }
-    if (__ballot(active) == 0) {
-      if (__ballot(!drained) == 0) break;
-      continue;
-    }
-    // ---- per-lane stage transitions up to the next memory action
+    if (__ballot(st != ST_DRAINED) == 0) break;
+    // ---- active lanes: stage transitions up to the next memory action
     int act = ACT_DONE, a = 0;
     uint32_t code = 0;
     bool em = false;
     Emit e;
     e.i = 0; e.j = 0; e.k = 0; e.kr = 0; e.s = 0;
-    if (active) {
-      if (--budget == 0) { atomicOr(&P.ctl[C_ERR], 1ull); active = false; }
-    }
-    if (active) {
+    if (st == ST_ACTIVE && --budget == 0) { atomicOr(&P.ctl[C_ERR], 1ull); st = ST_IDLE; }
+    if (st == ST_ACTIVE) {
       for (;;) {
         if (u == 2) {
           if (j == (int)qend) { em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s; act = ACT_DONE; break; }
-          a = rb[j];
-          if (a > 3) {
+          a = base_at(j);
+          if (a > 3) {                                  // forward extension fails on a non-ACGT base
             em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s;
             u = 3; k = 0; kr = 0; s = ix.n; fresh = true;
             continue;
@@ -481,80 +321,131 @@ __global__ void __launch_bounds__(256) k_smem_wave(IndexView ix, SeedParams P) {
         if (u == 1 && j < i) { u = 2; j = i + (int)l; fresh = false; continue; }
         if (u == 3 && j <= i) { u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; continue; }
         if (fresh && K > 0 && j - K + 1 >= (u == 1 ? i : i + 1)) {
-          bool ok = true;
-          code = 0;
-          for (int t = j - K + 1; t <= j; ++t) { int b = rb[t]; ok = ok && b < 4; code = code * 4 + (uint32_t)(b & 3); }
+          // k-mer P[j-K+1 .. j] from the packed read: its code is the bit field 2(j-K+1) .. 2(j+1)
+          const int a0 = j - K + 1, w = a0 >> 5, b0 = a0 & 31;
+          uint64_t bits = word_at(w) >> (2 * b0);
+          uint32_t nbits = nbits_at(w) >> b0;
+          if (b0 + K > 32) { bits |= word_at(w + 1) << (64 - 2 * b0); nbits |= nbits_at(w + 1) << (32 - b0); }
           fresh = false;
-          if (ok) { act = ACT_KMER; break; }
+          if ((nbits & ((1u << K) - 1)) == 0) { code = (uint32_t)(bits & ((1ull << (2 * K)) - 1)); act = ACT_KMER; break; }
         }
         fresh = false;
-        a = rb[j];
-        if (a > 3) {
+        a = base_at(j);
+        if (a > 3) {                                    // BackStep fails on a non-ACGT base
           if (j + (int)l < (int)qend) { u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; continue; }
           act = ACT_DONE; break;
         }
         act = ACT_BWD; break;
       }
-      if (act == ACT_DONE) active = false;
+      if (act == ACT_DONE) st = ST_IDLE;
     }
-    // ---- k-mer lookups (one 16-byte load per lane)
-    if (act == ACT_KMER) {
-      uint64_t ek, ekr, es;
-      kmer_unpack(ix.kmer[code], ek, ekr, es);
-      ++n_kmer;
-      if (es >= c) { k = ek; kr = ekr; s = es; j -= K; }
-    }
-    // ---- extension steps (Algorithm 1) with the wave-cooperative fetch
     const bool ext = act == ACT_BWD || act == ACT_FWD;
     const bool bwd = act == ACT_BWD;
     const uint64_t x1 = bwd ? k : kr, y = bwd ? kr : k;
     const int cc = bwd ? a : 3 - a;
     const uint64_t x2 = x1 + s;
-    const uint32_t L1 = ext ? (uint32_t)line_of(x1) : 0u, L2 = ext ? (uint32_t)line_of(x2) : 0u;
-    if (__ballot(ext)) {
-      wave_fetch(ix.lines, L1, ext, buf, lane);
-      const bool same = L1 == L2;
-      uint64_t E1 = 0, G1 = 0, E2 = 0, G2 = 0;
-      if (ext) lane_eg(buf, lane, cc, (int)(x1 - (uint64_t)L1 * MBW_BPL), same ? (int)(x2 - (uint64_t)L2 * MBW_BPL) : -1,
-                       E1, G1, E2, G2);
-      const bool two = ext && !same;
-      if (__ballot(two)) {
-        wave_fetch(ix.lines, L2, two, buf, lane);
-        if (two) {
-          uint64_t t1, t2;
-          lane_eg(buf, lane, cc, (int)(x2 - (uint64_t)L2 * MBW_BPL), -1, E2, G2, t1, t2);
-        }
-      }
-      if (ext) {
-        n_lines += two ? 2 : 1;
-        ++n_steps;
-        if (cc == 0) { E1 -= x1 > ix.primary ? 1 : 0; E2 -= x2 > ix.primary ? 1 : 0; }
-        const uint64_t dol = (x1 <= ix.primary && ix.primary < x2) ? 1 : 0;
-        const uint64_t ns = E2 - E1;
-        const uint64_t nx = sel4(ix.Cb[0], ix.Cb[1], ix.Cb[2], ix.Cb[3], cc) + E1;
-        const uint64_t ny = y + dol + (G2 - G1);
-        if (ns >= c) {
-          if (bwd) { k = nx; kr = ny; s = ns; j -= 1; }
-          else { kr = nx; k = ny; s = ns; j += 1; }
-        } else if (bwd) {
-          if (j + (int)l < (int)qend) { u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; }
-          else active = false;
-        } else {
-          em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s;
-          u = 3; k = 0; kr = 0; s = ix.n; fresh = true;
-        }
+    const uint32_t L1 = ext ? line_of(x1) : 0u, L2 = ext ? line_of(x2) : 0u;
+    const bool two = ext && L1 != L2;
+    // ---- the memory phase: everything the wave needs, issued together, waited for once
+    if (__ballot(ext)) fetch_lines_lds(ix.lines, L1, ext, bufA, lane);
+    if (__ballot(two)) fetch_lines_lds(ix.lines, L2, two, bufB, lane);
+    uint4 kent = make_uint4(0, 0, 0, 0);
+    if (act == ACT_KMER) kent = ix.kmer[code];
+    const int st_mem = st;
+    uint64_t r0 = 0, r1 = 0, r2 = 0;
+    Query qrec;
+    qrec.read_id = INVALID_READ; qrec.qbeg = qrec.qend = qrec.l = qrec.rlen = qrec.woff_lo = qrec.woff_hi = 0; qrec.c = 1;
+    if (st_mem == ST_REC) {
+      if (P.queries) qrec = P.queries[qi];
+      else { r0 = P.offs[qi]; r1 = P.offs[qi + 1]; r2 = R.woff[qi]; }
+    }
+    uint64_t g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0;
+    uint32_t h0 = 0, h1 = 0, h2 = 0, h3 = 0, h4 = 0;
+    if (STAGED && st_mem == ST_STAGE) {
+      g0 = R.pw[wo]; h0 = R.pn[wo];
+      if (nw > 1) { g1 = R.pw[wo + 1]; h1 = R.pn[wo + 1]; }
+      if (nw > 2) { g2 = R.pw[wo + 2]; h2 = R.pn[wo + 2]; }
+      if (nw > 3) { g3 = R.pw[wo + 3]; h3 = R.pn[wo + 3]; }
+      if (nw > 4) { g4 = R.pw[wo + 4]; h4 = R.pn[wo + 4]; }
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    // ---- compute
+    if (act == ACT_KMER) {
+      uint64_t ek, ekr, es;
+      kmer_unpack(kent, ek, ekr, es);
+      ++n_kmer;
+      if (es >= c) { k = ek; kr = ekr; s = es; j -= K; }
+    }
+    if (ext) {
+      const SymMasks sm = sym_masks(cc);
+      const uint32_t sb1 = 8 * (L1 >> MBW_SB_SHIFT), sb2 = 8 * (L2 >> MBW_SB_SHIFT);
+      const int o1 = (int)(x1 - (uint64_t)L1 * MBW_BPL), o2 = (int)(x2 - (uint64_t)L2 * MBW_BPL);
+      uint64_t E1, G1, E2, G2, t1, t2;
+      rank_lds(bufA, lane, cc, sm, sbt[sb1 + cc], sbt[sb1 + 4 + cc], o1, two ? -1 : o2, E1, G1, E2, G2);
+      if (two) rank_lds(bufB, lane, cc, sm, sbt[sb2 + cc], sbt[sb2 + 4 + cc], o2, -1, E2, G2, t1, t2);
+      n_lines += two ? 2 : 1;
+      ++n_steps;
+      uint64_t nx, ny, ns;
+      ext_update(E1, G1, E2, G2, cc, x1, s, y, ix.primary, ix.Cb, nx, ny, ns);
+      if (ns >= c) {
+        if (bwd) { k = nx; kr = ny; s = ns; j -= 1; }
+        else { kr = nx; k = ny; s = ns; j += 1; }
+      } else if (bwd) {                                 // BackStep failure: jump past j
+        if (j + (int)l < (int)qend) { u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; }
+        else st = ST_IDLE;
+      } else {                                          // forward failure: report, then stage 3 from j
+        em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s;
+        u = 3; k = 0; kr = 0; s = ix.n; fresh = true;
       }
     }
-    wave_emit(P, lane, em, read_id, e, wo);
+    if (STAGED && st_mem == ST_STAGE) {
+      mw[lane] = g0; mn[lane] = h0;
+      mw[64 + lane] = g1; mn[64 + lane] = h1;
+      mw[128 + lane] = g2; mn[128 + lane] = h2;
+      mw[192 + lane] = g3; mn[192 + lane] = h3;
+      mw[256 + lane] = g4; mn[256 + lane] = h4;
+    }
+    if (st_mem == ST_REC) {
+      if (P.queries) {
+        read_id = qrec.read_id; qbeg = qrec.qbeg; qend = qrec.qend; l = qrec.l; c = qrec.c;
+        rlen = qrec.rlen; wo = ((uint64_t)qrec.woff_hi << 32) | qrec.woff_lo;
+      } else {
+        read_id = (uint32_t)qi; qbeg = 0; qend = (uint32_t)(r1 - r0); l = (uint32_t)P.l; c = (uint32_t)P.c;
+        rlen = qend; wo = r2;
+      }
+      nw = (rlen + 31) >> 5;
+      // Algorithm 3 queues a string only if l - 1 < |P|
+      const bool work = read_id != INVALID_READ && l >= 1 && l - 1 < qend - qbeg && (!STAGED || nw <= STAGE_WORDS);
+      st = !work ? ST_IDLE : (STAGED ? ST_STAGE : ST_ACTIVE);
+    }
+    if ((STAGED && st_mem == ST_STAGE) || (!STAGED && st_mem == ST_REC && st == ST_ACTIVE)) {
+      u = 1; i = (int)qbeg; j = (int)(qbeg + l - 1);
+      k = 0; kr = 0; s = ix.n; fresh = true;
+      budget = 8ull * (qend - qbeg) * (qend - qbeg) + 64;
+      st = ST_ACTIVE;
+    }
+    wave_emit(P, lane, em, read_id, e, wout, rlen, wo);
   }
-  wave_close(P, lane, wo);
+  wave_close(P, lane, wout);
   atomicAdd(&P.ctl[C_LINES], (unsigned long long)(n_lines + n_kmer));
   atomicAdd(&P.ctl[C_STEPS], (unsigned long long)n_steps);
   atomicAdd(&P.ctl[C_KMER], (unsigned long long)n_kmer);
 }
 
 // ---------------------------------------------------------------------------------------------
-// plain SMEM kernel: one thread = one read, the serial algorithm with round 2 run inline
+// plain SMEM kernel: one thread = one read, the serial algorithm, round 2 run inline
+
+// One output slot for each lane active here: one atomic per group of simultaneously emitting lanes.
+__device__ __forceinline__ uint64_t active_slot(unsigned long long *counter) {
+  const uint64_t m = __ballot(1);
+  const int lane = (int)(threadIdx.x & 63);
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  unsigned long long b0 = 0;
+  if (lane == leader) b0 = atomicAdd(counter, (unsigned long long)__popcll(m));
+  b0 = __shfl(b0, leader);
+  return b0 + __popcll(m & ((1ull << lane) - 1));
+}
+
 struct PlainCtx {
   IndexView ix;
   const SeedParams *P;
@@ -563,17 +454,17 @@ struct PlainCtx {
   uint64_t lines, steps;
 };
 
-__device__ __forceinline__ uint64_t plain_step(PlainCtx &C, bool bwd, int a, uint64_t &k, uint64_t &kr, uint64_t s,
+__device__ __forceinline__ uint64_t plain_step(PlainCtx &C, bool bwd, int a, uint64_t k, uint64_t kr, uint64_t s,
                                                uint64_t &nk, uint64_t &nkr) {
   const uint64_t x = bwd ? k : kr, y = bwd ? kr : k;
   const int cc = bwd ? a : 3 - a;
-  const uint64_t x2 = x + s;
-  Occ4 o1 = occ_single(C.ix.lines, x, C.ix.primary);
-  Occ4 o2 = occ_single(C.ix.lines, x2, C.ix.primary);
-  C.lines += line_of(x) == line_of(x2) ? 1 : 2;
+  uint64_t E1, G1, E2, G2;
+  rank_global(C.ix, x, cc, E1, G1);
+  rank_global(C.ix, x + s, cc, E2, G2);
+  C.lines += line_of(x) == line_of(x + s) ? 1 : 2;
   C.steps++;
   uint64_t nx, ny, ns;
-  ext_update(o1, o2, cc, x, s, y, C.ix.primary, C.ix.Cb, nx, ny, ns);
+  ext_update(E1, G1, E2, G2, cc, x, s, y, C.ix.primary, C.ix.Cb, nx, ny, ns);
   if (bwd) { nk = nx; nkr = ny; } else { nkr = nx; nk = ny; }
   return ns;
 }
@@ -594,18 +485,15 @@ __device__ void plain_alg3(PlainCtx &C, int qbeg, int qend, int l, uint64_t c) {
     if (u == 1 || u == 3) {
       if (u == 1 && j < i) { u = 2; j = i + l; continue; }
       if (u == 3 && j <= i) { u = 1; i = j + 1; j = j + l; k = 0; kr = 0; s = n; continue; }
-      int a = C.rb[j];
+      const int a = C.rb[j];
       uint64_t nk = 0, nkr = 0, ns = 0;
       if (a < 4) ns = plain_step(C, true, a, k, kr, s, nk, nkr);
       if (ns >= c) { k = nk; kr = nkr; s = ns; j -= 1; continue; }
       if (j + l < qend) { u = 1; i = j + 1; j = j + l; k = 0; kr = 0; s = n; continue; }
       return;
     }
-    if (j == qend) {
-      emit_plain<ROUND>(C, i, j, k, kr, s);
-      return;
-    }
-    int a = C.rb[j];
+    if (j == qend) { emit_plain<ROUND>(C, i, j, k, kr, s); return; }
+    const int a = C.rb[j];
     uint64_t nk = 0, nkr = 0, ns = 0;
     if (a < 4) ns = plain_step(C, false, a, k, kr, s, nk, nkr);
     if (ns >= c) { k = nk; kr = nkr; s = ns; j += 1; continue; }
@@ -614,19 +502,25 @@ __device__ void plain_alg3(PlainCtx &C, int qbeg, int qend, int l, uint64_t c) {
   }
 }
 
+__device__ __forceinline__ void plain_record(PlainCtx &C, int round, int i, int j, uint64_t k, uint64_t kr, uint64_t s) {
+  const SeedParams &P = *C.P;
+  const uint64_t slot = active_slot(&P.ctl[C_NSEEDS]);
+  if (slot < P.seed_cap) {
+    SeedRec r;
+    r.read_id = C.read_id; r.qbeg = (uint32_t)i; r.qend = (uint32_t)j; r.flags = round == 2 ? MBW_SEED_ROUND2 : 0u;
+    r.k = k; r.kr = kr; r.s = s;
+    P.seeds[slot] = r;
+  }
+}
+
 template <>
 __device__ void emit_plain<2>(PlainCtx &C, int i, int j, uint64_t k, uint64_t kr, uint64_t s) {
-  SeedParams P2 = *C.P;
-  P2.round = 2;
-  emit_seed(P2, C.read_id, i, j, k, kr, s);
+  plain_record(C, 2, i, j, k, kr, s);
 }
 
 template <>
 __device__ void emit_plain<1>(PlainCtx &C, int i, int j, uint64_t k, uint64_t kr, uint64_t s) {
-  SeedParams P1 = *C.P;
-  P1.round = 1;
-  P1.reseed = 0;   // the sub-query runs inline below instead of being queued
-  emit_seed(P1, C.read_id, i, j, k, kr, s);
+  plain_record(C, 1, i, j, k, kr, s);
   if (C.P->reseed && j - i >= C.P->reseed_len && s <= (uint64_t)C.P->reseed_occ)
     plain_alg3<2>(C, i, j, (j - i) / 2, s + 1);
 }
@@ -636,7 +530,7 @@ __global__ void __launch_bounds__(256) k_smem_plain(IndexView ix, SeedParams P) 
   if (r >= P.n_queries) return;
   PlainCtx C;
   C.ix = ix; C.P = &P; C.read_id = (uint32_t)r; C.rb = P.codes + P.offs[r]; C.lines = 0; C.steps = 0;
-  int len = (int)(P.offs[r + 1] - P.offs[r]);
+  const int len = (int)(P.offs[r + 1] - P.offs[r]);
   plain_alg3<1>(C, 0, len, P.l, (uint64_t)P.c);
   atomicAdd(&P.ctl[C_LINES], (unsigned long long)C.lines);
   atomicAdd(&P.ctl[C_STEPS], (unsigned long long)C.steps);
@@ -644,6 +538,7 @@ __global__ void __launch_bounds__(256) k_smem_plain(IndexView ix, SeedParams P) 
 
 // ---------------------------------------------------------------------------------------------
 // seeds: sort keys, dedup, counts
+
 // sort key (read, qbeg, qend); unused slots (read_id INVALID_READ) get key n_reads << 32, after all
 __global__ void k_seed_keys(const SeedRec *__restrict__ raw, uint64_t ns, uint64_t n_reads, uint64_t *__restrict__ key,
                             uint32_t *__restrict__ val) {
@@ -669,20 +564,25 @@ __global__ void k_seed_emit(const SeedRec *__restrict__ raw, const uint32_t *__r
     mbw_seed_t o;
     o.read_id = r.read_id; o.qbeg = r.qbeg; o.qend = r.qend;
     o.k = r.k; o.kr = r.kr; o.s = r.s; o.pos_off = 0; o.reserved = 0;
-    bool loc = r.s <= max_occ;
+    const bool loc = r.s <= max_occ;
     o.flags = r.flags | (loc ? 0u : MBW_SEED_UNLOCATED);
     o.npos = loc ? (uint32_t)r.s : 0u;
-    uint32_t d = idx[t];
+    const uint32_t d = idx[t];
     out[d] = o;
     npos[d] = o.npos;
   }
 }
 
-__global__ void k_seed_posoff(mbw_seed_t *__restrict__ out, const uint64_t *__restrict__ off, uint64_t ns,
-                              uint32_t *__restrict__ sid_seed) {
-  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < ns; t += (uint64_t)gridDim.x * blockDim.x) {
+__global__ void k_seed_posoff(mbw_seed_t *__restrict__ out, const uint64_t *__restrict__ off, uint64_t ns) {
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < ns; t += (uint64_t)gridDim.x * blockDim.x)
     out[t].pos_off = off[t];
-    if (sid_seed && out[t].npos) sid_seed[off[t]] = (uint32_t)t;
+}
+
+// start row of every (seed, occurrence) pair: X[pos_off + i] = k + i
+__global__ void k_expand_rows(const mbw_seed_t *__restrict__ seeds, uint64_t ns, uint64_t *__restrict__ X) {
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < ns; t += (uint64_t)gridDim.x * blockDim.x) {
+    const mbw_seed_t sd = seeds[t];
+    for (uint32_t i = 0; i < sd.npos; ++i) X[sd.pos_off + i] = sd.k + i;
   }
 }
 
@@ -700,18 +600,20 @@ __device__ __forceinline__ uint64_t sample_index(uint64_t x, uint32_t r, int rsh
 __global__ void __launch_bounds__(256) k_locate_plain(IndexView ix, const mbw_seed_t *__restrict__ seeds, uint64_t ns,
                                                       uint64_t *__restrict__ pos, uint32_t rmask, int rshift,
                                                       unsigned long long *__restrict__ ctl) {
-  uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (t >= ns) return;
-  mbw_seed_t sd = seeds[t];
+  const mbw_seed_t sd = seeds[t];
   uint64_t lines = 0, lf = 0;
   for (uint32_t w = 0; w < sd.npos; ++w) {
     uint64_t x = sd.k + w, steps = 0;
     while (!sampled(x, ix.r, rmask)) {
       if (steps > ix.n) { atomicOr(&ctl[C_ERR], 2ull); x = 0; break; }
       if (x == ix.primary) { x = 0; ++steps; continue; }   // LF of the $ row is row 0
-      int b = bwt_single(ix.lines, x);
-      Occ4 o = occ_single(ix.lines, x, ix.primary);
-      x = ix.Cb[b] + o.v[b];
+      const int b = bwt_global(ix, x);
+      uint64_t E, G;
+      rank_global(ix, x, b, E, G);
+      if (b == 0 && x > ix.primary) E -= 1;
+      x = sel4(ix.Cb[0], ix.Cb[1], ix.Cb[2], ix.Cb[3], b) + E;
       ++steps; ++lines; ++lf;
     }
     uint64_t p = steps + ix.ssa[sample_index(x, ix.r, rshift)];
@@ -725,137 +627,68 @@ __global__ void __launch_bounds__(256) k_locate_plain(IndexView ix, const mbw_se
   }
 }
 
-// cooperative: persistent; each 8-lane group walks one SA row at a time, refilling from a queue
-// of all (seed, row) pairs (BatchLocate's refill of finished walks).
-__global__ void __launch_bounds__(256) k_locate_coop(IndexView ix, const mbw_seed_t *__restrict__ seeds,
-                                                     const uint32_t *__restrict__ sid, uint64_t n_pos,
-                                                     uint64_t *__restrict__ pos, uint32_t rmask, int rshift, int grab,
-                                                     unsigned long long *__restrict__ ctl) {
-  const int q = threadIdx.x & (MBW_GROUP - 1);
-  uint64_t wnext = 0, wlast = 0, w = 0, x = 0, steps = 0;
-  bool active = false;
-  uint64_t lines = 0, lf = 0;
-  for (;;) {
-    if (!active) {
-      if (wnext >= wlast) {
-        unsigned long long b0 = 0;
-        if (q == 0) b0 = atomicAdd(&ctl[C_WORK2], (unsigned long long)grab);
-        b0 = __shfl(b0, 0, MBW_GROUP);
-        if (b0 >= n_pos) break;
-        wnext = b0;
-        wlast = b0 + (uint64_t)grab < n_pos ? b0 + (uint64_t)grab : n_pos;
-      }
-      w = wnext++;
-      uint32_t t = sid[w];
-      x = seeds[t].k + (w - seeds[t].pos_off);
-      steps = 0;
-      active = true;
-    }
-    if (sampled(x, ix.r, rmask)) {
-      uint64_t p = steps + ix.ssa[sample_index(x, ix.r, rshift)];
-      if (p >= ix.n) p -= ix.n;
-      if (q == 0) pos[w] = p;
-      ++lines;
-      active = false;
-      continue;
-    }
-    if (x == ix.primary || steps > ix.n) {   // LF of the $ row is row 0; the cap only guards a corrupt index
-      if (steps > ix.n && q == 0) atomicOr(&ctl[C_ERR], 2ull);
-      x = 0; ++steps; continue;
-    }
-    const uint64_t L = line_of(x);
-    const int o = (int)(x - L * MBW_BPL);
-    uint4 d = ix.lines[L * MBW_LINE_U4 + q];
-    const uint64_t w0 = ((uint64_t)d.y << 32) | d.x, w1 = ((uint64_t)d.w << 32) | d.z;
-    // one reduction carries the in-line counts of A, C, G (16 bits each) and B[x] + 1 (top 16 bits,
-    // from the slice holding row o); a second one the line's prefix count of B[x]
-    uint64_t pk = 0;
-    if (q >= 2) {
-      pk = slice_counts(d, q, o) & 0xFFFFFFFFFFFFull;
-      if (q == 2 + (o >> 6)) {
-        uint64_t wsel = (o & 63) < 32 ? w0 : w1;
-        pk |= (((wsel >> (2 * (o & 31))) & 3) + 1) << 48;
-      }
-    }
-    pk = grp_sum64(pk);
-    const int b = (int)(pk >> 48) - 1;
-    uint64_t hv = 0;
-    if (q == 0) hv = b == 0 ? w0 : (b == 1 ? w1 : 0);
-    else if (q == 1) hv = b == 2 ? w0 : (b == 3 ? w1 : 0);
-    hv = grp_sum64(hv);
-    const uint64_t nA = pk & 0xffff, nC = (pk >> 16) & 0xffff, nG = (pk >> 32) & 0xffff;
-    const uint64_t inl = b == 0 ? nA : (b == 1 ? nC : (b == 2 ? nG : (uint64_t)o - nA - nC - nG));
-    const uint64_t occ = hv + inl - ((b == 0 && x > ix.primary) ? 1 : 0);
-    x = sel4(ix.Cb[0], ix.Cb[1], ix.Cb[2], ix.Cb[3], b) + occ;
-    ++steps; ++lines; ++lf;
-  }
-  if (q == 0 && lines) {
-    atomicAdd(&ctl[C_LINES_LOC], (unsigned long long)lines);
-    atomicAdd(&ctl[C_LFSTEPS], (unsigned long long)lf);
-  }
-}
-
-// wave-cooperative locate: every lane walks one SA row; idle lanes refill from the queue of all
-// (seed, row) pairs (one atomic per wave); lines are fetched with the wave-cooperative loads.
-__global__ void __launch_bounds__(256) k_locate_wave(IndexView ix, const mbw_seed_t *__restrict__ seeds,
-                                                     const uint32_t *__restrict__ sid, uint64_t n_pos,
+// wave: every lane walks one SA row; one memory phase per iteration holds the line fetches of the
+// walking lanes, the SA-sample reads of lanes whose row is sampled and the start row of each
+// lane's next walk (taken one walk ahead, so a finished lane continues at once).
+__global__ void __launch_bounds__(256) k_locate_wave(IndexView ix, const uint64_t *__restrict__ X, uint64_t n_pos,
                                                      uint64_t *__restrict__ pos, uint32_t rmask, int rshift,
                                                      unsigned long long *__restrict__ ctl) {
   __shared__ uint4 lbuf[4 * WAVE_U4];
+  __shared__ uint64_t sbt[MBW_MAX_SB * 8];
+  for (int t = threadIdx.x; t < 8 * ix.n_sb; t += blockDim.x) sbt[t] = ix.sbtab[t];
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   uint4 *buf = lbuf + (threadIdx.x >> 6) * WAVE_U4;
-  uint64_t w = 0, x = 0, steps = 0, lines = 0, lf = 0;
-  uint64_t cb = 0, ce = 0;
-  bool active = false, drained = false;
+  enum { W_NONE = 0, W_WALK = 1 };
+  enum { P_NONE = 0, P_PENDING = 1, P_READY = 2 };
+  int cur = W_NONE, pre = P_NONE;
+  bool drained = false;
+  uint64_t w = 0, x = 0, steps = 0, pw = 0, px = 0;
+  uint64_t lines = 0, lf = 0, cb = 0, ce = 0;
   for (;;) {
-    const bool want = !active && !drained;
+    if (cur == W_NONE && pre == P_READY) { cur = W_WALK; w = pw; x = px; steps = 0; pre = P_NONE; }
+    const bool want = pre == P_NONE && !drained;
     if (__ballot(want)) {
-      const uint64_t wi = wave_take(want, cb, ce, &ctl[C_WORK2], n_pos, lane);
-      if (want) {
-        w = wi;
-        if (w == ~0ull) drained = true;
-        else {
-          const uint32_t t = sid[w];
-          x = seeds[t].k + (w - seeds[t].pos_off);
-          steps = 0;
-          active = true;
-        }
-      }
+      const uint64_t t = wave_take(want, cb, ce, &ctl[C_WORK2], n_pos, lane);
+      if (want) { if (t == ~0ull) drained = true; else { pw = t; pre = P_PENDING; } }
     }
-    if (__ballot(active) == 0) {
-      if (__ballot(!drained) == 0) break;
-      continue;
-    }
-    bool need = false;
-    if (active) {
-      if (sampled(x, ix.r, rmask)) {
-        uint64_t p = steps + ix.ssa[sample_index(x, ix.r, rshift)];
-        if (p >= ix.n) p -= ix.n;
-        pos[w] = p;
-        ++lines;
-        active = false;
-      } else if (x == ix.primary || steps > ix.n) {   // LF of the $ row is row 0 (the cap guards a corrupt index)
+    if (__ballot(cur != W_NONE || pre != P_NONE) == 0) break;
+    bool need = false, fin = false;
+    if (cur == W_WALK) {
+      if (sampled(x, ix.r, rmask)) fin = true;
+      else if (x == ix.primary || steps > ix.n) {       // LF of the $ row is row 0 (the cap guards a corrupt index)
         if (steps > ix.n) atomicOr(&ctl[C_ERR], 2ull);
-        x = 0;
-        ++steps;
-      } else {
-        need = true;
-      }
+        x = 0; ++steps;
+      } else need = true;
     }
-    const uint32_t L = need ? (uint32_t)line_of(x) : 0u;
-    if (__ballot(need)) {
-      wave_fetch(ix.lines, L, need, buf, lane);
-      if (need) {
-        const int o = (int)(x - (uint64_t)L * MBW_BPL);
-        const uint4 bd = buf[slot_of(lane, 2 + (o >> 6))];
-        const uint64_t wsel = (o & 63) < 32 ? (((uint64_t)bd.y << 32) | bd.x) : (((uint64_t)bd.w << 32) | bd.z);
-        const int b = (int)((wsel >> (2 * (o & 31))) & 3);
-        uint64_t E, G, t1, t2;
-        lane_eg(buf, lane, b, o, -1, E, G, t1, t2);
-        if (b == 0 && x > ix.primary) E -= 1;
-        x = sel4(ix.Cb[0], ix.Cb[1], ix.Cb[2], ix.Cb[3], b) + E;
-        ++steps; ++lines; ++lf;
-      }
+    const uint32_t L = need ? line_of(x) : 0u;
+    // ---- memory phase
+    if (__ballot(need)) fetch_lines_lds(ix.lines, L, need, buf, lane);
+    uint64_t sv = 0;
+    if (fin) sv = ix.ssa[sample_index(x, ix.r, rshift)];
+    const bool ld = pre == P_PENDING;
+    if (ld) px = X[pw];
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    // ---- compute
+    if (ld) pre = P_READY;
+    if (fin) {
+      uint64_t p = steps + sv;
+      if (p >= ix.n) p -= ix.n;
+      pos[w] = p;
+      ++lines;
+      cur = W_NONE;
+    }
+    if (need) {
+      const int o = (int)(x - (uint64_t)L * MBW_BPL);
+      const int sl = block_slice(o);
+      const uint4 sa = lds_slice(buf, lane, sl), sbk = lds_slice(buf, lane, sl + 1);
+      const int b = bwt_from_block(sa, sbk, o);
+      const uint32_t sbi = 8 * (L >> MBW_SB_SHIFT);
+      uint64_t E, G;
+      rank_eg(lds_slice(buf, lane, 0), lds_slice(buf, lane, 1), sa, sbk, o, b, sym_masks(b), sbt[sbi + b], sbt[sbi + 4 + b], E, G);
+      if (b == 0 && x > ix.primary) E -= 1;
+      x = sel4(ix.Cb[0], ix.Cb[1], ix.Cb[2], ix.Cb[3], b) + E;
+      ++steps; ++lines; ++lf;
     }
   }
   atomicAdd(&ctl[C_LINES_LOC], (unsigned long long)lines);
@@ -867,7 +700,7 @@ __global__ void __launch_bounds__(256) k_locate_wave(IndexView ix, const mbw_see
 __global__ void k_bs_mark(const uint64_t *__restrict__ pos, uint64_t np, uint64_t len_r, int role, uint32_t *__restrict__ keep) {
   for (uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; w <= np; w += (uint64_t)gridDim.x * blockDim.x) {
     if (w == np) { keep[w] = 0; continue; }
-    uint64_t seg = pos[w] / len_r;
+    const uint64_t seg = pos[w] / len_r;
     keep[w] = (role == 1) ? (seg == 0 || seg == 2) : (seg == 1 || seg == 3);
   }
 }
@@ -880,16 +713,10 @@ __global__ void k_bs_compact(const uint64_t *__restrict__ pos, const uint32_t *_
 
 __global__ void k_bs_seeds(mbw_seed_t *__restrict__ seeds, uint64_t ns, const uint64_t *__restrict__ kidx) {
   for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < ns; t += (uint64_t)gridDim.x * blockDim.x) {
-    uint64_t a = seeds[t].pos_off, b = a + seeds[t].npos;
+    const uint64_t a = seeds[t].pos_off, b = a + seeds[t].npos;
     seeds[t].pos_off = kidx[a];
     seeds[t].npos = (uint32_t)(kidx[b] - kidx[a]);
   }
-}
-
-inline unsigned grid_for(uint64_t n, unsigned bs = 256, unsigned cap = 65536u * 8) {
-  uint64_t g = (n + bs - 1) / bs;
-  if (g < 1) g = 1;
-  return (unsigned)std::min<uint64_t>(g, cap);
 }
 
 }  // namespace
@@ -900,10 +727,9 @@ struct mbw_ctx {
   const mbw_index *ix;
   int device;
   int n_cu;
-  // grow-only device buffers
-  struct Buf { void *p = nullptr; size_t bytes = 0; };
-  Buf codes, ascii, lens, offs, raw, subq, keys0, keys1, vals0, vals1, flag, idx, seeds, npos, posoff, sid, pos, pos2,
-      keep, kidx, temp, ctl;
+  struct Buf { void *p = nullptr; size_t bytes = 0; };   // grow-only device buffers
+  Buf codes, ascii, lens, offs, raw, subq, keys0, keys1, vals0, vals1, flag, idx, seeds, npos, posoff, xrows, pos, pos2,
+      keep, kidx, temp, ctl, pwords, pnmask, woffs, nwords;
   hipEvent_t ev[8];
   unsigned long long host_ctl[C_COUNT];
   float ms_smem;
@@ -916,7 +742,11 @@ static int grow(mbw_ctx::Buf &b, size_t bytes) {
   if (b.p) { (void)hipFree(b.p); b.p = nullptr; b.bytes = 0; }
   size_t want = bytes + bytes / 4 + 256;
   hipError_t e = hipMalloc(&b.p, want);
-  if (e != hipSuccess) { b.p = nullptr; mbw_set_error(std::string("hipMalloc(") + std::to_string(want) + "): " + hipGetErrorString(e)); return MBW_E_NOMEM; }
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    mbw_set_error(std::string("hipMalloc(") + std::to_string(want) + "): " + hipGetErrorString(e));
+    return MBW_E_NOMEM;
+  }
   b.bytes = want;
   return 0;
 }
@@ -943,8 +773,8 @@ extern "C" void mbw_ctx_free(mbw_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   mbw_ctx::Buf *bs[] = {&c->codes, &c->ascii, &c->lens, &c->offs, &c->raw, &c->subq, &c->keys0, &c->keys1, &c->vals0,
-                        &c->vals1, &c->flag, &c->idx, &c->seeds, &c->npos, &c->posoff, &c->sid, &c->pos, &c->pos2,
-                        &c->keep, &c->kidx, &c->temp, &c->ctl};
+                        &c->vals1, &c->flag, &c->idx, &c->seeds, &c->npos, &c->posoff, &c->xrows, &c->pos, &c->pos2,
+                        &c->keep, &c->kidx, &c->temp, &c->ctl, &c->pwords, &c->pnmask, &c->woffs, &c->nwords};
   for (auto *b : bs) if (b->p) (void)hipFree(b->p);
   for (int t = 0; t < 8; ++t) (void)hipEventDestroy(c->ev[t]);
   delete c;
@@ -973,11 +803,26 @@ static int persistent_grid(const void *kern, int block, size_t lds, int n_cu, in
   return per * n_cu;
 }
 
-static int launch_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const mbw_seed_opts &o, int maxlen, hipStream_t st);
-static int run_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const mbw_seed_opts &o, int maxlen, hipStream_t st) {
+static int launch_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const ReadWords &R, const mbw_seed_opts &o, bool staged,
+                       hipStream_t st) {
+  if (o.kernel == MBW_KERNEL_PLAIN) {
+    k_smem_plain<<<grid_for(P.n_queries, 256), 256, 0, st>>>(v, P);
+  } else if (staged) {
+    const int grid = persistent_grid((const void *)k_smem_wave<true>, 128, 0, c->n_cu, o.blocks_per_cu);
+    k_smem_wave<true><<<grid, 128, 0, st>>>(v, P, R);
+  } else {
+    const int grid = persistent_grid((const void *)k_smem_wave<false>, 128, 0, c->n_cu, o.blocks_per_cu);
+    k_smem_wave<false><<<grid, 128, 0, st>>>(v, P, R);
+  }
+  TRY(hipGetLastError());
+  return 0;
+}
+
+static int run_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const ReadWords &R, const mbw_seed_opts &o, bool staged,
+                    hipStream_t st) {
   if (P.n_queries == 0) return 0;
   TRY(hipEventRecord(c->ev[1], st));
-  int r = launch_smem(c, v, P, o, maxlen, st);
+  int r = launch_smem(c, v, P, R, o, staged, st);
   if (r) return r;
   TRY(hipEventRecord(c->ev[2], st));
   TRY(hipEventSynchronize(c->ev[2]));
@@ -988,52 +833,24 @@ static int run_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const mbw_see
   return 0;
 }
 
-static int launch_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const mbw_seed_opts &o, int maxlen, hipStream_t st) {
-  if (o.kernel == MBW_KERNEL_PLAIN) {
-    k_smem_plain<<<grid_for(P.n_queries, 256), 256, 0, st>>>(v, P);
-    TRY(hipGetLastError());
-    return 0;
-  }
-  if (o.schedule == MBW_SCHED_WAVE) {
-    int grid = persistent_grid((const void *)k_smem_wave, 256, 0, c->n_cu, o.blocks_per_cu);
-    k_smem_wave<<<grid, 256, 0, st>>>(v, P);
-    TRY(hipGetLastError());
-    return 0;
-  }
-  int gpb = o.groups_per_block > 0 ? o.groups_per_block : 32;
-  if (gpb > 32) gpb = 32;
-  int block = gpb * MBW_GROUP;
-  if (maxlen <= 256) {
-    size_t lds = (size_t)gpb * 256;
-    int grid = persistent_grid((const void *)k_smem_coop<256>, block, lds, c->n_cu, o.blocks_per_cu);
-    k_smem_coop<256><<<grid, block, lds, st>>>(v, P);
-  } else {
-    int grid = persistent_grid((const void *)k_smem_coop<0>, block, 0, c->n_cu, o.blocks_per_cu);
-    k_smem_coop<0><<<grid, block, 0, st>>>(v, P);
-  }
-  TRY(hipGetLastError());
-  return 0;
-}
-
 extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads, int min_seed_len,
                         int max_occ, const mbw_seed_opts *opts, void *stream, mbw_result *out) {
   if (!c || !out) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
   memset(out, 0, sizeof(*out));
   if (min_seed_len < 1 || max_occ < 1) { mbw_set_error("min_seed_len and max_occ must be >= 1"); return MBW_E_INVAL; }
   if (n_reads > 0 && (!reads || !lengths)) { mbw_set_error("NULL reads or lengths"); return MBW_E_INVAL; }
-  if (n_reads >= (1ull << 32)) { mbw_set_error("too many reads in one call"); return MBW_E_INVAL; }
+  if (n_reads >= (1ull << 31)) { mbw_set_error("too many reads in one call"); return MBW_E_INVAL; }
   mbw_seed_opts o;
   if (opts) o = *opts;
   else { memset(&o, 0, sizeof(o)); o.min_occ = 1; o.reseed = 1; o.reseed_len = 38; o.reseed_occ = 10; o.use_kmer = 1; }
   if (o.min_occ < 1) { mbw_set_error("min_occ must be >= 1"); return MBW_E_INVAL; }
   if (o.bs_role && !c->ix->bisulfite) { mbw_set_error("bs_role needs a bisulfite index"); return MBW_E_INVAL; }
   if (o.bs_role < 0 || o.bs_role > 2) { mbw_set_error("bs_role must be 0, 1 or 2"); return MBW_E_INVAL; }
-  if (o.grab <= 0) o.grab = 8;
-  if (o.grab_locate <= 0) o.grab_locate = 64;
+  if (o.kernel != MBW_KERNEL_COOP && o.kernel != MBW_KERNEL_PLAIN) { mbw_set_error("unknown kernel"); return MBW_E_INVAL; }
   TRY(hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
   const mbw_index *ix = c->ix;
-  IndexView v = make_view(ix);
+  const IndexView v = make_view(ix);
   unsigned long long *ctl = (unsigned long long *)c->ctl.p;
   TRY(hipMemsetAsync(ctl, 0, C_COUNT * sizeof(unsigned long long), st));
   c->ms_smem = 0;
@@ -1064,7 +881,7 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   TRY(hipMemcpyAsync(&maxlen, ctl + C_MAXLEN, 8, hipMemcpyDeviceToHost, st));
   TRY(hipStreamSynchronize(st));
   if (maxlen > MBW_MAX_READ) { mbw_set_error("read longer than 65535 bases"); return MBW_E_INVAL; }
-  // encode
+  // encode, then pack for the wave kernels
   GROW(c->codes, total + 16);
   const uint8_t *dreads = reads;
   if (!is_device_ptr(reads)) {
@@ -1074,9 +891,32 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   }
   k_encode<<<grid_for(total), 256, 0, st>>>(dreads, total, o.bs_role, (uint8_t *)c->codes.p);
   TRY(hipGetLastError());
-  // SMEM rounds
-  // per-wave output chunks leave up to one partly used chunk per wave of the persistent grid
-  const uint64_t chunk_slack = (uint64_t)c->n_cu * 32 * OUT_CHUNK;
+  const bool coop = o.kernel != MBW_KERNEL_PLAIN;
+  const bool staged = coop && maxlen <= 32 * STAGE_WORDS && !o.no_stage;
+  ReadWords R;
+  R.pw = nullptr; R.pn = nullptr; R.woff = nullptr;
+  if (coop) {
+    GROW(c->nwords, (n_reads + 1) * 8);
+    GROW(c->woffs, (n_reads + 1) * 8);
+    uint64_t *nwd = (uint64_t *)c->nwords.p, *woff = (uint64_t *)c->woffs.p;
+    k_read_words<<<grid_for(n_reads + 1), 256, 0, st>>>(offs, n_reads, nwd);
+    TRY(hipGetLastError());
+    r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, nwd, woff, n_reads + 1, st); });
+    if (r) return r;
+    uint64_t totw = 0;
+    TRY(hipMemcpyAsync(&totw, woff + n_reads, 8, hipMemcpyDeviceToHost, st));
+    TRY(hipStreamSynchronize(st));
+    GROW(c->pwords, (totw + 2) * 8);
+    GROW(c->pnmask, (totw + 2) * 4);
+    k_pack_reads<<<grid_for(n_reads), 256, 0, st>>>((const uint8_t *)c->codes.p, offs, woff, n_reads, (uint64_t *)c->pwords.p,
+                                                    (uint32_t *)c->pnmask.p);
+    TRY(hipGetLastError());
+    R.pw = (const uint64_t *)c->pwords.p;
+    R.pn = (const uint32_t *)c->pnmask.p;
+    R.woff = woff;
+  }
+  // SMEM rounds.  Per-wave output chunks leave up to one partly used chunk per wave of the grid.
+  const uint64_t chunk_slack = (uint64_t)c->n_cu * 64 * OUT_CHUNK;
   uint64_t seed_cap = std::max<uint64_t>(1 << 16, n_reads * 4) + chunk_slack;
   if (c->raw.bytes / sizeof(SeedRec) > seed_cap) seed_cap = c->raw.bytes / sizeof(SeedRec);
   uint64_t subq_cap = std::max<uint64_t>(1 << 14, n_reads / 2) + chunk_slack;
@@ -1085,7 +925,7 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   memset(&P, 0, sizeof(P));
   P.codes = (const uint8_t *)c->codes.p; P.offs = offs; P.queries = nullptr; P.n_queries = n_reads;
   P.l = min_seed_len; P.c = o.min_occ; P.reseed = o.reseed; P.reseed_len = o.reseed_len; P.reseed_occ = o.reseed_occ;
-  P.round = 1; P.use_kmer = o.use_kmer; P.grab = o.grab; P.ctl = ctl;
+  P.round = 1; P.use_kmer = o.use_kmer; P.ctl = ctl;
   unsigned long long n1 = 0, nq = 0;
   for (int attempt = 0;; ++attempt) {
     GROW(c->raw, seed_cap * sizeof(SeedRec));
@@ -1094,7 +934,7 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     subq_cap = c->subq.bytes / sizeof(Query);
     P.seeds = (SeedRec *)c->raw.p; P.seed_cap = seed_cap; P.subq = (Query *)c->subq.p; P.subq_cap = subq_cap;
     TRY(hipMemsetAsync(ctl, 0, 8 * sizeof(unsigned long long), st));
-    r = run_smem(c, v, P, o, (int)maxlen, st);
+    r = run_smem(c, v, P, R, o, staged, st);
     if (r) return r;
     TRY(hipMemcpyAsync(&n1, ctl + C_NSEEDS, 8, hipMemcpyDeviceToHost, st));
     TRY(hipMemcpyAsync(&nq, ctl + C_NSUBQ, 8, hipMemcpyDeviceToHost, st));
@@ -1107,7 +947,7 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   unsigned long long stats1[3];
   TRY(hipMemcpyAsync(stats1, ctl + C_LINES, 3 * 8, hipMemcpyDeviceToHost, st));
   unsigned long long ntot = n1;
-  if (o.kernel != MBW_KERNEL_PLAIN && o.reseed && nq > 0) {
+  if (coop && o.reseed && nq > 0) {
     SeedParams P2 = P;
     P2.queries = (const Query *)c->subq.p; P2.n_queries = nq; P2.round = 2;
     for (int attempt = 0;; ++attempt) {
@@ -1116,13 +956,13 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
       TRY(hipMemcpyAsync(ctl + C_WORK, &zero, 8, hipMemcpyHostToDevice, st));
       TRY(hipMemcpyAsync(ctl + C_LINES, stats1, 3 * 8, hipMemcpyHostToDevice, st));
       P2.seeds = (SeedRec *)c->raw.p; P2.seed_cap = c->raw.bytes / sizeof(SeedRec);
-      r = run_smem(c, v, P2, o, (int)maxlen, st);
+      r = run_smem(c, v, P2, R, o, staged, st);
       if (r) return r;
       TRY(hipMemcpyAsync(&ntot, ctl + C_NSEEDS, 8, hipMemcpyDeviceToHost, st));
       TRY(hipStreamSynchronize(st));
       if (ntot <= P2.seed_cap) break;
       if (attempt > 3) { mbw_set_error("seed buffer did not converge"); return MBW_E_NOMEM; }
-      // keep round-1 records: grow by copying
+      // keep the round-1 records: grow by copying
       mbw_ctx::Buf nb;
       int rr = grow(nb, (ntot + ntot / 2 + 1024) * sizeof(SeedRec));
       if (rr) return rr;
@@ -1133,25 +973,22 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     }
   }
   // sort by (read, qbeg, qend), dedup, counts
-  uint64_t ns = ntot;
+  const uint64_t ns = ntot;
   GROW(c->keys0, ns * 8); GROW(c->keys1, ns * 8); GROW(c->vals0, ns * 4); GROW(c->vals1, ns * 4);
   GROW(c->flag, ns * 4 + 8); GROW(c->idx, ns * 4 + 8);
-  if (ns) {
-    k_seed_keys<<<grid_for(ns), 256, 0, st>>>((const SeedRec *)c->raw.p, ns, n_reads, (uint64_t *)c->keys0.p, (uint32_t *)c->vals0.p);
-    TRY(hipGetLastError());
-  }
-  int hibit = 33;   // key < (n_reads + 1) << 32
-  while (hibit < 64 && (1ull << (hibit - 32)) <= n_reads) ++hibit;
   hipcub::DoubleBuffer<uint64_t> dk((uint64_t *)c->keys0.p, (uint64_t *)c->keys1.p);
-  // (ns may be 0: every step below is skipped then)
   hipcub::DoubleBuffer<uint32_t> dv((uint32_t *)c->vals0.p, (uint32_t *)c->vals1.p);
-  if (ns > 1) {
-    r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceRadixSort::SortPairs(tp, tb, dk, dv, ns, 0, hibit, st); });
-    if (r) return r;
-  }
   uint32_t *flag = (uint32_t *)c->flag.p, *idx = (uint32_t *)c->idx.p;
   uint64_t nu = 0;
   if (ns) {
+    k_seed_keys<<<grid_for(ns), 256, 0, st>>>((const SeedRec *)c->raw.p, ns, n_reads, (uint64_t *)c->keys0.p, (uint32_t *)c->vals0.p);
+    TRY(hipGetLastError());
+    int hibit = 33;   // every key < (n_reads + 1) << 32
+    while (hibit < 64 && (1ull << (hibit - 32)) <= n_reads) ++hibit;
+    if (ns > 1) {
+      r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceRadixSort::SortPairs(tp, tb, dk, dv, ns, 0, hibit, st); });
+      if (r) return r;
+    }
     k_dedup_mark<<<grid_for(ns), 256, 0, st>>>(dk.Current(), ns, n_reads, flag);
     TRY(hipGetLastError());
     r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, flag, idx, ns, st); });
@@ -1178,49 +1015,28 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     if (r) return r;
     TRY(hipMemcpyAsync(&n_pos, posoff + nu, 8, hipMemcpyDeviceToHost, st));
     TRY(hipStreamSynchronize(st));
-  }
-  const bool coop = o.kernel != MBW_KERNEL_PLAIN;
-  GROW(c->pos, (n_pos + 1) * 8);
-  uint32_t *sid = nullptr;
-  if (coop && n_pos) {
-    GROW(c->sid, (n_pos + 1) * 4);
-    GROW(c->keep, (n_pos + 1) * 4);
-    sid = (uint32_t *)c->sid.p;
-    TRY(hipMemsetAsync(c->keep.p, 0, (n_pos + 1) * 4, st));
-  }
-  if (nu) {
-    k_seed_posoff<<<grid_for(nu), 256, 0, st>>>(seeds, posoff, nu, coop && n_pos ? (uint32_t *)c->keep.p : nullptr);
+    k_seed_posoff<<<grid_for(nu), 256, 0, st>>>(seeds, posoff, nu);
     TRY(hipGetLastError());
   }
+  GROW(c->pos, (n_pos + 1) * 8);
   // locate
   uint32_t rmask = (ix->sa_sample & (ix->sa_sample - 1)) == 0 ? (uint32_t)(ix->sa_sample - 1) : 0u;
-  if (ix->sa_sample == 1) rmask = 0;   // every row sampled: x % 1 == 0 path
   int rshift = -1;
   if ((ix->sa_sample & (ix->sa_sample - 1)) == 0) { rshift = 0; while ((1 << rshift) < ix->sa_sample) ++rshift; }
-  TRY(hipEventRecord(c->ev[3], st));   // re-recorded right before the locate launch below
+  TRY(hipEventRecord(c->ev[3], st));
   if (n_pos) {
     if (!coop) {
       TRY(hipEventRecord(c->ev[3], st));
       k_locate_plain<<<grid_for(nu), 256, 0, st>>>(v, seeds, nu, (uint64_t *)c->pos.p, rmask, rshift, ctl);
       TRY(hipGetLastError());
     } else {
-      uint32_t *seedmark = (uint32_t *)c->keep.p;
-      r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::InclusiveScan(tp, tb, seedmark, sid, hipcub::Max(), n_pos, st); });
-      if (r) return r;
-      if (o.schedule == MBW_SCHED_WAVE) {
-        int grid = persistent_grid((const void *)k_locate_wave, 256, 0, c->n_cu, o.blocks_per_cu);
-        TRY(hipEventRecord(c->ev[3], st));
-        k_locate_wave<<<grid, 256, 0, st>>>(v, seeds, sid, n_pos, (uint64_t *)c->pos.p, rmask, rshift, ctl);
-        TRY(hipGetLastError());
-      } else {
-      int gpb = o.groups_per_block > 0 ? std::min(o.groups_per_block, 32) : 32;
-      int block = gpb * MBW_GROUP;
-      int grid = persistent_grid((const void *)k_locate_coop, block, 0, c->n_cu, o.blocks_per_cu);
-      TRY(hipEventRecord(c->ev[3], st));
-      k_locate_coop<<<grid, block, 0, st>>>(v, seeds, sid, n_pos, (uint64_t *)c->pos.p, rmask, rshift,
-                                             o.grab_locate, ctl);
+      GROW(c->xrows, (n_pos + 1) * 8);
+      k_expand_rows<<<grid_for(nu), 256, 0, st>>>(seeds, nu, (uint64_t *)c->xrows.p);
       TRY(hipGetLastError());
-      }
+      const int grid = persistent_grid((const void *)k_locate_wave, 256, 0, c->n_cu, o.blocks_per_cu);
+      TRY(hipEventRecord(c->ev[3], st));
+      k_locate_wave<<<grid, 256, 0, st>>>(v, (const uint64_t *)c->xrows.p, n_pos, (uint64_t *)c->pos.p, rmask, rshift, ctl);
+      TRY(hipGetLastError());
     }
   }
   TRY(hipEventRecord(c->ev[4], st));
@@ -1247,13 +1063,12 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     final_pos = (const uint64_t *)c->pos2.p;
   }
   TRY(hipMemcpyAsync(c->host_ctl, ctl, C_COUNT * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-  TRY(hipStreamSynchronize(st));
+  TRY(hipEventRecord(c->ev[5], st));
+  TRY(hipEventSynchronize(c->ev[5]));
   if (c->host_ctl[C_ERR]) {
     mbw_set_error(std::string("kernel guard tripped (") + std::to_string(c->host_ctl[C_ERR]) + "): corrupt index or internal error");
     return MBW_E_HIP;
   }
-  TRY(hipEventRecord(c->ev[5], st));
-  TRY(hipEventSynchronize(c->ev[5]));
   float t_loc = 0, t_tot = 0;
   (void)hipEventElapsedTime(&t_loc, c->ev[3], c->ev[4]);
   (void)hipEventElapsedTime(&t_tot, c->ev[0], c->ev[5]);
@@ -1265,7 +1080,9 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   out->lines_locate = c->host_ctl[C_LINES_LOC];
   out->steps = c->host_ctl[C_STEPS];
   out->lf_steps = c->host_ctl[C_LFSTEPS];
-  out->ms_smem = c->ms_smem; out->ms_locate = t_loc; out->ms_total = t_tot;
+  out->ms_smem = c->ms_smem;
+  out->ms_locate = t_loc;
+  out->ms_total = t_tot;
   out->n_smem_launches = c->n_smem_launches;
   return MBW_OK;
 }

@@ -40,7 +40,8 @@ def compare_with_oracle(seeds, pos, ref_res, check_flags=True):
     assert np.array_equal(flat, ref_res.pos), "positions differ"
 
 
-HEADER = struct.Struct("<QII QQQQQ 5Q iiii QQQ Q")
+HEADER = struct.Struct("<QII QQQQQ 5Q iiii 64Q QQQ Q")
+MAX_SB = 8
 
 
 def read_index_file(path):
@@ -48,8 +49,10 @@ def read_index_file(path):
     with open(path, "rb") as f:
         raw = f.read()
     h = HEADER.unpack_from(raw, 0)
-    (magic, version, bpl, n, len_r, primary, n_lines, n_ssa, c0, c1, c2, c3, c4, r, K, bis, _pad,
-     s1, s2, s3, sh) = h
+    magic, version, bpl, n, len_r, primary, n_lines, n_ssa = h[:8]
+    C5 = list(h[8:13])
+    r, K, bis, n_sb = h[13:17]
+    sb = np.array(h[17:17 + 8 * MAX_SB], dtype=np.uint64).reshape(MAX_SB, 8)[:n_sb]
     off = HEADER.size
     lines = np.frombuffer(raw, dtype=np.uint64, count=n_lines * 16, offset=off).reshape(n_lines, 16)
     off += n_lines * 128
@@ -58,7 +61,7 @@ def read_index_file(path):
     kmer = None
     if K:
         kmer = np.frombuffer(raw, dtype=np.uint64, count=2 * 4 ** K, offset=off).reshape(-1, 2)
-    return dict(n=n, len_r=len_r, primary=primary, n_lines=n_lines, C=[c0, c1, c2, c3, c4], r=r, K=K,
+    return dict(n=n, len_r=len_r, primary=primary, n_lines=n_lines, C=C5, r=r, K=K, sb=sb,
                 lines=lines, ssa=ssa, kmer=kmer, bpl=bpl)
 
 
