@@ -98,6 +98,7 @@ def main():
     ap.add_argument("--cpu-pairs", type=int, default=250_000)
     ap.add_argument("--cpu-window", type=int, default=16_000_000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--probe", action="store_true", help="only run the copy and random-gather probes")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -112,6 +113,13 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.probe:
+        ms = mbw.probe_copy(1 << 30)
+        lps, gms = mbw.probe_gather(16 << 30)
+        print(json.dumps(dict(copy_bytes=1 << 30, copy_ms=round(ms, 3), copy_gbs=round(2 * (1 << 30) / ms / 1e6, 1),
+                              gather_lines_per_s=lps, gather_gbs_128=round(lps * 128 / 1e9, 1), gather_ms=round(gms, 3))))
+        return
+    gather_lps, _ = mbw.probe_gather(16 << 30)
     t0 = time.time()
     ref = synth.reference(1, args.ref_len, synth.REF_SEED + 3)
     log(f"reference {len(ref)} bases generated in {time.time() - t0:.1f} s")
@@ -179,7 +187,10 @@ def main():
                     lines_per_read=round(lines_smem / n_reads, 1),
                     locate=dict(achieved=round(lines_loc * LINE_BYTES / (ms_loc * 1e-3) / 1e9, 1),
                                 lines_per_read=round(lines_loc / n_reads, 1)),
-                    whole_path=round((lines_smem + lines_loc) * LINE_BYTES / (elapsed / args.steps) / 1e9, 1))
+                    whole_path=round((lines_smem + lines_loc) * LINE_BYTES / (elapsed / args.steps) / 1e9, 1),
+                    random_line_ceiling=dict(lines_per_s=round(gather_lps), gbs=round(gather_lps * LINE_BYTES / 1e9, 1),
+                                             probe="8 lanes x 16 B per random 128-B line, 16 GiB buffer"),
+                    frac_of_measured_ceiling=round(lines_smem / (ms_smem * 1e-3) / gather_lps, 3))
 
     cpu = None
     if not args.no_cpu:

@@ -171,6 +171,15 @@ int mbw_result_download(mbw_ctx *ctx, const mbw_result *res, mbw_seed_t *seeds, 
  * the four copies of length |R| map to their source coordinates likewise.) */
 int mbw_pos_to_ref(const mbw_index *idx, uint64_t pos, uint32_t len, int *strand, uint64_t *ref_pos);
 
+/* ---- diagnostics (not part of the seeding path) ----------------------------------------------
+ * mbw_probe_copy: streams `bytes` bytes (>= 4096) from one buffer to another once; *ms = kernel time.
+ *   Used to calibrate profiler byte counters against a known transfer.
+ * mbw_probe_gather: eight lanes fetch one random 128-byte line of a `bytes`-byte buffer (>= 1 MiB),
+ *   `iters` dependent fetches per lane group; *lines_per_s = random lines served per second.
+ * Both allocate and free their own device memory.  Errors: MBW_E_INVAL, MBW_E_NOMEM, MBW_E_HIP. */
+int mbw_probe_copy(int device, uint64_t bytes, float *ms);
+int mbw_probe_gather(int device, uint64_t bytes, int iters, double *lines_per_s, float *ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -34,7 +34,7 @@ SEED_ROUND2 = 2
 # the symbols include/mbw.h declares
 EXPORTS = ["mbw_strerror", "mbw_last_error", "mbw_index_build", "mbw_index_save", "mbw_index_load",
            "mbw_index_free", "mbw_index_info", "mbw_index_device_arrays", "mbw_ctx_create", "mbw_ctx_free",
-           "mbw_seed", "mbw_result_download", "mbw_pos_to_ref"]
+           "mbw_seed", "mbw_result_download", "mbw_pos_to_ref", "mbw_probe_copy", "mbw_probe_gather"]
 
 
 class MbwError(RuntimeError):
@@ -102,6 +102,8 @@ def load_library():
     L.mbw_seed.argtypes = [vp, vp, vp, u64, i32, i32, C.POINTER(SeedOpts), vp, C.POINTER(Result)]
     L.mbw_result_download.argtypes = [vp, C.POINTER(Result), vp, vp]
     L.mbw_pos_to_ref.argtypes = [vp, u64, C.c_uint32, C.POINTER(C.c_int), C.POINTER(C.c_uint64)]
+    L.mbw_probe_copy.argtypes = [i32, u64, C.POINTER(C.c_float)]
+    L.mbw_probe_gather.argtypes = [i32, u64, i32, C.POINTER(C.c_double), C.POINTER(C.c_float)]
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
@@ -267,6 +269,22 @@ class Context:
             self.free()
         except Exception:
             pass
+
+
+def probe_copy(nbytes: int = 1 << 30, device: int = 0) -> float:
+    """Kernel time (ms) of one streaming copy of `nbytes` bytes (profiler counter calibration)."""
+    L = load_library()
+    ms = C.c_float()
+    _check(L.mbw_probe_copy(int(device), int(nbytes), C.byref(ms)))
+    return ms.value
+
+
+def probe_gather(nbytes: int = 16 << 30, iters: int = 64, device: int = 0):
+    """Random 128-byte lines served per second over an `nbytes` buffer (eight lanes per line)."""
+    L = load_library()
+    lps, ms = C.c_double(), C.c_float()
+    _check(L.mbw_probe_gather(int(device), int(nbytes), int(iters), C.byref(lps), C.byref(ms)))
+    return lps.value, ms.value
 
 
 def canonical(seeds: np.ndarray, pos: np.ndarray):

@@ -104,24 +104,40 @@ __global__ void k_read_words(const uint64_t *__restrict__ offs, uint64_t n, uint
     nwords[r] = r < n ? (offs[r + 1] - offs[r] + 31) / 32 : 0;
 }
 
-__global__ void k_pack_reads(const uint8_t *__restrict__ codes, const uint64_t *__restrict__ offs, const uint64_t *__restrict__ woff,
-                             uint64_t n, uint64_t *__restrict__ pw, uint32_t *__restrict__ pn) {
-  for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < n; r += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t b = offs[r], len = offs[r + 1] - b, w0 = woff[r];
-    for (uint64_t w = 0; w * 32 < len; ++w) {
-      uint64_t v = 0;
-      uint32_t nb = 0;
-      for (int t = 0; t < 32; ++t) {
-        const uint64_t p = w * 32 + t;
-        if (p < len) {
-          const uint8_t cd = codes[b + p];
-          if (cd > 3) nb |= 1u << t;
-          else v |= (uint64_t)cd << (2 * t);
-        }
+// owner read of every packed word (word w of read r: wread[woff[r] + w] = r)
+__global__ void k_word_owner(const uint64_t *__restrict__ woff, uint64_t n, uint32_t *__restrict__ wread) {
+  for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < n; r += (uint64_t)gridDim.x * blockDim.x)
+    for (uint64_t w = woff[r]; w < woff[r + 1]; ++w) wread[w] = (uint32_t)r;
+}
+
+// one thread per packed word: 32 ASCII bases -> 2-bit codes + N bits (bisulfite conversion as in
+// k_encode); consecutive threads read consecutive bytes
+__global__ void k_pack_words(const uint8_t *__restrict__ ascii, const uint64_t *__restrict__ offs, const uint64_t *__restrict__ woff,
+                             const uint32_t *__restrict__ wread, uint64_t totw, int role, uint64_t *__restrict__ pw,
+                             uint32_t *__restrict__ pn) {
+  for (uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; w < totw; w += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t r = wread[w];
+    const uint64_t first = offs[r] + 32 * (w - woff[r]), end = offs[r + 1];
+    uint64_t v = 0;
+    uint32_t nb = 0;
+    for (int t = 0; t < 32; ++t) {
+      const uint64_t p = first + t;
+      if (p >= end) break;
+      int c;
+      switch (ascii[p]) {
+        case 'A': case 'a': c = 0; break;
+        case 'C': case 'c': c = 1; break;
+        case 'G': case 'g': c = 2; break;
+        case 'T': case 't': c = 3; break;
+        default: c = 4;
       }
-      pw[w0 + w] = v;
-      pn[w0 + w] = nb;
+      if (role == 1 && c == 1) c = 3;   // read 1: C -> T
+      if (role == 2 && c == 2) c = 0;   // read 2: G -> A
+      if (c > 3) nb |= 1u << t;
+      else v |= (uint64_t)c << (2 * t);
     }
+    pw[w] = v;
+    pn[w] = nb;
   }
 }
 
@@ -219,36 +235,38 @@ __device__ __forceinline__ void wave_close(const SeedParams &P, int lane, const 
 }
 
 // ---------------------------------------------------------------------------------------------
-// wave-cooperative line fetch, straight into LDS (global_load_lds, 16 bytes per lane).  Load t of
-// lane L writes buf[64 t + L] (the hardware places lane L's 16 bytes at base + 16 L) and fetches
-// slice ((L & 7) + (L >> 3)) & 7 of the line wanted by lane r = 8 t + (L >> 3); so slice j of
-// lane r's line sits at buf[8 r + ((j - r) & 7)], rotated by r to spread the LDS banks.
-#define WAVE_U4 (64 * MBW_LINE_U4)
+// Wave-cooperative fetch straight into LDS (global_load_lds, 16 bytes per lane).  A rank needs four
+// of a line's eight slices: the two header slices and the two slices of the 96-row block holding
+// the offset.  Load t of lane L fetches, for lane r = 16 t + (L >> 2), slice number (L - r) & 3 of
+// the list (0, 1, sl, sl + 1) (sl = block slice of lane r's offset) and lands at buf[64 t + L]
+// (the hardware places lane L's 16 bytes at base + 16 L), i.e. at buf[4 r + ((q + r) & 3)] for the
+// q-th slice of the list: 64 bytes per lane, rotated by r to spread the LDS banks.  Four load
+// instructions move the needed half-lines of all 64 lanes; the HBM transfer is still the whole
+// 128-byte line.
+#define WAVE_U4 (64 * 4)
 typedef __attribute__((address_space(3))) void lds_void;
 
-__device__ __forceinline__ void fetch_lines_lds(const uint4 *__restrict__ lines, uint32_t myL, bool myneed, uint4 *buf, int lane) {
-  const int g = lane >> 3, j = ((lane & 7) + g) & 7;
+__device__ __forceinline__ void fetch_blocks_lds(const uint4 *__restrict__ lines, uint32_t myL, int mysl, bool myneed,
+                                                 uint4 *buf, int lane) {
 #pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    const int src = 8 * t + g;
-    const uint32_t Ls = (uint32_t)__shfl((int)myL, src);
-    if (__shfl((int)myneed, src))
+  for (int t = 0; t < 4; ++t) {
+    const int r = 16 * t + (lane >> 2);
+    const uint32_t Ls = (uint32_t)__shfl((int)myL, r);
+    const int sl = __shfl(mysl, r);
+    const int q = (lane - r) & 3;
+    const int j = q < 2 ? q : sl + (q - 2);
+    if (__shfl((int)myneed, r))
       __builtin_amdgcn_global_load_lds((const void *)(lines + (uint64_t)Ls * MBW_LINE_U4 + j), (lds_void *)(buf + 64 * t), 16, 0, 0);
   }
 }
 
-__device__ __forceinline__ uint4 lds_slice(const uint4 *buf, int lane, int j) { return buf[8 * lane + ((j - lane) & 7)]; }
+// q-th slice (0: header counts, 1: sub-checkpoints, 2/3: the block) of lane r's fetched line
+__device__ __forceinline__ uint4 lds_q(const uint4 *buf, int r, int q) { return buf[4 * r + ((q + r) & 3)]; }
 
-// (E, G) at offsets o1 and, if o2 >= 0, o2 of the line staged for this lane
-__device__ __forceinline__ void rank_lds(const uint4 *buf, int lane, int c, const SymMasks &sm, uint64_t sbe, uint64_t sbg,
-                                         int o1, int o2, uint64_t &E1, uint64_t &G1, uint64_t &E2, uint64_t &G2) {
-  const uint4 h0 = lds_slice(buf, lane, 0), h1 = lds_slice(buf, lane, 1);
-  const int s1 = block_slice(o1);
-  rank_eg(h0, h1, lds_slice(buf, lane, s1), lds_slice(buf, lane, s1 + 1), o1, c, sm, sbe, sbg, E1, G1);
-  if (o2 >= 0) {
-    const int s2 = block_slice(o2);
-    rank_eg(h0, h1, lds_slice(buf, lane, s2), lds_slice(buf, lane, s2 + 1), o2, c, sm, sbe, sbg, E2, G2);
-  }
+// (E, G) at offset o of the half-line fetched for this lane
+__device__ __forceinline__ void rank_lds(const uint4 *buf, int lane, int o, int c, const SymMasks &sm, uint64_t sbe, uint64_t sbg,
+                                         uint64_t &E, uint64_t &G) {
+  rank_eg(lds_q(buf, lane, 0), lds_q(buf, lane, 1), lds_q(buf, lane, 2), lds_q(buf, lane, 3), o, c, sm, sbe, sbg, E, G);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -263,7 +281,7 @@ enum { ACT_DONE = 0, ACT_KMER = 1, ACT_BWD = 2, ACT_FWD = 3 };
 enum { ST_IDLE = 0, ST_REC = 1, ST_STAGE = 2, ST_ACTIVE = 3, ST_DRAINED = 4 };
 
 template <bool STAGED>
-__global__ void __launch_bounds__(128) k_smem_wave(IndexView ix, SeedParams P, ReadWords R) {
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) k_smem_wave(IndexView ix, SeedParams P, ReadWords R) {
   __shared__ uint4 lbuf[2][2 * WAVE_U4];                        // per wave: first and second lines
   __shared__ uint64_t sw[2][STAGED ? STAGE_WORDS * 64 : 1];     // staged bases, word w of lane L at [64 w + L]
   __shared__ uint32_t sn[2][STAGED ? STAGE_WORDS * 64 : 1];     // staged N bits
@@ -345,10 +363,13 @@ __global__ void __launch_bounds__(128) k_smem_wave(IndexView ix, SeedParams P, R
     const int cc = bwd ? a : 3 - a;
     const uint64_t x2 = x1 + s;
     const uint32_t L1 = ext ? line_of(x1) : 0u, L2 = ext ? line_of(x2) : 0u;
-    const bool two = ext && L1 != L2;
+    const int o1 = (int)(x1 - (uint64_t)L1 * MBW_BPL), o2 = (int)(x2 - (uint64_t)L2 * MBW_BPL);
+    const int sl1 = block_slice(o1), sl2 = block_slice(o2);
+    const bool two = ext && L1 != L2;                   // a second index line
+    const bool fetch2 = ext && (two || sl1 != sl2);     // a second half-line (same line, other block)
     // ---- the memory phase: everything the wave needs, issued together, waited for once
-    if (__ballot(ext)) fetch_lines_lds(ix.lines, L1, ext, bufA, lane);
-    if (__ballot(two)) fetch_lines_lds(ix.lines, L2, two, bufB, lane);
+    if (__ballot(ext)) fetch_blocks_lds(ix.lines, L1, sl1, ext, bufA, lane);
+    if (__ballot(fetch2)) fetch_blocks_lds(ix.lines, L2, sl2, fetch2, bufB, lane);
     uint4 kent = make_uint4(0, 0, 0, 0);
     if (act == ACT_KMER) kent = ix.kmer[code];
     const int st_mem = st;
@@ -379,10 +400,9 @@ __global__ void __launch_bounds__(128) k_smem_wave(IndexView ix, SeedParams P, R
     if (ext) {
       const SymMasks sm = sym_masks(cc);
       const uint32_t sb1 = 8 * (L1 >> MBW_SB_SHIFT), sb2 = 8 * (L2 >> MBW_SB_SHIFT);
-      const int o1 = (int)(x1 - (uint64_t)L1 * MBW_BPL), o2 = (int)(x2 - (uint64_t)L2 * MBW_BPL);
-      uint64_t E1, G1, E2, G2, t1, t2;
-      rank_lds(bufA, lane, cc, sm, sbt[sb1 + cc], sbt[sb1 + 4 + cc], o1, two ? -1 : o2, E1, G1, E2, G2);
-      if (two) rank_lds(bufB, lane, cc, sm, sbt[sb2 + cc], sbt[sb2 + 4 + cc], o2, -1, E2, G2, t1, t2);
+      uint64_t E1, G1, E2, G2;
+      rank_lds(bufA, lane, o1, cc, sm, sbt[sb1 + cc], sbt[sb1 + 4 + cc], E1, G1);
+      rank_lds(fetch2 ? bufB : bufA, lane, o2, cc, sm, sbt[sb2 + cc], sbt[sb2 + 4 + cc], E2, G2);
       n_lines += two ? 2 : 1;
       ++n_steps;
       uint64_t nx, ny, ns;
@@ -662,8 +682,9 @@ __global__ void __launch_bounds__(256) k_locate_wave(IndexView ix, const uint64_
       } else need = true;
     }
     const uint32_t L = need ? line_of(x) : 0u;
+    const int o = (int)(x - (uint64_t)L * MBW_BPL);
     // ---- memory phase
-    if (__ballot(need)) fetch_lines_lds(ix.lines, L, need, buf, lane);
+    if (__ballot(need)) fetch_blocks_lds(ix.lines, L, block_slice(o), need, buf, lane);
     uint64_t sv = 0;
     if (fin) sv = ix.ssa[sample_index(x, ix.r, rshift)];
     const bool ld = pre == P_PENDING;
@@ -679,13 +700,11 @@ __global__ void __launch_bounds__(256) k_locate_wave(IndexView ix, const uint64_
       cur = W_NONE;
     }
     if (need) {
-      const int o = (int)(x - (uint64_t)L * MBW_BPL);
-      const int sl = block_slice(o);
-      const uint4 sa = lds_slice(buf, lane, sl), sbk = lds_slice(buf, lane, sl + 1);
+      const uint4 sa = lds_q(buf, lane, 2), sbk = lds_q(buf, lane, 3);
       const int b = bwt_from_block(sa, sbk, o);
       const uint32_t sbi = 8 * (L >> MBW_SB_SHIFT);
       uint64_t E, G;
-      rank_eg(lds_slice(buf, lane, 0), lds_slice(buf, lane, 1), sa, sbk, o, b, sym_masks(b), sbt[sbi + b], sbt[sbi + 4 + b], E, G);
+      rank_eg(lds_q(buf, lane, 0), lds_q(buf, lane, 1), sa, sbk, o, b, sym_masks(b), sbt[sbi + b], sbt[sbi + 4 + b], E, G);
       if (b == 0 && x > ix.primary) E -= 1;
       x = sel4(ix.Cb[0], ix.Cb[1], ix.Cb[2], ix.Cb[3], b) + E;
       ++steps; ++lines; ++lf;
@@ -729,7 +748,7 @@ struct mbw_ctx {
   int n_cu;
   struct Buf { void *p = nullptr; size_t bytes = 0; };   // grow-only device buffers
   Buf codes, ascii, lens, offs, raw, subq, keys0, keys1, vals0, vals1, flag, idx, seeds, npos, posoff, xrows, pos, pos2,
-      keep, kidx, temp, ctl, pwords, pnmask, woffs, nwords;
+      keep, kidx, temp, ctl, pwords, pnmask, woffs, nwords, wread;
   hipEvent_t ev[8];
   unsigned long long host_ctl[C_COUNT];
   float ms_smem;
@@ -774,7 +793,7 @@ extern "C" void mbw_ctx_free(mbw_ctx *c) {
   (void)hipSetDevice(c->device);
   mbw_ctx::Buf *bs[] = {&c->codes, &c->ascii, &c->lens, &c->offs, &c->raw, &c->subq, &c->keys0, &c->keys1, &c->vals0,
                         &c->vals1, &c->flag, &c->idx, &c->seeds, &c->npos, &c->posoff, &c->xrows, &c->pos, &c->pos2,
-                        &c->keep, &c->kidx, &c->temp, &c->ctl, &c->pwords, &c->pnmask, &c->woffs, &c->nwords};
+                        &c->keep, &c->kidx, &c->temp, &c->ctl, &c->pwords, &c->pnmask, &c->woffs, &c->nwords, &c->wread};
   for (auto *b : bs) if (b->p) (void)hipFree(b->p);
   for (int t = 0; t < 8; ++t) (void)hipEventDestroy(c->ev[t]);
   delete c;
@@ -881,17 +900,19 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   TRY(hipMemcpyAsync(&maxlen, ctl + C_MAXLEN, 8, hipMemcpyDeviceToHost, st));
   TRY(hipStreamSynchronize(st));
   if (maxlen > MBW_MAX_READ) { mbw_set_error("read longer than 65535 bases"); return MBW_E_INVAL; }
-  // encode, then pack for the wave kernels
-  GROW(c->codes, total + 16);
+  // encode (plain kernel) or pack (wave kernels)
   const uint8_t *dreads = reads;
   if (!is_device_ptr(reads)) {
     GROW(c->ascii, total + 16);
     TRY(hipMemcpyAsync(c->ascii.p, reads, total, hipMemcpyHostToDevice, st));
     dreads = (const uint8_t *)c->ascii.p;
   }
-  k_encode<<<grid_for(total), 256, 0, st>>>(dreads, total, o.bs_role, (uint8_t *)c->codes.p);
-  TRY(hipGetLastError());
   const bool coop = o.kernel != MBW_KERNEL_PLAIN;
+  if (!coop) {   // the plain kernel reads one code per base
+    GROW(c->codes, total + 16);
+    k_encode<<<grid_for(total), 256, 0, st>>>(dreads, total, o.bs_role, (uint8_t *)c->codes.p);
+    TRY(hipGetLastError());
+  }
   const bool staged = coop && maxlen <= 32 * STAGE_WORDS && !o.no_stage;
   ReadWords R;
   R.pw = nullptr; R.pn = nullptr; R.woff = nullptr;
@@ -908,8 +929,11 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     TRY(hipStreamSynchronize(st));
     GROW(c->pwords, (totw + 2) * 8);
     GROW(c->pnmask, (totw + 2) * 4);
-    k_pack_reads<<<grid_for(n_reads), 256, 0, st>>>((const uint8_t *)c->codes.p, offs, woff, n_reads, (uint64_t *)c->pwords.p,
-                                                    (uint32_t *)c->pnmask.p);
+    GROW(c->wread, (totw + 2) * 4);
+    k_word_owner<<<grid_for(n_reads), 256, 0, st>>>(woff, n_reads, (uint32_t *)c->wread.p);
+    TRY(hipGetLastError());
+    k_pack_words<<<grid_for(totw), 256, 0, st>>>(dreads, offs, woff, (const uint32_t *)c->wread.p, totw, o.bs_role,
+                                                 (uint64_t *)c->pwords.p, (uint32_t *)c->pnmask.p);
     TRY(hipGetLastError());
     R.pw = (const uint64_t *)c->pwords.p;
     R.pn = (const uint32_t *)c->pnmask.p;
@@ -917,9 +941,9 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   }
   // SMEM rounds.  Per-wave output chunks leave up to one partly used chunk per wave of the grid.
   const uint64_t chunk_slack = (uint64_t)c->n_cu * 64 * OUT_CHUNK;
-  uint64_t seed_cap = std::max<uint64_t>(1 << 16, n_reads * 4) + chunk_slack;
+  uint64_t seed_cap = std::max<uint64_t>(1 << 16, n_reads * 6) + chunk_slack;
   if (c->raw.bytes / sizeof(SeedRec) > seed_cap) seed_cap = c->raw.bytes / sizeof(SeedRec);
-  uint64_t subq_cap = std::max<uint64_t>(1 << 14, n_reads / 2) + chunk_slack;
+  uint64_t subq_cap = std::max<uint64_t>(1 << 14, n_reads) + chunk_slack;
   if (c->subq.bytes / sizeof(Query) > subq_cap) subq_cap = c->subq.bytes / sizeof(Query);
   SeedParams P;
   memset(&P, 0, sizeof(P));
