@@ -183,7 +183,9 @@ def main():
     traffic = traffic_from_profile("smem", smem_bytes / max(launches, 1))
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                    kernel="k_smem_wave<staged> (both SMEM rounds)",
+                    kernel="k_smem_wave<staged> (both SMEM rounds)", launches_per_step=launches,
+                    avg_launch_ms=round(ms_smem / max(launches, 1), 3),
+                    bytes_per_launch=round(smem_bytes / max(launches, 1)),
                     lines_per_read=round(lines_smem / n_reads, 1),
                     locate=dict(achieved=round(lines_loc * LINE_BYTES / (ms_loc * 1e-3) / 1e9, 1),
                                 lines_per_read=round(lines_loc / n_reads, 1)),
