@@ -121,7 +121,7 @@ def main():
         return
     gather_lps, _ = mbw.probe_gather(16 << 30)
     t0 = time.time()
-    ref = synth.reference(1, args.ref_len, synth.REF_SEED + 3)
+    ref = synth.workload_reference("human_3gbp", args.ref_len)
     log(f"reference {len(ref)} bases generated in {time.time() - t0:.1f} s")
     t0 = time.time()
     idx = mbw.Index.build(ref.codes, sa_sample=args.sa_sample, kmer_k=args.kmer)
@@ -129,8 +129,7 @@ def main():
     log(f"index built on the GPU in {time.time() - t0:.1f} s: n={info['n']} lines={info['n_lines']} "
         f"resident={info['bytes_resident'] / 1e9:.2f} GB")
     t0 = time.time()
-    reads = synth.reads_fixed(ref, args.pairs, 150, True, p_sub=0.005, p_indel=0.0005, sat_frac=0.05,
-                              seed=synth.READ_SEED + 3)
+    reads = synth.workload_reads("human_3gbp", ref, args.pairs)
     n_reads = len(reads)
     log(f"{n_reads} reads generated in {time.time() - t0:.1f} s")
     dseq = torch.from_numpy(reads.seq).to(dev)
@@ -205,7 +204,7 @@ def main():
     line = dict(metric=METRIC, value=round(value, 1), unit="reads/s", n_gpus=1, steps=args.steps,
                 warmup=args.warmup, ms_per_step=round(elapsed / args.steps * 1e3, 2), higher_is_better=True,
                 scaling="weak", vs_baseline=None, dtype="u64", data="synthetic",
-                config=dict(workload=f"configs[3]: {args.ref_len / 1e9:.1f} Gbp synthetic reference, "
+                config=dict(workload=f"{args.ref_len / 1e9:.1f} Gbp synthetic reference, "
                                      f"{args.pairs} paired 150 bp reads ({n_reads} reads), 0.5% error, 5% from "
                                      f"satellites; (19,1)-SMEMs + re-seeding, max_occ 500",
                             min_seed_len=19, max_occ=500, sa_sample=args.sa_sample, kmer_k=args.kmer,

@@ -4,11 +4,15 @@ A plain CPU statement of the seeding path (see ``oracle.c`` for the paper passag
 follows).  Only the tests, ``__graft_entry__.smoke()`` and the benchmark's ``cpu_baseline`` leg
 may import this package; the product library never does, and the two share no code.
 
-Two oracles:
+Three oracles:
   * method 0 (O1): full suffix array by sorting; intervals, SMEMs and positions from their
     definitions (Section 2.1).
   * method 1 (O2): FM-index with Algorithm 1, serial Algorithm 3, Algorithm 2 LocateSlow over
     a sampled SA; counts the index lines a given line layout would touch.
+  * ``scan_seed`` (O3): no index; one pass over T finds every occurrence of every q-mer of a
+    sample of reads, and direct extension gives the SMEM set, s and the exact positions from the
+    definitions (Section 2.2).  For references too large to sort on the host; ds-interval bounds
+    are not produced (k = k' = 2^64 - 1).
 """
 from __future__ import annotations
 
@@ -70,6 +74,8 @@ def _load():
     L.orc_pi.argtypes = [vp, u8, u64]
     L.orc_locate_slow.restype = u64
     L.orc_locate_slow.argtypes = [vp, u64]
+    L.orc_scan_seed.restype = vp
+    L.orc_scan_seed.argtypes = [vp, u64, i32, vp, vp, u64, C.POINTER(_Opts), i32]
     _lib = L
     return L
 
@@ -180,25 +186,53 @@ class OracleIndex:
         o = _Opts(int(min_len), int(min_occ), int(max_occ), int(bool(reseed)), int(reseed_len),
                   int(reseed_occ), int(bs_role), int(method), int(kmer_k), int(bases_per_line))
         h = _lib.orc_seed(self._h, _p(seq), _p(offsets), nr, C.byref(o), int(threads))
-        try:
-            ns = int(_lib.orc_result_nseeds(h))
-            np_ = int(_lib.orc_result_npos(h))
-            a = dict(read_id=np.empty(ns, np.uint32), qbeg=np.empty(ns, np.uint32), qend=np.empty(ns, np.uint32),
-                     k=np.empty(ns, np.uint64), kr=np.empty(ns, np.uint64), s=np.empty(ns, np.uint64),
-                     npos=np.empty(ns, np.uint32), flags=np.empty(ns, np.uint32),
-                     pos_off=np.empty(ns, np.uint64), pos=np.empty(np_, np.uint64))
-            bufs = [a[x] if a[x].size else np.zeros(1, a[x].dtype) for x in
-                    ("read_id", "qbeg", "qend", "k", "kr", "s", "npos", "flags", "pos_off", "pos")]
-            _lib.orc_result_copy(h, *[_p(b) for b in bufs])
-            for name, b in zip(("read_id", "qbeg", "qend", "k", "kr", "s", "npos", "flags", "pos_off", "pos"), bufs):
-                a[name] = b[: a[name].size]
-            ln = np.zeros(5, np.uint64)
-            _lib.orc_result_lines(h, _p(ln))
-            lines = dict(lines=int(ln[0]), kmer_lookups=int(ln[1]), sa_reads=int(ln[2]), steps=int(ln[3]),
-                         lf_steps=int(ln[4]))
-        finally:
-            _lib.orc_result_free(h)
-        return SeedResult(lines=lines, **a)
+        return _result(h)
+
+
+def _result(h) -> SeedResult:
+    try:
+        ns = int(_lib.orc_result_nseeds(h))
+        np_ = int(_lib.orc_result_npos(h))
+        a = dict(read_id=np.empty(ns, np.uint32), qbeg=np.empty(ns, np.uint32), qend=np.empty(ns, np.uint32),
+                 k=np.empty(ns, np.uint64), kr=np.empty(ns, np.uint64), s=np.empty(ns, np.uint64),
+                 npos=np.empty(ns, np.uint32), flags=np.empty(ns, np.uint32),
+                 pos_off=np.empty(ns, np.uint64), pos=np.empty(np_, np.uint64))
+        names = ("read_id", "qbeg", "qend", "k", "kr", "s", "npos", "flags", "pos_off", "pos")
+        bufs = [a[x] if a[x].size else np.zeros(1, a[x].dtype) for x in names]
+        _lib.orc_result_copy(h, *[_p(b) for b in bufs])
+        for name, b in zip(names, bufs):
+            a[name] = b[: a[name].size]
+        ln = np.zeros(5, np.uint64)
+        _lib.orc_result_lines(h, _p(ln))
+        lines = dict(lines=int(ln[0]), kmer_lookups=int(ln[1]), sa_reads=int(ln[2]), steps=int(ln[3]),
+                     lf_steps=int(ln[4]))
+    finally:
+        _lib.orc_result_free(h)
+    return SeedResult(lines=lines, **a)
+
+
+def scan_seed(ref_codes: np.ndarray, seq: np.ndarray, offsets: np.ndarray, bisulfite: bool = False,
+              min_len: int = 19, min_occ: int = 1, max_occ: int = 500, reseed: bool = True,
+              reseed_len: int = 38, reseed_occ: int = 10, bs_role: int = 0, threads: int = 0) -> SeedResult:
+    """O3: SMEMs of both rounds, s and positions of a (small) read set over T = R . revcomp(R) . $
+    (or the bisulfite text) by one scan of T, without an index.  Needs min(l, reseed_len / 2)
+    between 1 and 32; k and k' come back as 2^64 - 1."""
+    L = _load()
+    ref = np.ascontiguousarray(ref_codes, dtype=np.uint8)
+    seq = np.ascontiguousarray(seq, dtype=np.uint8)
+    if seq.size == 0:
+        seq = np.zeros(1, np.uint8)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    q = min(min_len, reseed_len // 2) if reseed else min_len
+    if not 1 <= q <= 32:
+        raise ValueError("scan oracle needs a q-mer length between 1 and 32")
+    o = _Opts(int(min_len), int(min_occ), int(max_occ), int(bool(reseed)), int(reseed_len), int(reseed_occ),
+              int(bs_role), 2, 0, 0)
+    h = L.orc_scan_seed(_p(ref), ref.size, int(bool(bisulfite)), _p(seq), _p(offsets), offsets.size - 1,
+                        C.byref(o), int(threads))
+    if not h:
+        raise ValueError("scan oracle rejected its arguments")
+    return _result(h)
 
 
 def seed_reads(index: OracleIndex, reads, **kw) -> SeedResult:

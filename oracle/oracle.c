@@ -543,3 +543,240 @@ void orc_backward(const orc_index *ix, uint64_t iv[3], uint8_t a) { fm_backward(
 void orc_forward(const orc_index *ix, uint64_t iv[3], uint8_t a) { fm_forward(ix, iv, a, NULL); }
 uint64_t orc_pi(const orc_index *ix, uint8_t a, uint64_t k) { return fm_pi(ix, a, k); }
 uint64_t orc_locate_slow(const orc_index *ix, uint64_t k) { return fm_locate_slow(ix, k, NULL); }
+
+/* ------------------------------------------------------------------------------------------ */
+/* O3 ("scan"): (l,c)-SMEMs and their positions for a sample of reads over a text too large to
+ * sort, straight from the definitions of Section 2.2, with no index at all.
+ *
+ * Every match P[i,j) of length >= q begins with an occurrence of the q-mer P[i,i+q).  One pass
+ * over T therefore collects every occurrence p of every q-mer of the reads (q = the smallest
+ * seed length any round may ask for, at most 32).  Extending each occurrence to the right by
+ * direct comparison gives len(i,p) = the longest common prefix of P[i..] and T[p..], so
+ *     occ(P[i,j)) = |{p : len(i,p) >= j - i}|      for every j >= i + q,
+ * hence e(i) = max{ j : occ(P[i,j)) >= c } (the c-th largest len), the SMEM set
+ * {[i, e(i)) : (i = first offset or e(i-1) < e(i)) and e(i) - i >= l}, each SMEM's s and its
+ * exact position set {p : len(i,p) >= e(i) - i}.  Offsets whose q-mer occurs fewer than c times
+ * have e(i) < i + q and can neither start an SMEM nor block the next offset.  The ds-interval
+ * bounds lo(P), lo(revcomp P) need the sorted suffixes and are not produced (k = k' = ~0).
+ * Round 2 (Section 2.6) reuses the same occurrence lists with lengths capped at the sub-query's
+ * end.                                                                                       */
+typedef struct { uint64_t key; uint32_t read, off; } qmer_t;
+typedef struct { uint32_t kid; uint32_t pad; uint64_t p; } hit_t;
+
+static int cmp_qmer(const void *a, const void *b) {
+  const qmer_t *x = (const qmer_t *)a, *y = (const qmer_t *)b;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  if (x->read != y->read) return x->read < y->read ? -1 : 1;
+  return x->off < y->off ? -1 : x->off > y->off;
+}
+static inline uint64_t qmix(uint64_t k) { return (k * 0x9E3779B97F4A7C15ull) >> 40; }   /* 24-bit bucket */
+
+typedef struct { uint32_t len; uint64_t p; } occ_t;       /* one occurrence of the q-mer at an offset */
+
+/* e(i) over the query [qb, qe) for minimum occurrence c: i + the c-th largest match length
+ * (capped at the query end); -1 when fewer than c occurrences of the q-mer exist (then
+ * e(i) < i + q).  `hist` has room for qe - i + 1 counters.                                    */
+static int64_t scan_e(const occ_t *o, uint64_t no, uint64_t i, uint64_t qe, uint64_t c, uint64_t *hist) {
+  if (no < c) return -1;
+  const uint64_t cap = qe - i;
+  memset(hist, 0, (cap + 1) * 8);
+  for (uint64_t t = 0; t < no; ++t) hist[o[t].len < cap ? o[t].len : cap]++;
+  uint64_t cnt = 0;
+  for (uint64_t m = cap;; --m) {
+    cnt += hist[m];
+    if (cnt >= c) return (int64_t)(i + m);
+    if (m == 0) return -1;
+  }
+}
+
+static void scan_smems(const occ_t *const *occ, const uint64_t *nocc, uint64_t qb, uint64_t qe, int l, uint64_t c,
+                       int q, uint64_t *hist, smem_vec *out) {
+  int64_t prev = -1;
+  for (uint64_t i = qb; i < qe; ++i) {
+    int64_t e = (i + (uint64_t)q <= qe) ? scan_e(occ[i], nocc[i], i, qe, c, hist) : -1;
+    if (e >= 0 && e - (int64_t)i < q) e = -1;                 /* shorter than a q-mer: not exact here */
+    if (e >= 0 && e - (int64_t)i >= l && (i == qb || prev < e)) {
+      smem_t s;
+      s.qbeg = (uint32_t)i; s.qend = (uint32_t)e; s.k = ~0ull; s.kr = ~0ull; s.s = 0;
+      for (uint64_t t = 0; t < nocc[i]; ++t) s.s += occ[i][t].len >= (uint64_t)(e - (int64_t)i);
+      push_smem(out, s);
+    }
+    prev = e;
+  }
+}
+
+orc_result *orc_scan_seed(const uint8_t *R, uint64_t len_r, int bisulfite, const uint8_t *reads, const uint64_t *offsets,
+                          uint64_t n_reads, const orc_opts *o, int n_threads) {
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+  int q = o->min_len;
+  if (o->reseed && o->reseed_len / 2 < q) q = o->reseed_len / 2;
+  if (q > 32) q = 32;
+  if (q < 1) return NULL;
+  uint64_t n = 0;
+  uint8_t *T = build_text(R, len_r, bisulfite, &n);
+  const uint64_t lr_seg = len_r;   /* bisulfite segment length */
+  /* encode reads (Section 2.9 conversion by role), collect their q-mers */
+  uint64_t tot = offsets[n_reads];
+  uint8_t *P = (uint8_t *)malloc(tot + 1);
+  for (uint64_t t = 0; t < tot; ++t) {
+    uint8_t a = enc_ascii(reads[t]);
+    if (o->bs_role == 1 && a == 2) a = 4;
+    if (o->bs_role == 2 && a == 3) a = 1;
+    P[t] = a;
+  }
+  uint64_t nq = 0;
+  qmer_t *Q = (qmer_t *)malloc((tot + 1) * sizeof(qmer_t));
+  const uint64_t kmask = q == 32 ? ~0ull : ((1ull << (2 * q)) - 1);
+  for (uint64_t r = 0; r < n_reads; ++r) {
+    uint64_t b = offsets[r], m = offsets[r + 1] - b, key = 0, run = 0;
+    for (uint64_t t = 0; t < m; ++t) {
+      uint8_t a = P[b + t];
+      if (a < 1 || a > 4) { run = 0; key = 0; continue; }
+      key = ((key << 2) | (uint64_t)(a - 1)) & kmask;
+      if (++run >= (uint64_t)q) { Q[nq].key = key; Q[nq].read = (uint32_t)r; Q[nq].off = (uint32_t)(t + 1 - q); ++nq; }
+    }
+  }
+  qsort(Q, nq, sizeof(qmer_t), cmp_qmer);
+  uint64_t nu = 0;
+  uint64_t *U = (uint64_t *)malloc((nq + 1) * 8);
+  uint32_t *qkid = (uint32_t *)malloc((nq + 1) * 4);          /* key id of each read q-mer */
+  for (uint64_t t = 0; t < nq; ++t) {
+    if (nu == 0 || U[nu - 1] != Q[t].key) U[nu++] = Q[t].key;
+    qkid[t] = (uint32_t)(nu - 1);
+  }
+  uint64_t *bitmap = (uint64_t *)calloc((1u << 24) / 64, 8);
+  for (uint64_t t = 0; t < nu; ++t) { uint64_t h = qmix(U[t]); bitmap[h >> 6] |= 1ull << (h & 63); }
+  /* one pass over T: every occurrence of every read q-mer */
+  int nt = omp_get_max_threads();
+  hit_t **th = (hit_t **)calloc((size_t)nt, sizeof(hit_t *));
+  uint64_t *thn = (uint64_t *)calloc((size_t)nt, 8), *thc = (uint64_t *)calloc((size_t)nt, 8);
+  #pragma omp parallel
+  {
+    int tid = omp_get_thread_num();
+    uint64_t chunk = (n + (uint64_t)nt - 1) / (uint64_t)nt;
+    uint64_t a0 = chunk * (uint64_t)tid, a1 = a0 + chunk < n ? a0 + chunk : n;   /* start positions [a0, a1) */
+    uint64_t key = 0, run = 0;
+    for (uint64_t p = a0; p < a1 + (uint64_t)q - 1 && p < n; ++p) {
+      uint8_t a = T[p];
+      if (a < 1 || a > 4) { run = 0; key = 0; continue; }
+      key = ((key << 2) | (uint64_t)(a - 1)) & kmask;
+      if (++run < (uint64_t)q) continue;
+      uint64_t st = p + 1 - (uint64_t)q;
+      if (st < a0) continue;
+      uint64_t h = qmix(key);
+      if (!((bitmap[h >> 6] >> (h & 63)) & 1)) continue;
+      uint64_t lo = 0, hi = nu;
+      while (lo < hi) { uint64_t mid = (lo + hi) / 2; if (U[mid] < key) lo = mid + 1; else hi = mid; }
+      if (lo < nu && U[lo] == key) {
+        if (thn[tid] == thc[tid]) { thc[tid] = thc[tid] ? 2 * thc[tid] : 4096; th[tid] = (hit_t *)realloc(th[tid], thc[tid] * sizeof(hit_t)); }
+        th[tid][thn[tid]].kid = (uint32_t)lo; th[tid][thn[tid]].pad = 0; th[tid][thn[tid]].p = st; thn[tid]++;
+      }
+    }
+  }
+  /* group the hits by key id (counting sort): hits of key id u are H[hstart[u], hstart[u+1]) */
+  uint64_t nh = 0;
+  for (int t = 0; t < nt; ++t) nh += thn[t];
+  uint64_t *hstart = (uint64_t *)calloc(nu + 2, 8);
+  for (int t = 0; t < nt; ++t)
+    for (uint64_t x = 0; x < thn[t]; ++x) hstart[th[t][x].kid + 1]++;
+  for (uint64_t u = 0; u < nu; ++u) hstart[u + 1] += hstart[u];
+  uint64_t *fill = (uint64_t *)malloc((nu + 1) * 8);
+  memcpy(fill, hstart, (nu + 1) * 8);
+  hit_t *H = (hit_t *)malloc((nh + 1) * sizeof(hit_t));
+  for (int t = 0; t < nt; ++t) {
+    for (uint64_t x = 0; x < thn[t]; ++x) H[fill[th[t][x].kid]++] = th[t][x];
+    free(th[t]);
+  }
+  free(fill); free(th); free(thn); free(thc);
+  /* per read: occurrence lists with their match lengths, then the SMEMs of both rounds */
+  uint32_t *kid_at = (uint32_t *)malloc((tot + 1) * 4);
+  for (uint64_t t = 0; t < tot; ++t) kid_at[t] = 0xFFFFFFFFu;
+  for (uint64_t t = 0; t < nq; ++t) kid_at[offsets[Q[t].read] + Q[t].off] = qkid[t];
+  smem_vec *per = (smem_vec *)calloc(n_reads, sizeof(smem_vec));
+  uint64_t **ppos = (uint64_t **)calloc(n_reads, sizeof(uint64_t *));
+  uint32_t **pcnt = (uint32_t **)calloc(n_reads, sizeof(uint32_t *));
+  #pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t r = 0; r < (int64_t)n_reads; ++r) {
+    uint64_t b = offsets[r], m = offsets[r + 1] - b;
+    occ_t **occ = (occ_t **)calloc(m + 1, sizeof(occ_t *));
+    uint64_t *nocc = (uint64_t *)calloc(m + 1, 8);
+    for (uint64_t i = 0; i < m; ++i) {
+      uint32_t u = kid_at[b + i];
+      if (u == 0xFFFFFFFFu) continue;
+      uint64_t h0 = hstart[u], h1 = hstart[u + 1];
+      nocc[i] = h1 - h0;
+      occ[i] = (occ_t *)malloc((nocc[i] + 1) * sizeof(occ_t));
+      for (uint64_t t = h0; t < h1; ++t) {
+        uint64_t p = H[t].p, len = (uint64_t)q;
+        while (i + len < m && p + len < n && P[b + i + len] == T[p + len] && T[p + len] >= 1 && T[p + len] <= 4) ++len;
+        occ[i][t - h0].len = (uint32_t)len; occ[i][t - h0].p = p;
+      }
+    }
+    uint64_t *tmp = (uint64_t *)malloc((m + 2) * 8);
+    smem_vec *V = &per[r];
+    V->n = 0;
+    scan_smems((const occ_t *const *)occ, nocc, 0, m, o->min_len, (uint64_t)o->min_occ, q, tmp, V);
+    if (o->reseed) {
+      uint64_t n1 = V->n;
+      for (uint64_t t = 0; t < n1; ++t) {
+        smem_t s = V->v[t];
+        if (s.qend - s.qbeg >= (uint32_t)o->reseed_len && s.s <= (uint64_t)o->reseed_occ)
+          scan_smems((const occ_t *const *)occ, nocc, s.qbeg, s.qend, (int)((s.qend - s.qbeg) / 2), s.s + 1, q, tmp, V);
+      }
+    }
+    qsort(V->v, V->n, sizeof(smem_t), cmp_smem);
+    uint64_t w = 0;
+    for (uint64_t t = 0; t < V->n; ++t)
+      if (w == 0 || cmp_smem(&V->v[w - 1], &V->v[t]) != 0) V->v[w++] = V->v[t];
+    V->n = w;
+    uint64_t np = 0;
+    for (uint64_t t = 0; t < V->n; ++t) if (V->v[t].s <= (uint64_t)o->max_occ) np += V->v[t].s;
+    uint64_t *pp = (uint64_t *)malloc((np + 1) * 8);
+    uint32_t *pc = (uint32_t *)calloc(V->n + 1, 4);
+    uint64_t pw = 0;
+    for (uint64_t t = 0; t < V->n; ++t) {
+      smem_t *s = &V->v[t];
+      if (s->s > (uint64_t)o->max_occ) continue;
+      uint64_t w0 = pw, need = s->qend - s->qbeg;
+      for (uint64_t x = 0; x < nocc[s->qbeg]; ++x) {
+        const occ_t *oc = &occ[s->qbeg][x];
+        if (oc->len < need) continue;
+        uint64_t seg = oc->p / lr_seg;
+        int keep = o->bs_role == 1 ? (seg == 0 || seg == 2) : o->bs_role == 2 ? (seg == 1 || seg == 3) : 1;
+        if (keep) pp[pw++] = oc->p;
+      }
+      qsort(pp + w0, pw - w0, 8, cmp_u64);
+      pc[t] = (uint32_t)(pw - w0);
+    }
+    ppos[r] = pp; pcnt[r] = pc;
+    for (uint64_t i = 0; i < m; ++i) free(occ[i]);
+    free(occ); free(nocc); free(tmp);
+  }
+  orc_result *res = (orc_result *)calloc(1, sizeof(orc_result));
+  uint64_t ns = 0, npos = 0;
+  for (uint64_t r = 0; r < n_reads; ++r) { ns += per[r].n; for (uint64_t t = 0; t < per[r].n; ++t) npos += pcnt[r][t]; }
+  res->n_seeds = ns; res->n_pos = npos;
+  res->read_id = (uint32_t *)malloc((ns + 1) * 4); res->qbeg = (uint32_t *)malloc((ns + 1) * 4);
+  res->qend = (uint32_t *)malloc((ns + 1) * 4); res->npos = (uint32_t *)malloc((ns + 1) * 4);
+  res->flags = (uint32_t *)malloc((ns + 1) * 4);
+  res->k = (uint64_t *)malloc((ns + 1) * 8); res->kr = (uint64_t *)malloc((ns + 1) * 8);
+  res->s = (uint64_t *)malloc((ns + 1) * 8); res->pos_off = (uint64_t *)malloc((ns + 1) * 8);
+  res->pos = (uint64_t *)malloc((npos + 1) * 8);
+  uint64_t si = 0, pw = 0;
+  for (uint64_t r = 0; r < n_reads; ++r) {
+    uint64_t rp = 0;
+    for (uint64_t t = 0; t < per[r].n; ++t) {
+      smem_t *s = &per[r].v[t];
+      res->read_id[si] = (uint32_t)r; res->qbeg[si] = s->qbeg; res->qend[si] = s->qend;
+      res->k[si] = s->k; res->kr[si] = s->kr; res->s[si] = s->s; res->pos_off[si] = pw;
+      res->flags[si] = s->s > (uint64_t)o->max_occ ? 1u : 0u;
+      res->npos[si] = pcnt[r][t];
+      memcpy(res->pos + pw, ppos[r] + rp, (uint64_t)pcnt[r][t] * 8);
+      rp += pcnt[r][t]; pw += pcnt[r][t]; ++si;
+    }
+    free(per[r].v); free(ppos[r]); free(pcnt[r]);
+  }
+  free(per); free(ppos); free(pcnt);
+  free(kid_at); free(hstart); free(H); free(bitmap); free(qkid); free(U); free(Q); free(P); free(T);
+  return res;
+}

@@ -2,7 +2,7 @@
 
 This package holds none of the seeding method's arithmetic: it draws the inputs that both the
 CPU oracle and the GPU library consume.  Recipes follow the workload shapes used throughout the
-project (see ``CONFIGS``): a uniform-random genome with a divergent 2 kbp repeat family for the
+project (see ``WORKLOADS``): a uniform-random genome with a divergent 2 kbp repeat family for the
 small case, and a mixed genome (random sequence, interspersed 300 bp / 6 kbp repeat families at
 2-20% divergence, tandem 171 bp satellite arrays at 1-3% divergence) for the 100 Mbp and
 3.1 Gbp cases.  Reads carry substitutions and 1-3 bp indels.
@@ -221,38 +221,39 @@ def concat(a: ReadSet, b: ReadSet) -> ReadSet:
 
 
 # ------------------------------------------------------------------------------------------
-# the five workloads
+# the five workloads (reference recipe, size and seed; read model)
 
-CONFIGS = {
-    0: dict(desc="1 Mbp random + 20x2 kbp repeat @5%; 10,000 x 150 bp single-end, 0.5% sub, "
-                 "0.05% indel; min seed 19, max_occ 500", recipe=0, ref_len=1_000_000),
-    1: dict(desc="100 Mbp mixed genome; 1,000,000 pairs x 150 bp, insert N(400,50), errors as cfg0",
-            recipe=1, ref_len=100_000_000),
-    2: dict(desc="100 Mbp mixed genome; 500,000 reads, lognormal length 100-5000 bp (median 300), "
-                 "0.1% sub, 0.02% indel", recipe=1, ref_len=100_000_000),
-    3: dict(desc="3.1 Gbp mixed genome; 10,000,000 pairs x 150 bp at 0.5% error, 5% from satellites",
-            recipe=1, ref_len=3_100_000_000),
-    4: dict(desc="3.1 Gbp genome, bisulfite 3-base index + plain index; Poisson request stream",
-            recipe=1, ref_len=3_100_000_000),
+WORKLOADS = {
+    "small_1mbp": dict(desc="1 Mbp random + 20x2 kbp repeat @5%; 10,000 x 150 bp single-end, 0.5% sub, "
+                            "0.05% indel; min seed 19, max_occ 500", recipe=0, ref_len=1_000_000, seed=0),
+    "paired_100mbp": dict(desc="100 Mbp mixed genome; 1,000,000 pairs x 150 bp, insert N(400,50), 0.5% sub, "
+                               "0.05% indel", recipe=1, ref_len=100_000_000, seed=1),
+    "lognormal_100mbp": dict(desc="100 Mbp mixed genome; 500,000 reads, lognormal length 100-5000 bp "
+                                  "(median 300), 0.1% sub, 0.02% indel", recipe=1, ref_len=100_000_000, seed=1,
+                             read_seed=2),
+    "human_3gbp": dict(desc="3.1 Gbp mixed genome; 10,000,000 pairs x 150 bp at 0.5% error, 5% from "
+                            "satellites", recipe=1, ref_len=3_100_000_000, seed=3),
+    "serve_bs_3gbp": dict(desc="3.1 Gbp mixed genome, bisulfite 3-base index + plain index; Poisson request "
+                               "stream", recipe=1, ref_len=3_100_000_000, seed=3, read_seed=4),
 }
 
 
-def config_reference(cfg: int, ref_len: int | None = None) -> Reference:
-    c = CONFIGS[cfg]
-    seed = REF_SEED + (3 if cfg == 4 else (1 if cfg == 2 else cfg))
-    return reference(c["recipe"], ref_len or c["ref_len"], seed)
+def workload_reference(name: str, ref_len: int | None = None) -> Reference:
+    w = WORKLOADS[name]
+    return reference(w["recipe"], ref_len or w["ref_len"], REF_SEED + w["seed"])
 
 
-def config_reads(cfg: int, ref: Reference, n: int | None = None) -> ReadSet:
-    """Reads of workload ``cfg``; ``n`` overrides the read (or pair) count for bounded samples."""
-    seed = READ_SEED + cfg
-    if cfg == 0:
+def workload_reads(name: str, ref: Reference, n: int | None = None) -> ReadSet:
+    """Reads of workload ``name``; ``n`` overrides the read (or pair) count for bounded samples."""
+    w = WORKLOADS[name]
+    seed = READ_SEED + w.get("read_seed", w["seed"])
+    if name == "small_1mbp":
         return reads_fixed(ref, n or 10_000, 150, False, p_sub=0.005, p_indel=0.0005, seed=seed)
-    if cfg == 1:
+    if name == "paired_100mbp":
         return reads_fixed(ref, n or 1_000_000, 150, True, p_sub=0.005, p_indel=0.0005, seed=seed)
-    if cfg == 2:
+    if name == "lognormal_100mbp":
         return reads_lognormal(ref, n or 500_000, seed=seed)
-    if cfg == 3:
+    if name == "human_3gbp":
         return reads_fixed(ref, n or 10_000_000, 150, True, p_sub=0.005, p_indel=0.0005,
                            sat_frac=0.05, seed=seed)
-    raise ValueError("workload 4 reads are drawn per request (see reads_bisulfite)")
+    raise ValueError("serve_bs_3gbp reads are drawn per request (see reads_bisulfite)")

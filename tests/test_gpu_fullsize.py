@@ -1,0 +1,190 @@
+"""Parity at full workload sizes, in the launch configuration the benchmark times.
+
+The GPU seeds the whole batch (reads resident in device memory, one ``mbw_seed`` call); the
+oracle recomputes a seeded sample of the reads one by one and every seed, occurrence count and
+position of the sampled reads must agree exactly:
+
+* 100 Mbp mixed genome, 1,000,000 read pairs of 150 bp: oracle O1 (full suffix array,
+  definitions) on 20,000 sampled reads, all fields including the ds-interval bounds;
+* the same genome, 500,000 reads of 100-5000 bp (lognormal, median 300): O1 on 3,000 reads;
+* 3.1 Gbp mixed genome, 10,000,000 read pairs: oracle O3 (one scan of T per q-mer set, no index)
+  on 100 uniformly drawn reads plus 20 reads from satellite arrays; the bounds k' of the sampled
+  seeds are checked through the strand mirror (seeding revcomp(P) gives (k', k, s) and the
+  mirrored positions).
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from mbw_helpers import compare_with_oracle
+
+mbw = pytest.importorskip("paper_2606_15357_amd")
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+COMP = bytes.maketrans(b"ACGTNacgtn", b"TGCANtgcan")
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def device_batch(reads):
+    dev = torch.device("cuda:0")
+    return torch.from_numpy(reads.seq).to(dev), torch.from_numpy(reads.lengths.view(np.int32)).to(dev)
+
+
+def gpu_seed_batch(ctx, reads, **kw):
+    dseq, dlen = device_batch(reads)
+    out = ctx.seed(dseq, dlen, stream=torch.cuda.current_stream(), **kw)
+    torch.cuda.synchronize()
+    seeds, pos = out.download()
+    del dseq, dlen
+    return out, seeds, pos
+
+
+def sample_of(seeds, pos, ids):
+    """The seeds of reads `ids` (sorted), renumbered 0..len(ids)-1, with their own position array."""
+    m = np.isin(seeds["read_id"], ids)
+    sel = seeds[m].copy()
+    sel["read_id"] = np.searchsorted(ids, sel["read_id"]).astype(np.uint32)
+    chunks, off = [], 0
+    for t in range(sel.size):
+        o, c = int(sel["pos_off"][t]), int(sel["npos"][t])
+        chunks.append(pos[o:o + c])
+        sel["pos_off"][t] = off
+        off += c
+    p = np.concatenate(chunks) if chunks else np.zeros(0, np.uint64)
+    return sel, p
+
+
+def compare_without_bounds(seeds, pos, exp):
+    s, flat = mbw.canonical(seeds, pos)
+    assert len(s) == len(exp), (len(s), len(exp))
+    for f in ("read_id", "qbeg", "qend", "s", "npos"):
+        a, b = s[f].astype(np.uint64), getattr(exp, f).astype(np.uint64)
+        if not np.array_equal(a, b):
+            bad = np.nonzero(a != b)[0][:5]
+            raise AssertionError(f"{f} differs at {bad}: gpu {a[bad]} oracle {b[bad]}")
+    assert np.array_equal((s["flags"] & 1).astype(np.uint32), exp.flags & 1)
+    assert np.array_equal(flat, exp.pos)
+    return s, flat
+
+
+# ---------------------------------------------------------------------------------------------
+# 100 Mbp
+
+@pytest.fixture(scope="module")
+def genome100():
+    t = time.time()
+    ref = synth.workload_reference("paired_100mbp")
+    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=12)
+    ox = oracle.OracleIndex(ref.codes, sa_rate=8)
+    log(f"100 Mbp: GPU index + oracle index in {time.time() - t:.1f} s")
+    yield ref, idx, ox
+    idx.free()
+
+
+def test_paired_100mbp_sampled_parity(genome100):
+    ref, idx, ox = genome100
+    reads = synth.workload_reads("paired_100mbp", ref)
+    ids = np.sort(np.random.default_rng(101).choice(len(reads), 20_000, replace=False))
+    sub = reads.subset(ids)
+    exp = ox.seed(sub.seq, sub.offsets, min_len=19, max_occ=500)
+    assert len(exp) > 20_000
+    ctx = mbw.Context(idx)
+    counts = None
+    for kernel, stage in ((mbw.KERNEL_COOP, True), (mbw.KERNEL_COOP, False), (mbw.KERNEL_PLAIN, True)):
+        out, seeds, pos = gpu_seed_batch(ctx, reads, min_seed_len=19, max_occ=500, kernel=kernel, stage=stage)
+        log(f"kernel {kernel} stage {stage}: {out.n_seeds} seeds, {out.n_pos} positions")
+        if counts is None:
+            counts = (out.n_seeds, out.n_pos)
+        assert (out.n_seeds, out.n_pos) == counts
+        s, p = sample_of(seeds, pos, ids)
+        compare_with_oracle(s, p, exp)
+    ctx.free()
+
+
+def test_lognormal_100mbp_sampled_parity(genome100):
+    ref, idx, ox = genome100
+    reads = synth.workload_reads("lognormal_100mbp", ref)
+    assert reads.lengths.max() > 160 and reads.lengths.min() >= 100
+    ids = np.sort(np.random.default_rng(102).choice(len(reads), 3_000, replace=False))
+    sub = reads.subset(ids)
+    exp = ox.seed(sub.seq, sub.offsets, min_len=19, max_occ=500)
+    ctx = mbw.Context(idx)
+    counts = None
+    for kernel in (mbw.KERNEL_COOP, mbw.KERNEL_PLAIN):
+        out, seeds, pos = gpu_seed_batch(ctx, reads, min_seed_len=19, max_occ=500, kernel=kernel)
+        log(f"kernel {kernel}: {out.n_seeds} seeds, {out.n_pos} positions")
+        if counts is None:
+            counts = (out.n_seeds, out.n_pos)
+        assert (out.n_seeds, out.n_pos) == counts
+        s, p = sample_of(seeds, pos, ids)
+        compare_with_oracle(s, p, exp)
+    ctx.free()
+
+
+# ---------------------------------------------------------------------------------------------
+# 3.1 Gbp
+
+def test_human_3gbp_sampled_parity():
+    t0 = time.time()
+    ref = synth.workload_reference("human_3gbp")
+    log(f"3.1 Gbp reference in {time.time() - t0:.1f} s")
+    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=12)
+    info = idx.info()
+    log(f"GPU index in {time.time() - t0:.1f} s, n = {info['n']}")
+    reads = synth.workload_reads("human_3gbp", ref)
+    ctx = mbw.Context(idx)
+    out, seeds, pos = gpu_seed_batch(ctx, reads, min_seed_len=19, max_occ=500)
+    log(f"{len(reads)} reads: {out.n_seeds} seeds, {out.n_pos} positions ({time.time() - t0:.1f} s)")
+    # 100 uniform reads and 20 whose fragment starts inside a satellite array
+    rng = np.random.default_rng(103)
+    uni = rng.choice(len(reads), 100, replace=False)
+    sats = ref.sats[np.argsort(ref.sats[:, 0])]
+    j = np.searchsorted(sats[:, 0], reads.tpos, side="right") - 1
+    in_sat = np.nonzero((j >= 0) & (reads.tpos < sats[np.maximum(j, 0), 1]))[0]
+    sat = rng.choice(in_sat, 20, replace=False)
+    ids = np.unique(np.concatenate([uni, sat]))
+    sub = reads.subset(ids)
+    del reads
+    s_gpu, p_gpu = sample_of(seeds, pos, ids)
+    del seeds, pos
+    exp = oracle.scan_seed(ref.codes, sub.seq, sub.offsets, min_len=19, max_occ=500)
+    log(f"scan oracle: {len(exp)} seeds, {exp.pos.size} positions, {int((exp.flags & 1).sum())} over max_occ "
+        f"({time.time() - t0:.1f} s)")
+    assert len(exp) > 200 and (exp.flags & 1).sum() > 0
+    s, flat = compare_without_bounds(s_gpu, p_gpu, exp)
+    # k' through the strand mirror: seeding revcomp(P[i,j)) gives one SMEM (k', k, s) whose positions
+    # are 2|R| - p - (j - i)
+    loc = np.nonzero((s["npos"] > 0))[0]
+    rc = []
+    for t in loc:
+        r = int(s["read_id"][t])
+        a = int(sub.offsets[r]) + int(s["qbeg"][t])
+        b = int(sub.offsets[r]) + int(s["qend"][t])
+        rc.append(sub.seq[a:b].tobytes().translate(COMP)[::-1])
+    lens = np.array([len(x) for x in rc], np.uint32)
+    rseq = np.frombuffer(b"".join(rc), np.uint8).copy()
+    out2 = ctx.seed(rseq, lens, min_seed_len=19, max_occ=500, reseed=False)
+    s2, p2 = out2.download()
+    s2, flat2 = mbw.canonical(s2, p2)
+    assert len(s2) == len(loc)
+    assert np.all(s2["qbeg"] == 0) and np.array_equal(s2["qend"], lens)
+    assert np.array_equal(s2["k"], s["kr"][loc]) and np.array_equal(s2["kr"], s["k"][loc])
+    assert np.array_equal(s2["s"], s["s"][loc])
+    two_r = 2 * len(ref)
+    off = np.concatenate([[0], np.cumsum(s["npos"].astype(np.int64))])
+    off2 = np.concatenate([[0], np.cumsum(s2["npos"].astype(np.int64))])
+    for q, t in enumerate(loc):
+        mine = flat[off[t]:off[t + 1]].astype(np.int64)
+        mirrored = np.sort(two_r - mine - int(lens[q]))
+        assert np.array_equal(mirrored, flat2[off2[q]:off2[q + 1]].astype(np.int64))
+    ctx.free()
+    idx.free()
+    log(f"done in {time.time() - t0:.1f} s")

@@ -128,8 +128,8 @@ def test_tiny_seeding(name, kernel):
 
 @pytest.fixture(scope="module")
 def cfg0():
-    ref = synth.config_reference(0)
-    reads = synth.config_reads(0, ref)
+    ref = synth.workload_reference("small_1mbp")
+    reads = synth.workload_reads("small_1mbp", ref)
     ox = oracle.OracleIndex(ref.codes, sa_rate=8)
     exp = ox.seed(reads.seq, reads.offsets, min_len=19, max_occ=500)
     return ref, reads, ox, exp
@@ -237,3 +237,37 @@ def test_index_save_load_roundtrip(cfg0):
         assert e.value.code == mbw.MBW_E_FORMAT
         idx2.free()
     idx.free()
+
+
+def test_hand_worked_example():
+    """The hand-derived example (R = ACA, T = ACATGT$) straight from the GPU index and kernels."""
+    import json
+    g = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "hand_worked_aca.json")))
+    for K in (0, 1, 2):
+        idx = mbw.Index.build(ref_codes(g["R"]), sa_sample=2, kmer_k=K)
+        info = idx.info()
+        assert info["n"] == len(g["T"]) and info["primary"] == g["primary"]
+        assert [int(x) for x in info["C"]] == [0] + [g["C"][a] for a in "ACGT"]
+        with tempfile.TemporaryDirectory() as d:
+            p = os.path.join(d, "aca.mbw")
+            idx.save(p)
+            f = read_index_file(p)
+        B = "".join("ACGT"[int(x)] for x in decode_bwt(f))
+        assert B[:g["primary"]] + "$" + B[g["primary"] + 1:] == g["BWT"]
+        assert [int(x) for x in f["ssa"]] == g["SA"][::2]
+        for case in g["smems"]:
+            rs = readset([case["read"]])
+            for kernel in (0, 1):
+                out, seeds, pos = gpu_seed(idx, rs, min_seed_len=case["l"], min_occ=case["c"], kernel=kernel)
+                s, flat = mbw.canonical(seeds, pos)
+                got = [[int(s["qbeg"][t]), int(s["qend"][t]), int(s["k"][t]), int(s["kr"][t]), int(s["s"][t])]
+                       for t in range(len(s))]
+                assert got == case["out"], (case, kernel, K)
+                off = 0
+                for t in range(len(s)):
+                    sub = case["read"][got[t][0]:got[t][1]]
+                    n = int(s["npos"][t])
+                    if sub in g["positions"]:
+                        assert sorted(int(x) for x in flat[off:off + n]) == g["positions"][sub]
+                    off += n
+        idx.free()

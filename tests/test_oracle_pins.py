@@ -5,6 +5,9 @@
 * closed forms (homopolymer counts, a unique error-free read, mirrored strands),
 * the paper's algorithms (Algorithm 1/2/3 in oracle O2) against the definitions (oracle O1).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -287,8 +290,8 @@ def test_max_occ_rule():
 def test_algorithm3_equals_definition_small_workload():
     """O2 (Algorithm 3 + LocateSlow, with and without the k-mer shortcut) reproduces O1 on a
     slice of the 1 Mbp workload (all fields, all positions)."""
-    ref = synth.config_reference(0)
-    reads = synth.config_reads(0, ref, n=2000)
+    ref = synth.workload_reference("small_1mbp")
+    reads = synth.workload_reads("small_1mbp", ref, n=2000)
     ix = oracle.OracleIndex(ref.codes, sa_rate=8)
     a = ix.seed(reads.seq, reads.offsets, method=0)
     for kw in (dict(method=1), dict(method=1, kmer_k=10)):
@@ -296,3 +299,97 @@ def test_algorithm3_equals_definition_small_workload():
         for f in ("read_id", "qbeg", "qend", "k", "kr", "s", "npos", "flags", "pos_off", "pos"):
             assert np.array_equal(getattr(a, f), getattr(b, f)), (kw, f)
     assert len(a) > 2000
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "hand_worked_aca.json")
+
+
+def test_hand_worked_example():
+    """The hand-derived example (R = ACA, T = ACATGT$): suffix array, BWT, C, ds-intervals,
+    positions, LocateSlow through the $ row and SMEM sets, for both oracles."""
+    g = json.load(open(GOLDEN))
+    ox = oracle.OracleIndex(ref_codes(g["R"]), sa_rate=2)
+    assert "".join("$ACGT"[int(x)] for x in ox.text()) == g["T"]
+    assert [int(x) for x in ox.sa()] == g["SA"]
+    assert "".join("$ACGT"[int(x)] for x in ox.bwt()) == g["BWT"]
+    assert ox.primary == g["primary"]
+    C = ox.C()
+    assert [int(C[oracle.SYM[a]]) for a in "ACGT"] == [g["C"][a] for a in "ACGT"]
+    for p, iv in g["intervals"].items():
+        assert ox.interval(p) == tuple(iv), p
+        a = oracle.SYM[p[0]]
+        assert ox.backward(ox.interval(p[1:]), a) == tuple(iv) if len(p) > 1 else True
+    for row, v in g["locate_r2"].items():
+        if not row.startswith("_"):
+            assert ox.locate_slow(int(row)) == v[1]
+    for case in g["smems"]:
+        seq, offs = csr([case["read"]])
+        for method in (0, 1):
+            res = ox.seed(seq, offs, min_len=case["l"], min_occ=case["c"], method=method)
+            got = [[int(res.qbeg[t]), int(res.qend[t]), int(res.k[t]), int(res.kr[t]), int(res.s[t])]
+                   for t in range(len(res))]
+            assert got == case["out"], (case, method)
+            for t in range(len(res)):
+                sub = case["read"][got[t][0]:got[t][1]]
+                if sub in g["positions"]:
+                    ps = res.pos[int(res.pos_off[t]):int(res.pos_off[t]) + int(res.npos[t])]
+                    assert [int(x) for x in ps] == g["positions"][sub]
+
+
+def _same_except_bounds(a, b):
+    """Equal seed sets, occurrence counts, flags and positions (the scan oracle has no lo bounds)."""
+    assert len(a) == len(b)
+    for f in ("read_id", "qbeg", "qend", "s", "npos", "flags", "pos_off"):
+        assert np.array_equal(getattr(a, f), getattr(b, f)), f
+    assert np.array_equal(a.pos, b.pos)
+    assert np.all(a.k == np.uint64(2 ** 64 - 1)) and np.all(a.kr == np.uint64(2 ** 64 - 1))
+
+
+@pytest.mark.parametrize("name", ["random200", "period2", "palindrome", "repeats", "homopolymer", "len2"])
+def test_scan_oracle_equals_definition_tiny(name):
+    """O3 (one scan of T per q-mer set) reproduces O1 on tiny references: c in {1,2,3}, with and
+    without re-seeding, reads with N bases, reads shorter than l."""
+    R = TINY_REFS[name]
+    ox = oracle.OracleIndex(ref_codes(R), sa_rate=3)
+    rng = np.random.default_rng(11)
+    reads = []
+    for _ in range(30):
+        if len(R) < 3:
+            break
+        i = int(rng.integers(0, len(R) - 2))
+        j = int(rng.integers(i + 2, min(len(R), i + 40) + 1))
+        s = list(R[i:j])
+        for t in range(len(s)):
+            if rng.random() < 0.05:
+                s[t] = "ACGTN"[int(rng.integers(0, 5))]
+        s = "".join(s)
+        reads.append(s if rng.random() < 0.5 else brute.revcomp(s.replace("N", "A")))
+    reads += ["ACGTAC", "NNACGN", "A", "", "GATTACAGATTACA"]
+    seq, offs = csr(reads)
+    for l, c in [(3, 1), (4, 2), (2, 3), (5, 1)]:
+        for reseed in (False, True):
+            kw = dict(min_len=l, min_occ=c, max_occ=10 ** 6, reseed=reseed, reseed_len=2 * l, reseed_occ=3)
+            exp = ox.seed(seq, offs, **kw)
+            got = oracle.scan_seed(ref_codes(R), seq, offs, **kw)
+            _same_except_bounds(got, exp)
+
+
+def test_scan_oracle_equals_definition_workload_slice():
+    """O3 reproduces O1 on 150 bp reads over a 300 kbp slice of the 1 Mbp workload (l = 19,
+    re-seeding on, max_occ 500 and a small max_occ) and on bisulfite reads of both roles."""
+    ref = synth.workload_reference("small_1mbp")
+    sub = np.ascontiguousarray(ref.codes[:300_000])
+    ox = oracle.OracleIndex(sub, sa_rate=8)
+    sref = synth.Reference(sub, np.zeros((0, 2), np.uint64), 0, 0)
+    rs = synth.reads_fixed(sref, 400, 150, True, p_sub=0.01, p_indel=0.001, seed=9)
+    for mo in (500, 2):
+        exp = ox.seed(rs.seq, rs.offsets, max_occ=mo)
+        got = oracle.scan_seed(sub, rs.seq, rs.offsets, max_occ=mo)
+        _same_except_bounds(got, exp)
+    bref = synth.reference(0, 60_000, 31)
+    obs = oracle.OracleIndex(bref.codes, bisulfite=True, sa_rate=8)
+    brs = synth.reads_bisulfite(bref, 300, seed=5)
+    for role in (1, 2):
+        exp = obs.seed(brs.seq, brs.offsets, bs_role=role)
+        got = oracle.scan_seed(bref.codes, brs.seq, brs.offsets, bisulfite=True, bs_role=role)
+        _same_except_bounds(got, exp)
