@@ -232,35 +232,40 @@ __global__ void k_emit_rows(const uint64_t *__restrict__ sa, uint64_t M, uint64_
 // ---------------------------------------------------------------------------------------------
 // occurrence lines
 
-// rows of the line at 2 bits, sub-checkpoints (A, C, G in the first 96/192/288 rows), per-line totals
+// the line's six 64-row blocks as bit planes, sub-checkpoints (A, C, G in the first 64 b rows),
+// per-line totals
 __global__ void k_line_counts(const uint8_t *__restrict__ B, uint64_t n, uint64_t n_lines, uint64_t *__restrict__ cnt /*4 x n_lines*/,
                               uint4 *__restrict__ lines) {
   for (uint64_t L = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; L < n_lines; L += (uint64_t)gridDim.x * blockDim.x) {
-    uint64_t c[4] = {0, 0, 0, 0};
+    uint32_t c[4] = {0, 0, 0, 0};
     uint32_t *w32 = (uint32_t *)(lines + L * MBW_LINE_U4);
     uint64_t *w = (uint64_t *)(lines + L * MBW_LINE_U4);
-    for (int q = 0; q < 12; ++q) {
-      if (q % 3 == 0 && q > 0)   // sub-checkpoint after 96 (q/3) rows
-        w32[4 + q / 3 - 1] = (uint32_t)c[0] | ((uint32_t)c[1] << 10) | ((uint32_t)c[2] << 20);
-      uint64_t v = 0;
-      for (int t = 0; t < 32; ++t) {
-        uint64_t row = L * MBW_BPL + q * 32 + t;
-        if (row < n) { uint64_t b = B[row]; v |= b << (2 * t); c[b]++; }
+    for (int b = 0; b < 6; ++b) {
+      if (b > 0) w32[b == 1 ? 3 : 4 + (b - 2)] = c[0] | (c[1] << 9) | (c[2] << 18);
+      uint64_t lo = 0, hi = 0;
+      for (int t = 0; t < MBW_BLK; ++t) {
+        const uint64_t row = L * MBW_BPL + (uint64_t)b * MBW_BLK + t;
+        if (row < n) {
+          const uint32_t v = B[row];
+          lo |= (uint64_t)(v & 1u) << t;
+          hi |= (uint64_t)(v >> 1) << t;
+          c[v]++;
+        }
       }
-      w[4 + q] = v;
+      w[4 + 2 * b] = lo;
+      w[5 + 2 * b] = hi;
     }
-    w32[7] = 0;
     for (int a = 0; a < 4; ++a) cnt[a * n_lines + L] = c[a];
   }
 }
 
-// line header: counts before the line, relative to the start of its superblock
+// line header: counts of A, C, G before the line, relative to the start of its superblock
 __global__ void k_line_headers(const uint64_t *__restrict__ pre /*4 x n_lines exclusive sums*/, uint64_t n_lines,
                                const uint64_t *__restrict__ sbtab, uint4 *__restrict__ lines) {
   for (uint64_t L = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; L < n_lines; L += (uint64_t)gridDim.x * blockDim.x) {
     uint32_t *w = (uint32_t *)(lines + L * MBW_LINE_U4);
     const uint64_t *t = sbtab + 8 * (L >> MBW_SB_SHIFT);
-    for (int a = 0; a < 4; ++a) w[a] = (uint32_t)(pre[a * n_lines + L] - t[a]);
+    for (int a = 0; a < 3; ++a) w[a] = (uint32_t)(pre[a * n_lines + L] - t[a]);
   }
 }
 
@@ -658,7 +663,7 @@ extern "C" int mbw_pos_to_ref(const mbw_index *ix, uint64_t pos, uint32_t len, i
 // ---------------------------------------------------------------------------------------------
 // index files: header (magic, version, fields, FNV-1a of header and of each array) + arrays
 static const uint64_t kMagic = 0x3158444e4957424dull;  // "MBWINDX1"
-static const uint32_t kVersion = 2;
+static const uint32_t kVersion = 3;
 
 struct FileHeader {
   uint64_t magic;

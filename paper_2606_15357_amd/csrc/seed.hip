@@ -235,61 +235,27 @@ __device__ __forceinline__ void wave_close(const SeedParams &P, int lane, const 
 }
 
 // ---------------------------------------------------------------------------------------------
-// Wave-cooperative fetch straight into LDS (global_load_lds, 16 bytes per lane).  A rank needs four
-// of a line's eight slices: the two header slices and the two slices of the 96-row block holding
-// the offset.  Load t of lane L fetches, for lane r = 16 t + (L >> 2), slice number (L - r) & 3 of
-// the list (0, 1, sl, sl + 1) (sl = block slice of lane r's offset) and lands at buf[64 t + L]
-// (the hardware places lane L's 16 bytes at base + 16 L), i.e. at buf[4 r + ((q + r) & 3)] for the
-// q-th slice of the list: 64 bytes per lane, rotated by r to spread the LDS banks.  Four load
-// instructions move the needed half-lines of all 64 lanes; the HBM transfer is still the whole
-// 128-byte line.
-#define WAVE_U4 (64 * 4)
-typedef __attribute__((address_space(3))) void lds_void;
-
-__device__ __forceinline__ void fetch_blocks_lds(const uint4 *__restrict__ lines, uint32_t myL, int mysl, bool myneed,
-                                                 uint4 *buf, int lane) {
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int r = 16 * t + (lane >> 2);
-    const uint32_t Ls = (uint32_t)__shfl((int)myL, r);
-    const int sl = __shfl(mysl, r);
-    const int q = (lane - r) & 3;
-    const int j = q < 2 ? q : sl + (q - 2);
-    if (__shfl((int)myneed, r))
-      __builtin_amdgcn_global_load_lds((const void *)(lines + (uint64_t)Ls * MBW_LINE_U4 + j), (lds_void *)(buf + 64 * t), 16, 0, 0);
-  }
-}
-
-// q-th slice (0: header counts, 1: sub-checkpoints, 2/3: the block) of lane r's fetched line
-__device__ __forceinline__ uint4 lds_q(const uint4 *buf, int r, int q) { return buf[4 * r + ((q + r) & 3)]; }
-
-// (E, G) at offset o of the half-line fetched for this lane
-__device__ __forceinline__ void rank_lds(const uint4 *buf, int lane, int o, int c, const SymMasks &sm, uint64_t sbe, uint64_t sbg,
-                                         uint64_t &E, uint64_t &G) {
-  rank_eg(lds_q(buf, lane, 0), lds_q(buf, lane, 1), lds_q(buf, lane, 2), lds_q(buf, lane, 3), o, c, sm, sbe, sbg, E, G);
-}
-
-// ---------------------------------------------------------------------------------------------
 // SMEM kernel, wave schedule (Algorithm 3 per lane; persistent).
 //
 // Lane states: IDLE (takes a query), REC (the query's record is loaded in this iteration's memory
 // phase), STAGE (the read's packed words are loaded; STAGED only), ACTIVE (one memory action per
 // iteration: a k-mer table lookup or a backward/forward extension), DRAINED.  Stage changes that
-// need no memory are taken before the memory phase.
+// need no memory are taken before the memory phase.  In the memory phase every lane issues all of
+// its loads (the three 16-byte slices of each index line a rank needs, a k-mer entry, a query
+// record or the words of a read being staged) and the wave waits once.
 #define STAGE_WORDS 5   // staged reads of up to 160 bases
+#define SMEM_WAVES 4    // waves per block
 enum { ACT_DONE = 0, ACT_KMER = 1, ACT_BWD = 2, ACT_FWD = 3 };
 enum { ST_IDLE = 0, ST_REC = 1, ST_STAGE = 2, ST_ACTIVE = 3, ST_DRAINED = 4 };
 
 template <bool STAGED>
-__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) k_smem_wave(IndexView ix, SeedParams P, ReadWords R) {
-  __shared__ uint4 lbuf[2][2 * WAVE_U4];                        // per wave: first and second lines
-  __shared__ uint64_t sw[2][STAGED ? STAGE_WORDS * 64 : 1];     // staged bases, word w of lane L at [64 w + L]
-  __shared__ uint32_t sn[2][STAGED ? STAGE_WORDS * 64 : 1];     // staged N bits
+__global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, SeedParams P, ReadWords R) {
+  __shared__ uint64_t sw[SMEM_WAVES][STAGED ? STAGE_WORDS * 64 : 1];   // staged bases, word w of lane L at [64 w + L]
+  __shared__ uint32_t sn[SMEM_WAVES][STAGED ? STAGE_WORDS * 64 : 1];   // staged N bits
   __shared__ uint64_t sbt[MBW_MAX_SB * 8];
   for (int t = threadIdx.x; t < 8 * ix.n_sb; t += blockDim.x) sbt[t] = ix.sbtab[t];
   __syncthreads();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  uint4 *bufA = lbuf[wv], *bufB = lbuf[wv] + WAVE_U4;
   uint64_t *mw = sw[wv];
   uint32_t *mn = sn[wv];
   const int K = (P.use_kmer && ix.kmer) ? ix.K : 0;
@@ -362,14 +328,17 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) k
     const uint64_t x1 = bwd ? k : kr, y = bwd ? kr : k;
     const int cc = bwd ? a : 3 - a;
     const uint64_t x2 = x1 + s;
-    const uint32_t L1 = ext ? line_of(x1) : 0u, L2 = ext ? line_of(x2) : 0u;
+    const uint32_t L1 = line_of(x1), L2 = line_of(x2);
     const int o1 = (int)(x1 - (uint64_t)L1 * MBW_BPL), o2 = (int)(x2 - (uint64_t)L2 * MBW_BPL);
-    const int sl1 = block_slice(o1), sl2 = block_slice(o2);
-    const bool two = ext && L1 != L2;                   // a second index line
-    const bool fetch2 = ext && (two || sl1 != sl2);     // a second half-line (same line, other block)
-    // ---- the memory phase: everything the wave needs, issued together, waited for once
-    if (__ballot(ext)) fetch_blocks_lds(ix.lines, L1, sl1, ext, bufA, lane);
-    if (__ballot(fetch2)) fetch_blocks_lds(ix.lines, L2, sl2, fetch2, bufB, lane);
+    const bool two = ext && L1 != L2;                          // a second index line
+    const bool blk2 = ext && (two || (o1 >> 6) != (o2 >> 6));  // a second block slice
+    // ---- the memory phase: everything the lane needs, issued together, waited for once
+    const uint4 z4 = make_uint4(0, 0, 0, 0);
+    const uint4 *l1p = ix.lines + (uint64_t)L1 * MBW_LINE_U4, *l2p = ix.lines + (uint64_t)L2 * MBW_LINE_U4;
+    uint4 h0a = z4, h1a = z4, ba = z4, h0b = z4, h1b = z4, bb = z4;
+    if (ext) { h0a = l1p[0]; h1a = l1p[1]; ba = l1p[2 + (o1 >> 6)]; }
+    if (two) { h0b = l2p[0]; h1b = l2p[1]; }
+    if (blk2) bb = l2p[2 + (o2 >> 6)];
     uint4 kent = make_uint4(0, 0, 0, 0);
     if (act == ACT_KMER) kent = ix.kmer[code];
     const int st_mem = st;
@@ -398,11 +367,13 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) k
       if (es >= c) { k = ek; kr = ekr; s = es; j -= K; }
     }
     if (ext) {
+      if (!two) { h0b = h0a; h1b = h1a; }
+      if (!blk2) bb = ba;
       const SymMasks sm = sym_masks(cc);
       const uint32_t sb1 = 8 * (L1 >> MBW_SB_SHIFT), sb2 = 8 * (L2 >> MBW_SB_SHIFT);
       uint64_t E1, G1, E2, G2;
-      rank_lds(bufA, lane, o1, cc, sm, sbt[sb1 + cc], sbt[sb1 + 4 + cc], E1, G1);
-      rank_lds(fetch2 ? bufB : bufA, lane, o2, cc, sm, sbt[sb2 + cc], sbt[sb2 + 4 + cc], E2, G2);
+      rank_eg(h0a, h1a, ba, L1, o1, cc, sm, sbt[sb1 + cc], sbt[sb1 + 4 + cc], E1, G1);
+      rank_eg(h0b, h1b, bb, L2, o2, cc, sm, sbt[sb2 + cc], sbt[sb2 + 4 + cc], E2, G2);
       n_lines += two ? 2 : 1;
       ++n_steps;
       uint64_t nx, ny, ns;
@@ -653,12 +624,10 @@ __global__ void __launch_bounds__(256) k_locate_plain(IndexView ix, const mbw_se
 __global__ void __launch_bounds__(256) k_locate_wave(IndexView ix, const uint64_t *__restrict__ X, uint64_t n_pos,
                                                      uint64_t *__restrict__ pos, uint32_t rmask, int rshift,
                                                      unsigned long long *__restrict__ ctl) {
-  __shared__ uint4 lbuf[4 * WAVE_U4];
   __shared__ uint64_t sbt[MBW_MAX_SB * 8];
   for (int t = threadIdx.x; t < 8 * ix.n_sb; t += blockDim.x) sbt[t] = ix.sbtab[t];
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  uint4 *buf = lbuf + (threadIdx.x >> 6) * WAVE_U4;
   enum { W_NONE = 0, W_WALK = 1 };
   enum { P_NONE = 0, P_PENDING = 1, P_READY = 2 };
   int cur = W_NONE, pre = P_NONE;
@@ -681,10 +650,15 @@ __global__ void __launch_bounds__(256) k_locate_wave(IndexView ix, const uint64_
         x = 0; ++steps;
       } else need = true;
     }
-    const uint32_t L = need ? line_of(x) : 0u;
+    const uint32_t L = line_of(x);
     const int o = (int)(x - (uint64_t)L * MBW_BPL);
     // ---- memory phase
-    if (__ballot(need)) fetch_blocks_lds(ix.lines, L, block_slice(o), need, buf, lane);
+    const uint4 z4 = make_uint4(0, 0, 0, 0);
+    uint4 h0 = z4, h1 = z4, blk = z4;
+    if (need) {
+      const uint4 *lp = ix.lines + (uint64_t)L * MBW_LINE_U4;
+      h0 = lp[0]; h1 = lp[1]; blk = lp[2 + (o >> 6)];
+    }
     uint64_t sv = 0;
     if (fin) sv = ix.ssa[sample_index(x, ix.r, rshift)];
     const bool ld = pre == P_PENDING;
@@ -700,11 +674,10 @@ __global__ void __launch_bounds__(256) k_locate_wave(IndexView ix, const uint64_
       cur = W_NONE;
     }
     if (need) {
-      const uint4 sa = lds_q(buf, lane, 2), sbk = lds_q(buf, lane, 3);
-      const int b = bwt_from_block(sa, sbk, o);
+      const int b = bwt_from_block(blk, o);
       const uint32_t sbi = 8 * (L >> MBW_SB_SHIFT);
       uint64_t E, G;
-      rank_eg(lds_q(buf, lane, 0), lds_q(buf, lane, 1), sa, sbk, o, b, sym_masks(b), sbt[sbi + b], sbt[sbi + 4 + b], E, G);
+      rank_eg(h0, h1, blk, L, o, b, sym_masks(b), sbt[sbi + b], sbt[sbi + 4 + b], E, G);
       if (b == 0 && x > ix.primary) E -= 1;
       x = sel4(ix.Cb[0], ix.Cb[1], ix.Cb[2], ix.Cb[3], b) + E;
       ++steps; ++lines; ++lf;
@@ -827,11 +800,11 @@ static int launch_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const Read
   if (o.kernel == MBW_KERNEL_PLAIN) {
     k_smem_plain<<<grid_for(P.n_queries, 256), 256, 0, st>>>(v, P);
   } else if (staged) {
-    const int grid = persistent_grid((const void *)k_smem_wave<true>, 128, 0, c->n_cu, o.blocks_per_cu);
-    k_smem_wave<true><<<grid, 128, 0, st>>>(v, P, R);
+    const int grid = persistent_grid((const void *)k_smem_wave<true>, 64 * SMEM_WAVES, 0, c->n_cu, o.blocks_per_cu);
+    k_smem_wave<true><<<grid, 64 * SMEM_WAVES, 0, st>>>(v, P, R);
   } else {
-    const int grid = persistent_grid((const void *)k_smem_wave<false>, 128, 0, c->n_cu, o.blocks_per_cu);
-    k_smem_wave<false><<<grid, 128, 0, st>>>(v, P, R);
+    const int grid = persistent_grid((const void *)k_smem_wave<false>, 64 * SMEM_WAVES, 0, c->n_cu, o.blocks_per_cu);
+    k_smem_wave<false><<<grid, 64 * SMEM_WAVES, 0, st>>>(v, P, R);
   }
   TRY(hipGetLastError());
   return 0;

@@ -66,11 +66,13 @@ def read_index_file(path):
 
 
 def decode_bwt(idx):
-    """BWT codes (0..3, $ row as A) from the occurrence lines."""
+    """BWT codes (0..3, $ row as A) from the occurrence lines: six 64-row blocks per line, each a
+    u64 of low code bits followed by a u64 of high code bits."""
     lines = idx["lines"]
-    bits = lines[:, 4:16]
-    sh = (np.arange(32, dtype=np.uint64) * 2)
-    syms = ((bits[:, :, None] >> sh[None, None, :]) & 3).reshape(lines.shape[0], -1)
+    lo = lines[:, 4:16:2]
+    hi = lines[:, 5:16:2]
+    sh = np.arange(64, dtype=np.uint64)
+    syms = ((lo[:, :, None] >> sh) & 1) | (((hi[:, :, None] >> sh) & 1) << 1)
     return syms.reshape(-1)[: idx["n"]].astype(np.uint8)
 
 

@@ -67,20 +67,20 @@ def test_index_structure(name, r, K):
     assert [int(x) for x in info["C"]] == [int(x) for x in ox.C()[:5]]
     SA = ox.sa()
     assert np.array_equal(f["ssa"], SA[::r])
-    # line headers: superblock base + u32 count = count of each base before the line ($ row as A);
-    # sub-checkpoints: counts of A, C, G in the line's first 96, 192, 288 rows
+    # line headers: superblock base + u32 count = count of A, C, G before the line ($ row as A);
+    # sub-checkpoint b (1..5): counts of A, C, G in the line's first 64 b rows, 9 bits each
     Braw = B.astype(np.int64)
     w32 = f["lines"].view(np.uint32).reshape(f["n_lines"], 32)
     for L in range(f["n_lines"]):
         lo = L * 384
-        for a in range(4):
+        for a in range(3):
             assert int(f["sb"][L >> 23][a]) + int(w32[L, a]) == int(np.sum(Braw[:lo] == a))
-        for b in (1, 2, 3):
-            blk = Braw[lo:min(lo + 96 * b, f["n"])]
-            if lo + 96 * b > f["n"]:
+        for b in range(1, 6):
+            if lo + 64 * b > f["n"]:
                 continue
-            sub = int(w32[L, 3 + b])
-            assert [(sub >> (10 * a)) & 1023 for a in range(3)] == [int(np.sum(blk == a)) for a in range(3)]
+            blk = Braw[lo:lo + 64 * b]
+            sub = int(w32[L, 3 if b == 1 else 4 + (b - 2)])
+            assert [(sub >> (9 * a)) & 511 for a in range(3)] == [int(np.sum(blk == a)) for a in range(3)]
     if K:
         T = brute.text_of(R)
         for code in range(4 ** K):
