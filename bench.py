@@ -98,6 +98,8 @@ def main():
     ap.add_argument("--cpu-pairs", type=int, default=250_000)
     ap.add_argument("--cpu-window", type=int, default=16_000_000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--isa-sample", type=int, default=4, help="inverse-SA sampling step (0 = no unique-match path)")
+    ap.add_argument("--no-unique", action="store_true", help="extend unique matches base by base")
     ap.add_argument("--probe", action="store_true", help="only run the copy and random-gather probes")
     args = ap.parse_args()
 
@@ -115,16 +117,16 @@ def main():
     torch.cuda.set_device(dev)
     if args.probe:
         ms = mbw.probe_copy(1 << 30)
-        lps, gms = mbw.probe_gather(16 << 30)
+        lps, gms = mbw.probe_gather(8 << 30, iters=32)
         print(json.dumps(dict(copy_bytes=1 << 30, copy_ms=round(ms, 3), copy_gbs=round(2 * (1 << 30) / ms / 1e6, 1),
                               gather_lines_per_s=lps, gather_gbs_128=round(lps * 128 / 1e9, 1), gather_ms=round(gms, 3))))
         return
-    gather_lps, _ = mbw.probe_gather(16 << 30)
+    gather_lps, _ = mbw.probe_gather(8 << 30, iters=32)
     t0 = time.time()
     ref = synth.workload_reference("human_3gbp", args.ref_len)
     log(f"reference {len(ref)} bases generated in {time.time() - t0:.1f} s")
     t0 = time.time()
-    idx = mbw.Index.build(ref.codes, sa_sample=args.sa_sample, kmer_k=args.kmer)
+    idx = mbw.Index.build(ref.codes, sa_sample=args.sa_sample, kmer_k=args.kmer, isa_sample=args.isa_sample)
     info = idx.info()
     log(f"index built on the GPU in {time.time() - t0:.1f} s: n={info['n']} lines={info['n_lines']} "
         f"resident={info['bytes_resident'] / 1e9:.2f} GB")
@@ -140,7 +142,7 @@ def main():
 
     def step(kernel):
         return ctx.seed(dseq, dlen, min_seed_len=19, max_occ=500, kernel=kernel,
-                        stream=stream)
+                        unique_ext=not args.no_unique, stream=stream)
 
     for _ in range(args.warmup):
         out = step(mbw.KERNEL_COOP)
@@ -190,7 +192,7 @@ def main():
                                 lines_per_read=round(lines_loc / n_reads, 1)),
                     whole_path=round((lines_smem + lines_loc) * LINE_BYTES / (elapsed / args.steps) / 1e9, 1),
                     random_line_ceiling=dict(lines_per_s=round(gather_lps), gbs=round(gather_lps * LINE_BYTES / 1e9, 1),
-                                             probe="8 lanes x 16 B per random 128-B line, 16 GiB buffer"),
+                                             probe="one lane x 16 B per random 128-B line, 4 dependent chains per lane, 8 GiB buffer"),
                     frac_of_measured_ceiling=round(lines_smem / (ms_smem * 1e-3) / gather_lps, 3))
 
     cpu = None
@@ -208,6 +210,7 @@ def main():
                                      f"{args.pairs} paired 150 bp reads ({n_reads} reads), 0.5% error, 5% from "
                                      f"satellites; (19,1)-SMEMs + re-seeding, max_occ 500",
                             min_seed_len=19, max_occ=500, sa_sample=args.sa_sample, kmer_k=args.kmer,
+                            isa_sample=args.isa_sample, unique_ext=not args.no_unique,
                             bases_per_line=384, line_bytes=LINE_BYTES, index_gb=round(info["bytes_resident"] / 1e9, 2)),
                 plain_gpu=plain, roofline=roofline, cpu_baseline=cpu)
     print(json.dumps(line), flush=True)

@@ -47,6 +47,10 @@ typedef struct {
   uint64_t rng_seed;    /* ambiguous (non-ACGT) reference bases become random bases drawn from
                            SplitMix64 seeded with this value (Section 2.1)                       */
   int device;           /* HIP device ordinal that will hold the index                          */
+  int isa_sample;       /* 0: none.  q >= 1: also keep the packed text T (2 bits per symbol) and the
+                           inverse suffix array at text positions that are multiples of q (1..64),
+                           which let the seeding kernels extend a match that occurs once by
+                           comparing it with the text (same results, fewer index accesses).      */
 } mbw_build_opts;
 
 /* Build the index of `ref` (host pointer, `len` bases, 1 <= len < 2^38) on the GPU and keep it
@@ -78,16 +82,17 @@ typedef struct {
   int kmer_k;
   int bisulfite;
   int device;
+  int isa_sample;          /* 0 when the index holds no text / inverse-SA samples */
 } mbw_index_info_t;
 
 int mbw_index_info(const mbw_index *idx, mbw_index_info_t *out);
 
 /* Device pointers to the resident arrays (read-only views for tests and tools):
- * lines: n_lines x 128 B; each line = u32 counts of A,C,G,T in B from the start of its superblock
- *        (2^23 lines) to the line (the $ row counted as A), three u32 sub-checkpoints (A, C, G
- *        counts in 10-bit fields for the line's first 96/192/288 rows), one unused u32, then the
- *        line's 384 rows of B at 2 bits (row t in u64 word 4 + t/32, bits 2*(t%32)..+1; the $ row
- *        holds A).
+ * lines: n_lines x 128 B; each line = u32 counts of A, C, G in B from the start of its superblock
+ *        (2^23 lines) to the line (the $ row counted as A), five u32 sub-checkpoints (counts of A,
+ *        C, G in the line's first 64, 128, 192, 256, 320 rows, 9 bits each at bits 0, 9, 18),
+ *        then the line's six 64-row blocks, each a u64 of the low code bits and a u64 of the high
+ *        code bits (row t of the block at bit t; the $ row holds A).
  * ssa:   ceil(n/r) x u64, ssa[x/r] = S(x).
  * kmer:  4^k x 16 B packed (k:40 | k':40 | s:40 bits, little-endian), code = sum P[q]*4^q. */
 int mbw_index_device_arrays(const mbw_index *idx, const void **lines, const void **ssa, const void **kmer);
@@ -115,6 +120,9 @@ typedef struct {
   int use_kmer;       /* use the index's k-mer table (wave kernels) */
   int blocks_per_cu;  /* persistent grid size per compute unit (0 = occupancy limit) */
   int no_stage;       /* 1: do not stage reads of <= 160 bases in LDS */
+  int unique_ext;     /* 1: when the index holds the text and inverse-SA samples, a forward
+                         extension whose interval has s = 1 continues by comparing the read with
+                         the text at the match's single position (wave kernels; same results) */
 } mbw_seed_opts;
 
 
@@ -174,8 +182,9 @@ int mbw_pos_to_ref(const mbw_index *idx, uint64_t pos, uint32_t len, int *strand
 /* ---- diagnostics (not part of the seeding path) ----------------------------------------------
  * mbw_probe_copy: streams `bytes` bytes (>= 4096) from one buffer to another once; *ms = kernel time.
  *   Used to calibrate profiler byte counters against a known transfer.
- * mbw_probe_gather: eight lanes fetch one random 128-byte line of a `bytes`-byte buffer (>= 1 MiB),
- *   `iters` dependent fetches per lane group; *lines_per_s = random lines served per second.
+ * mbw_probe_gather: every lane follows four chains of random 128-byte lines (16 bytes read per line)
+ *   over the largest power-of-two number of lines that fits in `bytes` (>= 1 MiB), `iters` dependent
+ *   fetches per chain; *lines_per_s = random lines served per second.
  * Both allocate and free their own device memory.  Errors: MBW_E_INVAL, MBW_E_NOMEM, MBW_E_HIP. */
 int mbw_probe_copy(int device, uint64_t bytes, float *ms);
 int mbw_probe_gather(int device, uint64_t bytes, int iters, double *lines_per_s, float *ms);

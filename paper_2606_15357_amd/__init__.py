@@ -45,20 +45,20 @@ class MbwError(RuntimeError):
 
 class BuildOpts(C.Structure):
     _fields_ = [("sa_sample", C.c_int), ("kmer_k", C.c_int), ("bisulfite", C.c_int), ("ref_is_codes", C.c_int),
-                ("rng_seed", C.c_uint64), ("device", C.c_int)]
+                ("rng_seed", C.c_uint64), ("device", C.c_int), ("isa_sample", C.c_int)]
 
 
 class IndexInfo(C.Structure):
     _fields_ = [("n", C.c_uint64), ("len_r", C.c_uint64), ("primary", C.c_uint64), ("n_lines", C.c_uint64),
                 ("bytes_resident", C.c_uint64), ("C", C.c_uint64 * 5), ("bases_per_line", C.c_int),
                 ("line_bytes", C.c_int), ("sa_sample", C.c_int), ("kmer_k", C.c_int), ("bisulfite", C.c_int),
-                ("device", C.c_int)]
+                ("device", C.c_int), ("isa_sample", C.c_int)]
 
 
 class SeedOpts(C.Structure):
     _fields_ = [("min_occ", C.c_int), ("reseed", C.c_int), ("reseed_len", C.c_int), ("reseed_occ", C.c_int),
                 ("bs_role", C.c_int), ("kernel", C.c_int), ("use_kmer", C.c_int), ("blocks_per_cu", C.c_int),
-                ("no_stage", C.c_int)]
+                ("no_stage", C.c_int), ("unique_ext", C.c_int)]
 
 
 class Result(C.Structure):
@@ -146,8 +146,9 @@ class Index:
 
     @classmethod
     def build(cls, ref, sa_sample: int = 8, kmer_k: int = 10, bisulfite: bool = False, device: int = 0,
-              rng_seed: int = 0):
-        """``ref``: numpy uint8 codes 0..3 or ASCII bytes / str."""
+              rng_seed: int = 0, isa_sample: int = 4):
+        """``ref``: numpy uint8 codes 0..3 or ASCII bytes / str.  ``isa_sample`` > 0 also keeps the
+        packed text and inverse-SA samples for direct extension of unique matches."""
         L = load_library()
         if isinstance(ref, str):
             ref = ref.encode()
@@ -157,7 +158,8 @@ class Index:
         else:
             arr = np.ascontiguousarray(ref, dtype=np.uint8)
             codes = 1
-        o = BuildOpts(int(sa_sample), int(kmer_k), int(bool(bisulfite)), codes, int(rng_seed), int(device))
+        o = BuildOpts(int(sa_sample), int(kmer_k), int(bool(bisulfite)), codes, int(rng_seed), int(device),
+                      int(isa_sample))
         h = C.c_void_p()
         _check(L.mbw_index_build(arr.ctypes.data if arr.size else None, arr.size, C.byref(o), C.byref(h)))
         return cls(h)
@@ -241,7 +243,7 @@ class Context:
     def seed(self, reads, lengths, min_seed_len: int = 19, max_occ: int = 500, min_occ: int = 1,
              reseed: bool = True, reseed_len: int = 38, reseed_occ: int = 10, bs_role: int = 0,
              kernel: int = KERNEL_COOP, use_kmer: bool = True, blocks_per_cu: int = 0, stage: bool = True,
-             stream=None) -> SeedOutput:
+             unique_ext: bool = True, stream=None) -> SeedOutput:
         """``reads``: concatenated ASCII (numpy uint8 on the host or a torch uint8 CUDA tensor);
         ``lengths``: uint32 per read (numpy or torch)."""
         n = int(lengths.numel() if hasattr(lengths, "numel") else len(lengths))
@@ -250,7 +252,7 @@ class Context:
         if isinstance(reads, np.ndarray):
             reads = np.ascontiguousarray(reads, dtype=np.uint8)
         o = SeedOpts(int(min_occ), int(bool(reseed)), int(reseed_len), int(reseed_occ), int(bs_role), int(kernel),
-                     int(bool(use_kmer)), int(blocks_per_cu), int(not stage))
+                     int(bool(use_kmer)), int(blocks_per_cu), int(not stage), int(bool(unique_ext)))
         res = Result()
         rp = _ptr(reads) if n else None
         lp = _ptr(lengths) if n else None
@@ -280,7 +282,8 @@ def probe_copy(nbytes: int = 1 << 30, device: int = 0) -> float:
 
 
 def probe_gather(nbytes: int = 16 << 30, iters: int = 64, device: int = 0):
-    """Random 128-byte lines served per second over an `nbytes` buffer (eight lanes per line)."""
+    """Random 128-byte lines served per second over a power-of-two buffer of at most `nbytes` (one
+    lane per line, four dependent chains per lane)."""
     L = load_library()
     lps, ms = C.c_double(), C.c_float()
     _check(L.mbw_probe_gather(int(device), int(nbytes), int(iters), C.byref(lps), C.byref(ms)))

@@ -218,7 +218,8 @@ __global__ void k_apply_groups(uint32_t *__restrict__ grp, const uint32_t *__res
 
 // B rows and SA samples of a finished chunk
 __global__ void k_emit_rows(const uint64_t *__restrict__ sa, uint64_t M, uint64_t base, const uint64_t *__restrict__ Tw,
-                            uint32_t r, uint8_t *__restrict__ B, uint64_t *__restrict__ ssa, unsigned long long *__restrict__ primary) {
+                            uint32_t r, uint8_t *__restrict__ B, uint64_t *__restrict__ ssa, unsigned long long *__restrict__ primary,
+                            uint32_t ri, uint64_t *__restrict__ isa) {
   for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < M; x += (uint64_t)gridDim.x * blockDim.x) {
     uint64_t p = sa[x], row = base + x;
     uint8_t b = 0;
@@ -226,6 +227,7 @@ __global__ void k_emit_rows(const uint64_t *__restrict__ sa, uint64_t M, uint64_
     else b = (uint8_t)text_sym(Tw, p - 1);
     B[row] = b;
     if (row % r == 0) ssa[row / r] = p;
+    if (isa && p % ri == 0) isa[p / ri] = row;   // inverse SA at sampled text positions
   }
 }
 
@@ -285,7 +287,7 @@ __global__ void k_kmer_level(IndexView ix, const Iv *__restrict__ prev, uint64_t
       uint64_t E1, G1, E2, G2;
       rank_global(ix, p.k, a, E1, G1);
       rank_global(ix, p.k + p.s, a, E2, G2);
-      ext_update(E1, G1, E2, G2, a, p.k, p.s, p.kr, ix.primary, ix.Cb, o.k, o.kr, o.s);
+      ext_update(E1, G1, E2, G2, a, p.k, p.s, p.kr, ix.primary, sel4(ix.Cb[0], ix.Cb[1], ix.Cb[2], ix.Cb[3], a), o.k, o.kr, o.s);
     }
     next[e] = o;
   }
@@ -411,6 +413,8 @@ extern "C" void mbw_index_free(mbw_index *ix) {
   if (ix->ssa) (void)hipFree(ix->ssa);
   if (ix->kmer) (void)hipFree(ix->kmer);
   if (ix->sbtab) (void)hipFree(ix->sbtab);
+  if (ix->text) (void)hipFree(ix->text);
+  if (ix->isa) (void)hipFree(ix->isa);
   (void)hipSetDevice(cur);
   delete ix;
 }
@@ -499,6 +503,7 @@ extern "C" int mbw_index_build(const uint8_t *ref, uint64_t len, const mbw_build
   if (!ref || !opts || len == 0 || len >= (1ull << 38)) { mbw_set_error("bad reference or options"); return MBW_E_INVAL; }
   if (opts->sa_sample < 1 || opts->sa_sample > 1024) { mbw_set_error("sa_sample must be in [1,1024]"); return MBW_E_INVAL; }
   if (opts->kmer_k < 0 || opts->kmer_k > 13) { mbw_set_error("kmer_k must be in [0,13]"); return MBW_E_INVAL; }
+  if (opts->isa_sample < 0 || opts->isa_sample > 64) { mbw_set_error("isa_sample must be in [0,64]"); return MBW_E_INVAL; }
   TRY(hipSetDevice(opts->device));
   // host: codes, ambiguous bases -> random (counter-based SplitMix64), bisulfite conversion
   uint64_t lrp = opts->bisulfite ? 2 * len : len;
@@ -536,12 +541,13 @@ extern "C" int mbw_index_build(const uint8_t *ref, uint64_t len, const mbw_build
   ix->bisulfite = opts->bisulfite ? 1 : 0;
   ix->sa_sample = opts->sa_sample;
   ix->kmer_k = opts->kmer_k;
+  ix->isa_sample = opts->isa_sample;
   uint64_t m = 2 * lrp, n = m + 1;
   ix->n = n;
   hipStream_t st;
   if (hipStreamCreate(&st) != hipSuccess) { delete ix; mbw_set_error("hipStreamCreate failed"); return MBW_E_HIP; }
   int rc = [&]() -> int {
-    uint64_t nwords = (m + 31) / 32 + 2;
+    uint64_t nwords = (m + 31) / 32 + 4;   // slack: 32-byte text windows read past the last symbol
     DevBuf<uint64_t> Tw;
     TRY(Tw.alloc(nwords));
     {
@@ -568,6 +574,11 @@ extern "C" int mbw_index_build(const uint8_t *ref, uint64_t len, const mbw_build
     ix->n_ssa = (n + ix->sa_sample - 1) / ix->sa_sample;
     TRY(hipMalloc((void **)&ix->ssa, ix->n_ssa * sizeof(uint64_t)));
     ix->bytes += ix->n_ssa * sizeof(uint64_t);
+    if (ix->isa_sample) {
+      ix->n_isa = (n - 1) / ix->isa_sample + 1;   // text positions 0, q, 2q, ... <= n - 1
+      TRY(hipMalloc((void **)&ix->isa, ix->n_isa * sizeof(uint64_t)));
+      ix->bytes += ix->n_isa * sizeof(uint64_t);
+    }
     // chunk capacity from free memory (about 100 bytes per suffix in flight)
     size_t fr = 0, tot = 0;
     TRY(hipMemGetInfo(&fr, &tot));
@@ -600,7 +611,8 @@ extern "C" int mbw_index_build(const uint8_t *ref, uint64_t len, const mbw_build
                          u_gid.p, iota0.p, iota1.p, nk1.p, gid1.p, gseed.p, gscan.p, tmp_sa.p, tmp_nk.p, dcount.p,
                          tmp, st, &sa);
       if (r) return r;
-      k_emit_rows<<<grid_for(M), 256, 0, st>>>(sa, M, base, Tw.p, (uint32_t)ix->sa_sample, B.p, ix->ssa, dprim.p);
+      k_emit_rows<<<grid_for(M), 256, 0, st>>>(sa, M, base, Tw.p, (uint32_t)ix->sa_sample, B.p, ix->ssa, dprim.p,
+                                               (uint32_t)std::max(1, ix->isa_sample), ix->isa);
       TRY(hipGetLastError());
       base += M;
       b = e;
@@ -617,6 +629,11 @@ extern "C" int mbw_index_build(const uint8_t *ref, uint64_t len, const mbw_build
     int r = build_lines(ix, B.p, st);
     if (r) return r;
     B.release();
+    if (ix->isa_sample) {   // the packed text stays resident for direct extension of unique matches
+      ix->n_text = Tw.n;
+      ix->text = Tw.detach();
+      ix->bytes += ix->n_text * sizeof(uint64_t);
+    }
     r = build_kmer_table(ix, st);
     if (r) return r;
     TRY(hipStreamSynchronize(st));
@@ -635,6 +652,7 @@ extern "C" int mbw_index_info(const mbw_index *ix, mbw_index_info_t *o) {
   for (int a = 0; a < 5; ++a) o->C[a] = ix->C[a];
   o->bases_per_line = MBW_BPL; o->line_bytes = MBW_LINE_BYTES; o->sa_sample = ix->sa_sample;
   o->kmer_k = ix->kmer_k; o->bisulfite = ix->bisulfite; o->device = ix->device;
+  o->isa_sample = ix->isa_sample;
   return MBW_OK;
 }
 
@@ -663,7 +681,7 @@ extern "C" int mbw_pos_to_ref(const mbw_index *ix, uint64_t pos, uint32_t len, i
 // ---------------------------------------------------------------------------------------------
 // index files: header (magic, version, fields, FNV-1a of header and of each array) + arrays
 static const uint64_t kMagic = 0x3158444e4957424dull;  // "MBWINDX1"
-static const uint32_t kVersion = 3;
+static const uint32_t kVersion = 4;
 
 struct FileHeader {
   uint64_t magic;
@@ -672,7 +690,9 @@ struct FileHeader {
   uint64_t C[5];
   int32_t sa_sample, kmer_k, bisulfite, n_sb;
   uint64_t sb[MBW_MAX_SB * 8];
-  uint64_t sum_lines, sum_ssa, sum_kmer;
+  int32_t isa_sample, pad;
+  uint64_t n_text, n_isa;
+  uint64_t sum_lines, sum_ssa, sum_kmer, sum_text, sum_isa;
   uint64_t sum_header;
 };
 
@@ -695,10 +715,13 @@ extern "C" int mbw_index_save(const mbw_index *ix, const char *path) {
   if (!ix || !path) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
   TRY(hipSetDevice(ix->device));
   uint64_t kb = ix->kmer ? (1ull << (2 * ix->kmer_k)) * 16 : 0;
-  std::vector<uint8_t> lines(ix->n_lines * MBW_LINE_BYTES), ssa(ix->n_ssa * 8), kmer(kb);
+  std::vector<uint8_t> lines(ix->n_lines * MBW_LINE_BYTES), ssa(ix->n_ssa * 8), kmer(kb), text(ix->n_text * 8),
+      isa(ix->n_isa * 8);
   TRY(hipMemcpy(lines.data(), ix->lines, lines.size(), hipMemcpyDeviceToHost));
   TRY(hipMemcpy(ssa.data(), ix->ssa, ssa.size(), hipMemcpyDeviceToHost));
   if (kb) TRY(hipMemcpy(kmer.data(), ix->kmer, kb, hipMemcpyDeviceToHost));
+  if (text.size()) TRY(hipMemcpy(text.data(), ix->text, text.size(), hipMemcpyDeviceToHost));
+  if (isa.size()) TRY(hipMemcpy(isa.data(), ix->isa, isa.size(), hipMemcpyDeviceToHost));
   FileHeader hd;
   memset(&hd, 0, sizeof(hd));
   hd.magic = kMagic; hd.version = kVersion; hd.bpl = MBW_BPL;
@@ -707,14 +730,18 @@ extern "C" int mbw_index_save(const mbw_index *ix, const char *path) {
   hd.sa_sample = ix->sa_sample; hd.kmer_k = ix->kmer ? ix->kmer_k : 0; hd.bisulfite = ix->bisulfite;
   hd.n_sb = ix->n_sb;
   memcpy(hd.sb, ix->sb_host, sizeof(hd.sb));
+  hd.isa_sample = ix->isa_sample; hd.n_text = ix->n_text; hd.n_isa = ix->n_isa;
   hd.sum_lines = sum_words(lines.data(), lines.size());
   hd.sum_ssa = sum_words(ssa.data(), ssa.size());
   hd.sum_kmer = sum_words(kmer.data(), kmer.size());
+  hd.sum_text = sum_words(text.data(), text.size());
+  hd.sum_isa = sum_words(isa.data(), isa.size());
   hd.sum_header = fnv(&hd, offsetof(FileHeader, sum_header));
   FILE *f = fopen(path, "wb");
   if (!f) { mbw_set_error(std::string("cannot open ") + path); return MBW_E_IO; }
   bool ok = fwrite(&hd, sizeof(hd), 1, f) == 1 && fwrite(lines.data(), 1, lines.size(), f) == lines.size() &&
-            fwrite(ssa.data(), 1, ssa.size(), f) == ssa.size() && (kb == 0 || fwrite(kmer.data(), 1, kb, f) == kb);
+            fwrite(ssa.data(), 1, ssa.size(), f) == ssa.size() && (kb == 0 || fwrite(kmer.data(), 1, kb, f) == kb) &&
+            fwrite(text.data(), 1, text.size(), f) == text.size() && fwrite(isa.data(), 1, isa.size(), f) == isa.size();
   ok = (fclose(f) == 0) && ok;
   if (!ok) { mbw_set_error(std::string("write failed: ") + path); return MBW_E_IO; }
   return MBW_OK;
@@ -730,19 +757,26 @@ extern "C" int mbw_index_load(const char *path, int device, mbw_index **out) {
   if (hd.magic != kMagic || hd.version != kVersion || hd.bpl != MBW_BPL ||
       hd.sum_header != fnv(&hd, offsetof(FileHeader, sum_header)) || hd.n_lines != hd.n / MBW_BPL + 1 ||
       hd.sa_sample < 1 || hd.sa_sample > 1024 || hd.n_ssa != (hd.n + hd.sa_sample - 1) / hd.sa_sample ||
-      hd.kmer_k < 0 || hd.kmer_k > 13 || hd.n_sb != (int)(((hd.n_lines - 1) >> MBW_SB_SHIFT) + 1)) {
+      hd.kmer_k < 0 || hd.kmer_k > 13 || hd.n_sb != (int)(((hd.n_lines - 1) >> MBW_SB_SHIFT) + 1) ||
+      hd.isa_sample < 0 || hd.isa_sample > 64 ||
+      (hd.isa_sample ? (hd.n_isa != (hd.n - 1) / hd.isa_sample + 1 || hd.n_text != (hd.n - 1 + 31) / 32 + 4)
+                     : (hd.n_isa != 0 || hd.n_text != 0))) {
     fclose(f); mbw_set_error("bad magic, version or header fields"); return MBW_E_FORMAT;
   }
   uint64_t kb = hd.kmer_k ? (1ull << (2 * hd.kmer_k)) * 16 : 0;
-  std::vector<uint8_t> lines, ssa, kmer;
-  try { lines.resize(hd.n_lines * MBW_LINE_BYTES); ssa.resize(hd.n_ssa * 8); kmer.resize(kb); }
-  catch (...) { fclose(f); mbw_set_error("host allocation failed"); return MBW_E_NOMEM; }
+  std::vector<uint8_t> lines, ssa, kmer, text, isa;
+  try {
+    lines.resize(hd.n_lines * MBW_LINE_BYTES); ssa.resize(hd.n_ssa * 8); kmer.resize(kb);
+    text.resize(hd.n_text * 8); isa.resize(hd.n_isa * 8);
+  } catch (...) { fclose(f); mbw_set_error("host allocation failed"); return MBW_E_NOMEM; }
   bool ok = fread(lines.data(), 1, lines.size(), f) == lines.size() && fread(ssa.data(), 1, ssa.size(), f) == ssa.size() &&
-            (kb == 0 || fread(kmer.data(), 1, kb, f) == kb);
+            (kb == 0 || fread(kmer.data(), 1, kb, f) == kb) && fread(text.data(), 1, text.size(), f) == text.size() &&
+            fread(isa.data(), 1, isa.size(), f) == isa.size();
   fclose(f);
   if (!ok) { mbw_set_error("truncated index file"); return MBW_E_FORMAT; }
   if (sum_words(lines.data(), lines.size()) != hd.sum_lines || sum_words(ssa.data(), ssa.size()) != hd.sum_ssa ||
-      sum_words(kmer.data(), kmer.size()) != hd.sum_kmer) {
+      sum_words(kmer.data(), kmer.size()) != hd.sum_kmer || sum_words(text.data(), text.size()) != hd.sum_text ||
+      sum_words(isa.data(), isa.size()) != hd.sum_isa) {
     mbw_set_error("index checksum mismatch"); return MBW_E_FORMAT;
   }
   TRY(hipSetDevice(device));
@@ -753,6 +787,7 @@ extern "C" int mbw_index_load(const char *path, int device, mbw_index **out) {
   ix->sa_sample = hd.sa_sample; ix->kmer_k = hd.kmer_k; ix->bisulfite = hd.bisulfite;
   ix->n_sb = hd.n_sb;
   memcpy(ix->sb_host, hd.sb, sizeof(hd.sb));
+  ix->isa_sample = hd.isa_sample; ix->n_text = hd.n_text; ix->n_isa = hd.n_isa;
   int rc = [&]() -> int {
     TRY(hipMalloc((void **)&ix->sbtab, sizeof(hd.sb)));
     TRY(hipMemcpy(ix->sbtab, hd.sb, sizeof(hd.sb), hipMemcpyHostToDevice));
@@ -764,7 +799,13 @@ extern "C" int mbw_index_load(const char *path, int device, mbw_index **out) {
       TRY(hipMalloc((void **)&ix->kmer, kb));
       TRY(hipMemcpy(ix->kmer, kmer.data(), kb, hipMemcpyHostToDevice));
     }
-    ix->bytes = lines.size() + ssa.size() + kb + sizeof(hd.sb);
+    if (text.size()) {
+      TRY(hipMalloc((void **)&ix->text, text.size()));
+      TRY(hipMemcpy(ix->text, text.data(), text.size(), hipMemcpyHostToDevice));
+      TRY(hipMalloc((void **)&ix->isa, isa.size()));
+      TRY(hipMemcpy(ix->isa, isa.data(), isa.size(), hipMemcpyHostToDevice));
+    }
+    ix->bytes = lines.size() + ssa.size() + kb + sizeof(hd.sb) + text.size() + isa.size();
     return 0;
   }();
   if (rc) { mbw_index_free(ix); return rc; }

@@ -17,6 +17,9 @@
 //     sums (for the k' update of backward extension).
 //   * sampled SA: ssa[x / r] = S(x) for rows x that are multiples of r.
 //   * k-mer table: 4^K packed ds-intervals (16 bytes); the code of P[0..K) is sum_q P[q] 4^q.
+//   * optional: the text T without its $ (2 bits per symbol, 32 per u64, first symbol in the low
+//     bits) and the inverse suffix array at text positions that are multiples of q,
+//     isa[t / q] = the row whose suffix starts at t.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -41,6 +44,10 @@ struct mbw_index {
   uint64_t *ssa;               // n_ssa
   uint4 *kmer;                 // 4^K (or nullptr)
   uint64_t *sbtab;             // n_sb * 8: counts of A,C,G,T before the superblock, then sums of d > c
+  int isa_sample;              // 0: no text / inverse-SA samples
+  uint64_t n_text, n_isa;      // u64 words of the packed text, inverse-SA samples
+  uint64_t *text;
+  uint64_t *isa;
   uint64_t bytes;
 };
 
@@ -55,6 +62,9 @@ struct IndexView {
   uint32_t r;
   int K;
   int n_sb;
+  const uint64_t *__restrict__ text;   // packed T without $ (nullptr when absent)
+  const uint64_t *__restrict__ isa;    // isa[t / ri] = row of the suffix at t
+  uint32_t ri;
 };
 
 static inline IndexView make_view(const mbw_index *ix) {
@@ -63,6 +73,7 @@ static inline IndexView make_view(const mbw_index *ix) {
   v.n = ix->n; v.primary = ix->primary;
   for (int a = 0; a < 4; ++a) v.Cb[a] = ix->C[a + 1];
   v.r = (uint32_t)ix->sa_sample; v.K = ix->kmer_k; v.n_sb = ix->n_sb;
+  v.text = ix->text; v.isa = ix->isa; v.ri = (uint32_t)ix->isa_sample;
   return v;
 }
 
@@ -156,15 +167,15 @@ __device__ __forceinline__ void sb_values(const uint64_t *sbtab, uint32_t line, 
 //   y'  = y + [x <= primary < x+s] + sum_{d > c} (Occ(d, x+s) - Occ(d, x))
 // The last line is the k' update of BackwardExt: the symbols b < comp(c) (b = $ included) are
 // exactly $ and the complements of the bases d > c.  E1/G1 and E2/G2 are (Occ(c,.), sum_{d>c}
-// Occ(d,.)) at x and x+s before the $ correction.
+// Occ(d,.)) at x and x+s before the $ correction; Cc = C(c).
 __device__ __forceinline__ void ext_update(uint64_t E1, uint64_t G1, uint64_t E2, uint64_t G2, int c, uint64_t x,
-                                           uint64_t s, uint64_t y, uint64_t primary, const uint64_t Cb[4],
+                                           uint64_t s, uint64_t y, uint64_t primary, uint64_t Cc,
                                            uint64_t &nx, uint64_t &ny, uint64_t &ns) {
   const uint64_t x2 = x + s;
   if (c == 0) { E1 -= x > primary ? 1 : 0; E2 -= x2 > primary ? 1 : 0; }
   const uint64_t dol = (x <= primary && primary < x2) ? 1 : 0;
   ns = E2 - E1;
-  nx = sel4(Cb[0], Cb[1], Cb[2], Cb[3], c) + E1;
+  nx = Cc + E1;
   ny = y + dol + (G2 - G1);
 }
 

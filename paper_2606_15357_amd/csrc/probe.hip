@@ -15,28 +15,22 @@ __global__ void k_probe_copy(const uint4 *__restrict__ a, uint4 *__restrict__ b,
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) b[i] = a[i];
 }
 
-__device__ __forceinline__ uint64_t mix64(uint64_t z) {
-  z += 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
-// eight lanes fetch one random 128-byte line (16 bytes each); the next line depends on the data
-__global__ void k_probe_gather(const uint4 *__restrict__ buf, uint64_t nlines, int iters, uint64_t *__restrict__ out) {
+// Every lane follows four independent chains of random 128-byte lines (16 bytes read per line, one
+// lane per line, as the seeding kernels do); the next line of a chain depends on the data read, so
+// nothing can be prefetched, and the line index is a 32-bit LCG step masked to a power of two.
+__global__ void k_probe_gather(const uint4 *__restrict__ buf, uint32_t mask, int iters, uint64_t *__restrict__ out) {
   const uint64_t tid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  const int q = threadIdx.x & 7;
-  uint64_t h = mix64(tid >> 3);
+  uint32_t h0 = (uint32_t)(tid * 0x9E3779B1u) ^ 0x1234567u, h1 = h0 * 0x85EBCA6Bu + 1u, h2 = h1 * 0xC2B2AE35u + 7u,
+           h3 = h2 * 0x27D4EB2Fu + 13u;
   for (int it = 0; it < iters; ++it) {
-    const uint64_t line = h % nlines;
-    const uint4 v = buf[line * 8 + q];
-    uint32_t x = v.x ^ v.y ^ v.z ^ v.w;
-    x ^= __shfl_xor(x, 1, 8);
-    x ^= __shfl_xor(x, 2, 8);
-    x ^= __shfl_xor(x, 4, 8);
-    h = mix64(h ^ x);
+    const uint4 a = buf[(uint64_t)(h0 & mask) * 8], b = buf[(uint64_t)(h1 & mask) * 8 + 1],
+                c = buf[(uint64_t)(h2 & mask) * 8 + 2], d = buf[(uint64_t)(h3 & mask) * 8 + 3];
+    h0 = h0 * 1664525u + 1013904223u + a.x;
+    h1 = h1 * 1664525u + 1013904223u + b.y;
+    h2 = h2 * 1664525u + 1013904223u + c.z;
+    h3 = h3 * 1664525u + 1013904223u + d.w;
   }
-  out[tid] = h;
+  out[tid] = (uint64_t)(h0 ^ h1) << 32 | (h2 ^ h3);
 }
 
 }  // namespace
@@ -73,8 +67,10 @@ extern "C" int mbw_probe_copy(int device, uint64_t bytes, float *ms) {
 extern "C" int mbw_probe_gather(int device, uint64_t bytes, int iters, double *lines_per_s, float *ms) {
   if (!lines_per_s || !ms || bytes < (1u << 20) || iters < 1) { mbw_set_error("bad probe arguments"); return MBW_E_INVAL; }
   TRY(hipSetDevice(device));
-  const uint64_t nlines = bytes / 128;
-  const int grid = 16384, block = 256;
+  uint64_t nlines = 1;                                   // a power of two, at most bytes / 128 and 2^32
+  while (nlines * 2 <= bytes / 128 && nlines < (1ull << 32)) nlines *= 2;
+  const uint32_t mask = (uint32_t)(nlines - 1);
+  const int grid = 8192, block = 256;
   uint4 *buf = nullptr;
   uint64_t *out = nullptr;
   TRY(hipMalloc((void **)&buf, nlines * 128));
@@ -84,13 +80,13 @@ extern "C" int mbw_probe_gather(int device, uint64_t bytes, int iters, double *l
     TRY(hipMemset(buf, 0x5a, nlines * 128));
     TRY(hipEventCreate(&e0));
     TRY(hipEventCreate(&e1));
-    k_probe_gather<<<grid, block>>>(buf, nlines, iters, out);   // warm
+    k_probe_gather<<<grid, block>>>(buf, mask, iters, out);   // warm
     TRY(hipEventRecord(e0));
-    k_probe_gather<<<grid, block>>>(buf, nlines, iters, out);
+    k_probe_gather<<<grid, block>>>(buf, mask, iters, out);
     TRY(hipEventRecord(e1));
     TRY(hipEventSynchronize(e1));
     TRY(hipEventElapsedTime(ms, e0, e1));
-    *lines_per_s = (double)grid * block / 8 * iters / (*ms * 1e-3);
+    *lines_per_s = (double)grid * block * 4 * iters / (*ms * 1e-3);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return 0;

@@ -51,6 +51,10 @@ struct SeedParams {
   int l, c;                            // round 1 parameters
   int reseed, reseed_len, reseed_occ, round;
   int use_kmer;
+  int uniq;                            // extend s = 1 matches against the text (index has text + ISA)
+  uint32_t rmask;                      // r - 1 (the unique path needs r a power of two)
+  int rshift;                          // log2 r
+  int rishift;                         // log2 of the inverse-SA sampling step
   SeedRec *__restrict__ seeds;
   uint64_t seed_cap;
   Query *__restrict__ subq;
@@ -243,9 +247,17 @@ __device__ __forceinline__ void wave_close(const SeedParams &P, int lane, const 
 // need no memory are taken before the memory phase.  In the memory phase every lane issues all of
 // its loads (the three 16-byte slices of each index line a rank needs, a k-mer entry, a query
 // record or the words of a read being staged) and the wave waits once.
+//
+// Unique matches.  When forward extension (stage 2) reaches an interval with s = 1, P[i, j) occurs
+// at exactly one text position p, and P[i, j') occurs iff T[p, p + j' - i) = P[i, j'): the
+// extension is finished by comparing read and text directly, which gives the same end j.  The
+// interval of the result keeps k (the same single suffix) and s = 1; k' is the row of the suffix
+// at the mirrored position m - p - (j - i) (T without $ is its own reverse complement), found from
+// the nearest inverse-SA sample by LF steps.  Stages: 4 = LF walk from row k to a sampled row
+// (Algorithm 2), 5 = text comparison, 6 = inverse-SA sample read, 7 = LF walk to k'.
 #define STAGE_WORDS 5   // staged reads of up to 160 bases
 #define SMEM_WAVES 4    // waves per block
-enum { ACT_DONE = 0, ACT_KMER = 1, ACT_BWD = 2, ACT_FWD = 3 };
+enum { ACT_DONE = 0, ACT_KMER = 1, ACT_BWD = 2, ACT_FWD = 3, ACT_LF = 4, ACT_SSA = 5, ACT_TEXT = 6, ACT_ISA = 7 };
 enum { ST_IDLE = 0, ST_REC = 1, ST_STAGE = 2, ST_ACTIVE = 3, ST_DRAINED = 4 };
 
 template <bool STAGED>
@@ -253,7 +265,9 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
   __shared__ uint64_t sw[SMEM_WAVES][STAGED ? STAGE_WORDS * 64 : 1];   // staged bases, word w of lane L at [64 w + L]
   __shared__ uint32_t sn[SMEM_WAVES][STAGED ? STAGE_WORDS * 64 : 1];   // staged N bits
   __shared__ uint64_t sbt[MBW_MAX_SB * 8];
+  __shared__ uint64_t scb[4];
   for (int t = threadIdx.x; t < 8 * ix.n_sb; t += blockDim.x) sbt[t] = ix.sbtab[t];
+  if (threadIdx.x < 4) scb[threadIdx.x] = ix.Cb[threadIdx.x];
   __syncthreads();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   uint64_t *mw = sw[wv];
@@ -268,9 +282,12 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
     const int w = p >> 5, b = p & 31;
     return ((nbits_at(w) >> b) & 1) ? 4 : (int)((word_at(w) >> (2 * b)) & 3);
   };
+  const uint64_t tm = ix.n - 1;   // text length without $
   uint32_t read_id = 0, qbeg = 0, qend = 0, l = 0, c = 1;
   int u = 0, i = 0, j = 0;
   uint64_t k = 0, kr = 0, s = 0, budget = 0;
+  uint64_t wrow = 0, tp = 0;      // unique path: walk row (or sample index); text position of P[i]
+  uint32_t wcnt = 0;              // unique path: LF steps taken (stage 4) or still to take (stage 7)
   bool fresh = false;
   uint64_t n_lines = 0, n_steps = 0, n_kmer = 0;
   uint64_t cb = 0, ce = 0;
@@ -292,8 +309,24 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
     if (st == ST_ACTIVE && --budget == 0) { atomicOr(&P.ctl[C_ERR], 1ull); st = ST_IDLE; }
     if (st == ST_ACTIVE) {
       for (;;) {
+        if (u >= 4) {                                   // unique path
+          if (u == 4) {
+            const bool smp = (wrow & P.rmask) == 0;
+            if (smp) { act = ACT_SSA; break; }
+            if (wrow == ix.primary) { wrow = 0; ++wcnt; continue; }   // LF of the $ row is row 0
+            act = ACT_LF; break;
+          }
+          if (u == 5) { act = ACT_TEXT; break; }
+          if (u == 6) { act = ACT_ISA; break; }
+          if (wcnt > 0) { act = ACT_LF; break; }        // u == 7
+          em = true; e.i = i; e.j = j; e.k = k; e.kr = wrow; e.s = 1;
+          if (j == (int)qend) { act = ACT_DONE; break; }
+          u = 3; k = 0; kr = 0; s = ix.n; fresh = true;
+          continue;
+        }
         if (u == 2) {
           if (j == (int)qend) { em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s; act = ACT_DONE; break; }
+          if (P.uniq && s == 1) { u = 4; wrow = k; wcnt = 0; continue; }
           a = base_at(j);
           if (a > 3) {                                  // forward extension fails on a non-ACGT base
             em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s;
@@ -325,9 +358,10 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
     }
     const bool ext = act == ACT_BWD || act == ACT_FWD;
     const bool bwd = act == ACT_BWD;
-    const uint64_t x1 = bwd ? k : kr, y = bwd ? kr : k;
+    const bool lfa = act == ACT_LF;
+    const uint64_t x1 = lfa ? wrow : (bwd ? k : kr), y = bwd ? kr : k;
     const int cc = bwd ? a : 3 - a;
-    const uint64_t x2 = x1 + s;
+    const uint64_t x2 = x1 + (lfa ? 0ull : s);            // an LF step ranks one row
     const uint32_t L1 = line_of(x1), L2 = line_of(x2);
     const int o1 = (int)(x1 - (uint64_t)L1 * MBW_BPL), o2 = (int)(x2 - (uint64_t)L2 * MBW_BPL);
     const bool two = ext && L1 != L2;                          // a second index line
@@ -336,9 +370,19 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
     const uint4 z4 = make_uint4(0, 0, 0, 0);
     const uint4 *l1p = ix.lines + (uint64_t)L1 * MBW_LINE_U4, *l2p = ix.lines + (uint64_t)L2 * MBW_LINE_U4;
     uint4 h0a = z4, h1a = z4, ba = z4, h0b = z4, h1b = z4, bb = z4;
-    if (ext) { h0a = l1p[0]; h1a = l1p[1]; ba = l1p[2 + (o1 >> 6)]; }
+    if (ext || lfa) { h0a = l1p[0]; h1a = l1p[1]; ba = l1p[2 + (o1 >> 6)]; }
     if (two) { h0b = l2p[0]; h1b = l2p[1]; }
     if (blk2) bb = l2p[2 + (o2 >> 6)];
+    // unique path: a sampled SA / inverse-SA value, or 32 bytes of text around position tq
+    const uint64_t tq = tp + (uint64_t)(j - i);
+    const bool txt = act == ACT_TEXT && tq < tm;
+    if (txt) {
+      const uint4 *tw = (const uint4 *)(ix.text + ((tq >> 5) & ~1ull));
+      h0b = tw[0]; h1b = tw[1];
+    }
+    uint64_t mval = 0;
+    if (act == ACT_SSA) mval = ix.ssa[wrow >> P.rshift];
+    if (act == ACT_ISA) mval = ix.isa[wrow];
     uint4 kent = make_uint4(0, 0, 0, 0);
     if (act == ACT_KMER) kent = ix.kmer[code];
     const int st_mem = st;
@@ -366,29 +410,83 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
       ++n_kmer;
       if (es >= c) { k = ek; kr = ekr; s = es; j -= K; }
     }
-    if (ext) {
+    if (ext || lfa) {
+      // an LF step (unique path) is the first rank of an extension by its own row's symbol
+      const int cx = lfa ? bwt_from_block(ba, o1) : cc;
       if (!two) { h0b = h0a; h1b = h1a; }
       if (!blk2) bb = ba;
-      const SymMasks sm = sym_masks(cc);
+      const SymMasks sm = sym_masks(cx);
       const uint32_t sb1 = 8 * (L1 >> MBW_SB_SHIFT), sb2 = 8 * (L2 >> MBW_SB_SHIFT);
       uint64_t E1, G1, E2, G2;
-      rank_eg(h0a, h1a, ba, L1, o1, cc, sm, sbt[sb1 + cc], sbt[sb1 + 4 + cc], E1, G1);
-      rank_eg(h0b, h1b, bb, L2, o2, cc, sm, sbt[sb2 + cc], sbt[sb2 + 4 + cc], E2, G2);
-      n_lines += two ? 2 : 1;
-      ++n_steps;
+      rank_eg(h0a, h1a, ba, L1, o1, cx, sm, sbt[sb1 + cx], sbt[sb1 + 4 + cx], E1, G1);
+      rank_eg(h0b, h1b, bb, L2, o2, cx, sm, sbt[sb2 + cx], sbt[sb2 + 4 + cx], E2, G2);
       uint64_t nx, ny, ns;
-      ext_update(E1, G1, E2, G2, cc, x1, s, y, ix.primary, ix.Cb, nx, ny, ns);
-      if (ns >= c) {
-        if (bwd) { k = nx; kr = ny; s = ns; j -= 1; }
-        else { kr = nx; k = ny; s = ns; j += 1; }
-      } else if (bwd) {                                 // BackStep failure: jump past j
-        if (j + (int)l < (int)qend) { u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; }
-        else st = ST_IDLE;
-      } else {                                          // forward failure: report, then stage 3 from j
-        em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s;
-        u = 3; k = 0; kr = 0; s = ix.n; fresh = true;
+      ext_update(E1, G1, E2, G2, cx, x1, lfa ? 0ull : s, y, ix.primary, scb[cx], nx, ny, ns);
+      if (lfa) {
+        wrow = nx;
+        if (u == 4) ++wcnt; else --wcnt;
+        ++n_lines;
+      } else {
+        n_lines += two ? 2 : 1;
+        ++n_steps;
+        if (ns >= c) {
+          if (bwd) { k = nx; kr = ny; s = ns; j -= 1; }
+          else { kr = nx; k = ny; s = ns; j += 1; }
+        } else if (bwd) {                                 // BackStep failure: jump past j
+          if (j + (int)l < (int)qend) { u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; }
+          else st = ST_IDLE;
+        } else {                                          // forward failure: report, then stage 3 from j
+          em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s;
+          u = 3; k = 0; kr = 0; s = ix.n; fresh = true;
+        }
       }
     }
+    if (act == ACT_SSA) {                               // the occurrence: p = S(row) + steps (mod n)
+      uint64_t pp = mval + wcnt;
+      if (pp >= ix.n) pp -= ix.n;
+      tp = pp;
+      u = 5;
+      ++n_lines;
+    }
+    if (act == ACT_TEXT) {                              // compare up to 64 bases of read and text
+      const int lim0 = min(64, (int)qend - j);
+      int first = 0;
+      if (txt) {
+        const uint64_t wv0 = ((uint64_t)h0b.y << 32) | h0b.x, wv1 = ((uint64_t)h0b.w << 32) | h0b.z;
+        const uint64_t wv2 = ((uint64_t)h1b.y << 32) | h1b.x, wv3 = ((uint64_t)h1b.w << 32) | h1b.z;
+        const int off = 2 * (int)(tq - 32 * ((tq >> 5) & ~1ull));   // bit offset of tq in the window, 0..126
+        const int sh = off & 63;
+        const uint64_t lo = off < 64 ? wv0 : wv1, mid = off < 64 ? wv1 : wv2, hi = off < 64 ? wv2 : wv3;
+        const uint64_t t0 = sh ? (lo >> sh) | (mid << (64 - sh)) : lo;
+        const uint64_t t1 = sh ? (mid >> sh) | (hi << (64 - sh)) : mid;
+        const int w0 = j >> 5, rb = j & 31;
+        const uint32_t nw_q = (rlen + 31) >> 5;
+        const uint64_t a0 = word_at(w0), a1 = (uint32_t)(w0 + 1) < nw_q ? word_at(w0 + 1) : 0ull,
+                       a2 = (uint32_t)(w0 + 2) < nw_q ? word_at(w0 + 2) : 0ull;
+        const uint32_t n0 = nbits_at(w0), n1 = (uint32_t)(w0 + 1) < nw_q ? nbits_at(w0 + 1) : 0u,
+                       n2 = (uint32_t)(w0 + 2) < nw_q ? nbits_at(w0 + 2) : 0u;
+        const uint64_t r0 = rb ? (a0 >> (2 * rb)) | (a1 << (64 - 2 * rb)) : a0;
+        const uint64_t r1 = rb ? (a1 >> (2 * rb)) | (a2 << (64 - 2 * rb)) : a1;
+        const uint64_t nb = (((uint64_t)n2 << 32 | n1) << (32 - rb)) | ((uint64_t)n0 >> rb);
+        const uint64_t d0 = r0 ^ t0, d1 = r1 ^ t1;
+        const uint64_t f0 = (d0 | (d0 >> 1)) & 0x5555555555555555ull, f1 = (d1 | (d1 >> 1)) & 0x5555555555555555ull;
+        const int mm = f0 ? (__ffsll((long long)f0) - 1) >> 1 : (f1 ? 32 + ((__ffsll((long long)f1) - 1) >> 1) : 64);
+        const int nf = nb ? __ffsll((long long)nb) - 1 : 64;
+        const uint64_t left = tm - tq;                  // text symbols before the $
+        first = min(min(mm, nf), min(lim0, left < 64 ? (int)left : 64));
+        n_lines += ((((tq >> 5) & ~1ull) & 15) == 14) ? 2 : 1;
+      }
+      j += first;
+      if (first == 64 && j < (int)qend) {
+        // the whole window matched: continue with the next one
+      } else {                                          // end of the match: k' from the mirror position
+        const uint64_t pm = tm - tp - (uint64_t)(j - i);
+        const uint64_t q = ((pm >> P.rishift) + ((pm & ((1ull << P.rishift) - 1)) ? 1 : 0)) << P.rishift;
+        if (q >= tm) { wrow = 0; wcnt = (uint32_t)(tm - pm); u = 7; }   // row 0 holds the suffix at tm ($)
+        else { wrow = q >> P.rishift; wcnt = (uint32_t)(q - pm); u = 6; }
+      }
+    }
+    if (act == ACT_ISA) { wrow = mval; u = 7; ++n_lines; }
     if (STAGED && st_mem == ST_STAGE) {
       mw[lane] = g0; mn[lane] = h0;
       mw[64 + lane] = g1; mn[64 + lane] = h1;
@@ -455,7 +553,7 @@ __device__ __forceinline__ uint64_t plain_step(PlainCtx &C, bool bwd, int a, uin
   C.lines += line_of(x) == line_of(x + s) ? 1 : 2;
   C.steps++;
   uint64_t nx, ny, ns;
-  ext_update(E1, G1, E2, G2, cc, x, s, y, C.ix.primary, C.ix.Cb, nx, ny, ns);
+  ext_update(E1, G1, E2, G2, cc, x, s, y, C.ix.primary, sel4(C.ix.Cb[0], C.ix.Cb[1], C.ix.Cb[2], C.ix.Cb[3], cc), nx, ny, ns);
   if (bwd) { nk = nx; nkr = ny; } else { nkr = nx; nk = ny; }
   return ns;
 }
@@ -834,7 +932,10 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   if (n_reads >= (1ull << 31)) { mbw_set_error("too many reads in one call"); return MBW_E_INVAL; }
   mbw_seed_opts o;
   if (opts) o = *opts;
-  else { memset(&o, 0, sizeof(o)); o.min_occ = 1; o.reseed = 1; o.reseed_len = 38; o.reseed_occ = 10; o.use_kmer = 1; }
+  else {
+    memset(&o, 0, sizeof(o));
+    o.min_occ = 1; o.reseed = 1; o.reseed_len = 38; o.reseed_occ = 10; o.use_kmer = 1; o.unique_ext = 1;
+  }
   if (o.min_occ < 1) { mbw_set_error("min_occ must be >= 1"); return MBW_E_INVAL; }
   if (o.bs_role && !c->ix->bisulfite) { mbw_set_error("bs_role needs a bisulfite index"); return MBW_E_INVAL; }
   if (o.bs_role < 0 || o.bs_role > 2) { mbw_set_error("bs_role must be 0, 1 or 2"); return MBW_E_INVAL; }
@@ -923,6 +1024,14 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   P.codes = (const uint8_t *)c->codes.p; P.offs = offs; P.queries = nullptr; P.n_queries = n_reads;
   P.l = min_seed_len; P.c = o.min_occ; P.reseed = o.reseed; P.reseed_len = o.reseed_len; P.reseed_occ = o.reseed_occ;
   P.round = 1; P.use_kmer = o.use_kmer; P.ctl = ctl;
+  {
+    auto pow2 = [](int v) { return v > 0 && (v & (v - 1)) == 0; };
+    auto lg = [](int v) { int t = 0; while ((1 << t) < v) ++t; return t; };
+    P.uniq = (o.unique_ext && ix->text && ix->isa && pow2(ix->sa_sample) && pow2(ix->isa_sample)) ? 1 : 0;
+    P.rmask = (uint32_t)(ix->sa_sample - 1);
+    P.rshift = pow2(ix->sa_sample) ? lg(ix->sa_sample) : 0;
+    P.rishift = pow2(ix->isa_sample) ? lg(ix->isa_sample) : 0;
+  }
   unsigned long long n1 = 0, nq = 0;
   for (int attempt = 0;; ++attempt) {
     GROW(c->raw, seed_cap * sizeof(SeedRec));

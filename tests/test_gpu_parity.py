@@ -48,11 +48,12 @@ TINY = {
 
 
 @pytest.mark.parametrize("name", sorted(TINY))
-@pytest.mark.parametrize("r,K", [(1, 0), (3, 2), (8, 3)])
-def test_index_structure(name, r, K):
-    """BWT, C, primary row, SA samples and k-mer intervals of the GPU index equal the oracle's."""
+@pytest.mark.parametrize("r,K,ri", [(1, 0, 1), (3, 2, 3), (8, 3, 4), (8, 0, 0)])
+def test_index_structure(name, r, K, ri):
+    """BWT, C, primary row, SA samples, k-mer intervals, packed text and inverse-SA samples of the
+    GPU index equal the oracle's."""
     R = TINY[name]
-    idx = mbw.Index.build(ref_codes(R), sa_sample=r, kmer_k=K)
+    idx = mbw.Index.build(ref_codes(R), sa_sample=r, kmer_k=K, isa_sample=ri)
     info = idx.info()
     ox = oracle.OracleIndex(ref_codes(R), sa_rate=r)
     with tempfile.TemporaryDirectory() as d:
@@ -67,6 +68,19 @@ def test_index_structure(name, r, K):
     assert [int(x) for x in info["C"]] == [int(x) for x in ox.C()[:5]]
     SA = ox.sa()
     assert np.array_equal(f["ssa"], SA[::r])
+    assert f["isa_sample"] == ri and info["isa_sample"] == ri
+    if ri:
+        T = ox.text().astype(np.int64)                  # oracle codes: $ = 0, A..T = 1..4
+        m = ox.n - 1
+        sh = np.arange(32, dtype=np.uint64) * 2
+        tsyms = ((f["text"][:, None] >> sh) & 3).reshape(-1).astype(np.int64)
+        assert np.array_equal(tsyms[:m], T[:m] - 1)
+        assert not np.any(tsyms[m:])                     # padding after the last symbol
+        ISA = np.empty(ox.n, np.int64)
+        ISA[SA.astype(np.int64)] = np.arange(ox.n)
+        assert np.array_equal(f["isa"].astype(np.int64), ISA[::ri])
+    else:
+        assert f["text"].size == 0 and f["isa"].size == 0
     # line headers: superblock base + u32 count = count of A, C, G before the line ($ row as A);
     # sub-checkpoint b (1..5): counts of A, C, G in the line's first 64 b rows, 9 bits each
     Braw = B.astype(np.int64)
@@ -135,13 +149,15 @@ def cfg0():
     return ref, reads, ox, exp
 
 
-@pytest.mark.parametrize("kernel,K", [(0, 10), (0, 0), (1, 0), (0, 12)])
-def test_small_workload_parity(cfg0, kernel, K):
+@pytest.mark.parametrize("kernel,K,ri,uniq", [(0, 10, 4, True), (0, 10, 4, False), (0, 0, 1, True), (1, 0, 4, True),
+                                              (0, 12, 8, True), (0, 12, 0, True)])
+def test_small_workload_parity(cfg0, kernel, K, ri, uniq):
     """1 Mbp + repeat family reference, 10,000 x 150 bp reads, (19,1)-SMEMs with re-seeding,
-    max_occ 500: every seed, interval and position equals the oracle's."""
+    max_occ 500: every seed, interval and position equals the oracle's, with and without the
+    direct extension of unique matches (inverse-SA samples every ri text positions)."""
     ref, reads, ox, exp = cfg0
-    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=K)
-    out, seeds, pos = gpu_seed(idx, reads, min_seed_len=19, max_occ=500, kernel=kernel)
+    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=K, isa_sample=ri)
+    out, seeds, pos = gpu_seed(idx, reads, min_seed_len=19, max_occ=500, kernel=kernel, unique_ext=uniq)
     compare_with_oracle(seeds, pos, exp)
     assert out.n_seeds == len(exp)
     idx.free()
@@ -152,7 +168,7 @@ def test_line_count_matches_oracle(cfg0):
     ref, reads, ox, _ = cfg0
     for K in (0, 10):
         idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=K)
-        out, seeds, pos = gpu_seed(idx, reads, min_seed_len=19, max_occ=500, kernel=0)
+        out, seeds, pos = gpu_seed(idx, reads, min_seed_len=19, max_occ=500, kernel=0, unique_ext=False)
         o2 = ox.seed(reads.seq, reads.offsets, method=1, kmer_k=K, bases_per_line=384)
         assert out.steps == o2.lines["steps"]
         assert out.lines_smem == o2.lines["lines"] - o2.lines["lf_steps"] + o2.lines["kmer_lookups"]
