@@ -100,7 +100,11 @@ __global__ void k_widen(const uint32_t *__restrict__ len, uint64_t n, uint64_t *
     out[t] = v;
     mx = v > mx ? v : mx;
   }
-  atomicMax(maxlen, (unsigned long long)mx);
+  for (int d = 32; d >= 1; d >>= 1) {                   // wave maximum, one atomic per wave
+    const uint32_t o = (uint32_t)__shfl_xor((int)mx, d);
+    mx = o > mx ? o : mx;
+  }
+  if ((threadIdx.x & 63) == 0 && mx) atomicMax(maxlen, (unsigned long long)mx);
 }
 
 __global__ void k_read_words(const uint64_t *__restrict__ offs, uint64_t n, uint64_t *__restrict__ nwords) {
@@ -115,34 +119,70 @@ __global__ void k_word_owner(const uint64_t *__restrict__ woff, uint64_t n, uint
 }
 
 // one thread per packed word: 32 ASCII bases -> 2-bit codes + N bits (bisulfite conversion as in
-// k_encode); consecutive threads read consecutive bytes
-__global__ void k_pack_words(const uint8_t *__restrict__ ascii, const uint64_t *__restrict__ offs, const uint64_t *__restrict__ woff,
-                             const uint32_t *__restrict__ wread, uint64_t totw, int role, uint64_t *__restrict__ pw,
-                             uint32_t *__restrict__ pn) {
-  for (uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; w < totw; w += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t r = wread[w];
-    const uint64_t first = offs[r] + 32 * (w - woff[r]), end = offs[r + 1];
-    uint64_t v = 0;
-    uint32_t nb = 0;
-    for (int t = 0; t < 32; ++t) {
-      const uint64_t p = first + t;
-      if (p >= end) break;
-      int c;
-      switch (ascii[p]) {
-        case 'A': case 'a': c = 0; break;
-        case 'C': case 'c': c = 1; break;
-        case 'G': case 'g': c = 2; break;
-        case 'T': case 't': c = 3; break;
-        default: c = 4;
-      }
-      if (role == 1 && c == 1) c = 3;   // read 1: C -> T
-      if (role == 2 && c == 2) c = 0;   // read 2: G -> A
-      if (c > 3) nb |= 1u << t;
-      else v |= (uint64_t)c << (2 * t);
-    }
-    pw[w] = v;
-    pn[w] = nb;
+// k_encode; the code of an ACGT byte is its bits 1-2 with the Gray-code swap of G and T).  The words of a block cover one contiguous byte range of the reads (reads are stored
+// back to back and split into words in order), which the block first copies into LDS with
+// coalesced 4-byte loads (byte loads at the ends of the buffer).
+#define PACK_BLOCK 256
+__global__ void __launch_bounds__(PACK_BLOCK) k_pack_words(const uint8_t *__restrict__ ascii, uint64_t total,
+                                                           const uint64_t *__restrict__ offs, const uint64_t *__restrict__ woff,
+                                                           const uint32_t *__restrict__ wread, uint64_t totw, int role,
+                                                           uint64_t *__restrict__ pw, uint32_t *__restrict__ pn) {
+  __shared__ uint32_t buf[PACK_BLOCK * 8 + 16];         // the range (<= 32 * PACK_BLOCK + 3 bytes) + reads past it
+  __shared__ uint64_t range[2];
+  const uint64_t w0 = (uint64_t)blockIdx.x * PACK_BLOCK;
+  if (w0 >= totw) return;
+  const uint64_t w1 = min(w0 + PACK_BLOCK, totw);
+  if (threadIdx.x == 0) {
+    const uint32_t r0 = wread[w0], r1 = wread[w1 - 1];
+    range[0] = offs[r0] + 32 * (w0 - woff[r0]);
+    range[1] = min(offs[r1] + 32 * (w1 - 1 - woff[r1]) + 32, offs[r1 + 1]);
   }
+  __syncthreads();
+  const uint64_t b0 = range[0], b1 = range[1];
+  const uint64_t a0 = b0 & ~3ull;                       // first aligned dword of the range
+  const uint32_t ndw = (uint32_t)((b1 - a0 + 3) >> 2);  // <= 8 * PACK_BLOCK + 1
+  const bool aligned = (((uintptr_t)ascii) & 3) == 0;
+  for (uint32_t t = threadIdx.x; t < ndw; t += PACK_BLOCK) {
+    const uint64_t byte = a0 + 4ull * t;
+    uint32_t v;
+    if (aligned && byte + 4 <= total) v = *(const uint32_t *)(ascii + byte);
+    else {
+      v = 0;
+      for (int q = 0; q < 4; ++q)
+        if (byte + q < total) v |= (uint32_t)ascii[byte + q] << (8 * q);
+    }
+    buf[t] = v;
+  }
+  __syncthreads();
+  const uint64_t w = w0 + threadIdx.x;
+  if (w >= w1) return;
+  const uint32_t r = wread[w];
+  const uint64_t first = offs[r] + 32 * (w - woff[r]), end = offs[r + 1];
+  const int cnt = (int)min<uint64_t>(32, end - first);
+  const uint32_t boff = (uint32_t)(first - a0);
+  uint64_t v = 0;
+  uint32_t nb = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {                        // four bases per step, no branches
+    const uint32_t bo = boff + 4 * q, sh = (bo & 3) * 8;
+    const uint32_t lo = buf[bo >> 2], hi = buf[(bo >> 2) + 1];
+    const uint32_t d = sh ? (lo >> sh) | (hi << (32 - sh)) : lo;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int idx = 4 * q + t;
+      const uint32_t ch = (d >> (8 * t)) & 0xffu, lc = ch | 0x20u;
+      const uint32_t x = (ch >> 1) & 3u;                 // A 0, C 1, G 3, T 2 (either case)
+      uint32_t code = x ^ (x >> 1);                      // A 0, C 1, G 2, T 3
+      const bool valid = lc == 'a' || lc == 'c' || lc == 'g' || lc == 't';
+      code = (role == 1 && code == 1) ? 3u : code;       // read 1: C -> T
+      code = (role == 2 && code == 2) ? 0u : code;       // read 2: G -> A
+      const bool in = idx < cnt;
+      v |= (uint64_t)((in && valid) ? code : 0u) << (2 * idx);
+      nb |= ((in && !valid) ? 1u : 0u) << idx;
+    }
+  }
+  pw[w] = v;
+  pn[w] = nb;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -667,11 +707,21 @@ __global__ void k_seed_posoff(mbw_seed_t *__restrict__ out, const uint64_t *__re
     out[t].pos_off = off[t];
 }
 
-// start row of every (seed, occurrence) pair: X[pos_off + i] = k + i
-__global__ void k_expand_rows(const mbw_seed_t *__restrict__ seeds, uint64_t ns, uint64_t *__restrict__ X) {
-  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < ns; t += (uint64_t)gridDim.x * blockDim.x) {
-    const mbw_seed_t sd = seeds[t];
-    for (uint32_t i = 0; i < sd.npos; ++i) X[sd.pos_off + i] = sd.k + i;
+// start row of every (seed, occurrence) pair: X[pos_off + i] = k + i.  A wave takes 64 seeds and
+// writes each seed's rows with all of its lanes (coalesced, balanced for seeds with many rows).
+__global__ void __launch_bounds__(256) k_expand_rows(const mbw_seed_t *__restrict__ seeds, uint64_t ns, uint64_t *__restrict__ X) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t nwave = (uint64_t)gridDim.x * (blockDim.x >> 6);
+  for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64; base < ns; base += nwave * 64) {
+    uint64_t k = 0, off = 0;
+    uint32_t np = 0;
+    if (base + lane < ns) { const mbw_seed_t sd = seeds[base + lane]; k = sd.k; off = sd.pos_off; np = sd.npos; }
+    const int cnt = (int)min<uint64_t>(64, ns - base);
+    for (int t = 0; t < cnt; ++t) {
+      const uint64_t kt = __shfl(k, t), ot = __shfl(off, t);
+      const uint32_t nt = (uint32_t)__shfl((int)np, t);
+      for (uint32_t q = (uint32_t)lane; q < nt; q += 64) X[ot + q] = kt + q;
+    }
   }
 }
 
@@ -963,7 +1013,7 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   GROW(c->offs, (n_reads + 2) * sizeof(uint64_t));
   GROW(c->npos, (n_reads + 2) * sizeof(uint64_t));
   uint64_t *wide = (uint64_t *)c->npos.p;
-  k_widen<<<grid_for(n_reads + 1), 256, 0, st>>>(dlen, n_reads, wide, ctl + C_MAXLEN);
+  k_widen<<<grid_for(n_reads + 1, 256, 1024u), 256, 0, st>>>(dlen, n_reads, wide, ctl + C_MAXLEN);
   TRY(hipGetLastError());
   uint64_t *offs = (uint64_t *)c->offs.p;
   int r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, wide, offs, n_reads + 1, st); });
@@ -1006,8 +1056,12 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     GROW(c->wread, (totw + 2) * 4);
     k_word_owner<<<grid_for(n_reads), 256, 0, st>>>(woff, n_reads, (uint32_t *)c->wread.p);
     TRY(hipGetLastError());
-    k_pack_words<<<grid_for(totw), 256, 0, st>>>(dreads, offs, woff, (const uint32_t *)c->wread.p, totw, o.bs_role,
-                                                 (uint64_t *)c->pwords.p, (uint32_t *)c->pnmask.p);
+    if (totw) {
+      const uint64_t nblk = (totw + PACK_BLOCK - 1) / PACK_BLOCK;
+      if (nblk > 0x7fffffffull) { mbw_set_error("batch too large"); return MBW_E_INVAL; }
+      k_pack_words<<<(unsigned)nblk, PACK_BLOCK, 0, st>>>(dreads, total, offs, woff, (const uint32_t *)c->wread.p, totw,
+                                                         o.bs_role, (uint64_t *)c->pwords.p, (uint32_t *)c->pnmask.p);
+    }
     TRY(hipGetLastError());
     R.pw = (const uint64_t *)c->pwords.p;
     R.pn = (const uint32_t *)c->pnmask.p;
@@ -1137,7 +1191,7 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
       TRY(hipGetLastError());
     } else {
       GROW(c->xrows, (n_pos + 1) * 8);
-      k_expand_rows<<<grid_for(nu), 256, 0, st>>>(seeds, nu, (uint64_t *)c->xrows.p);
+      k_expand_rows<<<grid_for((nu + 63) / 64 * 64 / 4, 256, 65536u), 256, 0, st>>>(seeds, nu, (uint64_t *)c->xrows.p);
       TRY(hipGetLastError());
       const int grid = persistent_grid((const void *)k_locate_wave, 256, 0, c->n_cu, o.blocks_per_cu);
       TRY(hipEventRecord(c->ev[3], st));
