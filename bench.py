@@ -63,22 +63,25 @@ def traffic_from_profile(kernel: str, launches_bytes: float):
     return k.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(ref_codes, n_pairs: int, window: int, threads: int):
+def cpu_baseline(workload: str, ref_codes, n_pairs: int, window: int, threads: int):
     """The oracle (Algorithm 3 + LocateSlow + 10-mer shortcut, OpenMP over reads) on a bounded
-    sample: an oracle index over the first `window` bases of the same reference and read pairs
-    from that window drawn with the workload's read model."""
+    sample: an oracle index over the first `window` bases of the same reference and reads from
+    that window drawn with the workload's read model."""
     import oracle
     import synth
     sub = synth.Reference(np.ascontiguousarray(ref_codes[:window]), np.zeros((0, 2), np.uint64), 1, 0)
     t0 = time.time()
     ox = oracle.OracleIndex(sub.codes, sa_rate=8)
     t_build = time.time() - t0
-    rs = synth.reads_fixed(sub, n_pairs, 150, True, p_sub=0.005, p_indel=0.0005, seed=4003)
+    if workload == "lognormal_100mbp":
+        rs = synth.reads_lognormal(sub, n_pairs // 10, seed=4003)
+    else:
+        rs = synth.reads_fixed(sub, n_pairs, 150, True, p_sub=0.005, p_indel=0.0005, seed=4003)
     t0 = time.time()
     res = ox.seed(rs.seq, rs.offsets, min_len=19, max_occ=500, method=1, kmer_k=10, threads=threads)
     dt = time.time() - t0
     return dict(value=len(rs) / dt, unit="reads/s", cores=threads, kind="oracle",
-                sample=f"{len(rs)} x 150 bp reads ({n_pairs} pairs, workload read model) against an oracle index "
+                sample=f"{len(rs)} reads ({int(rs.lengths.sum())} bases, workload read model) against an oracle index "
                        f"of the first {window / 1e6:.0f} Mbp of the same 3.1 Gbp reference (index build "
                        f"{t_build:.1f} s excluded); oracle = serial Algorithm 3 + LocateSlow with the 10-mer "
                        f"shortcut per read, OpenMP over reads; {len(res)} seeds, {res.pos.size} positions; "
@@ -90,8 +93,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--ref-len", type=int, default=3_100_000_000)
-    ap.add_argument("--pairs", type=int, default=10_000_000)
+    ap.add_argument("--workload", default="human_3gbp", choices=["human_3gbp", "paired_100mbp", "lognormal_100mbp"],
+                    help="human_3gbp (the headline), or one of the 100 Mbp workloads")
+    ap.add_argument("--ref-len", type=int, default=0, help="reference length (0 = the workload's)")
+    ap.add_argument("--pairs", type=int, default=0, help="read pairs / reads (0 = the workload's)")
     ap.add_argument("--sa-sample", type=int, default=8)
     ap.add_argument("--kmer", type=int, default=12)
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the plain kernel (0 = skip)")
@@ -123,7 +128,9 @@ def main():
         return
     gather_lps, _ = mbw.probe_gather(8 << 30, iters=32)
     t0 = time.time()
-    ref = synth.workload_reference("human_3gbp", args.ref_len)
+    wl = synth.WORKLOADS[args.workload]
+    args.ref_len = args.ref_len or wl["ref_len"]
+    ref = synth.workload_reference(args.workload, args.ref_len)
     log(f"reference {len(ref)} bases generated in {time.time() - t0:.1f} s")
     t0 = time.time()
     idx = mbw.Index.build(ref.codes, sa_sample=args.sa_sample, kmer_k=args.kmer, isa_sample=args.isa_sample)
@@ -131,7 +138,7 @@ def main():
     log(f"index built on the GPU in {time.time() - t0:.1f} s: n={info['n']} lines={info['n_lines']} "
         f"resident={info['bytes_resident'] / 1e9:.2f} GB")
     t0 = time.time()
-    reads = synth.workload_reads("human_3gbp", ref, args.pairs)
+    reads = synth.workload_reads(args.workload, ref, args.pairs or None)
     n_reads = len(reads)
     log(f"{n_reads} reads generated in {time.time() - t0:.1f} s")
     dseq = torch.from_numpy(reads.seq).to(dev)
@@ -161,7 +168,8 @@ def main():
     lines_smem = out.lines_smem
     lines_loc = out.lines_locate
     log(f"wave path: {value / 1e6:.2f} M reads/s, {elapsed / args.steps * 1e3:.1f} ms/step; seeds {out.n_seeds} "
-        f"positions {out.n_pos}; smem {ms_smem:.1f} ms ({launches} launches, {lines_smem} lines), "
+        f"positions {out.n_pos}; smem {ms_smem:.1f} ms ({launches} launches, {lines_smem} lines, "
+        f"{out.wave_iters} wave iterations, lane use {out.lane_iters / max(1, 64 * out.wave_iters):.2f}), "
         f"locate {ms_loc:.1f} ms ({lines_loc} lines)")
 
     plain = None
@@ -199,16 +207,15 @@ def main():
     if not args.no_cpu:
         threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
         threads = max(1, min(threads, int(os.environ.get("OMP_NUM_THREADS", threads))))
-        cpu = cpu_baseline(ref.codes, args.cpu_pairs, args.cpu_window, threads)
+        cpu = cpu_baseline(args.workload, ref.codes, args.cpu_pairs, args.cpu_window, threads)
         cpu["value"] = round(cpu["value"], 1)
         log(f"cpu oracle: {cpu['value']:.0f} reads/s on {cpu['cores']} threads")
 
     line = dict(metric=METRIC, value=round(value, 1), unit="reads/s", n_gpus=1, steps=args.steps,
                 warmup=args.warmup, ms_per_step=round(elapsed / args.steps * 1e3, 2), higher_is_better=True,
                 scaling="weak", vs_baseline=None, dtype="u64", data="synthetic",
-                config=dict(workload=f"{args.ref_len / 1e9:.1f} Gbp synthetic reference, "
-                                     f"{args.pairs} paired 150 bp reads ({n_reads} reads), 0.5% error, 5% from "
-                                     f"satellites; (19,1)-SMEMs + re-seeding, max_occ 500",
+                config=dict(workload=wl["desc"] + f" ({n_reads} reads, {args.ref_len / 1e6:.0f} Mbp); (19,1)-SMEMs + "
+                                     f"re-seeding, max_occ 500",
                             min_seed_len=19, max_occ=500, sa_sample=args.sa_sample, kmer_k=args.kmer,
                             isa_sample=args.isa_sample, unique_ext=not args.no_unique,
                             bases_per_line=384, line_bytes=LINE_BYTES, index_gb=round(info["bytes_resident"] / 1e9, 2)),

@@ -123,6 +123,9 @@ typedef struct {
   int unique_ext;     /* 1: when the index holds the text and inverse-SA samples, a forward
                          extension whose interval has s = 1 continues by comparing the read with
                          the text at the match's single position (wave kernels; same results) */
+  int seg_len;        /* queries longer than this many bases (and reads too long for the LDS
+                         staging area) are split into segments seeded by separate lanes
+                         (wave kernels; same results); 0 = 256, minimum 32 */
 } mbw_seed_opts;
 
 
@@ -155,7 +158,10 @@ typedef struct {
   float ms_smem;            /* device time of the SMEM kernel launches (HIP events around each) */
   float ms_locate;          /* device time of the locate kernel launch */
   float ms_total;           /* device time of the whole call */
-  int n_smem_launches;      /* SMEM kernel launches in this call (round 1, round 2) */
+  int n_smem_launches;      /* SMEM kernel launches in this call (per round and length bin) */
+  uint64_t wave_iters;      /* diagnostics of the wave kernels: loop iterations summed over waves, */
+  uint64_t lane_iters;      /* and lane iterations that held a query (utilisation = lane / 64 wave) */
+  uint64_t max_chain;       /* the most iterations one query took (wave kernels) */
 } mbw_result;
 
 /* Seed a batch of reads.

@@ -58,14 +58,15 @@ class IndexInfo(C.Structure):
 class SeedOpts(C.Structure):
     _fields_ = [("min_occ", C.c_int), ("reseed", C.c_int), ("reseed_len", C.c_int), ("reseed_occ", C.c_int),
                 ("bs_role", C.c_int), ("kernel", C.c_int), ("use_kmer", C.c_int), ("blocks_per_cu", C.c_int),
-                ("no_stage", C.c_int), ("unique_ext", C.c_int)]
+                ("no_stage", C.c_int), ("unique_ext", C.c_int), ("seg_len", C.c_int)]
 
 
 class Result(C.Structure):
     _fields_ = [("n_seeds", C.c_uint64), ("n_pos", C.c_uint64), ("seeds", C.c_void_p), ("pos", C.c_void_p),
                 ("lines_smem", C.c_uint64), ("lines_locate", C.c_uint64), ("steps", C.c_uint64),
                 ("lf_steps", C.c_uint64), ("ms_smem", C.c_float), ("ms_locate", C.c_float), ("ms_total", C.c_float),
-                ("n_smem_launches", C.c_int)]
+                ("n_smem_launches", C.c_int), ("wave_iters", C.c_uint64), ("lane_iters", C.c_uint64),
+                ("max_chain", C.c_uint64)]
 
 
 SEED_DTYPE = np.dtype([("read_id", "<u4"), ("qbeg", "<u4"), ("qend", "<u4"), ("flags", "<u4"), ("k", "<u8"),
@@ -217,6 +218,9 @@ class SeedOutput:
     ms_locate: float
     ms_total: float
     n_smem_launches: int
+    wave_iters: int
+    lane_iters: int
+    max_chain: int
     _res: Result
     _ctx: "Context"
 
@@ -243,7 +247,7 @@ class Context:
     def seed(self, reads, lengths, min_seed_len: int = 19, max_occ: int = 500, min_occ: int = 1,
              reseed: bool = True, reseed_len: int = 38, reseed_occ: int = 10, bs_role: int = 0,
              kernel: int = KERNEL_COOP, use_kmer: bool = True, blocks_per_cu: int = 0, stage: bool = True,
-             unique_ext: bool = True, stream=None) -> SeedOutput:
+             unique_ext: bool = True, seg_len: int = 0, stream=None) -> SeedOutput:
         """``reads``: concatenated ASCII (numpy uint8 on the host or a torch uint8 CUDA tensor);
         ``lengths``: uint32 per read (numpy or torch)."""
         n = int(lengths.numel() if hasattr(lengths, "numel") else len(lengths))
@@ -252,14 +256,15 @@ class Context:
         if isinstance(reads, np.ndarray):
             reads = np.ascontiguousarray(reads, dtype=np.uint8)
         o = SeedOpts(int(min_occ), int(bool(reseed)), int(reseed_len), int(reseed_occ), int(bs_role), int(kernel),
-                     int(bool(use_kmer)), int(blocks_per_cu), int(not stage), int(bool(unique_ext)))
+                     int(bool(use_kmer)), int(blocks_per_cu), int(not stage), int(bool(unique_ext)), int(seg_len))
         res = Result()
         rp = _ptr(reads) if n else None
         lp = _ptr(lengths) if n else None
         _check(self._lib.mbw_seed(self._h, rp, lp, n, int(min_seed_len), int(max_occ), C.byref(o),
                                   _stream_handle(stream), C.byref(res)))
         return SeedOutput(res.n_seeds, res.n_pos, res.seeds or 0, res.pos or 0, res.lines_smem, res.lines_locate,
-                          res.steps, res.lf_steps, res.ms_smem, res.ms_locate, res.ms_total, res.n_smem_launches, res, self)
+                          res.steps, res.lf_steps, res.ms_smem, res.ms_locate, res.ms_total, res.n_smem_launches,
+                          res.wave_iters, res.lane_iters, res.max_chain, res, self)
 
     def free(self):
         if self._h:

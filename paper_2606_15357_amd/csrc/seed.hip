@@ -34,20 +34,27 @@
 
 namespace {
 
-// a query string: read_id's bases [qbeg, qend) with its own (l, c); rlen / woff locate the packed read
-struct Query { uint32_t read_id, qbeg, qend, l, c, rlen, woff_lo, woff_hi; };
+// a query string: read_id's bases [qbeg, qend) with its own (l, c); rlen / woff locate the packed read.
+// A long query is split into segments: the segment [qbeg, send) of the query [q0, qend) reports the
+// SMEMs of P[q0, qend) whose start lies in [qbeg, send).  Those are the SMEMs of P[qbeg, qend) with
+// such a start, except that one starting at qbeg > q0 is an SMEM of the whole query only if it
+// cannot be extended to the left (SEG_CHECK: one backward step decides).
+#define SEG_CHECK 1u
+struct Query { uint32_t read_id, qbeg, qend, l, c, rlen, woff_lo, woff_hi, send, flags; };
 #define INVALID_READ 0xFFFFFFFFu   // unused slot of a per-wave output chunk
 struct SeedRec { uint32_t read_id, qbeg, qend, flags; uint64_t k, kr, s; };
 
 // control block (device): counters shared by the kernels of one call
 enum { C_WORK = 0, C_NSEEDS = 1, C_NSUBQ = 2, C_LINES = 3, C_STEPS = 4, C_KMER = 5, C_LFSTEPS = 6, C_SAREADS = 7,
-       C_LINES_LOC = 8, C_WORK2 = 9, C_MAXLEN = 10, C_ERR = 11, C_COUNT = 16 };
+       C_LINES_LOC = 8, C_WORK2 = 9, C_MAXLEN = 10, C_ERR = 11, C_WITER = 12, C_LITER = 13, C_MAXCHAIN = 14,
+       C_COUNT = 16 };
 
 struct SeedParams {
   const uint8_t *__restrict__ codes;   // one code per base (plain kernel)
   const uint64_t *__restrict__ offs;   // read offsets (n_reads + 1)
   const Query *__restrict__ queries;   // round 2; nullptr in round 1
   uint64_t n_queries;
+  uint32_t chunk;                      // queries per work-queue grab
   int l, c;                            // round 1 parameters
   int reseed, reseed_len, reseed_occ, round;
   int use_kmer;
@@ -188,24 +195,24 @@ __global__ void __launch_bounds__(PACK_BLOCK) k_pack_words(const uint8_t *__rest
 // ---------------------------------------------------------------------------------------------
 // wave-level work and output distribution.  Hot counters see one atomic per chunk (device-scope
 // atomics on a single address serialise).  All 64 lanes of a wave call these together.
-#define WORK_CHUNK 256
+#define WORK_CHUNK 256   // largest work chunk; short queues use smaller ones (see chunk_for)
 #define OUT_CHUNK 256
 
 // Give each lane with `want` the next item of the wave's current chunk (grabbing new chunks as
 // needed); returns the item or ~0 when the queue is exhausted.
 __device__ __forceinline__ uint64_t wave_take(bool want, uint64_t &cb, uint64_t &ce, unsigned long long *counter,
-                                              uint64_t total, int lane) {
+                                              uint64_t total, int lane, uint32_t chunk = WORK_CHUNK) {
   uint64_t m = __ballot(want);
   uint64_t res = ~0ull;
   const uint64_t below = (1ull << lane) - 1;
   while (m) {
     if (cb >= ce) {
       unsigned long long b0 = 0;
-      if (lane == 0) b0 = atomicAdd(counter, (unsigned long long)WORK_CHUNK);
+      if (lane == 0) b0 = atomicAdd(counter, (unsigned long long)chunk);
       b0 = __shfl(b0, 0);
       if (b0 >= total) { cb = ce = total; break; }
       cb = b0;
-      ce = b0 + WORK_CHUNK < total ? b0 + WORK_CHUNK : total;
+      ce = b0 + chunk < total ? b0 + chunk : total;
     }
     const uint64_t avail = ce - cb;
     const uint32_t rank = __popcll(m & below);
@@ -263,6 +270,7 @@ __device__ __forceinline__ void wave_emit(const SeedParams &P, int lane, bool em
     Query q;
     q.read_id = read_id; q.qbeg = e.i; q.qend = e.j; q.l = (e.j - e.i) / 2; q.c = (uint32_t)(e.s + 1);
     q.rlen = rlen; q.woff_lo = (uint32_t)woff; q.woff_hi = (uint32_t)(woff >> 32);
+    q.send = e.j; q.flags = 0;
     P.subq[qs] = q;
   }
 }
@@ -273,7 +281,7 @@ __device__ __forceinline__ void wave_close(const SeedParams &P, int lane, const 
     if (t < P.seed_cap) { SeedRec r; r.read_id = INVALID_READ; r.qbeg = r.qend = r.flags = 0; r.k = r.kr = r.s = 0; P.seeds[t] = r; }
   for (uint64_t t = wo.qb + lane; t < wo.qe; t += 64)
     if (t < P.subq_cap) {
-      Query q; q.read_id = INVALID_READ; q.qbeg = q.qend = q.l = q.rlen = q.woff_lo = q.woff_hi = 0; q.c = 1;
+      Query q; q.read_id = INVALID_READ; q.qbeg = q.qend = q.l = q.rlen = q.woff_lo = q.woff_hi = q.send = q.flags = 0; q.c = 1;
       P.subq[t] = q;
     }
 }
@@ -323,23 +331,29 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
     return ((nbits_at(w) >> b) & 1) ? 4 : (int)((word_at(w) >> (2 * b)) & 3);
   };
   const uint64_t tm = ix.n - 1;   // text length without $
-  uint32_t read_id = 0, qbeg = 0, qend = 0, l = 0, c = 1;
+  uint32_t read_id = 0, qbeg = 0, qend = 0, l = 0, c = 1, segend = 0;
+  bool segchk = false;            // the SMEM starting at qbeg still needs its left check (stage 8)
   int u = 0, i = 0, j = 0;
   uint64_t k = 0, kr = 0, s = 0, budget = 0;
   uint64_t wrow = 0, tp = 0;      // unique path: walk row (or sample index); text position of P[i]
   uint32_t wcnt = 0;              // unique path: LF steps taken (stage 4) or still to take (stage 7)
   bool fresh = false;
-  uint64_t n_lines = 0, n_steps = 0, n_kmer = 0;
+  uint64_t n_lines = 0, n_steps = 0, n_kmer = 0, n_iter = 0, n_busy = 0;
+  uint32_t chain = 0, max_chain = 0;   // iterations of the current query; longest so far
   uint64_t cb = 0, ce = 0;
   WaveOut wout = {0, 0, 0, 0};
   for (;;) {
     // ---- idle lanes take a query (its record is loaded in this iteration's memory phase)
     const bool want = st == ST_IDLE;
     if (__ballot(want)) {
-      const uint64_t t = wave_take(want, cb, ce, &P.ctl[C_WORK], P.n_queries, lane);
+      const uint64_t t = wave_take(want, cb, ce, &P.ctl[C_WORK], P.n_queries, lane, P.chunk);
       if (want) { if (t == ~0ull) st = ST_DRAINED; else { qi = t; st = ST_REC; } }
     }
     if (__ballot(st != ST_DRAINED) == 0) break;
+    ++n_iter;
+    n_busy += st != ST_DRAINED && st != ST_IDLE;
+    if (st == ST_REC) chain = 0;
+    if (st != ST_DRAINED && st != ST_IDLE) { ++chain; max_chain = chain > max_chain ? chain : max_chain; }
     // ---- active lanes: stage transitions up to the next memory action
     int act = ACT_DONE, a = 0;
     uint32_t code = 0;
@@ -358,25 +372,40 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
           }
           if (u == 5) { act = ACT_TEXT; break; }
           if (u == 6) { act = ACT_ISA; break; }
-          if (wcnt > 0) { act = ACT_LF; break; }        // u == 7
-          em = true; e.i = i; e.j = j; e.k = k; e.kr = wrow; e.s = 1;
+          if (u == 7) {
+            if (wcnt > 0) { act = ACT_LF; break; }
+            if (segchk && i == (int)qbeg) { segchk = false; kr = wrow; s = 1; u = 8; continue; }
+            em = true; e.i = i; e.j = j; e.k = k; e.kr = wrow; e.s = 1;
+            if (j == (int)qend) { act = ACT_DONE; break; }
+            u = 3; k = 0; kr = 0; s = ix.n; fresh = true;
+            continue;
+          }
+          // u == 8: left check of a segment's first SMEM [qbeg, j) with interval (k, kr, s)
+          a = base_at(i - 1);
+          if (a <= 3) { act = ACT_BWD; break; }
+          em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s;   // P[i-1] matches nothing
           if (j == (int)qend) { act = ACT_DONE; break; }
           u = 3; k = 0; kr = 0; s = ix.n; fresh = true;
           continue;
         }
         if (u == 2) {
-          if (j == (int)qend) { em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s; act = ACT_DONE; break; }
-          if (P.uniq && s == 1) { u = 4; wrow = k; wcnt = 0; continue; }
-          a = base_at(j);
-          if (a > 3) {                                  // forward extension fails on a non-ACGT base
+          const bool qe = j == (int)qend;
+          a = qe ? 4 : base_at(j);
+          if (!qe && P.uniq && s == 1) { u = 4; wrow = k; wcnt = 0; continue; }
+          if (a > 3) {                                  // end of the query, or a non-ACGT base: SMEM [i, j)
+            if (segchk && i == (int)qbeg) { segchk = false; u = 8; continue; }
             em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s;
+            if (qe) { act = ACT_DONE; break; }
             u = 3; k = 0; kr = 0; s = ix.n; fresh = true;
             continue;
           }
           act = ACT_FWD; break;
         }
         if (u == 1 && j < i) { u = 2; j = i + (int)l; fresh = false; continue; }
-        if (u == 3 && j <= i) { u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; continue; }
+        if (u == 3 && j <= i) {
+          if (j + 1 >= (int)segend) { act = ACT_DONE; break; }   // the next start belongs to the next segment
+          u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; continue;
+        }
         if (fresh && K > 0 && j - K + 1 >= (u == 1 ? i : i + 1)) {
           // k-mer P[j-K+1 .. j] from the packed read: its code is the bit field 2(j-K+1) .. 2(j+1)
           const int a0 = j - K + 1, w = a0 >> 5, b0 = a0 & 31;
@@ -389,7 +418,9 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
         fresh = false;
         a = base_at(j);
         if (a > 3) {                                    // BackStep fails on a non-ACGT base
-          if (j + (int)l < (int)qend) { u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; continue; }
+          if (j + (int)l < (int)qend && j + 1 < (int)segend) {
+            u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; continue;
+          }
           act = ACT_DONE; break;
         }
         act = ACT_BWD; break;
@@ -426,13 +457,10 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
     uint4 kent = make_uint4(0, 0, 0, 0);
     if (act == ACT_KMER) kent = ix.kmer[code];
     const int st_mem = st;
-    uint64_t r0 = 0, r1 = 0, r2 = 0;
     Query qrec;
     qrec.read_id = INVALID_READ; qrec.qbeg = qrec.qend = qrec.l = qrec.rlen = qrec.woff_lo = qrec.woff_hi = 0; qrec.c = 1;
-    if (st_mem == ST_REC) {
-      if (P.queries) qrec = P.queries[qi];
-      else { r0 = P.offs[qi]; r1 = P.offs[qi + 1]; r2 = R.woff[qi]; }
-    }
+    qrec.send = qrec.flags = 0;
+    if (st_mem == ST_REC) qrec = P.queries[qi];
     uint64_t g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0;
     uint32_t h0 = 0, h1 = 0, h2 = 0, h3 = 0, h4 = 0;
     if (STAGED && st_mem == ST_STAGE) {
@@ -469,12 +497,18 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
       } else {
         n_lines += two ? 2 : 1;
         ++n_steps;
-        if (ns >= c) {
+        if (u == 8) {                                     // left check: report unless P[i-1, j) occurs c times
+          if (ns < c) { em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s; }
+          if (j == (int)qend) st = ST_IDLE;
+          else { u = 3; k = 0; kr = 0; s = ix.n; fresh = true; }
+        } else if (ns >= c) {
           if (bwd) { k = nx; kr = ny; s = ns; j -= 1; }
           else { kr = nx; k = ny; s = ns; j += 1; }
         } else if (bwd) {                                 // BackStep failure: jump past j
-          if (j + (int)l < (int)qend) { u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; }
+          if (j + (int)l < (int)qend && j + 1 < (int)segend) { u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; }
           else st = ST_IDLE;
+        } else if (segchk && i == (int)qbeg) {           // forward failure at a segment's first SMEM
+          segchk = false; u = 8;
         } else {                                          // forward failure: report, then stage 3 from j
           em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s;
           u = 3; k = 0; kr = 0; s = ix.n; fresh = true;
@@ -535,13 +569,9 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
       mw[256 + lane] = g4; mn[256 + lane] = h4;
     }
     if (st_mem == ST_REC) {
-      if (P.queries) {
-        read_id = qrec.read_id; qbeg = qrec.qbeg; qend = qrec.qend; l = qrec.l; c = qrec.c;
-        rlen = qrec.rlen; wo = ((uint64_t)qrec.woff_hi << 32) | qrec.woff_lo;
-      } else {
-        read_id = (uint32_t)qi; qbeg = 0; qend = (uint32_t)(r1 - r0); l = (uint32_t)P.l; c = (uint32_t)P.c;
-        rlen = qend; wo = r2;
-      }
+      read_id = qrec.read_id; qbeg = qrec.qbeg; qend = qrec.qend; l = qrec.l; c = qrec.c;
+      rlen = qrec.rlen; wo = ((uint64_t)qrec.woff_hi << 32) | qrec.woff_lo;
+      segend = qrec.send; segchk = (qrec.flags & SEG_CHECK) != 0;
       nw = (rlen + 31) >> 5;
       // Algorithm 3 queues a string only if l - 1 < |P|
       const bool work = read_id != INVALID_READ && l >= 1 && l - 1 < qend - qbeg && (!STAGED || nw <= STAGE_WORDS);
@@ -556,9 +586,100 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
     wave_emit(P, lane, em, read_id, e, wout, rlen, wo);
   }
   wave_close(P, lane, wout);
+  if (lane == 0) atomicAdd(&P.ctl[C_WITER], (unsigned long long)n_iter);
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint32_t o = (uint32_t)__shfl_xor((int)max_chain, d);
+    max_chain = o > max_chain ? o : max_chain;
+  }
+  if (lane == 0) atomicMax(&P.ctl[C_MAXCHAIN], (unsigned long long)max_chain);
+  atomicAdd(&P.ctl[C_LITER], (unsigned long long)n_busy);
   atomicAdd(&P.ctl[C_LINES], (unsigned long long)(n_lines + n_kmer));
   atomicAdd(&P.ctl[C_STEPS], (unsigned long long)n_steps);
   atomicAdd(&P.ctl[C_KMER], (unsigned long long)n_kmer);
+}
+
+// ---------------------------------------------------------------------------------------------
+// length bins: queries of reads that fit the LDS staging area run in the staged kernel, the rest
+// (longest first) in the unstaged one
+
+#define STAGE_MAX (32 * STAGE_WORDS)
+
+__global__ void k_read_bins(const uint64_t *__restrict__ offs, uint64_t n, int stage, uint32_t *__restrict__ flag) {
+  for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < n; r += (uint64_t)gridDim.x * blockDim.x)
+    flag[r] = (stage && offs[r + 1] - offs[r] <= STAGE_MAX) ? 1u : 0u;
+}
+
+// stable partition of read ids by flag (short reads first); sort keys of the long ones (longest first)
+__global__ void k_read_partition(const uint64_t *__restrict__ offs, const uint32_t *__restrict__ flag,
+                                 const uint32_t *__restrict__ pos, uint64_t n, uint64_t nshort, uint32_t *__restrict__ ids,
+                                 uint32_t *__restrict__ lkey) {
+  for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < n; r += (uint64_t)gridDim.x * blockDim.x) {
+    if (flag[r]) ids[pos[r]] = (uint32_t)r;
+    else {
+      const uint64_t t = r - pos[r];
+      ids[nshort + t] = (uint32_t)r;
+      lkey[t] = 65535u - (uint32_t)(offs[r + 1] - offs[r]);
+    }
+  }
+}
+
+// round-1 query records of reads ids[0..n)
+__global__ void k_make_queries(const uint32_t *__restrict__ ids, uint64_t n, const uint64_t *__restrict__ offs,
+                               const uint64_t *__restrict__ woff, uint32_t l, uint32_t c, Query *__restrict__ q) {
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < n; t += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t r = ids[t];
+    const uint32_t len = (uint32_t)(offs[r + 1] - offs[r]);
+    const uint64_t wo = woff[r];
+    Query x;
+    x.read_id = r; x.qbeg = 0; x.qend = len; x.l = l; x.c = c; x.rlen = len;
+    x.woff_lo = (uint32_t)wo; x.woff_hi = (uint32_t)(wo >> 32);
+    x.send = len; x.flags = 0;
+    q[t] = x;
+  }
+}
+
+// round-2 queries: short (staged) and long bins; unused slots of the per-wave output chunks dropped
+__global__ void k_query_bins(const Query *__restrict__ q, uint64_t n, int stage, uint32_t *__restrict__ fs,
+                             uint32_t *__restrict__ fl) {
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < n; t += (uint64_t)gridDim.x * blockDim.x) {
+    const bool valid = q[t].read_id != INVALID_READ;
+    const bool sh = stage && q[t].rlen <= STAGE_MAX;
+    fs[t] = (valid && sh) ? 1u : 0u;
+    fl[t] = (valid && !sh) ? 1u : 0u;
+  }
+}
+
+// segments of long queries: [qbeg, qend) becomes ceil((qend - qbeg) / seg) queries, each reporting
+// the SMEMs that start in its own seg bases (every segment after the first checks its first SMEM)
+__global__ void k_seg_count(const Query *__restrict__ q, uint64_t n, uint32_t seg, uint32_t *__restrict__ cnt) {
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < n; t += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t len = q[t].qend > q[t].qbeg ? q[t].qend - q[t].qbeg : 0u;
+    cnt[t] = len > seg ? (len + seg - 1) / seg : 1u;
+  }
+}
+
+__global__ void k_seg_write(const Query *__restrict__ q, uint64_t n, uint32_t seg, const uint32_t *__restrict__ cnt,
+                            const uint32_t *__restrict__ off, Query *__restrict__ out) {
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < n; t += (uint64_t)gridDim.x * blockDim.x) {
+    const Query x = q[t];
+    const uint32_t m = cnt[t];
+    for (uint32_t g = 0; g < m; ++g) {
+      Query y = x;
+      y.qbeg = x.qbeg + g * seg;
+      y.send = g + 1 < m ? y.qbeg + seg : x.send;
+      y.flags = g > 0 ? (x.flags | SEG_CHECK) : x.flags;
+      out[off[t] + g] = y;
+    }
+  }
+}
+
+__global__ void k_query_partition(const Query *__restrict__ in, const uint32_t *__restrict__ fs, const uint32_t *__restrict__ ps,
+                                  const uint32_t *__restrict__ fl, const uint32_t *__restrict__ pl, uint64_t n,
+                                  uint64_t nshort, Query *__restrict__ out) {
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < n; t += (uint64_t)gridDim.x * blockDim.x) {
+    if (fs[t]) out[ps[t]] = in[t];
+    else if (fl[t]) out[nshort + pl[t]] = in[t];
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -869,7 +990,8 @@ struct mbw_ctx {
   int n_cu;
   struct Buf { void *p = nullptr; size_t bytes = 0; };   // grow-only device buffers
   Buf codes, ascii, lens, offs, raw, subq, keys0, keys1, vals0, vals1, flag, idx, seeds, npos, posoff, xrows, pos, pos2,
-      keep, kidx, temp, ctl, pwords, pnmask, woffs, nwords, wread;
+      keep, kidx, temp, ctl, pwords, pnmask, woffs, nwords, wread, q1, q2, bf0, bf1, bp0, bp1, bid0, bid1, bk0, bk1, q1s,
+      q2s, sc0, sc1;
   hipEvent_t ev[8];
   unsigned long long host_ctl[C_COUNT];
   float ms_smem;
@@ -914,7 +1036,9 @@ extern "C" void mbw_ctx_free(mbw_ctx *c) {
   (void)hipSetDevice(c->device);
   mbw_ctx::Buf *bs[] = {&c->codes, &c->ascii, &c->lens, &c->offs, &c->raw, &c->subq, &c->keys0, &c->keys1, &c->vals0,
                         &c->vals1, &c->flag, &c->idx, &c->seeds, &c->npos, &c->posoff, &c->xrows, &c->pos, &c->pos2,
-                        &c->keep, &c->kidx, &c->temp, &c->ctl, &c->pwords, &c->pnmask, &c->woffs, &c->nwords, &c->wread};
+                        &c->keep, &c->kidx, &c->temp, &c->ctl, &c->pwords, &c->pnmask, &c->woffs, &c->nwords, &c->wread,
+                        &c->q1, &c->q2, &c->bf0, &c->bf1, &c->bp0, &c->bp1, &c->bid0, &c->bid1, &c->bk0, &c->bk1,
+                        &c->q1s, &c->q2s, &c->sc0, &c->sc1};
   for (auto *b : bs) if (b->p) (void)hipFree(b->p);
   for (int t = 0; t < 8; ++t) (void)hipEventDestroy(c->ev[t]);
   delete c;
@@ -961,6 +1085,13 @@ static int launch_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const Read
 static int run_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const ReadWords &R, const mbw_seed_opts &o, bool staged,
                     hipStream_t st) {
   if (P.n_queries == 0) return 0;
+  // at least ~8 grabs per wave of the persistent grid, so that long queries (queued longest
+  // first) spread over the whole chip
+  {
+    const uint64_t waves = (uint64_t)c->n_cu * 16;
+    uint64_t ch = P.n_queries / (waves * 8);
+    P.chunk = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(WORK_CHUNK, ch));
+  }
   TRY(hipEventRecord(c->ev[1], st));
   int r = launch_smem(c, v, P, R, o, staged, st);
   if (r) return r;
@@ -970,6 +1101,47 @@ static int run_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const ReadWor
   TRY(hipEventElapsedTime(&ms, c->ev[1], c->ev[2]));
   c->ms_smem += ms;
   c->n_smem_launches++;
+  return 0;
+}
+
+// one seeding round: the staged kernel over qs[0, ns), the unstaged one over ql[0, nl); each launch
+// starts its own work counter
+static int run_binned(mbw_ctx *c, const IndexView &v, SeedParams &P, const ReadWords &R, const mbw_seed_opts &o,
+                      const Query *qs, uint64_t ns, const Query *ql, uint64_t nl, hipStream_t st) {
+  if (ns) {
+    TRY(hipMemsetAsync(P.ctl + C_WORK, 0, 8, st));
+    P.queries = qs; P.n_queries = ns;
+    int r = run_smem(c, v, P, R, o, true, st);
+    if (r) return r;
+  }
+  if (nl) {
+    TRY(hipMemsetAsync(P.ctl + C_WORK, 0, 8, st));
+    P.queries = ql; P.n_queries = nl;
+    int r = run_smem(c, v, P, R, o, false, st);
+    if (r) return r;
+  }
+  return 0;
+}
+
+// split the n queries of q into segments (ctx buffer `out`); returns the segment count in *nseg
+static int segment_queries(mbw_ctx *c, const Query *q, uint64_t n, uint32_t seg, mbw_ctx::Buf &out, uint64_t *nseg,
+                           hipStream_t st) {
+  *nseg = 0;
+  if (!n) return 0;
+  GROW(c->sc0, (n + 1) * 4); GROW(c->sc1, (n + 1) * 4);
+  uint32_t *cnt = (uint32_t *)c->sc0.p, *off = (uint32_t *)c->sc1.p;
+  k_seg_count<<<grid_for(n), 256, 0, st>>>(q, n, seg, cnt);
+  TRY(hipGetLastError());
+  int r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, cnt, off, n, st); });
+  if (r) return r;
+  uint32_t tail[2] = {0, 0};
+  TRY(hipMemcpyAsync(&tail[0], cnt + n - 1, 4, hipMemcpyDeviceToHost, st));
+  TRY(hipMemcpyAsync(&tail[1], off + n - 1, 4, hipMemcpyDeviceToHost, st));
+  TRY(hipStreamSynchronize(st));
+  *nseg = (uint64_t)tail[0] + tail[1];
+  GROW(out, (*nseg + 1) * sizeof(Query));
+  k_seg_write<<<grid_for(n), 256, 0, st>>>(q, n, seg, cnt, off, (Query *)out.p);
+  TRY(hipGetLastError());
   return 0;
 }
 
@@ -1037,7 +1209,6 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     k_encode<<<grid_for(total), 256, 0, st>>>(dreads, total, o.bs_role, (uint8_t *)c->codes.p);
     TRY(hipGetLastError());
   }
-  const bool staged = coop && maxlen <= 32 * STAGE_WORDS && !o.no_stage;
   ReadWords R;
   R.pw = nullptr; R.pn = nullptr; R.woff = nullptr;
   if (coop) {
@@ -1086,6 +1257,47 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     P.rshift = pow2(ix->sa_sample) ? lg(ix->sa_sample) : 0;
     P.rishift = pow2(ix->isa_sample) ? lg(ix->isa_sample) : 0;
   }
+  // round-1 query records: reads that fit the LDS staging area first, then the others, longest first
+  uint64_t nshort1 = 0, nlong1 = 0;
+  const Query *q1 = nullptr;
+  const uint32_t seg_len = o.seg_len > 0 ? (uint32_t)std::max(32, o.seg_len) : 256u;
+  if (coop) {
+    GROW(c->q1, (n_reads + 1) * sizeof(Query));
+    GROW(c->bf0, (n_reads + 1) * 4); GROW(c->bp0, (n_reads + 1) * 4);
+    GROW(c->bid0, (n_reads + 1) * 4); GROW(c->bid1, (n_reads + 1) * 4);
+    GROW(c->bk0, (n_reads + 1) * 4); GROW(c->bk1, (n_reads + 1) * 4);
+    uint32_t *flag1 = (uint32_t *)c->bf0.p, *pos1 = (uint32_t *)c->bp0.p, *ids = (uint32_t *)c->bid0.p;
+    k_read_bins<<<grid_for(n_reads), 256, 0, st>>>(offs, n_reads, o.no_stage ? 0 : 1, flag1);
+    TRY(hipGetLastError());
+    r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, flag1, pos1, n_reads, st); });
+    if (r) return r;
+    uint32_t lastf = 0, lastp = 0;
+    TRY(hipMemcpyAsync(&lastf, flag1 + n_reads - 1, 4, hipMemcpyDeviceToHost, st));
+    TRY(hipMemcpyAsync(&lastp, pos1 + n_reads - 1, 4, hipMemcpyDeviceToHost, st));
+    TRY(hipStreamSynchronize(st));
+    nshort1 = (uint64_t)lastp + lastf;
+    const uint64_t nlong = n_reads - nshort1;
+    k_read_partition<<<grid_for(n_reads), 256, 0, st>>>(offs, flag1, pos1, n_reads, nshort1, ids, (uint32_t *)c->bk0.p);
+    TRY(hipGetLastError());
+    const uint32_t *long_ids = ids + nshort1;
+    if (nlong > 1) {
+      hipcub::DoubleBuffer<uint32_t> bk((uint32_t *)c->bk0.p, (uint32_t *)c->bk1.p);
+      hipcub::DoubleBuffer<uint32_t> bv(ids + nshort1, (uint32_t *)c->bid1.p);
+      r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceRadixSort::SortPairs(tp, tb, bk, bv, nlong, 0, 16, st); });
+      if (r) return r;
+      long_ids = bv.Current();
+    }
+    Query *qq = (Query *)c->q1.p;
+    if (nshort1)
+      k_make_queries<<<grid_for(nshort1), 256, 0, st>>>(ids, nshort1, offs, R.woff, (uint32_t)min_seed_len, (uint32_t)o.min_occ, qq);
+    if (nlong)
+      k_make_queries<<<grid_for(nlong), 256, 0, st>>>(long_ids, nlong, offs, R.woff, (uint32_t)min_seed_len, (uint32_t)o.min_occ,
+                                                      qq + nshort1);
+    TRY(hipGetLastError());
+    q1 = qq;
+    r = segment_queries(c, qq + nshort1, nlong, seg_len, c->q1s, &nlong1, st);
+    if (r) return r;
+  }
   unsigned long long n1 = 0, nq = 0;
   for (int attempt = 0;; ++attempt) {
     GROW(c->raw, seed_cap * sizeof(SeedRec));
@@ -1094,7 +1306,8 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     subq_cap = c->subq.bytes / sizeof(Query);
     P.seeds = (SeedRec *)c->raw.p; P.seed_cap = seed_cap; P.subq = (Query *)c->subq.p; P.subq_cap = subq_cap;
     TRY(hipMemsetAsync(ctl, 0, 8 * sizeof(unsigned long long), st));
-    r = run_smem(c, v, P, R, o, staged, st);
+    if (coop) r = run_binned(c, v, P, R, o, q1, nshort1, (const Query *)c->q1s.p, nlong1, st);
+    else r = run_smem(c, v, P, R, o, false, st);
     if (r) return r;
     TRY(hipMemcpyAsync(&n1, ctl + C_NSEEDS, 8, hipMemcpyDeviceToHost, st));
     TRY(hipMemcpyAsync(&nq, ctl + C_NSUBQ, 8, hipMemcpyDeviceToHost, st));
@@ -1108,15 +1321,36 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   TRY(hipMemcpyAsync(stats1, ctl + C_LINES, 3 * 8, hipMemcpyDeviceToHost, st));
   unsigned long long ntot = n1;
   if (coop && o.reseed && nq > 0) {
+    // round-2 queries by bin (unused chunk slots dropped)
+    GROW(c->q2, (nq + 1) * sizeof(Query));
+    GROW(c->bf0, (nq + 1) * 4); GROW(c->bf1, (nq + 1) * 4); GROW(c->bp0, (nq + 1) * 4); GROW(c->bp1, (nq + 1) * 4);
+    uint32_t *fs = (uint32_t *)c->bf0.p, *fl = (uint32_t *)c->bf1.p, *ps = (uint32_t *)c->bp0.p, *pl = (uint32_t *)c->bp1.p;
+    const Query *sq = (const Query *)c->subq.p;
+    k_query_bins<<<grid_for(nq), 256, 0, st>>>(sq, nq, o.no_stage ? 0 : 1, fs, fl);
+    TRY(hipGetLastError());
+    r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, fs, ps, nq, st); });
+    if (r) return r;
+    r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, fl, pl, nq, st); });
+    if (r) return r;
+    uint32_t tail[4] = {0, 0, 0, 0};
+    TRY(hipMemcpyAsync(&tail[0], fs + nq - 1, 4, hipMemcpyDeviceToHost, st));
+    TRY(hipMemcpyAsync(&tail[1], ps + nq - 1, 4, hipMemcpyDeviceToHost, st));
+    TRY(hipMemcpyAsync(&tail[2], fl + nq - 1, 4, hipMemcpyDeviceToHost, st));
+    TRY(hipMemcpyAsync(&tail[3], pl + nq - 1, 4, hipMemcpyDeviceToHost, st));
+    TRY(hipStreamSynchronize(st));
+    const uint64_t nshort2 = (uint64_t)tail[0] + tail[1], nlong2 = (uint64_t)tail[2] + tail[3];
+    k_query_partition<<<grid_for(nq), 256, 0, st>>>(sq, fs, ps, fl, pl, nq, nshort2, (Query *)c->q2.p);
+    TRY(hipGetLastError());
+    uint64_t nlong2s = 0;
+    r = segment_queries(c, (const Query *)c->q2.p + nshort2, nlong2, seg_len, c->q2s, &nlong2s, st);
+    if (r) return r;
     SeedParams P2 = P;
-    P2.queries = (const Query *)c->subq.p; P2.n_queries = nq; P2.round = 2;
+    P2.round = 2;
     for (int attempt = 0;; ++attempt) {
       TRY(hipMemcpyAsync(ctl + C_NSEEDS, &n1, 8, hipMemcpyHostToDevice, st));
-      unsigned long long zero = 0;
-      TRY(hipMemcpyAsync(ctl + C_WORK, &zero, 8, hipMemcpyHostToDevice, st));
       TRY(hipMemcpyAsync(ctl + C_LINES, stats1, 3 * 8, hipMemcpyHostToDevice, st));
       P2.seeds = (SeedRec *)c->raw.p; P2.seed_cap = c->raw.bytes / sizeof(SeedRec);
-      r = run_smem(c, v, P2, R, o, staged, st);
+      r = run_binned(c, v, P2, R, o, (const Query *)c->q2.p, nshort2, (const Query *)c->q2s.p, nlong2s, st);
       if (r) return r;
       TRY(hipMemcpyAsync(&ntot, ctl + C_NSEEDS, 8, hipMemcpyDeviceToHost, st));
       TRY(hipStreamSynchronize(st));
@@ -1244,6 +1478,9 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   out->ms_locate = t_loc;
   out->ms_total = t_tot;
   out->n_smem_launches = c->n_smem_launches;
+  out->wave_iters = c->host_ctl[C_WITER];
+  out->lane_iters = c->host_ctl[C_LITER];
+  out->max_chain = c->host_ctl[C_MAXCHAIN];
   return MBW_OK;
 }
 

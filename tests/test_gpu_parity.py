@@ -109,8 +109,10 @@ def test_index_structure(name, r, K, ri):
 
 
 @pytest.mark.parametrize("name", sorted(TINY))
-@pytest.mark.parametrize("kernel", [0, 1])
-def test_tiny_seeding(name, kernel):
+@pytest.mark.parametrize("kernel,variant", [(0, "default"), (1, "default"), (0, "segmented")])
+def test_tiny_seeding(name, kernel, variant):
+    """Tiny references, reads up to 60 bases, (l, c) in {(3,1), (5,1), (4,2), (2,3)}, both rounds;
+    'segmented' runs every read unstaged in 32-base segments."""
     R = TINY[name]
     rng = np.random.default_rng(3)
     reads = []
@@ -134,8 +136,9 @@ def test_tiny_seeding(name, kernel):
             for reseed in (False, True):
                 exp = ox.seed(rs.seq, rs.offsets, min_len=l, min_occ=c, max_occ=10 ** 6, reseed=reseed,
                               reseed_len=2 * l, reseed_occ=3)
+                extra = dict(stage=False, seg_len=32) if variant == "segmented" else {}
                 out, seeds, pos = gpu_seed(idx, rs, min_seed_len=l, min_occ=c, max_occ=10 ** 6, reseed=reseed,
-                                           reseed_len=2 * l, reseed_occ=3, kernel=kernel)
+                                           reseed_len=2 * l, reseed_occ=3, kernel=kernel, **extra)
                 compare_with_oracle(seeds, pos, exp)
         idx.free()
 
@@ -208,14 +211,15 @@ def test_edge_cases(cfg0):
 
 
 def test_ragged_lengths_and_occ(cfg0):
-    """Ragged read lengths 1..600, c in {1,2,3}, max_occ small enough to skip repeats."""
+    """Ragged read lengths 1..600 (staged and unstaged length bins, long reads in segments of 256,
+    64 and 32 bases), c in {1,2,3}, max_occ small enough to skip repeats."""
     ref, _, ox, _ = cfg0
     rs = synth.reads_uniform_len(ref, 3000, 1, 600, seed=77)
     idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=10)
     for c, mo in [(1, 3), (2, 500), (3, 20)]:
-        for kernel in (0, 1):
-            out, seeds, pos = gpu_seed(idx, rs, min_occ=c, max_occ=mo, kernel=kernel)
-            exp = ox.seed(rs.seq, rs.offsets, min_occ=c, max_occ=mo)
+        exp = ox.seed(rs.seq, rs.offsets, min_occ=c, max_occ=mo)
+        for kernel, seg in ((0, 0), (1, 0), (0, 64), (0, 32)):
+            out, seeds, pos = gpu_seed(idx, rs, min_occ=c, max_occ=mo, kernel=kernel, seg_len=seg)
             compare_with_oracle(seeds, pos, exp)
     idx.free()
 
