@@ -28,6 +28,7 @@ extern "C" {
 #define MBW_E_IO       -4   /* file could not be opened, read or written                          */
 #define MBW_E_FORMAT   -5   /* index file has a bad magic, version, size or checksum              */
 #define MBW_E_CAPACITY -6   /* a caller-provided buffer is too small (required sizes reported)     */
+#define MBW_E_BUSY     -7   /* serving: queue full on submit, or request not finished on wait      */
 
 const char *mbw_strerror(int code);
 /* Message of the calling thread's last failed call ("" if none).  Valid until the next call. */
@@ -180,6 +181,15 @@ int mbw_seed(mbw_ctx *ctx, const uint8_t *reads, const uint32_t *lengths, uint64
 /* Copy a result to host buffers (seeds: n_seeds records, pos: n_pos values; either may be NULL). */
 int mbw_result_download(mbw_ctx *ctx, const mbw_result *res, mbw_seed_t *seeds, uint64_t *pos);
 
+/* Autotuner for the wave kernels: runs mbw_seed on this batch with candidate schedules (length
+ * binning on or off, segment lengths 128/256/1024, persistent blocks per CU at the occupancy limit
+ * or 2, unique-match extension on or off), each once untimed and once timed, and writes the
+ * fastest to *best (other fields copied from *base, or the defaults when base is NULL) and its
+ * device time to *best_ms.  Every candidate yields the same seeds.  Blocking; uses ctx's buffers
+ * (its last result is overwritten).  Errors: as mbw_seed. */
+int mbw_tune(mbw_ctx *ctx, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads, int min_seed_len,
+             int max_occ, const mbw_seed_opts *base, void *stream, mbw_seed_opts *best, float *best_ms);
+
 /* Map a T position of a match of length len to (strand, reference position): pos < |R| is the
  * forward strand at pos; otherwise the reverse strand at 2|R| - pos - len.  (Bisulfite index:
  * the four copies of length |R| map to their source coordinates likewise.) */
@@ -194,6 +204,53 @@ int mbw_pos_to_ref(const mbw_index *idx, uint64_t pos, uint32_t len, int *strand
  * Both allocate and free their own device memory.  Errors: MBW_E_INVAL, MBW_E_NOMEM, MBW_E_HIP. */
 int mbw_probe_copy(int device, uint64_t bytes, float *ms);
 int mbw_probe_gather(int device, uint64_t bytes, int iters, double *lines_per_s, float *ms);
+
+/* ---- serving -------------------------------------------------------------------------------
+ * A request loop over one resident index.  Submitted requests are queued (host copies of their
+ * reads); admission is bounded by the bases waiting in the queue.  n_workers threads each own a
+ * seeding context and a HIP stream; a free worker takes queued requests in arrival order into one
+ * device batch (up to max_batch_reads reads and max_batch_bases bases; a larger single request
+ * runs alone), so requests that arrive while other batches run join the next batch at once, and
+ * the batches of different workers overlap on the device.  Each request's result equals what
+ * mbw_seed returns for that request alone (read ids relative to the request). */
+typedef struct mbw_server mbw_server;
+
+typedef struct {
+  int n_workers;              /* batches in flight at once (1..8) */
+  uint64_t max_batch_reads;   /* batch budget: reads ... */
+  uint64_t max_batch_bases;   /* ... and bases */
+  uint64_t max_queued_bases;  /* admission: submit returns MBW_E_BUSY when the queue is not empty and
+                                 would exceed this many bases */
+  int min_seed_len, max_occ;  /* as mbw_seed */
+  mbw_seed_opts opts;         /* as mbw_seed */
+  int device;                 /* must be the index's device */
+} mbw_serve_cfg;
+
+typedef struct {
+  uint64_t n_seeds, n_pos;
+  const mbw_seed_t *seeds;    /* host memory owned by the server until mbw_serve_release; read_id
+                                 counts from the request's first read, pos_off from its first
+                                 position */
+  const uint64_t *pos;
+  double t_submit, t_start, t_done;   /* seconds since mbw_serve_open (steady clock) */
+  uint64_t batch_id, batch_reads;     /* the device batch that carried the request */
+} mbw_serve_result;
+
+/* Start the workers.  The index must outlive the server.  Errors: MBW_E_INVAL, MBW_E_NOMEM, MBW_E_HIP. */
+int mbw_serve_open(const mbw_index *idx, const mbw_serve_cfg *cfg, mbw_server **out);
+/* Queue a request (host pointers, copied before return; lengths < 65536).  Non-blocking.
+ * Errors: MBW_E_INVAL, MBW_E_BUSY (queue full: retry later), MBW_E_NOMEM. */
+int mbw_serve_submit(mbw_server *s, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads,
+                     uint64_t *ticket);
+/* Wait up to timeout_ms (< 0: forever) for a request; MBW_E_BUSY if it is not finished by then,
+ * else its result (valid until mbw_serve_release) or the error its batch returned. */
+int mbw_serve_wait(mbw_server *s, uint64_t ticket, int timeout_ms, mbw_serve_result *out);
+/* Free a finished request's result.  Errors: MBW_E_INVAL (unknown ticket), MBW_E_BUSY (unfinished). */
+int mbw_serve_release(mbw_server *s, uint64_t ticket);
+/* Counters: device batches run, reads in them, requests waiting. */
+int mbw_serve_stats(mbw_server *s, uint64_t *batches, uint64_t *batch_reads, uint64_t *queued);
+/* Finish every queued request, stop the workers and free the server. */
+void mbw_serve_close(mbw_server *s);
 
 #ifdef __cplusplus
 }

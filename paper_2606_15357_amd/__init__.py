@@ -25,6 +25,7 @@ MBW_E_HIP = -3
 MBW_E_IO = -4
 MBW_E_FORMAT = -5
 MBW_E_CAPACITY = -6
+MBW_E_BUSY = -7
 
 KERNEL_COOP = 0
 KERNEL_PLAIN = 1
@@ -34,7 +35,9 @@ SEED_ROUND2 = 2
 # the symbols include/mbw.h declares
 EXPORTS = ["mbw_strerror", "mbw_last_error", "mbw_index_build", "mbw_index_save", "mbw_index_load",
            "mbw_index_free", "mbw_index_info", "mbw_index_device_arrays", "mbw_ctx_create", "mbw_ctx_free",
-           "mbw_seed", "mbw_result_download", "mbw_pos_to_ref", "mbw_probe_copy", "mbw_probe_gather"]
+           "mbw_seed", "mbw_result_download", "mbw_pos_to_ref", "mbw_probe_copy", "mbw_probe_gather", "mbw_tune",
+           "mbw_serve_open", "mbw_serve_submit", "mbw_serve_wait", "mbw_serve_release", "mbw_serve_stats",
+           "mbw_serve_close"]
 
 
 class MbwError(RuntimeError):
@@ -59,6 +62,18 @@ class SeedOpts(C.Structure):
     _fields_ = [("min_occ", C.c_int), ("reseed", C.c_int), ("reseed_len", C.c_int), ("reseed_occ", C.c_int),
                 ("bs_role", C.c_int), ("kernel", C.c_int), ("use_kmer", C.c_int), ("blocks_per_cu", C.c_int),
                 ("no_stage", C.c_int), ("unique_ext", C.c_int), ("seg_len", C.c_int)]
+
+
+class ServeCfg(C.Structure):
+    _fields_ = [("n_workers", C.c_int), ("max_batch_reads", C.c_uint64), ("max_batch_bases", C.c_uint64),
+                ("max_queued_bases", C.c_uint64), ("min_seed_len", C.c_int), ("max_occ", C.c_int),
+                ("opts", SeedOpts), ("device", C.c_int)]
+
+
+class ServeResult(C.Structure):
+    _fields_ = [("n_seeds", C.c_uint64), ("n_pos", C.c_uint64), ("seeds", C.c_void_p), ("pos", C.c_void_p),
+                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
+                ("batch_id", C.c_uint64), ("batch_reads", C.c_uint64)]
 
 
 class Result(C.Structure):
@@ -105,6 +120,14 @@ def load_library():
     L.mbw_pos_to_ref.argtypes = [vp, u64, C.c_uint32, C.POINTER(C.c_int), C.POINTER(C.c_uint64)]
     L.mbw_probe_copy.argtypes = [i32, u64, C.POINTER(C.c_float)]
     L.mbw_probe_gather.argtypes = [i32, u64, i32, C.POINTER(C.c_double), C.POINTER(C.c_float)]
+    L.mbw_tune.argtypes = [vp, vp, vp, u64, i32, i32, C.POINTER(SeedOpts), vp, C.POINTER(SeedOpts), C.POINTER(C.c_float)]
+    L.mbw_serve_open.argtypes = [vp, C.POINTER(ServeCfg), C.POINTER(vp)]
+    L.mbw_serve_submit.argtypes = [vp, vp, vp, u64, C.POINTER(C.c_uint64)]
+    L.mbw_serve_wait.argtypes = [vp, u64, i32, C.POINTER(ServeResult)]
+    L.mbw_serve_release.argtypes = [vp, u64]
+    L.mbw_serve_stats.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+    L.mbw_serve_close.argtypes = [vp]
+    L.mbw_serve_close.restype = None
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
@@ -266,6 +289,21 @@ class Context:
                           res.steps, res.lf_steps, res.ms_smem, res.ms_locate, res.ms_total, res.n_smem_launches,
                           res.wave_iters, res.lane_iters, res.max_chain, res, self)
 
+    def tune(self, reads, lengths, min_seed_len: int = 19, max_occ: int = 500, stream=None, **base) -> dict:
+        """Time candidate schedules on this batch (``mbw_tune``); returns the fastest as keyword
+        arguments for :meth:`seed` plus ``ms`` (its device time)."""
+        n = int(lengths.numel() if hasattr(lengths, "numel") else len(lengths))
+        b = SeedOpts(int(base.get("min_occ", 1)), int(bool(base.get("reseed", True))), int(base.get("reseed_len", 38)),
+                     int(base.get("reseed_occ", 10)), int(base.get("bs_role", 0)), KERNEL_COOP,
+                     int(bool(base.get("use_kmer", True))), 0, 0, 1, 0)
+        best = SeedOpts()
+        ms = C.c_float()
+        _check(self._lib.mbw_tune(self._h, _ptr(reads) if n else None, _ptr(lengths) if n else None, n,
+                                  int(min_seed_len), int(max_occ), C.byref(b), _stream_handle(stream), C.byref(best),
+                                  C.byref(ms)))
+        return dict(stage=not best.no_stage, seg_len=best.seg_len, blocks_per_cu=best.blocks_per_cu,
+                    unique_ext=bool(best.unique_ext), ms=ms.value)
+
     def free(self):
         if self._h:
             self._lib.mbw_ctx_free(self._h)
@@ -303,3 +341,70 @@ def canonical(seeds: np.ndarray, pos: np.ndarray):
     chunks = [np.sort(pos[int(o):int(o) + int(c)]) for o, c in zip(s["pos_off"], s["npos"])]
     flat = np.concatenate(chunks) if chunks else np.zeros(0, np.uint64)
     return s, flat
+
+
+class Server:
+    """Request loop over a resident index (``mbw_serve_*``): submit reads, wait for each
+    request's seeds and positions; batches of several requests overlap on the device."""
+
+    def __init__(self, index: Index, n_workers: int = 2, max_batch_reads: int = 1 << 20,
+                 max_batch_bases: int = 1 << 28, max_queued_bases: int = 1 << 32, min_seed_len: int = 19,
+                 max_occ: int = 500, **opts):
+        self._lib = load_library()
+        self.index = index
+        o = SeedOpts(int(opts.get("min_occ", 1)), int(bool(opts.get("reseed", True))), int(opts.get("reseed_len", 38)),
+                     int(opts.get("reseed_occ", 10)), int(opts.get("bs_role", 0)), KERNEL_COOP,
+                     int(bool(opts.get("use_kmer", True))), int(opts.get("blocks_per_cu", 0)),
+                     int(not opts.get("stage", True)), int(bool(opts.get("unique_ext", True))), int(opts.get("seg_len", 0)))
+        cfg = ServeCfg(int(n_workers), int(max_batch_reads), int(max_batch_bases), int(max_queued_bases),
+                       int(min_seed_len), int(max_occ), o, int(index.info()["device"]))
+        h = C.c_void_p()
+        _check(self._lib.mbw_serve_open(index._h, C.byref(cfg), C.byref(h)))
+        self._h = h
+
+    def submit(self, reads: np.ndarray, lengths: np.ndarray):
+        """Queue a request; returns its ticket, or None when the queue is full (MBW_E_BUSY)."""
+        reads = np.ascontiguousarray(reads, dtype=np.uint8)
+        lengths = np.ascontiguousarray(lengths, dtype=np.uint32)
+        t = C.c_uint64()
+        rc = self._lib.mbw_serve_submit(self._h, reads.ctypes.data if reads.size else None,
+                                        lengths.ctypes.data if lengths.size else None, lengths.size, C.byref(t))
+        if rc == MBW_E_BUSY:
+            return None
+        _check(rc)
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1, release: bool = True):
+        """(seeds, positions, timing dict) of a request, or None if not finished within timeout_ms."""
+        r = ServeResult()
+        rc = self._lib.mbw_serve_wait(self._h, int(ticket), int(timeout_ms), C.byref(r))
+        if rc == MBW_E_BUSY:
+            return None
+        _check(rc)
+        seeds = np.zeros(r.n_seeds, dtype=SEED_DTYPE)
+        pos = np.zeros(r.n_pos, dtype=np.uint64)
+        if r.n_seeds:
+            C.memmove(seeds.ctypes.data, r.seeds, r.n_seeds * SEED_DTYPE.itemsize)
+        if r.n_pos:
+            C.memmove(pos.ctypes.data, r.pos, r.n_pos * 8)
+        info = dict(t_submit=r.t_submit, t_start=r.t_start, t_done=r.t_done, batch_id=r.batch_id,
+                    batch_reads=r.batch_reads)
+        if release:
+            _check(self._lib.mbw_serve_release(self._h, int(ticket)))
+        return seeds, pos, info
+
+    def stats(self):
+        b, r, q = C.c_uint64(), C.c_uint64(), C.c_uint64()
+        _check(self._lib.mbw_serve_stats(self._h, C.byref(b), C.byref(r), C.byref(q)))
+        return dict(batches=b.value, batch_reads=r.value, queued=q.value)
+
+    def close(self):
+        if self._h:
+            self._lib.mbw_serve_close(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

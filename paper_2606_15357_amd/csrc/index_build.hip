@@ -400,6 +400,7 @@ extern "C" const char *mbw_strerror(int code) {
     case MBW_E_IO: return "I/O error";
     case MBW_E_FORMAT: return "bad index file format";
     case MBW_E_CAPACITY: return "buffer too small";
+    case MBW_E_BUSY: return "busy";
     default: return "unknown error";
   }
 }

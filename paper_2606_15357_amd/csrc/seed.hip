@@ -1484,6 +1484,42 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   return MBW_OK;
 }
 
+// ---------------------------------------------------------------------------------------------
+// autotuner: every candidate schedule gives the same seeds; each is run once to size the buffers
+// and once timed (device time of the whole call), and the fastest wins
+extern "C" int mbw_tune(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads, int min_seed_len,
+                        int max_occ, const mbw_seed_opts *base, void *stream, mbw_seed_opts *best, float *best_ms) {
+  if (!c || !best || !best_ms) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
+  mbw_seed_opts b;
+  if (base) b = *base;
+  else {
+    memset(&b, 0, sizeof(b));
+    b.min_occ = 1; b.reseed = 1; b.reseed_len = 38; b.reseed_occ = 10; b.use_kmer = 1; b.unique_ext = 1;
+  }
+  b.kernel = MBW_KERNEL_COOP;
+  const int stage_opts[2] = {0, 1};            // no_stage
+  const int seg_opts[3] = {128, 256, 1024};
+  const int bpc_opts[2] = {0, 2};
+  const int uniq_opts[2] = {1, 0};
+  float bt = 0;
+  bool have = false;
+  for (int u = 0; u < 2; ++u)
+    for (int ns = 0; ns < 2; ++ns)
+      for (int sg = 0; sg < 3; ++sg)
+        for (int bp = 0; bp < 2; ++bp) {
+          mbw_seed_opts o = b;
+          o.unique_ext = uniq_opts[u]; o.no_stage = stage_opts[ns]; o.seg_len = seg_opts[sg]; o.blocks_per_cu = bpc_opts[bp];
+          mbw_result res;
+          int r = mbw_seed(c, reads, lengths, n_reads, min_seed_len, max_occ, &o, stream, &res);
+          if (r) return r;
+          r = mbw_seed(c, reads, lengths, n_reads, min_seed_len, max_occ, &o, stream, &res);
+          if (r) return r;
+          if (!have || res.ms_total < bt) { bt = res.ms_total; *best = o; have = true; }
+        }
+  *best_ms = bt;
+  return MBW_OK;
+}
+
 extern "C" int mbw_result_download(mbw_ctx *c, const mbw_result *res, mbw_seed_t *seeds, uint64_t *pos) {
   if (!c || !res) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
   TRY(hipSetDevice(c->device));

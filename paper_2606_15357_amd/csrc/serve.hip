@@ -1,0 +1,268 @@
+// Serving runtime: a request loop around mbw_seed with the index resident in HBM.
+//
+// Requests (a few to tens of thousands of reads) are queued on submission; admission is bounded by
+// the bases waiting in the queue.  Each worker thread owns a seeding context and its own HIP stream.
+// A free worker forms a batch from the head of the queue (up to a read / base budget), so requests
+// that arrive while other batches are on the device join the next batch at once (continuous
+// batching), and batches of different workers run on the device at the same time.  A batch's
+// seeds come back sorted by read, so each request's seeds and positions are a contiguous slice,
+// which is copied out with read ids and position offsets made relative to the request.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "mbw_internal.h"
+#include "../../include/mbw.h"
+
+namespace {
+
+struct Request {
+  uint64_t ticket = 0;
+  std::vector<uint8_t> reads;
+  std::vector<uint32_t> lengths;
+  uint64_t bases = 0;
+  double t_submit = 0, t_start = 0, t_done = 0;
+  uint64_t batch_id = 0, batch_reads = 0;
+  int state = 0;   // 0 queued, 1 running, 2 done
+  int rc = MBW_OK;
+  std::vector<mbw_seed_t> seeds;
+  std::vector<uint64_t> pos;
+};
+
+// grow-only pinned host buffer
+struct Pinned {
+  void *p = nullptr;
+  size_t bytes = 0;
+  int ensure(size_t want) {
+    if (want <= bytes) return 0;
+    if (p) { (void)hipHostFree(p); p = nullptr; bytes = 0; }
+    const size_t b = want + want / 4 + 4096;
+    if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) { p = nullptr; return MBW_E_NOMEM; }
+    bytes = b;
+    return 0;
+  }
+  ~Pinned() { if (p) (void)hipHostFree(p); }
+};
+
+}  // namespace
+
+struct mbw_server {
+  const mbw_index *ix = nullptr;
+  mbw_serve_cfg cfg;
+  std::mutex mu;
+  std::condition_variable work_cv, done_cv;
+  std::deque<Request *> queue;
+  std::map<uint64_t, Request *> all;
+  uint64_t next_ticket = 1, queued_bases = 0, next_batch = 1;
+  bool stop = false;
+  std::vector<std::thread> workers;
+  std::chrono::steady_clock::time_point t0;
+  uint64_t batches = 0, batch_reads_sum = 0;
+
+  double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+};
+
+static void worker_main(mbw_server *s, mbw_ctx *ctx, hipStream_t st) {
+  Pinned hreads, hlens, hseeds, hpos;
+  (void)hipSetDevice(s->cfg.device);
+  for (;;) {
+    std::vector<Request *> batch;
+    uint64_t nreads = 0, nbases = 0, bid = 0;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->work_cv.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+      if (s->queue.empty()) return;   // stopping
+      while (!s->queue.empty()) {
+        Request *r = s->queue.front();
+        const uint64_t nr = r->lengths.size();
+        if (!batch.empty() && (nreads + nr > s->cfg.max_batch_reads || nbases + r->bases > s->cfg.max_batch_bases)) break;
+        s->queue.pop_front();
+        s->queued_bases -= r->bases;
+        batch.push_back(r);
+        nreads += nr;
+        nbases += r->bases;
+      }
+      bid = s->next_batch++;
+      const double t = s->now();
+      for (Request *r : batch) { r->state = 1; r->t_start = t; r->batch_id = bid; r->batch_reads = nreads; }
+      s->batches++;
+      s->batch_reads_sum += nreads;
+    }
+    // concatenate the batch in pinned memory and seed it
+    int rc = hreads.ensure(nbases + 16);
+    if (!rc) rc = hlens.ensure((nreads + 1) * sizeof(uint32_t));
+    mbw_result res;
+    memset(&res, 0, sizeof(res));
+    if (!rc) {
+      uint8_t *rb = (uint8_t *)hreads.p;
+      uint32_t *lb = (uint32_t *)hlens.p;
+      uint64_t ob = 0, orr = 0;
+      for (Request *r : batch) {
+        if (!r->reads.empty()) memcpy(rb + ob, r->reads.data(), r->reads.size());
+        if (!r->lengths.empty()) memcpy(lb + orr, r->lengths.data(), r->lengths.size() * sizeof(uint32_t));
+        ob += r->reads.size();
+        orr += r->lengths.size();
+      }
+      rc = mbw_seed(ctx, rb, lb, nreads, s->cfg.min_seed_len, s->cfg.max_occ, &s->cfg.opts, (void *)st, &res);
+    }
+    if (!rc) rc = hseeds.ensure((res.n_seeds + 1) * sizeof(mbw_seed_t));
+    if (!rc) rc = hpos.ensure((res.n_pos + 1) * sizeof(uint64_t));
+    if (!rc) rc = mbw_result_download(ctx, &res, (mbw_seed_t *)hseeds.p, (uint64_t *)hpos.p);
+    // split: seeds are sorted by read, positions follow the seeds
+    if (!rc) {
+      const mbw_seed_t *sd = (const mbw_seed_t *)hseeds.p;
+      const uint64_t *ps = (const uint64_t *)hpos.p;
+      uint64_t r0 = 0, t = 0;
+      for (Request *r : batch) {
+        const uint64_t r1 = r0 + r->lengths.size();
+        const uint64_t t0 = t;
+        while (t < res.n_seeds && sd[t].read_id < r1) ++t;
+        r->seeds.assign(sd + t0, sd + t);
+        uint64_t p0 = 0, p1 = 0;
+        if (t > t0) { p0 = sd[t0].pos_off; p1 = sd[t - 1].pos_off + sd[t - 1].npos; }
+        r->pos.assign(ps + p0, ps + p1);
+        for (mbw_seed_t &x : r->seeds) { x.read_id -= (uint32_t)r0; x.pos_off -= p0; }
+        r0 = r1;
+      }
+    }
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      const double t = s->now();
+      for (Request *r : batch) { r->rc = rc; r->state = 2; r->t_done = t; }
+    }
+    s->done_cv.notify_all();
+  }
+}
+
+extern "C" int mbw_serve_open(const mbw_index *ix, const mbw_serve_cfg *cfg, mbw_server **out) {
+  if (!ix || !cfg || !out) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
+  *out = nullptr;
+  if (cfg->n_workers < 1 || cfg->n_workers > 8 || cfg->max_batch_reads < 1 || cfg->max_batch_bases < 1 ||
+      cfg->min_seed_len < 1 || cfg->max_occ < 1) {
+    mbw_set_error("bad serve configuration"); return MBW_E_INVAL;
+  }
+  if (cfg->device != ix->device) { mbw_set_error("serve device differs from the index device"); return MBW_E_INVAL; }
+  mbw_server *s = new mbw_server();
+  s->ix = ix;
+  s->cfg = *cfg;
+  s->t0 = std::chrono::steady_clock::now();
+  std::vector<std::pair<mbw_ctx *, hipStream_t>> res;
+  for (int w = 0; w < cfg->n_workers; ++w) {
+    mbw_ctx *c = nullptr;
+    int r = mbw_ctx_create(ix, &c);
+    hipStream_t st = nullptr;
+    if (!r && hipStreamCreate(&st) != hipSuccess) { mbw_ctx_free(c); mbw_set_error("hipStreamCreate failed"); r = MBW_E_HIP; }
+    if (r) {
+      for (auto &x : res) { mbw_ctx_free(x.first); (void)hipStreamDestroy(x.second); }
+      delete s;
+      return r;
+    }
+    res.emplace_back(c, st);
+  }
+  for (auto &x : res)
+    s->workers.emplace_back([s, x] {
+      worker_main(s, x.first, x.second);
+      mbw_ctx_free(x.first);
+      (void)hipStreamDestroy(x.second);
+    });
+  *out = s;
+  return MBW_OK;
+}
+
+extern "C" int mbw_serve_submit(mbw_server *s, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads,
+                                uint64_t *ticket) {
+  if (!s || !ticket || (n_reads && (!reads || !lengths))) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
+  uint64_t bases = 0;
+  for (uint64_t i = 0; i < n_reads; ++i) {
+    if (lengths[i] > MBW_MAX_READ) { mbw_set_error("read longer than 65535 bases"); return MBW_E_INVAL; }
+    bases += lengths[i];
+  }
+  Request *r = new Request();
+  try {
+    r->reads.assign(reads, reads + bases);
+    r->lengths.assign(lengths, lengths + n_reads);
+  } catch (...) { delete r; mbw_set_error("host allocation failed"); return MBW_E_NOMEM; }
+  r->bases = bases;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) { delete r; mbw_set_error("server is closing"); return MBW_E_INVAL; }
+    if (!s->queue.empty() && s->queued_bases + bases > s->cfg.max_queued_bases) {
+      delete r;
+      mbw_set_error("queue full (admission by queued bases)");
+      return MBW_E_BUSY;
+    }
+    r->ticket = s->next_ticket++;
+    r->t_submit = s->now();
+    s->queue.push_back(r);
+    s->queued_bases += bases;
+    s->all[r->ticket] = r;
+    *ticket = r->ticket;
+  }
+  s->work_cv.notify_one();
+  return MBW_OK;
+}
+
+extern "C" int mbw_serve_wait(mbw_server *s, uint64_t ticket, int timeout_ms, mbw_serve_result *out) {
+  if (!s || !out) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->all.find(ticket);
+  if (it == s->all.end()) { mbw_set_error("unknown ticket"); return MBW_E_INVAL; }
+  Request *r = it->second;
+  auto ready = [&] { return r->state == 2; };
+  if (timeout_ms < 0) s->done_cv.wait(lk, ready);
+  else if (!s->done_cv.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready)) {
+    mbw_set_error("request not finished"); return MBW_E_BUSY;
+  }
+  if (r->rc) return r->rc;
+  out->n_seeds = r->seeds.size();
+  out->n_pos = r->pos.size();
+  out->seeds = r->seeds.data();
+  out->pos = r->pos.data();
+  out->t_submit = r->t_submit;
+  out->t_start = r->t_start;
+  out->t_done = r->t_done;
+  out->batch_id = r->batch_id;
+  out->batch_reads = r->batch_reads;
+  return MBW_OK;
+}
+
+extern "C" int mbw_serve_release(mbw_server *s, uint64_t ticket) {
+  if (!s) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->all.find(ticket);
+  if (it == s->all.end()) { mbw_set_error("unknown ticket"); return MBW_E_INVAL; }
+  if (it->second->state != 2) { mbw_set_error("request not finished"); return MBW_E_BUSY; }
+  delete it->second;
+  s->all.erase(it);
+  return MBW_OK;
+}
+
+extern "C" int mbw_serve_stats(mbw_server *s, uint64_t *batches, uint64_t *batch_reads, uint64_t *queued) {
+  if (!s) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (batches) *batches = s->batches;
+  if (batch_reads) *batch_reads = s->batch_reads_sum;
+  if (queued) *queued = s->queue.size();
+  return MBW_OK;
+}
+
+extern "C" void mbw_serve_close(mbw_server *s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->work_cv.notify_all();
+  for (auto &t : s->workers) t.join();   // queued requests are finished first
+  for (auto &kv : s->all) delete kv.second;
+  delete s;
+}

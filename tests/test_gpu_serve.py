@@ -1,0 +1,131 @@
+"""The autotuner and the serving runtime, through the C-ABI.
+
+* mbw_tune picks one of its candidate schedules; seeding with it is bit-exact against the oracle.
+* mbw_serve: every request's result equals the oracle's for that request alone, both when it is
+  served alone and when it is batched with many others submitted concurrently (tolerance 0);
+  batches really merge requests; admission refuses submissions when the queue is full.
+"""
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from mbw_helpers import compare_with_oracle, gpu_seed
+
+mbw = pytest.importorskip("paper_2606_15357_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def small():
+    ref = synth.workload_reference("small_1mbp")
+    ox = oracle.OracleIndex(ref.codes, sa_rate=8)
+    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=10)
+    yield ref, ox, idx
+    idx.free()
+
+
+def _requests(ref, n, seed):
+    """n requests of mixed sizes (1..2500 reads) and read lengths (20..700, some with N runs)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(n):
+        m = int(rng.integers(1, 2500))
+        if q % 3 == 0:
+            rs = synth.reads_uniform_len(ref, m, 20, 700, seed=seed * 1000 + q)
+        else:
+            rs = synth.reads_fixed(ref, m, 150, False, p_sub=0.01, p_indel=0.001, seed=seed * 1000 + q)
+        seq = rs.seq.copy()
+        if q % 5 == 1 and seq.size > 40:
+            seq[10:25] = ord("N")
+        out.append(synth.ReadSet(seq, rs.lengths, rs.offsets, rs.tpos, rs.tstrand))
+    return out
+
+
+def test_tune_picks_a_valid_schedule(small):
+    ref, ox, idx = small
+    reads = synth.reads_uniform_len(ref, 4000, 50, 900, seed=12)
+    ctx = mbw.Context(idx)
+    best = ctx.tune(reads.seq, reads.lengths)
+    assert best["seg_len"] in (128, 256, 1024) and best["blocks_per_cu"] in (0, 2) and best["ms"] > 0
+    ms = best.pop("ms")
+    out = ctx.seed(reads.seq, reads.lengths, **best)
+    seeds, pos = out.download()
+    compare_with_oracle(seeds, pos, ox.seed(reads.seq, reads.offsets))
+    ctx.free()
+    assert ms < 1e5
+
+
+def test_serve_alone_and_in_a_mix(small):
+    ref, ox, idx = small
+    reqs = _requests(ref, 40, seed=5)
+    exp = [ox.seed(r.seq, r.offsets) for r in reqs]
+    srv = mbw.Server(idx, n_workers=2, max_batch_reads=6000)
+    # request 7 alone
+    t = srv.submit(reqs[7].seq, reqs[7].lengths)
+    s_alone, p_alone, info_alone = srv.wait(t)
+    compare_with_oracle(s_alone, p_alone, exp[7])
+    # all requests from two threads at once
+    tickets = [None] * len(reqs)
+
+    def submit(lo):
+        for q in range(lo, len(reqs), 2):
+            while True:
+                tk = srv.submit(reqs[q].seq, reqs[q].lengths)
+                if tk is not None:
+                    tickets[q] = tk
+                    break
+
+    th = [threading.Thread(target=submit, args=(lo,)) for lo in (0, 1)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    merged = 0
+    for q in range(len(reqs)):
+        s, p, info = srv.wait(tickets[q])
+        compare_with_oracle(s, p, exp[q])
+        merged += info["batch_reads"] > len(reqs[q])
+        if q == 7:
+            a, fa = mbw.canonical(s, p)
+            b, fb = mbw.canonical(s_alone, p_alone)
+            assert a.tobytes() == b.tobytes() and fa.tobytes() == fb.tobytes()
+        assert info["t_submit"] <= info["t_start"] <= info["t_done"]
+    st = srv.stats()
+    assert merged > 0 and st["batches"] < len(reqs) + 1
+    srv.close()
+
+
+def test_serve_admission_by_queued_bases(small):
+    ref, ox, idx = small
+    reqs = _requests(ref, 12, seed=9)
+    srv = mbw.Server(idx, n_workers=1, max_batch_reads=10, max_queued_bases=2000)
+    accepted, refused = [], 0
+    for q, r in enumerate(reqs):
+        t = srv.submit(r.seq, r.lengths)
+        if t is None:
+            refused += 1
+        else:
+            accepted.append((q, t))
+    assert refused > 0 and accepted
+    for q, t in accepted:
+        s, p, _ = srv.wait(t)
+        compare_with_oracle(s, p, ox.seed(reqs[q].seq, reqs[q].offsets))
+    srv.close()
+
+
+def test_serve_empty_request_and_close_with_queue(small):
+    ref, ox, idx = small
+    srv = mbw.Server(idx, n_workers=1)
+    t0 = srv.submit(np.zeros(0, np.uint8), np.zeros(0, np.uint32))
+    reqs = _requests(ref, 3, seed=3)
+    ts = [srv.submit(r.seq, r.lengths) for r in reqs]
+    s, p, _ = srv.wait(t0)
+    assert len(s) == 0 and len(p) == 0
+    for q, t in enumerate(ts):
+        s, p, _ = srv.wait(t)
+        compare_with_oracle(s, p, ox.seed(reqs[q].seq, reqs[q].offsets))
+    srv.close()
