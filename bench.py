@@ -88,6 +88,74 @@ def cpu_baseline(workload: str, ref_codes, n_pairs: int, window: int, threads: i
                        f"{dt:.1f} s wall")
 
 
+def serve_leg(mbw, idx, reads, seconds: float, sched: dict):
+    """Open-loop serving on the resident index: Poisson arrivals, requests of log-uniform
+    1..20,000 reads drawn from the workload's reads, at half of the saturation rate measured by a
+    closed-loop burst; latency = submit to result on the host (the server's clock)."""
+    import threading
+    rng = np.random.default_rng(3000)
+    n = len(reads)
+
+    def request():
+        m = int(np.exp(rng.uniform(0.0, np.log(20000.0))))
+        r0 = int(rng.integers(0, n - m))
+        return reads.seq[int(reads.offsets[r0]):int(reads.offsets[r0 + m])], reads.lengths[r0:r0 + m]
+
+    srv = mbw.Server(idx, n_workers=4, max_batch_reads=100_000, **sched)
+    for _ in range(2):                                    # warm the workers' buffers
+        srv.wait(srv.submit(*request()))
+    burst = [request() for _ in range(300)]
+    t0 = time.perf_counter()
+    ts = [srv.submit(*r) for r in burst]
+    for t in ts:
+        srv.wait(t)
+    sat = sum(len(r[1]) for r in burst) / (time.perf_counter() - t0)
+    mean_req = (20000.0 - 1.0) / np.log(20000.0)
+    qps = 0.5 * sat / mean_req
+    arrivals = np.cumsum(rng.exponential(1.0 / qps, size=int(qps * seconds * 1.2) + 10))
+    arrivals = arrivals[arrivals < seconds]
+    reqs = [request() for _ in range(arrivals.size)]
+    tickets, lat, refused = [], [], 0
+    done = threading.Event()
+    info_all = []
+
+    def waiter():
+        k = 0
+        while k < len(reqs):
+            if k >= len(tickets):
+                time.sleep(0.0002)
+                continue
+            s, p, info = srv.wait(tickets[k])
+            info_all.append(info)
+            k += 1
+        done.set()
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = time.perf_counter()
+    for a, r in zip(arrivals, reqs):
+        d = t0 + a - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        t = srv.submit(*r)
+        while t is None:
+            refused += 1
+            time.sleep(0.0005)
+            t = srv.submit(*r)
+        tickets.append(t)
+    th.join()
+    srv.close()
+    lat = np.array([(i["t_done"] - i["t_submit"]) * 1e3 for i in info_all])
+    span = max(i["t_done"] for i in info_all) - min(i["t_submit"] for i in info_all)
+    nr = sum(len(r[1]) for r in reqs)
+    batches = len(set(i["batch_id"] for i in info_all))
+    return dict(requests=len(reqs), reads=nr, qps=round(qps, 1), seconds=seconds,
+                saturation_reads_per_s=round(sat, 1), reads_per_s=round(nr / span, 1),
+                p50_ms=round(float(np.percentile(lat, 50)), 3), p99_ms=round(float(np.percentile(lat, 99)), 3),
+                batches=batches, refused_submits=refused,
+                request_size="log-uniform 1..20000 reads", arrivals="Poisson at half the closed-loop saturation")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +174,9 @@ def main():
     ap.add_argument("--isa-sample", type=int, default=4, help="inverse-SA sampling step (0 = no unique-match path)")
     ap.add_argument("--no-unique", action="store_true", help="extend unique matches base by base")
     ap.add_argument("--probe", action="store_true", help="only run the copy and random-gather probes")
+    ap.add_argument("--no-tune", action="store_true", help="default schedule instead of the autotuned one")
+    ap.add_argument("--serve-seconds", type=float, default=6.0,
+                    help="open-loop serving leg on the same index (0 = skip)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -146,10 +217,19 @@ def main():
     torch.cuda.synchronize()
     ctx = mbw.Context(idx)
     stream = torch.cuda.current_stream()
+    sched = dict(unique_ext=not args.no_unique)
+    if not args.no_tune:
+        t0 = time.time()
+        m = min(n_reads, 4_000_000)
+        best = ctx.tune(dseq[: int(reads.offsets[m])], dlen[:m], stream=stream)
+        tune_ms = best.pop("ms")
+        if args.no_unique:
+            best["unique_ext"] = False
+        sched = best
+        log(f"autotuned on {m} reads in {time.time() - t0:.1f} s: {sched} ({tune_ms:.1f} ms)")
 
     def step(kernel):
-        return ctx.seed(dseq, dlen, min_seed_len=19, max_occ=500, kernel=kernel,
-                        unique_ext=not args.no_unique, stream=stream)
+        return ctx.seed(dseq, dlen, min_seed_len=19, max_occ=500, kernel=kernel, stream=stream, **sched)
 
     for _ in range(args.warmup):
         out = step(mbw.KERNEL_COOP)
@@ -211,6 +291,11 @@ def main():
         cpu["value"] = round(cpu["value"], 1)
         log(f"cpu oracle: {cpu['value']:.0f} reads/s on {cpu['cores']} threads")
 
+    serve = None
+    if args.serve_seconds > 0:
+        serve = serve_leg(mbw, idx, reads, args.serve_seconds, sched)
+        log(f"serving: {serve}")
+
     line = dict(metric=METRIC, value=round(value, 1), unit="reads/s", n_gpus=1, steps=args.steps,
                 warmup=args.warmup, ms_per_step=round(elapsed / args.steps * 1e3, 2), higher_is_better=True,
                 scaling="weak", vs_baseline=None, dtype="u64", data="synthetic",
@@ -219,7 +304,7 @@ def main():
                             min_seed_len=19, max_occ=500, sa_sample=args.sa_sample, kmer_k=args.kmer,
                             isa_sample=args.isa_sample, unique_ext=not args.no_unique,
                             bases_per_line=384, line_bytes=LINE_BYTES, index_gb=round(info["bytes_resident"] / 1e9, 2)),
-                plain_gpu=plain, roofline=roofline, cpu_baseline=cpu)
+                schedule=sched, plain_gpu=plain, roofline=roofline, cpu_baseline=cpu, serve=serve)
     print(json.dumps(line), flush=True)
 
 

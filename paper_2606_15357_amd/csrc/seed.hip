@@ -988,22 +988,25 @@ struct mbw_ctx {
   const mbw_index *ix;
   int device;
   int n_cu;
-  struct Buf { void *p = nullptr; size_t bytes = 0; };   // grow-only device buffers
+  struct Buf { void *p = nullptr; size_t bytes = 0; };   // grow-only device buffers (stream-ordered allocations)
   Buf codes, ascii, lens, offs, raw, subq, keys0, keys1, vals0, vals1, flag, idx, seeds, npos, posoff, xrows, pos, pos2,
       keep, kidx, temp, ctl, pwords, pnmask, woffs, nwords, wread, q1, q2, bf0, bf1, bp0, bp1, bid0, bid1, bk0, bk1, q1s,
       q2s, sc0, sc1;
   hipEvent_t ev[8];
+  hipStream_t cur = nullptr;   // stream of the current / last mbw_seed call
   unsigned long long host_ctl[C_COUNT];
   float ms_smem;
   int n_smem_launches;
 };
 
-static int grow(mbw_ctx::Buf &b, size_t bytes) {
+// Buffers grow on the call's stream with the stream-ordered allocator, so that a context growing
+// its work space does not wait for work of other contexts on other streams.
+static int grow(mbw_ctx *c, mbw_ctx::Buf &b, size_t bytes) {
   if (bytes == 0) bytes = 16;
   if (b.bytes >= bytes) return 0;
-  if (b.p) { (void)hipFree(b.p); b.p = nullptr; b.bytes = 0; }
-  size_t want = bytes + bytes / 4 + 256;
-  hipError_t e = hipMalloc(&b.p, want);
+  if (b.p) { (void)hipFreeAsync(b.p, c->cur); b.p = nullptr; b.bytes = 0; }
+  size_t want = bytes + bytes / 2 + 256;
+  hipError_t e = hipMallocAsync(&b.p, want, c->cur);
   if (e != hipSuccess) {
     b.p = nullptr;
     mbw_set_error(std::string("hipMalloc(") + std::to_string(want) + "): " + hipGetErrorString(e));
@@ -1012,7 +1015,7 @@ static int grow(mbw_ctx::Buf &b, size_t bytes) {
   b.bytes = want;
   return 0;
 }
-#define GROW(buf, bytes) do { int r_ = grow(buf, bytes); if (r_) return r_; } while (0)
+#define GROW(buf, bytes) do { int r_ = grow(c, buf, bytes); if (r_) return r_; } while (0)
 
 extern "C" int mbw_ctx_create(const mbw_index *ix, mbw_ctx **out) {
   if (!ix || !out) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
@@ -1026,7 +1029,16 @@ extern "C" int mbw_ctx_create(const mbw_index *ix, mbw_ctx **out) {
   c->n_cu = prop.multiProcessorCount;
   for (int t = 0; t < 8; ++t)
     if (hipEventCreate(&c->ev[t]) != hipSuccess) { delete c; mbw_set_error("hipEventCreate failed"); return MBW_E_HIP; }
-  if (grow(c->ctl, C_COUNT * sizeof(unsigned long long))) { delete c; return MBW_E_NOMEM; }
+  {
+    // keep memory freed by growing buffers in the device's pool instead of returning it at every sync
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, ix->device) == hipSuccess) {
+      uint64_t thr = ~0ull;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+  }
+  if (grow(c, c->ctl, C_COUNT * sizeof(unsigned long long))) { delete c; return MBW_E_NOMEM; }
+  (void)hipStreamSynchronize(nullptr);
   *out = c;
   return MBW_OK;
 }
@@ -1039,7 +1051,8 @@ extern "C" void mbw_ctx_free(mbw_ctx *c) {
                         &c->keep, &c->kidx, &c->temp, &c->ctl, &c->pwords, &c->pnmask, &c->woffs, &c->nwords, &c->wread,
                         &c->q1, &c->q2, &c->bf0, &c->bf1, &c->bp0, &c->bp1, &c->bid0, &c->bid1, &c->bk0, &c->bk1,
                         &c->q1s, &c->q2s, &c->sc0, &c->sc1};
-  for (auto *b : bs) if (b->p) (void)hipFree(b->p);
+  for (auto *b : bs) if (b->p) (void)hipFreeAsync(b->p, c->cur);
+  (void)hipStreamSynchronize(c->cur);
   for (int t = 0; t < 8; ++t) (void)hipEventDestroy(c->ev[t]);
   delete c;
 }
@@ -1164,6 +1177,7 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   if (o.kernel != MBW_KERNEL_COOP && o.kernel != MBW_KERNEL_PLAIN) { mbw_set_error("unknown kernel"); return MBW_E_INVAL; }
   TRY(hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
+  c->cur = st;
   const mbw_index *ix = c->ix;
   const IndexView v = make_view(ix);
   unsigned long long *ctl = (unsigned long long *)c->ctl.p;
@@ -1358,11 +1372,10 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
       if (attempt > 3) { mbw_set_error("seed buffer did not converge"); return MBW_E_NOMEM; }
       // keep the round-1 records: grow by copying
       mbw_ctx::Buf nb;
-      int rr = grow(nb, (ntot + ntot / 2 + 1024) * sizeof(SeedRec));
+      int rr = grow(c, nb, (ntot + ntot / 2 + 1024) * sizeof(SeedRec));
       if (rr) return rr;
       TRY(hipMemcpyAsync(nb.p, c->raw.p, n1 * sizeof(SeedRec), hipMemcpyDeviceToDevice, st));
-      TRY(hipStreamSynchronize(st));
-      (void)hipFree(c->raw.p);
+      (void)hipFreeAsync(c->raw.p, st);
       c->raw = nb;
     }
   }
@@ -1523,7 +1536,10 @@ extern "C" int mbw_tune(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
 extern "C" int mbw_result_download(mbw_ctx *c, const mbw_result *res, mbw_seed_t *seeds, uint64_t *pos) {
   if (!c || !res) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
   TRY(hipSetDevice(c->device));
-  if (seeds && res->n_seeds) TRY(hipMemcpy(seeds, res->seeds, res->n_seeds * sizeof(mbw_seed_t), hipMemcpyDeviceToHost));
-  if (pos && res->n_pos) TRY(hipMemcpy(pos, res->pos, res->n_pos * sizeof(uint64_t), hipMemcpyDeviceToHost));
+  // on the stream of the call that produced the result (a null-stream copy would wait for every stream)
+  if (seeds && res->n_seeds)
+    TRY(hipMemcpyAsync(seeds, res->seeds, res->n_seeds * sizeof(mbw_seed_t), hipMemcpyDeviceToHost, c->cur));
+  if (pos && res->n_pos) TRY(hipMemcpyAsync(pos, res->pos, res->n_pos * sizeof(uint64_t), hipMemcpyDeviceToHost, c->cur));
+  TRY(hipStreamSynchronize(c->cur));
   return MBW_OK;
 }

@@ -11,6 +11,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -25,6 +27,27 @@
 
 namespace {
 
+// grow-only pinned host buffer
+struct Pinned {
+  void *p = nullptr;
+  size_t bytes = 0;
+  int ensure(size_t want) {
+    if (want <= bytes) return 0;
+    if (p) { (void)hipHostFree(p); p = nullptr; bytes = 0; }
+    const size_t b = 2 * want + 4096;
+    if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) { p = nullptr; return MBW_E_NOMEM; }
+    bytes = b;
+    return 0;
+  }
+  ~Pinned() { if (p) (void)hipHostFree(p); }
+};
+
+// one batch's downloaded result, shared by its requests
+struct BatchBuf {
+  Pinned seeds, pos;
+  int refs = 0;
+};
+
 struct Request {
   uint64_t ticket = 0;
   std::vector<uint8_t> reads;
@@ -34,23 +57,8 @@ struct Request {
   uint64_t batch_id = 0, batch_reads = 0;
   int state = 0;   // 0 queued, 1 running, 2 done
   int rc = MBW_OK;
-  std::vector<mbw_seed_t> seeds;
-  std::vector<uint64_t> pos;
-};
-
-// grow-only pinned host buffer
-struct Pinned {
-  void *p = nullptr;
-  size_t bytes = 0;
-  int ensure(size_t want) {
-    if (want <= bytes) return 0;
-    if (p) { (void)hipHostFree(p); p = nullptr; bytes = 0; }
-    const size_t b = want + want / 4 + 4096;
-    if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) { p = nullptr; return MBW_E_NOMEM; }
-    bytes = b;
-    return 0;
-  }
-  ~Pinned() { if (p) (void)hipHostFree(p); }
+  BatchBuf *buf = nullptr;          // the shared batch result
+  uint64_t s0 = 0, ns = 0, p0 = 0, np = 0;   // this request's slice of it
 };
 
 }  // namespace
@@ -67,13 +75,23 @@ struct mbw_server {
   std::vector<std::thread> workers;
   std::chrono::steady_clock::time_point t0;
   uint64_t batches = 0, batch_reads_sum = 0;
+  bool trace = false;   // MBW_SERVE_TRACE=1: one line per batch on stderr
+  std::vector<BatchBuf *> free_bufs;
+
+  void unref(BatchBuf *b) {   // with mu held
+    if (b && --b->refs == 0) free_bufs.push_back(b);
+  }
 
   double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
 };
 
 static void worker_main(mbw_server *s, mbw_ctx *ctx, hipStream_t st) {
-  Pinned hreads, hlens, hseeds, hpos;
+  Pinned hreads, hlens;
   (void)hipSetDevice(s->cfg.device);
+  // pinned staging sized for a full batch up front (pinning memory while serving would stall)
+  const uint64_t br = std::min<uint64_t>(s->cfg.max_batch_reads, 1ull << 22);
+  (void)hreads.ensure(std::min<uint64_t>(s->cfg.max_batch_bases, br * 160) / 2 + 16);
+  (void)hlens.ensure(br * sizeof(uint32_t) / 2 + 16);
   for (;;) {
     std::vector<Request *> batch;
     uint64_t nreads = 0, nbases = 0, bid = 0;
@@ -98,6 +116,8 @@ static void worker_main(mbw_server *s, mbw_ctx *ctx, hipStream_t st) {
       s->batch_reads_sum += nreads;
     }
     // concatenate the batch in pinned memory and seed it
+    const double tb0 = s->now();
+    double tb1 = tb0, tb2 = tb0, tb3 = tb0;
     int rc = hreads.ensure(nbases + 16);
     if (!rc) rc = hlens.ensure((nreads + 1) * sizeof(uint32_t));
     mbw_result res;
@@ -112,32 +132,51 @@ static void worker_main(mbw_server *s, mbw_ctx *ctx, hipStream_t st) {
         ob += r->reads.size();
         orr += r->lengths.size();
       }
+      tb1 = s->now();
       rc = mbw_seed(ctx, rb, lb, nreads, s->cfg.min_seed_len, s->cfg.max_occ, &s->cfg.opts, (void *)st, &res);
+      tb2 = s->now();
     }
-    if (!rc) rc = hseeds.ensure((res.n_seeds + 1) * sizeof(mbw_seed_t));
-    if (!rc) rc = hpos.ensure((res.n_pos + 1) * sizeof(uint64_t));
-    if (!rc) rc = mbw_result_download(ctx, &res, (mbw_seed_t *)hseeds.p, (uint64_t *)hpos.p);
-    // split: seeds are sorted by read, positions follow the seeds
+    BatchBuf *bb = nullptr;
     if (!rc) {
-      const mbw_seed_t *sd = (const mbw_seed_t *)hseeds.p;
-      const uint64_t *ps = (const uint64_t *)hpos.p;
+      std::lock_guard<std::mutex> lk(s->mu);
+      if (!s->free_bufs.empty()) { bb = s->free_bufs.back(); s->free_bufs.pop_back(); }
+    }
+    if (!rc && !bb) {
+      bb = new BatchBuf();
+      rc = bb->seeds.ensure(br * 4 * sizeof(mbw_seed_t));
+      if (!rc) rc = bb->pos.ensure(br * 24 * sizeof(uint64_t));
+    }
+    if (!rc) rc = bb->seeds.ensure((res.n_seeds + 1) * sizeof(mbw_seed_t));
+    if (!rc) rc = bb->pos.ensure((res.n_pos + 1) * sizeof(uint64_t));
+    if (!rc) rc = mbw_result_download(ctx, &res, (mbw_seed_t *)bb->seeds.p, (uint64_t *)bb->pos.p);
+    tb3 = s->now();
+    // split: seeds are sorted by read, positions follow the seeds; rebase each slice in place
+    if (!rc) {
+      mbw_seed_t *sd = (mbw_seed_t *)bb->seeds.p;
       uint64_t r0 = 0, t = 0;
       for (Request *r : batch) {
         const uint64_t r1 = r0 + r->lengths.size();
         const uint64_t t0 = t;
         while (t < res.n_seeds && sd[t].read_id < r1) ++t;
-        r->seeds.assign(sd + t0, sd + t);
         uint64_t p0 = 0, p1 = 0;
         if (t > t0) { p0 = sd[t0].pos_off; p1 = sd[t - 1].pos_off + sd[t - 1].npos; }
-        r->pos.assign(ps + p0, ps + p1);
-        for (mbw_seed_t &x : r->seeds) { x.read_id -= (uint32_t)r0; x.pos_off -= p0; }
+        for (uint64_t q = t0; q < t; ++q) { sd[q].read_id -= (uint32_t)r0; sd[q].pos_off -= p0; }
+        r->buf = bb; r->s0 = t0; r->ns = t - t0; r->p0 = p0; r->np = p1 - p0;
         r0 = r1;
       }
     }
     {
       std::lock_guard<std::mutex> lk(s->mu);
       const double t = s->now();
-      for (Request *r : batch) { r->rc = rc; r->state = 2; r->t_done = t; }
+      if (bb) {
+        bb->refs = rc ? 0 : (int)batch.size();
+        if (rc) s->free_bufs.push_back(bb);
+      }
+      for (Request *r : batch) { r->rc = rc; r->state = 2; r->t_done = t; if (rc) r->buf = nullptr; }
+      if (s->trace)
+        fprintf(stderr, "[serve] batch %llu reads %llu: copy %.2f ms, seed %.2f ms (device %.2f), download %.2f ms, split %.2f ms\n",
+                (unsigned long long)bid, (unsigned long long)nreads, (tb1 - tb0) * 1e3, (tb2 - tb1) * 1e3, res.ms_total,
+                (tb3 - tb2) * 1e3, (t - tb3) * 1e3);
     }
     s->done_cv.notify_all();
   }
@@ -155,12 +194,16 @@ extern "C" int mbw_serve_open(const mbw_index *ix, const mbw_serve_cfg *cfg, mbw
   s->ix = ix;
   s->cfg = *cfg;
   s->t0 = std::chrono::steady_clock::now();
+  s->trace = getenv("MBW_SERVE_TRACE") && getenv("MBW_SERVE_TRACE")[0] == '1';
   std::vector<std::pair<mbw_ctx *, hipStream_t>> res;
   for (int w = 0; w < cfg->n_workers; ++w) {
     mbw_ctx *c = nullptr;
     int r = mbw_ctx_create(ix, &c);
     hipStream_t st = nullptr;
-    if (!r && hipStreamCreate(&st) != hipSuccess) { mbw_ctx_free(c); mbw_set_error("hipStreamCreate failed"); r = MBW_E_HIP; }
+    // non-blocking: the workers' streams never wait for work on the null stream
+    if (!r && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      mbw_ctx_free(c); mbw_set_error("hipStreamCreate failed"); r = MBW_E_HIP;
+    }
     if (r) {
       for (auto &x : res) { mbw_ctx_free(x.first); (void)hipStreamDestroy(x.second); }
       delete s;
@@ -223,10 +266,10 @@ extern "C" int mbw_serve_wait(mbw_server *s, uint64_t ticket, int timeout_ms, mb
     mbw_set_error("request not finished"); return MBW_E_BUSY;
   }
   if (r->rc) return r->rc;
-  out->n_seeds = r->seeds.size();
-  out->n_pos = r->pos.size();
-  out->seeds = r->seeds.data();
-  out->pos = r->pos.data();
+  out->n_seeds = r->ns;
+  out->n_pos = r->np;
+  out->seeds = r->buf ? (const mbw_seed_t *)r->buf->seeds.p + r->s0 : nullptr;
+  out->pos = r->buf ? (const uint64_t *)r->buf->pos.p + r->p0 : nullptr;
   out->t_submit = r->t_submit;
   out->t_start = r->t_start;
   out->t_done = r->t_done;
@@ -241,6 +284,7 @@ extern "C" int mbw_serve_release(mbw_server *s, uint64_t ticket) {
   auto it = s->all.find(ticket);
   if (it == s->all.end()) { mbw_set_error("unknown ticket"); return MBW_E_INVAL; }
   if (it->second->state != 2) { mbw_set_error("request not finished"); return MBW_E_BUSY; }
+  s->unref(it->second->buf);
   delete it->second;
   s->all.erase(it);
   return MBW_OK;
@@ -263,6 +307,7 @@ extern "C" void mbw_serve_close(mbw_server *s) {
   }
   s->work_cv.notify_all();
   for (auto &t : s->workers) t.join();   // queued requests are finished first
-  for (auto &kv : s->all) delete kv.second;
+  for (auto &kv : s->all) { s->unref(kv.second->buf); delete kv.second; }
+  for (BatchBuf *b : s->free_bufs) delete b;
   delete s;
 }
