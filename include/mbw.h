@@ -127,6 +127,8 @@ typedef struct {
   int seg_len;        /* queries longer than this many bases (and reads too long for the LDS
                          staging area) are split into segments seeded by separate lanes
                          (wave kernels; same results); 0 = 256, minimum 32 */
+  int bs_refine;      /* bisulfite only (needs bs_role): refine every kept (seed, position) pair
+                         as in Section 2.9 into mbw_result.pieces */
 } mbw_seed_opts;
 
 
@@ -147,6 +149,16 @@ typedef struct {
 #define MBW_SEED_UNLOCATED 1u
 #define MBW_SEED_ROUND2    2u
 
+/* A refined bisulfite seed match (Section 2.9): the kept (seed, position) pair of seed `seed` split
+ * at the bases where the original read has a C over an original reference T (read 1; read 2: G
+ * over A), which bisulfite conversion cannot explain; each piece of at least min_seed_len bases
+ * is P[qbeg, qend) of read read_id at text position pos.  The original reference base under text
+ * position t is R[t mod |R|] for t < 2|R| and the complement of R[(4|R| - 1 - t) mod |R|] above. */
+typedef struct {
+  uint32_t read_id, qbeg, qend, seed;
+  uint64_t pos;
+} mbw_piece_t;
+
 typedef struct {
   uint64_t n_seeds;
   uint64_t n_pos;
@@ -163,6 +175,8 @@ typedef struct {
   uint64_t wave_iters;      /* diagnostics of the wave kernels: loop iterations summed over waves, */
   uint64_t lane_iters;      /* and lane iterations that held a query (utilisation = lane / 64 wave) */
   uint64_t max_chain;       /* the most iterations one query took (wave kernels) */
+  uint64_t n_pieces;        /* bs_refine: refined pieces (device pointer, in seed and position order) */
+  const mbw_piece_t *pieces;
 } mbw_result;
 
 /* Seed a batch of reads.
@@ -180,6 +194,8 @@ int mbw_seed(mbw_ctx *ctx, const uint8_t *reads, const uint32_t *lengths, uint64
 
 /* Copy a result to host buffers (seeds: n_seeds records, pos: n_pos values; either may be NULL). */
 int mbw_result_download(mbw_ctx *ctx, const mbw_result *res, mbw_seed_t *seeds, uint64_t *pos);
+/* Copy the refined bisulfite pieces of a result (bs_refine) to host memory (n_pieces records). */
+int mbw_result_download_pieces(mbw_ctx *ctx, const mbw_result *res, mbw_piece_t *pieces);
 
 /* Autotuner for the wave kernels: runs mbw_seed on this batch with candidate schedules (length
  * binning on or off, segment lengths 128/256/1024, persistent blocks per CU at the occupancy limit

@@ -76,6 +76,9 @@ def _load():
     L.orc_locate_slow.argtypes = [vp, u64]
     L.orc_scan_seed.restype = vp
     L.orc_scan_seed.argtypes = [vp, u64, i32, vp, vp, u64, C.POINTER(_Opts), i32]
+    L.orc_bs_refine.restype = u64
+    L.orc_bs_refine.argtypes = [vp, u64, vp, vp, vp, vp, vp, vp, vp, u64, vp, i32, i32, C.POINTER(vp)]
+    L.orc_free_ptr.argtypes = [vp]
     _lib = L
     return L
 
@@ -233,6 +236,33 @@ def scan_seed(ref_codes: np.ndarray, seq: np.ndarray, offsets: np.ndarray, bisul
     if not h:
         raise ValueError("scan oracle rejected its arguments")
     return _result(h)
+
+
+PIECE_DTYPE = np.dtype([("read_id", "<u4"), ("qbeg", "<u4"), ("qend", "<u4"), ("seed", "<u4"), ("pos", "<u8")])
+
+
+def bs_refine(ref_codes: np.ndarray, seq: np.ndarray, offsets: np.ndarray, res: SeedResult, role: int,
+              min_len: int = 19) -> np.ndarray:
+    """Bisulfite seed refinement (Section 2.9) of a bisulfite seeding result: every retained (seed,
+    position) pair split at read-C-over-reference-T bases (read 2: G over A) of the original
+    sequences, pieces of >= min_len kept.  Returns PIECE_DTYPE records sorted by (read, qbeg,
+    qend, pos); ``seed`` is the index of the source seed in ``res``."""
+    L = _load()
+    ref = np.ascontiguousarray(ref_codes, dtype=np.uint8)
+    seq = np.ascontiguousarray(seq, dtype=np.uint8)
+    if seq.size == 0:
+        seq = np.zeros(1, np.uint8)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    arrs = [np.ascontiguousarray(a) if a.size else np.zeros(1, a.dtype) for a in
+            (res.read_id, res.qbeg, res.qend, res.pos_off, res.npos, res.pos)]
+    out = C.c_void_p()
+    n = L.orc_bs_refine(_p(ref), ref.size, _p(seq), _p(offsets), *[_p(a) for a in arrs[:5]], len(res), _p(arrs[5]),
+                        int(role), int(min_len), C.byref(out))
+    pieces = np.zeros(n, dtype=PIECE_DTYPE)
+    if n:
+        C.memmove(pieces.ctypes.data, out.value, n * PIECE_DTYPE.itemsize)
+    L.orc_free_ptr(out)
+    return pieces
 
 
 def seed_reads(index: OracleIndex, reads, **kw) -> SeedResult:

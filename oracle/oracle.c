@@ -780,3 +780,62 @@ orc_result *orc_scan_seed(const uint8_t *R, uint64_t len_r, int bisulfite, const
   free(kid_at); free(hstart); free(H); free(bitmap); free(qkid); free(U); free(Q); free(P); free(T);
   return res;
 }
+
+/* ------------------------------------------------------------------------------------------ */
+/* Bisulfite seed refinement (Section 2.9).  A retained seed match pairs the read bases
+ * P[qbeg, qend) with the text T[pos, pos + qend - qbeg) of the four-copy index.  Every text base
+ * has an original reference base: for t < 2|R| (the forward C->T and G->A copies) it is R[t mod |R|],
+ * for 2|R| <= t < 4|R| (the reverse copies) the complement of R[(4|R| - 1 - t) mod |R|].  Comparing
+ * the original read base with it, a read C over a reference T (read 1; read 2: a read G over a
+ * reference A) cannot come from bisulfite conversion; the seed match is split at every such base and
+ * the pieces of at least min_len bases are kept, each with its own text position.
+ * Output: pieces sorted by (read, qbeg, qend, pos). */
+typedef struct { uint32_t read_id, qbeg, qend, seed; uint64_t pos; } orc_piece;
+static int cmp_piece(const void *a, const void *b) {
+  const orc_piece *x = (const orc_piece *)a, *y = (const orc_piece *)b;
+  if (x->read_id != y->read_id) return x->read_id < y->read_id ? -1 : 1;
+  if (x->qbeg != y->qbeg) return x->qbeg < y->qbeg ? -1 : 1;
+  if (x->qend != y->qend) return x->qend < y->qend ? -1 : 1;
+  return x->pos < y->pos ? -1 : x->pos > y->pos;
+}
+static inline int orig_ref_base(const uint8_t *R, uint64_t L, uint64_t t) {   /* 0..3 */
+  if (t < 2 * L) return R[t % L];
+  return 3 - R[(4 * L - 1 - t) % L];
+}
+/* seeds: n_seeds records (read_id, qbeg, qend, pos_off, npos) of a bisulfite seeding result;
+ * returns the number of pieces and a malloc'ed array in *out. */
+uint64_t orc_bs_refine(const uint8_t *R, uint64_t L, const uint8_t *reads, const uint64_t *offsets,
+                       const uint32_t *read_id, const uint32_t *qbeg, const uint32_t *qend, const uint64_t *pos_off,
+                       const uint32_t *npos, uint64_t n_seeds, const uint64_t *pos, int role, int min_len,
+                       orc_piece **out) {
+  uint64_t cap = 1024, n = 0;
+  orc_piece *v = (orc_piece *)malloc(cap * sizeof(orc_piece));
+  for (uint64_t t = 0; t < n_seeds; ++t) {
+    const uint8_t *P = reads + offsets[read_id[t]];
+    for (uint32_t q = 0; q < npos[t]; ++q) {
+      const uint64_t p = pos[pos_off[t] + q];
+      uint32_t start = qbeg[t];
+      for (uint32_t i = qbeg[t]; i <= qend[t]; ++i) {
+        int cut = i == qend[t];
+        if (!cut) {
+          const uint8_t a = enc_ascii(P[i]);                 /* 1..4 = A..T, 5 = other */
+          const int rb = orig_ref_base(R, L, p + (i - qbeg[t]));
+          cut = (role == 1) ? (a == 2 && rb == 3) : (a == 3 && rb == 0);
+        }
+        if (cut) {
+          if (i - start >= (uint32_t)min_len) {
+            if (n == cap) { cap *= 2; v = (orc_piece *)realloc(v, cap * sizeof(orc_piece)); }
+            v[n].read_id = read_id[t]; v[n].qbeg = start; v[n].qend = i; v[n].seed = (uint32_t)t;
+            v[n].pos = p + (start - qbeg[t]);
+            ++n;
+          }
+          start = i + 1;
+        }
+      }
+    }
+  }
+  qsort(v, n, sizeof(orc_piece), cmp_piece);
+  *out = v;
+  return n;
+}
+void orc_free_ptr(void *p) { free(p); }

@@ -36,7 +36,7 @@ SEED_ROUND2 = 2
 EXPORTS = ["mbw_strerror", "mbw_last_error", "mbw_index_build", "mbw_index_save", "mbw_index_load",
            "mbw_index_free", "mbw_index_info", "mbw_index_device_arrays", "mbw_ctx_create", "mbw_ctx_free",
            "mbw_seed", "mbw_result_download", "mbw_pos_to_ref", "mbw_probe_copy", "mbw_probe_gather", "mbw_tune",
-           "mbw_serve_open", "mbw_serve_submit", "mbw_serve_wait", "mbw_serve_release", "mbw_serve_stats",
+           "mbw_result_download_pieces", "mbw_serve_open", "mbw_serve_submit", "mbw_serve_wait", "mbw_serve_release", "mbw_serve_stats",
            "mbw_serve_close"]
 
 
@@ -61,7 +61,7 @@ class IndexInfo(C.Structure):
 class SeedOpts(C.Structure):
     _fields_ = [("min_occ", C.c_int), ("reseed", C.c_int), ("reseed_len", C.c_int), ("reseed_occ", C.c_int),
                 ("bs_role", C.c_int), ("kernel", C.c_int), ("use_kmer", C.c_int), ("blocks_per_cu", C.c_int),
-                ("no_stage", C.c_int), ("unique_ext", C.c_int), ("seg_len", C.c_int)]
+                ("no_stage", C.c_int), ("unique_ext", C.c_int), ("seg_len", C.c_int), ("bs_refine", C.c_int)]
 
 
 class ServeCfg(C.Structure):
@@ -81,12 +81,13 @@ class Result(C.Structure):
                 ("lines_smem", C.c_uint64), ("lines_locate", C.c_uint64), ("steps", C.c_uint64),
                 ("lf_steps", C.c_uint64), ("ms_smem", C.c_float), ("ms_locate", C.c_float), ("ms_total", C.c_float),
                 ("n_smem_launches", C.c_int), ("wave_iters", C.c_uint64), ("lane_iters", C.c_uint64),
-                ("max_chain", C.c_uint64)]
+                ("max_chain", C.c_uint64), ("n_pieces", C.c_uint64), ("pieces", C.c_void_p)]
 
 
 SEED_DTYPE = np.dtype([("read_id", "<u4"), ("qbeg", "<u4"), ("qend", "<u4"), ("flags", "<u4"), ("k", "<u8"),
                        ("kr", "<u8"), ("s", "<u8"), ("pos_off", "<u8"), ("npos", "<u4"), ("reserved", "<u4")])
 assert SEED_DTYPE.itemsize == 56
+PIECE_DTYPE = np.dtype([("read_id", "<u4"), ("qbeg", "<u4"), ("qend", "<u4"), ("seed", "<u4"), ("pos", "<u8")])
 
 _lib = None
 
@@ -117,6 +118,7 @@ def load_library():
     L.mbw_ctx_free.restype = None
     L.mbw_seed.argtypes = [vp, vp, vp, u64, i32, i32, C.POINTER(SeedOpts), vp, C.POINTER(Result)]
     L.mbw_result_download.argtypes = [vp, C.POINTER(Result), vp, vp]
+    L.mbw_result_download_pieces.argtypes = [vp, C.POINTER(Result), vp]
     L.mbw_pos_to_ref.argtypes = [vp, u64, C.c_uint32, C.POINTER(C.c_int), C.POINTER(C.c_uint64)]
     L.mbw_probe_copy.argtypes = [i32, u64, C.POINTER(C.c_float)]
     L.mbw_probe_gather.argtypes = [i32, u64, i32, C.POINTER(C.c_double), C.POINTER(C.c_float)]
@@ -247,6 +249,13 @@ class SeedOutput:
     _res: Result
     _ctx: "Context"
 
+    def download_pieces(self):
+        """Refined bisulfite pieces (PIECE_DTYPE) on the host (``bs_refine=True``)."""
+        n = int(self._res.n_pieces)
+        out = np.zeros(n, dtype=PIECE_DTYPE)
+        _check(self._ctx._lib.mbw_result_download_pieces(self._ctx._h, C.byref(self._res), out.ctypes.data if n else None))
+        return out
+
     def download(self):
         """(seeds structured array, positions uint64 array) on the host."""
         seeds = np.zeros(self.n_seeds, dtype=SEED_DTYPE)
@@ -270,7 +279,7 @@ class Context:
     def seed(self, reads, lengths, min_seed_len: int = 19, max_occ: int = 500, min_occ: int = 1,
              reseed: bool = True, reseed_len: int = 38, reseed_occ: int = 10, bs_role: int = 0,
              kernel: int = KERNEL_COOP, use_kmer: bool = True, blocks_per_cu: int = 0, stage: bool = True,
-             unique_ext: bool = True, seg_len: int = 0, stream=None) -> SeedOutput:
+             unique_ext: bool = True, seg_len: int = 0, bs_refine: bool = False, stream=None) -> SeedOutput:
         """``reads``: concatenated ASCII (numpy uint8 on the host or a torch uint8 CUDA tensor);
         ``lengths``: uint32 per read (numpy or torch)."""
         n = int(lengths.numel() if hasattr(lengths, "numel") else len(lengths))
@@ -279,7 +288,8 @@ class Context:
         if isinstance(reads, np.ndarray):
             reads = np.ascontiguousarray(reads, dtype=np.uint8)
         o = SeedOpts(int(min_occ), int(bool(reseed)), int(reseed_len), int(reseed_occ), int(bs_role), int(kernel),
-                     int(bool(use_kmer)), int(blocks_per_cu), int(not stage), int(bool(unique_ext)), int(seg_len))
+                     int(bool(use_kmer)), int(blocks_per_cu), int(not stage), int(bool(unique_ext)), int(seg_len),
+                     int(bool(bs_refine)))
         res = Result()
         rp = _ptr(reads) if n else None
         lp = _ptr(lengths) if n else None
@@ -295,7 +305,7 @@ class Context:
         n = int(lengths.numel() if hasattr(lengths, "numel") else len(lengths))
         b = SeedOpts(int(base.get("min_occ", 1)), int(bool(base.get("reseed", True))), int(base.get("reseed_len", 38)),
                      int(base.get("reseed_occ", 10)), int(base.get("bs_role", 0)), KERNEL_COOP,
-                     int(bool(base.get("use_kmer", True))), 0, 0, 1, 0)
+                     int(bool(base.get("use_kmer", True))), 0, 0, 1, 0, 0)
         best = SeedOpts()
         ms = C.c_float()
         _check(self._lib.mbw_tune(self._h, _ptr(reads) if n else None, _ptr(lengths) if n else None, n,
@@ -355,7 +365,8 @@ class Server:
         o = SeedOpts(int(opts.get("min_occ", 1)), int(bool(opts.get("reseed", True))), int(opts.get("reseed_len", 38)),
                      int(opts.get("reseed_occ", 10)), int(opts.get("bs_role", 0)), KERNEL_COOP,
                      int(bool(opts.get("use_kmer", True))), int(opts.get("blocks_per_cu", 0)),
-                     int(not opts.get("stage", True)), int(bool(opts.get("unique_ext", True))), int(opts.get("seg_len", 0)))
+                     int(not opts.get("stage", True)), int(bool(opts.get("unique_ext", True))), int(opts.get("seg_len", 0)),
+                     int(bool(opts.get("bs_refine", False))))
         cfg = ServeCfg(int(n_workers), int(max_batch_reads), int(max_batch_bases), int(max_queued_bases),
                        int(min_seed_len), int(max_occ), o, int(index.info()["device"]))
         h = C.c_void_p()

@@ -82,6 +82,21 @@ __global__ void k_pack_text(const uint8_t *__restrict__ Rp, uint64_t lrp, uint64
   }
 }
 
+// the original reference of a bisulfite index from its two converted copies: a T in the C->T copy
+// was a C or a T, which the G->A copy still tells apart; every other base is unchanged there
+__global__ void k_pack_orig(const uint8_t *__restrict__ Rp, uint64_t len, uint64_t *__restrict__ ow, uint64_t nwords) {
+  for (uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; w < nwords; w += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t v = 0;
+    for (int t = 0; t < 32; ++t) {
+      const uint64_t i = w * 32 + t;
+      uint64_t a = 0;
+      if (i < len) a = Rp[i] == 3 ? Rp[len + i] : Rp[i];
+      v |= a << (2 * t);
+    }
+    ow[w] = v;
+  }
+}
+
 __device__ __forceinline__ uint64_t text_sym(const uint64_t *__restrict__ Tw, uint64_t p) {
   return (Tw[p >> 5] >> (2 * (p & 31))) & 3;
 }
@@ -416,6 +431,7 @@ extern "C" void mbw_index_free(mbw_index *ix) {
   if (ix->sbtab) (void)hipFree(ix->sbtab);
   if (ix->text) (void)hipFree(ix->text);
   if (ix->isa) (void)hipFree(ix->isa);
+  if (ix->orig) (void)hipFree(ix->orig);
   (void)hipSetDevice(cur);
   delete ix;
 }
@@ -557,6 +573,13 @@ extern "C" int mbw_index_build(const uint8_t *ref, uint64_t len, const mbw_build
       TRY(hipMemcpyAsync(dR.p, Rp.data(), lrp, hipMemcpyHostToDevice, st));
       k_pack_text<<<grid_for(nwords), 256, 0, st>>>(dR.p, lrp, Tw.p, nwords);
       TRY(hipGetLastError());
+      if (ix->bisulfite) {
+        ix->n_orig = (len + 31) / 32 + 2;
+        TRY(hipMalloc((void **)&ix->orig, ix->n_orig * sizeof(uint64_t)));
+        ix->bytes += ix->n_orig * sizeof(uint64_t);
+        k_pack_orig<<<grid_for(ix->n_orig), 256, 0, st>>>(dR.p, len, ix->orig, ix->n_orig);
+        TRY(hipGetLastError());
+      }
       TRY(hipStreamSynchronize(st));
     }
     std::vector<uint8_t>().swap(Rp);
@@ -682,7 +705,7 @@ extern "C" int mbw_pos_to_ref(const mbw_index *ix, uint64_t pos, uint32_t len, i
 // ---------------------------------------------------------------------------------------------
 // index files: header (magic, version, fields, FNV-1a of header and of each array) + arrays
 static const uint64_t kMagic = 0x3158444e4957424dull;  // "MBWINDX1"
-static const uint32_t kVersion = 4;
+static const uint32_t kVersion = 5;
 
 struct FileHeader {
   uint64_t magic;
@@ -692,8 +715,8 @@ struct FileHeader {
   int32_t sa_sample, kmer_k, bisulfite, n_sb;
   uint64_t sb[MBW_MAX_SB * 8];
   int32_t isa_sample, pad;
-  uint64_t n_text, n_isa;
-  uint64_t sum_lines, sum_ssa, sum_kmer, sum_text, sum_isa;
+  uint64_t n_text, n_isa, n_orig;
+  uint64_t sum_lines, sum_ssa, sum_kmer, sum_text, sum_isa, sum_orig;
   uint64_t sum_header;
 };
 
@@ -717,12 +740,13 @@ extern "C" int mbw_index_save(const mbw_index *ix, const char *path) {
   TRY(hipSetDevice(ix->device));
   uint64_t kb = ix->kmer ? (1ull << (2 * ix->kmer_k)) * 16 : 0;
   std::vector<uint8_t> lines(ix->n_lines * MBW_LINE_BYTES), ssa(ix->n_ssa * 8), kmer(kb), text(ix->n_text * 8),
-      isa(ix->n_isa * 8);
+      isa(ix->n_isa * 8), orig(ix->n_orig * 8);
   TRY(hipMemcpy(lines.data(), ix->lines, lines.size(), hipMemcpyDeviceToHost));
   TRY(hipMemcpy(ssa.data(), ix->ssa, ssa.size(), hipMemcpyDeviceToHost));
   if (kb) TRY(hipMemcpy(kmer.data(), ix->kmer, kb, hipMemcpyDeviceToHost));
   if (text.size()) TRY(hipMemcpy(text.data(), ix->text, text.size(), hipMemcpyDeviceToHost));
   if (isa.size()) TRY(hipMemcpy(isa.data(), ix->isa, isa.size(), hipMemcpyDeviceToHost));
+  if (orig.size()) TRY(hipMemcpy(orig.data(), ix->orig, orig.size(), hipMemcpyDeviceToHost));
   FileHeader hd;
   memset(&hd, 0, sizeof(hd));
   hd.magic = kMagic; hd.version = kVersion; hd.bpl = MBW_BPL;
@@ -731,18 +755,20 @@ extern "C" int mbw_index_save(const mbw_index *ix, const char *path) {
   hd.sa_sample = ix->sa_sample; hd.kmer_k = ix->kmer ? ix->kmer_k : 0; hd.bisulfite = ix->bisulfite;
   hd.n_sb = ix->n_sb;
   memcpy(hd.sb, ix->sb_host, sizeof(hd.sb));
-  hd.isa_sample = ix->isa_sample; hd.n_text = ix->n_text; hd.n_isa = ix->n_isa;
+  hd.isa_sample = ix->isa_sample; hd.n_text = ix->n_text; hd.n_isa = ix->n_isa; hd.n_orig = ix->n_orig;
   hd.sum_lines = sum_words(lines.data(), lines.size());
   hd.sum_ssa = sum_words(ssa.data(), ssa.size());
   hd.sum_kmer = sum_words(kmer.data(), kmer.size());
   hd.sum_text = sum_words(text.data(), text.size());
   hd.sum_isa = sum_words(isa.data(), isa.size());
+  hd.sum_orig = sum_words(orig.data(), orig.size());
   hd.sum_header = fnv(&hd, offsetof(FileHeader, sum_header));
   FILE *f = fopen(path, "wb");
   if (!f) { mbw_set_error(std::string("cannot open ") + path); return MBW_E_IO; }
   bool ok = fwrite(&hd, sizeof(hd), 1, f) == 1 && fwrite(lines.data(), 1, lines.size(), f) == lines.size() &&
             fwrite(ssa.data(), 1, ssa.size(), f) == ssa.size() && (kb == 0 || fwrite(kmer.data(), 1, kb, f) == kb) &&
-            fwrite(text.data(), 1, text.size(), f) == text.size() && fwrite(isa.data(), 1, isa.size(), f) == isa.size();
+            fwrite(text.data(), 1, text.size(), f) == text.size() && fwrite(isa.data(), 1, isa.size(), f) == isa.size() &&
+            fwrite(orig.data(), 1, orig.size(), f) == orig.size();
   ok = (fclose(f) == 0) && ok;
   if (!ok) { mbw_set_error(std::string("write failed: ") + path); return MBW_E_IO; }
   return MBW_OK;
@@ -761,23 +787,24 @@ extern "C" int mbw_index_load(const char *path, int device, mbw_index **out) {
       hd.kmer_k < 0 || hd.kmer_k > 13 || hd.n_sb != (int)(((hd.n_lines - 1) >> MBW_SB_SHIFT) + 1) ||
       hd.isa_sample < 0 || hd.isa_sample > 64 ||
       (hd.isa_sample ? (hd.n_isa != (hd.n - 1) / hd.isa_sample + 1 || hd.n_text != (hd.n - 1 + 31) / 32 + 4)
-                     : (hd.n_isa != 0 || hd.n_text != 0))) {
+                     : (hd.n_isa != 0 || hd.n_text != 0)) ||
+      hd.n_orig != (hd.bisulfite ? (hd.len_r + 31) / 32 + 2 : 0)) {
     fclose(f); mbw_set_error("bad magic, version or header fields"); return MBW_E_FORMAT;
   }
   uint64_t kb = hd.kmer_k ? (1ull << (2 * hd.kmer_k)) * 16 : 0;
-  std::vector<uint8_t> lines, ssa, kmer, text, isa;
+  std::vector<uint8_t> lines, ssa, kmer, text, isa, orig;
   try {
     lines.resize(hd.n_lines * MBW_LINE_BYTES); ssa.resize(hd.n_ssa * 8); kmer.resize(kb);
-    text.resize(hd.n_text * 8); isa.resize(hd.n_isa * 8);
+    text.resize(hd.n_text * 8); isa.resize(hd.n_isa * 8); orig.resize(hd.n_orig * 8);
   } catch (...) { fclose(f); mbw_set_error("host allocation failed"); return MBW_E_NOMEM; }
   bool ok = fread(lines.data(), 1, lines.size(), f) == lines.size() && fread(ssa.data(), 1, ssa.size(), f) == ssa.size() &&
             (kb == 0 || fread(kmer.data(), 1, kb, f) == kb) && fread(text.data(), 1, text.size(), f) == text.size() &&
-            fread(isa.data(), 1, isa.size(), f) == isa.size();
+            fread(isa.data(), 1, isa.size(), f) == isa.size() && fread(orig.data(), 1, orig.size(), f) == orig.size();
   fclose(f);
   if (!ok) { mbw_set_error("truncated index file"); return MBW_E_FORMAT; }
   if (sum_words(lines.data(), lines.size()) != hd.sum_lines || sum_words(ssa.data(), ssa.size()) != hd.sum_ssa ||
       sum_words(kmer.data(), kmer.size()) != hd.sum_kmer || sum_words(text.data(), text.size()) != hd.sum_text ||
-      sum_words(isa.data(), isa.size()) != hd.sum_isa) {
+      sum_words(isa.data(), isa.size()) != hd.sum_isa || sum_words(orig.data(), orig.size()) != hd.sum_orig) {
     mbw_set_error("index checksum mismatch"); return MBW_E_FORMAT;
   }
   TRY(hipSetDevice(device));
@@ -788,7 +815,7 @@ extern "C" int mbw_index_load(const char *path, int device, mbw_index **out) {
   ix->sa_sample = hd.sa_sample; ix->kmer_k = hd.kmer_k; ix->bisulfite = hd.bisulfite;
   ix->n_sb = hd.n_sb;
   memcpy(ix->sb_host, hd.sb, sizeof(hd.sb));
-  ix->isa_sample = hd.isa_sample; ix->n_text = hd.n_text; ix->n_isa = hd.n_isa;
+  ix->isa_sample = hd.isa_sample; ix->n_text = hd.n_text; ix->n_isa = hd.n_isa; ix->n_orig = hd.n_orig;
   int rc = [&]() -> int {
     TRY(hipMalloc((void **)&ix->sbtab, sizeof(hd.sb)));
     TRY(hipMemcpy(ix->sbtab, hd.sb, sizeof(hd.sb), hipMemcpyHostToDevice));
@@ -806,7 +833,11 @@ extern "C" int mbw_index_load(const char *path, int device, mbw_index **out) {
       TRY(hipMalloc((void **)&ix->isa, isa.size()));
       TRY(hipMemcpy(ix->isa, isa.data(), isa.size(), hipMemcpyHostToDevice));
     }
-    ix->bytes = lines.size() + ssa.size() + kb + sizeof(hd.sb) + text.size() + isa.size();
+    if (orig.size()) {
+      TRY(hipMalloc((void **)&ix->orig, orig.size()));
+      TRY(hipMemcpy(ix->orig, orig.data(), orig.size(), hipMemcpyHostToDevice));
+    }
+    ix->bytes = lines.size() + ssa.size() + kb + sizeof(hd.sb) + text.size() + isa.size() + orig.size();
     return 0;
   }();
   if (rc) { mbw_index_free(ix); return rc; }

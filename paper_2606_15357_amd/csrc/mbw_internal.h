@@ -20,6 +20,7 @@
 //   * optional: the text T without its $ (2 bits per symbol, 32 per u64, first symbol in the low
 //     bits) and the inverse suffix array at text positions that are multiples of q,
 //     isa[t / q] = the row whose suffix starts at t.
+//   * bisulfite indexes: the original (unconverted) reference R, packed like the text.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -48,6 +49,8 @@ struct mbw_index {
   uint64_t n_text, n_isa;      // u64 words of the packed text, inverse-SA samples
   uint64_t *text;
   uint64_t *isa;
+  uint64_t n_orig;             // bisulfite indexes: the original reference, packed like the text
+  uint64_t *orig;
   uint64_t bytes;
 };
 
@@ -65,6 +68,8 @@ struct IndexView {
   const uint64_t *__restrict__ text;   // packed T without $ (nullptr when absent)
   const uint64_t *__restrict__ isa;    // isa[t / ri] = row of the suffix at t
   uint32_t ri;
+  const uint64_t *__restrict__ orig;   // bisulfite: the original reference, packed (nullptr otherwise)
+  uint64_t len_r;
 };
 
 static inline IndexView make_view(const mbw_index *ix) {
@@ -74,6 +79,7 @@ static inline IndexView make_view(const mbw_index *ix) {
   for (int a = 0; a < 4; ++a) v.Cb[a] = ix->C[a + 1];
   v.r = (uint32_t)ix->sa_sample; v.K = ix->kmer_k; v.n_sb = ix->n_sb;
   v.text = ix->text; v.isa = ix->isa; v.ri = (uint32_t)ix->isa_sample;
+  v.orig = ix->orig; v.len_r = ix->len_r;
   return v;
 }
 

@@ -980,6 +980,72 @@ __global__ void k_bs_seeds(mbw_seed_t *__restrict__ seeds, uint64_t ns, const ui
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// bisulfite seed refinement (Section 2.9): every kept (seed, position) pair is compared base by
+// base with the original read and the original reference; it is split where read 1 has a C over a
+// reference T (read 2: G over A), which bisulfite conversion cannot produce, and pieces of at
+// least min_len bases are kept with their own text positions
+
+// the seed of every kept position
+__global__ void __launch_bounds__(256) k_pos_seed(const mbw_seed_t *__restrict__ seeds, uint64_t ns, uint32_t *__restrict__ ps) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t nwave = (uint64_t)gridDim.x * (blockDim.x >> 6);
+  for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64; base < ns; base += nwave * 64) {
+    uint64_t off = 0;
+    uint32_t np = 0;
+    if (base + lane < ns) { off = seeds[base + lane].pos_off; np = seeds[base + lane].npos; }
+    const int cnt = (int)min<uint64_t>(64, ns - base);
+    for (int t = 0; t < cnt; ++t) {
+      const uint64_t ot = __shfl(off, t);
+      const uint32_t nt = (uint32_t)__shfl((int)np, t);
+      for (uint32_t q = (uint32_t)lane; q < nt; q += 64) ps[ot + q] = (uint32_t)(base + t);
+    }
+  }
+}
+
+// original reference base (0..3) under text position t of the four-copy bisulfite text
+__device__ __forceinline__ int orig_base(const uint64_t *__restrict__ orig, uint64_t L, uint64_t t) {
+  uint64_t q;
+  bool rc = t >= 2 * L;
+  q = rc ? 4 * L - 1 - t : t;
+  if (q >= L) q -= L;
+  const int b = (int)((orig[q >> 5] >> (2 * (q & 31))) & 3);
+  return rc ? 3 - b : b;
+}
+
+// pass 0 (out == nullptr): pieces per position into cnt; pass 1: write them at poff
+__global__ void k_refine(const mbw_seed_t *__restrict__ seeds, const uint32_t *__restrict__ pseed,
+                         const uint64_t *__restrict__ pos, uint64_t np, const uint8_t *__restrict__ ascii,
+                         const uint64_t *__restrict__ offs, const uint64_t *__restrict__ orig, uint64_t L, int role,
+                         int min_len, uint32_t *__restrict__ cnt, const uint64_t *__restrict__ poff,
+                         mbw_piece_t *__restrict__ out) {
+  const uint32_t bad = role == 1 ? 'C' : 'G';          // read base that cannot face ...
+  const int over = role == 1 ? 3 : 0;                  // ... this original reference base
+  for (uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; w < np; w += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t t = pseed[w];
+    const mbw_seed_t sd = seeds[t];
+    const uint64_t p = pos[w];
+    const uint8_t *P = ascii + offs[sd.read_id];
+    uint32_t start = sd.qbeg, c = 0;
+    for (uint32_t i = sd.qbeg; i <= sd.qend; ++i) {
+      bool cut = i == sd.qend;
+      if (!cut) cut = ((uint32_t)P[i] & 0xDFu) == bad && orig_base(orig, L, p + (i - sd.qbeg)) == over;
+      if (cut) {
+        if (i - start >= (uint32_t)min_len) {
+          if (out) {
+            mbw_piece_t x;
+            x.read_id = sd.read_id; x.qbeg = start; x.qend = i; x.seed = t; x.pos = p + (start - sd.qbeg);
+            out[poff[w] + c] = x;
+          }
+          ++c;
+        }
+        start = i + 1;
+      }
+    }
+    if (!out) cnt[w] = c;
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------------------------
@@ -991,7 +1057,7 @@ struct mbw_ctx {
   struct Buf { void *p = nullptr; size_t bytes = 0; };   // grow-only device buffers (stream-ordered allocations)
   Buf codes, ascii, lens, offs, raw, subq, keys0, keys1, vals0, vals1, flag, idx, seeds, npos, posoff, xrows, pos, pos2,
       keep, kidx, temp, ctl, pwords, pnmask, woffs, nwords, wread, q1, q2, bf0, bf1, bp0, bp1, bid0, bid1, bk0, bk1, q1s,
-      q2s, sc0, sc1;
+      q2s, sc0, sc1, pseed, pcnt, ppoff, pieces;
   hipEvent_t ev[8];
   hipStream_t cur = nullptr;   // stream of the current / last mbw_seed call
   unsigned long long host_ctl[C_COUNT];
@@ -1050,7 +1116,7 @@ extern "C" void mbw_ctx_free(mbw_ctx *c) {
                         &c->vals1, &c->flag, &c->idx, &c->seeds, &c->npos, &c->posoff, &c->xrows, &c->pos, &c->pos2,
                         &c->keep, &c->kidx, &c->temp, &c->ctl, &c->pwords, &c->pnmask, &c->woffs, &c->nwords, &c->wread,
                         &c->q1, &c->q2, &c->bf0, &c->bf1, &c->bp0, &c->bp1, &c->bid0, &c->bid1, &c->bk0, &c->bk1,
-                        &c->q1s, &c->q2s, &c->sc0, &c->sc1};
+                        &c->q1s, &c->q2s, &c->sc0, &c->sc1, &c->pseed, &c->pcnt, &c->ppoff, &c->pieces};
   for (auto *b : bs) if (b->p) (void)hipFreeAsync(b->p, c->cur);
   (void)hipStreamSynchronize(c->cur);
   for (int t = 0; t < 8; ++t) (void)hipEventDestroy(c->ev[t]);
@@ -1173,6 +1239,9 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   }
   if (o.min_occ < 1) { mbw_set_error("min_occ must be >= 1"); return MBW_E_INVAL; }
   if (o.bs_role && !c->ix->bisulfite) { mbw_set_error("bs_role needs a bisulfite index"); return MBW_E_INVAL; }
+  if (o.bs_refine && (!o.bs_role || !c->ix->orig)) {
+    mbw_set_error("bs_refine needs bs_role and a bisulfite index"); return MBW_E_INVAL;
+  }
   if (o.bs_role < 0 || o.bs_role > 2) { mbw_set_error("bs_role must be 0, 1 or 2"); return MBW_E_INVAL; }
   if (o.kernel != MBW_KERNEL_COOP && o.kernel != MBW_KERNEL_PLAIN) { mbw_set_error("unknown kernel"); return MBW_E_INVAL; }
   TRY(hipSetDevice(c->device));
@@ -1469,6 +1538,31 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     n_pos = kept;
     final_pos = (const uint64_t *)c->pos2.p;
   }
+  // bisulfite refinement of every kept (seed, position) pair
+  uint64_t n_pieces = 0;
+  if (o.bs_refine && n_pos) {
+    GROW(c->pseed, (n_pos + 1) * 4);
+    GROW(c->pcnt, (n_pos + 1) * 4);
+    GROW(c->ppoff, (n_pos + 1) * 8);
+    uint32_t *ps = (uint32_t *)c->pseed.p, *pc = (uint32_t *)c->pcnt.p;
+    uint64_t *po = (uint64_t *)c->ppoff.p;
+    k_pos_seed<<<grid_for((nu + 63) / 64 * 64 / 4, 256, 65536u), 256, 0, st>>>(seeds, nu, ps);
+    TRY(hipGetLastError());
+    k_refine<<<grid_for(n_pos), 256, 0, st>>>(seeds, ps, final_pos, n_pos, dreads, offs, ix->orig, ix->len_r, o.bs_role,
+                                              min_seed_len, pc, nullptr, nullptr);
+    TRY(hipGetLastError());
+    TRY(hipMemsetAsync(pc + n_pos, 0, 4, st));
+    r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, pc, po, n_pos + 1, st); });
+    if (r) return r;
+    TRY(hipMemcpyAsync(&n_pieces, po + n_pos, 8, hipMemcpyDeviceToHost, st));
+    TRY(hipStreamSynchronize(st));
+    GROW(c->pieces, (n_pieces + 1) * sizeof(mbw_piece_t));
+    if (n_pieces) {
+      k_refine<<<grid_for(n_pos), 256, 0, st>>>(seeds, ps, final_pos, n_pos, dreads, offs, ix->orig, ix->len_r, o.bs_role,
+                                                min_seed_len, pc, po, (mbw_piece_t *)c->pieces.p);
+      TRY(hipGetLastError());
+    }
+  }
   TRY(hipMemcpyAsync(c->host_ctl, ctl, C_COUNT * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
   TRY(hipEventRecord(c->ev[5], st));
   TRY(hipEventSynchronize(c->ev[5]));
@@ -1494,6 +1588,17 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   out->wave_iters = c->host_ctl[C_WITER];
   out->lane_iters = c->host_ctl[C_LITER];
   out->max_chain = c->host_ctl[C_MAXCHAIN];
+  out->n_pieces = n_pieces;
+  out->pieces = n_pieces ? (const mbw_piece_t *)c->pieces.p : nullptr;
+  return MBW_OK;
+}
+
+extern "C" int mbw_result_download_pieces(mbw_ctx *c, const mbw_result *res, mbw_piece_t *pieces) {
+  if (!c || !res) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
+  TRY(hipSetDevice(c->device));
+  if (pieces && res->n_pieces)
+    TRY(hipMemcpyAsync(pieces, res->pieces, res->n_pieces * sizeof(mbw_piece_t), hipMemcpyDeviceToHost, c->cur));
+  TRY(hipStreamSynchronize(c->cur));
   return MBW_OK;
 }
 

@@ -291,3 +291,48 @@ def test_hand_worked_example():
                         assert sorted(int(x) for x in flat[off:off + n]) == g["positions"][sub]
                     off += n
         idx.free()
+
+
+def test_bisulfite_refinement():
+    """Refined bisulfite seed matches (Section 2.9) equal the oracle's, piece for piece, for read 1
+    (C->T) and read 2 (G->A) reads, with SNP-like planted mismatches; the index's stored original
+    reference decodes to R."""
+    ref = synth.reference(0, 200_000, 31)
+    ox = oracle.OracleIndex(ref.codes, bisulfite=True, sa_rate=8)
+    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=10, bisulfite=True)
+    with tempfile.TemporaryDirectory() as d:
+        p = os.path.join(d, "bs.mbw")
+        idx.save(p)
+        f = read_index_file(p)
+    sh = np.arange(32, dtype=np.uint64) * 2
+    orig = ((f["orig"][:, None] >> sh) & 3).reshape(-1)[: len(ref)].astype(np.uint8)
+    assert np.array_equal(orig, ref.codes)
+    rs = synth.reads_bisulfite(ref, 2000, seed=5)
+    # read 2 form: the G->A image of the same fragments (complement strand view)
+    seq2 = rs.seq.copy()
+    comp = bytes.maketrans(b"ACGT", b"TGCA")
+    for r in range(len(rs)):
+        a, b = int(rs.offsets[r]), int(rs.offsets[r + 1])
+        seq2[a:b] = np.frombuffer(rs.seq[a:b].tobytes().translate(comp)[::-1], np.uint8)
+    rng = np.random.default_rng(4)
+    for s_ in (rs.seq, seq2):                                   # a few planted C/G changes
+        hit = rng.integers(0, s_.size, s_.size // 200)
+        s_[hit] = np.where(rng.random(hit.size) < 0.5, ord("C"), ord("G"))
+    for role, seq in ((1, rs.seq), (2, seq2)):
+        exp_seeds = ox.seed(seq, rs.offsets, bs_role=role)
+        exp = oracle.bs_refine(ref.codes, seq, rs.offsets, exp_seeds, role, min_len=19)
+        assert len(exp) > 500
+        for kernel in (0, 1):
+            ctx = mbw.Context(idx)
+            out = ctx.seed(seq, rs.lengths, bs_role=role, kernel=kernel, bs_refine=True)
+            seeds, pos = out.download()
+            compare_with_oracle(seeds, pos, exp_seeds)
+            got = out.download_pieces()
+            order = np.lexsort((got["pos"], got["qend"], got["qbeg"], got["read_id"]))
+            got = got[order]
+            for fld in ("read_id", "qbeg", "qend", "pos"):
+                assert np.array_equal(got[fld], exp[fld]), fld
+            # the source seed: same (read, interval) family
+            assert np.all(seeds["read_id"][got["seed"]] == got["read_id"])
+            ctx.free()
+    idx.free()

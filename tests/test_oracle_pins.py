@@ -393,3 +393,63 @@ def test_scan_oracle_equals_definition_workload_slice():
         exp = obs.seed(brs.seq, brs.offsets, bs_role=role)
         got = oracle.scan_seed(bref.codes, brs.seq, brs.offsets, bisulfite=True, bs_role=role)
         _same_except_bounds(got, exp)
+
+
+def _bs_convert(s, frm, to, rng, p=1.0):
+    return "".join(to if (ch == frm and rng.random() < p) else ch for ch in s)
+
+
+@pytest.mark.parametrize("strand,role", [("fwd", 1), ("rev", 1), ("fwd", 2)])
+def test_bs_refine_truth(strand, role):
+    """Bisulfite refinement (Section 2.9) against simulation truth.  A read 1 is the C->T image of
+    the forward (or reverse) strand at offset o with 70% of its C's converted; a read 2 the G->A
+    image of the forward strand.  At its true text position (forward C->T copy: o; reverse: the
+    reverse G->A copy at 3|R| - o - m; forward G->A copy: |R| + o) the seed stays whole, and a
+    planted read C over reference T (read 2: G over A) at base q splits it into [0, q) and [q+1, m)
+    (pieces shorter than 19 dropped), the second piece at text position + q + 1."""
+    rng = np.random.default_rng(7)
+    L = 20_000
+    R = to_str(rng.integers(0, 4, L))
+    ox = oracle.OracleIndex(ref_codes(R), bisulfite=True, sa_rate=4)
+    m = 120
+    for trial in range(12):
+        o = int(rng.integers(0, L - m))
+        src = R[o:o + m] if strand == "fwd" else brute.revcomp(R[o:o + m])
+        if role == 1:
+            clean = _bs_convert(src, "C", "T", rng, 0.7)
+            bad, over = "C", "T"
+        else:
+            clean = _bs_convert(src, "G", "A", rng, 0.7)
+            bad, over = "G", "A"
+        truth = o if (strand == "fwd" and role == 1) else (L + o if role == 2 else 3 * L - o - m)
+        cand = [q for q in range(5, m - 5) if src[q] == over]
+        q = cand[int(rng.integers(0, len(cand)))]
+        planted = clean[:q] + bad + clean[q + 1:]
+        for read, cut in ((clean, None), (planted, q)):
+            seq, offs = csr([read])
+            res = ox.seed(seq, offs, min_len=19, bs_role=role, reseed=False)
+            pieces = oracle.bs_refine(ref_codes(R), seq, offs, res, role, min_len=19)
+            at = [(int(p["qbeg"]), int(p["qend"]), int(p["pos"])) for p in pieces
+                  if int(p["pos"]) - int(p["qbeg"]) == truth]
+            if cut is None:
+                assert at == [(0, m, truth)], (trial, at)
+            else:
+                exp = [(a, b, truth + a) for a, b in ((0, cut), (cut + 1, m)) if b - a >= 19]
+                assert at == exp, (trial, cut, at, exp)
+
+
+def test_bs_refine_pieces_are_maximal_and_clean():
+    """On a bisulfite workload: pieces lie inside their seeds, are at least 19 long, sorted, and
+    two pieces of one (seed, position) are separated by exactly the excluded base(s)."""
+    ref = synth.reference(0, 100_000, 31)
+    ox = oracle.OracleIndex(ref.codes, bisulfite=True, sa_rate=8)
+    rs = synth.reads_bisulfite(ref, 400, seed=5)
+    res = ox.seed(rs.seq, rs.offsets, bs_role=1)
+    pieces = oracle.bs_refine(ref.codes, rs.seq, rs.offsets, res, 1, min_len=19)
+    assert len(pieces) > 200
+    for p in pieces:
+        t = int(p["seed"])
+        assert res.read_id[t] == p["read_id"] and res.qbeg[t] <= p["qbeg"] < p["qend"] <= res.qend[t]
+        assert p["qend"] - p["qbeg"] >= 19
+    key = np.lexsort((pieces["pos"], pieces["qend"], pieces["qbeg"], pieces["read_id"]))
+    assert np.array_equal(key, np.arange(len(pieces)))
