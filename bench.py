@@ -156,13 +156,108 @@ def serve_leg(mbw, idx, reads, seconds: float, sched: dict):
                 request_size="log-uniform 1..20000 reads", arrivals="Poisson at half the closed-loop saturation")
 
 
+def serve_bs(mbw, synth, args):
+    """Serving with a bisulfite index and a plain index of the same 3.1 Gbp reference resident:
+    Poisson requests of log-uniform 1..20,000 reads; 90% of them directional bisulfite reads
+    (150 bp, read-1 form, seeded against the four-copy index with the strand filter and the seed
+    refinement), 10% plain reads of 1-5 kbp (against the plain index); arrival rate at half of the
+    closed-loop saturation; p50/p99 from submission to result on the host."""
+    import threading
+    t0 = time.time()
+    ref = synth.workload_reference("serve_bs_3gbp", args.ref_len or None)
+    bs_idx = mbw.Index.build(ref.codes, sa_sample=args.sa_sample, kmer_k=args.kmer, bisulfite=True, isa_sample=8)
+    t_bs = time.time() - t0
+    t0 = time.time()
+    pl_idx = mbw.Index.build(ref.codes, sa_sample=args.sa_sample, kmer_k=args.kmer, isa_sample=args.isa_sample)
+    t_pl = time.time() - t0
+    log(f"indexes built: bisulfite {t_bs:.1f} s ({bs_idx.info()['bytes_resident'] / 1e9:.1f} GB), "
+        f"plain {t_pl:.1f} s ({pl_idx.info()['bytes_resident'] / 1e9:.1f} GB)")
+    bs_pool = synth.reads_bisulfite(ref, 1_000_000, seed=synth.READ_SEED + 4)
+    pl_pool = synth.reads_uniform_len(ref, 20_000, 1000, 5000, p_sub=0.001, p_indel=0.0002, seed=synth.READ_SEED + 5)
+    rng = np.random.default_rng(3001)
+
+    def request():
+        m = int(np.exp(rng.uniform(0.0, np.log(20000.0))))
+        bs = rng.random() < 0.9
+        pool = bs_pool if bs else pl_pool
+        m = min(m, len(pool) - 1)
+        r0 = int(rng.integers(0, len(pool) - m))
+        return bs, pool.seq[int(pool.offsets[r0]):int(pool.offsets[r0 + m])], pool.lengths[r0:r0 + m]
+
+    srv = {True: mbw.Server(bs_idx, n_workers=4, max_batch_reads=100_000, bs_role=1, bs_refine=True),
+           False: mbw.Server(pl_idx, n_workers=2, max_batch_reads=20_000)}
+    for _ in range(3):
+        for k in (True, False):
+            srv[k].wait(srv[k].submit(*request()[1:]))
+    burst = [request() for _ in range(300)]
+    t0 = time.perf_counter()
+    ts = [(b, srv[b].submit(x, y)) for b, x, y in burst]
+    for b, t in ts:
+        srv[b].wait(t)
+    bases = sum(int(y.sum()) for _, _, y in burst)
+    sat_reads = sum(len(y) for _, _, y in burst) / (time.perf_counter() - t0)
+    mean_req = (20000.0 - 1.0) / np.log(20000.0)
+    qps = 0.5 * sat_reads / mean_req
+    arrivals = np.cumsum(rng.exponential(1.0 / qps, size=int(qps * args.serve_seconds * 1.2) + 10))
+    arrivals = arrivals[arrivals < args.serve_seconds]
+    reqs = [request() for _ in range(arrivals.size)]
+    tickets, infos = [], []
+
+    def waiter():
+        k = 0
+        while k < len(reqs):
+            if k >= len(tickets):
+                time.sleep(0.0002)
+                continue
+            b, t = tickets[k]
+            infos.append((b, srv[b].wait(t)[2]))
+            k += 1
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = time.perf_counter()
+    for a, (b, x, y) in zip(arrivals, reqs):
+        d = t0 + a - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        t = srv[b].submit(x, y)
+        while t is None:
+            time.sleep(0.0005)
+            t = srv[b].submit(x, y)
+        tickets.append((b, t))
+    th.join()
+    wall = time.perf_counter() - t0
+    for k in srv:
+        srv[k].close()
+    lat = {k: np.array([(i["t_done"] - i["t_submit"]) * 1e3 for b, i in infos if b == k]) for k in (True, False)}
+    allat = np.concatenate([lat[True], lat[False]])
+    nr = sum(len(y) for _, _, y in reqs)
+    res = dict(metric="reads seeded/s served (bisulfite + plain), p50/p99 request latency", value=round(nr / wall, 1),
+               unit="reads/s", n_gpus=1, higher_is_better=True, data="synthetic", dtype="u64",
+               requests=len(reqs), reads=nr, qps=round(qps, 1), seconds=args.serve_seconds,
+               p50_ms=round(float(np.percentile(allat, 50)), 3), p99_ms=round(float(np.percentile(allat, 99)), 3),
+               bisulfite=dict(requests=int(lat[True].size), p50_ms=round(float(np.percentile(lat[True], 50)), 3),
+                              p99_ms=round(float(np.percentile(lat[True], 99)), 3)),
+               plain_long=dict(requests=int(lat[False].size),
+                               p50_ms=round(float(np.percentile(lat[False], 50)), 3) if lat[False].size else None,
+                               p99_ms=round(float(np.percentile(lat[False], 99)), 3) if lat[False].size else None),
+               saturation_reads_per_s=round(sat_reads, 1), burst_bases=bases,
+               config=dict(workload="3.1 Gbp synthetic reference; bisulfite 4-copy index (n = 12.4 G + 1) and plain "
+                                    "index resident; 90% directional bisulfite 150 bp requests (strand filter + seed "
+                                    "refinement), 10% plain 1-5 kbp; log-uniform 1..20000 reads per request; Poisson "
+                                    "arrivals at half the closed-loop saturation",
+                           index_build_s=dict(bisulfite=round(t_bs, 1), plain=round(t_pl, 1))))
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="human_3gbp", choices=["human_3gbp", "paired_100mbp", "lognormal_100mbp"],
-                    help="human_3gbp (the headline), or one of the 100 Mbp workloads")
+    ap.add_argument("--workload", default="human_3gbp",
+                    choices=["human_3gbp", "paired_100mbp", "lognormal_100mbp", "serve_bs_3gbp"],
+                    help="human_3gbp (the headline), one of the 100 Mbp workloads, or the bisulfite serving workload")
     ap.add_argument("--ref-len", type=int, default=0, help="reference length (0 = the workload's)")
     ap.add_argument("--pairs", type=int, default=0, help="read pairs / reads (0 = the workload's)")
     ap.add_argument("--sa-sample", type=int, default=8)
@@ -196,6 +291,9 @@ def main():
         lps, gms = mbw.probe_gather(8 << 30, iters=32)
         print(json.dumps(dict(copy_bytes=1 << 30, copy_ms=round(ms, 3), copy_gbs=round(2 * (1 << 30) / ms / 1e6, 1),
                               gather_lines_per_s=lps, gather_gbs_128=round(lps * 128 / 1e9, 1), gather_ms=round(gms, 3))))
+        return
+    if args.workload == "serve_bs_3gbp":
+        serve_bs(mbw, synth, args)
         return
     gather_lps, _ = mbw.probe_gather(8 << 30, iters=32)
     t0 = time.time()
