@@ -308,8 +308,12 @@ __device__ __forceinline__ void wave_close(const SeedParams &P, int lane, const 
 enum { ACT_DONE = 0, ACT_KMER = 1, ACT_BWD = 2, ACT_FWD = 3, ACT_LF = 4, ACT_SSA = 5, ACT_TEXT = 6, ACT_ISA = 7 };
 enum { ST_IDLE = 0, ST_REC = 1, ST_STAGE = 2, ST_ACTIVE = 3, ST_DRAINED = 4 };
 
-template <bool STAGED>
+// STAGED: reads staged in LDS (the short-read bin; never segmented).  UNIQ: the unique-match path
+// is compiled in (round 1; in round 2 every interval has s >= c' >= 2).  Segment handling is
+// compiled into the unstaged kernel only.
+template <bool STAGED, bool UNIQ>
 __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, SeedParams P, ReadWords R) {
+  constexpr bool SEG = !STAGED;
   __shared__ uint64_t sw[SMEM_WAVES][STAGED ? STAGE_WORDS * 64 : 1];   // staged bases, word w of lane L at [64 w + L]
   __shared__ uint32_t sn[SMEM_WAVES][STAGED ? STAGE_WORDS * 64 : 1];   // staged N bits
   __shared__ uint64_t sbt[MBW_MAX_SB * 8];
@@ -363,18 +367,18 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
     if (st == ST_ACTIVE && --budget == 0) { atomicOr(&P.ctl[C_ERR], 1ull); st = ST_IDLE; }
     if (st == ST_ACTIVE) {
       for (;;) {
-        if (u >= 4) {                                   // unique path
-          if (u == 4) {
+        if ((UNIQ || SEG) && u >= 4) {                  // unique path (4-7), segment left check (8)
+          if (UNIQ && u == 4) {
             const bool smp = (wrow & P.rmask) == 0;
             if (smp) { act = ACT_SSA; break; }
             if (wrow == ix.primary) { wrow = 0; ++wcnt; continue; }   // LF of the $ row is row 0
             act = ACT_LF; break;
           }
-          if (u == 5) { act = ACT_TEXT; break; }
-          if (u == 6) { act = ACT_ISA; break; }
-          if (u == 7) {
+          if (UNIQ && u == 5) { act = ACT_TEXT; break; }
+          if (UNIQ && u == 6) { act = ACT_ISA; break; }
+          if (UNIQ && u == 7) {
             if (wcnt > 0) { act = ACT_LF; break; }
-            if (segchk && i == (int)qbeg) { segchk = false; kr = wrow; s = 1; u = 8; continue; }
+            if (SEG && segchk && i == (int)qbeg) { segchk = false; kr = wrow; s = 1; u = 8; continue; }
             em = true; e.i = i; e.j = j; e.k = k; e.kr = wrow; e.s = 1;
             if (j == (int)qend) { act = ACT_DONE; break; }
             u = 3; k = 0; kr = 0; s = ix.n; fresh = true;
@@ -391,9 +395,9 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
         if (u == 2) {
           const bool qe = j == (int)qend;
           a = qe ? 4 : base_at(j);
-          if (!qe && P.uniq && s == 1) { u = 4; wrow = k; wcnt = 0; continue; }
+          if (UNIQ && !qe && P.uniq && s == 1) { u = 4; wrow = k; wcnt = 0; continue; }
           if (a > 3) {                                  // end of the query, or a non-ACGT base: SMEM [i, j)
-            if (segchk && i == (int)qbeg) { segchk = false; u = 8; continue; }
+            if (SEG && segchk && i == (int)qbeg) { segchk = false; u = 8; continue; }
             em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s;
             if (qe) { act = ACT_DONE; break; }
             u = 3; k = 0; kr = 0; s = ix.n; fresh = true;
@@ -403,7 +407,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
         }
         if (u == 1 && j < i) { u = 2; j = i + (int)l; fresh = false; continue; }
         if (u == 3 && j <= i) {
-          if (j + 1 >= (int)segend) { act = ACT_DONE; break; }   // the next start belongs to the next segment
+          if (SEG && j + 1 >= (int)segend) { act = ACT_DONE; break; }   // the next start belongs to the next segment
           u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; continue;
         }
         if (fresh && K > 0 && j - K + 1 >= (u == 1 ? i : i + 1)) {
@@ -418,7 +422,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
         fresh = false;
         a = base_at(j);
         if (a > 3) {                                    // BackStep fails on a non-ACGT base
-          if (j + (int)l < (int)qend && j + 1 < (int)segend) {
+          if (j + (int)l < (int)qend && (!SEG || j + 1 < (int)segend)) {
             u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; continue;
           }
           act = ACT_DONE; break;
@@ -429,7 +433,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
     }
     const bool ext = act == ACT_BWD || act == ACT_FWD;
     const bool bwd = act == ACT_BWD;
-    const bool lfa = act == ACT_LF;
+    const bool lfa = UNIQ && act == ACT_LF;
     const uint64_t x1 = lfa ? wrow : (bwd ? k : kr), y = bwd ? kr : k;
     const int cc = bwd ? a : 3 - a;
     const uint64_t x2 = x1 + (lfa ? 0ull : s);            // an LF step ranks one row
@@ -446,14 +450,14 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
     if (blk2) bb = l2p[2 + (o2 >> 6)];
     // unique path: a sampled SA / inverse-SA value, or 32 bytes of text around position tq
     const uint64_t tq = tp + (uint64_t)(j - i);
-    const bool txt = act == ACT_TEXT && tq < tm;
+    const bool txt = UNIQ && act == ACT_TEXT && tq < tm;
     if (txt) {
       const uint4 *tw = (const uint4 *)(ix.text + ((tq >> 5) & ~1ull));
       h0b = tw[0]; h1b = tw[1];
     }
     uint64_t mval = 0;
-    if (act == ACT_SSA) mval = ix.ssa[wrow >> P.rshift];
-    if (act == ACT_ISA) mval = ix.isa[wrow];
+    if (UNIQ && act == ACT_SSA) mval = ix.ssa[wrow >> P.rshift];
+    if (UNIQ && act == ACT_ISA) mval = ix.isa[wrow];
     uint4 kent = make_uint4(0, 0, 0, 0);
     if (act == ACT_KMER) kent = ix.kmer[code];
     const int st_mem = st;
@@ -497,7 +501,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
       } else {
         n_lines += two ? 2 : 1;
         ++n_steps;
-        if (u == 8) {                                     // left check: report unless P[i-1, j) occurs c times
+        if (SEG && u == 8) {                              // left check: report unless P[i-1, j) occurs c times
           if (ns < c) { em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s; }
           if (j == (int)qend) st = ST_IDLE;
           else { u = 3; k = 0; kr = 0; s = ix.n; fresh = true; }
@@ -505,9 +509,9 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
           if (bwd) { k = nx; kr = ny; s = ns; j -= 1; }
           else { kr = nx; k = ny; s = ns; j += 1; }
         } else if (bwd) {                                 // BackStep failure: jump past j
-          if (j + (int)l < (int)qend && j + 1 < (int)segend) { u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; }
+          if (j + (int)l < (int)qend && (!SEG || j + 1 < (int)segend)) { u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; }
           else st = ST_IDLE;
-        } else if (segchk && i == (int)qbeg) {           // forward failure at a segment's first SMEM
+        } else if (SEG && segchk && i == (int)qbeg) {    // forward failure at a segment's first SMEM
           segchk = false; u = 8;
         } else {                                          // forward failure: report, then stage 3 from j
           em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s;
@@ -515,14 +519,14 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
         }
       }
     }
-    if (act == ACT_SSA) {                               // the occurrence: p = S(row) + steps (mod n)
+    if (UNIQ && act == ACT_SSA) {                       // the occurrence: p = S(row) + steps (mod n)
       uint64_t pp = mval + wcnt;
       if (pp >= ix.n) pp -= ix.n;
       tp = pp;
       u = 5;
       ++n_lines;
     }
-    if (act == ACT_TEXT) {                              // compare up to 64 bases of read and text
+    if (UNIQ && act == ACT_TEXT) {                      // compare up to 64 bases of read and text
       const int lim0 = min(64, (int)qend - j);
       int first = 0;
       if (txt) {
@@ -560,7 +564,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
         else { wrow = q >> P.rishift; wcnt = (uint32_t)(q - pm); u = 6; }
       }
     }
-    if (act == ACT_ISA) { wrow = mval; u = 7; ++n_lines; }
+    if (UNIQ && act == ACT_ISA) { wrow = mval; u = 7; ++n_lines; }
     if (STAGED && st_mem == ST_STAGE) {
       mw[lane] = g0; mn[lane] = h0;
       mw[64 + lane] = g1; mn[64 + lane] = h1;
@@ -571,7 +575,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
     if (st_mem == ST_REC) {
       read_id = qrec.read_id; qbeg = qrec.qbeg; qend = qrec.qend; l = qrec.l; c = qrec.c;
       rlen = qrec.rlen; wo = ((uint64_t)qrec.woff_hi << 32) | qrec.woff_lo;
-      segend = qrec.send; segchk = (qrec.flags & SEG_CHECK) != 0;
+      segend = qrec.send; segchk = SEG && (qrec.flags & SEG_CHECK) != 0;
       nw = (rlen + 31) >> 5;
       // Algorithm 3 queues a string only if l - 1 < |P|
       const bool work = read_id != INVALID_READ && l >= 1 && l - 1 < qend - qbeg && (!STAGED || nw <= STAGE_WORDS);
@@ -1146,17 +1150,19 @@ static int persistent_grid(const void *kern, int block, size_t lds, int n_cu, in
   return per * n_cu;
 }
 
+template <bool STAGED, bool UNIQ>
+static void launch_wave(mbw_ctx *c, const IndexView &v, SeedParams &P, const ReadWords &R, const mbw_seed_opts &o,
+                        hipStream_t st) {
+  const int grid = persistent_grid((const void *)k_smem_wave<STAGED, UNIQ>, 64 * SMEM_WAVES, 0, c->n_cu, o.blocks_per_cu);
+  k_smem_wave<STAGED, UNIQ><<<grid, 64 * SMEM_WAVES, 0, st>>>(v, P, R);
+}
+
 static int launch_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const ReadWords &R, const mbw_seed_opts &o, bool staged,
                        hipStream_t st) {
-  if (o.kernel == MBW_KERNEL_PLAIN) {
-    k_smem_plain<<<grid_for(P.n_queries, 256), 256, 0, st>>>(v, P);
-  } else if (staged) {
-    const int grid = persistent_grid((const void *)k_smem_wave<true>, 64 * SMEM_WAVES, 0, c->n_cu, o.blocks_per_cu);
-    k_smem_wave<true><<<grid, 64 * SMEM_WAVES, 0, st>>>(v, P, R);
-  } else {
-    const int grid = persistent_grid((const void *)k_smem_wave<false>, 64 * SMEM_WAVES, 0, c->n_cu, o.blocks_per_cu);
-    k_smem_wave<false><<<grid, 64 * SMEM_WAVES, 0, st>>>(v, P, R);
-  }
+  const bool uniq = P.uniq && P.round == 1;
+  if (o.kernel == MBW_KERNEL_PLAIN) k_smem_plain<<<grid_for(P.n_queries, 256), 256, 0, st>>>(v, P);
+  else if (staged) { if (uniq) launch_wave<true, true>(c, v, P, R, o, st); else launch_wave<true, false>(c, v, P, R, o, st); }
+  else { if (uniq) launch_wave<false, true>(c, v, P, R, o, st); else launch_wave<false, false>(c, v, P, R, o, st); }
   TRY(hipGetLastError());
   return 0;
 }
