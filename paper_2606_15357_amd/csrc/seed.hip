@@ -40,7 +40,7 @@ namespace {
 // such a start, except that one starting at qbeg > q0 is an SMEM of the whole query only if it
 // cannot be extended to the left (SEG_CHECK: one backward step decides).
 #define SEG_CHECK 1u
-struct Query { uint32_t read_id, qbeg, qend, l, c, rlen, woff_lo, woff_hi, send, flags; };
+struct Query { uint32_t read_id, qbeg, qend, l, c, rlen, woff_lo, woff_hi, send, flags, pad0, pad1; };   // 48 bytes
 #define INVALID_READ 0xFFFFFFFFu   // unused slot of a per-wave output chunk
 struct SeedRec { uint32_t read_id, qbeg, qend, flags; uint64_t k, kr, s; };
 
@@ -311,24 +311,34 @@ enum { ST_IDLE = 0, ST_REC = 1, ST_STAGE = 2, ST_ACTIVE = 3, ST_DRAINED = 4 };
 // STAGED: reads staged in LDS (the short-read bin; never segmented).  UNIQ: the unique-match path
 // is compiled in (round 1; in round 2 every interval has s >= c' >= 2).  Segment handling is
 // compiled into the unstaged kernel only.
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Records that arrive in the memory phase (query records, k-mer entries, staged read words) are
+// loaded straight into LDS (global_load_lds: lane L's bytes land at base + size * L), so they
+// occupy no registers while the wave waits.
 template <bool STAGED, bool UNIQ>
 __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, SeedParams P, ReadWords R) {
   constexpr bool SEG = !STAGED;
-  __shared__ uint64_t sw[SMEM_WAVES][STAGED ? STAGE_WORDS * 64 : 1];   // staged bases, word w of lane L at [64 w + L]
+  __shared__ uint32_t swl[SMEM_WAVES][STAGED ? STAGE_WORDS * 64 : 1];  // staged bases: low / high halves of
+  __shared__ uint32_t swh[SMEM_WAVES][STAGED ? STAGE_WORDS * 64 : 1];  // word w of lane L at [64 w + L]
   __shared__ uint32_t sn[SMEM_WAVES][STAGED ? STAGE_WORDS * 64 : 1];   // staged N bits
+  __shared__ uint4 sq[SMEM_WAVES][3][64];                              // query records (48 bytes)
+  __shared__ uint4 sk[SMEM_WAVES][64];                                 // k-mer table entries
   __shared__ uint64_t sbt[MBW_MAX_SB * 8];
   __shared__ uint64_t scb[4];
   for (int t = threadIdx.x; t < 8 * ix.n_sb; t += blockDim.x) sbt[t] = ix.sbtab[t];
   if (threadIdx.x < 4) scb[threadIdx.x] = ix.Cb[threadIdx.x];
   __syncthreads();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  uint64_t *mw = sw[wv];
+  uint32_t *mwl = swl[wv], *mwh = swh[wv];
   uint32_t *mn = sn[wv];
   const int K = (P.use_kmer && ix.kmer) ? ix.K : 0;
   int st = ST_IDLE;
   uint64_t qi = 0, wo = 0;
   uint32_t nw = 0, rlen = 0;
-  auto word_at = [&](int w) -> uint64_t { return STAGED ? mw[64 * w + lane] : R.pw[wo + w]; };
+  auto word_at = [&](int w) -> uint64_t {
+    return STAGED ? (((uint64_t)mwh[64 * w + lane] << 32) | mwl[64 * w + lane]) : R.pw[wo + w];
+  };
   auto nbits_at = [&](int w) -> uint32_t { return STAGED ? mn[64 * w + lane] : R.pn[wo + w]; };
   auto base_at = [&](int p) -> int {
     const int w = p >> 5, b = p & 31;
@@ -458,27 +468,29 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
     uint64_t mval = 0;
     if (UNIQ && act == ACT_SSA) mval = ix.ssa[wrow >> P.rshift];
     if (UNIQ && act == ACT_ISA) mval = ix.isa[wrow];
-    uint4 kent = make_uint4(0, 0, 0, 0);
-    if (act == ACT_KMER) kent = ix.kmer[code];
+    if (act == ACT_KMER) __builtin_amdgcn_global_load_lds((const void *)(ix.kmer + code), (lds_void *)sk[wv], 16, 0, 0);
     const int st_mem = st;
-    Query qrec;
-    qrec.read_id = INVALID_READ; qrec.qbeg = qrec.qend = qrec.l = qrec.rlen = qrec.woff_lo = qrec.woff_hi = 0; qrec.c = 1;
-    qrec.send = qrec.flags = 0;
-    if (st_mem == ST_REC) qrec = P.queries[qi];
-    uint64_t g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0;
-    uint32_t h0 = 0, h1 = 0, h2 = 0, h3 = 0, h4 = 0;
+    if (st_mem == ST_REC) {
+      const uint4 *qp = (const uint4 *)(P.queries + qi);
+      __builtin_amdgcn_global_load_lds((const void *)qp, (lds_void *)sq[wv][0], 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void *)(qp + 1), (lds_void *)sq[wv][1], 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void *)(qp + 2), (lds_void *)sq[wv][2], 16, 0, 0);
+    }
     if (STAGED && st_mem == ST_STAGE) {
-      g0 = R.pw[wo]; h0 = R.pn[wo];
-      if (nw > 1) { g1 = R.pw[wo + 1]; h1 = R.pn[wo + 1]; }
-      if (nw > 2) { g2 = R.pw[wo + 2]; h2 = R.pn[wo + 2]; }
-      if (nw > 3) { g3 = R.pw[wo + 3]; h3 = R.pn[wo + 3]; }
-      if (nw > 4) { g4 = R.pw[wo + 4]; h4 = R.pn[wo + 4]; }
+#pragma unroll
+      for (int w = 0; w < STAGE_WORDS; ++w)
+        if ((uint32_t)w < nw) {
+          const uint32_t *wp = (const uint32_t *)(R.pw + wo + w);
+          __builtin_amdgcn_global_load_lds((const void *)wp, (lds_void *)(mwl + 64 * w), 4, 0, 0);
+          __builtin_amdgcn_global_load_lds((const void *)(wp + 1), (lds_void *)(mwh + 64 * w), 4, 0, 0);
+          __builtin_amdgcn_global_load_lds((const void *)(R.pn + wo + w), (lds_void *)(mn + 64 * w), 4, 0, 0);
+        }
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     // ---- compute
     if (act == ACT_KMER) {
       uint64_t ek, ekr, es;
-      kmer_unpack(kent, ek, ekr, es);
+      kmer_unpack(sk[wv][lane], ek, ekr, es);
       ++n_kmer;
       if (es >= c) { k = ek; kr = ekr; s = es; j -= K; }
     }
@@ -565,17 +577,11 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
       }
     }
     if (UNIQ && act == ACT_ISA) { wrow = mval; u = 7; ++n_lines; }
-    if (STAGED && st_mem == ST_STAGE) {
-      mw[lane] = g0; mn[lane] = h0;
-      mw[64 + lane] = g1; mn[64 + lane] = h1;
-      mw[128 + lane] = g2; mn[128 + lane] = h2;
-      mw[192 + lane] = g3; mn[192 + lane] = h3;
-      mw[256 + lane] = g4; mn[256 + lane] = h4;
-    }
     if (st_mem == ST_REC) {
-      read_id = qrec.read_id; qbeg = qrec.qbeg; qend = qrec.qend; l = qrec.l; c = qrec.c;
-      rlen = qrec.rlen; wo = ((uint64_t)qrec.woff_hi << 32) | qrec.woff_lo;
-      segend = qrec.send; segchk = SEG && (qrec.flags & SEG_CHECK) != 0;
+      const uint4 q0 = sq[wv][0][lane], q1 = sq[wv][1][lane], q2 = sq[wv][2][lane];
+      read_id = q0.x; qbeg = q0.y; qend = q0.z; l = q0.w; c = q1.x;
+      rlen = q1.y; wo = ((uint64_t)q1.w << 32) | q1.z;
+      segend = q2.x; segchk = SEG && (q2.y & SEG_CHECK) != 0;
       nw = (rlen + 31) >> 5;
       // Algorithm 3 queues a string only if l - 1 < |P|
       const bool work = read_id != INVALID_READ && l >= 1 && l - 1 < qend - qbeg && (!STAGED || nw <= STAGE_WORDS);
