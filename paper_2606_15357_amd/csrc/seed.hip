@@ -317,7 +317,7 @@ typedef __attribute__((address_space(3))) void lds_void;
 // loaded straight into LDS (global_load_lds: lane L's bytes land at base + size * L), so they
 // occupy no registers while the wave waits.
 template <bool STAGED, bool UNIQ>
-__global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, SeedParams P, ReadWords R) {
+__global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_per_eu(4))) k_smem_wave(IndexView ix, SeedParams P, ReadWords R) {
   constexpr bool SEG = !STAGED;
   __shared__ uint32_t swl[SMEM_WAVES][STAGED ? STAGE_WORDS * 64 : 1];  // staged bases: low / high halves of
   __shared__ uint32_t swh[SMEM_WAVES][STAGED ? STAGE_WORDS * 64 : 1];  // word w of lane L at [64 w + L]
@@ -334,8 +334,17 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
   uint32_t *mn = sn[wv];
   const int K = (P.use_kmer && ix.kmer) ? ix.K : 0;
   int st = ST_IDLE;
-  uint64_t qi = 0, wo = 0;
-  uint32_t nw = 0, rlen = 0;
+  uint32_t qi = 0;                // queue index of the query being loaded (queues hold < 2^32 queries)
+  uint64_t wo = 0;                // unstaged: first packed word of the read (the staged kernel reads it from LDS)
+  uint32_t nw = 0;
+  // cold fields of the current query, read from its record in LDS (written once per query)
+  auto q_read_id = [&]() -> uint32_t { return sq[wv][0][lane].x; };
+  auto q_rlen = [&]() -> uint32_t { return sq[wv][1][lane].y; };
+  auto q_wo = [&]() -> uint64_t {
+    if (!STAGED) return wo;
+    const uint4 q1 = sq[wv][1][lane];
+    return ((uint64_t)q1.w << 32) | q1.z;
+  };
   auto word_at = [&](int w) -> uint64_t {
     return STAGED ? (((uint64_t)mwh[64 * w + lane] << 32) | mwl[64 * w + lane]) : R.pw[wo + w];
   };
@@ -345,14 +354,18 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
     return ((nbits_at(w) >> b) & 1) ? 4 : (int)((word_at(w) >> (2 * b)) & 3);
   };
   const uint64_t tm = ix.n - 1;   // text length without $
-  uint32_t read_id = 0, qbeg = 0, qend = 0, l = 0, c = 1, segend = 0;
+  uint32_t qbeg = 0, qend = 0, l = 0, c = 1, segend = 0;
   bool segchk = false;            // the SMEM starting at qbeg still needs its left check (stage 8)
   int u = 0, i = 0, j = 0;
-  uint64_t k = 0, kr = 0, s = 0, budget = 0;
-  uint64_t wrow = 0, tp = 0;      // unique path: walk row (or sample index); text position of P[i]
+  uint64_t k = 0, kr = 0, s = 0;
+  uint32_t budget = 0;            // iteration guard of the current query (a corrupt index cannot loop forever)
+  uint64_t wrow = 0;              // unique path: walk row (or sample index)
+  __shared__ uint64_t stp[SMEM_WAVES][64];   // unique path: text position of P[i] (rarely read: kept in LDS)
+  uint64_t *tpl = &stp[wv][lane];
   uint32_t wcnt = 0;              // unique path: LF steps taken (stage 4) or still to take (stage 7)
   bool fresh = false;
-  uint64_t n_lines = 0, n_steps = 0, n_kmer = 0, n_iter = 0, n_busy = 0;
+  uint32_t n_lines = 0, n_steps = 0, n_kmer = 0;   // per lane (well below 2^32 per launch)
+  uint64_t n_iter = 0, n_busy = 0;                 // per wave
   uint32_t chain = 0, max_chain = 0;   // iterations of the current query; longest so far
   uint64_t cb = 0, ce = 0;
   WaveOut wout = {0, 0, 0, 0};
@@ -361,11 +374,11 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
     const bool want = st == ST_IDLE;
     if (__ballot(want)) {
       const uint64_t t = wave_take(want, cb, ce, &P.ctl[C_WORK], P.n_queries, lane, P.chunk);
-      if (want) { if (t == ~0ull) st = ST_DRAINED; else { qi = t; st = ST_REC; } }
+      if (want) { if (t == ~0ull) st = ST_DRAINED; else { qi = (uint32_t)t; st = ST_REC; } }
     }
     if (__ballot(st != ST_DRAINED) == 0) break;
     ++n_iter;
-    n_busy += st != ST_DRAINED && st != ST_IDLE;
+    n_busy += __popcll(__ballot(st != ST_DRAINED && st != ST_IDLE));
     if (st == ST_REC) chain = 0;
     if (st != ST_DRAINED && st != ST_IDLE) { ++chain; max_chain = chain > max_chain ? chain : max_chain; }
     // ---- active lanes: stage transitions up to the next memory action
@@ -459,7 +472,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
     if (two) { h0b = l2p[0]; h1b = l2p[1]; }
     if (blk2) bb = l2p[2 + (o2 >> 6)];
     // unique path: a sampled SA / inverse-SA value, or 32 bytes of text around position tq
-    const uint64_t tq = tp + (uint64_t)(j - i);
+    const uint64_t tq = (UNIQ && act == ACT_TEXT ? *tpl : 0ull) + (uint64_t)(j - i);
     const bool txt = UNIQ && act == ACT_TEXT && tq < tm;
     if (txt) {
       const uint4 *tw = (const uint4 *)(ix.text + ((tq >> 5) & ~1ull));
@@ -480,10 +493,10 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
 #pragma unroll
       for (int w = 0; w < STAGE_WORDS; ++w)
         if ((uint32_t)w < nw) {
-          const uint32_t *wp = (const uint32_t *)(R.pw + wo + w);
+          const uint32_t *wp = (const uint32_t *)(R.pw + q_wo() + w);
           __builtin_amdgcn_global_load_lds((const void *)wp, (lds_void *)(mwl + 64 * w), 4, 0, 0);
           __builtin_amdgcn_global_load_lds((const void *)(wp + 1), (lds_void *)(mwh + 64 * w), 4, 0, 0);
-          __builtin_amdgcn_global_load_lds((const void *)(R.pn + wo + w), (lds_void *)(mn + 64 * w), 4, 0, 0);
+          __builtin_amdgcn_global_load_lds((const void *)(R.pn + q_wo() + w), (lds_void *)(mn + 64 * w), 4, 0, 0);
         }
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -534,7 +547,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
     if (UNIQ && act == ACT_SSA) {                       // the occurrence: p = S(row) + steps (mod n)
       uint64_t pp = mval + wcnt;
       if (pp >= ix.n) pp -= ix.n;
-      tp = pp;
+      *tpl = pp;
       u = 5;
       ++n_lines;
     }
@@ -550,7 +563,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
         const uint64_t t0 = sh ? (lo >> sh) | (mid << (64 - sh)) : lo;
         const uint64_t t1 = sh ? (mid >> sh) | (hi << (64 - sh)) : mid;
         const int w0 = j >> 5, rb = j & 31;
-        const uint32_t nw_q = (rlen + 31) >> 5;
+        const uint32_t nw_q = (q_rlen() + 31) >> 5;
         const uint64_t a0 = word_at(w0), a1 = (uint32_t)(w0 + 1) < nw_q ? word_at(w0 + 1) : 0ull,
                        a2 = (uint32_t)(w0 + 2) < nw_q ? word_at(w0 + 2) : 0ull;
         const uint32_t n0 = nbits_at(w0), n1 = (uint32_t)(w0 + 1) < nw_q ? nbits_at(w0 + 1) : 0u,
@@ -570,7 +583,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
       if (first == 64 && j < (int)qend) {
         // the whole window matched: continue with the next one
       } else {                                          // end of the match: k' from the mirror position
-        const uint64_t pm = tm - tp - (uint64_t)(j - i);
+        const uint64_t pm = tm - *tpl - (uint64_t)(j - i);
         const uint64_t q = ((pm >> P.rishift) + ((pm & ((1ull << P.rishift) - 1)) ? 1 : 0)) << P.rishift;
         if (q >= tm) { wrow = 0; wcnt = (uint32_t)(tm - pm); u = 7; }   // row 0 holds the suffix at tm ($)
         else { wrow = q >> P.rishift; wcnt = (uint32_t)(q - pm); u = 6; }
@@ -579,8 +592,9 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
     if (UNIQ && act == ACT_ISA) { wrow = mval; u = 7; ++n_lines; }
     if (st_mem == ST_REC) {
       const uint4 q0 = sq[wv][0][lane], q1 = sq[wv][1][lane], q2 = sq[wv][2][lane];
-      read_id = q0.x; qbeg = q0.y; qend = q0.z; l = q0.w; c = q1.x;
-      rlen = q1.y; wo = ((uint64_t)q1.w << 32) | q1.z;
+      const uint32_t read_id = q0.x, rlen = q1.y;
+      qbeg = q0.y; qend = q0.z; l = q0.w; c = q1.x;
+      if (!STAGED) wo = ((uint64_t)q1.w << 32) | q1.z;
       segend = q2.x; segchk = SEG && (q2.y & SEG_CHECK) != 0;
       nw = (rlen + 31) >> 5;
       // Algorithm 3 queues a string only if l - 1 < |P|
@@ -590,19 +604,22 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) k_smem_wave(IndexView ix, See
     if ((STAGED && st_mem == ST_STAGE) || (!STAGED && st_mem == ST_REC && st == ST_ACTIVE)) {
       u = 1; i = (int)qbeg; j = (int)(qbeg + l - 1);
       k = 0; kr = 0; s = ix.n; fresh = true;
-      budget = 8ull * (qend - qbeg) * (qend - qbeg) + 64;
+      {
+        const uint64_t b = 8ull * (qend - qbeg) * (qend - qbeg) + 64;
+        budget = b > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)b;
+      }
       st = ST_ACTIVE;
     }
-    wave_emit(P, lane, em, read_id, e, wout, rlen, wo);
+    wave_emit(P, lane, em, q_read_id(), e, wout, q_rlen(), q_wo());
   }
   wave_close(P, lane, wout);
   if (lane == 0) atomicAdd(&P.ctl[C_WITER], (unsigned long long)n_iter);
+  if (lane == 0) atomicAdd(&P.ctl[C_LITER], (unsigned long long)n_busy);
   for (int d = 32; d >= 1; d >>= 1) {
     const uint32_t o = (uint32_t)__shfl_xor((int)max_chain, d);
     max_chain = o > max_chain ? o : max_chain;
   }
   if (lane == 0) atomicMax(&P.ctl[C_MAXCHAIN], (unsigned long long)max_chain);
-  atomicAdd(&P.ctl[C_LITER], (unsigned long long)n_busy);
   atomicAdd(&P.ctl[C_LINES], (unsigned long long)(n_lines + n_kmer));
   atomicAdd(&P.ctl[C_STEPS], (unsigned long long)n_steps);
   atomicAdd(&P.ctl[C_KMER], (unsigned long long)n_kmer);
