@@ -303,8 +303,14 @@ def main():
     log(f"reference {len(ref)} bases generated in {time.time() - t0:.1f} s")
     t0 = time.time()
     idx = mbw.Index.build(ref.codes, sa_sample=args.sa_sample, kmer_k=args.kmer, isa_sample=args.isa_sample)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
     info = idx.info()
-    log(f"index built on the GPU in {time.time() - t0:.1f} s: n={info['n']} lines={info['n_lines']} "
+    index_build = dict(seconds=round(build_s, 2), text_bases_per_s=round(info["n"] / build_s),
+                       n=info["n"], resident_gb=round(info["bytes_resident"] / 1e9, 2),
+                       includes="upload of the reference codes, suffix sorting, occurrence lines, SA/ISA samples, "
+                                "k-mer table; first call in the process")
+    log(f"index built on the GPU in {build_s:.1f} s: n={info['n']} lines={info['n_lines']} "
         f"resident={info['bytes_resident'] / 1e9:.2f} GB")
     t0 = time.time()
     reads = synth.workload_reads(args.workload, ref, args.pairs or None)
@@ -402,7 +408,8 @@ def main():
                             min_seed_len=19, max_occ=500, sa_sample=args.sa_sample, kmer_k=args.kmer,
                             isa_sample=args.isa_sample, unique_ext=not args.no_unique,
                             bases_per_line=384, line_bytes=LINE_BYTES, index_gb=round(info["bytes_resident"] / 1e9, 2)),
-                schedule=sched, plain_gpu=plain, roofline=roofline, cpu_baseline=cpu, serve=serve)
+                schedule=sched, plain_gpu=plain, roofline=roofline, cpu_baseline=cpu, serve=serve,
+                index_build=index_build)
     print(json.dumps(line), flush=True)
 
 
