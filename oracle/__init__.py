@@ -13,6 +13,9 @@ Three oracles:
     sample of reads, and direct extension gives the SMEM set, s and the exact positions from the
     definitions (Section 2.2).  For references too large to sort on the host; ds-interval bounds
     are not produced (k = k' = 2^64 - 1).
+
+Also: ``bs_refine`` (Section 2.9 seed refinement at read-C-over-reference-T bases) and
+``rescue`` / ``rescue_diagonals`` (Section 2.7 mate-rescue prefilter, M_t counted pair by pair).
 """
 from __future__ import annotations
 
@@ -78,6 +81,9 @@ def _load():
     L.orc_scan_seed.argtypes = [vp, u64, i32, vp, vp, u64, C.POINTER(_Opts), i32]
     L.orc_bs_refine.restype = u64
     L.orc_bs_refine.argtypes = [vp, u64, vp, vp, vp, vp, vp, vp, vp, u64, vp, i32, i32, C.POINTER(vp)]
+    L.orc_rescue_diag_ascii.argtypes = [vp, u64, vp, u64, i32, i32, vp]
+    L.orc_rescue.restype = i32
+    L.orc_rescue.argtypes = [vp, u64, i32, vp, vp, u64, vp, vp, vp, u64, i32, i32, vp, vp, i32]
     L.orc_free_ptr.argtypes = [vp]
     _lib = L
     return L
@@ -268,3 +274,43 @@ def bs_refine(ref_codes: np.ndarray, seq: np.ndarray, offsets: np.ndarray, res: 
 def seed_reads(index: OracleIndex, reads, **kw) -> SeedResult:
     """Convenience: seed a ``synth.ReadSet``-like object (``seq``, ``offsets``)."""
     return index.seed(reads.seq, reads.offsets, **kw)
+
+
+def rescue_diagonals(read: bytes | str, window: bytes | str, q: int = 7, role: int = 0) -> np.ndarray:
+    """Mate-rescue prefilter (Section 2.7) for one read and one window given as ASCII: the vector
+    M_t = #{(i, j): P[i, i+q) = W[j, j+q), j - i = t}, element t + |P| - q, counted from the
+    definition.  Empty when |P| < q or |W| < q."""
+    L = _load()
+    p = np.frombuffer(read.encode() if isinstance(read, str) else bytes(read), dtype=np.uint8).copy()
+    w = np.frombuffer(window.encode() if isinstance(window, str) else bytes(window), dtype=np.uint8).copy()
+    nd = p.size + w.size - 2 * q + 1 if p.size >= q and w.size >= q else 0
+    M = np.zeros(max(nd, 1), dtype=np.uint32)
+    pp = p if p.size else np.zeros(1, np.uint8)
+    ww = w if w.size else np.zeros(1, np.uint8)
+    L.orc_rescue_diag_ascii(_p(pp), p.size, _p(ww), w.size, int(q), int(role), _p(M))
+    return M[:nd]
+
+
+def rescue(ref_codes: np.ndarray, seq: np.ndarray, offsets: np.ndarray, read_id, win_beg, win_len, q: int = 7,
+           role: int = 0, bisulfite: bool = False, threads: int = 0):
+    """Mate-rescue prefilter (Section 2.7) for candidates (read read_id[c], window
+    T[win_beg[c], win_beg[c] + win_len[c]) of the text of ``ref_codes``): returns (max_hits u32,
+    best_t i32), best_t the smallest t with M_t = max_hits (0 when that is 0)."""
+    L = _load()
+    ref = np.ascontiguousarray(ref_codes, dtype=np.uint8)
+    seq = np.ascontiguousarray(seq, dtype=np.uint8)
+    if seq.size == 0:
+        seq = np.zeros(1, np.uint8)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    rid = np.ascontiguousarray(read_id, dtype=np.uint32)
+    beg = np.ascontiguousarray(win_beg, dtype=np.uint64)
+    wl = np.ascontiguousarray(win_len, dtype=np.uint32)
+    n = rid.size
+    mh = np.zeros(max(n, 1), np.uint32)
+    bt = np.zeros(max(n, 1), np.int32)
+    pad = [a if a.size else np.zeros(1, a.dtype) for a in (rid, beg, wl)]
+    rc = L.orc_rescue(_p(ref), ref.size, int(bisulfite), _p(seq), _p(offsets), offsets.size - 1, _p(pad[0]),
+                      _p(pad[1]), _p(pad[2]), n, int(q), int(role), _p(mh), _p(bt), int(threads))
+    if rc != 0:
+        raise ValueError("rescue candidate out of range")
+    return mh[:n], bt[:n]

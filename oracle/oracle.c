@@ -21,6 +21,7 @@
  *   Algorithm 3 (BatchFindSMEM stages 1-3 with BackStep), one query at a time -> alg3_smems()
  *   Section 2.6 (two seeding rounds: re-seed long, rare SMEMs)             -> seed_query()
  *   Section 2.9 (bisulfite: 3-base index of C->T(R) . G->A(R), read conversion, strand filter)
+ *   Section 2.7 (mate-rescue prefilter: q-mer matches per diagonal, M_t)  -> rescue_diag()
  *
  * Two oracles live here:
  *   O1 ("definition"): full suffix array by comparison sort; intervals by binary search over the
@@ -838,4 +839,79 @@ uint64_t orc_bs_refine(const uint8_t *R, uint64_t L, const uint8_t *reads, const
   *out = v;
   return n;
 }
+/* ---------------------------------------------------------------------------------------------
+ * Mate-rescue prefilter (Section 2.7), straight from its definition.  For a read P and a window W
+ * of the text,
+ *     M_t = |{(i, j) : P[i, i+q) = W[j, j+q) and j - i = t}|,   0 <= i <= |P|-q, 0 <= j <= |W|-q,
+ * counted pair by pair.  A read base outside ACGT (code 5) equals no text symbol, so a q-mer that
+ * holds one matches nothing.  M is stored at index t + |P| - q (|P| + |W| - 2q + 1 entries).
+ * Reported per candidate: max_t M_t and the smallest t attaining it (0 when the maximum is 0,
+ * which includes |P| < q and |W| < q).
+ */
+static void rescue_diag(const uint8_t *P, uint64_t np, const uint8_t *W, uint64_t nw, int q, uint32_t *M) {
+  if (np < (uint64_t)q || nw < (uint64_t)q) return;
+  for (uint64_t i = 0; i + q <= np; ++i)
+    for (uint64_t j = 0; j + q <= nw; ++j) {
+      int eq = 1;
+      for (int d = 0; d < q && eq; ++d) eq = P[i + d] >= 1 && P[i + d] <= 4 && P[i + d] == W[j + d];
+      if (eq) M[j - i + np - q] += 1;
+    }
+}
+
+static void rescue_best(const uint32_t *M, uint64_t np, uint64_t nw, int q, uint32_t *max_hits, int32_t *best_t) {
+  *max_hits = 0; *best_t = 0;
+  if (np < (uint64_t)q || nw < (uint64_t)q) return;
+  uint64_t nd = np + nw - 2 * (uint64_t)q + 1;
+  for (uint64_t x = 0; x < nd; ++x)
+    if (M[x] > *max_hits) { *max_hits = M[x]; *best_t = (int32_t)((int64_t)x - (int64_t)(np - q)); }
+}
+
+static uint8_t rescue_read_sym(uint8_t ch, int role) {
+  uint8_t a = enc_ascii(ch);
+  if (role == 1 && a == 2) a = 4;   /* read 1: C -> T (Section 2.9) */
+  if (role == 2 && a == 3) a = 1;   /* read 2: G -> A */
+  return a;
+}
+
+/* The whole vector M for one ASCII read and one ASCII window (pins and tests). */
+void orc_rescue_diag_ascii(const uint8_t *p, uint64_t np, const uint8_t *w, uint64_t nw, int q, int role, uint32_t *M) {
+  uint8_t *P = (uint8_t *)malloc(np + 1), *W = (uint8_t *)malloc(nw + 1);
+  for (uint64_t t = 0; t < np; ++t) P[t] = rescue_read_sym(p[t], role);
+  for (uint64_t t = 0; t < nw; ++t) { W[t] = enc_ascii(w[t]); if (W[t] > 4) W[t] = 6; }  /* window N: matches nothing */
+  if (np >= (uint64_t)q && nw >= (uint64_t)q) memset(M, 0, (np + nw - 2 * (uint64_t)q + 1) * sizeof(uint32_t));
+  rescue_diag(P, np, W, nw, q, M);
+  free(P); free(W);
+}
+
+/* Candidates (read_id[c], window T[win_beg[c], win_beg[c] + win_len[c])) over the text of R
+ * (plain, or the four-copy bisulfite text).  Returns 0, or -1 for a read id or window out of range. */
+int orc_rescue(const uint8_t *R, uint64_t len_r, int bisulfite, const uint8_t *reads, const uint64_t *offsets,
+               uint64_t n_reads, const uint32_t *read_id, const uint64_t *win_beg, const uint32_t *win_len,
+               uint64_t n_cand, int q, int role, uint32_t *max_hits, int32_t *best_t, int n_threads) {
+  if (q < 1) return -1;
+  uint64_t n = 0;
+  uint8_t *T = build_text(R, len_r, bisulfite, &n);
+  for (uint64_t c = 0; c < n_cand; ++c)
+    if (read_id[c] >= n_reads || win_beg[c] > n - 1 || win_len[c] > n - 1 - win_beg[c]) { free(T); return -1; }
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+  #pragma omp parallel
+  {
+    uint8_t *P = NULL; uint32_t *M = NULL; uint64_t pcap = 0, mcap = 0;
+    #pragma omp for schedule(dynamic, 16)
+    for (int64_t c = 0; c < (int64_t)n_cand; ++c) {
+      uint64_t b = offsets[read_id[c]], np = offsets[read_id[c] + 1] - b, nw = win_len[c];
+      if (pcap < np + 1) { free(P); pcap = np + 1; P = (uint8_t *)malloc(pcap); }
+      for (uint64_t t = 0; t < np; ++t) P[t] = rescue_read_sym(reads[b + t], role);
+      uint64_t nd = np + nw + 1;
+      if (mcap < nd) { free(M); mcap = nd; M = (uint32_t *)malloc(mcap * sizeof(uint32_t)); }
+      memset(M, 0, nd * sizeof(uint32_t));
+      rescue_diag(P, np, T + win_beg[c], nw, q, M);
+      rescue_best(M, np, nw, q, &max_hits[c], &best_t[c]);
+    }
+    free(P); free(M);
+  }
+  free(T);
+  return 0;
+}
+
 void orc_free_ptr(void *p) { free(p); }

@@ -223,6 +223,45 @@ def concat(a: ReadSet, b: ReadSet) -> ReadSet:
 # ------------------------------------------------------------------------------------------
 # the five workloads (reference recipe, size and seed; read model)
 
+RESCUE_CAND_DTYPE = np.dtype([("read_id", "<u4"), ("win_len", "<u4"), ("win_beg", "<u8")])
+
+
+def rescue_candidates(reads: ReadSet, ref_len: int, decoys: bool = True, seed: int = 0, ins_mean: float = 400.0,
+                      ins_sd: float = 50.0, rlen: int = 150):
+    """Mate-rescue candidates for a paired read set from ``reads_fixed(..., paired=True)``: for
+    every pair, the mate whose text position is known from the simulation (read 1 of a forward
+    fragment at ``tpos``, read 2 of a reverse one at ``tpos + 32``) stands for the mapped read,
+    and the other mate is looked for in the window where a proper pair puts it: with T = R .
+    revcomp(R) and an insert of il bases, a mate of the read at text position p starts at
+    2|R| - p - il, so the window is [2|R| - p - ins_mean - 4 ins_sd, + 8 ins_sd + rlen) clipped to
+    [0, 2|R|).  With ``decoys`` every true candidate is followed by one for the same read at a
+    uniformly random window of the same length.  Returns (candidates, decoy flags)."""
+    n_pairs = len(reads) // 2
+    two_l = 2 * int(ref_len)
+    rev = reads.tstrand[0::2][:n_pairs].astype(np.int64)
+    st = reads.tpos[0::2][:n_pairs].astype(np.int64)
+    p = np.where(rev == 0, st, st + 32)
+    mate = np.where(rev == 0, 2 * np.arange(n_pairs) + 1, 2 * np.arange(n_pairs))
+    b = two_l - p - int(round(ins_mean + 4 * ins_sd))
+    e = b + int(round(8 * ins_sd)) + int(rlen)
+    b = np.clip(b, 0, two_l)
+    e = np.clip(e, 0, two_l)
+    k = 2 if decoys else 1
+    out = np.zeros(n_pairs * k, dtype=RESCUE_CAND_DTYPE)
+    flag = np.zeros(n_pairs * k, dtype=np.uint8)
+    out["read_id"][0::k] = mate
+    out["win_beg"][0::k] = b
+    out["win_len"][0::k] = e - b
+    if decoys:
+        rng = np.random.default_rng(seed)
+        wl = e - b
+        out["read_id"][1::2] = mate
+        out["win_len"][1::2] = wl
+        out["win_beg"][1::2] = (rng.random(n_pairs) * (two_l - wl + 1)).astype(np.int64)
+        flag[1::2] = 1
+    return out, flag
+
+
 WORKLOADS = {
     "small_1mbp": dict(desc="1 Mbp random + 20x2 kbp repeat @5%; 10,000 x 150 bp single-end, 0.5% sub, "
                             "0.05% indel; min seed 19, max_occ 500", recipe=0, ref_len=1_000_000, seed=0),
