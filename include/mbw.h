@@ -211,6 +211,63 @@ int mbw_tune(mbw_ctx *ctx, const uint8_t *reads, const uint32_t *lengths, uint64
  * the four copies of length |R| map to their source coordinates likewise.) */
 int mbw_pos_to_ref(const mbw_index *idx, uint64_t pos, uint32_t len, int *strand, uint64_t *ref_pos);
 
+/* ---- mate-rescue prefilter (Section 2.7) -----------------------------------------------------
+ * For a read P and a reference window W, M_t is the number of pairs (i, j) with
+ * P[i, i+q) = W[j, j+q) and j - i = t; max_t M_t approximates the best ungapped alignment of P in
+ * W, and a candidate goes on to Smith-Waterman only when max_t M_t >= min_hits.  A q-mer of P that
+ * holds a base other than A/C/G/T matches nothing. */
+
+/* One candidate: read `read_id` of the batch against the window T[win_beg, win_beg + win_len) of
+ * the index text (T coordinates as for positions; the window may not reach the sentinel:
+ * win_beg + win_len <= n - 1). */
+typedef struct {
+  uint32_t read_id;
+  uint32_t win_len;
+  uint64_t win_beg;
+} mbw_rescue_cand_t;
+
+/* Per candidate: max_hits = max_t M_t; best_t = the smallest t (-(|P|-q) <= t <= |W|-q) with
+ * M_t = max_hits, or 0 when max_hits = 0 (also when |P| < q or |W| < q). */
+typedef struct {
+  uint32_t max_hits;
+  int32_t best_t;
+} mbw_rescue_hit_t;
+
+typedef struct {
+  int q;          /* q-mer length, 1..15 (7 in the paper) */
+  int min_hits;   /* pass threshold on max_t M_t (10 in the paper), >= 0 */
+  int bs_role;    /* bisulfite index only: 1 converts C->T in the read, 2 G->A (as for seeding) */
+} mbw_rescue_opts;
+
+typedef struct {
+  uint64_t n_cands;
+  uint64_t n_pass;
+  const mbw_rescue_hit_t *hits;   /* device pointer, n_cands records in candidate order */
+  const uint32_t *pass;           /* device pointer, n_pass candidate indices (ascending) with
+                                     max_hits >= min_hits */
+  float ms_kernel;                /* device time of the prefilter kernel (HIP events) */
+  float ms_total;                 /* device time of the whole call */
+} mbw_rescue_result;
+
+/* Run the prefilter over a batch of candidates.
+ *   reads, lengths, n_reads: as for mbw_seed (ASCII, host or device).  Reads are limited by the
+ *            device's LDS: 3|P|/2 rounded up to a power of two, plus |P| + |W|, 32-bit words
+ *            per wave must fit in 64 KiB (about |P| <= 2000 with |W| <= 8000).
+ *   cands:   n_cands candidates (host or device), n_cands < 2^31.
+ *   opts:    NULL = q 7, min_hits 10, no conversion.
+ * The index must hold the packed text (built with isa_sample > 0, the default).  Results stay in
+ * device memory owned by ctx until the next mbw_rescue_filter on it; a seeding result of the same
+ * ctx is left intact.  Blocking on `stream` (the pass count is needed on the host).
+ * Errors: MBW_E_INVAL (q, min_hits, bs_role, a read_id >= n_reads, a window outside the text, an
+ * index without text, sizes beyond the LDS limit), MBW_E_NOMEM, MBW_E_HIP. */
+int mbw_rescue_filter(mbw_ctx *ctx, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads,
+                      const mbw_rescue_cand_t *cands, uint64_t n_cands, const mbw_rescue_opts *opts, void *stream,
+                      mbw_rescue_result *out);
+
+/* Copy a prefilter result to host buffers (hits: n_cands records, pass: n_pass indices; either
+ * may be NULL). */
+int mbw_rescue_download(mbw_ctx *ctx, const mbw_rescue_result *res, mbw_rescue_hit_t *hits, uint32_t *pass);
+
 /* ---- diagnostics (not part of the seeding path) ----------------------------------------------
  * mbw_probe_copy: streams `bytes` bytes (>= 4096) from one buffer to another once; *ms = kernel time.
  *   Used to calibrate profiler byte counters against a known transfer.

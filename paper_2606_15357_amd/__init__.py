@@ -37,7 +37,7 @@ EXPORTS = ["mbw_strerror", "mbw_last_error", "mbw_index_build", "mbw_index_save"
            "mbw_index_free", "mbw_index_info", "mbw_index_device_arrays", "mbw_ctx_create", "mbw_ctx_free",
            "mbw_seed", "mbw_result_download", "mbw_pos_to_ref", "mbw_probe_copy", "mbw_probe_gather", "mbw_tune",
            "mbw_result_download_pieces", "mbw_serve_open", "mbw_serve_submit", "mbw_serve_wait", "mbw_serve_release", "mbw_serve_stats",
-           "mbw_serve_close"]
+           "mbw_serve_close", "mbw_rescue_filter", "mbw_rescue_download"]
 
 
 class MbwError(RuntimeError):
@@ -76,6 +76,15 @@ class ServeResult(C.Structure):
                 ("batch_id", C.c_uint64), ("batch_reads", C.c_uint64)]
 
 
+class RescueOpts(C.Structure):
+    _fields_ = [("q", C.c_int), ("min_hits", C.c_int), ("bs_role", C.c_int)]
+
+
+class RescueResult(C.Structure):
+    _fields_ = [("n_cands", C.c_uint64), ("n_pass", C.c_uint64), ("hits", C.c_void_p), ("pass_", C.c_void_p),
+                ("ms_kernel", C.c_float), ("ms_total", C.c_float)]
+
+
 class Result(C.Structure):
     _fields_ = [("n_seeds", C.c_uint64), ("n_pos", C.c_uint64), ("seeds", C.c_void_p), ("pos", C.c_void_p),
                 ("lines_smem", C.c_uint64), ("lines_locate", C.c_uint64), ("steps", C.c_uint64),
@@ -88,6 +97,8 @@ SEED_DTYPE = np.dtype([("read_id", "<u4"), ("qbeg", "<u4"), ("qend", "<u4"), ("f
                        ("kr", "<u8"), ("s", "<u8"), ("pos_off", "<u8"), ("npos", "<u4"), ("reserved", "<u4")])
 assert SEED_DTYPE.itemsize == 56
 PIECE_DTYPE = np.dtype([("read_id", "<u4"), ("qbeg", "<u4"), ("qend", "<u4"), ("seed", "<u4"), ("pos", "<u8")])
+RESCUE_CAND_DTYPE = np.dtype([("read_id", "<u4"), ("win_len", "<u4"), ("win_beg", "<u8")])
+RESCUE_HIT_DTYPE = np.dtype([("max_hits", "<u4"), ("best_t", "<i4")])
 
 _lib = None
 
@@ -130,6 +141,8 @@ def load_library():
     L.mbw_serve_stats.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
     L.mbw_serve_close.argtypes = [vp]
     L.mbw_serve_close.restype = None
+    L.mbw_rescue_filter.argtypes = [vp, vp, vp, u64, vp, u64, C.POINTER(RescueOpts), vp, C.POINTER(RescueResult)]
+    L.mbw_rescue_download.argtypes = [vp, C.POINTER(RescueResult), vp, vp]
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
@@ -266,8 +279,29 @@ class SeedOutput:
         return seeds, pos
 
 
+@dataclass
+class RescueOutput:
+    n_cands: int
+    n_pass: int
+    hits_ptr: int
+    pass_ptr: int
+    ms_kernel: float
+    ms_total: float
+    _res: RescueResult
+    _ctx: "Context"
+
+    def download(self):
+        """(hits as RESCUE_HIT_DTYPE records, passing candidate indices as uint32) on the host."""
+        hits = np.zeros(self.n_cands, dtype=RESCUE_HIT_DTYPE)
+        passed = np.zeros(self.n_pass, dtype=np.uint32)
+        _check(self._ctx._lib.mbw_rescue_download(self._ctx._h, C.byref(self._res),
+                                                  hits.ctypes.data if self.n_cands else None,
+                                                  passed.ctypes.data if self.n_pass else None))
+        return hits, passed
+
+
 class Context:
-    """Work space for a stream of ``mbw_seed`` calls against one index."""
+    """Work space for a stream of ``mbw_seed`` / ``mbw_rescue_filter`` calls against one index."""
 
     def __init__(self, index: Index):
         self._lib = load_library()
@@ -298,6 +332,30 @@ class Context:
         return SeedOutput(res.n_seeds, res.n_pos, res.seeds or 0, res.pos or 0, res.lines_smem, res.lines_locate,
                           res.steps, res.lf_steps, res.ms_smem, res.ms_locate, res.ms_total, res.n_smem_launches,
                           res.wave_iters, res.lane_iters, res.max_chain, res, self)
+
+    def rescue(self, reads, lengths, cands, q: int = 7, min_hits: int = 10, bs_role: int = 0,
+               stream=None) -> RescueOutput:
+        """Mate-rescue prefilter (``mbw_rescue_filter``).  ``cands``: RESCUE_CAND_DTYPE records on
+        the host, or a torch uint8/int64 CUDA tensor holding them (16 bytes each)."""
+        n = int(lengths.numel() if hasattr(lengths, "numel") else len(lengths))
+        if isinstance(lengths, np.ndarray):
+            lengths = np.ascontiguousarray(lengths, dtype=np.uint32)
+        if isinstance(reads, np.ndarray):
+            reads = np.ascontiguousarray(reads, dtype=np.uint8)
+        if isinstance(cands, np.ndarray):
+            cands = np.ascontiguousarray(cands)
+            if cands.dtype != RESCUE_CAND_DTYPE:
+                raise TypeError("candidates must be RESCUE_CAND_DTYPE records")
+            nc = cands.size
+        else:
+            nc = cands.numel() * cands.element_size() // RESCUE_CAND_DTYPE.itemsize
+        o = RescueOpts(int(q), int(min_hits), int(bs_role))
+        res = RescueResult()
+        _check(self._lib.mbw_rescue_filter(self._h, _ptr(reads) if n else None, _ptr(lengths) if n else None, n,
+                                           _ptr(cands) if nc else None, nc, C.byref(o), _stream_handle(stream),
+                                           C.byref(res)))
+        return RescueOutput(res.n_cands, res.n_pass, res.hits or 0, res.pass_ or 0, res.ms_kernel, res.ms_total,
+                            res, self)
 
     def tune(self, reads, lengths, min_seed_len: int = 19, max_occ: int = 500, stream=None, **base) -> dict:
         """Time candidate schedules on this batch (``mbw_tune``); returns the fastest as keyword

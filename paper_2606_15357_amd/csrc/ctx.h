@@ -1,0 +1,73 @@
+// Host-side state of one mbw_ctx (shared by the seeding and mate-rescue entry points) and the
+// helpers that grow its device buffers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "mbw_internal.h"
+#include "../../include/mbw.h"
+
+#define MBW_CTL_WORDS 16   // u64 counters of the control block of one call
+
+struct mbw_ctx {
+  const mbw_index *ix;
+  int device;
+  int n_cu;
+  struct Buf { void *p = nullptr; size_t bytes = 0; };   // grow-only device buffers (stream-ordered allocations)
+  // seeding
+  Buf codes, ascii, lens, offs, raw, subq, keys0, keys1, vals0, vals1, flag, idx, seeds, npos, posoff, xrows, pos, pos2,
+      keep, kidx, temp, ctl, pwords, pnmask, woffs, nwords, wread, q1, q2, bf0, bf1, bp0, bp1, bid0, bid1, bk0, bk1, q1s,
+      q2s, sc0, sc1, pseed, pcnt, ppoff, pieces;
+  // mate-rescue prefilter (its own buffers, so that it leaves the last seeding result intact)
+  Buf rc_lens, rc_wide, rc_offs, rc_ascii, rc_cand, rc_ctl, rc_hits, rc_flags, rc_pass;
+  hipEvent_t ev[8];
+  hipStream_t cur = nullptr;   // stream of the current / last call
+  unsigned long long host_ctl[MBW_CTL_WORDS];
+  float ms_smem;
+  int n_smem_launches;
+
+  std::vector<Buf *> buffers() {
+    return {&codes, &ascii, &lens, &offs, &raw, &subq, &keys0, &keys1, &vals0, &vals1, &flag, &idx, &seeds, &npos,
+            &posoff, &xrows, &pos, &pos2, &keep, &kidx, &temp, &ctl, &pwords, &pnmask, &woffs, &nwords, &wread, &q1,
+            &q2, &bf0, &bf1, &bp0, &bp1, &bid0, &bid1, &bk0, &bk1, &q1s, &q2s, &sc0, &sc1, &pseed, &pcnt, &ppoff,
+            &pieces, &rc_lens, &rc_wide, &rc_offs, &rc_ascii, &rc_cand, &rc_ctl, &rc_hits, &rc_flags, &rc_pass};
+  }
+};
+
+// Buffers grow on the call's stream with the stream-ordered allocator, so that a context growing
+// its work space does not wait for work of other contexts on other streams.
+static inline int grow(mbw_ctx *c, mbw_ctx::Buf &b, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  if (b.bytes >= bytes) return 0;
+  if (b.p) { (void)hipFreeAsync(b.p, c->cur); b.p = nullptr; b.bytes = 0; }
+  size_t want = bytes + bytes / 2 + 256;
+  hipError_t e = hipMallocAsync(&b.p, want, c->cur);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    mbw_set_error(std::string("hipMalloc(") + std::to_string(want) + "): " + hipGetErrorString(e));
+    return MBW_E_NOMEM;
+  }
+  b.bytes = want;
+  return 0;
+}
+#define GROW(buf, bytes) do { int r_ = grow(c, buf, bytes); if (r_) return r_; } while (0)
+
+static inline bool is_device_ptr(const void *p) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) { (void)hipGetLastError(); return false; }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+// run a hipcub device-wide algorithm with the context's temporary buffer
+template <class F>
+static int cub_call(mbw_ctx *c, F f) {
+  size_t tb = 0;
+  MBW_HIP_TRY(f((void *)nullptr, tb));
+  GROW(c->temp, tb);
+  size_t have = c->temp.bytes;
+  MBW_HIP_TRY(f(c->temp.p, have));
+  return 0;
+}

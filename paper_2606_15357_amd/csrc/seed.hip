@@ -27,6 +27,7 @@
 #include <string>
 #include <vector>
 
+#include "ctx.h"
 #include "mbw_internal.h"
 #include "../../include/mbw.h"
 
@@ -1076,39 +1077,8 @@ __global__ void k_refine(const mbw_seed_t *__restrict__ seeds, const uint32_t *_
 }  // namespace
 
 // ---------------------------------------------------------------------------------------------
-// context
-struct mbw_ctx {
-  const mbw_index *ix;
-  int device;
-  int n_cu;
-  struct Buf { void *p = nullptr; size_t bytes = 0; };   // grow-only device buffers (stream-ordered allocations)
-  Buf codes, ascii, lens, offs, raw, subq, keys0, keys1, vals0, vals1, flag, idx, seeds, npos, posoff, xrows, pos, pos2,
-      keep, kidx, temp, ctl, pwords, pnmask, woffs, nwords, wread, q1, q2, bf0, bf1, bp0, bp1, bid0, bid1, bk0, bk1, q1s,
-      q2s, sc0, sc1, pseed, pcnt, ppoff, pieces;
-  hipEvent_t ev[8];
-  hipStream_t cur = nullptr;   // stream of the current / last mbw_seed call
-  unsigned long long host_ctl[C_COUNT];
-  float ms_smem;
-  int n_smem_launches;
-};
-
-// Buffers grow on the call's stream with the stream-ordered allocator, so that a context growing
-// its work space does not wait for work of other contexts on other streams.
-static int grow(mbw_ctx *c, mbw_ctx::Buf &b, size_t bytes) {
-  if (bytes == 0) bytes = 16;
-  if (b.bytes >= bytes) return 0;
-  if (b.p) { (void)hipFreeAsync(b.p, c->cur); b.p = nullptr; b.bytes = 0; }
-  size_t want = bytes + bytes / 2 + 256;
-  hipError_t e = hipMallocAsync(&b.p, want, c->cur);
-  if (e != hipSuccess) {
-    b.p = nullptr;
-    mbw_set_error(std::string("hipMalloc(") + std::to_string(want) + "): " + hipGetErrorString(e));
-    return MBW_E_NOMEM;
-  }
-  b.bytes = want;
-  return 0;
-}
-#define GROW(buf, bytes) do { int r_ = grow(c, buf, bytes); if (r_) return r_; } while (0)
+// context (struct mbw_ctx and its buffer helpers: ctx.h)
+static_assert(C_COUNT <= MBW_CTL_WORDS, "control block larger than the context's host copy");
 
 extern "C" int mbw_ctx_create(const mbw_index *ix, mbw_ctx **out) {
   if (!ix || !out) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
@@ -1139,31 +1109,10 @@ extern "C" int mbw_ctx_create(const mbw_index *ix, mbw_ctx **out) {
 extern "C" void mbw_ctx_free(mbw_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
-  mbw_ctx::Buf *bs[] = {&c->codes, &c->ascii, &c->lens, &c->offs, &c->raw, &c->subq, &c->keys0, &c->keys1, &c->vals0,
-                        &c->vals1, &c->flag, &c->idx, &c->seeds, &c->npos, &c->posoff, &c->xrows, &c->pos, &c->pos2,
-                        &c->keep, &c->kidx, &c->temp, &c->ctl, &c->pwords, &c->pnmask, &c->woffs, &c->nwords, &c->wread,
-                        &c->q1, &c->q2, &c->bf0, &c->bf1, &c->bp0, &c->bp1, &c->bid0, &c->bid1, &c->bk0, &c->bk1,
-                        &c->q1s, &c->q2s, &c->sc0, &c->sc1, &c->pseed, &c->pcnt, &c->ppoff, &c->pieces};
-  for (auto *b : bs) if (b->p) (void)hipFreeAsync(b->p, c->cur);
+  for (auto *b : c->buffers()) if (b->p) (void)hipFreeAsync(b->p, c->cur);
   (void)hipStreamSynchronize(c->cur);
   for (int t = 0; t < 8; ++t) (void)hipEventDestroy(c->ev[t]);
   delete c;
-}
-
-static bool is_device_ptr(const void *p) {
-  hipPointerAttribute_t a;
-  if (hipPointerGetAttributes(&a, p) != hipSuccess) { (void)hipGetLastError(); return false; }
-  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
-}
-
-template <class F>
-static int cub_call(mbw_ctx *c, F f) {
-  size_t tb = 0;
-  TRY(f((void *)nullptr, tb));
-  GROW(c->temp, tb);
-  size_t have = c->temp.bytes;
-  TRY(f(c->temp.p, have));
-  return 0;
 }
 
 static int persistent_grid(const void *kern, int block, size_t lds, int n_cu, int per_cu_req) {

@@ -10,7 +10,8 @@ position of the sampled reads must agree exactly:
 * 3.1 Gbp mixed genome, 10,000,000 read pairs: oracle O3 (one scan of T per q-mer set, no index)
   on 100 uniformly drawn reads plus 20 reads from satellite arrays; the bounds k' of the sampled
   seeds are checked through the strand mirror (seeding revcomp(P) gives (k', k, s) and the
-  mirrored positions).
+  mirrored positions).  The mate-rescue prefilter runs over 20,000,000 candidates of the same
+  batch; 1,200 sampled candidates must match the oracle exactly.
 """
 import time
 
@@ -143,6 +144,25 @@ def test_human_3gbp_sampled_parity():
     ctx = mbw.Context(idx)
     out, seeds, pos = gpu_seed_batch(ctx, reads, min_seed_len=19, max_occ=500)
     log(f"{len(reads)} reads: {out.n_seeds} seeds, {out.n_pos} positions ({time.time() - t0:.1f} s)")
+    # mate-rescue prefilter over the whole batch (a true-mate and a decoy window per pair, device
+    # inputs, as the benchmark runs it); the oracle recomputes 1,200 sampled candidates
+    cands, decoy = synth.rescue_candidates(reads, len(ref), decoys=True, seed=104)
+    dseq, dlen = device_batch(reads)
+    dc = torch.from_numpy(cands.view(np.uint8)).to(torch.device("cuda:0"))
+    rout = ctx.rescue(dseq, dlen, dc, stream=torch.cuda.current_stream())
+    hits, passed = rout.download()
+    del dseq, dlen, dc
+    assert np.array_equal(passed, np.flatnonzero(hits["max_hits"] >= 10).astype(np.uint32))
+    csub = np.sort(np.random.default_rng(105).choice(len(cands), 1200, replace=False))
+    rids, inv = np.unique(cands["read_id"][csub], return_inverse=True)
+    rsub = reads.subset(rids)
+    mh, bt = oracle.rescue(ref.codes, rsub.seq, rsub.offsets, inv.astype(np.uint32), cands["win_beg"][csub],
+                           cands["win_len"][csub], q=7)
+    assert np.array_equal(hits["max_hits"][csub], mh) and np.array_equal(hits["best_t"][csub], bt)
+    assert np.mean(hits["max_hits"][decoy == 0] >= 10) > 0.95 and np.mean(hits["max_hits"][decoy == 1] >= 10) < 0.05
+    log(f"rescue prefilter: {len(cands)} candidates, {rout.n_pass} pass, kernel {rout.ms_kernel:.1f} ms "
+        f"({time.time() - t0:.1f} s)")
+    del cands, decoy, hits, passed
     # 100 uniform reads and 20 whose fragment starts inside a satellite array
     rng = np.random.default_rng(103)
     uni = rng.choice(len(reads), 100, replace=False)
