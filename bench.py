@@ -88,6 +88,57 @@ def cpu_baseline(workload: str, ref_codes, n_pairs: int, window: int, threads: i
                        f"{dt:.1f} s wall")
 
 
+def rescue_leg(mbw, torch, ctx, ref, reads, dseq, dlen, steps: int, warmup: int, cpu: bool, threads: int,
+               window: int):
+    """Mate-rescue prefilter (Section 2.7, q = 7, pass at max_t M_t >= 10) on the resident index:
+    for every read pair of the batch one candidate window where a proper pair puts the mate (from
+    the simulated position of the other mate) and one uniformly random decoy window of the same
+    length (about 550 bases), all in device memory; candidates/s over `steps` calls.  The CPU
+    baseline runs the oracle (M_t by definition, OpenMP over candidates) on a bounded sample of
+    the same recipe over the first `window` bases of the reference."""
+    import synth
+    cands, decoy = synth.rescue_candidates(reads, len(ref), decoys=True, seed=5000)
+    dc = torch.from_numpy(cands.view(np.uint8)).to(dseq.device)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        out = ctx.rescue(dseq, dlen, dc, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [ctx.rescue(dseq, dlen, dc, stream=stream) for _ in range(steps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out = outs[-1]
+    hits, _ = out.download()
+    pw = reads.lengths[cands["read_id"]].astype(np.float64) - 6
+    ww = cands["win_len"].astype(np.float64) - 6
+    cells = float(np.sum(np.maximum(pw, 0) * np.maximum(ww, 0)))
+    ms_k = sum(o.ms_kernel for o in outs) / len(outs)
+    in_bytes = float(reads.lengths[cands["read_id"]].astype(np.float64).sum() + cands["win_len"].astype(np.float64).sum() / 4
+                     + 16 * len(cands))
+    res = dict(value=round(len(cands) * steps / el, 1), unit="candidates/s", candidates=len(cands),
+               ms_per_step=round(el / steps * 1e3, 2), kernel_ms=round(ms_k, 2), q=7, min_hits=10,
+               pass_true=round(float(np.mean(hits["max_hits"][decoy == 0] >= 10)), 4),
+               pass_decoy=round(float(np.mean(hits["max_hits"][decoy == 1] >= 10)), 4),
+               qmer_pairs_per_s=round(cells / (ms_k * 1e-3), 1),
+               input_gbs=round(in_bytes / (ms_k * 1e-3) / 1e9, 1))
+    del dc
+    if cpu:
+        import oracle
+        sub = synth.Reference(np.ascontiguousarray(ref.codes[:window]), np.zeros((0, 2), np.uint64), 1, 0)
+        rs = synth.reads_fixed(sub, 50_000, 150, True, p_sub=0.005, p_indel=0.0005, seed=5001)
+        sc, _ = synth.rescue_candidates(rs, window, decoys=True, seed=5002)
+        t0 = time.time()
+        oracle.rescue(sub.codes, rs.seq, rs.offsets, sc["read_id"], sc["win_beg"], sc["win_len"], q=7,
+                      threads=threads)
+        dt = time.time() - t0
+        res["cpu_baseline"] = dict(value=round(len(sc) / dt, 1), unit="candidates/s", cores=threads, kind="oracle",
+                                   sample=f"{len(sc)} candidates (50,000 pairs of the workload's read model, a true-mate "
+                                          f"and a decoy window each) over the first {window / 1e6:.0f} Mbp of the "
+                                          f"reference; oracle = M_t counted pair by pair, OpenMP over candidates; "
+                                          f"{dt:.1f} s wall")
+    return res
+
+
 def serve_leg(mbw, idx, reads, seconds: float, sched: dict):
     """Open-loop serving on the resident index: Poisson arrivals, requests of log-uniform
     1..20,000 reads drawn from the workload's reads, at half of the saturation rate measured by a
@@ -270,6 +321,7 @@ def main():
     ap.add_argument("--no-unique", action="store_true", help="extend unique matches base by base")
     ap.add_argument("--probe", action="store_true", help="only run the copy and random-gather probes")
     ap.add_argument("--no-tune", action="store_true", help="default schedule instead of the autotuned one")
+    ap.add_argument("--no-rescue", action="store_true", help="skip the mate-rescue prefilter leg")
     ap.add_argument("--serve-seconds", type=float, default=6.0,
                     help="open-loop serving leg on the same index (0 = skip)")
     args = ap.parse_args()
@@ -395,6 +447,14 @@ def main():
         cpu["value"] = round(cpu["value"], 1)
         log(f"cpu oracle: {cpu['value']:.0f} reads/s on {cpu['cores']} threads")
 
+    rescue = None
+    if not args.no_rescue and args.workload in ("human_3gbp", "paired_100mbp"):
+        threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+        threads = max(1, min(threads, int(os.environ.get("OMP_NUM_THREADS", threads))))
+        rescue = rescue_leg(mbw, torch, ctx, ref, reads, dseq, dlen, args.steps, args.warmup, not args.no_cpu, threads,
+                            args.cpu_window)
+        log(f"rescue prefilter: {rescue}")
+
     serve = None
     if args.serve_seconds > 0:
         serve = serve_leg(mbw, idx, reads, args.serve_seconds, sched)
@@ -409,7 +469,7 @@ def main():
                             isa_sample=args.isa_sample, unique_ext=not args.no_unique,
                             bases_per_line=384, line_bytes=LINE_BYTES, index_gb=round(info["bytes_resident"] / 1e9, 2)),
                 schedule=sched, plain_gpu=plain, roofline=roofline, cpu_baseline=cpu, serve=serve,
-                index_build=index_build)
+                index_build=index_build, rescue=rescue)
     print(json.dumps(line), flush=True)
 
 
