@@ -7,9 +7,11 @@
 //                    plane, 64 bases per wave ballot;
 //   2. window planes each lane splits one 32-base text word into its low and high bits;
 //   3. table         every read q-mer without N (key = low bits | high bits << q) is inserted into
-//                    an open-addressing hash table whose slots chain the read positions of the key;
-//   4. diagonals     every window q-mer looks its key up and adds one to the counter of diagonal
-//                    j - i for each read position i in the chain;
+//                    an open-addressing hash table whose slots chain the read positions of the key,
+//                    and marked in a 2^14-bit presence filter (indexed by the key itself for q <= 7,
+//                    so exact there; by a hash of it above);
+//   4. diagonals     every window q-mer whose filter bit is set looks its key up and adds one to
+//                    the (16-bit) counter of diagonal j - i for each read position i in the chain;
 //   5. reduce        (max counter, smallest diagonal holding it) over the wave.
 // The work per candidate is O(|P| + |W| + matching pairs) rather than the O(|P| |W|) of testing
 // every diagonal; the pass list is a device-wide selection of candidates with max >= min_hits.
@@ -49,22 +51,30 @@ struct RescueArgs {
   unsigned long long *__restrict__ ctl;
 };
 
-// LDS areas of one wave, in 32-bit words
+// LDS areas of one wave, in 32-bit words; every area starts on a 16-byte boundary and spans a
+// multiple of four words (cleared and scanned with 16-byte accesses)
+constexpr uint32_t RC_FBITS = 14;                     // presence filter: 2^14 bits
+constexpr uint32_t RC_FWORDS = (1u << RC_FBITS) / 32;
+
 struct RcLayout {
-  uint32_t ts, rw, ww;
-  uint32_t key, head, next, cnt, rlo, rhi, rn, wlo, whi, total;
+  uint32_t ts, cw, rw, ww;
+  uint32_t key, head, filt, next, cnt, rlo, rhi, rn, wlo, whi, total;
 };
+
+__host__ __device__ inline uint32_t rc_up4(uint32_t x) { return (x + 3) & ~3u; }
 
 __host__ __device__ inline RcLayout rc_layout(uint32_t tbits, uint32_t cap_p, uint32_t cap_w) {
   RcLayout L;
   L.ts = 1u << tbits;
-  L.rw = 2 * ((cap_p + 63) / 64) + 2;   // read planes: two words per 64 bases + padding
-  L.ww = (cap_w + 63) / 32 + 2;         // window planes: the window may start at bit 31 of a word
+  L.cw = rc_up4((cap_p + cap_w + 1) / 2);       // two 16-bit diagonal counters per word
+  L.rw = rc_up4(2 * ((cap_p + 63) / 64) + 2);   // read planes: two words per 64 bases + padding
+  L.ww = rc_up4((cap_w + 63) / 32 + 2);         // window planes: the window may start at bit 31
   L.key = 0;
   L.head = L.key + L.ts;
-  L.next = L.head + L.ts;
-  L.cnt = L.next + cap_p;
-  L.rlo = L.cnt + cap_p + cap_w;
+  L.filt = L.head + L.ts;
+  L.next = L.filt + RC_FWORDS;
+  L.cnt = L.next + rc_up4(cap_p);
+  L.rlo = L.cnt + L.cw;
   L.rhi = L.rlo + L.rw;
   L.rn = L.rhi + L.rw;
   L.wlo = L.rn + L.rw;
@@ -73,18 +83,16 @@ __host__ __device__ inline RcLayout rc_layout(uint32_t tbits, uint32_t cap_p, ui
   return L;
 }
 
-__device__ __forceinline__ uint32_t rc_code(uint8_t ch, int role) {
-  uint32_t c;
-  switch (ch) {
-    case 'A': case 'a': c = 0; break;
-    case 'C': case 'c': c = 1; break;
-    case 'G': case 'g': c = 2; break;
-    case 'T': case 't': c = 3; break;
-    default: return 4;
-  }
-  if (role == 1 && c == 1) c = 3;   // read 1 of a bisulfite pair: C -> T
-  if (role == 2 && c == 2) c = 0;   // read 2: G -> A
-  return c;
+// A0 C1 G2 T3 from ASCII without branches: bits 1-2 of the letter are 0, 1, 3, 2 for A, C, G, T
+// (either case); anything else is 4
+__device__ __forceinline__ uint32_t rc_code(uint32_t ch, int role) {
+  const uint32_t u = ch | 0x20u;
+  const bool ok = (u == 'a') | (u == 'c') | (u == 'g') | (u == 't');
+  const uint32_t x = (ch >> 1) & 3u;
+  uint32_t c = x ^ (x >> 1);
+  c = (role == 1 && c == 1) ? 3u : c;   // read 1 of a bisulfite pair: C -> T
+  c = (role == 2 && c == 2) ? 0u : c;   // read 2: G -> A
+  return ok ? c : 4u;
 }
 
 // the even (low code) bits of a 32-base text word, packed into 32 bits
@@ -103,25 +111,36 @@ __device__ __forceinline__ uint32_t plane_bits(const uint32_t *pl, uint32_t b) {
   return __builtin_amdgcn_alignbit(pl[(b >> 5) + 1], pl[b >> 5], b & 31);
 }
 
+// workgroup barrier that orders LDS only (global loads issued before it stay in flight)
+__device__ __forceinline__ void rc_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ uint32_t rc_hash(uint32_t key, uint32_t tbits) {
   return (key * 0x9E3779B1u) >> (32 - tbits);
 }
 
 __global__ void __launch_bounds__(64) k_rescue(RescueArgs A) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ uint4 lds4[];
+  uint32_t *lds = (uint32_t *)lds4;
   const RcLayout L = rc_layout(A.tbits, A.cap_p, A.cap_w);
-  uint32_t *key = lds + L.key, *head = lds + L.head, *next = lds + L.next, *cnt = lds + L.cnt;
+  uint32_t *key = lds + L.key, *head = lds + L.head, *filt = lds + L.filt, *next = lds + L.next, *cnt = lds + L.cnt;
   uint32_t *rlo = lds + L.rlo, *rhi = lds + L.rhi, *rn = lds + L.rn, *wlo = lds + L.wlo, *whi = lds + L.whi;
   const uint32_t lane = threadIdx.x;
   const uint32_t q = (uint32_t)A.q, qm = (1u << q) - 1, tmask = L.ts - 1;
+  const bool direct = 2 * q <= RC_FBITS;   // the filter is indexed by the key itself
+  const uint4 zero4 = make_uint4(0, 0, 0, 0), none4 = make_uint4(RC_NONE, RC_NONE, RC_NONE, RC_NONE);
 
   for (uint64_t ci = blockIdx.x; ci < A.n_cand; ci += gridDim.x) {
     const mbw_rescue_cand_t cd = A.cand[ci];
-    uint64_t rb = 0, np = 0;
-    bool bad = cd.read_id >= A.n_reads;
-    if (!bad) { rb = A.offs[cd.read_id]; np = A.offs[cd.read_id + 1] - rb; }
+    uint64_t o0 = 0, o1 = 0;
+    if (cd.read_id < A.n_reads) { o0 = A.offs[cd.read_id]; o1 = A.offs[cd.read_id + 1]; }
+    const uint64_t rb = o0, np = o1 - o0;
     const uint64_t nw = cd.win_len;
-    bad = bad || cd.win_beg > A.m || nw > A.m - cd.win_beg || np > A.cap_p || nw > A.cap_w;
+    const bool bad = cd.read_id >= A.n_reads || cd.win_beg > A.m || nw > A.m - cd.win_beg || np > A.cap_p ||
+                     nw > A.cap_w;
     if (bad || np < q || nw < q) {   // (the host rejects bad candidates before the launch)
       if (lane == 0) {
         A.hits[ci].max_hits = 0;
@@ -131,69 +150,110 @@ __global__ void __launch_bounds__(64) k_rescue(RescueArgs A) {
       }
       continue;
     }
-    // 1. read planes (positions past the read count as N)
-    const uint32_t nchunk = (uint32_t)((np + 63) / 64);
-    for (uint32_t k = 0; k < nchunk; ++k) {
-      const uint64_t p = (uint64_t)k * 64 + lane;
-      const uint32_t c = p < np ? rc_code(A.reads[rb + p], A.role) : 4u;
-      const uint64_t blo = __ballot(c < 4 && (c & 1)), bhi = __ballot(c < 4 && (c & 2)), bn = __ballot(c >= 4);
-      if (lane < 2) {
-        rlo[2 * k + lane] = (uint32_t)(blo >> (32 * lane));
-        rhi[2 * k + lane] = (uint32_t)(bhi >> (32 * lane));
-        rn[2 * k + lane] = (uint32_t)(bn >> (32 * lane));
-      }
-    }
-    if (lane < 2) { rlo[2 * nchunk + lane] = 0; rhi[2 * nchunk + lane] = 0; rn[2 * nchunk + lane] = RC_NONE; }
-    // 2. window planes: text words covering [win_beg, win_beg + nw), window base j at bit s0 + j
+    // 1. window text words (in flight while the read is encoded): words covering
+    //    [win_beg, win_beg + nw), window base j at bit s0 + j of the planes
     const uint64_t wb = cd.win_beg >> 5;
     const uint32_t s0 = (uint32_t)(cd.win_beg & 31);
     const uint32_t nww = (uint32_t)((s0 + nw + 31) >> 5);
-    for (uint32_t k = lane; k < nww; k += 64) {
+    const uint64_t tw0 = lane < nww ? A.text[wb + lane] : 0ull;
+    // 2. read planes, 256 bases per round: four coalesced byte loads per lane (address clamped
+    //    into the read, so all are issued before one wait), then one ballot per plane and 64
+    //    bases (positions past the read count as N).  The first round is peeled off the loop so
+    //    that its loads overlap the text load.
+    const uint32_t nchunk = (uint32_t)((np + 63) / 64);
+    auto read_round = [&](uint32_t k0) {
+      uint32_t c[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint64_t p = (uint64_t)(k0 + u) * 64 + lane;
+        c[u] = A.reads[rb + (p < np ? p : np - 1)];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool in = (uint64_t)(k0 + u) * 64 + lane < np;
+        const uint32_t cu = in ? rc_code(c[u], A.role) : 4u;
+        if (k0 + u < nchunk) {
+          const uint64_t blo = __ballot(cu < 4 && (cu & 1)), bhi = __ballot(cu < 4 && (cu & 2));
+          const uint64_t bn = __ballot(cu >= 4);
+          if (lane < 2) {
+            const uint32_t k = 2 * (k0 + u) + lane;
+            rlo[k] = (uint32_t)(blo >> (32 * lane));
+            rhi[k] = (uint32_t)(bhi >> (32 * lane));
+            rn[k] = (uint32_t)(bn >> (32 * lane));
+          }
+        }
+      }
+    };
+    read_round(0);
+    for (uint32_t k0 = 4; k0 < nchunk; k0 += 4) read_round(k0);
+    if (lane < 2) { rlo[2 * nchunk + lane] = 0; rhi[2 * nchunk + lane] = 0; rn[2 * nchunk + lane] = RC_NONE; }
+    if (lane < nww) { wlo[lane] = even_bits(tw0); whi[lane] = even_bits(tw0 >> 1); }
+    for (uint32_t k = lane + 64; k < nww; k += 64) {
       const uint64_t x = A.text[wb + k];
       wlo[k] = even_bits(x);
       whi[k] = even_bits(x >> 1);
     }
     if (lane == 0) { wlo[nww] = 0; whi[nww] = 0; }
-    // 3. clear the table and the diagonal counters (diagonal t at t + |P| - q)
+    // 3. clear the table, the filter and the diagonal counters (diagonal t at t + |P| - q, two
+    //    16-bit counters per word)
     const uint32_t base = (uint32_t)np - q;
     const uint32_t nd = (uint32_t)(np + nw) - 2 * q + 1;
-    for (uint32_t k = lane; k < L.ts; k += 64) { key[k] = 0; head[k] = RC_NONE; }
-    for (uint32_t k = lane; k < nd; k += 64) cnt[k] = 0;
-    __syncthreads();
+    for (uint32_t k = lane; k < L.ts / 4; k += 64) { lds4[L.key / 4 + k] = zero4; lds4[L.head / 4 + k] = none4; }
+    for (uint32_t k = lane; k < RC_FWORDS / 4; k += 64) lds4[L.filt / 4 + k] = zero4;
+    const uint32_t ncw4 = ((nd + 1) / 2 + 3) / 4;
+    for (uint32_t k = lane; k < ncw4; k += 64) lds4[L.cnt / 4 + k] = zero4;
+    rc_sync();
     // 4. insert the read's q-mers
     for (uint32_t i = lane; i + q <= (uint32_t)np; i += 64) {
       if (plane_bits(rn, i) & qm) continue;
-      const uint32_t kk = ((plane_bits(rlo, i) & qm) | ((plane_bits(rhi, i) & qm) << q)) + 1;
+      const uint32_t code = (plane_bits(rlo, i) & qm) | ((plane_bits(rhi, i) & qm) << q);
+      const uint32_t kk = code + 1;
+      const uint32_t f = direct ? code : rc_hash(kk, RC_FBITS);
+      atomicOr(&filt[f >> 5], 1u << (f & 31));
       uint32_t s = rc_hash(kk, A.tbits);
-      for (;;) {   // the table has more slots than the read has positions: an empty slot exists
+      for (uint32_t g = 0; g < L.ts; ++g) {   // more slots than read positions: an empty one exists
         const uint32_t old = atomicCAS(&key[s], 0u, kk);
         if (old == 0u || old == kk) break;
         s = (s + 1) & tmask;
       }
       next[i] = atomicExch(&head[s], i);
     }
-    __syncthreads();
-    // 5. look up the window's q-mers, count per diagonal
+    rc_sync();
+    // 5. look up the window's q-mers whose filter bit is set, count per diagonal
     for (uint32_t j = lane; j + q <= (uint32_t)nw; j += 64) {
       const uint32_t b = s0 + j;
-      const uint32_t kk = ((plane_bits(wlo, b) & qm) | ((plane_bits(whi, b) & qm) << q)) + 1;
+      const uint32_t code = (plane_bits(wlo, b) & qm) | ((plane_bits(whi, b) & qm) << q);
+      const uint32_t kk = code + 1;
+      const uint32_t f = direct ? code : rc_hash(kk, RC_FBITS);
+      if (!((filt[f >> 5] >> (f & 31)) & 1u)) continue;
       uint32_t s = rc_hash(kk, A.tbits);
-      for (;;) {
+      for (uint32_t g = 0; g < L.ts; ++g) {
         const uint32_t k = key[s];
         if (k == 0u) break;
-        if (k == kk) {
-          for (uint32_t i = head[s]; i != RC_NONE; i = next[i]) atomicAdd(&cnt[j - i + base], 1u);
+        if (k == kk) {   // a chain holds distinct read positions i <= |P| - q
+          uint32_t i = head[s];
+          for (uint32_t h = 0; i <= base && h <= base; ++h) {
+            const uint32_t x = j - i + base;
+            atomicAdd(&cnt[x >> 1], 1u << (16 * (x & 1)));
+            i = next[i];
+          }
           break;
         }
         s = (s + 1) & tmask;
       }
     }
-    __syncthreads();
-    // 6. max over the diagonals, smallest t on ties
+    rc_sync();
+    // 6. max over the diagonals, smallest t on ties (8 counters per lane and step, ascending)
     uint32_t bv = 0, bx = RC_NONE;
-    for (uint32_t x = lane; x < nd; x += 64) {
-      const uint32_t v = cnt[x];
-      if (v > bv) { bv = v; bx = x; }
+    for (uint32_t k = lane; k < ncw4; k += 64) {
+      const uint4 v = lds4[L.cnt / 4 + k];
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t lo = w[u] & 0xFFFFu, hi = w[u] >> 16;
+        if (lo > bv) { bv = lo; bx = 8 * k + 2 * u; }
+        if (hi > bv) { bv = hi; bx = 8 * k + 2 * u + 1; }
+      }
     }
     for (int off = 32; off > 0; off >>= 1) {
       const uint32_t ov = __shfl_xor(bv, off), ox = __shfl_xor(bx, off);
@@ -204,7 +264,7 @@ __global__ void __launch_bounds__(64) k_rescue(RescueArgs A) {
       A.hits[ci].best_t = bv ? (int32_t)bx - (int32_t)base : 0;
       A.flags[ci] = bv >= A.min_hits;
     }
-    __syncthreads();   // the next candidate reuses the LDS area
+    rc_sync();   // the next candidate reuses the LDS area
   }
 }
 
