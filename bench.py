@@ -4,7 +4,7 @@
 Workload (default): a synthetic 3.1 Gbp reference (55% random sequence, 35% interspersed repeat
 families of 300 bp / 6 kbp copies at 2-20% divergence, 10% tandem arrays of 171 bp units at 1-3%
 divergence), indexed on the GPU (T = R . revcomp(R) . $, n = 6.2 G; 128-byte occurrence lines of
-384 rows; SA sampled every 8 rows; 12-mer interval table), and 10,000,000 read pairs of 150 bp
+384 rows; SA sampled every 8 rows; 14-mer interval table), and 10,000,000 read pairs of 150 bp
 (20,000,000 reads) at 0.5% substitutions + 0.05% 1-3 bp indels, 5% of pairs drawn from satellite
 arrays.  One step = one ``mbw_seed`` call over the whole batch with the reads already resident in
 HBM: encode, both SMEM rounds, sort/dedup, locate of every seed with s <= 500.
@@ -80,12 +80,24 @@ def cpu_baseline(workload: str, ref_codes, n_pairs: int, window: int, threads: i
     t0 = time.time()
     res = ox.seed(rs.seq, rs.offsets, min_len=19, max_occ=500, method=1, kmer_k=10, threads=threads)
     dt = time.time() - t0
-    return dict(value=len(rs) / dt, unit="reads/s", cores=threads, kind="oracle",
+    one = rs.subset(np.arange(min(len(rs), 20_000)))
+    t0 = time.time()
+    ox.seed(one.seq, one.offsets, min_len=19, max_occ=500, method=1, kmer_k=10, threads=1)
+    dt1 = time.time() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return dict(value=len(rs) / dt, unit="reads/s", cores=threads, kind="oracle", cpu_model=model,
+                value_1core=round(len(one) / dt1, 1),
                 sample=f"{len(rs)} reads ({int(rs.lengths.sum())} bases, workload read model) against an oracle index "
                        f"of the first {window / 1e6:.0f} Mbp of the same 3.1 Gbp reference (index build "
                        f"{t_build:.1f} s excluded); oracle = serial Algorithm 3 + LocateSlow with the 10-mer "
                        f"shortcut per read, OpenMP over reads; {len(res)} seeds, {res.pos.size} positions; "
-                       f"{dt:.1f} s wall")
+                       f"{dt:.1f} s wall; value_1core: the first {len(one)} of these reads on one thread, "
+                       f"{dt1:.1f} s")
 
 
 def rescue_leg(mbw, torch, ctx, ref, reads, dseq, dlen, steps: int, warmup: int, cpu: bool, threads: int,
@@ -312,7 +324,7 @@ def main():
     ap.add_argument("--ref-len", type=int, default=0, help="reference length (0 = the workload's)")
     ap.add_argument("--pairs", type=int, default=0, help="read pairs / reads (0 = the workload's)")
     ap.add_argument("--sa-sample", type=int, default=8)
-    ap.add_argument("--kmer", type=int, default=12)
+    ap.add_argument("--kmer", type=int, default=14)
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the plain kernel (0 = skip)")
     ap.add_argument("--cpu-pairs", type=int, default=250_000)
     ap.add_argument("--cpu-window", type=int, default=16_000_000)

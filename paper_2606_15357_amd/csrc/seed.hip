@@ -563,12 +563,14 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
         const uint64_t lo = off < 64 ? wv0 : wv1, mid = off < 64 ? wv1 : wv2, hi = off < 64 ? wv2 : wv3;
         const uint64_t t0 = sh ? (lo >> sh) | (mid << (64 - sh)) : lo;
         const uint64_t t1 = sh ? (mid >> sh) | (hi << (64 - sh)) : mid;
+        // read bases j .. j+63: words past the read's end hold stale bases, which the limit
+        // qend - j cuts off (staged: indexes clamped into the lane's LDS area; unstaged: the packed
+        // batch ends with two spare words)
         const int w0 = j >> 5, rb = j & 31;
-        const uint32_t nw_q = (q_rlen() + 31) >> 5;
-        const uint64_t a0 = word_at(w0), a1 = (uint32_t)(w0 + 1) < nw_q ? word_at(w0 + 1) : 0ull,
-                       a2 = (uint32_t)(w0 + 2) < nw_q ? word_at(w0 + 2) : 0ull;
-        const uint32_t n0 = nbits_at(w0), n1 = (uint32_t)(w0 + 1) < nw_q ? nbits_at(w0 + 1) : 0u,
-                       n2 = (uint32_t)(w0 + 2) < nw_q ? nbits_at(w0 + 2) : 0u;
+        const int w1 = STAGED ? min(w0 + 1, STAGE_WORDS - 1) : w0 + 1;
+        const int w2 = STAGED ? min(w0 + 2, STAGE_WORDS - 1) : w0 + 2;
+        const uint64_t a0 = word_at(w0), a1 = word_at(w1), a2 = word_at(w2);
+        const uint32_t n0 = nbits_at(w0), n1 = nbits_at(w1), n2 = nbits_at(w2);
         const uint64_t r0 = rb ? (a0 >> (2 * rb)) | (a1 << (64 - 2 * rb)) : a0;
         const uint64_t r1 = rb ? (a1 >> (2 * rb)) | (a2 << (64 - 2 * rb)) : a1;
         const uint64_t nb = (((uint64_t)n2 << 32 | n1) << (32 - rb)) | ((uint64_t)n0 >> rb);
@@ -856,8 +858,10 @@ __global__ void k_seed_posoff(mbw_seed_t *__restrict__ out, const uint64_t *__re
     out[t].pos_off = off[t];
 }
 
-// start row of every (seed, occurrence) pair: X[pos_off + i] = k + i.  A wave takes 64 seeds and
-// writes each seed's rows with all of its lanes (coalesced, balanced for seeds with many rows).
+// start row of every (seed, occurrence) pair: X[pos_off + i] = k + i.  A wave takes 64 seeds; a
+// seed with few rows is written by its own lane (neighbouring lanes write neighbouring runs), a
+// seed with many by all lanes of the wave (coalesced).
+#define EXPAND_LANE_MAX 8
 __global__ void __launch_bounds__(256) k_expand_rows(const mbw_seed_t *__restrict__ seeds, uint64_t ns, uint64_t *__restrict__ X) {
   const int lane = threadIdx.x & 63;
   const uint64_t nwave = (uint64_t)gridDim.x * (blockDim.x >> 6);
@@ -865,8 +869,13 @@ __global__ void __launch_bounds__(256) k_expand_rows(const mbw_seed_t *__restric
     uint64_t k = 0, off = 0;
     uint32_t np = 0;
     if (base + lane < ns) { const mbw_seed_t sd = seeds[base + lane]; k = sd.k; off = sd.pos_off; np = sd.npos; }
-    const int cnt = (int)min<uint64_t>(64, ns - base);
-    for (int t = 0; t < cnt; ++t) {
+    const bool mine = np <= EXPAND_LANE_MAX;
+    if (mine)
+      for (uint32_t q = 0; q < np; ++q) X[off + q] = k + q;
+    uint64_t big = __ballot(!mine);
+    while (big) {
+      const int t = __ffsll((long long)big) - 1;
+      big &= big - 1;
       const uint64_t kt = __shfl(k, t), ot = __shfl(off, t);
       const uint32_t nt = (uint32_t)__shfl((int)np, t);
       for (uint32_t q = (uint32_t)lane; q < nt; q += 64) X[ot + q] = kt + q;
