@@ -519,7 +519,7 @@ extern "C" int mbw_index_build(const uint8_t *ref, uint64_t len, const mbw_build
   *out = nullptr;
   if (!ref || !opts || len == 0 || len >= (1ull << 38)) { mbw_set_error("bad reference or options"); return MBW_E_INVAL; }
   if (opts->sa_sample < 1 || opts->sa_sample > 1024) { mbw_set_error("sa_sample must be in [1,1024]"); return MBW_E_INVAL; }
-  if (opts->kmer_k < 0 || opts->kmer_k > 14) { mbw_set_error("kmer_k must be in [0,14]"); return MBW_E_INVAL; }
+  if (opts->kmer_k < 0 || opts->kmer_k > 15) { mbw_set_error("kmer_k must be in [0,15]"); return MBW_E_INVAL; }
   if (opts->isa_sample < 0 || opts->isa_sample > 64) { mbw_set_error("isa_sample must be in [0,64]"); return MBW_E_INVAL; }
   TRY(hipSetDevice(opts->device));
   // host: codes, ambiguous bases -> random (counter-based SplitMix64), bisulfite conversion
@@ -784,7 +784,7 @@ extern "C" int mbw_index_load(const char *path, int device, mbw_index **out) {
   if (hd.magic != kMagic || hd.version != kVersion || hd.bpl != MBW_BPL ||
       hd.sum_header != fnv(&hd, offsetof(FileHeader, sum_header)) || hd.n_lines != hd.n / MBW_BPL + 1 ||
       hd.sa_sample < 1 || hd.sa_sample > 1024 || hd.n_ssa != (hd.n + hd.sa_sample - 1) / hd.sa_sample ||
-      hd.kmer_k < 0 || hd.kmer_k > 14 || hd.n_sb != (int)(((hd.n_lines - 1) >> MBW_SB_SHIFT) + 1) ||
+      hd.kmer_k < 0 || hd.kmer_k > 15 || hd.n_sb != (int)(((hd.n_lines - 1) >> MBW_SB_SHIFT) + 1) ||
       hd.isa_sample < 0 || hd.isa_sample > 64 ||
       (hd.isa_sample ? (hd.n_isa != (hd.n - 1) / hd.isa_sample + 1 || hd.n_text != (hd.n - 1 + 31) / 32 + 4)
                      : (hd.n_isa != 0 || hd.n_text != 0)) ||

@@ -49,5 +49,5 @@ def test_invalid_build_options():
         mbw.Index.build(np.zeros(10, np.uint8), sa_sample=0)
     assert e.value.code == mbw.MBW_E_INVAL
     with pytest.raises(mbw.MbwError) as e:
-        mbw.Index.build(np.zeros(10, np.uint8), kmer_k=15)
+        mbw.Index.build(np.zeros(10, np.uint8), kmer_k=16)
     assert e.value.code == mbw.MBW_E_INVAL

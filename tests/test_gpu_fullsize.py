@@ -83,7 +83,7 @@ def compare_without_bounds(seeds, pos, exp):
 def genome100():
     t = time.time()
     ref = synth.workload_reference("paired_100mbp")
-    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=12)
+    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=15)
     ox = oracle.OracleIndex(ref.codes, sa_rate=8)
     log(f"100 Mbp: GPU index + oracle index in {time.time() - t:.1f} s")
     yield ref, idx, ox
@@ -137,7 +137,7 @@ def test_human_3gbp_sampled_parity():
     t0 = time.time()
     ref = synth.workload_reference("human_3gbp")
     log(f"3.1 Gbp reference in {time.time() - t0:.1f} s")
-    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=12)
+    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=15)
     info = idx.info()
     log(f"GPU index in {time.time() - t0:.1f} s, n = {info['n']}")
     reads = synth.workload_reads("human_3gbp", ref)

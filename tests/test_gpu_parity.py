@@ -153,7 +153,8 @@ def cfg0():
 
 
 @pytest.mark.parametrize("kernel,K,ri,uniq", [(0, 10, 4, True), (0, 10, 4, False), (0, 0, 1, True), (1, 0, 4, True),
-                                              (0, 12, 8, True), (0, 12, 0, True), (0, 14, 4, True), (1, 14, 4, True)])
+                                              (0, 12, 8, True), (0, 12, 0, True), (0, 14, 4, True), (1, 14, 4, True),
+                                              (0, 15, 4, True)])
 def test_small_workload_parity(cfg0, kernel, K, ri, uniq):
     """1 Mbp + repeat family reference, 10,000 x 150 bp reads, (19,1)-SMEMs with re-seeding,
     max_occ 500: every seed, interval and position equals the oracle's, with and without the
