@@ -4,7 +4,8 @@
 Workload (default): a synthetic 3.1 Gbp reference (55% random sequence, 35% interspersed repeat
 families of 300 bp / 6 kbp copies at 2-20% divergence, 10% tandem arrays of 171 bp units at 1-3%
 divergence), indexed on the GPU (T = R . revcomp(R) . $, n = 6.2 G; 128-byte occurrence lines of
-384 rows; SA sampled every 8 rows; 15-mer interval table), and 10,000,000 read pairs of 150 bp
+384 rows; SA sampled every 8 rows; 15-mer interval table, the size picked from the text
+length), and 10,000,000 read pairs of 150 bp
 (20,000,000 reads) at 0.5% substitutions + 0.05% 1-3 bp indels, 5% of pairs drawn from satellite
 arrays.  One step = one ``mbw_seed`` call over the whole batch with the reads already resident in
 HBM: encode, both SMEM rounds, sort/dedup, locate of every seed with s <= 500.
@@ -324,7 +325,7 @@ def main():
     ap.add_argument("--ref-len", type=int, default=0, help="reference length (0 = the workload's)")
     ap.add_argument("--pairs", type=int, default=0, help="read pairs / reads (0 = the workload's)")
     ap.add_argument("--sa-sample", type=int, default=8)
-    ap.add_argument("--kmer", type=int, default=15)
+    ap.add_argument("--kmer", type=int, default=-1, help="k-mer table size (-1 = from the text length)")
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the plain kernel (0 = skip)")
     ap.add_argument("--cpu-pairs", type=int, default=250_000)
     ap.add_argument("--cpu-window", type=int, default=16_000_000)
@@ -477,7 +478,7 @@ def main():
                 scaling="weak", vs_baseline=None, dtype="u64", data="synthetic",
                 config=dict(workload=wl["desc"] + f" ({n_reads} reads, {args.ref_len / 1e6:.0f} Mbp); (19,1)-SMEMs + "
                                      f"re-seeding, max_occ 500",
-                            min_seed_len=19, max_occ=500, sa_sample=args.sa_sample, kmer_k=args.kmer,
+                            min_seed_len=19, max_occ=500, sa_sample=args.sa_sample, kmer_k=info["kmer_k"],
                             isa_sample=args.isa_sample, unique_ext=not args.no_unique,
                             bases_per_line=384, line_bytes=LINE_BYTES, index_gb=round(info["bytes_resident"] / 1e9, 2)),
                 schedule=sched, plain_gpu=plain, roofline=roofline, cpu_baseline=cpu, serve=serve,

@@ -41,7 +41,10 @@ typedef struct {
   int sa_sample;        /* r: S(x) is kept for rows x that are multiples of r (Section 2.4);
                            1 <= r <= 1024.  Locate walks take about r-1 LF steps on average.     */
   int kmer_k;           /* k-mer ds-interval table (Section 2.5 precomputes all 10-mers):
-                           0 = no table, else 1..15 (4^k entries of 16 bytes).                   */
+                           0 = no table, 1..15 (4^k entries of 16 bytes), or -1 = automatic:
+                           floor(log4 n) - 1 capped at 15, so that a k-mer occurs about 4 times
+                           or more in T (15 for a 3.1 Gbp reference, 12 for 100 Mbp); the
+                           value used is reported by mbw_index_info.                              */
   int bisulfite;        /* 0: T = R . revcomp(R) . $.  1: four-copy 3-base text over
                            C->T(R) . G->A(R) and its reverse complement (Section 2.9).           */
   int ref_is_codes;     /* 1: ref holds codes 0..3 (A,C,G,T); 0: ASCII (case-insensitive)      */

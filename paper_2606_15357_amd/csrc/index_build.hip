@@ -519,7 +519,7 @@ extern "C" int mbw_index_build(const uint8_t *ref, uint64_t len, const mbw_build
   *out = nullptr;
   if (!ref || !opts || len == 0 || len >= (1ull << 38)) { mbw_set_error("bad reference or options"); return MBW_E_INVAL; }
   if (opts->sa_sample < 1 || opts->sa_sample > 1024) { mbw_set_error("sa_sample must be in [1,1024]"); return MBW_E_INVAL; }
-  if (opts->kmer_k < 0 || opts->kmer_k > 15) { mbw_set_error("kmer_k must be in [0,15]"); return MBW_E_INVAL; }
+  if (opts->kmer_k < -1 || opts->kmer_k > 15) { mbw_set_error("kmer_k must be -1 or in [0,15]"); return MBW_E_INVAL; }
   if (opts->isa_sample < 0 || opts->isa_sample > 64) { mbw_set_error("isa_sample must be in [0,64]"); return MBW_E_INVAL; }
   TRY(hipSetDevice(opts->device));
   // host: codes, ambiguous bases -> random (counter-based SplitMix64), bisulfite conversion
@@ -557,10 +557,15 @@ extern "C" int mbw_index_build(const uint8_t *ref, uint64_t len, const mbw_build
   ix->len_r = len;
   ix->bisulfite = opts->bisulfite ? 1 : 0;
   ix->sa_sample = opts->sa_sample;
-  ix->kmer_k = opts->kmer_k;
   ix->isa_sample = opts->isa_sample;
   uint64_t m = 2 * lrp, n = m + 1;
   ix->n = n;
+  ix->kmer_k = opts->kmer_k;
+  if (ix->kmer_k < 0) {   // automatic: the largest k whose k-mers occur about 4 times or more in T
+    int lg = 0;
+    while (lg < 31 && (1ull << (2 * (lg + 1))) <= n) ++lg;   // floor(log4 n)
+    ix->kmer_k = std::max(1, std::min(15, lg - 1));
+  }
   hipStream_t st;
   if (hipStreamCreate(&st) != hipSuccess) { delete ix; mbw_set_error("hipStreamCreate failed"); return MBW_E_HIP; }
   int rc = [&]() -> int {

@@ -51,3 +51,6 @@ def test_invalid_build_options():
     with pytest.raises(mbw.MbwError) as e:
         mbw.Index.build(np.zeros(10, np.uint8), kmer_k=16)
     assert e.value.code == mbw.MBW_E_INVAL
+    with pytest.raises(mbw.MbwError) as e:
+        mbw.Index.build(np.zeros(10, np.uint8), kmer_k=-2)
+    assert e.value.code == mbw.MBW_E_INVAL

@@ -167,6 +167,17 @@ def test_small_workload_parity(cfg0, kernel, K, ri, uniq):
     idx.free()
 
 
+def test_automatic_kmer_size(cfg0):
+    """kmer_k = -1 picks floor(log4 n) - 1 (n = 2,080,001 here: 9) and seeds bit-exactly."""
+    ref, reads, ox, exp = cfg0
+    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=-1)
+    n = idx.info()["n"]
+    assert idx.info()["kmer_k"] == max(1, min(15, int(np.floor(np.log(n) / np.log(4))) - 1)) == 9
+    out, seeds, pos = gpu_seed(idx, reads, min_seed_len=19, max_occ=500)
+    compare_with_oracle(seeds, pos, exp)
+    idx.free()
+
+
 def test_line_count_matches_oracle(cfg0):
     """The kernel's algorithmic line counter equals the oracle's count for the same layout."""
     ref, reads, ox, _ = cfg0
