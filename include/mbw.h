@@ -310,6 +310,9 @@ typedef struct {
   const uint64_t *pos;
   double t_submit, t_start, t_done;   /* seconds since mbw_serve_open (steady clock) */
   uint64_t batch_id, batch_reads;     /* the device batch that carried the request */
+  uint64_t n_pieces;          /* opts.bs_refine: the request's refined pieces (host memory owned by
+                                 the server), read_id and seed counted from the request's own */
+  const mbw_piece_t *pieces;
 } mbw_serve_result;
 
 /* Start the workers.  The index must outlive the server.  Errors: MBW_E_INVAL, MBW_E_NOMEM, MBW_E_HIP. */

@@ -73,7 +73,8 @@ class ServeCfg(C.Structure):
 class ServeResult(C.Structure):
     _fields_ = [("n_seeds", C.c_uint64), ("n_pos", C.c_uint64), ("seeds", C.c_void_p), ("pos", C.c_void_p),
                 ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
-                ("batch_id", C.c_uint64), ("batch_reads", C.c_uint64)]
+                ("batch_id", C.c_uint64), ("batch_reads", C.c_uint64), ("n_pieces", C.c_uint64),
+                ("pieces", C.c_void_p)]
 
 
 class RescueOpts(C.Structure):
@@ -444,7 +445,9 @@ class Server:
         return t.value
 
     def wait(self, ticket: int, timeout_ms: int = -1, release: bool = True):
-        """(seeds, positions, timing dict) of a request, or None if not finished within timeout_ms."""
+        """(seeds, positions, info) of a request, or None if not finished within timeout_ms; info has
+        the timing, the batch and, for a bisulfite server with bs_refine, the refined pieces
+        (PIECE_DTYPE, read_id and seed counted within the request)."""
         r = ServeResult()
         rc = self._lib.mbw_serve_wait(self._h, int(ticket), int(timeout_ms), C.byref(r))
         if rc == MBW_E_BUSY:
@@ -456,8 +459,11 @@ class Server:
             C.memmove(seeds.ctypes.data, r.seeds, r.n_seeds * SEED_DTYPE.itemsize)
         if r.n_pos:
             C.memmove(pos.ctypes.data, r.pos, r.n_pos * 8)
+        pieces = np.zeros(r.n_pieces, dtype=PIECE_DTYPE)
+        if r.n_pieces:
+            C.memmove(pieces.ctypes.data, r.pieces, r.n_pieces * PIECE_DTYPE.itemsize)
         info = dict(t_submit=r.t_submit, t_start=r.t_start, t_done=r.t_done, batch_id=r.batch_id,
-                    batch_reads=r.batch_reads)
+                    batch_reads=r.batch_reads, pieces=pieces)
         if release:
             _check(self._lib.mbw_serve_release(self._h, int(ticket)))
         return seeds, pos, info

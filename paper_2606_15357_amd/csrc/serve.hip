@@ -44,7 +44,7 @@ struct Pinned {
 
 // one batch's downloaded result, shared by its requests
 struct BatchBuf {
-  Pinned seeds, pos;
+  Pinned seeds, pos, pieces;
   int refs = 0;
 };
 
@@ -58,7 +58,8 @@ struct Request {
   int state = 0;   // 0 queued, 1 running, 2 done
   int rc = MBW_OK;
   BatchBuf *buf = nullptr;          // the shared batch result
-  uint64_t s0 = 0, ns = 0, p0 = 0, np = 0;   // this request's slice of it
+  uint64_t s0 = 0, ns = 0, p0 = 0, np = 0;   // this request's slice of it (seeds, positions,
+  uint64_t c0 = 0, nc = 0;                    // refined pieces)
 };
 
 }  // namespace
@@ -149,19 +150,27 @@ static void worker_main(mbw_server *s, mbw_ctx *ctx, hipStream_t st) {
     if (!rc) rc = bb->seeds.ensure((res.n_seeds + 1) * sizeof(mbw_seed_t));
     if (!rc) rc = bb->pos.ensure((res.n_pos + 1) * sizeof(uint64_t));
     if (!rc) rc = mbw_result_download(ctx, &res, (mbw_seed_t *)bb->seeds.p, (uint64_t *)bb->pos.p);
+    if (!rc && res.n_pieces) {
+      rc = bb->pieces.ensure((res.n_pieces + 1) * sizeof(mbw_piece_t));
+      if (!rc) rc = mbw_result_download_pieces(ctx, &res, (mbw_piece_t *)bb->pieces.p);
+    }
     tb3 = s->now();
-    // split: seeds are sorted by read, positions follow the seeds; rebase each slice in place
+    // split: seeds are sorted by read, positions follow the seeds, refined pieces follow their
+    // seeds; rebase each slice in place
     if (!rc) {
       mbw_seed_t *sd = (mbw_seed_t *)bb->seeds.p;
-      uint64_t r0 = 0, t = 0;
+      mbw_piece_t *pc = (mbw_piece_t *)bb->pieces.p;
+      uint64_t r0 = 0, t = 0, c = 0;
       for (Request *r : batch) {
         const uint64_t r1 = r0 + r->lengths.size();
-        const uint64_t t0 = t;
+        const uint64_t t0 = t, c0 = c;
         while (t < res.n_seeds && sd[t].read_id < r1) ++t;
         uint64_t p0 = 0, p1 = 0;
         if (t > t0) { p0 = sd[t0].pos_off; p1 = sd[t - 1].pos_off + sd[t - 1].npos; }
         for (uint64_t q = t0; q < t; ++q) { sd[q].read_id -= (uint32_t)r0; sd[q].pos_off -= p0; }
-        r->buf = bb; r->s0 = t0; r->ns = t - t0; r->p0 = p0; r->np = p1 - p0;
+        while (c < res.n_pieces && pc[c].seed < t) ++c;
+        for (uint64_t q = c0; q < c; ++q) { pc[q].read_id -= (uint32_t)r0; pc[q].seed -= (uint32_t)t0; }
+        r->buf = bb; r->s0 = t0; r->ns = t - t0; r->p0 = p0; r->np = p1 - p0; r->c0 = c0; r->nc = c - c0;
         r0 = r1;
       }
     }
@@ -275,6 +284,8 @@ extern "C" int mbw_serve_wait(mbw_server *s, uint64_t ticket, int timeout_ms, mb
   out->t_done = r->t_done;
   out->batch_id = r->batch_id;
   out->batch_reads = r->batch_reads;
+  out->n_pieces = r->nc;
+  out->pieces = r->buf && r->nc ? (const mbw_piece_t *)r->buf->pieces.p + r->c0 : nullptr;
   return MBW_OK;
 }
 

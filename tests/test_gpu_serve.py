@@ -129,3 +129,43 @@ def test_serve_empty_request_and_close_with_queue(small):
         s, p, _ = srv.wait(t)
         compare_with_oracle(s, p, ox.seed(reqs[q].seq, reqs[q].offsets))
     srv.close()
+
+
+def test_serve_bisulfite_refined_pieces():
+    """A bisulfite server (read 1, strand filter, refinement): every request's seeds, positions and
+    refined pieces equal the oracle's for that request alone, with piece read ids and seed indexes
+    counted within the request, also when requests share a device batch."""
+    ref = synth.reference(0, 200_000, 31)
+    ox = oracle.OracleIndex(ref.codes, bisulfite=True, sa_rate=8)
+    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=10, bisulfite=True)
+    rs = synth.reads_bisulfite(ref, 1500, seed=6)
+    seq = rs.seq.copy()
+    rng = np.random.default_rng(7)
+    hit = rng.integers(0, seq.size, seq.size // 200)            # a few planted C changes
+    seq[hit] = ord("C")
+    cuts = np.unique(np.concatenate([[0, len(rs)], rng.integers(1, len(rs), 24)]))
+    reqs = []
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        o0, o1 = int(rs.offsets[a]), int(rs.offsets[b])
+        offs = (rs.offsets[a:b + 1] - rs.offsets[a]).astype(np.uint64)
+        reqs.append((seq[o0:o1].copy(), rs.lengths[a:b].copy(), offs))
+    srv = mbw.Server(idx, n_workers=2, max_batch_reads=400, bs_role=1, bs_refine=True)
+    tickets = [srv.submit(s, l) for s, l, _ in reqs]
+    merged = 0
+    for (s, l, offs), t in zip(reqs, tickets):
+        seeds, pos, info = srv.wait(t)
+        exp = ox.seed(s, offs, bs_role=1)
+        compare_with_oracle(seeds, pos, exp)
+        pieces = info["pieces"]
+        want = oracle.bs_refine(ref.codes, s, offs, exp, 1, min_len=19)
+        got = pieces[np.lexsort((pieces["pos"], pieces["qend"], pieces["qbeg"], pieces["read_id"]))]
+        assert len(got) == len(want)
+        for f in ("read_id", "qbeg", "qend", "pos"):
+            assert np.array_equal(got[f], want[f]), f
+        assert np.all(pieces["seed"] < len(seeds))
+        assert np.all(seeds["read_id"][pieces["seed"]] == pieces["read_id"])
+        assert np.all((seeds["qbeg"][pieces["seed"]] <= pieces["qbeg"]) & (pieces["qend"] <= seeds["qend"][pieces["seed"]]))
+        merged += info["batch_reads"] > len(l)
+    assert merged > 0
+    srv.close()
+    idx.free()
