@@ -361,6 +361,8 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
   uint64_t k = 0, kr = 0, s = 0;
   uint32_t budget = 0;            // iteration guard of the current query (a corrupt index cannot loop forever)
   uint64_t wrow = 0;              // unique path: walk row (or sample index)
+  uint64_t wrow2 = 0;             // unique path, first walk: the row of the reverse-complement match
+  bool wmir = false;              // the occurrence was found by the reverse-complement walk
   __shared__ uint64_t stp[SMEM_WAVES][64];   // unique path: text position of P[i] (rarely read: kept in LDS)
   uint64_t *tpl = &stp[wv][lane];
   uint32_t wcnt = 0;              // unique path: LF steps taken (stage 4) or still to take (stage 7)
@@ -392,10 +394,9 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
     if (st == ST_ACTIVE) {
       for (;;) {
         if ((UNIQ || SEG) && u >= 4) {                  // unique path (4-7), segment left check (8)
-          if (UNIQ && u == 4) {
-            const bool smp = (wrow & P.rmask) == 0;
-            if (smp) { act = ACT_SSA; break; }
-            if (wrow == ix.primary) { wrow = 0; ++wcnt; continue; }   // LF of the $ row is row 0
+          if (UNIQ && u == 4) {   // walk both rows of the match until one reaches a sampled row
+            const bool s1 = (wrow & P.rmask) == 0, s2 = (wrow2 & P.rmask) == 0;
+            if (s1 || s2) { wmir = !s1; if (!s1) wrow = wrow2; act = ACT_SSA; break; }
             act = ACT_LF; break;
           }
           if (UNIQ && u == 5) { act = ACT_TEXT; break; }
@@ -419,7 +420,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
         if (u == 2) {
           const bool qe = j == (int)qend;
           a = qe ? 4 : base_at(j);
-          if (UNIQ && !qe && P.uniq && s == 1) { u = 4; wrow = k; wcnt = 0; continue; }
+          if (UNIQ && !qe && P.uniq && s == 1) { u = 4; wrow = k; wrow2 = kr; wcnt = 0; continue; }
           if (a > 3) {                                  // end of the query, or a non-ACGT base: SMEM [i, j)
             if (SEG && segchk && i == (int)qbeg) { segchk = false; u = 8; continue; }
             em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s;
@@ -458,13 +459,14 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
     const bool ext = act == ACT_BWD || act == ACT_FWD;
     const bool bwd = act == ACT_BWD;
     const bool lfa = UNIQ && act == ACT_LF;
+    const bool lf2 = lfa && u == 4;                      // first walk: LF of both rows of the match
     const uint64_t x1 = lfa ? wrow : (bwd ? k : kr), y = bwd ? kr : k;
     const int cc = bwd ? a : 3 - a;
-    const uint64_t x2 = x1 + (lfa ? 0ull : s);            // an LF step ranks one row
+    const uint64_t x2 = lf2 ? wrow2 : x1 + (lfa ? 0ull : s);   // a single LF step ranks one row
     const uint32_t L1 = line_of(x1), L2 = line_of(x2);
     const int o1 = (int)(x1 - (uint64_t)L1 * MBW_BPL), o2 = (int)(x2 - (uint64_t)L2 * MBW_BPL);
-    const bool two = ext && L1 != L2;                          // a second index line
-    const bool blk2 = ext && (two || (o1 >> 6) != (o2 >> 6));  // a second block slice
+    const bool two = (ext || lf2) && L1 != L2;                          // a second index line
+    const bool blk2 = (ext || lf2) && (two || (o1 >> 6) != (o2 >> 6));  // a second block slice
     // ---- the memory phase: everything the lane needs, issued together, waited for once
     const uint4 z4 = make_uint4(0, 0, 0, 0);
     const uint4 *l1p = ix.lines + (uint64_t)L1 * MBW_LINE_U4, *l2p = ix.lines + (uint64_t)L2 * MBW_LINE_U4;
@@ -513,16 +515,22 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
       const int cx = lfa ? bwt_from_block(ba, o1) : cc;
       if (!two) { h0b = h0a; h1b = h1a; }
       if (!blk2) bb = ba;
-      const SymMasks sm = sym_masks(cx);
+      const int cx2 = lf2 ? bwt_from_block(bb, o2) : cx;   // the second walk ranks its own row's symbol
+      const SymMasks sm = sym_masks(cx), sm2 = sym_masks(cx2);
       const uint32_t sb1 = 8 * (L1 >> MBW_SB_SHIFT), sb2 = 8 * (L2 >> MBW_SB_SHIFT);
       uint64_t E1, G1, E2, G2;
       rank_eg(h0a, h1a, ba, L1, o1, cx, sm, sbt[sb1 + cx], sbt[sb1 + 4 + cx], E1, G1);
-      rank_eg(h0b, h1b, bb, L2, o2, cx, sm, sbt[sb2 + cx], sbt[sb2 + 4 + cx], E2, G2);
+      rank_eg(h0b, h1b, bb, L2, o2, cx2, sm2, sbt[sb2 + cx2], sbt[sb2 + 4 + cx2], E2, G2);
       uint64_t nx, ny, ns;
       ext_update(E1, G1, E2, G2, cx, x1, lfa ? 0ull : s, y, ix.primary, scb[cx], nx, ny, ns);
-      if (lfa) {
+      if (lf2) {                                          // LF of both rows; the $ row maps to row 0
+        wrow = x1 == ix.primary ? 0ull : nx;
+        wrow2 = x2 == ix.primary ? 0ull : scb[cx2] + E2 - ((cx2 == 0 && x2 > ix.primary) ? 1ull : 0ull);
+        ++wcnt;
+        n_lines += two ? 2 : 1;
+      } else if (lfa) {                                   // second walk (never meets the $ row)
         wrow = nx;
-        if (u == 4) ++wcnt; else --wcnt;
+        --wcnt;
         ++n_lines;
       } else {
         n_lines += two ? 2 : 1;
@@ -548,6 +556,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
     if (UNIQ && act == ACT_SSA) {                       // the occurrence: p = S(row) + steps (mod n)
       uint64_t pp = mval + wcnt;
       if (pp >= ix.n) pp -= ix.n;
+      if (wmir) pp = tm - pp - (uint64_t)(j - i);       // the mirror of the reverse-complement match
       *tpl = pp;
       u = 5;
       ++n_lines;
