@@ -20,7 +20,7 @@ struct mbw_ctx {
   // seeding
   Buf codes, ascii, lens, offs, raw, subq, keys0, keys1, vals0, vals1, flag, idx, seeds, npos, posoff, xrows, pos, pos2,
       keep, kidx, temp, ctl, pwords, pnmask, woffs, nwords, wread, q1, q2, bf0, bf1, bp0, bp1, bid0, bid1, bk0, bk1, q1s,
-      q2s, sc0, sc1, pseed, pcnt, ppoff, pieces;
+      q2s, sc0, sc1, pseed, pcnt, ppoff, pieces, kpos;
   // mate-rescue prefilter (its own buffers, so that it leaves the last seeding result intact)
   Buf rc_lens, rc_wide, rc_offs, rc_ascii, rc_cand, rc_ctl, rc_hits, rc_flags, rc_pass;
   hipEvent_t ev[8];
@@ -33,7 +33,7 @@ struct mbw_ctx {
     return {&codes, &ascii, &lens, &offs, &raw, &subq, &keys0, &keys1, &vals0, &vals1, &flag, &idx, &seeds, &npos,
             &posoff, &xrows, &pos, &pos2, &keep, &kidx, &temp, &ctl, &pwords, &pnmask, &woffs, &nwords, &wread, &q1,
             &q2, &bf0, &bf1, &bp0, &bp1, &bid0, &bid1, &bk0, &bk1, &q1s, &q2s, &sc0, &sc1, &pseed, &pcnt, &ppoff,
-            &pieces, &rc_lens, &rc_wide, &rc_offs, &rc_ascii, &rc_cand, &rc_ctl, &rc_hits, &rc_flags, &rc_pass};
+            &pieces, &kpos, &rc_lens, &rc_wide, &rc_offs, &rc_ascii, &rc_cand, &rc_ctl, &rc_hits, &rc_flags, &rc_pass};
   }
 };
 

@@ -43,7 +43,9 @@ namespace {
 #define SEG_CHECK 1u
 struct Query { uint32_t read_id, qbeg, qend, l, c, rlen, woff_lo, woff_hi, send, flags, pad0, pad1; };   // 48 bytes
 #define INVALID_READ 0xFFFFFFFFu   // unused slot of a per-wave output chunk
-struct SeedRec { uint32_t read_id, qbeg, qend, flags; uint64_t k, kr, s; };
+// pos: the text position of the SMEM when the unique-match path found it (s = 1), else NO_POS
+#define NO_POS 0xFFFFFFFFFFFFFFFFull
+struct SeedRec { uint32_t read_id, qbeg, qend, flags; uint64_t k, kr, s, pos; };
 
 // control block (device): counters shared by the kernels of one call
 enum { C_WORK = 0, C_NSEEDS = 1, C_NSUBQ = 2, C_LINES = 3, C_STEPS = 4, C_KMER = 5, C_LFSTEPS = 6, C_SAREADS = 7,
@@ -250,26 +252,30 @@ __device__ __forceinline__ uint64_t wave_slot(bool em, uint64_t &ob, uint64_t &o
   return res;
 }
 
+// s carries KNOWN_POS when the unique-match path found the match's text position (in the lane's
+// text-position slot)
+#define KNOWN_POS (1ull << 63)
 struct Emit { uint32_t i, j; uint64_t k, kr, s; };
 struct WaveOut { uint64_t sb, se, qb, qe; };
 
 // this iteration's SMEMs (at most one per lane) and, in round 1, their re-seeding queries
 __device__ __forceinline__ void wave_emit(const SeedParams &P, int lane, bool em, uint32_t read_id, const Emit &e, WaveOut &wo,
-                                          uint32_t rlen, uint64_t woff) {
+                                          uint32_t rlen, uint64_t woff, const uint64_t *pos) {
   if (!__ballot(em)) return;
   const uint64_t slot = wave_slot(em, wo.sb, wo.se, &P.ctl[C_NSEEDS], lane);
   if (em && slot < P.seed_cap) {
     SeedRec r;
     r.read_id = read_id; r.qbeg = e.i; r.qend = e.j; r.flags = P.round == 2 ? MBW_SEED_ROUND2 : 0u;
-    r.k = e.k; r.kr = e.kr; r.s = e.s;
+    r.k = e.k; r.kr = e.kr; r.s = e.s & ~KNOWN_POS; r.pos = (e.s & KNOWN_POS) ? *pos : NO_POS;
     P.seeds[slot] = r;
   }
-  const bool rq = em && P.round == 1 && P.reseed && (int)(e.j - e.i) >= P.reseed_len && e.s <= (uint64_t)P.reseed_occ;
+  const uint64_t es = e.s & ~KNOWN_POS;
+  const bool rq = em && P.round == 1 && P.reseed && (int)(e.j - e.i) >= P.reseed_len && es <= (uint64_t)P.reseed_occ;
   if (!__ballot(rq)) return;
   const uint64_t qs = wave_slot(rq, wo.qb, wo.qe, &P.ctl[C_NSUBQ], lane);
   if (rq && qs < P.subq_cap) {
     Query q;
-    q.read_id = read_id; q.qbeg = e.i; q.qend = e.j; q.l = (e.j - e.i) / 2; q.c = (uint32_t)(e.s + 1);
+    q.read_id = read_id; q.qbeg = e.i; q.qend = e.j; q.l = (e.j - e.i) / 2; q.c = (uint32_t)(es + 1);
     q.rlen = rlen; q.woff_lo = (uint32_t)woff; q.woff_hi = (uint32_t)(woff >> 32);
     q.send = e.j; q.flags = 0;
     P.subq[qs] = q;
@@ -279,7 +285,7 @@ __device__ __forceinline__ void wave_emit(const SeedParams &P, int lane, bool em
 // mark the unused tail of the wave's output chunks invalid
 __device__ __forceinline__ void wave_close(const SeedParams &P, int lane, const WaveOut &wo) {
   for (uint64_t t = wo.sb + lane; t < wo.se; t += 64)
-    if (t < P.seed_cap) { SeedRec r; r.read_id = INVALID_READ; r.qbeg = r.qend = r.flags = 0; r.k = r.kr = r.s = 0; P.seeds[t] = r; }
+    if (t < P.seed_cap) { SeedRec r; r.read_id = INVALID_READ; r.qbeg = r.qend = r.flags = 0; r.k = r.kr = r.s = 0; r.pos = NO_POS; P.seeds[t] = r; }
   for (uint64_t t = wo.qb + lane; t < wo.qe; t += 64)
     if (t < P.subq_cap) {
       Query q; q.read_id = INVALID_READ; q.qbeg = q.qend = q.l = q.rlen = q.woff_lo = q.woff_hi = q.send = q.flags = 0; q.c = 1;
@@ -404,7 +410,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
           if (UNIQ && u == 7) {
             if (wcnt > 0) { act = ACT_LF; break; }
             if (SEG && segchk && i == (int)qbeg) { segchk = false; kr = wrow; s = 1; u = 8; continue; }
-            em = true; e.i = i; e.j = j; e.k = k; e.kr = wrow; e.s = 1;
+            em = true; e.i = i; e.j = j; e.k = k; e.kr = wrow; e.s = 1 | KNOWN_POS;
             if (j == (int)qend) { act = ACT_DONE; break; }
             u = 3; k = 0; kr = 0; s = ix.n; fresh = true;
             continue;
@@ -622,7 +628,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
       }
       st = ST_ACTIVE;
     }
-    wave_emit(P, lane, em, q_read_id(), e, wout, q_rlen(), q_wo());
+    wave_emit(P, lane, em, q_read_id(), e, wout, q_rlen(), q_wo(), tpl);
   }
   wave_close(P, lane, wout);
   if (lane == 0) atomicAdd(&P.ctl[C_WITER], (unsigned long long)n_iter);
@@ -797,7 +803,7 @@ __device__ __forceinline__ void plain_record(PlainCtx &C, int round, int i, int 
   if (slot < P.seed_cap) {
     SeedRec r;
     r.read_id = C.read_id; r.qbeg = (uint32_t)i; r.qend = (uint32_t)j; r.flags = round == 2 ? MBW_SEED_ROUND2 : 0u;
-    r.k = k; r.kr = kr; r.s = s;
+    r.k = k; r.kr = kr; r.s = s; r.pos = NO_POS;
     P.seeds[slot] = r;
   }
 }
@@ -846,7 +852,7 @@ __global__ void k_dedup_mark(const uint64_t *__restrict__ key, uint64_t ns, uint
 
 __global__ void k_seed_emit(const SeedRec *__restrict__ raw, const uint32_t *__restrict__ val, const uint32_t *__restrict__ flag,
                             const uint32_t *__restrict__ idx, uint64_t ns, uint64_t max_occ, mbw_seed_t *__restrict__ out,
-                            uint64_t *__restrict__ npos) {
+                            uint64_t *__restrict__ npos, uint64_t *__restrict__ kpos) {
   for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < ns; t += (uint64_t)gridDim.x * blockDim.x) {
     if (!flag[t]) continue;
     SeedRec r = raw[val[t]];
@@ -859,6 +865,7 @@ __global__ void k_seed_emit(const SeedRec *__restrict__ raw, const uint32_t *__r
     const uint32_t d = idx[t];
     out[d] = o;
     npos[d] = o.npos;
+    kpos[d] = r.pos;
   }
 }
 
@@ -869,17 +876,20 @@ __global__ void k_seed_posoff(mbw_seed_t *__restrict__ out, const uint64_t *__re
 
 // start row of every (seed, occurrence) pair: X[pos_off + i] = k + i.  A wave takes 64 seeds; a
 // seed with few rows is written by its own lane (neighbouring lanes write neighbouring runs), a
-// seed with many by all lanes of the wave (coalesced).
+// seed with many by all lanes of the wave (coalesced).  A seed whose position the unique-match
+// path already found gets it written to the output and NO_POS in X (locate skips it).
 #define EXPAND_LANE_MAX 8
-__global__ void __launch_bounds__(256) k_expand_rows(const mbw_seed_t *__restrict__ seeds, uint64_t ns, uint64_t *__restrict__ X) {
+__global__ void __launch_bounds__(256) k_expand_rows(const mbw_seed_t *__restrict__ seeds, const uint64_t *__restrict__ kpos,
+                                                     uint64_t ns, uint64_t *__restrict__ X, uint64_t *__restrict__ pos) {
   const int lane = threadIdx.x & 63;
   const uint64_t nwave = (uint64_t)gridDim.x * (blockDim.x >> 6);
   for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64; base < ns; base += nwave * 64) {
-    uint64_t k = 0, off = 0;
+    uint64_t k = 0, off = 0, kp = NO_POS;
     uint32_t np = 0;
-    if (base + lane < ns) { const mbw_seed_t sd = seeds[base + lane]; k = sd.k; off = sd.pos_off; np = sd.npos; }
+    if (base + lane < ns) { const mbw_seed_t sd = seeds[base + lane]; k = sd.k; off = sd.pos_off; np = sd.npos; kp = kpos[base + lane]; }
     const bool mine = np <= EXPAND_LANE_MAX;
-    if (mine)
+    if (mine && np == 1 && kp != NO_POS) { X[off] = NO_POS; pos[off] = kp; }
+    else if (mine)
       for (uint32_t q = 0; q < np; ++q) X[off + q] = k + q;
     uint64_t big = __ballot(!mine);
     while (big) {
@@ -980,7 +990,7 @@ __global__ void __launch_bounds__(256) k_locate_wave(IndexView ix, const uint64_
     if (ld) px = X[pw];
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     // ---- compute
-    if (ld) pre = P_READY;
+    if (ld) pre = px == NO_POS ? P_NONE : P_READY;   // NO_POS: located by the SMEM kernel already
     if (fin) {
       uint64_t p = steps + sv;
       if (p >= ix.n) p -= ix.n;
@@ -1474,10 +1484,12 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   GROW(c->seeds, (nu + 1) * sizeof(mbw_seed_t));
   GROW(c->npos, (nu + 2) * 8);
   GROW(c->posoff, (nu + 2) * 8);
+  GROW(c->kpos, (nu + 1) * 8);
   mbw_seed_t *seeds = (mbw_seed_t *)c->seeds.p;
   uint64_t *npos = (uint64_t *)c->npos.p, *posoff = (uint64_t *)c->posoff.p;
   if (ns) {
-    k_seed_emit<<<grid_for(ns), 256, 0, st>>>((const SeedRec *)c->raw.p, dv.Current(), flag, idx, ns, (uint64_t)max_occ, seeds, npos);
+    k_seed_emit<<<grid_for(ns), 256, 0, st>>>((const SeedRec *)c->raw.p, dv.Current(), flag, idx, ns, (uint64_t)max_occ, seeds, npos,
+                                              (uint64_t *)c->kpos.p);
     TRY(hipGetLastError());
   }
   uint64_t n_pos = 0;
@@ -1503,7 +1515,8 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
       TRY(hipGetLastError());
     } else {
       GROW(c->xrows, (n_pos + 1) * 8);
-      k_expand_rows<<<grid_for((nu + 63) / 64 * 64 / 4, 256, 65536u), 256, 0, st>>>(seeds, nu, (uint64_t *)c->xrows.p);
+      k_expand_rows<<<grid_for((nu + 63) / 64 * 64 / 4, 256, 65536u), 256, 0, st>>>(seeds, (const uint64_t *)c->kpos.p, nu,
+                                                                                     (uint64_t *)c->xrows.p, (uint64_t *)c->pos.p);
       TRY(hipGetLastError());
       const int grid = persistent_grid((const void *)k_locate_wave, 256, 0, c->n_cu, o.blocks_per_cu);
       TRY(hipEventRecord(c->ev[3], st));
