@@ -835,19 +835,21 @@ __global__ void __launch_bounds__(256) k_smem_plain(IndexView ix, SeedParams P) 
 // seeds: sort keys, dedup, counts
 
 // sort key (read, qbeg, qend); unused slots (read_id INVALID_READ) get key n_reads << 32, after all
-__global__ void k_seed_keys(const SeedRec *__restrict__ raw, uint64_t ns, uint64_t n_reads, uint64_t *__restrict__ key,
+// sort key (read, qbeg, qend) with qb bits for each offset (qb = bit length of the longest read);
+// unused slots sort last as n_reads << 2 qb
+__global__ void k_seed_keys(const SeedRec *__restrict__ raw, uint64_t ns, uint64_t n_reads, int qb, uint64_t *__restrict__ key,
                             uint32_t *__restrict__ val) {
   for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < ns; t += (uint64_t)gridDim.x * blockDim.x) {
     SeedRec r = raw[t];
-    key[t] = r.read_id == INVALID_READ ? (n_reads << 32)
-                                       : (((uint64_t)r.read_id << 32) | ((uint64_t)r.qbeg << 16) | (uint64_t)r.qend);
+    key[t] = r.read_id == INVALID_READ ? (n_reads << (2 * qb))
+                                       : (((uint64_t)r.read_id << (2 * qb)) | ((uint64_t)r.qbeg << qb) | (uint64_t)r.qend);
     val[t] = (uint32_t)t;
   }
 }
 
-__global__ void k_dedup_mark(const uint64_t *__restrict__ key, uint64_t ns, uint64_t n_reads, uint32_t *__restrict__ flag) {
+__global__ void k_dedup_mark(const uint64_t *__restrict__ key, uint64_t ns, uint64_t n_reads, int qb, uint32_t *__restrict__ flag) {
   for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < ns; t += (uint64_t)gridDim.x * blockDim.x)
-    flag[t] = (key[t] < (n_reads << 32) && (t == 0 || key[t] != key[t - 1])) ? 1u : 0u;
+    flag[t] = (key[t] < (n_reads << (2 * qb)) && (t == 0 || key[t] != key[t - 1])) ? 1u : 0u;
 }
 
 __global__ void k_seed_emit(const SeedRec *__restrict__ raw, const uint32_t *__restrict__ val, const uint32_t *__restrict__ flag,
@@ -1463,15 +1465,18 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   uint32_t *flag = (uint32_t *)c->flag.p, *idx = (uint32_t *)c->idx.p;
   uint64_t nu = 0;
   if (ns) {
-    k_seed_keys<<<grid_for(ns), 256, 0, st>>>((const SeedRec *)c->raw.p, ns, n_reads, (uint64_t *)c->keys0.p, (uint32_t *)c->vals0.p);
+    int qb = 1;       // bits of an offset within a read (offsets run to the longest read's length)
+    while ((1ull << qb) <= maxlen) ++qb;
+    k_seed_keys<<<grid_for(ns), 256, 0, st>>>((const SeedRec *)c->raw.p, ns, n_reads, qb, (uint64_t *)c->keys0.p,
+                                               (uint32_t *)c->vals0.p);
     TRY(hipGetLastError());
-    int hibit = 33;   // every key < (n_reads + 1) << 32
-    while (hibit < 64 && (1ull << (hibit - 32)) <= n_reads) ++hibit;
+    int hibit = 2 * qb + 1;   // every key < (n_reads + 1) << 2 qb
+    while (hibit < 64 && (1ull << (hibit - 2 * qb)) <= n_reads) ++hibit;
     if (ns > 1) {
       r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceRadixSort::SortPairs(tp, tb, dk, dv, ns, 0, hibit, st); });
       if (r) return r;
     }
-    k_dedup_mark<<<grid_for(ns), 256, 0, st>>>(dk.Current(), ns, n_reads, flag);
+    k_dedup_mark<<<grid_for(ns), 256, 0, st>>>(dk.Current(), ns, n_reads, qb, flag);
     TRY(hipGetLastError());
     r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, flag, idx, ns, st); });
     if (r) return r;
