@@ -341,7 +341,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the seeding path is "
-              "data-parallel over reads with a replicated index; multi-GPU runs are not part of this build.",
+              "data-parallel over reads with a replicated index; this benchmark runs on one GPU.",
               file=sys.stderr)
         sys.exit(2)
 
