@@ -308,8 +308,10 @@ __device__ __forceinline__ void wave_close(const SeedParams &P, int lane, const 
 // extension is finished by comparing read and text directly, which gives the same end j.  The
 // interval of the result keeps k (the same single suffix) and s = 1; k' is the row of the suffix
 // at the mirrored position m - p - (j - i) (T without $ is its own reverse complement), found from
-// the nearest inverse-SA sample by LF steps.  Stages: 4 = LF walk from row k to a sampled row
-// (Algorithm 2), 5 = text comparison, 6 = inverse-SA sample read, 7 = LF walk to k'.
+// the nearest inverse-SA sample by LF steps.  Stages: 4 = LF walks from row k and from the
+// reverse-complement row k' in step until one reaches a sampled row (Algorithm 2; the second gives
+// the mirror of p), 5 = text comparison, 6 = inverse-SA sample read, 7 = LF walk to k'.  The seed
+// carries p to locate, which does not walk it again.
 #define STAGE_WORDS 5   // staged reads of up to 160 bases
 #define SMEM_WAVES 4    // waves per block
 enum { ACT_DONE = 0, ACT_KMER = 1, ACT_BWD = 2, ACT_FWD = 3, ACT_LF = 4, ACT_SSA = 5, ACT_TEXT = 6, ACT_ISA = 7 };
