@@ -271,6 +271,13 @@ int mbw_rescue_filter(mbw_ctx *ctx, const uint8_t *reads, const uint32_t *length
  * may be NULL). */
 int mbw_rescue_download(mbw_ctx *ctx, const mbw_rescue_result *res, mbw_rescue_hit_t *hits, uint32_t *pass);
 
+/* ---- debug -----------------------------------------------------------------------------------
+ * Cap the device work space every context may hold (bytes; 0 = no cap, the default).  A call that
+ * would grow a context beyond it fails with MBW_E_NOMEM and leaves the context usable; for tests of
+ * allocation failure (a serving batch that fails reports the error to each of its requests and
+ * the server goes on).  Process-wide. */
+int mbw_debug_set_mem_limit(uint64_t bytes);
+
 /* ---- diagnostics (not part of the seeding path) ----------------------------------------------
  * mbw_probe_copy: streams `bytes` bytes (>= 4096) from one buffer to another once; *ms = kernel time.
  *   Used to calibrate profiler byte counters against a known transfer.

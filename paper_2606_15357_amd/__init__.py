@@ -37,7 +37,7 @@ EXPORTS = ["mbw_strerror", "mbw_last_error", "mbw_index_build", "mbw_index_save"
            "mbw_index_free", "mbw_index_info", "mbw_index_device_arrays", "mbw_ctx_create", "mbw_ctx_free",
            "mbw_seed", "mbw_result_download", "mbw_pos_to_ref", "mbw_probe_copy", "mbw_probe_gather", "mbw_tune",
            "mbw_result_download_pieces", "mbw_serve_open", "mbw_serve_submit", "mbw_serve_wait", "mbw_serve_release", "mbw_serve_stats",
-           "mbw_serve_close", "mbw_rescue_filter", "mbw_rescue_download"]
+           "mbw_serve_close", "mbw_rescue_filter", "mbw_rescue_download", "mbw_debug_set_mem_limit"]
 
 
 class MbwError(RuntimeError):
@@ -144,6 +144,7 @@ def load_library():
     L.mbw_serve_close.restype = None
     L.mbw_rescue_filter.argtypes = [vp, vp, vp, u64, vp, u64, C.POINTER(RescueOpts), vp, C.POINTER(RescueResult)]
     L.mbw_rescue_download.argtypes = [vp, C.POINTER(RescueResult), vp, vp]
+    L.mbw_debug_set_mem_limit.argtypes = [u64]
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
@@ -385,6 +386,12 @@ class Context:
             pass
 
 
+def set_mem_limit(nbytes: int) -> None:
+    """Debug: cap the device work space of every context (0 = no cap); for allocation-failure
+    tests."""
+    _check(load_library().mbw_debug_set_mem_limit(int(nbytes)))
+
+
 def probe_copy(nbytes: int = 1 << 30, device: int = 0) -> float:
     """Kernel time (ms) of one streaming copy of `nbytes` bytes (profiler counter calibration)."""
     L = load_library()
@@ -452,7 +459,11 @@ class Server:
         rc = self._lib.mbw_serve_wait(self._h, int(ticket), int(timeout_ms), C.byref(r))
         if rc == MBW_E_BUSY:
             return None
-        _check(rc)
+        if rc != MBW_OK:
+            err = MbwError(rc, self._lib.mbw_last_error().decode(errors="replace"))
+            if release:   # the request failed (its whole batch did): free it and report
+                self._lib.mbw_serve_release(self._h, int(ticket))
+            raise err
         seeds = np.zeros(r.n_seeds, dtype=SEED_DTYPE)
         pos = np.zeros(r.n_pos, dtype=np.uint64)
         if r.n_seeds:

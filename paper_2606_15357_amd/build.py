@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmbw.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["index_build.hip", "seed.hip", "probe.hip", "serve.hip", "rescue.hip"]
+SOURCES = ["index_build.hip", "seed.hip", "probe.hip", "serve.hip", "rescue.hip", "debug.hip"]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
          # keep the compiler from forming packed FP32 instructions
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -37,13 +38,25 @@ struct mbw_ctx {
   }
 };
 
+// cap on the device work space of every context, 0 = none (mbw_debug_set_mem_limit)
+extern std::atomic<unsigned long long> g_mbw_mem_limit;
+
 // Buffers grow on the call's stream with the stream-ordered allocator, so that a context growing
-// its work space does not wait for work of other contexts on other streams.
+// its work space does not wait for work of other contexts on other streams.  A growth the cap
+// refuses leaves the buffer as it was.
 static inline int grow(mbw_ctx *c, mbw_ctx::Buf &b, size_t bytes) {
   if (bytes == 0) bytes = 16;
   if (b.bytes >= bytes) return 0;
-  if (b.p) { (void)hipFreeAsync(b.p, c->cur); b.p = nullptr; b.bytes = 0; }
   size_t want = bytes + bytes / 2 + 256;
+  if (const unsigned long long lim = g_mbw_mem_limit.load(std::memory_order_relaxed)) {
+    unsigned long long used = 0;
+    for (auto *x : c->buffers()) used += x->bytes;
+    if (used - b.bytes + want > lim) {
+      mbw_set_error("device work space over the debug cap (" + std::to_string(lim) + " bytes)");
+      return MBW_E_NOMEM;
+    }
+  }
+  if (b.p) { (void)hipFreeAsync(b.p, c->cur); b.p = nullptr; b.bytes = 0; }
   hipError_t e = hipMallocAsync(&b.p, want, c->cur);
   if (e != hipSuccess) {
     b.p = nullptr;

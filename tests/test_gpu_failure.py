@@ -1,0 +1,70 @@
+"""Allocation failure, forced from the host through the debug cap on context work space.
+
+* mbw_seed returns MBW_E_NOMEM when its work space would exceed the cap, and the same context
+  seeds correctly (bit-exact against the oracle) once the cap is lifted;
+* the rescue prefilter fails the same way and recovers;
+* a serving batch that fails reports the error to its request; the server then serves the next
+  request correctly.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from mbw_helpers import compare_with_oracle
+
+mbw = pytest.importorskip("paper_2606_15357_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def small():
+    ref = synth.workload_reference("small_1mbp")
+    ox = oracle.OracleIndex(ref.codes, sa_rate=8)
+    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=10)
+    yield ref, ox, idx
+    idx.free()
+
+
+def test_seed_and_rescue_fail_then_recover(small):
+    ref, ox, idx = small
+    reads = synth.reads_fixed(ref, 3000, 150, True, p_sub=0.005, p_indel=0.0005, seed=71)
+    cands, _ = synth.rescue_candidates(reads, len(ref), decoys=True, seed=72)
+    ctx = mbw.Context(idx)
+    try:
+        mbw.set_mem_limit(1 << 20)
+        with pytest.raises(mbw.MbwError) as e:
+            ctx.seed(reads.seq, reads.lengths)
+        assert e.value.code == mbw.MBW_E_NOMEM
+        with pytest.raises(mbw.MbwError) as e:
+            ctx.rescue(reads.seq, reads.lengths, cands)
+        assert e.value.code == mbw.MBW_E_NOMEM
+    finally:
+        mbw.set_mem_limit(0)
+    out = ctx.seed(reads.seq, reads.lengths)
+    s, p = out.download()
+    compare_with_oracle(s, p, ox.seed(reads.seq, reads.offsets))
+    hits, passed = ctx.rescue(reads.seq, reads.lengths, cands).download()
+    mh, bt = oracle.rescue(ref.codes, reads.seq, reads.offsets, cands["read_id"], cands["win_beg"], cands["win_len"])
+    assert np.array_equal(hits["max_hits"], mh) and np.array_equal(hits["best_t"], bt)
+    ctx.free()
+
+
+def test_serving_isolates_a_failed_batch(small):
+    ref, ox, idx = small
+    big = synth.reads_fixed(ref, 2000, 150, False, seed=73)
+    ok = synth.reads_fixed(ref, 300, 150, False, seed=74)
+    srv = mbw.Server(idx, n_workers=1)
+    try:
+        mbw.set_mem_limit(1 << 20)
+        t = srv.submit(big.seq, big.lengths)
+        with pytest.raises(mbw.MbwError) as e:
+            srv.wait(t)
+        assert e.value.code == mbw.MBW_E_NOMEM
+    finally:
+        mbw.set_mem_limit(0)
+    t = srv.submit(ok.seq, ok.lengths)
+    s, p, info = srv.wait(t)
+    compare_with_oracle(s, p, ox.seed(ok.seq, ok.offsets))
+    srv.close()
