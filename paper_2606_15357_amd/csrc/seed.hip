@@ -26,6 +26,8 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <cstdio>
+#include <cstdlib>
 
 #include "ctx.h"
 #include "mbw_internal.h"
@@ -1171,6 +1173,12 @@ static int launch_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const Read
   return 0;
 }
 
+// MBW_TRACE=1: one JSON line on stderr per SMEM launch and per mbw_seed call
+static bool trace_on() {
+  static const bool on = getenv("MBW_TRACE") && getenv("MBW_TRACE")[0] == '1';
+  return on;
+}
+
 static int run_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const ReadWords &R, const mbw_seed_opts &o, bool staged,
                     hipStream_t st) {
   if (P.n_queries == 0) return 0;
@@ -1190,6 +1198,9 @@ static int run_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const ReadWor
   TRY(hipEventElapsedTime(&ms, c->ev[1], c->ev[2]));
   c->ms_smem += ms;
   c->n_smem_launches++;
+  if (trace_on())
+    fprintf(stderr, "{\"mbw\": \"smem_launch\", \"round\": %d, \"staged\": %d, \"queries\": %llu, \"chunk\": %u, \"ms\": %.3f}\n",
+            P.round, (int)staged, (unsigned long long)P.n_queries, P.chunk, ms);
   return 0;
 }
 
@@ -1606,6 +1617,14 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   out->max_chain = c->host_ctl[C_MAXCHAIN];
   out->n_pieces = n_pieces;
   out->pieces = n_pieces ? (const mbw_piece_t *)c->pieces.p : nullptr;
+  if (trace_on())
+    fprintf(stderr, "{\"mbw\": \"seed\", \"reads\": %llu, \"seeds\": %llu, \"positions\": %llu, \"pieces\": %llu, "
+            "\"smem_launches\": %d, \"ms_smem\": %.3f, \"ms_locate\": %.3f, \"ms_total\": %.3f, \"lines_smem\": %llu, "
+            "\"lines_locate\": %llu, \"wave_iters\": %llu, \"lane_iters\": %llu, \"max_chain\": %llu}\n",
+            (unsigned long long)n_reads, (unsigned long long)nu, (unsigned long long)n_pos, (unsigned long long)n_pieces,
+            out->n_smem_launches, out->ms_smem, out->ms_locate, out->ms_total, (unsigned long long)out->lines_smem,
+            (unsigned long long)out->lines_locate, (unsigned long long)out->wave_iters, (unsigned long long)out->lane_iters,
+            (unsigned long long)out->max_chain);
   return MBW_OK;
 }
 
