@@ -409,7 +409,7 @@ static void seed_query(const orc_index *ix, const uint8_t *P, uint64_t m, const 
         find_smems(ix, P + s.qbeg, s.qend - s.qbeg, (int)((s.qend - s.qbeg) / 2), s.s + 1, o, s.qbeg, out, lc);
     }
   }
-  qsort(out->v, out->n, sizeof(smem_t), cmp_smem);
+  if (out->n > 1) qsort(out->v, out->n, sizeof(smem_t), cmp_smem);
   uint64_t w = 0;
   for (uint64_t t = 0; t < out->n; ++t)
     if (w == 0 || cmp_smem(&out->v[w - 1], &out->v[t]) != 0) out->v[w++] = out->v[t];
