@@ -392,6 +392,7 @@ def main():
         m = min(n_reads, 4_000_000)
         best = ctx.tune(dseq[: int(reads.offsets[m])], dlen[:m], stream=stream)
         tune_ms = best.pop("ms")
+        best.pop("cached", None)
         if args.no_unique:
             best["unique_ext"] = False
         sched = best

@@ -10,6 +10,8 @@ handed to the library) and ``stream`` may be a ``torch.cuda.Stream``.
 from __future__ import annotations
 
 import ctypes as C
+import hashlib
+import json
 import os
 from dataclasses import dataclass
 
@@ -149,6 +151,30 @@ def load_library():
         getattr(L, name)
     _lib = L
     return L
+
+
+_lib_id = None
+
+
+def _library_id() -> str:
+    """Hash of the built library file (tuner cache entries of another build do not apply)."""
+    global _lib_id
+    if _lib_id is None:
+        h = hashlib.sha1()
+        with open(LIB_PATH, "rb") as fh:
+            for chunk in iter(lambda: fh.read(1 << 20), b""):
+                h.update(chunk)
+        _lib_id = h.hexdigest()[:16]
+    return _lib_id
+
+
+def _read_json(path: str) -> dict:
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+        return d if isinstance(d, dict) else {}
+    except (OSError, ValueError):
+        return {}
 
 
 def _check(rc):
@@ -359,10 +385,21 @@ class Context:
         return RescueOutput(res.n_cands, res.n_pass, res.hits or 0, res.pass_ or 0, res.ms_kernel, res.ms_total,
                             res, self)
 
-    def tune(self, reads, lengths, min_seed_len: int = 19, max_occ: int = 500, stream=None, **base) -> dict:
+    def tune(self, reads, lengths, min_seed_len: int = 19, max_occ: int = 500, stream=None, cache=None,
+             **base) -> dict:
         """Time candidate schedules on this batch (``mbw_tune``); returns the fastest as keyword
-        arguments for :meth:`seed` plus ``ms`` (its device time)."""
+        arguments for :meth:`seed` plus ``ms`` (its device time).  With ``cache`` (a JSON file
+        path) the pick is stored under a key made of the library build, the index parameters, the
+        seeding parameters and a coarse profile of the batch's read lengths (log2 buckets of the
+        median and the longest read); a later call with the same key returns the stored pick
+        without timing anything (``cached`` is then True)."""
         n = int(lengths.numel() if hasattr(lengths, "numel") else len(lengths))
+        key = None
+        if cache:
+            key = self._tune_key(lengths, min_seed_len, max_occ, base)
+            stored = _read_json(cache)
+            if key in stored:
+                return dict(stored[key], cached=True)
         b = SeedOpts(int(base.get("min_occ", 1)), int(bool(base.get("reseed", True))), int(base.get("reseed_len", 38)),
                      int(base.get("reseed_occ", 10)), int(base.get("bs_role", 0)), KERNEL_COOP,
                      int(bool(base.get("use_kmer", True))), 0, 0, 1, 0, 0)
@@ -371,8 +408,29 @@ class Context:
         _check(self._lib.mbw_tune(self._h, _ptr(reads) if n else None, _ptr(lengths) if n else None, n,
                                   int(min_seed_len), int(max_occ), C.byref(b), _stream_handle(stream), C.byref(best),
                                   C.byref(ms)))
-        return dict(stage=not best.no_stage, seg_len=best.seg_len, blocks_per_cu=best.blocks_per_cu,
-                    unique_ext=bool(best.unique_ext), ms=ms.value)
+        res = dict(stage=not best.no_stage, seg_len=best.seg_len, blocks_per_cu=best.blocks_per_cu,
+                   unique_ext=bool(best.unique_ext), ms=ms.value)
+        if cache:
+            stored = _read_json(cache)
+            stored[key] = res
+            tmp = f"{cache}.tmp{os.getpid()}"
+            with open(tmp, "w") as fh:
+                json.dump(stored, fh, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return dict(res, cached=False)
+
+    def _tune_key(self, lengths, min_seed_len, max_occ, base) -> str:
+        if hasattr(lengths, "cpu"):
+            lengths = lengths.cpu().numpy()
+        lens = np.asarray(lengths).astype(np.int64)
+        med = int(np.median(lens)) if lens.size else 0
+        mx = int(lens.max()) if lens.size else 0
+        info = self.index.info()
+        parts = [_library_id(), f"n={info['n']}", f"r={info['sa_sample']}", f"K={info['kmer_k']}",
+                 f"ri={info['isa_sample']}", f"bs={info['bisulfite']}", f"l={min_seed_len}", f"max_occ={max_occ}",
+                 "opts=" + ",".join(f"{k}={base[k]}" for k in sorted(base)),
+                 f"median_log2={med.bit_length()}", f"max_log2={mx.bit_length()}"]
+        return "|".join(parts)
 
     def free(self):
         if self._h:

@@ -52,11 +52,31 @@ def test_tune_picks_a_valid_schedule(small):
     best = ctx.tune(reads.seq, reads.lengths)
     assert best["seg_len"] in (128, 256, 1024) and best["blocks_per_cu"] in (0, 2) and best["ms"] > 0
     ms = best.pop("ms")
+    assert best.pop("cached") is False
     out = ctx.seed(reads.seq, reads.lengths, **best)
     seeds, pos = out.download()
     compare_with_oracle(seeds, pos, ox.seed(reads.seq, reads.offsets))
     ctx.free()
     assert ms < 1e5
+
+
+def test_tune_cache(small, tmp_path):
+    """A stored pick is returned for the same index, parameters and read-length profile without
+    timing; another length profile is tuned and stored beside it."""
+    ref, ox, idx = small
+    short = synth.reads_fixed(ref, 3000, 150, False, seed=13)
+    long_ = synth.reads_uniform_len(ref, 2000, 400, 2000, seed=14)
+    path = str(tmp_path / "tune.json")
+    ctx = mbw.Context(idx)
+    a = ctx.tune(short.seq, short.lengths, cache=path)
+    b = ctx.tune(short.seq, short.lengths, cache=path)
+    assert a["cached"] is False and b["cached"] is True
+    assert {k: a[k] for k in a if k != "cached"} == {k: b[k] for k in b if k != "cached"}
+    c = ctx.tune(long_.seq, long_.lengths, cache=path)
+    assert c["cached"] is False
+    import json
+    assert len(json.load(open(path))) == 2
+    ctx.free()
 
 
 def test_serve_alone_and_in_a_mix(small):
