@@ -122,7 +122,11 @@ typedef struct {
   int kernel;         /* MBW_KERNEL_COOP (default: persistent wave kernels) or MBW_KERNEL_PLAIN
                          (one read per thread running the serial algorithm; the baseline) */
   int use_kmer;       /* use the index's k-mer table (wave kernels) */
-  int blocks_per_cu;  /* persistent grid size per compute unit (0 = occupancy limit) */
+  int blocks_per_cu;  /* persistent grid size per compute unit (wave kernels): > 0 that many (at
+                         most the occupancy limit), -1 the occupancy limit, 0 sized per launch by
+                         its work (about one block per CU per 1,200 round-1 queries, 4,000
+                         round-2 queries or 24,000 positions to locate, up to the occupancy
+                         limit: small batches run faster on fewer waves) */
   int no_stage;       /* 1: do not stage reads of <= 160 bases in LDS */
   int unique_ext;     /* 1: when the index holds the text and inverse-SA samples, a forward
                          extension whose interval has s = 1 continues by comparing the read with
@@ -201,8 +205,8 @@ int mbw_result_download(mbw_ctx *ctx, const mbw_result *res, mbw_seed_t *seeds, 
 int mbw_result_download_pieces(mbw_ctx *ctx, const mbw_result *res, mbw_piece_t *pieces);
 
 /* Autotuner for the wave kernels: runs mbw_seed on this batch with candidate schedules (length
- * binning on or off, segment lengths 128/256/1024, persistent blocks per CU at the occupancy limit
- * or 2, unique-match extension on or off), each once untimed and once timed, and writes the
+ * binning on or off, segment lengths 128/256/1024, persistent blocks per CU sized by the work or at
+ * the occupancy limit, unique-match extension on or off), each once untimed and once timed, and writes the
  * fastest to *best (other fields copied from *base, or the defaults when base is NULL) and its
  * device time to *best_ms.  Every candidate yields the same seeds.  Blocking; uses ctx's buffers
  * (its last result is overwritten).  Errors: as mbw_seed. */

@@ -295,6 +295,18 @@ __device__ __forceinline__ void wave_close(const SeedParams &P, int lane, const 
     }
 }
 
+// Per-launch statistics: summed (or maximised) over the wave and added to the control block by
+// lane 0, and only when not zero: same-address device-scope atomics serialise, and a persistent
+// grid ends thousands of waves, most of them idle on a small batch, at about the same time.
+__device__ __forceinline__ void wave_stat(unsigned long long *dst, uint64_t v, bool is_max = false) {
+  unsigned long long x = v;
+  for (int d = 32; d >= 1; d >>= 1) {
+    const unsigned long long o = __shfl_xor(x, d);
+    x = is_max ? (o > x ? o : x) : x + o;
+  }
+  if ((threadIdx.x & 63) == 0 && x) { if (is_max) atomicMax(dst, x); else atomicAdd(dst, x); }
+}
+
 // ---------------------------------------------------------------------------------------------
 // SMEM kernel, wave schedule (Algorithm 3 per lane; persistent).
 //
@@ -635,16 +647,12 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
     wave_emit(P, lane, em, q_read_id(), e, wout, q_rlen(), q_wo(), tpl);
   }
   wave_close(P, lane, wout);
-  if (lane == 0) atomicAdd(&P.ctl[C_WITER], (unsigned long long)n_iter);
-  if (lane == 0) atomicAdd(&P.ctl[C_LITER], (unsigned long long)n_busy);
-  for (int d = 32; d >= 1; d >>= 1) {
-    const uint32_t o = (uint32_t)__shfl_xor((int)max_chain, d);
-    max_chain = o > max_chain ? o : max_chain;
-  }
-  if (lane == 0) atomicMax(&P.ctl[C_MAXCHAIN], (unsigned long long)max_chain);
-  atomicAdd(&P.ctl[C_LINES], (unsigned long long)(n_lines + n_kmer));
-  atomicAdd(&P.ctl[C_STEPS], (unsigned long long)n_steps);
-  atomicAdd(&P.ctl[C_KMER], (unsigned long long)n_kmer);
+  // n_iter and n_busy are per wave (the same in every lane); the rest are per lane
+  if ((threadIdx.x & 63) == 0 && n_iter) { atomicAdd(&P.ctl[C_WITER], (unsigned long long)n_iter); atomicAdd(&P.ctl[C_LITER], (unsigned long long)n_busy); }
+  wave_stat(&P.ctl[C_MAXCHAIN], max_chain, true);
+  wave_stat(&P.ctl[C_LINES], (uint64_t)n_lines + n_kmer);
+  wave_stat(&P.ctl[C_STEPS], n_steps);
+  wave_stat(&P.ctl[C_KMER], n_kmer);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1014,8 +1022,8 @@ __global__ void __launch_bounds__(256) k_locate_wave(IndexView ix, const uint64_
       ++steps; ++lines; ++lf;
     }
   }
-  atomicAdd(&ctl[C_LINES_LOC], (unsigned long long)lines);
-  atomicAdd(&ctl[C_LFSTEPS], (unsigned long long)lf);
+  wave_stat(&ctl[C_LINES_LOC], lines);
+  wave_stat(&ctl[C_LFSTEPS], lf);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1149,26 +1157,53 @@ extern "C" void mbw_ctx_free(mbw_ctx *c) {
   delete c;
 }
 
-static int persistent_grid(const void *kern, int block, size_t lds, int n_cu, int per_cu_req) {
+// Persistent grid: blocks per CU as requested (> 0), the occupancy limit (< 0), or (0) sized by
+// the launch's work, `per_block` items per block and CU, up to the occupancy limit.  A small batch
+// is bound by its longest chains of dependent loads: more waves per SIMD only slow each one
+// (they share the SIMD) and add same-address atomics on the work counter, which serialise.
+static int persistent_grid(const void *kern, int block, size_t lds, int n_cu, int per_cu_req, uint64_t work,
+                           uint64_t per_block) {
   int per = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, block, lds) != hipSuccess || per < 1) per = 4;
-  if (per_cu_req > 0 && per_cu_req < per) per = per_cu_req;
+  int want = per_cu_req;
+  if (want == 0) {
+    const uint64_t unit = per_block * (uint64_t)n_cu;
+    want = (int)std::min<uint64_t>((uint64_t)per, std::max<uint64_t>(1, (work + unit - 1) / unit));
+  }
+  if (want > 0 && want < per) per = want;
   return per * n_cu;
 }
 
+// automatic sizing (blocks_per_cu = 0): items per block and CU, measured at 3.1 Gbp on 150 bp
+// reads (a round-2 query costs less than a round-1 one: most fail their first test)
+#define AUTO_QUERIES_R1 1200
+#define AUTO_QUERIES_R2 4000
+#define AUTO_ROWS_LOCATE 24000
+
 template <bool STAGED, bool UNIQ>
-static void launch_wave(mbw_ctx *c, const IndexView &v, SeedParams &P, const ReadWords &R, const mbw_seed_opts &o,
-                        hipStream_t st) {
-  const int grid = persistent_grid((const void *)k_smem_wave<STAGED, UNIQ>, 64 * SMEM_WAVES, 0, c->n_cu, o.blocks_per_cu);
-  k_smem_wave<STAGED, UNIQ><<<grid, 64 * SMEM_WAVES, 0, st>>>(v, P, R);
+static int wave_grid(mbw_ctx *c, const SeedParams &P, const mbw_seed_opts &o) {
+  return persistent_grid((const void *)k_smem_wave<STAGED, UNIQ>, 64 * SMEM_WAVES, 0, c->n_cu, o.blocks_per_cu,
+                         P.n_queries, P.round == 1 ? AUTO_QUERIES_R1 : AUTO_QUERIES_R2);
 }
 
-static int launch_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const ReadWords &R, const mbw_seed_opts &o, bool staged,
-                       hipStream_t st) {
+static int smem_grid(mbw_ctx *c, const SeedParams &P, const mbw_seed_opts &o, bool staged) {
   const bool uniq = P.uniq && P.round == 1;
+  if (staged) return uniq ? wave_grid<true, true>(c, P, o) : wave_grid<true, false>(c, P, o);
+  return uniq ? wave_grid<false, true>(c, P, o) : wave_grid<false, false>(c, P, o);
+}
+
+static int launch_smem(const IndexView &v, SeedParams &P, const ReadWords &R, const mbw_seed_opts &o, bool staged,
+                       int grid, hipStream_t st) {
+  const bool uniq = P.uniq && P.round == 1;
+  const int bs = 64 * SMEM_WAVES;
   if (o.kernel == MBW_KERNEL_PLAIN) k_smem_plain<<<grid_for(P.n_queries, 256), 256, 0, st>>>(v, P);
-  else if (staged) { if (uniq) launch_wave<true, true>(c, v, P, R, o, st); else launch_wave<true, false>(c, v, P, R, o, st); }
-  else { if (uniq) launch_wave<false, true>(c, v, P, R, o, st); else launch_wave<false, false>(c, v, P, R, o, st); }
+  else if (staged) {
+    if (uniq) k_smem_wave<true, true><<<grid, bs, 0, st>>>(v, P, R);
+    else k_smem_wave<true, false><<<grid, bs, 0, st>>>(v, P, R);
+  } else {
+    if (uniq) k_smem_wave<false, true><<<grid, bs, 0, st>>>(v, P, R);
+    else k_smem_wave<false, false><<<grid, bs, 0, st>>>(v, P, R);
+  }
   TRY(hipGetLastError());
   return 0;
 }
@@ -1182,15 +1217,16 @@ static bool trace_on() {
 static int run_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const ReadWords &R, const mbw_seed_opts &o, bool staged,
                     hipStream_t st) {
   if (P.n_queries == 0) return 0;
+  const int grid = o.kernel == MBW_KERNEL_PLAIN ? 0 : smem_grid(c, P, o, staged);
   // at least ~8 grabs per wave of the persistent grid, so that long queries (queued longest
   // first) spread over the whole chip
   {
-    const uint64_t waves = (uint64_t)c->n_cu * 16;
+    const uint64_t waves = (uint64_t)std::max(grid, 1) * SMEM_WAVES;
     uint64_t ch = P.n_queries / (waves * 8);
     P.chunk = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(WORK_CHUNK, ch));
   }
   TRY(hipEventRecord(c->ev[1], st));
-  int r = launch_smem(c, v, P, R, o, staged, st);
+  int r = launch_smem(v, P, R, o, staged, grid, st);
   if (r) return r;
   TRY(hipEventRecord(c->ev[2], st));
   TRY(hipEventSynchronize(c->ev[2]));
@@ -1199,8 +1235,8 @@ static int run_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const ReadWor
   c->ms_smem += ms;
   c->n_smem_launches++;
   if (trace_on())
-    fprintf(stderr, "{\"mbw\": \"smem_launch\", \"round\": %d, \"staged\": %d, \"queries\": %llu, \"chunk\": %u, \"ms\": %.3f}\n",
-            P.round, (int)staged, (unsigned long long)P.n_queries, P.chunk, ms);
+    fprintf(stderr, "{\"mbw\": \"smem_launch\", \"round\": %d, \"staged\": %d, \"queries\": %llu, \"blocks\": %d, \"chunk\": %u, "
+            "\"ms\": %.3f}\n", P.round, (int)staged, (unsigned long long)P.n_queries, grid, P.chunk, ms);
   return 0;
 }
 
@@ -1536,7 +1572,7 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
       k_expand_rows<<<grid_for((nu + 63) / 64 * 64 / 4, 256, 65536u), 256, 0, st>>>(seeds, (const uint64_t *)c->kpos.p, nu,
                                                                                      (uint64_t *)c->xrows.p, (uint64_t *)c->pos.p);
       TRY(hipGetLastError());
-      const int grid = persistent_grid((const void *)k_locate_wave, 256, 0, c->n_cu, o.blocks_per_cu);
+      const int grid = persistent_grid((const void *)k_locate_wave, 256, 0, c->n_cu, o.blocks_per_cu, n_pos, AUTO_ROWS_LOCATE);
       TRY(hipEventRecord(c->ev[3], st));
       k_locate_wave<<<grid, 256, 0, st>>>(v, (const uint64_t *)c->xrows.p, n_pos, (uint64_t *)c->pos.p, rmask, rshift, ctl);
       TRY(hipGetLastError());
@@ -1652,7 +1688,7 @@ extern "C" int mbw_tune(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   b.kernel = MBW_KERNEL_COOP;
   const int stage_opts[2] = {0, 1};            // no_stage
   const int seg_opts[3] = {128, 256, 1024};
-  const int bpc_opts[2] = {0, 2};
+  const int bpc_opts[2] = {0, -1};            // sized by the work, occupancy limit
   const int uniq_opts[2] = {1, 0};
   float bt = 0;
   bool have = false;

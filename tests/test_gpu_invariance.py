@@ -3,8 +3,8 @@
 The SMEM set, each interval and each position set are fixed by the reads and the index, so the
 result must not depend on how the work is scheduled.  On ragged reads (20-700 bases, N runs) over
 the 1 Mbp genome, bit-exact in canonical order:
-  * length binning on / off x persistent blocks per CU (occupancy limit, 2, 1) x segment length
-    (32, default) x unique-match path on / off, against the oracle;
+  * length binning on / off x persistent blocks per CU (sized by the work, occupancy limit, 2,
+    1) x segment length (32, default) x unique-match path on / off, against the oracle;
   * the same call twice (determinism, byte for byte);
   * the batch split at arbitrary points (read ids offset), against the whole batch;
   * the reads in shuffled order (seeds mapped back through the permutation).
@@ -50,7 +50,7 @@ def canon(out):
 def test_every_schedule_matches_the_oracle(setup):
     reads, exp, idx = setup
     ctx = mbw.Context(idx)
-    for stage, bpc, seg, uniq in itertools.product((True, False), (0, 2, 1), (32, 0), (True, False)):
+    for stage, bpc, seg, uniq in itertools.product((True, False), (0, -1, 2, 1), (32, 0), (True, False)):
         out = ctx.seed(reads.seq, reads.lengths, stage=stage, blocks_per_cu=bpc, seg_len=seg, unique_ext=uniq)
         s, p = out.download()
         compare_with_oracle(s, p, exp)
