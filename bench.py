@@ -152,6 +152,31 @@ def rescue_leg(mbw, torch, ctx, ref, reads, dseq, dlen, steps: int, warmup: int,
     return res
 
 
+def latency_leg(torch, ctx, reads, dseq, dlen, sched: dict, stream):
+    """Per-call time of small batches (reads already in HBM): persistent grids sized by the work
+    (blocks_per_cu = 0) against grids at the occupancy limit (-1)."""
+    rows = []
+    for n in (1, 100, 1000, 20_000, 100_000, 400_000):
+        if n > len(reads):
+            break
+        nb = int(reads.offsets[n])
+        row = dict(reads=n)
+        for name, bpc in (("work_sized_ms", 0), ("occupancy_limit_ms", -1)):
+            kw = dict(sched, blocks_per_cu=bpc)
+            for _ in range(2):
+                ctx.seed(dseq[:nb], dlen[:n], min_seed_len=19, max_occ=500, stream=stream, **kw)
+            ts = []
+            for _ in range(7):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx.seed(dseq[:nb], dlen[:n], min_seed_len=19, max_occ=500, stream=stream, **kw)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            row[name] = round(float(np.median(ts)) * 1e3, 3)
+        rows.append(row)
+    return dict(unit="ms per mbw_seed call, reads in HBM, median of 7", batches=rows)
+
+
 def serve_leg(mbw, idx, reads, seconds: float, sched: dict):
     """Open-loop serving on the resident index: Poisson arrivals, requests of log-uniform
     1..20,000 reads drawn from the workload's reads, at half of the saturation rate measured by a
@@ -335,6 +360,7 @@ def main():
     ap.add_argument("--probe", action="store_true", help="only run the copy and random-gather probes")
     ap.add_argument("--no-tune", action="store_true", help="default schedule instead of the autotuned one")
     ap.add_argument("--no-rescue", action="store_true", help="skip the mate-rescue prefilter leg")
+    ap.add_argument("--no-latency", action="store_true", help="skip the small-batch latency leg")
     ap.add_argument("--serve-seconds", type=float, default=6.0,
                     help="open-loop serving leg on the same index (0 = skip)")
     args = ap.parse_args()
@@ -469,6 +495,11 @@ def main():
                             args.cpu_window)
         log(f"rescue prefilter: {rescue}")
 
+    latency = None
+    if not args.no_latency:
+        latency = latency_leg(torch, ctx, reads, dseq, dlen, sched, stream)
+        log(f"small batches: {latency}")
+
     serve = None
     if args.serve_seconds > 0:
         serve = serve_leg(mbw, idx, reads, args.serve_seconds, sched)
@@ -482,7 +513,7 @@ def main():
                             min_seed_len=19, max_occ=500, sa_sample=args.sa_sample, kmer_k=info["kmer_k"],
                             isa_sample=args.isa_sample, unique_ext=not args.no_unique,
                             bases_per_line=384, line_bytes=LINE_BYTES, index_gb=round(info["bytes_resident"] / 1e9, 2)),
-                schedule=sched, plain_gpu=plain, roofline=roofline, cpu_baseline=cpu, serve=serve,
+                schedule=sched, plain_gpu=plain, roofline=roofline, cpu_baseline=cpu, serve=serve, batch_latency=latency,
                 index_build=index_build, rescue=rescue)
     print(json.dumps(line), flush=True)
 
