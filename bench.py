@@ -177,10 +177,11 @@ def latency_leg(torch, ctx, reads, dseq, dlen, sched: dict, stream):
     return dict(unit="ms per mbw_seed call, reads in HBM, median of 7", batches=rows)
 
 
-def serve_leg(mbw, idx, reads, seconds: float, sched: dict):
+def serve_leg(mbw, idx, reads, seconds: float, sched: dict, fixed_qps: float = 0.0):
     """Open-loop serving on the resident index: Poisson arrivals, requests of log-uniform
     1..20,000 reads drawn from the workload's reads, at half of the saturation rate measured by a
-    closed-loop burst; latency = submit to result on the host (the server's clock)."""
+    closed-loop burst (or at fixed_qps requests/s); latency = submit to result on the host (the
+    server's clock)."""
     import threading
     rng = np.random.default_rng(3000)
     n = len(reads)
@@ -200,7 +201,7 @@ def serve_leg(mbw, idx, reads, seconds: float, sched: dict):
         srv.wait(t)
     sat = sum(len(r[1]) for r in burst) / (time.perf_counter() - t0)
     mean_req = (20000.0 - 1.0) / np.log(20000.0)
-    qps = 0.5 * sat / mean_req
+    qps = fixed_qps if fixed_qps > 0 else 0.5 * sat / mean_req
     arrivals = np.cumsum(rng.exponential(1.0 / qps, size=int(qps * seconds * 1.2) + 10))
     arrivals = arrivals[arrivals < seconds]
     reqs = [request() for _ in range(arrivals.size)]
@@ -242,7 +243,8 @@ def serve_leg(mbw, idx, reads, seconds: float, sched: dict):
                 saturation_reads_per_s=round(sat, 1), reads_per_s=round(nr / span, 1),
                 p50_ms=round(float(np.percentile(lat, 50)), 3), p99_ms=round(float(np.percentile(lat, 99)), 3),
                 batches=batches, refused_submits=refused,
-                request_size="log-uniform 1..20000 reads", arrivals="Poisson at half the closed-loop saturation")
+                request_size="log-uniform 1..20000 reads",
+                arrivals=f"Poisson at {fixed_qps:g} requests/s" if fixed_qps > 0 else "Poisson at half the closed-loop saturation")
 
 
 def serve_bs(mbw, synth, args):
@@ -361,6 +363,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="default schedule instead of the autotuned one")
     ap.add_argument("--no-rescue", action="store_true", help="skip the mate-rescue prefilter leg")
     ap.add_argument("--no-latency", action="store_true", help="skip the small-batch latency leg")
+    ap.add_argument("--serve-qps", type=float, default=0.0,
+                    help="serving leg arrival rate in requests/s (0 = half the measured saturation)")
     ap.add_argument("--serve-seconds", type=float, default=6.0,
                     help="open-loop serving leg on the same index (0 = skip)")
     args = ap.parse_args()
@@ -502,7 +506,7 @@ def main():
 
     serve = None
     if args.serve_seconds > 0:
-        serve = serve_leg(mbw, idx, reads, args.serve_seconds, sched)
+        serve = serve_leg(mbw, idx, reads, args.serve_seconds, sched, args.serve_qps)
         log(f"serving: {serve}")
 
     line = dict(metric=METRIC, value=round(value, 1), unit="reads/s", n_gpus=1, steps=args.steps,
