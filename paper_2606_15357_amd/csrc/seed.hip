@@ -1330,10 +1330,39 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   uint64_t *offs = (uint64_t *)c->offs.p;
   int r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, wide, offs, n_reads + 1, st); });
   if (r) return r;
-  uint64_t total = 0;
+  const bool coop = o.kernel != MBW_KERNEL_PLAIN;
+  // wave kernels: packed-word offsets and the LDS-staging bins follow from the offsets alone, so
+  // their scans run before the one wait that reads every size the next steps need
+  uint64_t *nwd = nullptr, *woff = nullptr;
+  uint32_t *flag1 = nullptr, *pos1 = nullptr;
+  if (coop) {
+    GROW(c->nwords, (n_reads + 1) * 8);
+    GROW(c->woffs, (n_reads + 1) * 8);
+    nwd = (uint64_t *)c->nwords.p; woff = (uint64_t *)c->woffs.p;
+    k_read_words<<<grid_for(n_reads + 1), 256, 0, st>>>(offs, n_reads, nwd);
+    TRY(hipGetLastError());
+    r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, nwd, woff, n_reads + 1, st); });
+    if (r) return r;
+    GROW(c->q1, (n_reads + 1) * sizeof(Query));
+    GROW(c->bf0, (n_reads + 1) * 4); GROW(c->bp0, (n_reads + 1) * 4);
+    GROW(c->bid0, (n_reads + 1) * 4); GROW(c->bid1, (n_reads + 1) * 4);
+    GROW(c->bk0, (n_reads + 1) * 4); GROW(c->bk1, (n_reads + 1) * 4);
+    flag1 = (uint32_t *)c->bf0.p; pos1 = (uint32_t *)c->bp0.p;
+    k_read_bins<<<grid_for(n_reads), 256, 0, st>>>(offs, n_reads, o.no_stage ? 0 : 1, flag1);
+    TRY(hipGetLastError());
+    r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, flag1, pos1, n_reads, st); });
+    if (r) return r;
+  }
+  uint64_t total = 0, totw = 0;
   unsigned long long maxlen = 0;
+  uint32_t lastf = 0, lastp = 0;
   TRY(hipMemcpyAsync(&total, offs + n_reads, 8, hipMemcpyDeviceToHost, st));
   TRY(hipMemcpyAsync(&maxlen, ctl + C_MAXLEN, 8, hipMemcpyDeviceToHost, st));
+  if (coop) {
+    TRY(hipMemcpyAsync(&totw, woff + n_reads, 8, hipMemcpyDeviceToHost, st));
+    TRY(hipMemcpyAsync(&lastf, flag1 + n_reads - 1, 4, hipMemcpyDeviceToHost, st));
+    TRY(hipMemcpyAsync(&lastp, pos1 + n_reads - 1, 4, hipMemcpyDeviceToHost, st));
+  }
   TRY(hipStreamSynchronize(st));
   if (maxlen > MBW_MAX_READ) { mbw_set_error("read longer than 65535 bases"); return MBW_E_INVAL; }
   // encode (plain kernel) or pack (wave kernels)
@@ -1343,7 +1372,6 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     TRY(hipMemcpyAsync(c->ascii.p, reads, total, hipMemcpyHostToDevice, st));
     dreads = (const uint8_t *)c->ascii.p;
   }
-  const bool coop = o.kernel != MBW_KERNEL_PLAIN;
   if (!coop) {   // the plain kernel reads one code per base
     GROW(c->codes, total + 16);
     k_encode<<<grid_for(total), 256, 0, st>>>(dreads, total, o.bs_role, (uint8_t *)c->codes.p);
@@ -1352,16 +1380,6 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   ReadWords R;
   R.pw = nullptr; R.pn = nullptr; R.woff = nullptr;
   if (coop) {
-    GROW(c->nwords, (n_reads + 1) * 8);
-    GROW(c->woffs, (n_reads + 1) * 8);
-    uint64_t *nwd = (uint64_t *)c->nwords.p, *woff = (uint64_t *)c->woffs.p;
-    k_read_words<<<grid_for(n_reads + 1), 256, 0, st>>>(offs, n_reads, nwd);
-    TRY(hipGetLastError());
-    r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, nwd, woff, n_reads + 1, st); });
-    if (r) return r;
-    uint64_t totw = 0;
-    TRY(hipMemcpyAsync(&totw, woff + n_reads, 8, hipMemcpyDeviceToHost, st));
-    TRY(hipStreamSynchronize(st));
     GROW(c->pwords, (totw + 2) * 8);
     GROW(c->pnmask, (totw + 2) * 4);
     GROW(c->wread, (totw + 2) * 4);
@@ -1402,19 +1420,7 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   const Query *q1 = nullptr;
   const uint32_t seg_len = o.seg_len > 0 ? (uint32_t)std::max(32, o.seg_len) : 256u;
   if (coop) {
-    GROW(c->q1, (n_reads + 1) * sizeof(Query));
-    GROW(c->bf0, (n_reads + 1) * 4); GROW(c->bp0, (n_reads + 1) * 4);
-    GROW(c->bid0, (n_reads + 1) * 4); GROW(c->bid1, (n_reads + 1) * 4);
-    GROW(c->bk0, (n_reads + 1) * 4); GROW(c->bk1, (n_reads + 1) * 4);
-    uint32_t *flag1 = (uint32_t *)c->bf0.p, *pos1 = (uint32_t *)c->bp0.p, *ids = (uint32_t *)c->bid0.p;
-    k_read_bins<<<grid_for(n_reads), 256, 0, st>>>(offs, n_reads, o.no_stage ? 0 : 1, flag1);
-    TRY(hipGetLastError());
-    r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, flag1, pos1, n_reads, st); });
-    if (r) return r;
-    uint32_t lastf = 0, lastp = 0;
-    TRY(hipMemcpyAsync(&lastf, flag1 + n_reads - 1, 4, hipMemcpyDeviceToHost, st));
-    TRY(hipMemcpyAsync(&lastp, pos1 + n_reads - 1, 4, hipMemcpyDeviceToHost, st));
-    TRY(hipStreamSynchronize(st));
+    uint32_t *ids = (uint32_t *)c->bid0.p;
     nshort1 = (uint64_t)lastp + lastf;
     const uint64_t nlong = n_reads - nshort1;
     k_read_partition<<<grid_for(n_reads), 256, 0, st>>>(offs, flag1, pos1, n_reads, nshort1, ids, (uint32_t *)c->bk0.p);
