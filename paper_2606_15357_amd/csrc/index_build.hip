@@ -140,23 +140,41 @@ __global__ void __launch_bounds__(256) k_bucket_hist(const uint64_t *__restrict_
     if (h[t]) atomicAdd(&hist[t], (unsigned long long)h[t]);
 }
 
-// positions whose bucket lies in [blo, bhi) -> out (order is irrelevant: the sort fixes it)
+// positions whose bucket lies in [blo, bhi) -> out (order is irrelevant: the sort fixes it).
+// Each wave takes SEL_SUB x 64 consecutive positions, keeps its lane's selection bits in a register
+// and reserves the output for all of them with one atomic: the reservation counter is a single
+// address, and same-address device-scope atomics serialise (one per 64 positions kept this pass
+// at about 5 G positions/s).
+#define SEL_SUB 32
 __global__ void k_select(const uint64_t *__restrict__ Tw, uint64_t m, uint64_t n, uint32_t blo, uint32_t bhi,
                          uint64_t *__restrict__ out, unsigned long long *__restrict__ count) {
   const int lane = threadIdx.x & 63;
-  for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x; base < n; base += (uint64_t)gridDim.x * blockDim.x) {
-    uint64_t i = base + threadIdx.x;
-    bool f = false;
-    if (i < n) {
-      uint32_t b = bucket_of(key21(Tw, m, i));
-      f = b >= blo && b < bhi;
+  const uint64_t below = (1ull << lane) - 1;
+  const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nwave = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t base = wave * 64 * SEL_SUB; base < n; base += nwave * 64 * SEL_SUB) {
+    uint32_t bits = 0;
+    uint32_t cnt = 0;
+#pragma unroll 4
+    for (int t = 0; t < SEL_SUB; ++t) {
+      const uint64_t i = base + (uint64_t)t * 64 + lane;
+      bool f = false;
+      if (i < n) {
+        const uint32_t b = bucket_of(key21(Tw, m, i));
+        f = b >= blo && b < bhi;
+      }
+      bits |= (f ? 1u : 0u) << t;
+      cnt += __popcll(__ballot(f));
     }
-    uint64_t mask = __ballot(f);
-    uint32_t cnt = __popcll(mask);
     unsigned long long off = 0;
     if (lane == 0 && cnt) off = atomicAdd(count, (unsigned long long)cnt);
     off = __shfl(off, 0);
-    if (f) out[off + __popcll(mask & ((1ull << lane) - 1))] = i;
+    for (int t = 0; t < SEL_SUB; ++t) {
+      const bool f = (bits >> t) & 1u;
+      const uint64_t mask = __ballot(f);
+      if (f) out[off + __popcll(mask & below)] = base + (uint64_t)t * 64 + lane;
+      off += __popcll(mask);
+    }
   }
 }
 
@@ -185,6 +203,23 @@ __global__ void k_scatter_unres(const uint32_t *__restrict__ flag, const uint32_
                                 const uint32_t *__restrict__ grp, uint32_t *__restrict__ u_slot, uint32_t *__restrict__ u_gid) {
   for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < M; x += (uint64_t)gridDim.x * blockDim.x)
     if (flag[x]) { uint32_t u = idx[x]; u_slot[u] = (uint32_t)x; u_gid[u] = grp[x]; }
+}
+
+// later rounds look only at the previous round's unresolved rows (groups only split): the same
+// test and compaction over that list, which keeps ascending row order
+__global__ void k_mark_unres_list(const uint8_t *__restrict__ bnd, const uint32_t *__restrict__ list, uint64_t MU,
+                                  uint32_t *__restrict__ flag) {
+  for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < MU; u += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t x = list[u];
+    flag[u] = (bnd[x] && bnd[x + 1]) ? 0u : 1u;
+  }
+}
+
+__global__ void k_scatter_unres_list(const uint32_t *__restrict__ flag, const uint32_t *__restrict__ idx,
+                                     const uint32_t *__restrict__ list, uint64_t MU, const uint32_t *__restrict__ grp,
+                                     uint32_t *__restrict__ u_slot, uint32_t *__restrict__ u_gid) {
+  for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < MU; u += (uint64_t)gridDim.x * blockDim.x)
+    if (flag[u]) { const uint32_t x = list[u], v = idx[u]; u_slot[v] = x; u_gid[v] = grp[x]; }
 }
 
 __global__ void k_u_keys(const uint64_t *__restrict__ Tw, uint64_t m, const uint64_t *__restrict__ sa,
@@ -317,9 +352,9 @@ __global__ void k_kmer_pack(const Iv *__restrict__ lv, uint64_t nent, uint4 *__r
 // suffix sorting of one chunk; returns 0 or an MBW error code
 int sort_chunk(const uint64_t *Tw, uint64_t m, uint64_t n, uint32_t blo, uint32_t bhi, uint64_t M,
                uint64_t *sa0, uint64_t *sa1, uint64_t *key0, uint64_t *key1, uint8_t *bnd, uint32_t *grp,
-               uint32_t *flag, uint32_t *idx, uint32_t *u_slot, uint32_t *u_gid, uint32_t *iota0, uint32_t *iota1,
-               uint64_t *nk1, uint32_t *gid1, uint32_t *gseed, uint32_t *gscan, uint64_t *tmp_sa, uint64_t *tmp_nk,
-               unsigned long long *dcount, Temp &tmp, hipStream_t st, uint64_t **sa_out) {
+               uint32_t *flag, uint32_t *idx, uint32_t *u_slot, uint32_t *u_slot2, uint32_t *u_gid, uint32_t *iota0,
+               uint32_t *iota1, uint64_t *nk1, uint32_t *gid1, uint32_t *gseed, uint32_t *gscan, uint64_t *tmp_sa,
+               uint64_t *tmp_nk, unsigned long long *dcount, Temp &tmp, hipStream_t st, uint64_t **sa_out) {
   TRY(hipMemsetAsync(dcount, 0, sizeof(unsigned long long), st));
   k_select<<<grid_for(n), 256, 0, st>>>(Tw, m, n, blo, bhi, sa0, dcount);
   TRY(hipGetLastError());
@@ -342,21 +377,29 @@ int sort_chunk(const uint64_t *Tw, uint64_t m, uint64_t n, uint32_t blo, uint32_
   TRY(hipcub::DeviceScan::InclusiveScan(nullptr, tb, idx, grp, hipcub::Max(), M, st));
   TRY(tmp.ensure(tb));
   TRY(hipcub::DeviceScan::InclusiveScan(tmp.b.p, tb, idx, grp, hipcub::Max(), M, st));
+  uint64_t MU = M;   // candidates of this round: all rows in the first, then the last round's unresolved list
   for (uint64_t round = 1;; ++round) {
     if (round > n / 21 + 4) { mbw_set_error("suffix refinement did not converge"); return MBW_E_HIP; }
-    k_mark_unres<<<grid_for(M), 256, 0, st>>>(bnd, M, flag);
+    uint32_t *prev = u_slot;
+    if (round == 1) k_mark_unres<<<grid_for(M), 256, 0, st>>>(bnd, M, flag);
+    else k_mark_unres_list<<<grid_for(MU), 256, 0, st>>>(bnd, prev, MU, flag);
     TRY(hipGetLastError());
     tb = 0;
-    TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, flag, idx, M, st));
+    TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, flag, idx, MU, st));
     TRY(tmp.ensure(tb));
-    TRY(hipcub::DeviceScan::ExclusiveSum(tmp.b.p, tb, flag, idx, M, st));
+    TRY(hipcub::DeviceScan::ExclusiveSum(tmp.b.p, tb, flag, idx, MU, st));
     uint32_t lastf = 0, lasti = 0;
-    TRY(hipMemcpyAsync(&lastf, flag + M - 1, 4, hipMemcpyDeviceToHost, st));
-    TRY(hipMemcpyAsync(&lasti, idx + M - 1, 4, hipMemcpyDeviceToHost, st));
+    TRY(hipMemcpyAsync(&lastf, flag + MU - 1, 4, hipMemcpyDeviceToHost, st));
+    TRY(hipMemcpyAsync(&lasti, idx + MU - 1, 4, hipMemcpyDeviceToHost, st));
     TRY(hipStreamSynchronize(st));
-    uint64_t MU = (uint64_t)lasti + lastf;
+    const uint64_t MU0 = MU;
+    MU = (uint64_t)lasti + lastf;
     if (MU == 0) break;
-    k_scatter_unres<<<grid_for(M), 256, 0, st>>>(flag, idx, M, grp, u_slot, u_gid);
+    if (round == 1) k_scatter_unres<<<grid_for(M), 256, 0, st>>>(flag, idx, M, grp, u_slot, u_gid);
+    else {
+      k_scatter_unres_list<<<grid_for(MU0), 256, 0, st>>>(flag, idx, prev, MU0, grp, u_slot2, u_gid);
+      std::swap(u_slot, u_slot2);
+    }
     TRY(hipGetLastError());
     uint64_t d = 21 * round;
     k_u_keys<<<grid_for(MU), 256, 0, st>>>(Tw, m, sa, u_slot, MU, d, tmp_nk /*nk*/, iota0);
@@ -611,19 +654,20 @@ extern "C" int mbw_index_build(const uint8_t *ref, uint64_t len, const mbw_build
     // chunk capacity from free memory (about 100 bytes per suffix in flight)
     size_t fr = 0, tot = 0;
     TRY(hipMemGetInfo(&fr, &tot));
-    uint64_t cap = (fr > (size_t)(2ull << 30)) ? (uint64_t)((fr - (2ull << 30)) / 104) : (uint64_t)(fr / 208);
+    uint64_t cap = (fr > (size_t)(2ull << 30)) ? (uint64_t)((fr - (2ull << 30)) / 108) : (uint64_t)(fr / 216);
     cap = std::min<uint64_t>(cap, (1ull << 31) - 1024);
     uint64_t maxb = *std::max_element(h.begin(), h.end());
     if (cap < maxb) cap = maxb;
     cap = std::min<uint64_t>(cap, n);
     DevBuf<uint64_t> sa0, sa1, key0, key1, nk1, tmp_sa, tmp_nk;
     DevBuf<uint8_t> bnd;
-    DevBuf<uint32_t> grp, flag, idx, u_slot, u_gid, iota0, iota1, gid1, gseed, gscan;
+    DevBuf<uint32_t> grp, flag, idx, u_slot, u_slot2, u_gid, iota0, iota1, gid1, gseed, gscan;
     DevBuf<unsigned long long> dcount, dprim;
     TRY(sa0.alloc(cap)); TRY(sa1.alloc(cap)); TRY(key0.alloc(cap)); TRY(key1.alloc(cap));
     TRY(nk1.alloc(cap)); TRY(tmp_sa.alloc(cap)); TRY(tmp_nk.alloc(cap));
     TRY(bnd.alloc(cap + 1));
-    TRY(grp.alloc(cap)); TRY(flag.alloc(cap)); TRY(idx.alloc(cap)); TRY(u_slot.alloc(cap)); TRY(u_gid.alloc(cap));
+    TRY(grp.alloc(cap)); TRY(flag.alloc(cap)); TRY(idx.alloc(cap)); TRY(u_slot.alloc(cap)); TRY(u_slot2.alloc(cap));
+    TRY(u_gid.alloc(cap));
     TRY(iota0.alloc(cap)); TRY(iota1.alloc(cap)); TRY(gid1.alloc(cap)); TRY(gseed.alloc(cap)); TRY(gscan.alloc(cap));
     TRY(dcount.alloc(1)); TRY(dprim.alloc(1));
     TRY(hipMemsetAsync(dprim.p, 0xff, 8, st));
@@ -637,8 +681,8 @@ extern "C" int mbw_index_build(const uint8_t *ref, uint64_t len, const mbw_build
       if (M == 0) { b = e; continue; }
       uint64_t *sa = nullptr;
       int r = sort_chunk(Tw.p, m, n, b, e, M, sa0.p, sa1.p, key0.p, key1.p, bnd.p, grp.p, flag.p, idx.p, u_slot.p,
-                         u_gid.p, iota0.p, iota1.p, nk1.p, gid1.p, gseed.p, gscan.p, tmp_sa.p, tmp_nk.p, dcount.p,
-                         tmp, st, &sa);
+                         u_slot2.p, u_gid.p, iota0.p, iota1.p, nk1.p, gid1.p, gseed.p, gscan.p, tmp_sa.p, tmp_nk.p,
+                         dcount.p, tmp, st, &sa);
       if (r) return r;
       k_emit_rows<<<grid_for(M), 256, 0, st>>>(sa, M, base, Tw.p, (uint32_t)ix->sa_sample, B.p, ix->ssa, dprim.p,
                                                (uint32_t)std::max(1, ix->isa_sample), ix->isa);
@@ -653,7 +697,8 @@ extern "C" int mbw_index_build(const uint8_t *ref, uint64_t len, const mbw_build
     ix->primary = prim;
     // free the sorting space before the lines are built
     sa0.release(); sa1.release(); key0.release(); key1.release(); nk1.release(); tmp_sa.release(); tmp_nk.release();
-    bnd.release(); grp.release(); flag.release(); idx.release(); u_slot.release(); u_gid.release(); iota0.release();
+    bnd.release(); grp.release(); flag.release(); idx.release(); u_slot.release(); u_slot2.release(); u_gid.release();
+    iota0.release();
     iota1.release(); gid1.release(); gseed.release(); gscan.release(); tmp.b.release();
     int r = build_lines(ix, B.p, st);
     if (r) return r;
