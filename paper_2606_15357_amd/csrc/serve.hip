@@ -5,8 +5,9 @@
 // A free worker forms a batch from the head of the queue (up to a read / base budget), so requests
 // that arrive while other batches are on the device join the next batch at once (continuous
 // batching), and batches of different workers run on the device at the same time.  A batch's
-// seeds come back sorted by read, so each request's seeds and positions are a contiguous slice,
-// which is copied out with read ids and position offsets made relative to the request.
+// seeds come back sorted by read, so each request's seeds and positions are a contiguous slice;
+// read ids and position offsets are made relative to each request on the device, and the batch is
+// downloaded once into a pinned buffer its requests share.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,6 +42,77 @@ struct Pinned {
   }
   ~Pinned() { if (p) (void)hipHostFree(p); }
 };
+
+// grow-only device buffer (per worker)
+struct DevScratch {
+  void *p = nullptr;
+  size_t bytes = 0;
+  int ensure(size_t want) {
+    if (want <= bytes) return 0;
+    if (p) { (void)hipFree(p); p = nullptr; bytes = 0; }
+    const size_t b = 2 * want + 256;
+    if (hipMalloc(&p, b) != hipSuccess) { p = nullptr; return MBW_E_NOMEM; }
+    bytes = b;
+    return 0;
+  }
+  ~DevScratch() { if (p) (void)hipFree(p); }
+};
+
+// Per-request split of a batch's result, on the device.  Seeds come back sorted by read and
+// positions and refined pieces follow their seeds, so request i (reads [rstart[i], rstart[i+1]))
+// owns a contiguous run of each: SplitBound i holds the first seed, position and piece of that run
+// (entry nreq closes the last one).  Read ids, position offsets and the pieces' seed indexes are
+// then made relative to their request in place.
+struct SplitBound { uint64_t t0, p0, c0; };
+
+__device__ __forceinline__ uint64_t seeds_before_read(const mbw_seed_t *sd, uint64_t n, uint32_t r) {
+  uint64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) / 2;
+    if (sd[mid].read_id < r) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// the request holding read r: the last i with rstart[i] <= r (empty requests share their start
+// with the next one)
+__device__ __forceinline__ uint32_t request_of(const uint32_t *rstart, uint32_t nreq, uint32_t r) {
+  uint32_t lo = 0, hi = nreq;   // rstart[0] = 0 <= r
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (rstart[mid] <= r) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void k_split_bounds(const mbw_seed_t *__restrict__ sd, uint64_t ns, uint64_t np, const mbw_piece_t *__restrict__ pc,
+                               uint64_t nc, const uint32_t *__restrict__ rstart, uint32_t nreq, SplitBound *__restrict__ b) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= nreq; i += gridDim.x * blockDim.x) {
+    const uint64_t t0 = i == nreq ? ns : seeds_before_read(sd, ns, rstart[i]);
+    uint64_t lo = 0, hi = nc;
+    while (lo < hi) {
+      const uint64_t mid = (lo + hi) / 2;
+      if (pc[mid].seed < t0) lo = mid + 1; else hi = mid;
+    }
+    b[i] = SplitBound{t0, t0 < ns ? sd[t0].pos_off : np, lo};
+  }
+}
+
+__global__ void k_split_rebase(mbw_seed_t *__restrict__ sd, uint64_t ns, mbw_piece_t *__restrict__ pc, uint64_t nc,
+                               const uint32_t *__restrict__ rstart, uint32_t nreq, const SplitBound *__restrict__ b) {
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < ns + nc; t += (uint64_t)gridDim.x * blockDim.x) {
+    if (t < ns) {
+      const uint32_t i = request_of(rstart, nreq, sd[t].read_id);
+      sd[t].read_id -= rstart[i];
+      sd[t].pos_off -= b[i].p0;
+    } else {
+      mbw_piece_t &q = pc[t - ns];
+      const uint32_t i = request_of(rstart, nreq, q.read_id);
+      q.read_id -= rstart[i];
+      q.seed -= (uint32_t)b[i].t0;
+    }
+  }
+}
 
 // one batch's downloaded result, shared by its requests
 struct BatchBuf {
@@ -87,7 +159,8 @@ struct mbw_server {
 };
 
 static void worker_main(mbw_server *s, mbw_ctx *ctx, hipStream_t st) {
-  Pinned hreads, hlens;
+  Pinned hreads, hlens, hreq, hbnd;
+  DevScratch dreq, dbnd;
   (void)hipSetDevice(s->cfg.device);
   // pinned staging sized for a full batch up front (pinning memory while serving would stall)
   const uint64_t br = std::min<uint64_t>(s->cfg.max_batch_reads, 1ull << 22);
@@ -147,6 +220,32 @@ static void worker_main(mbw_server *s, mbw_ctx *ctx, hipStream_t st) {
       rc = bb->seeds.ensure(br * 4 * sizeof(mbw_seed_t));
       if (!rc) rc = bb->pos.ensure(br * 24 * sizeof(uint64_t));
     }
+    // split into requests on the device (read ids, position offsets and piece seed indexes made
+    // relative to each request), then one download of the batch and of the request bounds
+    const uint32_t nreq = (uint32_t)batch.size();
+    if (!rc) rc = hreq.ensure((nreq + 1) * sizeof(uint32_t));
+    if (!rc) rc = hbnd.ensure((nreq + 1) * sizeof(SplitBound));
+    if (!rc) rc = dreq.ensure((nreq + 1) * sizeof(uint32_t));
+    if (!rc) rc = dbnd.ensure((nreq + 1) * sizeof(SplitBound));
+    if (!rc) {
+      uint32_t *rs = (uint32_t *)hreq.p;
+      uint64_t r0 = 0;
+      for (uint32_t i = 0; i < nreq; ++i) { rs[i] = (uint32_t)r0; r0 += batch[i]->lengths.size(); }
+      rs[nreq] = (uint32_t)r0;
+      const unsigned gb = (unsigned)std::min<uint64_t>((nreq + 256) / 256, 1024);
+      const unsigned gr = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((res.n_seeds + res.n_pieces + 255) / 256, 4096));
+      if (hipMemcpyAsync(dreq.p, rs, (nreq + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, st) != hipSuccess) rc = MBW_E_HIP;
+      if (!rc) {
+        k_split_bounds<<<gb, 256, 0, st>>>(res.seeds, res.n_seeds, res.n_pos, res.pieces, res.n_pieces,
+                                           (const uint32_t *)dreq.p, nreq, (SplitBound *)dbnd.p);
+        if (res.n_seeds + res.n_pieces)
+          k_split_rebase<<<gr, 256, 0, st>>>((mbw_seed_t *)res.seeds, res.n_seeds, (mbw_piece_t *)res.pieces, res.n_pieces,
+                                             (const uint32_t *)dreq.p, nreq, (const SplitBound *)dbnd.p);
+        if (hipGetLastError() != hipSuccess) rc = MBW_E_HIP;
+      }
+      if (!rc && hipMemcpyAsync(hbnd.p, dbnd.p, (nreq + 1) * sizeof(SplitBound), hipMemcpyDeviceToHost, st) != hipSuccess)
+        rc = MBW_E_HIP;
+    }
     if (!rc) rc = bb->seeds.ensure((res.n_seeds + 1) * sizeof(mbw_seed_t));
     if (!rc) rc = bb->pos.ensure((res.n_pos + 1) * sizeof(uint64_t));
     if (!rc) rc = mbw_result_download(ctx, &res, (mbw_seed_t *)bb->seeds.p, (uint64_t *)bb->pos.p);
@@ -155,23 +254,12 @@ static void worker_main(mbw_server *s, mbw_ctx *ctx, hipStream_t st) {
       if (!rc) rc = mbw_result_download_pieces(ctx, &res, (mbw_piece_t *)bb->pieces.p);
     }
     tb3 = s->now();
-    // split: seeds are sorted by read, positions follow the seeds, refined pieces follow their
-    // seeds; rebase each slice in place
     if (!rc) {
-      mbw_seed_t *sd = (mbw_seed_t *)bb->seeds.p;
-      mbw_piece_t *pc = (mbw_piece_t *)bb->pieces.p;
-      uint64_t r0 = 0, t = 0, c = 0;
-      for (Request *r : batch) {
-        const uint64_t r1 = r0 + r->lengths.size();
-        const uint64_t t0 = t, c0 = c;
-        while (t < res.n_seeds && sd[t].read_id < r1) ++t;
-        uint64_t p0 = 0, p1 = 0;
-        if (t > t0) { p0 = sd[t0].pos_off; p1 = sd[t - 1].pos_off + sd[t - 1].npos; }
-        for (uint64_t q = t0; q < t; ++q) { sd[q].read_id -= (uint32_t)r0; sd[q].pos_off -= p0; }
-        while (c < res.n_pieces && pc[c].seed < t) ++c;
-        for (uint64_t q = c0; q < c; ++q) { pc[q].read_id -= (uint32_t)r0; pc[q].seed -= (uint32_t)t0; }
-        r->buf = bb; r->s0 = t0; r->ns = t - t0; r->p0 = p0; r->np = p1 - p0; r->c0 = c0; r->nc = c - c0;
-        r0 = r1;
+      const SplitBound *b = (const SplitBound *)hbnd.p;
+      for (uint32_t i = 0; i < nreq; ++i) {
+        Request *r = batch[i];
+        r->buf = bb; r->s0 = b[i].t0; r->ns = b[i + 1].t0 - b[i].t0; r->p0 = b[i].p0; r->np = b[i + 1].p0 - b[i].p0;
+        r->c0 = b[i].c0; r->nc = b[i + 1].c0 - b[i].c0;
       }
     }
     {
