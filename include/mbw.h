@@ -205,8 +205,8 @@ int mbw_result_download(mbw_ctx *ctx, const mbw_result *res, mbw_seed_t *seeds, 
 int mbw_result_download_pieces(mbw_ctx *ctx, const mbw_result *res, mbw_piece_t *pieces);
 
 /* Autotuner for the wave kernels: runs mbw_seed on this batch with candidate schedules (length
- * binning on or off, segment lengths 128/256/1024, persistent blocks per CU sized by the work or at
- * the occupancy limit, unique-match extension on or off), each once untimed and once timed, and writes the
+ * binning on or off, segment lengths 128/256/1024, persistent blocks per CU sized by the work, at
+ * the occupancy limit or 2, unique-match extension on or off), each once untimed and once timed, and writes the
  * fastest to *best (other fields copied from *base, or the defaults when base is NULL) and its
  * device time to *best_ms.  Every candidate yields the same seeds.  Blocking; uses ctx's buffers
  * (its last result is overwritten).  Errors: as mbw_seed. */

@@ -322,10 +322,10 @@ __device__ __forceinline__ void wave_stat(unsigned long long *dst, uint64_t v, b
 // extension is finished by comparing read and text directly, which gives the same end j.  The
 // interval of the result keeps k (the same single suffix) and s = 1; k' is the row of the suffix
 // at the mirrored position m - p - (j - i) (T without $ is its own reverse complement), found from
-// the nearest inverse-SA sample by LF steps.  Stages: 4 = LF walks from row k and from the
-// reverse-complement row k' in step until one reaches a sampled row (Algorithm 2; the second gives
-// the mirror of p), 5 = text comparison, 6 = inverse-SA sample read, 7 = LF walk to k'.  The seed
-// carries p to locate, which does not walk it again.
+// the nearest inverse-SA sample by LF steps.  Stages: 4 = LF walk from row k (in the staged
+// kernel also from the reverse-complement row k', in step) until a sampled row is reached
+// (Algorithm 2; the second walk gives the mirror of p), 5 = text comparison, 6 = inverse-SA sample
+// read, 7 = LF walk to k'.  The seed carries p to locate, which does not walk it again.
 #define STAGE_WORDS 5   // staged reads of up to 160 bases
 #define SMEM_WAVES 4    // waves per block
 enum { ACT_DONE = 0, ACT_KMER = 1, ACT_BWD = 2, ACT_FWD = 3, ACT_LF = 4, ACT_SSA = 5, ACT_TEXT = 6, ACT_ISA = 7 };
@@ -342,6 +342,10 @@ typedef __attribute__((address_space(3))) void lds_void;
 template <bool STAGED, bool UNIQ>
 __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_per_eu(4))) k_smem_wave(IndexView ix, SeedParams P, ReadWords R) {
   constexpr bool SEG = !STAGED;
+  // the unique path's first walk follows both rows of the match in the staged kernel only: in the
+  // unstaged one the second row's state made the compiler spill four times as many scalar
+  // registers, which cost more than the shorter walk saves
+  constexpr bool DUAL = STAGED;
   __shared__ uint32_t swl[SMEM_WAVES][STAGED ? STAGE_WORDS * 64 : 1];  // staged bases: low / high halves of
   __shared__ uint32_t swh[SMEM_WAVES][STAGED ? STAGE_WORDS * 64 : 1];  // word w of lane L at [64 w + L]
   __shared__ uint32_t sn[SMEM_WAVES][STAGED ? STAGE_WORDS * 64 : 1];   // staged N bits
@@ -417,8 +421,9 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
       for (;;) {
         if ((UNIQ || SEG) && u >= 4) {                  // unique path (4-7), segment left check (8)
           if (UNIQ && u == 4) {   // walk both rows of the match until one reaches a sampled row
-            const bool s1 = (wrow & P.rmask) == 0, s2 = (wrow2 & P.rmask) == 0;
+            const bool s1 = (wrow & P.rmask) == 0, s2 = DUAL && (wrow2 & P.rmask) == 0;
             if (s1 || s2) { wmir = !s1; if (!s1) wrow = wrow2; act = ACT_SSA; break; }
+            if (!DUAL && wrow == ix.primary) { wrow = 0; ++wcnt; continue; }   // LF of the $ row is row 0
             act = ACT_LF; break;
           }
           if (UNIQ && u == 5) { act = ACT_TEXT; break; }
@@ -481,7 +486,8 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
     const bool ext = act == ACT_BWD || act == ACT_FWD;
     const bool bwd = act == ACT_BWD;
     const bool lfa = UNIQ && act == ACT_LF;
-    const bool lf2 = lfa && u == 4;                      // first walk: LF of both rows of the match
+    const bool lf1 = lfa && u == 4;                      // first walk
+    const bool lf2 = DUAL && lf1;                        // ... LF of both rows of the match
     const uint64_t x1 = lfa ? wrow : (bwd ? k : kr), y = bwd ? kr : k;
     const int cc = bwd ? a : 3 - a;
     const uint64_t x2 = lf2 ? wrow2 : x1 + (lfa ? 0ull : s);   // a single LF step ranks one row
@@ -550,9 +556,9 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
         wrow2 = x2 == ix.primary ? 0ull : scb[cx2] + E2 - ((cx2 == 0 && x2 > ix.primary) ? 1ull : 0ull);
         ++wcnt;
         n_lines += two ? 2 : 1;
-      } else if (lfa) {                                   // second walk (never meets the $ row)
+      } else if (lfa) {                                   // single-row walk (the second never meets the $ row)
         wrow = nx;
-        --wcnt;
+        if (lf1) ++wcnt; else --wcnt;
         ++n_lines;
       } else {
         n_lines += two ? 2 : 1;
@@ -578,7 +584,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
     if (UNIQ && act == ACT_SSA) {                       // the occurrence: p = S(row) + steps (mod n)
       uint64_t pp = mval + wcnt;
       if (pp >= ix.n) pp -= ix.n;
-      if (wmir) pp = tm - pp - (uint64_t)(j - i);       // the mirror of the reverse-complement match
+      if (DUAL && wmir) pp = tm - pp - (uint64_t)(j - i);   // the mirror of the reverse-complement match
       *tpl = pp;
       u = 5;
       ++n_lines;
@@ -1694,14 +1700,14 @@ extern "C" int mbw_tune(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   b.kernel = MBW_KERNEL_COOP;
   const int stage_opts[2] = {0, 1};            // no_stage
   const int seg_opts[3] = {128, 256, 1024};
-  const int bpc_opts[2] = {0, -1};            // sized by the work, occupancy limit
+  const int bpc_opts[3] = {0, -1, 2};         // sized by the work, occupancy limit, 2
   const int uniq_opts[2] = {1, 0};
   float bt = 0;
   bool have = false;
   for (int u = 0; u < 2; ++u)
     for (int ns = 0; ns < 2; ++ns)
       for (int sg = 0; sg < 3; ++sg)
-        for (int bp = 0; bp < 2; ++bp) {
+        for (int bp = 0; bp < 3; ++bp) {
           mbw_seed_opts o = b;
           o.unique_ext = uniq_opts[u]; o.no_stage = stage_opts[ns]; o.seg_len = seg_opts[sg]; o.blocks_per_cu = bpc_opts[bp];
           mbw_result res;
