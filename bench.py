@@ -177,7 +177,8 @@ def latency_leg(torch, ctx, reads, dseq, dlen, sched: dict, stream):
     return dict(unit="ms per mbw_seed call, reads in HBM, median of 7", batches=rows)
 
 
-def serve_leg(mbw, idx, reads, seconds: float, sched: dict, fixed_qps: float = 0.0):
+def serve_leg(mbw, idx, reads, seconds: float, sched: dict, fixed_qps: float = 0.0, workers: int = 4,
+              max_batch: int = 100_000):
     """Open-loop serving on the resident index: Poisson arrivals, requests of log-uniform
     1..20,000 reads drawn from the workload's reads, at half of the saturation rate measured by a
     closed-loop burst (or at fixed_qps requests/s); latency = submit to result on the host (the
@@ -191,7 +192,7 @@ def serve_leg(mbw, idx, reads, seconds: float, sched: dict, fixed_qps: float = 0
         r0 = int(rng.integers(0, n - m))
         return reads.seq[int(reads.offsets[r0]):int(reads.offsets[r0 + m])], reads.lengths[r0:r0 + m]
 
-    srv = mbw.Server(idx, n_workers=4, max_batch_reads=100_000, **sched)
+    srv = mbw.Server(idx, n_workers=workers, max_batch_reads=max_batch, **sched)
     for _ in range(2):                                    # warm the workers' buffers
         srv.wait(srv.submit(*request()))
     burst = [request() for _ in range(300)]
@@ -242,7 +243,7 @@ def serve_leg(mbw, idx, reads, seconds: float, sched: dict, fixed_qps: float = 0
     return dict(requests=len(reqs), reads=nr, qps=round(qps, 1), seconds=seconds,
                 saturation_reads_per_s=round(sat, 1), reads_per_s=round(nr / span, 1),
                 p50_ms=round(float(np.percentile(lat, 50)), 3), p99_ms=round(float(np.percentile(lat, 99)), 3),
-                batches=batches, refused_submits=refused,
+                batches=batches, refused_submits=refused, workers=workers, max_batch_reads=max_batch,
                 request_size="log-uniform 1..20000 reads",
                 arrivals=f"Poisson at {fixed_qps:g} requests/s" if fixed_qps > 0 else "Poisson at half the closed-loop saturation")
 
@@ -275,8 +276,8 @@ def serve_bs(mbw, synth, args):
         r0 = int(rng.integers(0, len(pool) - m))
         return bs, pool.seq[int(pool.offsets[r0]):int(pool.offsets[r0 + m])], pool.lengths[r0:r0 + m]
 
-    srv = {True: mbw.Server(bs_idx, n_workers=4, max_batch_reads=100_000, bs_role=1, bs_refine=True),
-           False: mbw.Server(pl_idx, n_workers=2, max_batch_reads=20_000)}
+    srv = {True: mbw.Server(bs_idx, n_workers=args.bs_workers, max_batch_reads=100_000, bs_role=1, bs_refine=True),
+           False: mbw.Server(pl_idx, n_workers=args.bs_plain_workers, max_batch_reads=20_000)}
     for _ in range(3):
         for k in (True, False):
             srv[k].wait(srv[k].submit(*request()[1:]))
@@ -288,7 +289,7 @@ def serve_bs(mbw, synth, args):
     bases = sum(int(y.sum()) for _, _, y in burst)
     sat_reads = sum(len(y) for _, _, y in burst) / (time.perf_counter() - t0)
     mean_req = (20000.0 - 1.0) / np.log(20000.0)
-    qps = 0.5 * sat_reads / mean_req
+    qps = args.serve_qps if args.serve_qps > 0 else 0.5 * sat_reads / mean_req
     arrivals = np.cumsum(rng.exponential(1.0 / qps, size=int(qps * args.serve_seconds * 1.2) + 10))
     arrivals = arrivals[arrivals < args.serve_seconds]
     reqs = [request() for _ in range(arrivals.size)]
@@ -336,7 +337,9 @@ def serve_bs(mbw, synth, args):
                config=dict(workload="3.1 Gbp synthetic reference; bisulfite 4-copy index (n = 12.4 G + 1) and plain "
                                     "index resident; 90% directional bisulfite 150 bp requests (strand filter + seed "
                                     "refinement), 10% plain 1-5 kbp; log-uniform 1..20000 reads per request; Poisson "
-                                    "arrivals at half the closed-loop saturation",
+                                    "arrivals at " + (f"{args.serve_qps:g} requests/s" if args.serve_qps > 0
+                                                      else "half the closed-loop saturation"),
+                           workers=dict(bisulfite=args.bs_workers, plain=args.bs_plain_workers),
                            index_build_s=dict(bisulfite=round(t_bs, 1), plain=round(t_pl, 1))))
     print(json.dumps(res), flush=True)
 
@@ -363,6 +366,12 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="default schedule instead of the autotuned one")
     ap.add_argument("--no-rescue", action="store_true", help="skip the mate-rescue prefilter leg")
     ap.add_argument("--no-latency", action="store_true", help="skip the small-batch latency leg")
+    ap.add_argument("--serve-workers", type=int, default=3,
+                    help="serving leg: worker threads, one stream each (3 gave the lowest latency at 1,750 and "
+                         "2,500 requests/s; the process has 4 hardware queues)")
+    ap.add_argument("--bs-workers", type=int, default=2, help="serve_bs_3gbp: workers of the bisulfite server")
+    ap.add_argument("--bs-plain-workers", type=int, default=1, help="serve_bs_3gbp: workers of the plain server")
+    ap.add_argument("--serve-max-batch", type=int, default=100_000, help="serving leg: reads per batch at most")
     ap.add_argument("--serve-qps", type=float, default=0.0,
                     help="serving leg arrival rate in requests/s (0 = half the measured saturation)")
     ap.add_argument("--serve-seconds", type=float, default=6.0,
@@ -506,7 +515,8 @@ def main():
 
     serve = None
     if args.serve_seconds > 0:
-        serve = serve_leg(mbw, idx, reads, args.serve_seconds, sched, args.serve_qps)
+        serve = serve_leg(mbw, idx, reads, args.serve_seconds, sched, args.serve_qps, args.serve_workers,
+                          args.serve_max_batch)
         log(f"serving: {serve}")
 
     line = dict(metric=METRIC, value=round(value, 1), unit="reads/s", n_gpus=1, steps=args.steps,
