@@ -3,7 +3,8 @@
 * mbw_tune picks one of its candidate schedules; seeding with it is bit-exact against the oracle.
 * mbw_serve: every request's result equals the oracle's for that request alone, both when it is
   served alone and when it is batched with many others submitted concurrently (tolerance 0);
-  batches really merge requests; admission refuses submissions when the queue is full.
+  batches really merge requests; admission refuses submissions when the queue is full; the
+  device-side split of a batch handles empty and seedless requests.
 """
 import threading
 
@@ -189,3 +190,39 @@ def test_serve_bisulfite_refined_pieces():
     assert merged > 0
     srv.close()
     idx.free()
+
+
+def test_serve_many_tiny_requests_share_a_batch(small):
+    """The per-request split of a batch (done on the device) at its edges: empty requests, requests
+    whose reads are all shorter than the minimum seed length (no seeds), and one- to three-read
+    requests, all queued behind a large request so that they are seeded as one batch."""
+    ref, ox, idx = small
+    big = synth.reads_fixed(ref, 3000, 150, False, p_sub=0.01, p_indel=0.001, seed=12)
+    tiny = []
+    for q in range(60):
+        kind = q % 5
+        if kind == 0:
+            tiny.append((np.zeros(0, np.uint8), np.zeros(0, np.uint32)))
+            continue
+        m = 1 + q % 3
+        lo, hi = (8, 18) if kind == 1 else (19, 300)
+        rs = synth.reads_uniform_len(ref, m, lo, hi, seed=2000 + q)
+        tiny.append((rs.seq.copy(), rs.lengths.copy()))
+    srv = mbw.Server(idx, n_workers=1, max_batch_reads=100_000)
+    tb = srv.submit(big.seq, big.lengths)
+    ts = [srv.submit(s, l) for s, l in tiny]
+    s, p, _ = srv.wait(tb)
+    compare_with_oracle(s, p, ox.seed(big.seq, big.offsets))
+    shared = 0
+    for (seq, lens), t in zip(tiny, ts):
+        s, p, info = srv.wait(t)
+        offs = np.concatenate([[0], np.cumsum(lens.astype(np.uint64))]).astype(np.uint64)
+        if len(lens) == 0:
+            assert len(s) == 0 and len(p) == 0
+        else:
+            compare_with_oracle(s, p, ox.seed(seq, offs))
+            if lens.max() < 19:
+                assert len(s) == 0
+        shared += info["batch_reads"] > len(lens)
+    assert shared >= 40
+    srv.close()
