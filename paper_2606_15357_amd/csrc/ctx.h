@@ -27,6 +27,8 @@ struct mbw_ctx {
   hipEvent_t ev[8];
   hipStream_t cur = nullptr;   // stream of the current / last call
   unsigned long long host_ctl[MBW_CTL_WORDS];
+  uint64_t *hfetch = nullptr;   // pinned host words that a kernel fills with the sizes the host waits for
+  uint64_t *dfetch = nullptr;   // ... the same memory as the device addresses it
   float ms_smem;
   int n_smem_launches;
 

@@ -1149,6 +1149,14 @@ extern "C" int mbw_ctx_create(const mbw_index *ix, mbw_ctx **out) {
     }
   }
   if (grow(c, c->ctl, C_COUNT * sizeof(unsigned long long))) { delete c; return MBW_E_NOMEM; }
+  if (hipHostMalloc((void **)&c->hfetch, MBW_CTL_WORDS * sizeof(uint64_t), hipHostMallocCoherent) != hipSuccess ||
+      hipHostGetDevicePointer((void **)&c->dfetch, c->hfetch, 0) != hipSuccess) {
+    if (c->hfetch) (void)hipHostFree(c->hfetch);
+    (void)hipFreeAsync(c->ctl.p, c->cur);
+    delete c;
+    mbw_set_error("pinned host buffer allocation failed");
+    return MBW_E_NOMEM;
+  }
   (void)hipStreamSynchronize(nullptr);
   *out = c;
   return MBW_OK;
@@ -1160,6 +1168,7 @@ extern "C" void mbw_ctx_free(mbw_ctx *c) {
   for (auto *b : c->buffers()) if (b->p) (void)hipFreeAsync(b->p, c->cur);
   (void)hipStreamSynchronize(c->cur);
   for (int t = 0; t < 8; ++t) (void)hipEventDestroy(c->ev[t]);
+  if (c->hfetch) (void)hipHostFree(c->hfetch);
   delete c;
 }
 
@@ -1265,6 +1274,36 @@ static int run_binned(mbw_ctx *c, const IndexView &v, SeedParams &P, const ReadW
   return 0;
 }
 
+// Sizes the host needs before it can launch the next steps (counts, scan totals): one kernel copies
+// up to FETCH_MAX device words into the context's pinned host buffer and the host waits once.  A
+// device-to-host copy per value costs a copy dispatch of its own, about 30 us each on a small batch.
+#define FETCH_MAX MBW_CTL_WORDS
+static_assert(C_COUNT <= FETCH_MAX, "the whole control block fits one fetch");
+struct FetchList { const void *p[FETCH_MAX]; int wide[FETCH_MAX]; int n; };
+struct FetchItem { const void *p; int wide; };   // wide: 8-byte word, else 4-byte
+__global__ void k_fetch(FetchList f, uint64_t *dst) {
+  const int t = threadIdx.x;
+  if (t < f.n) dst[t] = f.wide[t] ? *(const uint64_t *)f.p[t] : (uint64_t)*(const uint32_t *)f.p[t];
+  __threadfence_system();
+}
+static int fetch(mbw_ctx *c, hipStream_t st, std::initializer_list<FetchItem> items, uint64_t *out) {
+  FetchList f;
+  f.n = 0;
+  for (const FetchItem &it : items) { f.p[f.n] = it.p; f.wide[f.n] = it.wide; ++f.n; }
+  k_fetch<<<1, 64, 0, st>>>(f, c->dfetch);
+  TRY(hipGetLastError());
+  TRY(hipStreamSynchronize(st));
+  for (int t = 0; t < f.n; ++t) out[t] = ((volatile uint64_t *)c->hfetch)[t];
+  return 0;
+}
+#define FETCH(...) do { int r_ = fetch(c, st, __VA_ARGS__); if (r_) return r_; } while (0)
+
+// round 2 starts from round 1's seed count and line statistics again on a retry
+__global__ void k_ctl_restore(unsigned long long *ctl, unsigned long long n1, unsigned long long l0, unsigned long long l1,
+                              unsigned long long l2) {
+  if (threadIdx.x == 0) { ctl[C_NSEEDS] = n1; ctl[C_LINES] = l0; ctl[C_LINES + 1] = l1; ctl[C_LINES + 2] = l2; }
+}
+
 // split the n queries of q into segments (ctx buffer `out`); returns the segment count in *nseg
 static int segment_queries(mbw_ctx *c, const Query *q, uint64_t n, uint32_t seg, mbw_ctx::Buf &out, uint64_t *nseg,
                            hipStream_t st) {
@@ -1276,11 +1315,9 @@ static int segment_queries(mbw_ctx *c, const Query *q, uint64_t n, uint32_t seg,
   TRY(hipGetLastError());
   int r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, cnt, off, n, st); });
   if (r) return r;
-  uint32_t tail[2] = {0, 0};
-  TRY(hipMemcpyAsync(&tail[0], cnt + n - 1, 4, hipMemcpyDeviceToHost, st));
-  TRY(hipMemcpyAsync(&tail[1], off + n - 1, 4, hipMemcpyDeviceToHost, st));
-  TRY(hipStreamSynchronize(st));
-  *nseg = (uint64_t)tail[0] + tail[1];
+  uint64_t tail[2] = {0, 0};
+  FETCH({{cnt + n - 1, 0}, {off + n - 1, 0}}, tail);
+  *nseg = tail[0] + tail[1];
   GROW(out, (*nseg + 1) * sizeof(Query));
   k_seg_write<<<grid_for(n), 256, 0, st>>>(q, n, seg, cnt, off, (Query *)out.p);
   TRY(hipGetLastError());
@@ -1359,17 +1396,13 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, flag1, pos1, n_reads, st); });
     if (r) return r;
   }
-  uint64_t total = 0, totw = 0;
-  unsigned long long maxlen = 0;
-  uint32_t lastf = 0, lastp = 0;
-  TRY(hipMemcpyAsync(&total, offs + n_reads, 8, hipMemcpyDeviceToHost, st));
-  TRY(hipMemcpyAsync(&maxlen, ctl + C_MAXLEN, 8, hipMemcpyDeviceToHost, st));
-  if (coop) {
-    TRY(hipMemcpyAsync(&totw, woff + n_reads, 8, hipMemcpyDeviceToHost, st));
-    TRY(hipMemcpyAsync(&lastf, flag1 + n_reads - 1, 4, hipMemcpyDeviceToHost, st));
-    TRY(hipMemcpyAsync(&lastp, pos1 + n_reads - 1, 4, hipMemcpyDeviceToHost, st));
+  uint64_t total = 0, totw = 0, maxlen = 0, lastf = 0, lastp = 0;
+  {
+    uint64_t v[5] = {0, 0, 0, 0, 0};
+    if (coop) FETCH({{offs + n_reads, 1}, {ctl + C_MAXLEN, 1}, {woff + n_reads, 1}, {flag1 + n_reads - 1, 0}, {pos1 + n_reads - 1, 0}}, v);
+    else FETCH({{offs + n_reads, 1}, {ctl + C_MAXLEN, 1}}, v);
+    total = v[0]; maxlen = v[1]; totw = v[2]; lastf = v[3]; lastp = v[4];
   }
-  TRY(hipStreamSynchronize(st));
   if (maxlen > MBW_MAX_READ) { mbw_set_error("read longer than 65535 bases"); return MBW_E_INVAL; }
   // encode (plain kernel) or pack (wave kernels)
   const uint8_t *dreads = reads;
@@ -1427,7 +1460,7 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   const uint32_t seg_len = o.seg_len > 0 ? (uint32_t)std::max(32, o.seg_len) : 256u;
   if (coop) {
     uint32_t *ids = (uint32_t *)c->bid0.p;
-    nshort1 = (uint64_t)lastp + lastf;
+    nshort1 = lastp + lastf;
     const uint64_t nlong = n_reads - nshort1;
     k_read_partition<<<grid_for(n_reads), 256, 0, st>>>(offs, flag1, pos1, n_reads, nshort1, ids, (uint32_t *)c->bk0.p);
     TRY(hipGetLastError());
@@ -1450,7 +1483,7 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     r = segment_queries(c, qq + nshort1, nlong, seg_len, c->q1s, &nlong1, st);
     if (r) return r;
   }
-  unsigned long long n1 = 0, nq = 0;
+  unsigned long long n1 = 0, nq = 0, stats1[3] = {0, 0, 0};
   for (int attempt = 0;; ++attempt) {
     GROW(c->raw, seed_cap * sizeof(SeedRec));
     GROW(c->subq, subq_cap * sizeof(Query));
@@ -1461,16 +1494,16 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     if (coop) r = run_binned(c, v, P, R, o, q1, nshort1, (const Query *)c->q1s.p, nlong1, st);
     else r = run_smem(c, v, P, R, o, false, st);
     if (r) return r;
-    TRY(hipMemcpyAsync(&n1, ctl + C_NSEEDS, 8, hipMemcpyDeviceToHost, st));
-    TRY(hipMemcpyAsync(&nq, ctl + C_NSUBQ, 8, hipMemcpyDeviceToHost, st));
-    TRY(hipStreamSynchronize(st));
+    {
+      uint64_t v[5];
+      FETCH({{ctl + C_NSEEDS, 1}, {ctl + C_NSUBQ, 1}, {ctl + C_LINES, 1}, {ctl + C_LINES + 1, 1}, {ctl + C_LINES + 2, 1}}, v);
+      n1 = v[0]; nq = v[1]; stats1[0] = v[2]; stats1[1] = v[3]; stats1[2] = v[4];
+    }
     if (n1 <= seed_cap && nq <= subq_cap) break;
     if (attempt > 3) { mbw_set_error("seed buffer did not converge"); return MBW_E_NOMEM; }
     seed_cap = std::max<uint64_t>(seed_cap, n1 + n1 / 2 + 1024);
     subq_cap = std::max<uint64_t>(subq_cap, nq + nq / 2 + 1024);
   }
-  unsigned long long stats1[3];
-  TRY(hipMemcpyAsync(stats1, ctl + C_LINES, 3 * 8, hipMemcpyDeviceToHost, st));
   unsigned long long ntot = n1;
   if (coop && o.reseed && nq > 0) {
     // round-2 queries by bin (unused chunk slots dropped)
@@ -1484,13 +1517,9 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     if (r) return r;
     r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, fl, pl, nq, st); });
     if (r) return r;
-    uint32_t tail[4] = {0, 0, 0, 0};
-    TRY(hipMemcpyAsync(&tail[0], fs + nq - 1, 4, hipMemcpyDeviceToHost, st));
-    TRY(hipMemcpyAsync(&tail[1], ps + nq - 1, 4, hipMemcpyDeviceToHost, st));
-    TRY(hipMemcpyAsync(&tail[2], fl + nq - 1, 4, hipMemcpyDeviceToHost, st));
-    TRY(hipMemcpyAsync(&tail[3], pl + nq - 1, 4, hipMemcpyDeviceToHost, st));
-    TRY(hipStreamSynchronize(st));
-    const uint64_t nshort2 = (uint64_t)tail[0] + tail[1], nlong2 = (uint64_t)tail[2] + tail[3];
+    uint64_t tail[4] = {0, 0, 0, 0};
+    FETCH({{fs + nq - 1, 0}, {ps + nq - 1, 0}, {fl + nq - 1, 0}, {pl + nq - 1, 0}}, tail);
+    const uint64_t nshort2 = tail[0] + tail[1], nlong2 = tail[2] + tail[3];
     k_query_partition<<<grid_for(nq), 256, 0, st>>>(sq, fs, ps, fl, pl, nq, nshort2, (Query *)c->q2.p);
     TRY(hipGetLastError());
     uint64_t nlong2s = 0;
@@ -1499,13 +1528,16 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     SeedParams P2 = P;
     P2.round = 2;
     for (int attempt = 0;; ++attempt) {
-      TRY(hipMemcpyAsync(ctl + C_NSEEDS, &n1, 8, hipMemcpyHostToDevice, st));
-      TRY(hipMemcpyAsync(ctl + C_LINES, stats1, 3 * 8, hipMemcpyHostToDevice, st));
+      k_ctl_restore<<<1, 64, 0, st>>>(ctl, n1, stats1[0], stats1[1], stats1[2]);
+      TRY(hipGetLastError());
       P2.seeds = (SeedRec *)c->raw.p; P2.seed_cap = c->raw.bytes / sizeof(SeedRec);
       r = run_binned(c, v, P2, R, o, (const Query *)c->q2.p, nshort2, (const Query *)c->q2s.p, nlong2s, st);
       if (r) return r;
-      TRY(hipMemcpyAsync(&ntot, ctl + C_NSEEDS, 8, hipMemcpyDeviceToHost, st));
-      TRY(hipStreamSynchronize(st));
+      {
+        uint64_t v[1];
+        FETCH({{ctl + C_NSEEDS, 1}}, v);
+        ntot = v[0];
+      }
       if (ntot <= P2.seed_cap) break;
       if (attempt > 3) { mbw_set_error("seed buffer did not converge"); return MBW_E_NOMEM; }
       // keep the round-1 records: grow by copying
@@ -1541,11 +1573,9 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     TRY(hipGetLastError());
     r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, flag, idx, ns, st); });
     if (r) return r;
-    uint32_t lastf = 0, lasti = 0;
-    TRY(hipMemcpyAsync(&lastf, flag + ns - 1, 4, hipMemcpyDeviceToHost, st));
-    TRY(hipMemcpyAsync(&lasti, idx + ns - 1, 4, hipMemcpyDeviceToHost, st));
-    TRY(hipStreamSynchronize(st));
-    nu = (uint64_t)lasti + lastf;
+    uint64_t v[2];
+    FETCH({{flag + ns - 1, 0}, {idx + ns - 1, 0}}, v);
+    nu = v[1] + v[0];
   }
   GROW(c->seeds, (nu + 1) * sizeof(mbw_seed_t));
   GROW(c->npos, (nu + 2) * 8);
@@ -1563,8 +1593,7 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     TRY(hipMemsetAsync(npos + nu, 0, 8, st));
     r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, npos, posoff, nu + 1, st); });
     if (r) return r;
-    TRY(hipMemcpyAsync(&n_pos, posoff + nu, 8, hipMemcpyDeviceToHost, st));
-    TRY(hipStreamSynchronize(st));
+    FETCH({{posoff + nu, 1}}, &n_pos);
     k_seed_posoff<<<grid_for(nu), 256, 0, st>>>(seeds, posoff, nu);
     TRY(hipGetLastError());
   }
@@ -1608,8 +1637,7 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     k_bs_seeds<<<grid_for(nu), 256, 0, st>>>(seeds, nu, kidx);
     TRY(hipGetLastError());
     uint64_t kept = 0;
-    TRY(hipMemcpyAsync(&kept, kidx + n_pos, 8, hipMemcpyDeviceToHost, st));
-    TRY(hipStreamSynchronize(st));
+    FETCH({{kidx + n_pos, 1}}, &kept);
     n_pos = kept;
     final_pos = (const uint64_t *)c->pos2.p;
   }
@@ -1629,8 +1657,7 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     TRY(hipMemsetAsync(pc + n_pos, 0, 4, st));
     r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, pc, po, n_pos + 1, st); });
     if (r) return r;
-    TRY(hipMemcpyAsync(&n_pieces, po + n_pos, 8, hipMemcpyDeviceToHost, st));
-    TRY(hipStreamSynchronize(st));
+    FETCH({{po + n_pos, 1}}, &n_pieces);
     GROW(c->pieces, (n_pieces + 1) * sizeof(mbw_piece_t));
     if (n_pieces) {
       k_refine<<<grid_for(n_pos), 256, 0, st>>>(seeds, ps, final_pos, n_pos, dreads, offs, ix->orig, ix->len_r, o.bs_role,
@@ -1638,9 +1665,16 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
       TRY(hipGetLastError());
     }
   }
-  TRY(hipMemcpyAsync(c->host_ctl, ctl, C_COUNT * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
   TRY(hipEventRecord(c->ev[5], st));
-  TRY(hipEventSynchronize(c->ev[5]));
+  {
+    FetchList f;
+    f.n = C_COUNT;
+    for (int t = 0; t < C_COUNT; ++t) { f.p[t] = ctl + t; f.wide[t] = 1; }
+    k_fetch<<<1, 64, 0, st>>>(f, c->dfetch);
+    TRY(hipGetLastError());
+    TRY(hipStreamSynchronize(st));
+    for (int t = 0; t < C_COUNT; ++t) c->host_ctl[t] = ((volatile uint64_t *)c->hfetch)[t];
+  }
   if (c->host_ctl[C_ERR]) {
     mbw_set_error(std::string("kernel guard tripped (") + std::to_string(c->host_ctl[C_ERR]) + "): corrupt index or internal error");
     return MBW_E_HIP;
