@@ -327,8 +327,9 @@ __device__ __forceinline__ void wave_stat(unsigned long long *dst, uint64_t v, b
 // (Algorithm 2; the second walk gives the mirror of p), 5 = text comparison, 6 = inverse-SA sample
 // read, 7 = LF walk to k'.  The seed carries p to locate, which does not walk it again.
 #define STAGE_WORDS 5   // staged reads of up to 160 bases
+#define SOLO_STEPS 1024 // extension steps a wave's last working lane takes in one iteration
 #define SMEM_WAVES 4    // waves per block
-enum { ACT_DONE = 0, ACT_KMER = 1, ACT_BWD = 2, ACT_FWD = 3, ACT_LF = 4, ACT_SSA = 5, ACT_TEXT = 6, ACT_ISA = 7 };
+enum { ACT_DONE = 0, ACT_KMER = 1, ACT_BWD = 2, ACT_FWD = 3, ACT_LF = 4, ACT_SSA = 5, ACT_TEXT = 6, ACT_ISA = 7, ACT_SKIP = 8 };
 enum { ST_IDLE = 0, ST_REC = 1, ST_STAGE = 2, ST_ACTIVE = 3, ST_DRAINED = 4 };
 
 // STAGED: reads staged in LDS (the short-read bin; never segmented).  UNIQ: the unique-match path
@@ -482,6 +483,41 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
         act = ACT_BWD; break;
       }
       if (act == ACT_DONE) st = ST_IDLE;
+    }
+    if (__popcll(__ballot(st != ST_DRAINED)) == 1 &&
+        ((act == ACT_BWD && (u == 1 || u == 3)) || (act == ACT_FWD && u == 2))) {
+      // Tail of a launch: the queue is exhausted and this is the wave's only working lane, so its
+      // extension steps (backward in stages 1 and 3, forward in stage 2) run back to back here,
+      // without the rest of the iteration (the same steps in the same order).  A failing step, a
+      // non-ACGT base, the end of the stage, a unique match (s = 1, for the unique-match path)
+      // and a step beyond SOLO_STEPS are left to the next iteration.
+      const bool sbwd = act == ACT_BWD;
+      for (int t = 0; t < SOLO_STEPS; ++t) {
+        const int sc = sbwd ? a : 3 - a;
+        const uint64_t sx1 = sbwd ? k : kr, sx2 = sx1 + s, sy = sbwd ? kr : k;
+        const uint32_t sL1 = line_of(sx1), sL2 = line_of(sx2);
+        const int so1 = (int)(sx1 - (uint64_t)sL1 * MBW_BPL), so2 = (int)(sx2 - (uint64_t)sL2 * MBW_BPL);
+        const uint4 *p1 = ix.lines + (uint64_t)sL1 * MBW_LINE_U4, *p2 = ix.lines + (uint64_t)sL2 * MBW_LINE_U4;
+        const bool stwo = sL1 != sL2, sblk2 = stwo || (so1 >> 6) != (so2 >> 6);
+        const uint4 g0 = p1[0], g1 = p1[1], gb = p1[2 + (so1 >> 6)];
+        const uint4 q0 = stwo ? p2[0] : g0, q1 = stwo ? p2[1] : g1, qb = sblk2 ? p2[2 + (so2 >> 6)] : gb;
+        const SymMasks ssm = sym_masks(sc);
+        const uint32_t sb1 = 8 * (sL1 >> MBW_SB_SHIFT), sb2 = 8 * (sL2 >> MBW_SB_SHIFT);
+        uint64_t E1, G1, E2, G2, nx, ny, ns;
+        rank_eg(g0, g1, gb, sL1, so1, sc, ssm, sbt[sb1 + sc], sbt[sb1 + 4 + sc], E1, G1);
+        rank_eg(q0, q1, qb, sL2, so2, sc, ssm, sbt[sb2 + sc], sbt[sb2 + 4 + sc], E2, G2);
+        ext_update(E1, G1, E2, G2, sc, sx1, s, sy, ix.primary, scb[sc], nx, ny, ns);
+        if (ns < c) break;
+        n_lines += stwo ? 2 : 1;
+        ++n_steps;
+        if (sbwd) { k = nx; kr = ny; j -= 1; }
+        else { kr = nx; k = ny; j += 1; }
+        s = ns;
+        act = ACT_SKIP;
+        if (sbwd ? ((u == 1 && j < i) || (u == 3 && j <= i)) : (j == (int)qend || (UNIQ && P.uniq && s == 1))) break;
+        a = base_at(j);
+        if (a > 3) break;
+      }
     }
     const bool ext = act == ACT_BWD || act == ACT_FWD;
     const bool bwd = act == ACT_BWD;
