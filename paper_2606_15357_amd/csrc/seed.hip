@@ -484,39 +484,49 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
       }
       if (act == ACT_DONE) st = ST_IDLE;
     }
-    if (__popcll(__ballot(st != ST_DRAINED)) == 1 &&
-        ((act == ACT_BWD && (u == 1 || u == 3)) || (act == ACT_FWD && u == 2))) {
-      // Tail of a launch: the queue is exhausted and this is the wave's only working lane, so its
-      // extension steps (backward in stages 1 and 3, forward in stage 2) run back to back here,
-      // without the rest of the iteration (the same steps in the same order).  A failing step, a
-      // non-ACGT base, the end of the stage, a unique match (s = 1, for the unique-match path)
-      // and a step beyond SOLO_STEPS are left to the next iteration.
+    const bool selig = (act == ACT_BWD && (u == 1 || u == 3)) || (act == ACT_FWD && u == 2);
+    const uint64_t sbusy = __ballot(st != ST_DRAINED);
+    if (sbusy != 0 && __ballot(selig) == sbusy) {
+      // Tail of a launch: the queue is exhausted and every working lane of the wave is extending,
+      // so their extension steps (backward in stages 1 and 3, forward in stage 2) run back to back
+      // here, without the rest of the iteration (the same steps in the same order), until the
+      // first lane stops: a failing step, a non-ACGT base, the end of the stage and a unique match
+      // (s = 1, for the unique-match path) are left to the next iteration, as is a step beyond
+      // SOLO_STEPS.
       const bool sbwd = act == ACT_BWD;
+      bool go = selig;
       for (int t = 0; t < SOLO_STEPS; ++t) {
-        const int sc = sbwd ? a : 3 - a;
-        const uint64_t sx1 = sbwd ? k : kr, sx2 = sx1 + s, sy = sbwd ? kr : k;
-        const uint32_t sL1 = line_of(sx1), sL2 = line_of(sx2);
-        const int so1 = (int)(sx1 - (uint64_t)sL1 * MBW_BPL), so2 = (int)(sx2 - (uint64_t)sL2 * MBW_BPL);
-        const uint4 *p1 = ix.lines + (uint64_t)sL1 * MBW_LINE_U4, *p2 = ix.lines + (uint64_t)sL2 * MBW_LINE_U4;
-        const bool stwo = sL1 != sL2, sblk2 = stwo || (so1 >> 6) != (so2 >> 6);
-        const uint4 g0 = p1[0], g1 = p1[1], gb = p1[2 + (so1 >> 6)];
-        const uint4 q0 = stwo ? p2[0] : g0, q1 = stwo ? p2[1] : g1, qb = sblk2 ? p2[2 + (so2 >> 6)] : gb;
-        const SymMasks ssm = sym_masks(sc);
-        const uint32_t sb1 = 8 * (sL1 >> MBW_SB_SHIFT), sb2 = 8 * (sL2 >> MBW_SB_SHIFT);
-        uint64_t E1, G1, E2, G2, nx, ny, ns;
-        rank_eg(g0, g1, gb, sL1, so1, sc, ssm, sbt[sb1 + sc], sbt[sb1 + 4 + sc], E1, G1);
-        rank_eg(q0, q1, qb, sL2, so2, sc, ssm, sbt[sb2 + sc], sbt[sb2 + 4 + sc], E2, G2);
-        ext_update(E1, G1, E2, G2, sc, sx1, s, sy, ix.primary, scb[sc], nx, ny, ns);
-        if (ns < c) break;
-        n_lines += stwo ? 2 : 1;
-        ++n_steps;
-        if (sbwd) { k = nx; kr = ny; j -= 1; }
-        else { kr = nx; k = ny; j += 1; }
-        s = ns;
-        act = ACT_SKIP;
-        if (sbwd ? ((u == 1 && j < i) || (u == 3 && j <= i)) : (j == (int)qend || (UNIQ && P.uniq && s == 1))) break;
-        a = base_at(j);
-        if (a > 3) break;
+        if (go) {
+          const int sc = sbwd ? a : 3 - a;
+          const uint64_t sx1 = sbwd ? k : kr, sx2 = sx1 + s, sy = sbwd ? kr : k;
+          const uint32_t sL1 = line_of(sx1), sL2 = line_of(sx2);
+          const int so1 = (int)(sx1 - (uint64_t)sL1 * MBW_BPL), so2 = (int)(sx2 - (uint64_t)sL2 * MBW_BPL);
+          const uint4 *p1 = ix.lines + (uint64_t)sL1 * MBW_LINE_U4, *p2 = ix.lines + (uint64_t)sL2 * MBW_LINE_U4;
+          const bool stwo = sL1 != sL2, sblk2 = stwo || (so1 >> 6) != (so2 >> 6);
+          const uint4 g0 = p1[0], g1 = p1[1], gb = p1[2 + (so1 >> 6)];
+          const uint4 q0 = stwo ? p2[0] : g0, q1 = stwo ? p2[1] : g1, qb = sblk2 ? p2[2 + (so2 >> 6)] : gb;
+          const SymMasks ssm = sym_masks(sc);
+          const uint32_t sb1 = 8 * (sL1 >> MBW_SB_SHIFT), sb2 = 8 * (sL2 >> MBW_SB_SHIFT);
+          uint64_t E1, G1, E2, G2, nx, ny, ns;
+          rank_eg(g0, g1, gb, sL1, so1, sc, ssm, sbt[sb1 + sc], sbt[sb1 + 4 + sc], E1, G1);
+          rank_eg(q0, q1, qb, sL2, so2, sc, ssm, sbt[sb2 + sc], sbt[sb2 + 4 + sc], E2, G2);
+          ext_update(E1, G1, E2, G2, sc, sx1, s, sy, ix.primary, scb[sc], nx, ny, ns);
+          if (ns < c) go = false;
+          else {
+            n_lines += stwo ? 2 : 1;
+            ++n_steps;
+            if (sbwd) { k = nx; kr = ny; j -= 1; }
+            else { kr = nx; k = ny; j += 1; }
+            s = ns;
+            act = ACT_SKIP;
+            if (sbwd ? ((u == 1 && j < i) || (u == 3 && j <= i)) : (j == (int)qend || (UNIQ && P.uniq && s == 1))) go = false;
+            else {
+              a = base_at(j);
+              if (a > 3) go = false;
+            }
+          }
+        }
+        if (__ballot(selig && !go)) break;
       }
     }
     const bool ext = act == ACT_BWD || act == ACT_FWD;
