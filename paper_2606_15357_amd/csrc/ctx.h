@@ -24,7 +24,7 @@ struct mbw_ctx {
       q2s, sc0, sc1, pseed, pcnt, ppoff, pieces, kpos;
   // mate-rescue prefilter (its own buffers, so that it leaves the last seeding result intact)
   Buf rc_lens, rc_wide, rc_offs, rc_ascii, rc_cand, rc_ctl, rc_hits, rc_flags, rc_pass;
-  hipEvent_t ev[8];
+  hipEvent_t ev[8] = {};
   hipStream_t cur = nullptr;   // stream of the current / last call
   unsigned long long host_ctl[MBW_CTL_WORDS];
   uint64_t *hfetch = nullptr;   // pinned host words that a kernel fills with the sizes the host waits for

@@ -327,7 +327,7 @@ __device__ __forceinline__ void wave_stat(unsigned long long *dst, uint64_t v, b
 // (Algorithm 2; the second walk gives the mirror of p), 5 = text comparison, 6 = inverse-SA sample
 // read, 7 = LF walk to k'.  The seed carries p to locate, which does not walk it again.
 #define STAGE_WORDS 5   // staged reads of up to 160 bases
-#define SOLO_STEPS 1024 // extension steps a wave's last working lane takes in one iteration
+#define SOLO_STEPS 1024 // extension steps the tail loop takes in one iteration
 #define SMEM_WAVES 4    // waves per block
 enum { ACT_DONE = 0, ACT_KMER = 1, ACT_BWD = 2, ACT_FWD = 3, ACT_LF = 4, ACT_SSA = 5, ACT_TEXT = 6, ACT_ISA = 7, ACT_SKIP = 8 };
 enum { ST_IDLE = 0, ST_REC = 1, ST_STAGE = 2, ST_ACTIVE = 3, ST_DRAINED = 4 };
@@ -1185,7 +1185,7 @@ extern "C" int mbw_ctx_create(const mbw_index *ix, mbw_ctx **out) {
   if (hipGetDeviceProperties(&prop, ix->device) != hipSuccess) { delete c; mbw_set_error("hipGetDeviceProperties failed"); return MBW_E_HIP; }
   c->n_cu = prop.multiProcessorCount;
   for (int t = 0; t < 8; ++t)
-    if (hipEventCreate(&c->ev[t]) != hipSuccess) { delete c; mbw_set_error("hipEventCreate failed"); return MBW_E_HIP; }
+    if (hipEventCreate(&c->ev[t]) != hipSuccess) { mbw_ctx_free(c); mbw_set_error("hipEventCreate failed"); return MBW_E_HIP; }
   {
     // keep memory freed by growing buffers in the device's pool instead of returning it at every sync
     hipMemPool_t pool;
@@ -1197,9 +1197,7 @@ extern "C" int mbw_ctx_create(const mbw_index *ix, mbw_ctx **out) {
   if (grow(c, c->ctl, C_COUNT * sizeof(unsigned long long))) { delete c; return MBW_E_NOMEM; }
   if (hipHostMalloc((void **)&c->hfetch, MBW_CTL_WORDS * sizeof(uint64_t), hipHostMallocCoherent) != hipSuccess ||
       hipHostGetDevicePointer((void **)&c->dfetch, c->hfetch, 0) != hipSuccess) {
-    if (c->hfetch) (void)hipHostFree(c->hfetch);
-    (void)hipFreeAsync(c->ctl.p, c->cur);
-    delete c;
+    mbw_ctx_free(c);
     mbw_set_error("pinned host buffer allocation failed");
     return MBW_E_NOMEM;
   }
@@ -1213,7 +1211,7 @@ extern "C" void mbw_ctx_free(mbw_ctx *c) {
   (void)hipSetDevice(c->device);
   for (auto *b : c->buffers()) if (b->p) (void)hipFreeAsync(b->p, c->cur);
   (void)hipStreamSynchronize(c->cur);
-  for (int t = 0; t < 8; ++t) (void)hipEventDestroy(c->ev[t]);
+  for (int t = 0; t < 8; ++t) if (c->ev[t]) (void)hipEventDestroy(c->ev[t]);
   if (c->hfetch) (void)hipHostFree(c->hfetch);
   delete c;
 }
@@ -1333,6 +1331,7 @@ __global__ void k_fetch(FetchList f, uint64_t *dst) {
   __threadfence_system();
 }
 static int fetch(mbw_ctx *c, hipStream_t st, std::initializer_list<FetchItem> items, uint64_t *out) {
+  if (items.size() > FETCH_MAX) { mbw_set_error("internal: too many values in one fetch"); return MBW_E_INVAL; }
   FetchList f;
   f.n = 0;
   for (const FetchItem &it : items) { f.p[f.n] = it.p; f.wide[f.n] = it.wide; ++f.n; }
