@@ -5,8 +5,11 @@ oracle recomputes a seeded sample of the reads one by one and every seed, occurr
 position of the sampled reads must agree exactly:
 
 * 100 Mbp mixed genome, 1,000,000 read pairs of 150 bp: oracle O1 (full suffix array,
-  definitions) on 20,000 sampled reads, all fields including the ds-interval bounds;
-* the same genome, 500,000 reads of 100-5000 bp (lognormal, median 300): O1 on 3,000 reads;
+  definitions) on 20,000 sampled reads, all fields including the ds-interval bounds; the whole
+  results of the wave kernels (with and without length binning) and the plain kernel are
+  identical array for array;
+* the same genome, 500,000 reads of 100-5000 bp (lognormal, median 300): O1 on 3,000 reads; wave
+  and plain kernels identical over the whole batch;
 * 3.1 Gbp mixed genome, 10,000,000 read pairs: oracle O3 (one scan of T per q-mer set, no index)
   on 100 uniformly drawn reads plus 20 reads from satellite arrays; the bounds k' of the sampled
   seeds are checked through the strand mirror (seeding revcomp(P) gives (k', k, s) and the
@@ -63,6 +66,19 @@ def sample_of(seeds, pos, ids):
     return sel, p
 
 
+def same_arrays(seeds, pos, seeds0, pos0):
+    """Two whole results are identical (every field of every seed, every position)."""
+    if len(seeds) != len(seeds0) or len(pos) != len(pos0):
+        log(f"sizes differ: {len(seeds)} / {len(seeds0)} seeds, {len(pos)} / {len(pos0)} positions")
+        return False
+    for f in seeds.dtype.names:
+        if f != "reserved" and not np.array_equal(seeds[f], seeds0[f]):
+            bad = np.nonzero(seeds[f] != seeds0[f])[0][:5]
+            log(f"field {f} differs at {bad}")
+            return False
+    return bool(np.array_equal(pos, pos0))
+
+
 def compare_without_bounds(seeds, pos, exp):
     s, flat = mbw.canonical(seeds, pos)
     assert len(s) == len(exp), (len(s), len(exp))
@@ -98,13 +114,14 @@ def test_paired_100mbp_sampled_parity(genome100):
     exp = ox.seed(sub.seq, sub.offsets, min_len=19, max_occ=500)
     assert len(exp) > 20_000
     ctx = mbw.Context(idx)
-    counts = None
+    first = None
     for kernel, stage in ((mbw.KERNEL_COOP, True), (mbw.KERNEL_COOP, False), (mbw.KERNEL_PLAIN, True)):
         out, seeds, pos = gpu_seed_batch(ctx, reads, min_seed_len=19, max_occ=500, kernel=kernel, stage=stage)
         log(f"kernel {kernel} stage {stage}: {out.n_seeds} seeds, {out.n_pos} positions")
-        if counts is None:
-            counts = (out.n_seeds, out.n_pos)
-        assert (out.n_seeds, out.n_pos) == counts
+        if first is None:
+            first = (seeds.copy(), pos.copy())
+        else:   # every schedule returns the same arrays: seeds sorted by read, positions in SA-row order
+            assert same_arrays(seeds, pos, *first)
         s, p = sample_of(seeds, pos, ids)
         compare_with_oracle(s, p, exp)
     ctx.free()
@@ -118,13 +135,14 @@ def test_lognormal_100mbp_sampled_parity(genome100):
     sub = reads.subset(ids)
     exp = ox.seed(sub.seq, sub.offsets, min_len=19, max_occ=500)
     ctx = mbw.Context(idx)
-    counts = None
+    first = None
     for kernel in (mbw.KERNEL_COOP, mbw.KERNEL_PLAIN):
         out, seeds, pos = gpu_seed_batch(ctx, reads, min_seed_len=19, max_occ=500, kernel=kernel)
         log(f"kernel {kernel}: {out.n_seeds} seeds, {out.n_pos} positions")
-        if counts is None:
-            counts = (out.n_seeds, out.n_pos)
-        assert (out.n_seeds, out.n_pos) == counts
+        if first is None:
+            first = (seeds.copy(), pos.copy())
+        else:
+            assert same_arrays(seeds, pos, *first)
         s, p = sample_of(seeds, pos, ids)
         compare_with_oracle(s, p, exp)
     ctx.free()
