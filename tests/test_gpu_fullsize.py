@@ -10,8 +10,9 @@ position of the sampled reads must agree exactly:
   identical array for array;
 * the same genome, 500,000 reads of 100-5000 bp (lognormal, median 300): O1 on 3,000 reads; wave
   and plain kernels identical over the whole batch;
-* 3.1 Gbp mixed genome, 10,000,000 read pairs: oracle O3 (one scan of T per q-mer set, no index)
-  on 100 uniformly drawn reads plus 20 reads from satellite arrays; the bounds k' of the sampled
+* 3.1 Gbp mixed genome, 10,000,000 read pairs: the wave and plain kernels identical over the
+  whole batch; oracle O3 (one scan of T per q-mer set, no index) on 100 uniformly drawn reads
+  plus 20 reads from satellite arrays; the bounds k' of the sampled
   seeds are checked through the strand mirror (seeding revcomp(P) gives (k', k, s) and the
   mirrored positions).  The mate-rescue prefilter runs over 20,000,000 candidates of the same
   batch; 1,200 sampled candidates must match the oracle exactly.
@@ -162,6 +163,11 @@ def test_human_3gbp_sampled_parity():
     ctx = mbw.Context(idx)
     out, seeds, pos = gpu_seed_batch(ctx, reads, min_seed_len=19, max_occ=500)
     log(f"{len(reads)} reads: {out.n_seeds} seeds, {out.n_pos} positions ({time.time() - t0:.1f} s)")
+    # the plain one-read-per-thread kernel returns the same arrays for the whole batch
+    _, seeds_p, pos_p = gpu_seed_batch(ctx, reads, min_seed_len=19, max_occ=500, kernel=mbw.KERNEL_PLAIN)
+    assert same_arrays(seeds_p, pos_p, seeds, pos)
+    del seeds_p, pos_p
+    log(f"plain kernel: same {out.n_seeds} seeds and {out.n_pos} positions ({time.time() - t0:.1f} s)")
     # mate-rescue prefilter over the whole batch (a true-mate and a decoy window per pair, device
     # inputs, as the benchmark runs it); the oracle recomputes 1,200 sampled candidates
     cands, decoy = synth.rescue_candidates(reads, len(ref), decoys=True, seed=104)
