@@ -322,30 +322,23 @@ __global__ void k_line_headers(const uint64_t *__restrict__ pre /*4 x n_lines ex
 }
 
 // ---------------------------------------------------------------------------------------------
-// k-mer table: level t+1 from level t by one backward extension (Algorithm 1)
-struct Iv { uint64_t k, kr, s; };
-
-// level t+1 from level t: code(aP) = a + 4 code(P) (the first base is the least significant digit)
-__global__ void k_kmer_level(IndexView ix, const Iv *__restrict__ prev, uint64_t nprev, Iv *__restrict__ next) {
+// k-mer table: level t+1 from level t by one backward extension (Algorithm 1), every level in the
+// table's packed form.  Level t+1 from level t: code(aP) = a + 4 code(P) (the first base is the
+// least significant digit).
+__global__ void k_kmer_level(IndexView ix, const uint4 *__restrict__ prev, uint64_t nprev, uint4 *__restrict__ next) {
   uint64_t total = nprev * 4;
   for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < total; e += (uint64_t)gridDim.x * blockDim.x) {
     const int a = (int)(e & 3);
-    Iv p = prev[e >> 2];
-    Iv o;
-    if (p.s == 0) { o.k = 0; o.kr = 0; o.s = 0; }
-    else {
+    uint64_t pk, pkr, ps, ok = 0, okr = 0, os = 0;
+    kmer_unpack(prev[e >> 2], pk, pkr, ps);
+    if (ps != 0) {
       uint64_t E1, G1, E2, G2;
-      rank_global(ix, p.k, a, E1, G1);
-      rank_global(ix, p.k + p.s, a, E2, G2);
-      ext_update(E1, G1, E2, G2, a, p.k, p.s, p.kr, ix.primary, sel4(ix.Cb[0], ix.Cb[1], ix.Cb[2], ix.Cb[3], a), o.k, o.kr, o.s);
+      rank_global(ix, pk, a, E1, G1);
+      rank_global(ix, pk + ps, a, E2, G2);
+      ext_update(E1, G1, E2, G2, a, pk, ps, pkr, ix.primary, sel4(ix.Cb[0], ix.Cb[1], ix.Cb[2], ix.Cb[3], a), ok, okr, os);
     }
-    next[e] = o;
+    next[e] = kmer_pack(ok, okr, os);
   }
-}
-
-__global__ void k_kmer_pack(const Iv *__restrict__ lv, uint64_t nent, uint4 *__restrict__ tab) {
-  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < nent; e += (uint64_t)gridDim.x * blockDim.x)
-    tab[e] = kmer_pack(lv[e].k, lv[e].kr, lv[e].s);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -483,26 +476,26 @@ static int build_kmer_table(mbw_index *ix, hipStream_t st) {
   int K = ix->kmer_k;
   if (K <= 0) return 0;
   IndexView v = make_view(ix);
-  DevBuf<Iv> a, b;
-  uint64_t ntop = 1ull << (2 * K);
-  TRY(a.alloc(ntop));
-  TRY(b.alloc(ntop));
-  Iv root = {0, 0, ix->n};
-  TRY(hipMemcpyAsync(a.p, &root, sizeof(Iv), hipMemcpyHostToDevice, st));
-  uint64_t cnt = 1;
-  Iv *cur = a.p, *nxt = b.p;
-  for (int t = 0; t < K; ++t) {
-    k_kmer_level<<<grid_for(cnt * 4), 256, 0, st>>>(v, cur, cnt, nxt);
-    TRY(hipGetLastError());
-    std::swap(cur, nxt);
-    cnt *= 4;
-  }
+  const uint64_t ntop = 1ull << (2 * K);
   uint4 *tab = nullptr;
   TRY(hipMalloc((void **)&tab, ntop * sizeof(uint4)));
   ix->kmer = tab;
   ix->bytes += ntop * sizeof(uint4);
-  k_kmer_pack<<<grid_for(ntop), 256, 0, st>>>(cur, ntop, tab);
-  TRY(hipGetLastError());
+  // the levels alternate between the table and a scratch buffer of a quarter of its size, so that
+  // level K lands in the table: level t lies in the table when K - t is even
+  DevBuf<uint4> scratch;
+  TRY(scratch.alloc(ntop / 4));
+  uint4 *cur = (K % 2 == 0) ? tab : scratch.p;
+  const uint4 root = kmer_pack(0, 0, ix->n);
+  TRY(hipMemcpyAsync(cur, &root, sizeof(uint4), hipMemcpyHostToDevice, st));
+  uint64_t cnt = 1;
+  for (int t = 0; t < K; ++t) {
+    uint4 *nxt = (cur == tab) ? scratch.p : tab;
+    k_kmer_level<<<grid_for(cnt * 4), 256, 0, st>>>(v, cur, cnt, nxt);
+    TRY(hipGetLastError());
+    cur = nxt;
+    cnt *= 4;
+  }
   TRY(hipStreamSynchronize(st));
   return 0;
 }
