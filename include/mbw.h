@@ -206,8 +206,8 @@ int mbw_result_download_pieces(mbw_ctx *ctx, const mbw_result *res, mbw_piece_t 
 
 /* Autotuner for the wave kernels: runs mbw_seed on this batch with candidate schedules (length
  * binning on or off, segment lengths 128/256/1024, persistent blocks per CU sized by the work, at
- * the occupancy limit or 2, unique-match extension on or off), each once untimed and once timed, and writes the
- * fastest to *best (other fields copied from *base, or the defaults when base is NULL) and its
+ * the occupancy limit or 2, unique-match extension on or off), each once untimed and once timed,
+ * and writes the fastest to *best (other fields copied from *base, or the defaults when base is NULL) and its
  * device time to *best_ms.  Every candidate yields the same seeds.  Blocking; uses ctx's buffers
  * (its last result is overwritten).  Errors: as mbw_seed. */
 int mbw_tune(mbw_ctx *ctx, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads, int min_seed_len,
@@ -303,7 +303,9 @@ int mbw_probe_gather(int device, uint64_t bytes, int iters, double *lines_per_s,
 typedef struct mbw_server mbw_server;
 
 typedef struct {
-  int n_workers;              /* batches in flight at once (1..8) */
+  int n_workers;              /* batches in flight at once (1..8); each worker has its own stream,
+                                 and a process gets a few hardware queues (4 on MI355X by default),
+                                 so more workers than that share them */
   uint64_t max_batch_reads;   /* batch budget: reads ... */
   uint64_t max_batch_bases;   /* ... and bases */
   uint64_t max_queued_bases;  /* admission: submit returns MBW_E_BUSY when the queue is not empty and
