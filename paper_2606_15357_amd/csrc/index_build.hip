@@ -143,8 +143,8 @@ __global__ void __launch_bounds__(256) k_bucket_hist(const uint64_t *__restrict_
 // positions whose bucket lies in [blo, bhi) -> out (order is irrelevant: the sort fixes it).
 // Each wave takes SEL_SUB x 64 consecutive positions, keeps its lane's selection bits in a register
 // and reserves the output for all of them with one atomic: the reservation counter is a single
-// address, and same-address device-scope atomics serialise (one per 64 positions kept this pass
-// at about 5 G positions/s).
+// address, and same-address device-scope atomics serialise (with one reservation per 64 positions
+// the pass ran at about 5 G positions/s).
 #define SEL_SUB 32
 __global__ void k_select(const uint64_t *__restrict__ Tw, uint64_t m, uint64_t n, uint32_t blo, uint32_t bhi,
                          uint64_t *__restrict__ out, unsigned long long *__restrict__ count) {
