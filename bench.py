@@ -38,11 +38,39 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def strip_comments(src: str) -> str:
+    """C/C++ source without its comments and blank lines, trailing spaces removed: the text the
+    compiler acts on, so that a change to a comment keeps the hash below."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            out.append(" ")
+            i = n if j < 0 else j + 2
+        elif c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    lines = (ln.rstrip() for ln in "".join(out).split("\n"))
+    return "\n".join(ln for ln in lines if ln)
+
+
 def kernel_source_hash():
+    """Key of the committed counter summary: the seeding and index kernels' sources, comments
+    excluded."""
     h = hashlib.sha256()
     for f in ("seed.hip", "mbw_internal.h", "index_build.hip"):
-        with open(os.path.join(ROOT, "paper_2606_15357_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2606_15357_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(strip_comments(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -1,0 +1,41 @@
+"""Host logic of bench.py (CPU only): the key under which the committed counter summary is used."""
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_strip_comments_keeps_code_and_literals():
+    src = ('int a = 1;   // note\n'
+           '/* block\n   comment */ const char *s = "x // y /* z */";\n'
+           "\n"
+           "char q = '\"'; char r = '\\''; // after\n"
+           'int b = "\\"//"[0];\n')
+    assert bench.strip_comments(src) == (
+        'int a = 1;\n'
+        '  const char *s = "x // y /* z */";\n'
+        "char q = '\"'; char r = '\\'';\n"
+        'int b = "\\"//"[0];')
+
+
+def test_comment_edits_keep_the_key_and_code_edits_change_it():
+    code = "__global__ void k(int *p) {\n  p[0] = 1;  // one\n}\n"
+    reworded = ("// header\n/* two\n   lines */\n__global__ void k(int *p) {\n"
+                "  p[0] = 1;  // the value one,\n  // reworded\n\n}\n")
+    changed = "__global__ void k(int *p) {\n  p[0] = 2;  // one\n}\n"
+    assert bench.strip_comments(code) == bench.strip_comments(reworded)
+    assert bench.strip_comments(code) != bench.strip_comments(changed)
+
+
+def test_traffic_is_null_for_another_source_hash(tmp_path, monkeypatch):
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "traffic.json").write_text(
+        '{"source_hash": "0000000000000000", "kernels": {"smem": {"hbm_bytes_per_launch": 5.0}}}')
+    monkeypatch.setattr(bench, "ROOT", tmp_path)
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "1111111111111111")
+    assert bench.traffic_from_profile("smem", 1.0) is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0000000000000000")
+    assert bench.traffic_from_profile("smem", 1.0) == 5.0
