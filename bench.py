@@ -205,7 +205,7 @@ def latency_leg(torch, ctx, reads, dseq, dlen, sched: dict, stream):
     return dict(unit="ms per mbw_seed call, reads in HBM, median of 7", batches=rows)
 
 
-def serve_leg(mbw, idx, reads, seconds: float, sched: dict, fixed_qps: float = 0.0, workers: int = 4,
+def serve_leg(mbw, idx, reads, seconds: float, sched: dict, fixed_qps: float = 0.0, workers: int = 3,
               max_batch: int = 100_000):
     """Open-loop serving on the resident index: Poisson arrivals, requests of log-uniform
     1..20,000 reads drawn from the workload's reads, at half of the saturation rate measured by a
@@ -280,8 +280,9 @@ def serve_bs(mbw, synth, args):
     """Serving with a bisulfite index and a plain index of the same 3.1 Gbp reference resident:
     Poisson requests of log-uniform 1..20,000 reads; 90% of them directional bisulfite reads
     (150 bp, read-1 form, seeded against the four-copy index with the strand filter and the seed
-    refinement), 10% plain reads of 1-5 kbp (against the plain index); arrival rate at half of the
-    closed-loop saturation; p50/p99 from submission to result on the host."""
+    refinement), 10% plain reads of 1-5 kbp (against the plain index); arrivals at --serve-qps
+    requests/s, or at half of the closed-loop saturation when that is 0; p50/p99 from submission to
+    result on the host."""
     import threading
     t0 = time.time()
     ref = synth.workload_reference("serve_bs_3gbp", args.ref_len or None)
