@@ -1194,7 +1194,7 @@ extern "C" int mbw_ctx_create(const mbw_index *ix, mbw_ctx **out) {
       (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
     }
   }
-  if (grow(c, c->ctl, C_COUNT * sizeof(unsigned long long))) { delete c; return MBW_E_NOMEM; }
+  if (grow(c, c->ctl, C_COUNT * sizeof(unsigned long long))) { mbw_ctx_free(c); return MBW_E_NOMEM; }
   if (hipHostMalloc((void **)&c->hfetch, MBW_CTL_WORDS * sizeof(uint64_t), hipHostMallocCoherent) != hipSuccess ||
       hipHostGetDevicePointer((void **)&c->dfetch, c->hfetch, 0) != hipSuccess) {
     mbw_ctx_free(c);

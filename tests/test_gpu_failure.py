@@ -3,6 +3,8 @@
 * mbw_seed returns MBW_E_NOMEM when its work space would exceed the cap, and the same context
   seeds correctly (bit-exact against the oracle) once the cap is lifted;
 * the rescue prefilter fails the same way and recovers;
+* creating a context under a cap too small for its control block fails with MBW_E_NOMEM and
+  releases what it had made; a context created after the cap is lifted seeds correctly;
 * a serving batch that fails reports the error to its request; the server then serves the next
   request correctly.
 """
@@ -48,6 +50,23 @@ def test_seed_and_rescue_fail_then_recover(small):
     hits, passed = ctx.rescue(reads.seq, reads.lengths, cands).download()
     mh, bt = oracle.rescue(ref.codes, reads.seq, reads.offsets, cands["read_id"], cands["win_beg"], cands["win_len"])
     assert np.array_equal(hits["max_hits"], mh) and np.array_equal(hits["best_t"], bt)
+    ctx.free()
+
+
+def test_context_creation_fails_then_recovers(small):
+    ref, ox, idx = small
+    reads = synth.reads_fixed(ref, 500, 150, True, seed=75)
+    try:
+        mbw.set_mem_limit(1)
+        for _ in range(3):
+            with pytest.raises(mbw.MbwError) as e:
+                mbw.Context(idx)
+            assert e.value.code == mbw.MBW_E_NOMEM
+    finally:
+        mbw.set_mem_limit(0)
+    ctx = mbw.Context(idx)
+    s, p = ctx.seed(reads.seq, reads.lengths).download()
+    compare_with_oracle(s, p, ox.seed(reads.seq, reads.offsets))
     ctx.free()
 
 
