@@ -64,10 +64,12 @@ typedef struct {
  * mbw_index_free.  Blocking.  Errors: MBW_E_INVAL (len, options), MBW_E_NOMEM, MBW_E_HIP.      */
 int mbw_index_build(const uint8_t *ref, uint64_t len, const mbw_build_opts *opts, mbw_index **out);
 
-/* Write the resident index to `path` (versioned header + checksummed arrays).  Blocking. */
+/* Write the resident index to `path` (versioned header + checksummed arrays), streamed through
+ * 128 MiB of pinned host memory.  Blocking.  Errors: MBW_E_IO, MBW_E_NOMEM, MBW_E_HIP. */
 int mbw_index_save(const mbw_index *idx, const char *path);
 
-/* Read an index file written by mbw_index_save and make it resident on `device`.
+/* Read an index file written by mbw_index_save and make it resident on `device`, streamed
+ * through 128 MiB of pinned host memory.  The file size must equal what the header states.
  * Errors: MBW_E_IO, MBW_E_FORMAT (magic, version, sizes or checksum), MBW_E_NOMEM, MBW_E_HIP. */
 int mbw_index_load(const char *path, int device, mbw_index **out);
 

@@ -769,27 +769,90 @@ static uint64_t fnv(const void *p, size_t n, uint64_t h = 1469598103934665603ull
   return h;
 }
 
-// checksum of a large array: FNV of 64-bit words, strided by blocks (fast, order-sensitive)
-static uint64_t sum_words(const void *p, size_t bytes) {
-  const uint64_t *w = (const uint64_t *)p;
-  size_t nw = bytes / 8;
-  uint64_t h = 1469598103934665603ull;
-  for (size_t i = 0; i < nw; ++i) { h ^= w[i] + i; h *= 1099511628211ull; }
-  return h;
+// checksum of a large array: FNV-1a over its 64-bit words, each added to its word index (order
+// sensitive); computed chunk by chunk as the array streams through the host
+struct SumWords {
+  uint64_t h = 1469598103934665603ull, i = 0;
+  void add(const void *p, size_t bytes) {
+    const uint64_t *w = (const uint64_t *)p;
+    for (size_t k = 0; k < bytes / 8; ++k, ++i) { h ^= w[k] + i; h *= 1099511628211ull; }
+  }
+};
+
+// Arrays move between the device and an index file through two pinned host chunks on a stream of
+// their own: host memory stays bounded whatever the index size (39 GB at 3.1 Gbp), the copy of
+// one chunk overlaps the file I/O and checksum of the other, and every array is checksummed on
+// the way.
+static const size_t kChunk = 64ull << 20;
+
+struct Staging {
+  uint8_t *buf[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipStream_t st = nullptr;
+  int init() {
+    TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    for (int b = 0; b < 2; ++b) {
+      TRY(hipHostMalloc((void **)&buf[b], kChunk, hipHostMallocDefault));
+      TRY(hipEventCreateWithFlags(&ev[b], hipEventDisableTiming));
+      TRY(hipEventRecord(ev[b], st));
+    }
+    return 0;
+  }
+  ~Staging() {
+    if (st) (void)hipStreamSynchronize(st);   // no copy may still use a chunk being freed
+    for (int b = 0; b < 2; ++b) {
+      if (ev[b]) (void)hipEventDestroy(ev[b]);
+      if (buf[b]) (void)hipHostFree(buf[b]);
+    }
+    if (st) (void)hipStreamDestroy(st);
+  }
+};
+
+// device -> file; the download of chunk c + 1 runs while chunk c is checksummed and written
+static int save_array(Staging &S, FILE *f, const void *dev, size_t bytes, uint64_t *sum) {
+  SumWords h;
+  const uint8_t *d = (const uint8_t *)dev;
+  const size_t nc = (bytes + kChunk - 1) / kChunk;
+  auto fetch = [&](size_t c) -> int {
+    const size_t off = c * kChunk;
+    TRY(hipMemcpyAsync(S.buf[c & 1], d + off, std::min(kChunk, bytes - off), hipMemcpyDeviceToHost, S.st));
+    TRY(hipEventRecord(S.ev[c & 1], S.st));
+    return 0;
+  };
+  if (nc) { int r = fetch(0); if (r) return r; }
+  for (size_t c = 0; c < nc; ++c) {
+    const size_t len = std::min(kChunk, bytes - c * kChunk);
+    TRY(hipEventSynchronize(S.ev[c & 1]));
+    if (c + 1 < nc) { int r = fetch(c + 1); if (r) return r; }
+    h.add(S.buf[c & 1], len);
+    if (fwrite(S.buf[c & 1], 1, len, f) != len) { mbw_set_error("index file write failed"); return MBW_E_IO; }
+  }
+  *sum = h.h;
+  return 0;
 }
+
+// file -> device; chunk c + 1 is read and checksummed while chunk c uploads
+static int load_array(Staging &S, FILE *f, void *dev, size_t bytes, uint64_t *sum) {
+  SumWords h;
+  uint8_t *d = (uint8_t *)dev;
+  for (size_t off = 0, c = 0; off < bytes; off += kChunk, ++c) {
+    const size_t len = std::min(kChunk, bytes - off);
+    TRY(hipEventSynchronize(S.ev[c & 1]));   // the chunk's previous upload has finished
+    if (fread(S.buf[c & 1], 1, len, f) != len) { mbw_set_error("truncated index file"); return MBW_E_FORMAT; }
+    h.add(S.buf[c & 1], len);
+    TRY(hipMemcpyAsync(d + off, S.buf[c & 1], len, hipMemcpyHostToDevice, S.st));
+    TRY(hipEventRecord(S.ev[c & 1], S.st));
+  }
+  TRY(hipStreamSynchronize(S.st));
+  *sum = h.h;
+  return 0;
+}
+
+static uint64_t kmer_bytes(int k) { return k ? (1ull << (2 * k)) * 16 : 0; }
 
 extern "C" int mbw_index_save(const mbw_index *ix, const char *path) {
   if (!ix || !path) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
   TRY(hipSetDevice(ix->device));
-  uint64_t kb = ix->kmer ? (1ull << (2 * ix->kmer_k)) * 16 : 0;
-  std::vector<uint8_t> lines(ix->n_lines * MBW_LINE_BYTES), ssa(ix->n_ssa * 8), kmer(kb), text(ix->n_text * 8),
-      isa(ix->n_isa * 8), orig(ix->n_orig * 8);
-  TRY(hipMemcpy(lines.data(), ix->lines, lines.size(), hipMemcpyDeviceToHost));
-  TRY(hipMemcpy(ssa.data(), ix->ssa, ssa.size(), hipMemcpyDeviceToHost));
-  if (kb) TRY(hipMemcpy(kmer.data(), ix->kmer, kb, hipMemcpyDeviceToHost));
-  if (text.size()) TRY(hipMemcpy(text.data(), ix->text, text.size(), hipMemcpyDeviceToHost));
-  if (isa.size()) TRY(hipMemcpy(isa.data(), ix->isa, isa.size(), hipMemcpyDeviceToHost));
-  if (orig.size()) TRY(hipMemcpy(orig.data(), ix->orig, orig.size(), hipMemcpyDeviceToHost));
   FileHeader hd;
   memset(&hd, 0, sizeof(hd));
   hd.magic = kMagic; hd.version = kVersion; hd.bpl = MBW_BPL;
@@ -799,22 +862,28 @@ extern "C" int mbw_index_save(const mbw_index *ix, const char *path) {
   hd.n_sb = ix->n_sb;
   memcpy(hd.sb, ix->sb_host, sizeof(hd.sb));
   hd.isa_sample = ix->isa_sample; hd.n_text = ix->n_text; hd.n_isa = ix->n_isa; hd.n_orig = ix->n_orig;
-  hd.sum_lines = sum_words(lines.data(), lines.size());
-  hd.sum_ssa = sum_words(ssa.data(), ssa.size());
-  hd.sum_kmer = sum_words(kmer.data(), kmer.size());
-  hd.sum_text = sum_words(text.data(), text.size());
-  hd.sum_isa = sum_words(isa.data(), isa.size());
-  hd.sum_orig = sum_words(orig.data(), orig.size());
-  hd.sum_header = fnv(&hd, offsetof(FileHeader, sum_header));
+  Staging S;
+  int r = S.init();
+  if (r) return r;
   FILE *f = fopen(path, "wb");
   if (!f) { mbw_set_error(std::string("cannot open ") + path); return MBW_E_IO; }
-  bool ok = fwrite(&hd, sizeof(hd), 1, f) == 1 && fwrite(lines.data(), 1, lines.size(), f) == lines.size() &&
-            fwrite(ssa.data(), 1, ssa.size(), f) == ssa.size() && (kb == 0 || fwrite(kmer.data(), 1, kb, f) == kb) &&
-            fwrite(text.data(), 1, text.size(), f) == text.size() && fwrite(isa.data(), 1, isa.size(), f) == isa.size() &&
-            fwrite(orig.data(), 1, orig.size(), f) == orig.size();
-  ok = (fclose(f) == 0) && ok;
-  if (!ok) { mbw_set_error(std::string("write failed: ") + path); return MBW_E_IO; }
-  return MBW_OK;
+  // the header goes first with the checksums left zero, and is rewritten once they are known
+  r = fwrite(&hd, sizeof(hd), 1, f) == 1 ? 0 : MBW_E_IO;
+  if (r) mbw_set_error(std::string("write failed: ") + path);
+  if (!r) r = save_array(S, f, ix->lines, hd.n_lines * MBW_LINE_BYTES, &hd.sum_lines);
+  if (!r) r = save_array(S, f, ix->ssa, hd.n_ssa * 8, &hd.sum_ssa);
+  if (!r) r = save_array(S, f, ix->kmer, kmer_bytes(hd.kmer_k), &hd.sum_kmer);
+  if (!r) r = save_array(S, f, ix->text, hd.n_text * 8, &hd.sum_text);
+  if (!r) r = save_array(S, f, ix->isa, hd.n_isa * 8, &hd.sum_isa);
+  if (!r) r = save_array(S, f, ix->orig, hd.n_orig * 8, &hd.sum_orig);
+  if (!r) {
+    hd.sum_header = fnv(&hd, offsetof(FileHeader, sum_header));
+    if (fseek(f, 0, SEEK_SET) != 0 || fwrite(&hd, sizeof(hd), 1, f) != 1) {
+      mbw_set_error(std::string("write failed: ") + path); r = MBW_E_IO;
+    }
+  }
+  if (fclose(f) != 0 && !r) { mbw_set_error(std::string("write failed: ") + path); r = MBW_E_IO; }
+  return r;
 }
 
 extern "C" int mbw_index_load(const char *path, int device, mbw_index **out) {
@@ -834,23 +903,19 @@ extern "C" int mbw_index_load(const char *path, int device, mbw_index **out) {
       hd.n_orig != (hd.bisulfite ? (hd.len_r + 31) / 32 + 2 : 0)) {
     fclose(f); mbw_set_error("bad magic, version or header fields"); return MBW_E_FORMAT;
   }
-  uint64_t kb = hd.kmer_k ? (1ull << (2 * hd.kmer_k)) * 16 : 0;
-  std::vector<uint8_t> lines, ssa, kmer, text, isa, orig;
-  try {
-    lines.resize(hd.n_lines * MBW_LINE_BYTES); ssa.resize(hd.n_ssa * 8); kmer.resize(kb);
-    text.resize(hd.n_text * 8); isa.resize(hd.n_isa * 8); orig.resize(hd.n_orig * 8);
-  } catch (...) { fclose(f); mbw_set_error("host allocation failed"); return MBW_E_NOMEM; }
-  bool ok = fread(lines.data(), 1, lines.size(), f) == lines.size() && fread(ssa.data(), 1, ssa.size(), f) == ssa.size() &&
-            (kb == 0 || fread(kmer.data(), 1, kb, f) == kb) && fread(text.data(), 1, text.size(), f) == text.size() &&
-            fread(isa.data(), 1, isa.size(), f) == isa.size() && fread(orig.data(), 1, orig.size(), f) == orig.size();
-  fclose(f);
-  if (!ok) { mbw_set_error("truncated index file"); return MBW_E_FORMAT; }
-  if (sum_words(lines.data(), lines.size()) != hd.sum_lines || sum_words(ssa.data(), ssa.size()) != hd.sum_ssa ||
-      sum_words(kmer.data(), kmer.size()) != hd.sum_kmer || sum_words(text.data(), text.size()) != hd.sum_text ||
-      sum_words(isa.data(), isa.size()) != hd.sum_isa || sum_words(orig.data(), orig.size()) != hd.sum_orig) {
-    mbw_set_error("index checksum mismatch"); return MBW_E_FORMAT;
+  const uint64_t kb = kmer_bytes(hd.kmer_k);
+  const uint64_t payload = hd.n_lines * MBW_LINE_BYTES + hd.n_ssa * 8 + kb + (hd.n_text + hd.n_isa + hd.n_orig) * 8;
+  // the file must hold exactly the arrays its header states (checked before any device allocation)
+  if (fseeko(f, 0, SEEK_END) != 0) { fclose(f); mbw_set_error("cannot seek index file"); return MBW_E_IO; }
+  const off_t fsize = ftello(f);
+  if (fsize < 0 || (uint64_t)fsize != sizeof(hd) + payload || fseeko(f, (off_t)sizeof(hd), SEEK_SET) != 0) {
+    fclose(f);
+    mbw_set_error((fsize >= 0 && (uint64_t)fsize < sizeof(hd) + payload) ? "truncated index file"
+                                                                          : "index file size differs from its header");
+    return MBW_E_FORMAT;
   }
-  TRY(hipSetDevice(device));
+  int rc = [&]() -> int { TRY(hipSetDevice(device)); return 0; }();
+  if (rc) { fclose(f); return rc; }
   mbw_index *ix = new mbw_index();
   memset(ix, 0, sizeof(*ix));
   ix->device = device; ix->n = hd.n; ix->len_r = hd.len_r; ix->primary = hd.primary; ix->n_lines = hd.n_lines;
@@ -859,30 +924,30 @@ extern "C" int mbw_index_load(const char *path, int device, mbw_index **out) {
   ix->n_sb = hd.n_sb;
   memcpy(ix->sb_host, hd.sb, sizeof(hd.sb));
   ix->isa_sample = hd.isa_sample; ix->n_text = hd.n_text; ix->n_isa = hd.n_isa; ix->n_orig = hd.n_orig;
-  int rc = [&]() -> int {
+  rc = [&]() -> int {
+    Staging S;
+    int r = S.init();
+    if (r) return r;
+    auto place = [&](auto **dst, uint64_t bytes, uint64_t want) -> int {
+      uint64_t got = 0;
+      if (bytes) TRY(hipMalloc((void **)dst, bytes));
+      int e = load_array(S, f, *dst, bytes, &got);
+      if (e) return e;
+      if (got != want) { mbw_set_error("index checksum mismatch"); return MBW_E_FORMAT; }
+      return 0;
+    };
     TRY(hipMalloc((void **)&ix->sbtab, sizeof(hd.sb)));
     TRY(hipMemcpy(ix->sbtab, hd.sb, sizeof(hd.sb), hipMemcpyHostToDevice));
-    TRY(hipMalloc((void **)&ix->lines, lines.size()));
-    TRY(hipMemcpy(ix->lines, lines.data(), lines.size(), hipMemcpyHostToDevice));
-    TRY(hipMalloc((void **)&ix->ssa, ssa.size()));
-    TRY(hipMemcpy(ix->ssa, ssa.data(), ssa.size(), hipMemcpyHostToDevice));
-    if (kb) {
-      TRY(hipMalloc((void **)&ix->kmer, kb));
-      TRY(hipMemcpy(ix->kmer, kmer.data(), kb, hipMemcpyHostToDevice));
-    }
-    if (text.size()) {
-      TRY(hipMalloc((void **)&ix->text, text.size()));
-      TRY(hipMemcpy(ix->text, text.data(), text.size(), hipMemcpyHostToDevice));
-      TRY(hipMalloc((void **)&ix->isa, isa.size()));
-      TRY(hipMemcpy(ix->isa, isa.data(), isa.size(), hipMemcpyHostToDevice));
-    }
-    if (orig.size()) {
-      TRY(hipMalloc((void **)&ix->orig, orig.size()));
-      TRY(hipMemcpy(ix->orig, orig.data(), orig.size(), hipMemcpyHostToDevice));
-    }
-    ix->bytes = lines.size() + ssa.size() + kb + sizeof(hd.sb) + text.size() + isa.size() + orig.size();
+    if ((r = place(&ix->lines, hd.n_lines * MBW_LINE_BYTES, hd.sum_lines))) return r;
+    if ((r = place(&ix->ssa, hd.n_ssa * 8, hd.sum_ssa))) return r;
+    if ((r = place(&ix->kmer, kb, hd.sum_kmer))) return r;
+    if ((r = place(&ix->text, hd.n_text * 8, hd.sum_text))) return r;
+    if ((r = place(&ix->isa, hd.n_isa * 8, hd.sum_isa))) return r;
+    if ((r = place(&ix->orig, hd.n_orig * 8, hd.sum_orig))) return r;
+    ix->bytes = hd.n_lines * MBW_LINE_BYTES + hd.n_ssa * 8 + kb + sizeof(hd.sb) + (hd.n_text + hd.n_isa + hd.n_orig) * 8;
     return 0;
   }();
+  fclose(f);
   if (rc) { mbw_index_free(ix); return rc; }
   *out = ix;
   return MBW_OK;

@@ -271,6 +271,50 @@ def test_index_save_load_roundtrip(cfg0):
     idx.free()
 
 
+def test_index_file_streams_in_chunks(cfg0):
+    """Save and load move arrays through 64 MiB host chunks: a 12-mer table (256 MiB) spans
+    four; the reloaded index seeds bit-exact, its file is byte-identical when
+    saved again, and a file cut short, one with bytes appended, or one with a byte flipped in its
+    last chunk is refused."""
+    ref, reads, ox, exp = cfg0
+    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=12, isa_sample=4)
+    with tempfile.TemporaryDirectory() as d:
+        p, q = os.path.join(d, "a.mbw"), os.path.join(d, "b.mbw")
+        idx.save(p)
+        idx.free()
+        size = os.path.getsize(p)
+        assert size > 4 * (64 << 20)
+        idx2 = mbw.Index.load(p)
+        out, seeds, pos = gpu_seed(idx2, reads)
+        compare_with_oracle(seeds, pos, exp)
+        idx2.save(q)
+        idx2.free()
+        with open(p, "rb") as fa, open(q, "rb") as fb:
+            while True:
+                a, b = fa.read(1 << 24), fb.read(1 << 24)
+                assert a == b
+                if not a:
+                    break
+        os.truncate(q, size - 8)
+        with pytest.raises(mbw.MbwError) as e:
+            mbw.Index.load(q)
+        assert e.value.code == mbw.MBW_E_FORMAT and "truncated" in str(e.value)
+        with open(p, "ab") as f:
+            f.write(b"\0" * 8)
+        with pytest.raises(mbw.MbwError) as e:
+            mbw.Index.load(p)
+        assert e.value.code == mbw.MBW_E_FORMAT
+        os.truncate(p, size)
+        with open(p, "r+b") as f:
+            f.seek(size - 12)
+            b = f.read(1)
+            f.seek(size - 12)
+            f.write(bytes([b[0] ^ 0x10]))
+        with pytest.raises(mbw.MbwError) as e:
+            mbw.Index.load(p)
+        assert e.value.code == mbw.MBW_E_FORMAT and "checksum" in str(e.value)
+
+
 def test_hand_worked_example():
     """The hand-derived example (R = ACA, T = ACATGT$) straight from the GPU index and kernels."""
     import json
