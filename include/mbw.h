@@ -55,6 +55,10 @@ typedef struct {
                            inverse suffix array at text positions that are multiples of q (1..64),
                            which let the seeding kernels extend a match that occurs once by
                            comparing it with the text (same results, fewer index accesses).      */
+  int sb_lines_log2;    /* occurrence lines per superblock as a power of two: 0 = the default 2^23
+                           (each superblock spans 3.2 G rows of B, so a 3.1 Gbp plain index has 2 and
+                           a bisulfite one 4); 1..23 smaller, for tests that need several
+                           superblocks on a small reference.  An index may have at most 8.        */
 } mbw_build_opts;
 
 /* Build the index of `ref` (host pointer, `len` bases, 1 <= len < 2^38) on the GPU and keep it
@@ -69,8 +73,11 @@ int mbw_index_build(const uint8_t *ref, uint64_t len, const mbw_build_opts *opts
 int mbw_index_save(const mbw_index *idx, const char *path);
 
 /* Read an index file written by mbw_index_save and make it resident on `device`, streamed
- * through 128 MiB of pinned host memory.  The file size must equal what the header states.
- * Errors: MBW_E_IO, MBW_E_FORMAT (magic, version, sizes or checksum), MBW_E_NOMEM, MBW_E_HIP. */
+ * through 128 MiB of pinned host memory.  Before anything is allocated the header must pass the
+ * builder's limits (n < 2^39, n = 2|R|+1 or 4|R|+1, primary < n, C non-decreasing with C[$] = 0,
+ * C[A] = 1 and C[T] <= n, at most 8 superblocks, array sizes consistent) and the file size must
+ * equal what the header states.
+ * Errors: MBW_E_IO, MBW_E_FORMAT (magic, version, fields, sizes or checksum), MBW_E_NOMEM, MBW_E_HIP. */
 int mbw_index_load(const char *path, int device, mbw_index **out);
 
 void mbw_index_free(mbw_index *idx);
@@ -89,13 +96,15 @@ typedef struct {
   int bisulfite;
   int device;
   int isa_sample;          /* 0 when the index holds no text / inverse-SA samples */
+  int sb_lines_log2;       /* occurrence lines per superblock = 2^sb_lines_log2 */
+  int n_superblocks;
 } mbw_index_info_t;
 
 int mbw_index_info(const mbw_index *idx, mbw_index_info_t *out);
 
 /* Device pointers to the resident arrays (read-only views for tests and tools):
  * lines: n_lines x 128 B; each line = u32 counts of A, C, G in B from the start of its superblock
- *        (2^23 lines) to the line (the $ row counted as A), five u32 sub-checkpoints (counts of A,
+ *        (2^sb_lines_log2 lines) to the line (the $ row counted as A), five u32 sub-checkpoints (counts of A,
  *        C, G in the line's first 64, 128, 192, 256, 320 rows, 9 bits each at bits 0, 9, 18),
  *        then the line's six 64-row blocks, each a u64 of the low code bits and a u64 of the high
  *        code bits (row t of the block at bit t; the $ row holds A).
@@ -107,7 +116,10 @@ int mbw_index_device_arrays(const mbw_index *idx, const void **lines, const void
 typedef struct mbw_ctx mbw_ctx;
 
 /* A context owns the device work space and result buffers for one stream of mbw_seed calls.
- * Contexts are not thread-safe; use one per host thread / stream.  The index must outlive it. */
+ * Contexts are not thread-safe; use one per host thread / stream.  The index must outlive it.
+ * mbw_ctx_free waits for all work on the context's device (so it is safe after a call that failed
+ * part way, and the caller's last stream need not exist any more), frees the work space on a
+ * stream of the context's own and trims the device's memory pool. */
 int mbw_ctx_create(const mbw_index *idx, mbw_ctx **out);
 void mbw_ctx_free(mbw_ctx *ctx);
 
@@ -283,16 +295,6 @@ int mbw_rescue_download(mbw_ctx *ctx, const mbw_rescue_result *res, mbw_rescue_h
  * allocation failure (a serving batch that fails reports the error to each of its requests and
  * the server goes on).  Process-wide. */
 int mbw_debug_set_mem_limit(uint64_t bytes);
-
-/* ---- diagnostics (not part of the seeding path) ----------------------------------------------
- * mbw_probe_copy: streams `bytes` bytes (>= 4096) from one buffer to another once; *ms = kernel time.
- *   Used to calibrate profiler byte counters against a known transfer.
- * mbw_probe_gather: every lane follows four chains of random 128-byte lines (16 bytes read per line)
- *   over the largest power-of-two number of lines that fits in `bytes` (>= 1 MiB), `iters` dependent
- *   fetches per chain; *lines_per_s = random lines served per second.
- * Both allocate and free their own device memory.  Errors: MBW_E_INVAL, MBW_E_NOMEM, MBW_E_HIP. */
-int mbw_probe_copy(int device, uint64_t bytes, float *ms);
-int mbw_probe_gather(int device, uint64_t bytes, int iters, double *lines_per_s, float *ms);
 
 /* ---- serving -------------------------------------------------------------------------------
  * A request loop over one resident index.  Submitted requests are queued (host copies of their

@@ -37,7 +37,7 @@ SEED_ROUND2 = 2
 # the symbols include/mbw.h declares
 EXPORTS = ["mbw_strerror", "mbw_last_error", "mbw_index_build", "mbw_index_save", "mbw_index_load",
            "mbw_index_free", "mbw_index_info", "mbw_index_device_arrays", "mbw_ctx_create", "mbw_ctx_free",
-           "mbw_seed", "mbw_result_download", "mbw_pos_to_ref", "mbw_probe_copy", "mbw_probe_gather", "mbw_tune",
+           "mbw_seed", "mbw_result_download", "mbw_pos_to_ref", "mbw_tune",
            "mbw_result_download_pieces", "mbw_serve_open", "mbw_serve_submit", "mbw_serve_wait", "mbw_serve_release", "mbw_serve_stats",
            "mbw_serve_close", "mbw_rescue_filter", "mbw_rescue_download", "mbw_debug_set_mem_limit"]
 
@@ -50,14 +50,14 @@ class MbwError(RuntimeError):
 
 class BuildOpts(C.Structure):
     _fields_ = [("sa_sample", C.c_int), ("kmer_k", C.c_int), ("bisulfite", C.c_int), ("ref_is_codes", C.c_int),
-                ("rng_seed", C.c_uint64), ("device", C.c_int), ("isa_sample", C.c_int)]
+                ("rng_seed", C.c_uint64), ("device", C.c_int), ("isa_sample", C.c_int), ("sb_lines_log2", C.c_int)]
 
 
 class IndexInfo(C.Structure):
     _fields_ = [("n", C.c_uint64), ("len_r", C.c_uint64), ("primary", C.c_uint64), ("n_lines", C.c_uint64),
                 ("bytes_resident", C.c_uint64), ("C", C.c_uint64 * 5), ("bases_per_line", C.c_int),
                 ("line_bytes", C.c_int), ("sa_sample", C.c_int), ("kmer_k", C.c_int), ("bisulfite", C.c_int),
-                ("device", C.c_int), ("isa_sample", C.c_int)]
+                ("device", C.c_int), ("isa_sample", C.c_int), ("sb_lines_log2", C.c_int), ("n_superblocks", C.c_int)]
 
 
 class SeedOpts(C.Structure):
@@ -134,8 +134,6 @@ def load_library():
     L.mbw_result_download.argtypes = [vp, C.POINTER(Result), vp, vp]
     L.mbw_result_download_pieces.argtypes = [vp, C.POINTER(Result), vp]
     L.mbw_pos_to_ref.argtypes = [vp, u64, C.c_uint32, C.POINTER(C.c_int), C.POINTER(C.c_uint64)]
-    L.mbw_probe_copy.argtypes = [i32, u64, C.POINTER(C.c_float)]
-    L.mbw_probe_gather.argtypes = [i32, u64, i32, C.POINTER(C.c_double), C.POINTER(C.c_float)]
     L.mbw_tune.argtypes = [vp, vp, vp, u64, i32, i32, C.POINTER(SeedOpts), vp, C.POINTER(SeedOpts), C.POINTER(C.c_float)]
     L.mbw_serve_open.argtypes = [vp, C.POINTER(ServeCfg), C.POINTER(vp)]
     L.mbw_serve_submit.argtypes = [vp, vp, vp, u64, C.POINTER(C.c_uint64)]
@@ -213,9 +211,10 @@ class Index:
 
     @classmethod
     def build(cls, ref, sa_sample: int = 8, kmer_k: int = 10, bisulfite: bool = False, device: int = 0,
-              rng_seed: int = 0, isa_sample: int = 4):
+              rng_seed: int = 0, isa_sample: int = 4, sb_lines_log2: int = 0):
         """``ref``: numpy uint8 codes 0..3 or ASCII bytes / str.  ``isa_sample`` > 0 also keeps the
-        packed text and inverse-SA samples for direct extension of unique matches."""
+        packed text and inverse-SA samples for direct extension of unique matches.
+        ``sb_lines_log2``: occurrence lines per superblock as a power of two (0 = 2^23)."""
         L = load_library()
         if isinstance(ref, str):
             ref = ref.encode()
@@ -226,7 +225,7 @@ class Index:
             arr = np.ascontiguousarray(ref, dtype=np.uint8)
             codes = 1
         o = BuildOpts(int(sa_sample), int(kmer_k), int(bool(bisulfite)), codes, int(rng_seed), int(device),
-                      int(isa_sample))
+                      int(isa_sample), int(sb_lines_log2))
         h = C.c_void_p()
         _check(L.mbw_index_build(arr.ctypes.data if arr.size else None, arr.size, C.byref(o), C.byref(h)))
         return cls(h)
@@ -450,20 +449,41 @@ def set_mem_limit(nbytes: int) -> None:
     _check(load_library().mbw_debug_set_mem_limit(int(nbytes)))
 
 
+_probe = None
+
+
+def _probe_library():
+    """The measurement helper library (libmbw_probe.so, built beside libmbw.so)."""
+    global _probe
+    if _probe is None:
+        path = os.path.join(HERE, "libmbw_probe.so")
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with `python -m paper_2606_15357_amd.build`")
+        P = C.CDLL(path)
+        P.mbwprobe_copy.argtypes = [C.c_int, C.c_uint64, C.POINTER(C.c_float)]
+        P.mbwprobe_gather.argtypes = [C.c_int, C.c_uint64, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_float)]
+        P.mbwprobe_last_error.restype = C.c_char_p
+        _probe = P
+    return _probe
+
+
+def _probe_check(rc):
+    if rc != 0:
+        raise MbwError(rc, _probe_library().mbwprobe_last_error().decode(errors="replace"))
+
+
 def probe_copy(nbytes: int = 1 << 30, device: int = 0) -> float:
     """Kernel time (ms) of one streaming copy of `nbytes` bytes (profiler counter calibration)."""
-    L = load_library()
     ms = C.c_float()
-    _check(L.mbw_probe_copy(int(device), int(nbytes), C.byref(ms)))
+    _probe_check(_probe_library().mbwprobe_copy(int(device), int(nbytes), C.byref(ms)))
     return ms.value
 
 
 def probe_gather(nbytes: int = 16 << 30, iters: int = 64, device: int = 0):
     """Random 128-byte lines served per second over a power-of-two buffer of at most `nbytes` (one
     lane per line, four dependent chains per lane)."""
-    L = load_library()
     lps, ms = C.c_double(), C.c_float()
-    _check(L.mbw_probe_gather(int(device), int(nbytes), int(iters), C.byref(lps), C.byref(ms)))
+    _probe_check(_probe_library().mbwprobe_gather(int(device), int(nbytes), int(iters), C.byref(lps), C.byref(ms)))
     return lps.value, ms.value
 
 

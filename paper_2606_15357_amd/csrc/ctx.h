@@ -25,7 +25,15 @@ struct mbw_ctx {
   // mate-rescue prefilter (its own buffers, so that it leaves the last seeding result intact)
   Buf rc_lens, rc_wide, rc_offs, rc_ascii, rc_cand, rc_ctl, rc_hits, rc_flags, rc_pass;
   hipEvent_t ev[8] = {};
+  // SMEM launches whose device time is still to be read: a start and an end event each, read once
+  // the host has waited for the stream anyway (no wait of its own per launch)
+  static const int kLaunchSlots = 8;
+  hipEvent_t lev[2 * kLaunchSlots] = {};
+  int n_pending = 0;
+  struct LaunchNote { int round, staged, grid; uint64_t queries; uint32_t chunk; };
+  LaunchNote pending[kLaunchSlots];
   hipStream_t cur = nullptr;   // stream of the current / last call
+  hipStream_t own = nullptr;   // the context's own stream: frees its buffers when it is destroyed
   unsigned long long host_ctl[MBW_CTL_WORDS];
   uint64_t *hfetch = nullptr;   // pinned host words that a kernel fills with the sizes the host waits for
   uint64_t *dfetch = nullptr;   // ... the same memory as the device addresses it

@@ -313,10 +313,10 @@ __global__ void k_line_counts(const uint8_t *__restrict__ B, uint64_t n, uint64_
 
 // line header: counts of A, C, G before the line, relative to the start of its superblock
 __global__ void k_line_headers(const uint64_t *__restrict__ pre /*4 x n_lines exclusive sums*/, uint64_t n_lines,
-                               const uint64_t *__restrict__ sbtab, uint4 *__restrict__ lines) {
+                               const uint64_t *__restrict__ sbtab, uint32_t sb_shift, uint4 *__restrict__ lines) {
   for (uint64_t L = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; L < n_lines; L += (uint64_t)gridDim.x * blockDim.x) {
     uint32_t *w = (uint32_t *)(lines + L * MBW_LINE_U4);
-    const uint64_t *t = sbtab + 8 * (L >> MBW_SB_SHIFT);
+    const uint64_t *t = sbtab + 8 * (L >> sb_shift);
     for (int a = 0; a < 3; ++a) w[a] = (uint32_t)(pre[a * n_lines + L] - t[a]);
   }
 }
@@ -503,8 +503,12 @@ static int build_kmer_table(mbw_index *ix, hipStream_t st) {
 static int build_lines(mbw_index *ix, const uint8_t *B, hipStream_t st) {
   uint64_t n = ix->n, nl = n / MBW_BPL + 1;
   ix->n_lines = nl;
-  ix->n_sb = (int)(((nl - 1) >> MBW_SB_SHIFT) + 1);
-  if (ix->n_sb > MBW_MAX_SB) { mbw_set_error("reference too large for the superblock table"); return MBW_E_INVAL; }
+  ix->n_sb = (int)(((nl - 1) >> ix->sb_shift) + 1);
+  if (ix->n_sb > MBW_MAX_SB) {
+    mbw_set_error("reference too large for the superblock table (" + std::to_string(ix->n_sb) + " superblocks of 2^" +
+                  std::to_string(ix->sb_shift) + " lines; at most " + std::to_string(MBW_MAX_SB) + ")");
+    return MBW_E_INVAL;
+  }
   TRY(hipMalloc((void **)&ix->lines, nl * MBW_LINE_BYTES));
   ix->bytes += nl * MBW_LINE_BYTES;
   DevBuf<uint64_t> cnt, pre;
@@ -524,7 +528,7 @@ static int build_lines(mbw_index *ix, const uint8_t *B, hipStream_t st) {
     TRY(hipMemcpyAsync(&tot[a], pre.p + a * nl + nl - 1, 8, hipMemcpyDeviceToHost, st));
     TRY(hipMemcpyAsync(&last[a], cnt.p + a * nl + nl - 1, 8, hipMemcpyDeviceToHost, st));
     for (int sb = 0; sb < ix->n_sb; ++sb)
-      TRY(hipMemcpyAsync(&ix->sb_host[8 * sb + a], pre.p + a * nl + ((uint64_t)sb << MBW_SB_SHIFT), 8,
+      TRY(hipMemcpyAsync(&ix->sb_host[8 * sb + a], pre.p + a * nl + ((uint64_t)sb << ix->sb_shift), 8,
                          hipMemcpyDeviceToHost, st));
   }
   TRY(hipStreamSynchronize(st));
@@ -537,7 +541,7 @@ static int build_lines(mbw_index *ix, const uint8_t *B, hipStream_t st) {
   TRY(hipMalloc((void **)&ix->sbtab, MBW_MAX_SB * 8 * sizeof(uint64_t)));
   ix->bytes += MBW_MAX_SB * 8 * sizeof(uint64_t);
   TRY(hipMemcpyAsync(ix->sbtab, ix->sb_host, MBW_MAX_SB * 8 * sizeof(uint64_t), hipMemcpyHostToDevice, st));
-  k_line_headers<<<grid_for(nl), 256, 0, st>>>(pre.p, nl, ix->sbtab, ix->lines);
+  k_line_headers<<<grid_for(nl), 256, 0, st>>>(pre.p, nl, ix->sbtab, (uint32_t)ix->sb_shift, ix->lines);
   TRY(hipGetLastError());
   TRY(hipStreamSynchronize(st));
   for (int a = 0; a < 4; ++a) tot[a] += last[a];
@@ -557,6 +561,9 @@ extern "C" int mbw_index_build(const uint8_t *ref, uint64_t len, const mbw_build
   if (opts->sa_sample < 1 || opts->sa_sample > 1024) { mbw_set_error("sa_sample must be in [1,1024]"); return MBW_E_INVAL; }
   if (opts->kmer_k < -1 || opts->kmer_k > 15) { mbw_set_error("kmer_k must be -1 or in [0,15]"); return MBW_E_INVAL; }
   if (opts->isa_sample < 0 || opts->isa_sample > 64) { mbw_set_error("isa_sample must be in [0,64]"); return MBW_E_INVAL; }
+  if (opts->sb_lines_log2 < 0 || opts->sb_lines_log2 > MBW_SB_SHIFT) {
+    mbw_set_error("sb_lines_log2 must be in [0," + std::to_string(MBW_SB_SHIFT) + "]"); return MBW_E_INVAL;
+  }
   TRY(hipSetDevice(opts->device));
   // host: codes, ambiguous bases -> random (counter-based SplitMix64), bisulfite conversion
   uint64_t lrp = opts->bisulfite ? 2 * len : len;
@@ -594,6 +601,7 @@ extern "C" int mbw_index_build(const uint8_t *ref, uint64_t len, const mbw_build
   ix->bisulfite = opts->bisulfite ? 1 : 0;
   ix->sa_sample = opts->sa_sample;
   ix->isa_sample = opts->isa_sample;
+  ix->sb_shift = opts->sb_lines_log2 ? opts->sb_lines_log2 : MBW_SB_SHIFT;
   uint64_t m = 2 * lrp, n = m + 1;
   ix->n = n;
   ix->kmer_k = opts->kmer_k;
@@ -720,6 +728,8 @@ extern "C" int mbw_index_info(const mbw_index *ix, mbw_index_info_t *o) {
   o->bases_per_line = MBW_BPL; o->line_bytes = MBW_LINE_BYTES; o->sa_sample = ix->sa_sample;
   o->kmer_k = ix->kmer_k; o->bisulfite = ix->bisulfite; o->device = ix->device;
   o->isa_sample = ix->isa_sample;
+  o->sb_lines_log2 = ix->sb_shift;
+  o->n_superblocks = ix->n_sb;
   return MBW_OK;
 }
 
@@ -748,7 +758,7 @@ extern "C" int mbw_pos_to_ref(const mbw_index *ix, uint64_t pos, uint32_t len, i
 // ---------------------------------------------------------------------------------------------
 // index files: header (magic, version, fields, FNV-1a of header and of each array) + arrays
 static const uint64_t kMagic = 0x3158444e4957424dull;  // "MBWINDX1"
-static const uint32_t kVersion = 5;
+static const uint32_t kVersion = 6;
 
 struct FileHeader {
   uint64_t magic;
@@ -757,7 +767,7 @@ struct FileHeader {
   uint64_t C[5];
   int32_t sa_sample, kmer_k, bisulfite, n_sb;
   uint64_t sb[MBW_MAX_SB * 8];
-  int32_t isa_sample, pad;
+  int32_t isa_sample, sb_shift;
   uint64_t n_text, n_isa, n_orig;
   uint64_t sum_lines, sum_ssa, sum_kmer, sum_text, sum_isa, sum_orig;
   uint64_t sum_header;
@@ -861,7 +871,7 @@ extern "C" int mbw_index_save(const mbw_index *ix, const char *path) {
   hd.sa_sample = ix->sa_sample; hd.kmer_k = ix->kmer ? ix->kmer_k : 0; hd.bisulfite = ix->bisulfite;
   hd.n_sb = ix->n_sb;
   memcpy(hd.sb, ix->sb_host, sizeof(hd.sb));
-  hd.isa_sample = ix->isa_sample; hd.n_text = ix->n_text; hd.n_isa = ix->n_isa; hd.n_orig = ix->n_orig;
+  hd.isa_sample = ix->isa_sample; hd.sb_shift = ix->sb_shift; hd.n_text = ix->n_text; hd.n_isa = ix->n_isa; hd.n_orig = ix->n_orig;
   Staging S;
   int r = S.init();
   if (r) return r;
@@ -893,10 +903,18 @@ extern "C" int mbw_index_load(const char *path, int device, mbw_index **out) {
   if (!f) { mbw_set_error(std::string("cannot open ") + path); return MBW_E_IO; }
   FileHeader hd;
   if (fread(&hd, sizeof(hd), 1, f) != 1) { fclose(f); mbw_set_error("short header"); return MBW_E_FORMAT; }
+  // every field is checked against the limits the builder applies before anything is allocated: the
+  // kernels index their LDS superblock table by line >> sb_shift, and row arithmetic assumes n < 2^39
+  bool c_ok = hd.C[0] == 0 && hd.C[1] == 1;   // C[$] = 0 and exactly one $ row
+  for (int a = 1; a < 4; ++a) c_ok = c_ok && hd.C[a] <= hd.C[a + 1];
+  c_ok = c_ok && hd.C[4] <= hd.n;
   if (hd.magic != kMagic || hd.version != kVersion || hd.bpl != MBW_BPL ||
-      hd.sum_header != fnv(&hd, offsetof(FileHeader, sum_header)) || hd.n_lines != hd.n / MBW_BPL + 1 ||
+      hd.sum_header != fnv(&hd, offsetof(FileHeader, sum_header)) || hd.n < 3 || hd.n >= (1ull << 39) ||
+      hd.len_r == 0 || hd.n != (hd.bisulfite ? 4 : 2) * hd.len_r + 1 || hd.primary >= hd.n || !c_ok ||
+      hd.n_lines != hd.n / MBW_BPL + 1 || hd.sb_shift < 1 || hd.sb_shift > MBW_SB_SHIFT || hd.n_sb < 1 ||
+      hd.n_sb > MBW_MAX_SB || (hd.bisulfite != 0 && hd.bisulfite != 1) ||
       hd.sa_sample < 1 || hd.sa_sample > 1024 || hd.n_ssa != (hd.n + hd.sa_sample - 1) / hd.sa_sample ||
-      hd.kmer_k < 0 || hd.kmer_k > 15 || hd.n_sb != (int)(((hd.n_lines - 1) >> MBW_SB_SHIFT) + 1) ||
+      hd.kmer_k < 0 || hd.kmer_k > 15 || hd.n_sb != (int)(((hd.n_lines - 1) >> hd.sb_shift) + 1) ||
       hd.isa_sample < 0 || hd.isa_sample > 64 ||
       (hd.isa_sample ? (hd.n_isa != (hd.n - 1) / hd.isa_sample + 1 || hd.n_text != (hd.n - 1 + 31) / 32 + 4)
                      : (hd.n_isa != 0 || hd.n_text != 0)) ||
@@ -922,6 +940,7 @@ extern "C" int mbw_index_load(const char *path, int device, mbw_index **out) {
   ix->n_ssa = hd.n_ssa; for (int a = 0; a < 5; ++a) ix->C[a] = hd.C[a];
   ix->sa_sample = hd.sa_sample; ix->kmer_k = hd.kmer_k; ix->bisulfite = hd.bisulfite;
   ix->n_sb = hd.n_sb;
+  ix->sb_shift = hd.sb_shift;
   memcpy(ix->sb_host, hd.sb, sizeof(hd.sb));
   ix->isa_sample = hd.isa_sample; ix->n_text = hd.n_text; ix->n_isa = hd.n_isa; ix->n_orig = hd.n_orig;
   rc = [&]() -> int {

@@ -3,9 +3,9 @@
 // Resident FM-index (paper Sections 2.1, 2.2 and 2.4; the line format is this library's own,
 // sized for gfx950 where a random HBM access moves one 128-byte L2 line):
 //   * occurrence lines, 128 bytes each (8 slices of 16 bytes), one per 384 rows of B:
-//       slice 0     u32 counts of A, C, G in B from the start of the line's superblock (2^23
-//                   lines) up to the line (the $ row is stored and counted as A; rank corrects
-//                   it), then sub-checkpoint 1
+//       slice 0     u32 counts of A, C, G in B from the start of the line's superblock (2^h
+//                   lines, h = 23 by default and smaller on request) up to the line (the $ row is
+//                   stored and counted as A; rank corrects it), then sub-checkpoint 1
 //       slice 1     sub-checkpoints 2, 3, 4, 5
 //                   (sub-checkpoint b: counts of A, C, G in the line's first 64 b rows, 9 bits
 //                   each at bits 0, 9, 18 of a u32)
@@ -30,8 +30,8 @@
 #define MBW_LINE_BYTES 128
 #define MBW_LINE_U4 8          // 16-byte slices per line
 #define MBW_BLK 64             // rows per block (one 16-byte slice)
-#define MBW_SB_SHIFT 23        // lines per superblock = 2^23 (3.2 G rows < 2^32)
-#define MBW_MAX_SB 8
+#define MBW_SB_SHIFT 23        // default and largest log2 of the lines per superblock (3.2 G rows < 2^32)
+#define MBW_MAX_SB 8           // superblocks an index may have (the table lives in LDS)
 #define MBW_MAX_READ 65535
 
 struct mbw_index {
@@ -40,6 +40,7 @@ struct mbw_index {
   uint64_t C[5];               // C[$], C[A], C[C], C[G], C[T]
   int sa_sample, kmer_k, bisulfite;
   int n_sb;
+  int sb_shift;                // log2 of the lines per superblock (1..MBW_SB_SHIFT)
   uint64_t sb_host[MBW_MAX_SB * 8];
   uint4 *lines;                // n_lines * 8
   uint64_t *ssa;               // n_ssa
@@ -65,6 +66,7 @@ struct IndexView {
   uint32_t r;
   int K;
   int n_sb;
+  uint32_t sb_shift;           // superblock of line L: L >> sb_shift
   const uint64_t *__restrict__ text;   // packed T without $ (nullptr when absent)
   const uint64_t *__restrict__ isa;    // isa[t / ri] = row of the suffix at t
   uint32_t ri;
@@ -77,7 +79,7 @@ static inline IndexView make_view(const mbw_index *ix) {
   v.lines = ix->lines; v.ssa = ix->ssa; v.kmer = ix->kmer; v.sbtab = ix->sbtab;
   v.n = ix->n; v.primary = ix->primary;
   for (int a = 0; a < 4; ++a) v.Cb[a] = ix->C[a + 1];
-  v.r = (uint32_t)ix->sa_sample; v.K = ix->kmer_k; v.n_sb = ix->n_sb;
+  v.r = (uint32_t)ix->sa_sample; v.K = ix->kmer_k; v.n_sb = ix->n_sb; v.sb_shift = (uint32_t)ix->sb_shift;
   v.text = ix->text; v.isa = ix->isa; v.ri = (uint32_t)ix->isa_sample;
   v.orig = ix->orig; v.len_r = ix->len_r;
   return v;
@@ -134,15 +136,16 @@ __device__ __forceinline__ uint32_t sub_word(uint4 h0, uint4 h1, int b) {
   return b == 0 ? 0u : (b == 1 ? h0.w : (b == 2 ? h1.x : (b == 3 ? h1.y : (b == 4 ? h1.z : h1.w))));
 }
 
-// Occ(c, x) (E) and sum_{d > c} Occ(d, x) (G), x at offset o of line L, from the line's two header
-// slices and the slice of block o / 64, and the superblock values sbe = count of c before the
-// superblock, sbg = sum over d > c of the counts before it.  The $ row is not corrected here.
-__device__ __forceinline__ void rank_eg(uint4 h0, uint4 h1, uint4 blk, uint32_t L, int o, int c, const SymMasks &sm,
+// Occ(c, x) (E) and sum_{d > c} Occ(d, x) (G), x at offset o of a line that is line Lrel of its
+// superblock, from the line's two header slices and the slice of block o / 64, and the superblock
+// values sbe = count of c before the superblock, sbg = sum over d > c of the counts before it.  The
+// $ row is not corrected here.
+__device__ __forceinline__ void rank_eg(uint4 h0, uint4 h1, uint4 blk, uint32_t Lrel, int o, int c, const SymMasks &sm,
                                         uint64_t sbe, uint64_t sbg, uint64_t &E, uint64_t &G) {
   const int b = o >> 6, r = o & 63;
   const uint32_t sw = sub_word(h0, h1, b);
   const uint32_t sA = sw & 511u, sC = (sw >> 9) & 511u, sG = (sw >> 18) & 511u;
-  const uint32_t rows = MBW_BPL * (L & ((1u << MBW_SB_SHIFT) - 1)) + MBW_BLK * b;   // rows before the block
+  const uint32_t rows = MBW_BPL * Lrel + MBW_BLK * b;   // rows of the superblock before the block
   const uint32_t tA = h0.x + sA, tC = h0.y + sC, tG = h0.z + sG, tT = rows - tA - tC - tG;
   uint32_t e, g;
   block_eg(blk, r, sm, e, g);
@@ -159,9 +162,10 @@ __device__ __forceinline__ int bwt_from_block(uint4 blk, int o) {
   return (int)(((lo >> (r & 31)) & 1u) | (((hi >> (r & 31)) & 1u) << 1));
 }
 
-// Superblock values for symbol c: count of c before superblock s, and the sum over d > c.
-__device__ __forceinline__ void sb_values(const uint64_t *sbtab, uint32_t line, int c, uint64_t &sbe, uint64_t &sbg) {
-  const uint64_t *t = sbtab + 8 * (line >> MBW_SB_SHIFT);
+// Superblock values for symbol c: count of c before the superblock of `line`, and the sum over d > c.
+__device__ __forceinline__ void sb_values(const uint64_t *sbtab, uint32_t line, uint32_t sb_shift, int c, uint64_t &sbe,
+                                          uint64_t &sbg) {
+  const uint64_t *t = sbtab + 8 * (line >> sb_shift);
   sbe = t[c];
   sbg = t[4 + c];
 }
@@ -192,8 +196,8 @@ __device__ __forceinline__ void rank_global(const IndexView &ix, uint64_t x, int
   const uint4 *ln = ix.lines + (uint64_t)L * MBW_LINE_U4;
   const uint4 h0 = ln[0], h1 = ln[1], blk = ln[2 + (o >> 6)];
   uint64_t sbe, sbg;
-  sb_values(ix.sbtab, L, c, sbe, sbg);
-  rank_eg(h0, h1, blk, L, o, c, sym_masks(c), sbe, sbg, E, G);
+  sb_values(ix.sbtab, L, ix.sb_shift, c, sbe, sbg);
+  rank_eg(h0, h1, blk, L & ((1u << ix.sb_shift) - 1), o, c, sym_masks(c), sbe, sbg, E, G);
 }
 
 // B[x] from global memory

@@ -13,10 +13,11 @@
 //
 // Two kernel families run the smem and locate steps:
 //   * wave (default): persistent kernels in which every lane owns one query (or one locate walk)
-//     and each iteration has exactly one memory phase: the wave fetches all occurrence lines it
-//     needs cooperatively (eight lanes per 128-byte line, straight into LDS), together with k-mer
-//     table entries, the records of new queries and the words of reads being staged; then each
-//     lane ranks its own line from LDS.  Reads of up to 160 bases are staged in LDS.
+//     and each iteration has exactly one memory phase: every lane issues the loads its step needs
+//     (the three 16-byte slices of each occurrence line its rank reads, into registers), k-mer
+//     table entries, records of new queries and the words of reads being staged (those three
+//     straight into LDS), and the wave waits once; then each lane ranks from its own registers.
+//     Reads of up to 160 bases are staged in LDS for the whole query.
 //   * plain (the baseline): one thread runs the serial algorithm for one read (round 2 inline) and
 //     one thread locates one seed; ranks read their line straight from global memory.
 #include <hip/hip_runtime.h>
@@ -358,6 +359,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
   if (threadIdx.x < 4) scb[threadIdx.x] = ix.Cb[threadIdx.x];
   __syncthreads();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t sbm = (1u << ix.sb_shift) - 1;   // line index within its superblock
   uint32_t *mwl = swl[wv], *mwh = swh[wv];
   uint32_t *mn = sn[wv];
   const int K = (P.use_kmer && ix.kmer) ? ix.K : 0;
@@ -487,15 +489,19 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
     const bool selig = (act == ACT_BWD && (u == 1 || u == 3)) || (act == ACT_FWD && u == 2);
     const uint64_t sbusy = __ballot(st != ST_DRAINED);
     if (sbusy != 0 && __ballot(selig) == sbusy) {
-      // Tail of a launch: the queue is exhausted and every working lane of the wave is extending,
-      // so their extension steps (backward in stages 1 and 3, forward in stage 2) run back to back
-      // here, without the rest of the iteration (the same steps in the same order), until the
-      // first lane stops: a failing step, a non-ACGT base, the end of the stage and a unique match
-      // (s = 1, for the unique-match path) are left to the next iteration, as is a step beyond
-      // SOLO_STEPS.
+      // Every lane of the wave that still has work is extending (backward in stages 1 and 3,
+      // forward in stage 2), and none takes a query, stages a read or loads a record: their
+      // extension steps run back to back here, without the rest of the iteration (the same steps
+      // in the same order), until the first lane stops: a failing step, a non-ACGT base, the end of
+      // the stage and a unique match (s = 1, for the unique-match path) are left to the next
+      // iteration, as is a step beyond SOLO_STEPS or the lane's work budget.  This happens mid-launch
+      // whenever all 64 lanes extend at once, and always at the end of a launch, where the queue is
+      // exhausted and a few long queries are left.  Each step counts against the query's budget and
+      // its chain length like an iteration.
       const bool sbwd = act == ACT_BWD;
       bool go = selig;
       for (int t = 0; t < SOLO_STEPS; ++t) {
+        if (go && budget <= 1) go = false;             // the guard of the main loop decides
         if (go) {
           const int sc = sbwd ? a : 3 - a;
           const uint64_t sx1 = sbwd ? k : kr, sx2 = sx1 + s, sy = sbwd ? kr : k;
@@ -506,15 +512,17 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
           const uint4 g0 = p1[0], g1 = p1[1], gb = p1[2 + (so1 >> 6)];
           const uint4 q0 = stwo ? p2[0] : g0, q1 = stwo ? p2[1] : g1, qb = sblk2 ? p2[2 + (so2 >> 6)] : gb;
           const SymMasks ssm = sym_masks(sc);
-          const uint32_t sb1 = 8 * (sL1 >> MBW_SB_SHIFT), sb2 = 8 * (sL2 >> MBW_SB_SHIFT);
+          const uint32_t sb1 = 8 * (sL1 >> ix.sb_shift), sb2 = 8 * (sL2 >> ix.sb_shift);
           uint64_t E1, G1, E2, G2, nx, ny, ns;
-          rank_eg(g0, g1, gb, sL1, so1, sc, ssm, sbt[sb1 + sc], sbt[sb1 + 4 + sc], E1, G1);
-          rank_eg(q0, q1, qb, sL2, so2, sc, ssm, sbt[sb2 + sc], sbt[sb2 + 4 + sc], E2, G2);
+          rank_eg(g0, g1, gb, sL1 & sbm, so1, sc, ssm, sbt[sb1 + sc], sbt[sb1 + 4 + sc], E1, G1);
+          rank_eg(q0, q1, qb, sL2 & sbm, so2, sc, ssm, sbt[sb2 + sc], sbt[sb2 + 4 + sc], E2, G2);
           ext_update(E1, G1, E2, G2, sc, sx1, s, sy, ix.primary, scb[sc], nx, ny, ns);
           if (ns < c) go = false;
           else {
             n_lines += stwo ? 2 : 1;
             ++n_steps;
+            --budget;
+            ++chain;
             if (sbwd) { k = nx; kr = ny; j -= 1; }
             else { kr = nx; k = ny; j += 1; }
             s = ns;
@@ -528,6 +536,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
         }
         if (__ballot(selig && !go)) break;
       }
+      max_chain = chain > max_chain ? chain : max_chain;
     }
     const bool ext = act == ACT_BWD || act == ACT_FWD;
     const bool bwd = act == ACT_BWD;
@@ -591,10 +600,10 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
       if (!blk2) bb = ba;
       const int cx2 = lf2 ? bwt_from_block(bb, o2) : cx;   // the second walk ranks its own row's symbol
       const SymMasks sm = sym_masks(cx), sm2 = sym_masks(cx2);
-      const uint32_t sb1 = 8 * (L1 >> MBW_SB_SHIFT), sb2 = 8 * (L2 >> MBW_SB_SHIFT);
+      const uint32_t sb1 = 8 * (L1 >> ix.sb_shift), sb2 = 8 * (L2 >> ix.sb_shift);
       uint64_t E1, G1, E2, G2;
-      rank_eg(h0a, h1a, ba, L1, o1, cx, sm, sbt[sb1 + cx], sbt[sb1 + 4 + cx], E1, G1);
-      rank_eg(h0b, h1b, bb, L2, o2, cx2, sm2, sbt[sb2 + cx2], sbt[sb2 + 4 + cx2], E2, G2);
+      rank_eg(h0a, h1a, ba, L1 & sbm, o1, cx, sm, sbt[sb1 + cx], sbt[sb1 + 4 + cx], E1, G1);
+      rank_eg(h0b, h1b, bb, L2 & sbm, o2, cx2, sm2, sbt[sb2 + cx2], sbt[sb2 + 4 + cx2], E2, G2);
       uint64_t nx, ny, ns;
       ext_update(E1, G1, E2, G2, cx, x1, lfa ? 0ull : s, y, ix.primary, scb[cx], nx, ny, ns);
       if (lf2) {                                          // LF of both rows; the $ row maps to row 0
@@ -1019,6 +1028,7 @@ __global__ void __launch_bounds__(256) k_locate_wave(IndexView ix, const uint64_
   for (int t = threadIdx.x; t < 8 * ix.n_sb; t += blockDim.x) sbt[t] = ix.sbtab[t];
   __syncthreads();
   const int lane = threadIdx.x & 63;
+  const uint32_t sbm = (1u << ix.sb_shift) - 1;
   enum { W_NONE = 0, W_WALK = 1 };
   enum { P_NONE = 0, P_PENDING = 1, P_READY = 2 };
   int cur = W_NONE, pre = P_NONE;
@@ -1066,9 +1076,9 @@ __global__ void __launch_bounds__(256) k_locate_wave(IndexView ix, const uint64_
     }
     if (need) {
       const int b = bwt_from_block(blk, o);
-      const uint32_t sbi = 8 * (L >> MBW_SB_SHIFT);
+      const uint32_t sbi = 8 * (L >> ix.sb_shift);
       uint64_t E, G;
-      rank_eg(h0, h1, blk, L, o, b, sym_masks(b), sbt[sbi + b], sbt[sbi + 4 + b], E, G);
+      rank_eg(h0, h1, blk, L & sbm, o, b, sym_masks(b), sbt[sbi + b], sbt[sbi + 4 + b], E, G);
       if (b == 0 && x > ix.primary) E -= 1;
       x = sel4(ix.Cb[0], ix.Cb[1], ix.Cb[2], ix.Cb[3], b) + E;
       ++steps; ++lines; ++lf;
@@ -1184,8 +1194,13 @@ extern "C" int mbw_ctx_create(const mbw_index *ix, mbw_ctx **out) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, ix->device) != hipSuccess) { delete c; mbw_set_error("hipGetDeviceProperties failed"); return MBW_E_HIP; }
   c->n_cu = prop.multiProcessorCount;
+  if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess) {
+    c->own = nullptr; mbw_ctx_free(c); mbw_set_error("hipStreamCreate failed"); return MBW_E_HIP;
+  }
   for (int t = 0; t < 8; ++t)
     if (hipEventCreate(&c->ev[t]) != hipSuccess) { mbw_ctx_free(c); mbw_set_error("hipEventCreate failed"); return MBW_E_HIP; }
+  for (int t = 0; t < 2 * mbw_ctx::kLaunchSlots; ++t)
+    if (hipEventCreate(&c->lev[t]) != hipSuccess) { mbw_ctx_free(c); mbw_set_error("hipEventCreate failed"); return MBW_E_HIP; }
   {
     // keep memory freed by growing buffers in the device's pool instead of returning it at every sync
     hipMemPool_t pool;
@@ -1206,12 +1221,23 @@ extern "C" int mbw_ctx_create(const mbw_index *ix, mbw_ctx **out) {
   return MBW_OK;
 }
 
+// Entry points wait for their stream before they return, except when they fail part way; the
+// device-wide wait covers that case without touching the caller's last stream (which may be gone).
+// The buffers are then freed on the context's own stream and the device's pool gives the freed
+// memory back.
 extern "C" void mbw_ctx_free(mbw_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
-  for (auto *b : c->buffers()) if (b->p) (void)hipFreeAsync(b->p, c->cur);
-  (void)hipStreamSynchronize(c->cur);
+  (void)hipDeviceSynchronize();
+  if (c->own) {
+    for (auto *b : c->buffers()) if (b->p) (void)hipFreeAsync(b->p, c->own);
+    (void)hipStreamSynchronize(c->own);
+    (void)hipStreamDestroy(c->own);
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, c->device) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
+  }
   for (int t = 0; t < 8; ++t) if (c->ev[t]) (void)hipEventDestroy(c->ev[t]);
+  for (int t = 0; t < 2 * mbw_ctx::kLaunchSlots; ++t) if (c->lev[t]) (void)hipEventDestroy(c->lev[t]);
   if (c->hfetch) (void)hipHostFree(c->hfetch);
   delete c;
 }
@@ -1273,6 +1299,22 @@ static bool trace_on() {
   return on;
 }
 
+// Device times of the SMEM launches recorded so far, read after the host has waited for the
+// stream (every launch is followed by such a wait before its slot could be needed again).
+static int flush_launch_times(mbw_ctx *c) {
+  for (int t = 0; t < c->n_pending; ++t) {
+    float ms = 0;
+    TRY(hipEventElapsedTime(&ms, c->lev[2 * t], c->lev[2 * t + 1]));
+    c->ms_smem += ms;
+    const mbw_ctx::LaunchNote &n = c->pending[t];
+    if (trace_on())
+      fprintf(stderr, "{\"mbw\": \"smem_launch\", \"round\": %d, \"staged\": %d, \"queries\": %llu, \"blocks\": %d, "
+              "\"chunk\": %u, \"ms\": %.3f}\n", n.round, n.staged, (unsigned long long)n.queries, n.grid, n.chunk, ms);
+  }
+  c->n_pending = 0;
+  return 0;
+}
+
 static int run_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const ReadWords &R, const mbw_seed_opts &o, bool staged,
                     hipStream_t st) {
   if (P.n_queries == 0) return 0;
@@ -1284,18 +1326,18 @@ static int run_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const ReadWor
     uint64_t ch = P.n_queries / (waves * 8);
     P.chunk = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(WORK_CHUNK, ch));
   }
-  TRY(hipEventRecord(c->ev[1], st));
+  if (c->n_pending == mbw_ctx::kLaunchSlots) {   // not reached by mbw_seed's launch sequence
+    TRY(hipStreamSynchronize(st));
+    int r = flush_launch_times(c);
+    if (r) return r;
+  }
+  const int slot = c->n_pending++;
+  c->pending[slot] = {P.round, (int)staged, grid, P.n_queries, P.chunk};
+  TRY(hipEventRecord(c->lev[2 * slot], st));
   int r = launch_smem(v, P, R, o, staged, grid, st);
   if (r) return r;
-  TRY(hipEventRecord(c->ev[2], st));
-  TRY(hipEventSynchronize(c->ev[2]));
-  float ms = 0;
-  TRY(hipEventElapsedTime(&ms, c->ev[1], c->ev[2]));
-  c->ms_smem += ms;
+  TRY(hipEventRecord(c->lev[2 * slot + 1], st));
   c->n_smem_launches++;
-  if (trace_on())
-    fprintf(stderr, "{\"mbw\": \"smem_launch\", \"round\": %d, \"staged\": %d, \"queries\": %llu, \"blocks\": %d, \"chunk\": %u, "
-            "\"ms\": %.3f}\n", P.round, (int)staged, (unsigned long long)P.n_queries, grid, P.chunk, ms);
   return 0;
 }
 
@@ -1339,7 +1381,7 @@ static int fetch(mbw_ctx *c, hipStream_t st, std::initializer_list<FetchItem> it
   TRY(hipGetLastError());
   TRY(hipStreamSynchronize(st));
   for (int t = 0; t < f.n; ++t) out[t] = ((volatile uint64_t *)c->hfetch)[t];
-  return 0;
+  return flush_launch_times(c);
 }
 #define FETCH(...) do { int r_ = fetch(c, st, __VA_ARGS__); if (r_) return r_; } while (0)
 
@@ -1398,6 +1440,7 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   TRY(hipMemsetAsync(ctl, 0, C_COUNT * sizeof(unsigned long long), st));
   c->ms_smem = 0;
   c->n_smem_launches = 0;
+  c->n_pending = 0;
   TRY(hipEventRecord(c->ev[0], st));
   if (n_reads == 0) {
     TRY(hipStreamSynchronize(st));
@@ -1719,6 +1762,8 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     TRY(hipGetLastError());
     TRY(hipStreamSynchronize(st));
     for (int t = 0; t < C_COUNT; ++t) c->host_ctl[t] = ((volatile uint64_t *)c->hfetch)[t];
+    r = flush_launch_times(c);
+    if (r) return r;
   }
   if (c->host_ctl[C_ERR]) {
     mbw_set_error(std::string("kernel guard tripped (") + std::to_string(c->host_ctl[C_ERR]) + "): corrupt index or internal error");

@@ -1,13 +1,22 @@
-// Diagnostics beside the seeding path: a streaming copy (to calibrate the HBM byte counters of the
-// profiler against a known size) and a random 128-byte line gather (the rate at which this GPU
-// serves independent random line accesses, the ceiling the seeding kernels are compared with).
+// Measurement helpers beside the seeding library (built into libmbw_probe.so, not libmbw.so): a
+// streaming copy (to calibrate the HBM byte counters of the profiler against a known size) and a
+// random 128-byte line gather (the rate at which this GPU serves independent random line accesses,
+// the ceiling the seeding kernels are compared with).
+//
+// C ABI (status 0 on success, -1 bad argument, -2 out of memory, -3 HIP error; message from
+// mbwprobe_last_error()):
+//   int mbwprobe_copy(int device, uint64_t bytes, float *ms)
+//       streams `bytes` bytes (>= 4096) from one buffer to another once; *ms = kernel time.
+//   int mbwprobe_gather(int device, uint64_t bytes, int iters, double *lines_per_s, float *ms)
+//       every lane follows four chains of random 128-byte lines (16 bytes read per line) over the
+//       largest power-of-two number of lines that fits in `bytes` (>= 1 MiB), `iters` dependent
+//       fetches per chain; *lines_per_s = random lines served per second.
+// Both allocate and free their own device memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <string>
-
-#include "mbw_internal.h"
-#include "../../include/mbw.h"
 
 namespace {
 
@@ -35,15 +44,26 @@ __global__ void k_probe_gather(const uint4 *__restrict__ buf, uint32_t mask, int
 
 }  // namespace
 
-#define TRY(call) MBW_HIP_TRY(call)
+static thread_local std::string g_probe_err;
+static void set_error(const std::string &m) { g_probe_err = m; }
+extern "C" const char *mbwprobe_last_error(void) { return g_probe_err.c_str(); }
 
-extern "C" int mbw_probe_copy(int device, uint64_t bytes, float *ms) {
-  if (!ms || bytes < 4096) { mbw_set_error("bad probe arguments"); return MBW_E_INVAL; }
+#define TRY(call)                                                                          \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess) {                                                                \
+      set_error(std::string(#call) + ": " + hipGetErrorString(e_));                        \
+      return e_ == hipErrorOutOfMemory ? -2 : -3;                                          \
+    }                                                                                      \
+  } while (0)
+
+extern "C" int mbwprobe_copy(int device, uint64_t bytes, float *ms) {
+  if (!ms || bytes < 4096) { set_error("bad probe arguments"); return -1; }
   TRY(hipSetDevice(device));
   const uint64_t n = bytes / 16;
   uint4 *a = nullptr, *b = nullptr;
   TRY(hipMalloc((void **)&a, n * 16));
-  if (hipMalloc((void **)&b, n * 16) != hipSuccess) { (void)hipFree(a); mbw_set_error("hipMalloc failed"); return MBW_E_NOMEM; }
+  if (hipMalloc((void **)&b, n * 16) != hipSuccess) { (void)hipFree(a); set_error("hipMalloc failed"); return -2; }
   hipEvent_t e0, e1;
   int rc = [&]() -> int {
     TRY(hipMemset(a, 1, n * 16));
@@ -64,8 +84,8 @@ extern "C" int mbw_probe_copy(int device, uint64_t bytes, float *ms) {
   return rc;
 }
 
-extern "C" int mbw_probe_gather(int device, uint64_t bytes, int iters, double *lines_per_s, float *ms) {
-  if (!lines_per_s || !ms || bytes < (1u << 20) || iters < 1) { mbw_set_error("bad probe arguments"); return MBW_E_INVAL; }
+extern "C" int mbwprobe_gather(int device, uint64_t bytes, int iters, double *lines_per_s, float *ms) {
+  if (!lines_per_s || !ms || bytes < (1u << 20) || iters < 1) { set_error("bad probe arguments"); return -1; }
   TRY(hipSetDevice(device));
   uint64_t nlines = 1;                                   // a power of two, at most bytes / 128 and 2^32
   while (nlines * 2 <= bytes / 128 && nlines < (1ull << 32)) nlines *= 2;
@@ -74,7 +94,7 @@ extern "C" int mbw_probe_gather(int device, uint64_t bytes, int iters, double *l
   uint4 *buf = nullptr;
   uint64_t *out = nullptr;
   TRY(hipMalloc((void **)&buf, nlines * 128));
-  if (hipMalloc((void **)&out, (uint64_t)grid * block * 8) != hipSuccess) { (void)hipFree(buf); mbw_set_error("hipMalloc failed"); return MBW_E_NOMEM; }
+  if (hipMalloc((void **)&out, (uint64_t)grid * block * 8) != hipSuccess) { (void)hipFree(buf); set_error("hipMalloc failed"); return -2; }
   hipEvent_t e0, e1;
   int rc = [&]() -> int {
     TRY(hipMemset(buf, 0x5a, nlines * 128));

@@ -62,13 +62,13 @@ def read_index_file(path):
     if K:
         kmer = np.frombuffer(raw, dtype=np.uint64, count=2 * 4 ** K, offset=off).reshape(-1, 2)
         off += 16 * 4 ** K
-    isa_sample, _pad, n_text, n_isa, n_orig = h[17 + 8 * MAX_SB:22 + 8 * MAX_SB]
+    isa_sample, sb_shift, n_text, n_isa, n_orig = h[17 + 8 * MAX_SB:22 + 8 * MAX_SB]
     text = np.frombuffer(raw, dtype=np.uint64, count=n_text, offset=off)
     off += 8 * n_text
     isa = np.frombuffer(raw, dtype=np.uint64, count=n_isa, offset=off)
     off += 8 * n_isa
     orig = np.frombuffer(raw, dtype=np.uint64, count=n_orig, offset=off)
-    return dict(n=n, len_r=len_r, primary=primary, n_lines=n_lines, C=C5, r=r, K=K, sb=sb, bis=bis,
+    return dict(n=n, len_r=len_r, primary=primary, n_lines=n_lines, C=C5, r=r, K=K, sb=sb, bis=bis, sb_shift=sb_shift,
                 lines=lines, ssa=ssa, kmer=kmer, bpl=bpl, isa_sample=isa_sample, text=text, isa=isa, orig=orig)
 
 

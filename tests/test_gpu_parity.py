@@ -88,7 +88,7 @@ def test_index_structure(name, r, K, ri):
     for L in range(f["n_lines"]):
         lo = L * 384
         for a in range(3):
-            assert int(f["sb"][L >> 23][a]) + int(w32[L, a]) == int(np.sum(Braw[:lo] == a))
+            assert int(f["sb"][L >> f["sb_shift"]][a]) + int(w32[L, a]) == int(np.sum(Braw[:lo] == a))
         for b in range(1, 6):
             if lo + 64 * b > f["n"]:
                 continue
@@ -390,5 +390,109 @@ def test_bisulfite_refinement():
                 assert np.array_equal(got[fld], exp[fld]), fld
             # the source seed: same (read, interval) family
             assert np.all(seeds["read_id"][got["seed"]] == got["read_id"])
+            ctx.free()
+    idx.free()
+
+
+# ---------------------------------------------------------------------------------------------
+# several superblocks on small references: the row arithmetic past the first superblock (counts
+# relative to a superblock, the superblock table, lines on both sides of a boundary) that the
+# 3.1 Gbp indexes need, checked against the definition oracle with every field compared
+
+@pytest.mark.parametrize("kernel,K,ri,uniq", [(0, 10, 4, True), (0, 10, 4, False), (0, 0, 1, True), (1, 10, 4, True),
+                                              (0, 15, 4, True), (1, 0, 0, True)])
+def test_multi_superblock_parity(cfg0, kernel, K, ri, uniq):
+    """The 1 Mbp workload on an index with 2^10 lines (393,216 rows) per superblock, so that its
+    2,080,001 rows span 6 superblocks: every seed, ds-interval (k, k', s) and position of all
+    10,000 reads equals O1's, with and without the unique-match path."""
+    ref, reads, ox, exp = cfg0
+    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=K, isa_sample=ri, sb_lines_log2=10)
+    info = idx.info()
+    assert info["sb_lines_log2"] == 10 and info["n_superblocks"] == 6
+    out, seeds, pos = gpu_seed(idx, reads, min_seed_len=19, max_occ=500, kernel=kernel, unique_ext=uniq)
+    compare_with_oracle(seeds, pos, exp)
+    # seeds whose intervals lie wholly past the first superblock (k and k + s above 393,216)
+    assert np.sum(seeds["k"] > 393_216 * 2) > 1000
+    idx.free()
+
+
+def test_multi_superblock_structure_and_tiny_seeding():
+    """A 60 kbp reference (random with repeats) indexed with 2^6 lines (24,576 rows) per superblock
+    (5 superblocks): the stored superblock table and every line header equal prefix counts of the
+    oracle's BWT, the 6-mer table equals the oracle's intervals, the file round trip keeps the
+    superblock size, and seeding with (l, c) in {(12,1), (15,2), (10,3)} equals O1 for both kernels,
+    segmented and not."""
+    ref = synth.reference(0, 20_000, 41)
+    R = ref.codes
+    ox = oracle.OracleIndex(R, sa_rate=4)
+    idx = mbw.Index.build(R, sa_sample=4, kmer_k=6, isa_sample=2, sb_lines_log2=6)
+    info = idx.info()
+    assert info["n_superblocks"] == ((info["n_lines"] - 1) >> 6) + 1 >= 3
+    with tempfile.TemporaryDirectory() as d:
+        p = os.path.join(d, "sb.mbw")
+        idx.save(p)
+        f = read_index_file(p)
+        idx2 = mbw.Index.load(p)
+        assert idx2.info()["sb_lines_log2"] == 6 and idx2.info()["n_superblocks"] == info["n_superblocks"]
+    assert f["sb_shift"] == 6
+    B = ox.bwt().astype(np.int64) - 1
+    B[ox.primary] = 0
+    assert np.array_equal(decode_bwt(f), B.astype(np.uint8))
+    cum = np.zeros((4, B.size + 1), np.int64)
+    for a in range(4):
+        cum[a, 1:] = np.cumsum(B == a)
+    for sb in range(info["n_superblocks"]):
+        row = min(sb * 64 * 384, B.size)
+        assert [int(f["sb"][sb][a]) for a in range(4)] == [int(cum[a, row]) for a in range(4)]
+        assert [int(f["sb"][sb][4 + c]) for c in range(4)] == [int(sum(cum[d, row] for d in range(c + 1, 4)))
+                                                               for c in range(4)]
+    w32 = f["lines"].view(np.uint32).reshape(f["n_lines"], 32)
+    for L in range(f["n_lines"]):
+        lo = L * 384
+        for a in range(3):
+            assert int(f["sb"][L >> 6][a]) + int(w32[L, a]) == int(cum[a, lo])
+    for code in range(4 ** 6):
+        kmer = "".join(ACGT[(code >> (2 * q)) & 3] for q in range(6))
+        exp = ox.interval(kmer)
+        got = unpack_kmer(f["kmer"][code])
+        assert got[2] == exp[2] and (exp[2] == 0 or got == exp), (kmer, got, exp)
+    rs = synth.reads_uniform_len(ref, 400, 1, 200, seed=42)
+    for ix_ in (idx, idx2):
+        for (l, c) in [(12, 1), (15, 2), (10, 3)]:
+            exp = ox.seed(rs.seq, rs.offsets, min_len=l, min_occ=c, max_occ=10 ** 6, reseed=True, reseed_len=2 * l,
+                          reseed_occ=3)
+            for kernel, extra in ((0, {}), (1, {}), (0, dict(stage=False, seg_len=32))):
+                out, seeds, pos = gpu_seed(ix_, rs, min_seed_len=l, min_occ=c, max_occ=10 ** 6, reseed=True,
+                                           reseed_len=2 * l, reseed_occ=3, kernel=kernel, **extra)
+                compare_with_oracle(seeds, pos, exp)
+    idx2.free()
+    idx.free()
+
+
+def test_multi_superblock_bisulfite():
+    """A bisulfite (four-copy) index of 200 kbp with 2^8 lines per superblock (800,001 rows in 9
+    superblocks would exceed the table, so 2^9: 5 superblocks): both read roles, both kernels,
+    with refinement, equal the oracle; an index that would need more than 8 superblocks is
+    refused."""
+    ref = synth.reference(0, 200_000, 31)
+    with pytest.raises(mbw.MbwError) as e:
+        mbw.Index.build(ref.codes, sa_sample=8, kmer_k=10, bisulfite=True, sb_lines_log2=8)
+    assert e.value.code == mbw.MBW_E_INVAL and "superblock" in str(e.value)
+    ox = oracle.OracleIndex(ref.codes, bisulfite=True, sa_rate=8)
+    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=10, bisulfite=True, sb_lines_log2=9)
+    assert idx.info()["n_superblocks"] == 5
+    rs = synth.reads_bisulfite(ref, 2000, seed=5)
+    for role in (1, 2):
+        exp = ox.seed(rs.seq, rs.offsets, bs_role=role)
+        pieces = oracle.bs_refine(ref.codes, rs.seq, rs.offsets, exp, role, min_len=19)
+        for kernel in (0, 1):
+            ctx = mbw.Context(idx)
+            out = ctx.seed(rs.seq, rs.lengths, bs_role=role, kernel=kernel, bs_refine=True)
+            seeds, pos = out.download()
+            compare_with_oracle(seeds, pos, exp)
+            got = out.download_pieces()
+            got = got[np.lexsort((got["pos"], got["qend"], got["qbeg"], got["read_id"]))]
+            for fld in ("read_id", "qbeg", "qend", "pos"):
+                assert np.array_equal(got[fld], pieces[fld]), fld
             ctx.free()
     idx.free()
