@@ -14,8 +14,10 @@ Three oracles:
     definitions (Section 2.2).  For references too large to sort on the host; ds-interval bounds
     are not produced (k = k' = 2^64 - 1).
 
-Also: ``bs_refine`` (Section 2.9 seed refinement at read-C-over-reference-T bases) and
-``rescue`` / ``rescue_diagonals`` (Section 2.7 mate-rescue prefilter, M_t counted pair by pair).
+Also: ``bs_refine`` (Section 2.9 seed refinement at read-C-over-reference-T bases),
+``rescue`` / ``rescue_diagonals`` (Section 2.7 mate-rescue prefilter, M_t counted pair by pair) and
+``chain`` / ``chain_dp`` (Section 2.6: minimap2's chaining recurrence over variable-length seeds,
+up to 50 chains per read).
 """
 from __future__ import annotations
 
@@ -44,6 +46,10 @@ class _Opts(C.Structure):
     _fields_ = [("min_len", C.c_int), ("min_occ", C.c_int), ("max_occ", C.c_int), ("reseed", C.c_int),
                 ("reseed_len", C.c_int), ("reseed_occ", C.c_int), ("bs_role", C.c_int),
                 ("method", C.c_int), ("kmer_k", C.c_int), ("bases_per_line", C.c_int)]
+
+
+class _ChainOpts(C.Structure):
+    _fields_ = [("max_gap", C.c_int), ("max_pred", C.c_int), ("max_chains", C.c_int), ("min_score", C.c_int)]
 
 
 def _load():
@@ -85,6 +91,9 @@ def _load():
     L.orc_rescue.restype = i32
     L.orc_rescue.argtypes = [vp, u64, i32, vp, vp, u64, vp, vp, vp, u64, i32, i32, vp, vp, i32]
     L.orc_free_ptr.argtypes = [vp]
+    L.orc_chain_dp.argtypes = [vp, vp, vp, vp, u64, i32, i32, vp, vp]
+    L.orc_chain.restype = u64
+    L.orc_chain.argtypes = [vp, vp, vp, vp, vp, u64, vp, u64, C.POINTER(_ChainOpts)] + [C.POINTER(vp)] * 8 + [vp]
     _lib = L
     return L
 
@@ -314,3 +323,56 @@ def rescue(ref_codes: np.ndarray, seq: np.ndarray, offsets: np.ndarray, read_id,
     if rc != 0:
         raise ValueError("rescue candidate out of range")
     return mh[:n], bt[:n]
+
+
+CHAIN_DTYPE = np.dtype([("read_id", "<u4"), ("score", "<i4"), ("n_anchors", "<u4"), ("copy", "<u4"),
+                        ("anchor_off", "<u8")])
+ANCHOR_DTYPE = np.dtype([("qbeg", "<u4"), ("qend", "<u4"), ("pos", "<u8")])
+
+
+def chain_dp(x, y, w, g, max_gap: int = 5000, max_pred: int = 50):
+    """f and predecessor p (-1: none) of anchors already in chaining order (x, y, w ascending)."""
+    L = _load()
+    x = np.ascontiguousarray(x, dtype=np.uint64)
+    y = np.ascontiguousarray(y, dtype=np.uint32)
+    w = np.ascontiguousarray(w, dtype=np.uint32)
+    g = np.ascontiguousarray(g, dtype=np.uint32)
+    n = x.size
+    f = np.zeros(max(n, 1), np.int32)
+    p = np.zeros(max(n, 1), np.int64)
+    pad = [a if a.size else np.zeros(1, a.dtype) for a in (x, y, w, g)]
+    L.orc_chain_dp(*[_p(a) for a in pad], n, int(max_gap), int(max_pred), _p(f), _p(p))
+    return f[:n], p[:n]
+
+
+def chain(res: SeedResult, seg_len: int, max_gap: int = 5000, max_pred: int = 50, max_chains: int = 50,
+          min_score: int = 19):
+    """Chains (Section 2.6) of every read of a seeding result whose seeds are sorted by read:
+    (CHAIN_DTYPE records in read and rank order, ANCHOR_DTYPE records of the chains' anchors, each
+    chain's anchors ascending).  ``seg_len`` is the length of one copy of the reference in T (|R|)."""
+    L = _load()
+    arrs = [np.ascontiguousarray(a) if a.size else np.zeros(1, a.dtype) for a in
+            (res.read_id, res.qbeg, res.qend, res.pos_off, res.npos)]
+    pos = np.ascontiguousarray(res.pos) if res.pos.size else np.zeros(1, np.uint64)
+    o = _ChainOpts(int(max_gap), int(max_pred), int(max_chains), int(min_score))
+    ptrs = [C.c_void_p() for _ in range(8)]
+    na = C.c_uint64()
+    nc = L.orc_chain(*[_p(a) for a in arrs], len(res), _p(pos), int(seg_len), C.byref(o), *[C.byref(q) for q in ptrs],
+                     C.byref(na))
+    na = na.value
+    chains = np.zeros(nc, CHAIN_DTYPE)
+    anchors = np.zeros(na, ANCHOR_DTYPE)
+    def take(q, ctype, n):
+        return np.ctypeslib.as_array(C.cast(q, C.POINTER(ctype)), shape=(n,)).copy() if n else None
+
+    if nc:
+        for name, q, ct in (("read_id", ptrs[0], C.c_uint32), ("score", ptrs[1], C.c_int32),
+                            ("n_anchors", ptrs[2], C.c_uint32), ("copy", ptrs[3], C.c_uint32),
+                            ("anchor_off", ptrs[4], C.c_uint64)):
+            chains[name] = take(q, ct, nc)
+    if na:
+        for name, q, ct in (("qbeg", ptrs[5], C.c_uint32), ("qend", ptrs[6], C.c_uint32), ("pos", ptrs[7], C.c_uint64)):
+            anchors[name] = take(q, ct, na)
+    for q in ptrs:
+        L.orc_free_ptr(q)
+    return chains, anchors

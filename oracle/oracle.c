@@ -915,3 +915,176 @@ int orc_rescue(const uint8_t *R, uint64_t len_r, int bisulfite, const uint8_t *r
 }
 
 void orc_free_ptr(void *p) { free(p); }
+
+/* ---------------------------------------------------------------------------------------------
+ * Chaining (Section 2.6): minibwa chains its variable-length seeds with the chaining of minimap2
+ * (Li 2018, Bioinformatics 34:3094, Section 2.1), adapted to seeds of different lengths, and keeps
+ * up to 50 chains per read.  The paper states no formula of its own; this is the published
+ * recurrence with the readings below (fixed so that every value is an integer and exact).
+ *
+ * Anchors.  Every located (seed, position) pair of a read is an anchor: the seed P[qbeg, qend)
+ * matches T[p, p + w), w = qend - qbeg; its end is (x, y) = (p + w - 1, qend - 1) and its copy
+ * g = floor(x / L) (L = |R|: 0 forward, 1 reverse strand; four copies for a bisulfite index).
+ * A read's anchors are sorted by (x, y, w).
+ * Recurrence.  f(i) = max( w_i, max_j f(j) + alpha(j, i) - beta(j, i) ) over the h anchors
+ * before i in that order (j = i-h .. i-1) with g_j = g_i, x_j < x_i, y_j < y_i and
+ * max(x_i - x_j, y_i - y_j) <= G, where alpha(j, i) = min(x_i - x_j, y_i - y_j, w_i) and
+ * beta(j, i) = gamma(|(y_i - y_j) - (x_i - x_j)|), gamma(0) = 0,
+ * gamma(l) = floor(l * wbar / 100) + floor(floor(log2 l) / 2), wbar = floor(mean span of the
+ * read's anchors).  The predecessor p(i) is the largest such j attaining the maximum when that
+ * maximum exceeds w_i, else -1.
+ * Chains.  Anchors are taken in order of descending f (equal f: smaller index first); from each
+ * anchor not used yet, p is followed, marking every anchor reached as used, until p = -1 or the
+ * next anchor is already used.  The chain is the anchors visited; its score is f(end) minus f of
+ * the used anchor it stopped at (f(end) when it stopped at p = -1).  Chains scoring at least
+ * min_score are kept, ordered by score (descending; equal scores by end index ascending), and the
+ * first max_chains returned, each with its anchors in ascending order.
+ */
+typedef struct { uint64_t x; uint32_t y, w, g; uint32_t qbeg, qend; uint64_t pos; } orc_anchor;
+typedef struct { int max_gap, max_pred, max_chains, min_score; } orc_chain_opts;
+
+static int cmp_anchor(const void *a, const void *b) {
+  const orc_anchor *u = (const orc_anchor *)a, *v = (const orc_anchor *)b;
+  if (u->x != v->x) return u->x < v->x ? -1 : 1;
+  if (u->y != v->y) return u->y < v->y ? -1 : 1;
+  return u->w < v->w ? -1 : u->w > v->w;
+}
+
+static int64_t chain_gamma(int64_t l, int64_t wbar) {
+  if (l < 0) l = -l;
+  if (l == 0) return 0;
+  int lg = 0;
+  while ((l >> (lg + 1)) != 0) ++lg;                    /* floor(log2 l) */
+  return l * wbar / 100 + lg / 2;
+}
+
+/* f and p of anchors already in chaining order (x, y, w ascending) */
+static void chain_dp(const uint64_t *x, const uint32_t *y, const uint32_t *w, const uint32_t *g, uint64_t N,
+                     int max_gap, int max_pred, int32_t *f, int64_t *p) {
+  if (N == 0) return;
+  uint64_t sw = 0;
+  for (uint64_t i = 0; i < N; ++i) sw += w[i];
+  const int64_t wbar = (int64_t)(sw / N);
+  for (uint64_t i = 0; i < N; ++i) {
+    int64_t best = w[i], bj = -1;
+    uint64_t j0 = i > (uint64_t)max_pred ? i - (uint64_t)max_pred : 0;
+    for (uint64_t j = j0; j < i; ++j) {
+      if (g[j] != g[i] || x[j] >= x[i] || y[j] >= y[i]) continue;
+      int64_t dx = (int64_t)(x[i] - x[j]), dy = (int64_t)y[i] - (int64_t)y[j];
+      if (dx > max_gap || dy > max_gap) continue;
+      int64_t a = dx < dy ? dx : dy;
+      if (a > (int64_t)w[i]) a = w[i];
+      int64_t sc = f[j] + a - chain_gamma(dy - dx, wbar);
+      if (sc > best || (sc == best && bj >= 0)) { best = sc; bj = (int64_t)j; }   /* later j wins a tie */
+    }
+    f[i] = (int32_t)best;
+    p[i] = bj;
+  }
+}
+
+/* exported for the pins: anchors given in chaining order */
+void orc_chain_dp(const uint64_t *x, const uint32_t *y, const uint32_t *w, const uint32_t *g, uint64_t N, int max_gap,
+                  int max_pred, int32_t *f, int64_t *p) {
+  chain_dp(x, y, w, g, N, max_gap, max_pred, f, p);
+}
+
+typedef struct { int32_t score; uint64_t end, start, n; } orc_chain_rec;
+static const int32_t *g_chain_f;
+static int cmp_by_f(const void *a, const void *b) {
+  uint64_t i = *(const uint64_t *)a, j = *(const uint64_t *)b;
+  if (g_chain_f[i] != g_chain_f[j]) return g_chain_f[i] > g_chain_f[j] ? -1 : 1;
+  return i < j ? -1 : 1;
+}
+static int cmp_chain_rec(const void *a, const void *b) {
+  const orc_chain_rec *u = (const orc_chain_rec *)a, *v = (const orc_chain_rec *)b;
+  if (u->score != v->score) return u->score > v->score ? -1 : 1;
+  return u->end < v->end ? -1 : u->end > v->end;
+}
+
+/* Chains of every read of a seeding result (seeds sorted by read, each seed's npos positions at
+ * pos[pos_off ..]).  Output: for each read its chains in rank order -> chain arrays (read, score,
+ * number of anchors, copy, offset into the anchor arrays) and the anchors of every chain in
+ * ascending order (qbeg, qend, pos).  Returns the chain count; arrays malloc'ed. */
+uint64_t orc_chain(const uint32_t *read_id, const uint32_t *qbeg, const uint32_t *qend, const uint64_t *pos_off,
+                   const uint32_t *npos, uint64_t n_seeds, const uint64_t *pos, uint64_t seg_len,
+                   const orc_chain_opts *o, uint32_t **c_read, int32_t **c_score, uint32_t **c_n, uint32_t **c_g,
+                   uint64_t **c_off, uint32_t **a_qbeg, uint32_t **a_qend, uint64_t **a_pos, uint64_t *n_anchors_out) {
+  uint64_t ccap = 1024, nc = 0, acap = 1024, na = 0;
+  uint32_t *cr = malloc(ccap * 4), *cn = malloc(ccap * 4), *cg = malloc(ccap * 4);
+  int32_t *cs = malloc(ccap * 4);
+  uint64_t *co = malloc(ccap * 8);
+  uint32_t *aq = malloc(acap * 4), *ae = malloc(acap * 4);
+  uint64_t *ap = malloc(acap * 8);
+  uint64_t t0 = 0;
+  while (t0 < n_seeds) {
+    uint64_t t1 = t0;
+    while (t1 < n_seeds && read_id[t1] == read_id[t0]) ++t1;
+    uint64_t N = 0;
+    for (uint64_t t = t0; t < t1; ++t) N += npos[t];
+    if (N) {
+      orc_anchor *A = malloc(N * sizeof(orc_anchor));
+      uint64_t k = 0;
+      for (uint64_t t = t0; t < t1; ++t)
+        for (uint32_t q = 0; q < npos[t]; ++q, ++k) {
+          uint32_t w = qend[t] - qbeg[t];
+          A[k].pos = pos[pos_off[t] + q];
+          A[k].x = A[k].pos + w - 1; A[k].y = qend[t] - 1; A[k].w = w;
+          A[k].g = (uint32_t)(A[k].x / seg_len); A[k].qbeg = qbeg[t]; A[k].qend = qend[t];
+        }
+      qsort(A, N, sizeof(orc_anchor), cmp_anchor);
+      uint64_t *x = malloc(N * 8);
+      uint32_t *y = malloc(N * 4), *w = malloc(N * 4), *g = malloc(N * 4);
+      for (uint64_t i = 0; i < N; ++i) { x[i] = A[i].x; y[i] = A[i].y; w[i] = A[i].w; g[i] = A[i].g; }
+      int32_t *f = malloc(N * 4);
+      int64_t *p = malloc(N * 8);
+      chain_dp(x, y, w, g, N, o->max_gap, o->max_pred, f, p);
+      /* backtracking in order of descending f */
+      uint64_t *ord = malloc(N * 8);
+      for (uint64_t i = 0; i < N; ++i) ord[i] = i;
+      g_chain_f = f;
+      qsort(ord, N, 8, cmp_by_f);
+      uint8_t *used = calloc(N, 1);
+      orc_chain_rec *R = malloc(N * sizeof(orc_chain_rec));
+      uint64_t nr = 0;
+      for (uint64_t q = 0; q < N; ++q) {
+        uint64_t e = ord[q];
+        if (used[e]) continue;
+        uint64_t i = e, n = 0;
+        int32_t sc = f[e];
+        for (;;) {
+          used[i] = 1; ++n;
+          if (p[i] < 0) break;
+          if (used[p[i]]) { sc = f[e] - f[p[i]]; break; }
+          i = (uint64_t)p[i];
+        }
+        if (sc >= o->min_score) { R[nr].score = sc; R[nr].end = e; R[nr].start = i; R[nr].n = n; ++nr; }
+      }
+      qsort(R, nr, sizeof(orc_chain_rec), cmp_chain_rec);
+      if (nr > (uint64_t)o->max_chains) nr = (uint64_t)o->max_chains;
+      for (uint64_t c = 0; c < nr; ++c) {
+        if (nc == ccap) {
+          ccap *= 2;
+          cr = realloc(cr, ccap * 4); cn = realloc(cn, ccap * 4); cg = realloc(cg, ccap * 4);
+          cs = realloc(cs, ccap * 4); co = realloc(co, ccap * 8);
+        }
+        cr[nc] = read_id[t0]; cs[nc] = R[c].score; cn[nc] = (uint32_t)R[c].n; cg[nc] = A[R[c].end].g; co[nc] = na;
+        while (na + R[c].n > acap) {
+          acap *= 2;
+          aq = realloc(aq, acap * 4); ae = realloc(ae, acap * 4); ap = realloc(ap, acap * 8);
+        }
+        uint64_t i = R[c].end;
+        for (uint64_t m = R[c].n; m-- > 0;) {               /* backwards along p, written ascending */
+          aq[na + m] = A[i].qbeg; ae[na + m] = A[i].qend; ap[na + m] = A[i].pos;
+          if (m) i = (uint64_t)p[i];
+        }
+        na += R[c].n;
+        ++nc;
+      }
+      free(A); free(x); free(y); free(w); free(g); free(f); free(p); free(ord); free(used); free(R);
+    }
+    t0 = t1;
+  }
+  *c_read = cr; *c_score = cs; *c_n = cn; *c_g = cg; *c_off = co;
+  *a_qbeg = aq; *a_qend = ae; *a_pos = ap; *n_anchors_out = na;
+  return nc;
+}
