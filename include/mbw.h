@@ -289,6 +289,60 @@ int mbw_rescue_filter(mbw_ctx *ctx, const uint8_t *reads, const uint32_t *length
  * may be NULL). */
 int mbw_rescue_download(mbw_ctx *ctx, const mbw_rescue_result *res, mbw_rescue_hit_t *hits, uint32_t *pass);
 
+/* ---- chaining (Section 2.6) -------------------------------------------------------------------
+ * minibwa chains its variable-length seeds with minimap2's chaining (Li 2018), adapted to seeds of
+ * different lengths, and keeps up to 50 chains per read.  Every located (seed, position) pair of a
+ * seeding result is an anchor: span w = qend - qbeg, end (x, y) = (pos + w - 1, qend - 1), copy
+ * g = x / |R| (0 forward, 1 reverse strand; 0..3 for a bisulfite index).  A read's anchors are
+ * ordered by (x, y, w), and (all integers)
+ *   f(i) = max(w_i, max_j f(j) + alpha(j,i) - beta(j,i))
+ * over the max_pred anchors j before i with g_j = g_i, x_j < x_i, y_j < y_i, x_i - x_j <= max_gap
+ * and y_i - y_j <= max_gap; alpha = min(x_i - x_j, y_i - y_j, w_i), beta = gamma(|dy - dx|),
+ * gamma(0) = 0, gamma(l) = floor(l * wbar / 100) + floor(floor(log2 l) / 2), wbar = the read's
+ * mean anchor span rounded down.  The predecessor of i is the nearest j reaching the maximum when
+ * it exceeds w_i.  Anchors are then taken in order of descending f (equal f: earlier first); from
+ * each unused one the predecessors are followed, marking anchors used, until there is none or the
+ * next is used; the chain scores f(end) minus f of the used anchor where it stopped.  Chains scoring
+ * at least min_score are ranked by score (equal: earlier end first) and the first max_chains kept. */
+typedef struct {
+  int max_gap;      /* G, >= 1 (5000) */
+  int max_pred;     /* h: predecessors looked at, 1..64 (50) */
+  int max_chains;   /* chains kept per read, 1..64 (50, Section 2.6) */
+  int min_score;    /* (19) */
+} mbw_chain_opts;
+
+typedef struct {
+  uint32_t read_id, n_anchors;
+  int32_t score;
+  uint32_t copy;          /* g of its anchors */
+  uint64_t anchor_off;    /* its anchors: anchors[anchor_off .. anchor_off + n_anchors), ascending */
+} mbw_chain_t;
+
+typedef struct {
+  uint32_t qbeg, qend;    /* the seed P[qbeg, qend) */
+  uint64_t pos;           /* its text position (T coordinates) */
+} mbw_anchor_t;
+
+typedef struct {
+  uint64_t n_chains;
+  uint64_t n_anchors;              /* anchors in the kept chains */
+  uint64_t n_input_anchors;        /* located (seed, position) pairs chained */
+  const mbw_chain_t *chains;       /* device pointer: by read, then rank */
+  const mbw_anchor_t *anchors;     /* device pointer */
+  float ms_kernel;                 /* device time of the chaining kernel (the recurrence and extraction) */
+  float ms_total;                  /* device time of the whole call (anchors, sorts, chaining, output) */
+} mbw_chain_result;
+
+/* Chain the seeds of a seeding result whose arrays are in device memory (an mbw_seed result:
+ * seeds sorted by read, each seed's positions at pos[pos_off ..]; every read_id < n_reads).  opts
+ * NULL = the defaults above.  The result stays in device memory owned by ctx until the next
+ * mbw_chain on it (a seeding or prefilter result of ctx is left intact).  Blocking on `stream`.
+ * Errors: MBW_E_INVAL (options, sizes, a seed with read_id >= n_reads), MBW_E_NOMEM, MBW_E_HIP. */
+int mbw_chain(mbw_ctx *ctx, const mbw_result *seeds, uint64_t n_reads, const mbw_chain_opts *opts, void *stream,
+              mbw_chain_result *out);
+/* Copy a chaining result to host buffers (n_chains and n_anchors records; either may be NULL). */
+int mbw_chain_download(mbw_ctx *ctx, const mbw_chain_result *res, mbw_chain_t *chains, mbw_anchor_t *anchors);
+
 /* ---- debug -----------------------------------------------------------------------------------
  * Cap the device work space every context may hold (bytes; 0 = no cap, the default).  A call that
  * would grow a context beyond it fails with MBW_E_NOMEM and leaves the context usable; for tests of

@@ -39,7 +39,8 @@ EXPORTS = ["mbw_strerror", "mbw_last_error", "mbw_index_build", "mbw_index_save"
            "mbw_index_free", "mbw_index_info", "mbw_index_device_arrays", "mbw_ctx_create", "mbw_ctx_free",
            "mbw_seed", "mbw_result_download", "mbw_pos_to_ref", "mbw_tune",
            "mbw_result_download_pieces", "mbw_serve_open", "mbw_serve_submit", "mbw_serve_wait", "mbw_serve_release", "mbw_serve_stats",
-           "mbw_serve_close", "mbw_rescue_filter", "mbw_rescue_download", "mbw_debug_set_mem_limit"]
+           "mbw_serve_close", "mbw_rescue_filter", "mbw_rescue_download", "mbw_debug_set_mem_limit", "mbw_chain",
+           "mbw_chain_download"]
 
 
 class MbwError(RuntimeError):
@@ -88,6 +89,15 @@ class RescueResult(C.Structure):
                 ("ms_kernel", C.c_float), ("ms_total", C.c_float)]
 
 
+class ChainOpts(C.Structure):
+    _fields_ = [("max_gap", C.c_int), ("max_pred", C.c_int), ("max_chains", C.c_int), ("min_score", C.c_int)]
+
+
+class ChainResult(C.Structure):
+    _fields_ = [("n_chains", C.c_uint64), ("n_anchors", C.c_uint64), ("n_input_anchors", C.c_uint64),
+                ("chains", C.c_void_p), ("anchors", C.c_void_p), ("ms_kernel", C.c_float), ("ms_total", C.c_float)]
+
+
 class Result(C.Structure):
     _fields_ = [("n_seeds", C.c_uint64), ("n_pos", C.c_uint64), ("seeds", C.c_void_p), ("pos", C.c_void_p),
                 ("lines_smem", C.c_uint64), ("lines_locate", C.c_uint64), ("steps", C.c_uint64),
@@ -102,6 +112,9 @@ assert SEED_DTYPE.itemsize == 56
 PIECE_DTYPE = np.dtype([("read_id", "<u4"), ("qbeg", "<u4"), ("qend", "<u4"), ("seed", "<u4"), ("pos", "<u8")])
 RESCUE_CAND_DTYPE = np.dtype([("read_id", "<u4"), ("win_len", "<u4"), ("win_beg", "<u8")])
 RESCUE_HIT_DTYPE = np.dtype([("max_hits", "<u4"), ("best_t", "<i4")])
+CHAIN_DTYPE = np.dtype([("read_id", "<u4"), ("n_anchors", "<u4"), ("score", "<i4"), ("copy", "<u4"),
+                        ("anchor_off", "<u8")])
+ANCHOR_DTYPE = np.dtype([("qbeg", "<u4"), ("qend", "<u4"), ("pos", "<u8")])
 
 _lib = None
 
@@ -145,6 +158,8 @@ def load_library():
     L.mbw_rescue_filter.argtypes = [vp, vp, vp, u64, vp, u64, C.POINTER(RescueOpts), vp, C.POINTER(RescueResult)]
     L.mbw_rescue_download.argtypes = [vp, C.POINTER(RescueResult), vp, vp]
     L.mbw_debug_set_mem_limit.argtypes = [u64]
+    L.mbw_chain.argtypes = [vp, C.POINTER(Result), u64, C.POINTER(ChainOpts), vp, C.POINTER(ChainResult)]
+    L.mbw_chain_download.argtypes = [vp, C.POINTER(ChainResult), vp, vp]
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
@@ -307,6 +322,26 @@ class SeedOutput:
 
 
 @dataclass
+class ChainOutput:
+    n_chains: int
+    n_anchors: int
+    n_input_anchors: int
+    ms_kernel: float
+    ms_total: float
+    _res: ChainResult
+    _ctx: "Context"
+
+    def download(self):
+        """(chains as CHAIN_DTYPE records by read and rank, their anchors as ANCHOR_DTYPE) on the host."""
+        chains = np.zeros(self.n_chains, dtype=CHAIN_DTYPE)
+        anchors = np.zeros(self.n_anchors, dtype=ANCHOR_DTYPE)
+        _check(self._ctx._lib.mbw_chain_download(self._ctx._h, C.byref(self._res),
+                                                 chains.ctypes.data if self.n_chains else None,
+                                                 anchors.ctypes.data if self.n_anchors else None))
+        return chains, anchors
+
+
+@dataclass
 class RescueOutput:
     n_cands: int
     n_pass: int
@@ -383,6 +418,15 @@ class Context:
                                            C.byref(res)))
         return RescueOutput(res.n_cands, res.n_pass, res.hits or 0, res.pass_ or 0, res.ms_kernel, res.ms_total,
                             res, self)
+
+    def chain(self, seeds: SeedOutput, n_reads: int, max_gap: int = 5000, max_pred: int = 50, max_chains: int = 50,
+              min_score: int = 19, stream=None) -> ChainOutput:
+        """Chains of the located seeds of a seeding result of this context (``mbw_chain``)."""
+        o = ChainOpts(int(max_gap), int(max_pred), int(max_chains), int(min_score))
+        res = ChainResult()
+        _check(self._lib.mbw_chain(self._h, C.byref(seeds._res), int(n_reads), C.byref(o), _stream_handle(stream),
+                                   C.byref(res)))
+        return ChainOutput(res.n_chains, res.n_anchors, res.n_input_anchors, res.ms_kernel, res.ms_total, res, self)
 
     def tune(self, reads, lengths, min_seed_len: int = 19, max_occ: int = 500, stream=None, cache=None,
              **base) -> dict:

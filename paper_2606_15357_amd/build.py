@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmbw.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["index_build.hip", "seed.hip", "serve.hip", "rescue.hip", "debug.hip"]
+SOURCES = ["index_build.hip", "seed.hip", "serve.hip", "rescue.hip", "chain.hip", "debug.hip"]
 PROBE_SRC = os.path.join(HERE, "probe", "probe.hip")
 PROBE_OUT = os.path.join(HERE, "libmbw_probe.so")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
