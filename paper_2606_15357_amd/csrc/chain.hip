@@ -23,11 +23,10 @@
 // its chain's anchors by walking the predecessors.  The search stops as soon as no unused anchor
 // can reach min_score or the last kept chain's score (a chain never scores above f of its end), so
 // a read with many anchors does not pay for chains it cannot keep.
-#include <cstring>
-
 #include <hip/hip_runtime.h>
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_scan.hpp>
+#include <hipcub/hipcub.hpp>
+
+#include <cstring>
 
 #include <algorithm>
 #include <string>
@@ -43,7 +42,8 @@ namespace {
 struct Anchor { uint64_t x; uint32_t yw; uint32_t g; };   // yw = y << 16 | w (y, w < 2^16)
 struct ChainRec { int32_t score; uint32_t end, n, off; };   // end: index of the last anchor in the read
 
-enum { CH_BAD = 0, CH_CTL = 4 };
+// control words: bad input seeds, the read work counter, guard trips of the chaining kernel
+enum { CH_BAD = 0, CH_NEXT = 1, CH_GUARD = 2, CH_CTL = 4 };
 
 inline unsigned grid_for(uint64_t n, unsigned bs = 256, unsigned cap = 65536u * 8) {
   uint64_t g = (n + bs - 1) / bs;
@@ -117,12 +117,23 @@ __global__ void k_ch_slots(const unsigned long long *__restrict__ cnt, uint64_t 
     slots[r] = r < n_reads ? (cnt[r] < maxc ? cnt[r] : (unsigned long long)maxc) : 0ull;
 }
 
+// Values every lane of the wave agrees on are moved into scalar registers (readfirstlane), so that
+// the loops and branches they control compile to scalar branches and the wave stays converged: a
+// cross-lane read (ds_bpermute) inside a loop the compiler has to treat as divergent could read a
+// lane that already left it.
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni(uint64_t v) {
+  return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
+}
+
+// maximum over the wave, returned in a scalar register
 __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
   for (int d = 32; d >= 1; d >>= 1) {
     const uint64_t o = __shfl_xor(v, d);
     v = o > v ? o : v;
   }
-  return v;
+  return uni(v);
 }
 
 __device__ __forceinline__ int64_t chain_gap(int64_t l, int64_t wbar) {
@@ -130,6 +141,16 @@ __device__ __forceinline__ int64_t chain_gap(int64_t l, int64_t wbar) {
   if (l == 0) return 0;
   const int lg = 63 - __clzll((unsigned long long)l);
   return l * wbar / 100 + lg / 2;
+}
+
+// f, p and the used flags of a read are written and read back by the same wave in one launch;
+// neighbouring reads share cache lines with them, so another wave of the CU may have brought a
+// line into the (non-coherent) vector L1 before it was written.  These accesses go to L2.
+template <class T> __device__ __forceinline__ T ld_l2(const T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T> __device__ __forceinline__ void st_l2(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 struct ChainArgs {
@@ -145,21 +166,27 @@ struct ChainArgs {
   ChainRec *__restrict__ CH;            // kept chains, per read from cslot[r]
   uint32_t *__restrict__ CA;            // anchors of the kept chains (index within the read), per read from aoff[r]
   unsigned long long *__restrict__ nch, *__restrict__ nanc;   // per read
-  unsigned long long *__restrict__ next;   // work counter (reads)
+  unsigned long long *__restrict__ ctl;    // CH_NEXT: work counter (reads); CH_GUARD: guard trips
+  uint64_t na;                             // anchors in total
 };
 
 __global__ void __launch_bounds__(256) k_chain(ChainArgs a) {
+  // Every loop below has a hard bound taken from the validated anchor count N of the read (a wave
+  // takes at most n_reads + 1 reads); a bound that is reached marks CH_GUARD and ends the work of
+  // the wave on that read, so a corrupt input can only produce an error, never a runaway loop.
   const int lane = threadIdx.x & 63;
-  uint64_t r = 0;
-  for (;;) {
-    {
-      unsigned long long t = 0;
-      if (lane == 0) t = atomicAdd(a.next, 1ull);
-      r = __shfl(t, 0);
-    }
+  for (uint64_t take = 0; take <= a.n_reads; ++take) {
+    unsigned long long t = 0;
+    if (lane == 0) t = atomicAdd(&a.ctl[CH_NEXT], 1ull);
+    const uint64_t r = uni((uint64_t)__shfl(t, 0));
     if (r >= a.n_reads) break;
-    const uint64_t a0 = a.aoff[r];
-    const uint32_t N = (uint32_t)(a.aoff[r + 1] - a0);
+    const uint64_t a0 = uni((uint64_t)a.aoff[r]);
+    const uint64_t a1 = uni((uint64_t)a.aoff[r + 1]);
+    if (a1 < a0 || a1 > a.na) {
+      if (lane == 0) { atomicOr(&a.ctl[CH_GUARD], 1ull); a.nch[r] = 0; a.nanc[r] = 0; }
+      continue;
+    }
+    const uint32_t N = (uint32_t)(a1 - a0);
     if (N == 0) {
       if (lane == 0) { a.nch[r] = 0; a.nanc[r] = 0; }
       continue;
@@ -170,7 +197,7 @@ __global__ void __launch_bounds__(256) k_chain(ChainArgs a) {
     uint64_t sw = 0;
     for (uint32_t i = lane; i < N; i += 64) sw += As[i].yw & 0xffffu;
     for (int d = 32; d >= 1; d >>= 1) sw += __shfl_xor(sw, d);
-    const int64_t wbar = (int64_t)(sw / N);
+    const int64_t wbar = (int64_t)(uni(sw) / N);
     // ---- the recurrence: lane t holds anchor i-1-t (x, y, copy, f)
     uint64_t px = 0;
     uint32_t py = 0, pg = 0;
@@ -191,10 +218,10 @@ __global__ void __launch_bounds__(256) k_chain(ChainArgs a) {
           if (sc > (int64_t)wi) key = ((uint64_t)sc << 6) | (uint64_t)(63 - lane);   // equal scores: nearer wins
         }
       }
-      key = wave_max_u64(key);
+      key = wave_max_u64(key);   // scalar
       int32_t fi = (int32_t)wi, pi = -1;
       if (key) { fi = (int32_t)(key >> 6); pi = (int32_t)i - 1 - (63 - (int32_t)(key & 63)); }
-      if (lane == 0) { F[i] = fi; P[i] = pi; U[i] = 0; }
+      if (lane == 0) { st_l2(&F[i], fi); st_l2(&P[i], pi); st_l2(&U[i], (uint8_t)0); }
       px = __shfl_up(px, 1); py = __shfl_up(py, 1); pg = __shfl_up(pg, 1); pf = __shfl_up(pf, 1);
       if (lane == 0) { px = xi; py = yi; pg = gi; pf = fi; }
     }
@@ -203,11 +230,13 @@ __global__ void __launch_bounds__(256) k_chain(ChainArgs a) {
     int nc = 0;
     int32_t cs = 0;
     uint32_t ce = 0, cn = 0;
-    for (;;) {
+    bool tripped = false;
+    for (uint32_t round = 0;; ++round) {
+      if (round > N) { tripped = true; break; }   // every round uses at least one anchor
       uint64_t best = 0;
       for (uint32_t i = lane; i < N; i += 64)
-        if (!U[i]) {
-          const uint64_t k = ((uint64_t)(uint32_t)F[i] << 32) | (uint64_t)(0xffffffffu - i);
+        if (!ld_l2(&U[i])) {
+          const uint64_t k = ((uint64_t)(uint32_t)ld_l2(&F[i]) << 32) | (uint64_t)(0xffffffffu - i);
           best = k > best ? k : best;
         }
       best = wave_max_u64(best);
@@ -215,27 +244,29 @@ __global__ void __launch_bounds__(256) k_chain(ChainArgs a) {
       const int32_t fm = (int32_t)(best >> 32);
       const uint32_t im = 0xffffffffu - (uint32_t)best;
       if (fm < a.minsc) break;                                       // no chain can reach min_score
-      const int32_t last = __shfl(cs, a.maxc - 1);
+      const int32_t last = uni(__shfl(cs, a.maxc - 1));
       if (nc == a.maxc && fm < last) break;                          // none can displace the last kept
       int32_t sc = fm;
-      uint32_t n = 0;
+      uint32_t n = 0, bad = 0;
       if (lane == 0) {
         uint32_t k = im;
         for (;;) {
-          U[k] = 1;
+          st_l2(&U[k], (uint8_t)1);
           ++n;
-          const int32_t pk = P[k];
+          const int32_t pk = ld_l2(&P[k]);
           if (pk < 0) break;
-          if (U[pk]) { sc = fm - F[pk]; break; }
+          if ((uint32_t)pk >= k || n >= N) { bad = 1; break; }   // predecessors lie strictly before
+          if (ld_l2(&U[pk])) { sc = fm - ld_l2(&F[pk]); break; }
           k = (uint32_t)pk;
         }
       }
       __threadfence_block();
-      sc = __shfl(sc, 0);
-      n = (uint32_t)__shfl((int)n, 0);
+      if (uni((uint32_t)__shfl((int)bad, 0))) { tripped = true; break; }
+      sc = uni(__shfl(sc, 0));
+      n = uni((uint32_t)__shfl((int)n, 0));
       if (sc >= a.minsc) {
         const bool before = lane < nc && (cs > sc || (cs == sc && ce < im));
-        const int q = __popcll(__ballot(before));
+        const int q = (int)uni((uint32_t)__popcll(__ballot(before)));
         const int32_t us = __shfl_up(cs, 1);
         const uint32_t ue = __shfl_up(ce, 1), un = __shfl_up(cn, 1);
         if (lane > q) { cs = us; ce = ue; cn = un; }
@@ -243,22 +274,27 @@ __global__ void __launch_bounds__(256) k_chain(ChainArgs a) {
         nc = nc < a.maxc ? nc + 1 : a.maxc;
       }
     }
+    if (tripped) {
+      if (lane == 0) { atomicOr(&a.ctl[CH_GUARD], 2ull); a.nch[r] = 0; a.nanc[r] = 0; }
+      continue;
+    }
     // ---- output: chain records and each chain's anchors (walked back from its end)
     uint32_t mine = lane < nc ? cn : 0u, off = mine;
     for (int d = 1; d < 64; d <<= 1) {
       const uint32_t o = (uint32_t)__shfl_up((int)off, d);
       if (lane >= d) off += o;
     }
-    const uint32_t total = (uint32_t)__shfl((int)off, 63);
+    const uint32_t total = uni((uint32_t)__shfl((int)off, 63));
     off -= mine;
     if (lane < nc) {
       ChainRec c;
       c.score = cs; c.end = ce; c.n = cn; c.off = off;
       a.CH[a.cslot[r] + lane] = c;
       uint32_t k = ce;
-      for (uint32_t m = cn; m-- > 0;) {
+      for (uint32_t m = cn; m-- > 0;) {   // cn <= N, and every k stays below N (checked when walked above)
         a.CA[a0 + off + m] = k;
-        if (m) k = (uint32_t)P[k];
+        if (m) k = (uint32_t)ld_l2(&P[k]);
+        if (k >= N) { atomicOr(&a.ctl[CH_GUARD], 4ull); break; }
       }
     }
     if (lane == 0) { a.nch[r] = (unsigned long long)nc; a.nanc[r] = total; }
@@ -294,9 +330,6 @@ __global__ void __launch_bounds__(256) k_ch_emit(const Anchor *__restrict__ As, 
     }
   }
 }
-
-template <class F>
-int prim_call(mbw_ctx *c, F f) { return cub_call(c, f); }
 
 }  // namespace
 
@@ -348,33 +381,44 @@ extern "C" int mbw_chain(mbw_ctx *c, const mbw_result *res, uint64_t n_reads, co
     TRY(hipGetLastError());
   }
   int r = 0;
+  const uint32_t *order = va;   // anchor indices in (read, x, y, w) order
   if (na > 1) {
     // (y, w), then (read, x): both stable, so the anchors end up in (read, x, y, w) order
-    r = prim_call(c, [&](void *tp, size_t &tb) {
-      return rocprim::radix_sort_pairs(tp, tb, k2a, k2b, va, vb, na, 0, 32, st);
-    });
+    hipcub::DoubleBuffer<uint32_t> kb2(k2a, k2b), vb2(va, vb);
+    r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceRadixSort::SortPairs(tp, tb, kb2, vb2, na, 0, 32, st); });
     if (r) return r;
-    k_ch_gather_k1<<<grid_for(na), 256, 0, st>>>(k1a, vb, na, k1b);
+    k_ch_gather_k1<<<grid_for(na), 256, 0, st>>>(k1a, vb2.Current(), na, k1b);
     TRY(hipGetLastError());
-    r = prim_call(c, [&](void *tp, size_t &tb) {
-      return rocprim::radix_sort_pairs(tp, tb, k1b, k1a, vb, va, na, 0, (unsigned)(xb + rb), st);
+    hipcub::DoubleBuffer<uint64_t> kb1(k1b, k1a);
+    hipcub::DoubleBuffer<uint32_t> vb1(vb2.Current(), vb2.Alternate());
+    r = cub_call(c, [&](void *tp, size_t &tb) {
+      return hipcub::DeviceRadixSort::SortPairs(tp, tb, kb1, vb1, na, 0, xb + rb, st);
     });
     if (r) return r;
+    order = vb1.Current();
   }
   if (na) {
-    k_ch_gather_anchors<<<grid_for(na), 256, 0, st>>>(A, va, na, As);   // one anchor: va[0] = 0 from the anchor kernel
+    k_ch_gather_anchors<<<grid_for(na), 256, 0, st>>>(A, order, na, As);   // one anchor: va[0] = 0 from the anchor kernel
     TRY(hipGetLastError());
   }
-  r = prim_call(c, [&](void *tp, size_t &tb) {
-    return rocprim::exclusive_scan(tp, tb, cnt, aoff, 0ull, n_reads + 1, rocprim::plus<unsigned long long>(), st);
-  });
+  r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, cnt, aoff, n_reads + 1, st); });
   if (r) return r;
   k_ch_slots<<<grid_for(n_reads + 1), 256, 0, st>>>(cnt, n_reads, (uint32_t)o.max_chains, slot);
   TRY(hipGetLastError());
-  r = prim_call(c, [&](void *tp, size_t &tb) {
-    return rocprim::exclusive_scan(tp, tb, slot, cslot, 0ull, n_reads + 1, rocprim::plus<unsigned long long>(), st);
-  });
+  r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, slot, cslot, n_reads + 1, st); });
   if (r) return r;
+  {
+    // the per-read ranges must tile the anchors exactly before the chaining kernel relies on them
+    uint64_t chk[3] = {0, 0, 0};
+    TRY(hipMemcpyAsync(&chk[0], aoff + n_reads, 8, hipMemcpyDeviceToHost, st));
+    TRY(hipMemcpyAsync(&chk[1], cslot + n_reads, 8, hipMemcpyDeviceToHost, st));
+    TRY(hipMemcpyAsync(&chk[2], ctl + CH_BAD, 8, hipMemcpyDeviceToHost, st));
+    TRY(hipStreamSynchronize(st));
+    if (chk[2]) { mbw_set_error("seeds with a read id >= n_reads or an empty or over-long interval"); return MBW_E_INVAL; }
+    if (chk[0] != na || chk[1] > std::min<uint64_t>(na, n_reads * (uint64_t)o.max_chains)) {
+      mbw_set_error("internal: anchor ranges do not cover the anchors"); return MBW_E_HIP;
+    }
+  }
   // slots in total: at most max_chains per read
   const uint64_t slots_cap = std::min<uint64_t>(na, n_reads * (uint64_t)o.max_chains) + 1;
   GROW(c->ch_F, (na + 1) * 4); GROW(c->ch_P, (na + 1) * 4); GROW(c->ch_U, na + 1);
@@ -389,7 +433,7 @@ extern "C" int mbw_chain(mbw_ctx *c, const mbw_result *res, uint64_t n_reads, co
   ca.As = As; ca.aoff = aoff; ca.cslot = cslot; ca.n_reads = n_reads; ca.G = o.max_gap; ca.h = o.max_pred;
   ca.maxc = o.max_chains; ca.minsc = o.min_score;
   ca.F = (int32_t *)c->ch_F.p; ca.P = (int32_t *)c->ch_P.p; ca.U = (uint8_t *)c->ch_U.p;
-  ca.CH = (ChainRec *)c->ch_CH.p; ca.CA = (uint32_t *)c->ch_CA.p; ca.nch = nch; ca.nanc = nanc; ca.next = ctl + 1;
+  ca.CH = (ChainRec *)c->ch_CH.p; ca.CA = (uint32_t *)c->ch_CA.p; ca.nch = nch; ca.nanc = nanc; ca.ctl = ctl; ca.na = na;
   TRY(hipEventRecord(c->ev[1], st));
   if (n_reads) {
     int per = 0;
@@ -399,20 +443,16 @@ extern "C" int mbw_chain(mbw_ctx *c, const mbw_result *res, uint64_t n_reads, co
     TRY(hipGetLastError());
   }
   TRY(hipEventRecord(c->ev[2], st));
-  r = prim_call(c, [&](void *tp, size_t &tb) {
-    return rocprim::exclusive_scan(tp, tb, nch, choff, 0ull, n_reads + 1, rocprim::plus<unsigned long long>(), st);
-  });
+  r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, nch, choff, n_reads + 1, st); });
   if (r) return r;
-  r = prim_call(c, [&](void *tp, size_t &tb) {
-    return rocprim::exclusive_scan(tp, tb, nanc, anoff, 0ull, n_reads + 1, rocprim::plus<unsigned long long>(), st);
-  });
+  r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, nanc, anoff, n_reads + 1, st); });
   if (r) return r;
   uint64_t h[3] = {0, 0, 0};
-  TRY(hipMemcpyAsync(&h[0], ctl + CH_BAD, 8, hipMemcpyDeviceToHost, st));
+  TRY(hipMemcpyAsync(&h[0], ctl + CH_GUARD, 8, hipMemcpyDeviceToHost, st));
   TRY(hipMemcpyAsync(&h[1], choff + n_reads, 8, hipMemcpyDeviceToHost, st));
   TRY(hipMemcpyAsync(&h[2], anoff + n_reads, 8, hipMemcpyDeviceToHost, st));
   TRY(hipStreamSynchronize(st));
-  if (h[0]) { mbw_set_error("seeds with a read id >= n_reads or an empty or over-long interval"); return MBW_E_INVAL; }
+  if (h[0]) { mbw_set_error("chaining kernel guard tripped (" + std::to_string(h[0]) + ")"); return MBW_E_HIP; }
   const uint64_t n_chains = h[1], n_anch = h[2];
   GROW(c->ch_out, (n_chains + 1) * sizeof(mbw_chain_t));
   GROW(c->ch_outa, (n_anch + 1) * sizeof(mbw_anchor_t));
