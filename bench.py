@@ -119,6 +119,7 @@ def cpu_baseline(workload: str, ref_codes, n_pairs: int, window: int, threads: i
             model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
     except OSError:
         pass
+    cpu_baseline.last_result = (res, window)
     return dict(value=len(rs) / dt, unit="reads/s", cores=threads, kind="oracle", cpu_model=model,
                 value_1core=round(len(one) / dt1, 1),
                 sample=f"{len(rs)} reads ({int(rs.lengths.sum())} bases, workload read model) against an oracle index "
@@ -178,6 +179,35 @@ def rescue_leg(mbw, torch, ctx, ref, reads, dseq, dlen, steps: int, warmup: int,
                                           f"reference; oracle = M_t counted pair by pair, OpenMP over candidates; "
                                           f"{dt:.1f} s wall")
     return res
+
+
+def chain_leg(torch, ctx, out, n_reads: int, steps: int, stream):
+    """Chaining (Section 2.6) of the whole seeding result of a step: anchors of every located seed,
+    sorted per read, the chaining recurrence and the extraction of up to 50 chains per read
+    (``mbw_chain``); anchors/s over `steps` calls, the chaining kernel's own time beside the call's."""
+    ctx.chain(out, n_reads, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [ctx.chain(out, n_reads, stream=stream) for _ in range(steps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ch = res[-1]
+    return dict(value=round(ch.n_input_anchors * steps / el, 1), unit="anchors/s",
+                reads_per_s=round(n_reads * steps / el, 1), ms_per_call=round(el / steps * 1e3, 2),
+                kernel_ms=round(sum(r.ms_kernel for r in res) / len(res), 2), anchors=ch.n_input_anchors,
+                chains=ch.n_chains, anchors_in_chains=ch.n_anchors,
+                params="max_gap 5000, 50 predecessors, 50 chains per read, min score 19")
+
+
+def chain_cpu_baseline(res, seg_len: int, sample: str):
+    """The chaining oracle (one thread) on the seeds of the CPU-baseline sample."""
+    import oracle
+    t0 = time.time()
+    chains, _ = oracle.chain(res, seg_len=seg_len)
+    dt = time.time() - t0
+    return dict(value=round(int(res.pos.size) / dt, 1), unit="anchors/s", cores=1, kind="oracle",
+                sample=f"the oracle's seeds of the seeding CPU baseline ({sample}); {int(res.pos.size)} anchors, "
+                       f"{chains.size} chains, {dt:.1f} s on one thread")
 
 
 def latency_leg(torch, ctx, reads, dseq, dlen, sched: dict, stream):
@@ -394,6 +424,7 @@ def main():
     ap.add_argument("--probe", action="store_true", help="only run the copy and random-gather probes")
     ap.add_argument("--no-tune", action="store_true", help="default schedule instead of the autotuned one")
     ap.add_argument("--no-rescue", action="store_true", help="skip the mate-rescue prefilter leg")
+    ap.add_argument("--no-chain", action="store_true", help="skip the chaining leg")
     ap.add_argument("--no-latency", action="store_true", help="skip the small-batch latency leg")
     ap.add_argument("--serve-workers", type=int, default=3,
                     help="serving leg: worker threads, one stream each (3 gave the lowest latency at 1,750 and "
@@ -490,6 +521,11 @@ def main():
         f"{out.wave_iters} wave iterations, lane use {out.lane_iters / max(1, 64 * out.wave_iters):.2f}), "
         f"locate {ms_loc:.1f} ms ({lines_loc} lines)")
 
+    chain = None
+    if not args.no_chain:
+        chain = chain_leg(torch, ctx, out, n_reads, args.steps, stream)
+        log(f"chaining: {chain}")
+
     plain = None
     if args.plain_steps > 0:
         step(mbw.KERNEL_PLAIN)
@@ -529,6 +565,12 @@ def main():
         cpu["value"] = round(cpu["value"], 1)
         log(f"cpu oracle: {cpu['value']:.0f} reads/s on {cpu['cores']} threads")
 
+    if chain is not None and cpu is not None and getattr(cpu_baseline, "last_result", None):
+        res_cpu, window = cpu_baseline.last_result
+        chain["cpu_baseline"] = chain_cpu_baseline(res_cpu, window, f"{len(res_cpu)} seeds over the first "
+                                                                   f"{window / 1e6:.0f} Mbp")
+        log(f"chaining cpu oracle: {chain['cpu_baseline']['value']:.0f} anchors/s")
+
     rescue = None
     if not args.no_rescue and args.workload in ("human_3gbp", "paired_100mbp"):
         threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
@@ -557,7 +599,7 @@ def main():
                             isa_sample=args.isa_sample, unique_ext=not args.no_unique,
                             bases_per_line=384, line_bytes=LINE_BYTES, index_gb=round(info["bytes_resident"] / 1e9, 2)),
                 schedule=sched, plain_gpu=plain, roofline=roofline, cpu_baseline=cpu, serve=serve, batch_latency=latency,
-                index_build=index_build, rescue=rescue)
+                index_build=index_build, rescue=rescue, chain=chain)
     print(json.dumps(line), flush=True)
 
 

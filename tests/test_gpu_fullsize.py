@@ -12,9 +12,10 @@ position of the sampled reads must agree exactly:
   and plain kernels identical over the whole batch;
 * 3.1 Gbp mixed genome, 10,000,000 read pairs: the wave and plain kernels identical over the
   whole batch; oracle O3 (one scan of T per q-mer set, no index) on 100 uniformly drawn reads
-  plus 20 reads from satellite arrays; the bounds k' of the sampled
-  seeds are checked through the strand mirror (seeding revcomp(P) gives (k', k, s) and the
-  mirrored positions).  The mate-rescue prefilter runs over 20,000,000 candidates of the same
+  plus 20 reads from satellite arrays; the bounds k' of the sampled seeds are checked through the
+  strand mirror (seeding revcomp(P) gives (k', k, s) and the mirrored positions).  The whole batch
+  is chained (Section 2.6) and the chains of the sampled reads equal the chaining oracle's on the
+  scan oracle's seeds.  The mate-rescue prefilter runs over 20,000,000 candidates of the same
   batch; 1,200 sampled candidates must match the oracle exactly.
 """
 import time
@@ -65,6 +66,21 @@ def sample_of(seeds, pos, ids):
         off += c
     p = np.concatenate(chunks) if chunks else np.zeros(0, np.uint64)
     return sel, p
+
+
+def chains_of(chains, anchors, ids):
+    """The chains of reads `ids` (sorted), renumbered 0..len(ids)-1, with their own anchor array."""
+    m = np.isin(chains["read_id"], ids)
+    sel = chains[m].copy()
+    sel["read_id"] = np.searchsorted(ids, sel["read_id"]).astype(np.uint32)
+    parts, off = [], 0
+    for t in range(sel.size):
+        o, c = int(sel["anchor_off"][t]), int(sel["n_anchors"][t])
+        parts.append(anchors[o:o + c])
+        sel["anchor_off"][t] = off
+        off += c
+    a = np.concatenate(parts) if parts else anchors[:0]
+    return sel, a
 
 
 def same_arrays(seeds, pos, seeds0, pos0):
@@ -163,6 +179,12 @@ def test_human_3gbp_sampled_parity():
     ctx = mbw.Context(idx)
     out, seeds, pos = gpu_seed_batch(ctx, reads, min_seed_len=19, max_occ=500)
     log(f"{len(reads)} reads: {out.n_seeds} seeds, {out.n_pos} positions ({time.time() - t0:.1f} s)")
+    # chaining of the whole batch (Section 2.6); the sampled reads are compared with the chaining
+    # oracle run on the scan oracle's seeds below
+    ch = ctx.chain(out, len(reads))
+    gchains, ganchors = ch.download()
+    log(f"chaining: {ch.n_input_anchors} anchors -> {ch.n_chains} chains ({ch.n_anchors} anchors), kernel "
+        f"{ch.ms_kernel:.1f} ms, call {ch.ms_total:.1f} ms ({time.time() - t0:.1f} s)")
     # the plain one-read-per-thread kernel returns the same arrays for the whole batch
     _, seeds_p, pos_p = gpu_seed_batch(ctx, reads, min_seed_len=19, max_occ=500, kernel=mbw.KERNEL_PLAIN)
     assert same_arrays(seeds_p, pos_p, seeds, pos)
@@ -199,11 +221,20 @@ def test_human_3gbp_sampled_parity():
     del reads
     s_gpu, p_gpu = sample_of(seeds, pos, ids)
     del seeds, pos
+    gc, ga = chains_of(gchains, ganchors, ids)
+    del gchains, ganchors
     exp = oracle.scan_seed(ref.codes, sub.seq, sub.offsets, min_len=19, max_occ=500)
     log(f"scan oracle: {len(exp)} seeds, {exp.pos.size} positions, {int((exp.flags & 1).sum())} over max_occ "
         f"({time.time() - t0:.1f} s)")
     assert len(exp) > 200 and (exp.flags & 1).sum() > 0
     s, flat = compare_without_bounds(s_gpu, p_gpu, exp)
+    ec, ea = oracle.chain(exp, seg_len=len(ref))
+    assert gc.size == ec.size and gc.size > 100
+    for f in ("read_id", "score", "n_anchors", "copy", "anchor_off"):
+        assert np.array_equal(gc[f].astype(np.int64), ec[f].astype(np.int64)), f
+    for f in ("qbeg", "qend", "pos"):
+        assert np.array_equal(ga[f].astype(np.uint64), ea[f].astype(np.uint64)), f
+    log(f"chains of the sample equal the chaining oracle's ({gc.size} chains)")
     # k' through the strand mirror: seeding revcomp(P[i,j)) gives one SMEM (k', k, s) whose positions
     # are 2|R| - p - (j - i)
     loc = np.nonzero((s["npos"] > 0))[0]
