@@ -127,13 +127,20 @@ __device__ __forceinline__ uint64_t uni(uint64_t v) {
   return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
 }
 
-// maximum over the wave, returned in a scalar register
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
-  for (int d = 32; d >= 1; d >>= 1) {
-    const uint64_t o = __shfl_xor(v, d);
-    v = o > v ? o : v;
-  }
-  return uni(v);
+// Maximum / minimum of a 32-bit value over the wave with DPP row operations (swap within quads,
+// mirror within half rows and rows, then the row broadcasts of 15 and 31), which leave the result
+// in lane 63; returned in a scalar register.
+template <bool MAX> __device__ __forceinline__ uint32_t dpp_pick(uint32_t a, uint32_t b) {
+  return MAX ? (a > b ? a : b) : (a < b ? a : b);
+}
+template <bool MAX> __device__ __forceinline__ uint32_t wave_reduce_u32(uint32_t v) {
+  v = dpp_pick<MAX>(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xf, 0xf, false));    // quad_perm 1,0,3,2
+  v = dpp_pick<MAX>(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xf, 0xf, false));    // quad_perm 2,3,0,1
+  v = dpp_pick<MAX>(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x141, 0xf, 0xf, false));   // row_half_mirror
+  v = dpp_pick<MAX>(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x140, 0xf, 0xf, false));   // row_mirror
+  v = dpp_pick<MAX>(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x142, 0xa, 0xf, false));   // row_bcast:15
+  v = dpp_pick<MAX>(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x143, 0xc, 0xf, false));   // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 __device__ __forceinline__ int64_t chain_gap(int64_t l, int64_t wbar) {
@@ -198,34 +205,40 @@ __global__ void __launch_bounds__(256) k_chain(ChainArgs a) {
     for (uint32_t i = lane; i < N; i += 64) sw += As[i].yw & 0xffffu;
     for (int d = 32; d >= 1; d >>= 1) sw += __shfl_xor(sw, d);
     const int64_t wbar = (int64_t)(uni(sw) / N);
-    // ---- the recurrence: lane t holds anchor i-1-t (x, y, copy, f)
+    // ---- the recurrence.  Lane t keeps the last anchor j with j = t (mod 64): (x, y, copy, f, j);
+    // the h <= 64 candidate predecessors of anchor i are then in distinct lanes and nothing moves
+    // between lanes from one anchor to the next.
     uint64_t px = 0;
     uint32_t py = 0, pg = 0;
     int32_t pf = 0;
+    int64_t pj = -1;
     Anchor nx = As[0];
     for (uint32_t i = 0; i < N; ++i) {
       const Anchor cur = nx;
       if (i + 1 < N) nx = As[i + 1];
       const uint64_t xi = cur.x;
       const uint32_t yi = cur.yw >> 16, wi = cur.yw & 0xffffu, gi = cur.g;
-      uint64_t key = 0;
-      if ((uint32_t)lane < i && lane < a.h && pg == gi && px < xi && py < yi) {
+      uint32_t key = 0;
+      if (pj >= 0 && pj >= (int64_t)i - a.h && pg == gi && px < xi && py < yi) {
         const int64_t dx = (int64_t)(xi - px), dy = (int64_t)(yi - py);
         if (dx <= a.G && dy <= a.G) {
           int64_t al = dx < dy ? dx : dy;
           if (al > (int64_t)wi) al = wi;
           const int64_t sc = (int64_t)pf + al - chain_gap(dy - dx, wbar);
-          if (sc > (int64_t)wi) key = ((uint64_t)sc << 6) | (uint64_t)(63 - lane);   // equal scores: nearer wins
+          // sc <= f_j + w_i < 2^17: it fits with the predecessor's distance in 32 bits;
+          // equal scores: the nearer predecessor (larger j) wins
+          if (sc > (int64_t)wi) key = ((uint32_t)sc << 6) | (uint32_t)(pj + 64 - (int64_t)i);
         }
       }
-      key = wave_max_u64(key);   // scalar
+      key = wave_reduce_u32<true>(key);
       int32_t fi = (int32_t)wi, pi = -1;
-      if (key) { fi = (int32_t)(key >> 6); pi = (int32_t)i - 1 - (63 - (int32_t)(key & 63)); }
-      if (lane == 0) { st_l2(&F[i], fi); st_l2(&P[i], pi); st_l2(&U[i], (uint8_t)0); }
-      px = __shfl_up(px, 1); py = __shfl_up(py, 1); pg = __shfl_up(pg, 1); pf = __shfl_up(pf, 1);
-      if (lane == 0) { px = xi; py = yi; pg = gi; pf = fi; }
+      if (key) { fi = (int32_t)(key >> 6); pi = (int32_t)i - 64 + (int32_t)(key & 63); }
+      if (lane == (int)(i & 63)) {
+        st_l2(&F[i], fi); st_l2(&P[i], pi); st_l2(&U[i], (uint8_t)0);
+        px = xi; py = yi; pg = gi; pf = fi; pj = i;
+      }
     }
-    __threadfence_block();   // lane 0's f, p and cleared flags are read by every lane below
+    __threadfence_block();   // f, p and cleared flags written by one lane each are read by every lane below
     // ---- chains, in order of descending f; the kept ones one per lane in rank order
     int nc = 0;
     int32_t cs = 0;
@@ -233,19 +246,25 @@ __global__ void __launch_bounds__(256) k_chain(ChainArgs a) {
     bool tripped = false;
     for (uint32_t round = 0;; ++round) {
       if (round > N) { tripped = true; break; }   // every round uses at least one anchor
-      uint64_t best = 0;
-      for (uint32_t i = lane; i < N; i += 64)
-        if (!ld_l2(&U[i])) {
-          const uint64_t k = ((uint64_t)(uint32_t)ld_l2(&F[i]) << 32) | (uint64_t)(0xffffffffu - i);
-          best = k > best ? k : best;
-        }
-      best = wave_max_u64(best);
-      if (!best) break;
-      const int32_t fm = (int32_t)(best >> 32);
-      const uint32_t im = 0xffffffffu - (uint32_t)best;
+      // the unused anchor of largest f (equal f: smallest index): f first, then the index
+      uint32_t bf = 0, bi = 0xffffffffu;
+      for (uint32_t i = lane; i < N; i += 64) {
+        const uint8_t used = ld_l2(&U[i]);
+        const uint32_t f = (uint32_t)ld_l2(&F[i]);   // f >= 1
+        if (!used && f > bf) { bf = f; bi = i; }     // i grows: the first of equal f is kept
+      }
+      const uint32_t fmax = wave_reduce_u32<true>(bf);
+      if (!fmax) break;
+      const uint32_t im = wave_reduce_u32<false>(bf == fmax ? bi : 0xffffffffu);
+      const int32_t fm = (int32_t)fmax;
       if (fm < a.minsc) break;                                       // no chain can reach min_score
-      const int32_t last = uni(__shfl(cs, a.maxc - 1));
-      if (nc == a.maxc && fm < last) break;                          // none can displace the last kept
+      if (nc == a.maxc) {
+        // a new chain scores <= fm and ranks before the last kept one only with a higher score, or
+        // an equal one and an earlier end; later candidates have smaller f, or equal f and a later end
+        const int32_t last = uni(__shfl(cs, a.maxc - 1));
+        const uint32_t last_end = uni((uint32_t)__shfl((int)ce, a.maxc - 1));
+        if (fm < last || (fm == last && im > last_end)) break;
+      }
       int32_t sc = fm;
       uint32_t n = 0, bad = 0;
       if (lane == 0) {
