@@ -17,12 +17,13 @@
 // score (equal scores: earlier end first) and the best max_chains kept.
 //
 // GPU form: one wave per read.  The recurrence runs over the read's anchors in order with the h
-// candidate predecessors spread over the lanes (lane t holds anchor i-1-t, shifted one lane per
-// anchor), one wave maximum per anchor.  Chains are extracted by repeated wave maxima over the
-// unused anchors; the kept chains live one per lane, in rank order, and each lane finally writes
-// its chain's anchors by walking the predecessors.  The search stops as soon as no unused anchor
-// can reach min_score or the last kept chain's score (a chain never scores above f of its end), so
-// a read with many anchors does not pay for chains it cannot keep.
+// candidate predecessors spread over the lanes (anchor j stays in lane j mod 64), one DPP wave
+// maximum per anchor.  f, predecessors and used flags sit in the wave's LDS area (global memory for
+// the rare read with more than 1,024 anchors).  Chains are extracted by repeated wave maxima over
+// the unused anchors; the kept chains live one per lane, in rank order, and each lane finally
+// writes its chain's anchors by walking the predecessors.  The search stops as soon as no unused
+// anchor can reach min_score or displace the last kept chain (a chain never scores above f of its
+// end), so a read with many anchors does not pay for chains it cannot keep.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
@@ -150,16 +151,6 @@ __device__ __forceinline__ int64_t chain_gap(int64_t l, int64_t wbar) {
   return l * wbar / 100 + lg / 2;
 }
 
-// f, p and the used flags of a read are written and read back by the same wave in one launch;
-// neighbouring reads share cache lines with them, so another wave of the CU may have brought a
-// line into the (non-coherent) vector L1 before it was written.  These accesses go to L2.
-template <class T> __device__ __forceinline__ T ld_l2(const T *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <class T> __device__ __forceinline__ void st_l2(T *p, T v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 struct ChainArgs {
   const Anchor *__restrict__ As;        // anchors sorted by (read, x, y, w)
   const unsigned long long *__restrict__ aoff;   // first anchor of every read (n_reads + 1)
@@ -167,9 +158,9 @@ struct ChainArgs {
   uint64_t n_reads;
   int64_t G;
   int h, maxc, minsc;
-  int32_t *__restrict__ F;              // f of every anchor
-  int32_t *__restrict__ P;              // predecessor (index within the read) or -1
-  uint8_t *__restrict__ U;              // used by a chain
+  int32_t *__restrict__ F;              // reads with more than CH_CAP anchors: f of every anchor,
+  int32_t *__restrict__ P;              // its predecessor (index within the read) or -1,
+  uint8_t *__restrict__ U;              // and whether a chain has used it
   ChainRec *__restrict__ CH;            // kept chains, per read from cslot[r]
   uint32_t *__restrict__ CA;            // anchors of the kept chains (index within the read), per read from aoff[r]
   unsigned long long *__restrict__ nch, *__restrict__ nanc;   // per read
@@ -177,11 +168,139 @@ struct ChainArgs {
   uint64_t na;                             // anchors in total
 };
 
-__global__ void __launch_bounds__(256) k_chain(ChainArgs a) {
-  // Every loop below has a hard bound taken from the validated anchor count N of the read (a wave
-  // takes at most n_reads + 1 reads); a bound that is reached marks CH_GUARD and ends the work of
-  // the wave on that read, so a corrupt input can only produce an error, never a runaway loop.
-  const int lane = threadIdx.x & 63;
+// A read's f, predecessors and used flags live in the wave's LDS area when it has at most CH_CAP
+// anchors (nearly all reads), else in the global arrays; either way only the wave that chains the
+// read touches them.
+#define CH_CAP 1024
+#define CH_WAVES 4
+
+// One read: the recurrence, chain extraction and output.  Returns false when a guard bound was
+// reached.  Every loop is bounded by the read's anchor count N.
+__device__ __forceinline__ bool chain_read(const ChainArgs &a, uint64_t r, uint64_t a0, uint32_t N, int32_t *F, int32_t *P,
+                                           uint8_t *U, int lane) {
+  const Anchor *As = a.As + a0;
+  uint64_t sw = 0;
+  for (uint32_t i = lane; i < N; i += 64) sw += As[i].yw & 0xffffu;
+  for (int d = 32; d >= 1; d >>= 1) sw += __shfl_xor(sw, d);
+  const int64_t wbar = (int64_t)(uni(sw) / N);
+  // ---- the recurrence.  Lane t keeps the last anchor j with j = t (mod 64): (x, y, copy, f, j);
+  // the h <= 64 candidate predecessors of anchor i are then in distinct lanes and nothing moves
+  // between lanes from one anchor to the next.
+  uint64_t px = 0;
+  uint32_t py = 0, pg = 0;
+  int32_t pf = 0;
+  int64_t pj = -1;
+  Anchor nx = As[0];
+  for (uint32_t i = 0; i < N; ++i) {
+    const Anchor cur = nx;
+    if (i + 1 < N) nx = As[i + 1];
+    const uint64_t xi = cur.x;
+    const uint32_t yi = cur.yw >> 16, wi = cur.yw & 0xffffu, gi = cur.g;
+    uint32_t key = 0;
+    if (pj >= 0 && pj >= (int64_t)i - a.h && pg == gi && px < xi && py < yi) {
+      const int64_t dx = (int64_t)(xi - px), dy = (int64_t)(yi - py);
+      if (dx <= a.G && dy <= a.G) {
+        int64_t al = dx < dy ? dx : dy;
+        if (al > (int64_t)wi) al = wi;
+        const int64_t sc = (int64_t)pf + al - chain_gap(dy - dx, wbar);
+        // sc <= f_j + w_i < 2^17: it fits with the predecessor's distance in 32 bits;
+        // equal scores: the nearer predecessor (larger j) wins
+        if (sc > (int64_t)wi) key = ((uint32_t)sc << 6) | (uint32_t)(pj + 64 - (int64_t)i);
+      }
+    }
+    key = wave_reduce_u32<true>(key);
+    int32_t fi = (int32_t)wi, pi = -1;
+    if (key) { fi = (int32_t)(key >> 6); pi = (int32_t)i - 64 + (int32_t)(key & 63); }
+    if (lane == (int)(i & 63)) {
+      F[i] = fi; P[i] = pi; U[i] = 0;
+      px = xi; py = yi; pg = gi; pf = fi; pj = i;
+    }
+  }
+  __threadfence_block();   // f, p and cleared flags written by one lane each are read by every lane below
+  // ---- chains, in order of descending f; the kept ones one per lane in rank order
+  int nc = 0;
+  int32_t cs = 0;
+  uint32_t ce = 0, cn = 0;
+  for (uint32_t round = 0;; ++round) {
+    if (round > N) return false;   // every round uses at least one anchor
+    // the unused anchor of largest f (equal f: smallest index): f first, then the index
+    uint32_t bf = 0, bi = 0xffffffffu;
+    for (uint32_t i = lane; i < N; i += 64) {
+      const uint32_t f = U[i] ? 0u : (uint32_t)F[i];   // f >= 1
+      if (f > bf) { bf = f; bi = i; }                  // i grows: the first of equal f is kept
+    }
+    const uint32_t fmax = wave_reduce_u32<true>(bf);
+    if (!fmax) break;
+    const uint32_t im = wave_reduce_u32<false>(bf == fmax ? bi : 0xffffffffu);
+    const int32_t fm = (int32_t)fmax;
+    if (fm < a.minsc) break;                                       // no chain can reach min_score
+    if (nc == a.maxc) {
+      // a new chain scores <= fm and ranks before the last kept one only with a higher score, or
+      // an equal one and an earlier end; later candidates have smaller f, or equal f and a later end
+      const int32_t last = uni(__shfl(cs, a.maxc - 1));
+      const uint32_t last_end = uni((uint32_t)__shfl((int)ce, a.maxc - 1));
+      if (fm < last || (fm == last && im > last_end)) break;
+    }
+    int32_t sc = fm;
+    uint32_t n = 0, bad = 0;
+    if (lane == 0) {
+      uint32_t k = im;
+      for (;;) {
+        U[k] = 1;
+        ++n;
+        const int32_t pk = P[k];
+        if (pk < 0) break;
+        if ((uint32_t)pk >= k || n >= N) { bad = 1; break; }   // predecessors lie strictly before
+        if (U[pk]) { sc = fm - F[pk]; break; }
+        k = (uint32_t)pk;
+      }
+    }
+    __threadfence_block();
+    if (uni((uint32_t)__shfl((int)bad, 0))) return false;
+    sc = uni(__shfl(sc, 0));
+    n = uni((uint32_t)__shfl((int)n, 0));
+    if (sc >= a.minsc) {
+      const bool before = lane < nc && (cs > sc || (cs == sc && ce < im));
+      const int q = (int)uni((uint32_t)__popcll(__ballot(before)));
+      const int32_t us = __shfl_up(cs, 1);
+      const uint32_t ue = __shfl_up(ce, 1), un = __shfl_up(cn, 1);
+      if (lane > q) { cs = us; ce = ue; cn = un; }
+      if (lane == q) { cs = sc; ce = im; cn = n; }
+      nc = nc < a.maxc ? nc + 1 : a.maxc;
+    }
+  }
+  // ---- output: chain records and each chain's anchors (walked back from its end)
+  uint32_t mine = lane < nc ? cn : 0u, off = mine;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = (uint32_t)__shfl_up((int)off, d);
+    if (lane >= d) off += o;
+  }
+  const uint32_t total = uni((uint32_t)__shfl((int)off, 63));
+  off -= mine;
+  bool ok = true;
+  if (lane < nc) {
+    ChainRec c;
+    c.score = cs; c.end = ce; c.n = cn; c.off = off;
+    a.CH[a.cslot[r] + lane] = c;
+    uint32_t k = ce;
+    for (uint32_t m = cn; m-- > 0;) {   // cn <= N, and every k stays below N (checked when walked above)
+      a.CA[a0 + off + m] = k;
+      if (m) k = (uint32_t)P[k];
+      if (k >= N) { ok = false; break; }
+    }
+  }
+  if (__ballot(!ok)) return false;
+  if (lane == 0) { a.nch[r] = (unsigned long long)nc; a.nanc[r] = total; }
+  return true;
+}
+
+__global__ void __launch_bounds__(64 * CH_WAVES) k_chain(ChainArgs a) {
+  // Every loop has a hard bound taken from the validated anchor count N of the read (a wave takes
+  // at most n_reads + 1 reads); a bound that is reached marks CH_GUARD and ends the work of the
+  // wave on that read, so a corrupt input can only produce an error, never a runaway loop.
+  __shared__ int32_t sF[CH_WAVES][CH_CAP], sP[CH_WAVES][CH_CAP];
+  __shared__ uint8_t sU[CH_WAVES][CH_CAP];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (uint64_t take = 0; take <= a.n_reads; ++take) {
     unsigned long long t = 0;
     if (lane == 0) t = atomicAdd(&a.ctl[CH_NEXT], 1ull);
@@ -198,125 +317,9 @@ __global__ void __launch_bounds__(256) k_chain(ChainArgs a) {
       if (lane == 0) { a.nch[r] = 0; a.nanc[r] = 0; }
       continue;
     }
-    const Anchor *As = a.As + a0;
-    int32_t *F = a.F + a0, *P = a.P + a0;
-    uint8_t *U = a.U + a0;
-    uint64_t sw = 0;
-    for (uint32_t i = lane; i < N; i += 64) sw += As[i].yw & 0xffffu;
-    for (int d = 32; d >= 1; d >>= 1) sw += __shfl_xor(sw, d);
-    const int64_t wbar = (int64_t)(uni(sw) / N);
-    // ---- the recurrence.  Lane t keeps the last anchor j with j = t (mod 64): (x, y, copy, f, j);
-    // the h <= 64 candidate predecessors of anchor i are then in distinct lanes and nothing moves
-    // between lanes from one anchor to the next.
-    uint64_t px = 0;
-    uint32_t py = 0, pg = 0;
-    int32_t pf = 0;
-    int64_t pj = -1;
-    Anchor nx = As[0];
-    for (uint32_t i = 0; i < N; ++i) {
-      const Anchor cur = nx;
-      if (i + 1 < N) nx = As[i + 1];
-      const uint64_t xi = cur.x;
-      const uint32_t yi = cur.yw >> 16, wi = cur.yw & 0xffffu, gi = cur.g;
-      uint32_t key = 0;
-      if (pj >= 0 && pj >= (int64_t)i - a.h && pg == gi && px < xi && py < yi) {
-        const int64_t dx = (int64_t)(xi - px), dy = (int64_t)(yi - py);
-        if (dx <= a.G && dy <= a.G) {
-          int64_t al = dx < dy ? dx : dy;
-          if (al > (int64_t)wi) al = wi;
-          const int64_t sc = (int64_t)pf + al - chain_gap(dy - dx, wbar);
-          // sc <= f_j + w_i < 2^17: it fits with the predecessor's distance in 32 bits;
-          // equal scores: the nearer predecessor (larger j) wins
-          if (sc > (int64_t)wi) key = ((uint32_t)sc << 6) | (uint32_t)(pj + 64 - (int64_t)i);
-        }
-      }
-      key = wave_reduce_u32<true>(key);
-      int32_t fi = (int32_t)wi, pi = -1;
-      if (key) { fi = (int32_t)(key >> 6); pi = (int32_t)i - 64 + (int32_t)(key & 63); }
-      if (lane == (int)(i & 63)) {
-        st_l2(&F[i], fi); st_l2(&P[i], pi); st_l2(&U[i], (uint8_t)0);
-        px = xi; py = yi; pg = gi; pf = fi; pj = i;
-      }
-    }
-    __threadfence_block();   // f, p and cleared flags written by one lane each are read by every lane below
-    // ---- chains, in order of descending f; the kept ones one per lane in rank order
-    int nc = 0;
-    int32_t cs = 0;
-    uint32_t ce = 0, cn = 0;
-    bool tripped = false;
-    for (uint32_t round = 0;; ++round) {
-      if (round > N) { tripped = true; break; }   // every round uses at least one anchor
-      // the unused anchor of largest f (equal f: smallest index): f first, then the index
-      uint32_t bf = 0, bi = 0xffffffffu;
-      for (uint32_t i = lane; i < N; i += 64) {
-        const uint8_t used = ld_l2(&U[i]);
-        const uint32_t f = (uint32_t)ld_l2(&F[i]);   // f >= 1
-        if (!used && f > bf) { bf = f; bi = i; }     // i grows: the first of equal f is kept
-      }
-      const uint32_t fmax = wave_reduce_u32<true>(bf);
-      if (!fmax) break;
-      const uint32_t im = wave_reduce_u32<false>(bf == fmax ? bi : 0xffffffffu);
-      const int32_t fm = (int32_t)fmax;
-      if (fm < a.minsc) break;                                       // no chain can reach min_score
-      if (nc == a.maxc) {
-        // a new chain scores <= fm and ranks before the last kept one only with a higher score, or
-        // an equal one and an earlier end; later candidates have smaller f, or equal f and a later end
-        const int32_t last = uni(__shfl(cs, a.maxc - 1));
-        const uint32_t last_end = uni((uint32_t)__shfl((int)ce, a.maxc - 1));
-        if (fm < last || (fm == last && im > last_end)) break;
-      }
-      int32_t sc = fm;
-      uint32_t n = 0, bad = 0;
-      if (lane == 0) {
-        uint32_t k = im;
-        for (;;) {
-          st_l2(&U[k], (uint8_t)1);
-          ++n;
-          const int32_t pk = ld_l2(&P[k]);
-          if (pk < 0) break;
-          if ((uint32_t)pk >= k || n >= N) { bad = 1; break; }   // predecessors lie strictly before
-          if (ld_l2(&U[pk])) { sc = fm - ld_l2(&F[pk]); break; }
-          k = (uint32_t)pk;
-        }
-      }
-      __threadfence_block();
-      if (uni((uint32_t)__shfl((int)bad, 0))) { tripped = true; break; }
-      sc = uni(__shfl(sc, 0));
-      n = uni((uint32_t)__shfl((int)n, 0));
-      if (sc >= a.minsc) {
-        const bool before = lane < nc && (cs > sc || (cs == sc && ce < im));
-        const int q = (int)uni((uint32_t)__popcll(__ballot(before)));
-        const int32_t us = __shfl_up(cs, 1);
-        const uint32_t ue = __shfl_up(ce, 1), un = __shfl_up(cn, 1);
-        if (lane > q) { cs = us; ce = ue; cn = un; }
-        if (lane == q) { cs = sc; ce = im; cn = n; }
-        nc = nc < a.maxc ? nc + 1 : a.maxc;
-      }
-    }
-    if (tripped) {
-      if (lane == 0) { atomicOr(&a.ctl[CH_GUARD], 2ull); a.nch[r] = 0; a.nanc[r] = 0; }
-      continue;
-    }
-    // ---- output: chain records and each chain's anchors (walked back from its end)
-    uint32_t mine = lane < nc ? cn : 0u, off = mine;
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t o = (uint32_t)__shfl_up((int)off, d);
-      if (lane >= d) off += o;
-    }
-    const uint32_t total = uni((uint32_t)__shfl((int)off, 63));
-    off -= mine;
-    if (lane < nc) {
-      ChainRec c;
-      c.score = cs; c.end = ce; c.n = cn; c.off = off;
-      a.CH[a.cslot[r] + lane] = c;
-      uint32_t k = ce;
-      for (uint32_t m = cn; m-- > 0;) {   // cn <= N, and every k stays below N (checked when walked above)
-        a.CA[a0 + off + m] = k;
-        if (m) k = (uint32_t)ld_l2(&P[k]);
-        if (k >= N) { atomicOr(&a.ctl[CH_GUARD], 4ull); break; }
-      }
-    }
-    if (lane == 0) { a.nch[r] = (unsigned long long)nc; a.nanc[r] = total; }
+    const bool ok = N <= CH_CAP ? chain_read(a, r, a0, N, sF[wv], sP[wv], sU[wv], lane)
+                                : chain_read(a, r, a0, N, a.F + a0, a.P + a0, a.U + a0, lane);
+    if (!ok && lane == 0) { atomicOr(&a.ctl[CH_GUARD], 2ull); a.nch[r] = 0; a.nanc[r] = 0; }
   }
 }
 
@@ -456,9 +459,10 @@ extern "C" int mbw_chain(mbw_ctx *c, const mbw_result *res, uint64_t n_reads, co
   TRY(hipEventRecord(c->ev[1], st));
   if (n_reads) {
     int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_chain, 256, 0) != hipSuccess || per < 1) per = 4;
-    const uint64_t grid = std::min<uint64_t>((n_reads + 3) / 4, (uint64_t)per * c->n_cu);
-    k_chain<<<(unsigned)grid, 256, 0, st>>>(ca);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_chain, 64 * CH_WAVES, 0) != hipSuccess || per < 1)
+      per = 4;
+    const uint64_t grid = std::min<uint64_t>((n_reads + CH_WAVES - 1) / CH_WAVES, (uint64_t)per * c->n_cu);
+    k_chain<<<(unsigned)grid, 64 * CH_WAVES, 0, st>>>(ca);
     TRY(hipGetLastError());
   }
   TRY(hipEventRecord(c->ev[2], st));
