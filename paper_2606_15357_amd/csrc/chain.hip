@@ -185,36 +185,47 @@ __device__ __forceinline__ bool chain_read(const ChainArgs &a, uint64_t r, uint6
   const int64_t wbar = (int64_t)(uni(sw) / N);
   // ---- the recurrence.  Lane t keeps the last anchor j with j = t (mod 64): (x, y, copy, f, j);
   // the h <= 64 candidate predecessors of anchor i are then in distinct lanes and nothing moves
-  // between lanes from one anchor to the next.
+  // between lanes from one anchor to the next.  The anchors themselves stream through registers 64
+  // at a time (lane t loads anchor c0 + t; the next chunk is in flight while this one is used) and
+  // each step reads its anchor from its lane with readlane.
   uint64_t px = 0;
   uint32_t py = 0, pg = 0;
   int32_t pf = 0;
   int64_t pj = -1;
-  Anchor nx = As[0];
-  for (uint32_t i = 0; i < N; ++i) {
-    const Anchor cur = nx;
-    if (i + 1 < N) nx = As[i + 1];
-    const uint64_t xi = cur.x;
-    const uint32_t yi = cur.yw >> 16, wi = cur.yw & 0xffffu, gi = cur.g;
-    uint32_t key = 0;
-    if (pj >= 0 && pj >= (int64_t)i - a.h && pg == gi && px < xi && py < yi) {
-      const int64_t dx = (int64_t)(xi - px), dy = (int64_t)(yi - py);
-      if (dx <= a.G && dy <= a.G) {
-        int64_t al = dx < dy ? dx : dy;
-        if (al > (int64_t)wi) al = wi;
-        const int64_t sc = (int64_t)pf + al - chain_gap(dy - dx, wbar);
-        // sc <= f_j + w_i < 2^17: it fits with the predecessor's distance in 32 bits;
-        // equal scores: the nearer predecessor (larger j) wins
-        if (sc > (int64_t)wi) key = ((uint32_t)sc << 6) | (uint32_t)(pj + 64 - (int64_t)i);
+  Anchor cur = {0, 0, 0}, nxt = {0, 0, 0};
+  if ((uint32_t)lane < N) cur = As[lane];
+  if (64u + lane < N) nxt = As[64 + lane];
+  for (uint32_t c0 = 0; c0 < N; c0 += 64) {
+    const uint32_t cnt = N - c0 < 64u ? N - c0 : 64u;
+    for (uint32_t t = 0; t < cnt; ++t) {
+      const uint32_t i = c0 + t;
+      const uint64_t xi = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(cur.x >> 32), (int)t) << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)cur.x, (int)t);
+      const uint32_t yw = (uint32_t)__builtin_amdgcn_readlane((int)cur.yw, (int)t);
+      const uint32_t gi = (uint32_t)__builtin_amdgcn_readlane((int)cur.g, (int)t);
+      const uint32_t yi = yw >> 16, wi = yw & 0xffffu;
+      uint32_t key = 0;
+      if (pj >= 0 && pj >= (int64_t)i - a.h && pg == gi && px < xi && py < yi) {
+        const int64_t dx = (int64_t)(xi - px), dy = (int64_t)(yi - py);
+        if (dx <= a.G && dy <= a.G) {
+          int64_t al = dx < dy ? dx : dy;
+          if (al > (int64_t)wi) al = wi;
+          const int64_t sc = (int64_t)pf + al - chain_gap(dy - dx, wbar);
+          // sc <= f_j + w_i < 2^17: it fits with the predecessor's distance in 32 bits;
+          // equal scores: the nearer predecessor (larger j) wins
+          if (sc > (int64_t)wi) key = ((uint32_t)sc << 6) | (uint32_t)(pj + 64 - (int64_t)i);
+        }
+      }
+      key = wave_reduce_u32<true>(key);
+      int32_t fi = (int32_t)wi, pi = -1;
+      if (key) { fi = (int32_t)(key >> 6); pi = (int32_t)i - 64 + (int32_t)(key & 63); }
+      if ((uint32_t)lane == t) {
+        F[i] = fi; P[i] = pi; U[i] = 0;
+        px = xi; py = yi; pg = gi; pf = fi; pj = i;
       }
     }
-    key = wave_reduce_u32<true>(key);
-    int32_t fi = (int32_t)wi, pi = -1;
-    if (key) { fi = (int32_t)(key >> 6); pi = (int32_t)i - 64 + (int32_t)(key & 63); }
-    if (lane == (int)(i & 63)) {
-      F[i] = fi; P[i] = pi; U[i] = 0;
-      px = xi; py = yi; pg = gi; pf = fi; pj = i;
-    }
+    cur = nxt;
+    if (c0 + 128 + lane < N) nxt = As[c0 + 128 + lane];
   }
   __threadfence_block();   // f, p and cleared flags written by one lane each are read by every lane below
   // ---- chains, in order of descending f; the kept ones one per lane in rank order
