@@ -195,7 +195,8 @@ def chain_leg(torch, ctx, out, n_reads: int, steps: int, stream):
     return dict(value=round(ch.n_input_anchors * steps / el, 1), unit="anchors/s",
                 reads_per_s=round(n_reads * steps / el, 1), ms_per_call=round(el / steps * 1e3, 2),
                 kernel_ms=round(sum(r.ms_kernel for r in res) / len(res), 2), anchors=ch.n_input_anchors,
-                chains=ch.n_chains, anchors_in_chains=ch.n_anchors,
+                chains=ch.n_chains, anchors_in_chains=ch.n_anchors, max_read_anchors=ch.max_read_anchors,
+                reads_over_lds=ch.reads_over_lds,
                 params="max_gap 5000, 50 predecessors, 50 chains per read, min score 19")
 
 

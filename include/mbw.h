@@ -331,6 +331,8 @@ typedef struct {
   const mbw_anchor_t *anchors;     /* device pointer */
   float ms_kernel;                 /* device time of the chaining kernel (the recurrence and extraction) */
   float ms_total;                  /* device time of the whole call (anchors, sorts, chaining, output) */
+  uint64_t max_read_anchors;       /* the most anchors one read has */
+  uint64_t reads_over_lds;         /* reads with more than 1,024 anchors (chained from global memory) */
 } mbw_chain_result;
 
 /* Chain the seeds of a seeding result whose arrays are in device memory (an mbw_seed result:

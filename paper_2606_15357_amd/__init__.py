@@ -95,7 +95,8 @@ class ChainOpts(C.Structure):
 
 class ChainResult(C.Structure):
     _fields_ = [("n_chains", C.c_uint64), ("n_anchors", C.c_uint64), ("n_input_anchors", C.c_uint64),
-                ("chains", C.c_void_p), ("anchors", C.c_void_p), ("ms_kernel", C.c_float), ("ms_total", C.c_float)]
+                ("chains", C.c_void_p), ("anchors", C.c_void_p), ("ms_kernel", C.c_float), ("ms_total", C.c_float),
+                ("max_read_anchors", C.c_uint64), ("reads_over_lds", C.c_uint64)]
 
 
 class Result(C.Structure):
@@ -328,6 +329,8 @@ class ChainOutput:
     n_input_anchors: int
     ms_kernel: float
     ms_total: float
+    max_read_anchors: int
+    reads_over_lds: int
     _res: ChainResult
     _ctx: "Context"
 
@@ -426,7 +429,8 @@ class Context:
         res = ChainResult()
         _check(self._lib.mbw_chain(self._h, C.byref(seeds._res), int(n_reads), C.byref(o), _stream_handle(stream),
                                    C.byref(res)))
-        return ChainOutput(res.n_chains, res.n_anchors, res.n_input_anchors, res.ms_kernel, res.ms_total, res, self)
+        return ChainOutput(res.n_chains, res.n_anchors, res.n_input_anchors, res.ms_kernel, res.ms_total,
+                           res.max_read_anchors, res.reads_over_lds, res, self)
 
     def tune(self, reads, lengths, min_seed_len: int = 19, max_occ: int = 500, stream=None, cache=None,
              **base) -> dict:

@@ -43,8 +43,9 @@ namespace {
 struct Anchor { uint64_t x; uint32_t yw; uint32_t g; };   // yw = y << 16 | w (y, w < 2^16)
 struct ChainRec { int32_t score; uint32_t end, n, off; };   // end: index of the last anchor in the read
 
-// control words: bad input seeds, the read work counter, guard trips of the chaining kernel
-enum { CH_BAD = 0, CH_NEXT = 1, CH_GUARD = 2, CH_CTL = 4 };
+// control words: bad input seeds, the read work counter, guard trips of the chaining kernel, the
+// largest anchor count of a read, reads chained from global memory (more than CH_CAP anchors)
+enum { CH_BAD = 0, CH_NEXT = 1, CH_GUARD = 2, CH_MAXN = 3, CH_BIG = 4, CH_CTL = 8 };
 
 inline unsigned grid_for(uint64_t n, unsigned bs = 256, unsigned cap = 65536u * 8) {
   uint64_t g = (n + bs - 1) / bs;
@@ -328,6 +329,10 @@ __global__ void __launch_bounds__(64 * CH_WAVES) k_chain(ChainArgs a) {
       if (lane == 0) { a.nch[r] = 0; a.nanc[r] = 0; }
       continue;
     }
+    if (lane == 0) {
+      atomicMax(&a.ctl[CH_MAXN], (unsigned long long)N);
+      if (N > CH_CAP) atomicAdd(&a.ctl[CH_BIG], 1ull);
+    }
     const bool ok = N <= CH_CAP ? chain_read(a, r, a0, N, sF[wv], sP[wv], sU[wv], lane)
                                 : chain_read(a, r, a0, N, a.F + a0, a.P + a0, a.U + a0, lane);
     if (!ok && lane == 0) { atomicOr(&a.ctl[CH_GUARD], 2ull); a.nch[r] = 0; a.nanc[r] = 0; }
@@ -481,7 +486,8 @@ extern "C" int mbw_chain(mbw_ctx *c, const mbw_result *res, uint64_t n_reads, co
   if (r) return r;
   r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, nanc, anoff, n_reads + 1, st); });
   if (r) return r;
-  uint64_t h[3] = {0, 0, 0};
+  uint64_t h[5] = {0, 0, 0, 0, 0};
+  TRY(hipMemcpyAsync(&h[3], ctl + CH_MAXN, 16, hipMemcpyDeviceToHost, st));
   TRY(hipMemcpyAsync(&h[0], ctl + CH_GUARD, 8, hipMemcpyDeviceToHost, st));
   TRY(hipMemcpyAsync(&h[1], choff + n_reads, 8, hipMemcpyDeviceToHost, st));
   TRY(hipMemcpyAsync(&h[2], anoff + n_reads, 8, hipMemcpyDeviceToHost, st));
@@ -508,6 +514,8 @@ extern "C" int mbw_chain(mbw_ctx *c, const mbw_result *res, uint64_t n_reads, co
   out->anchors = (const mbw_anchor_t *)c->ch_outa.p;
   out->ms_kernel = tk;
   out->ms_total = tt;
+  out->max_read_anchors = h[3];
+  out->reads_over_lds = h[4];
   return MBW_OK;
 }
 
