@@ -167,6 +167,7 @@ struct ChainArgs {
   unsigned long long *__restrict__ nch, *__restrict__ nanc;   // per read
   unsigned long long *__restrict__ ctl;    // CH_NEXT: work counter (reads); CH_GUARD: guard trips
   uint64_t na;                             // anchors in total
+  uint32_t chunk;                          // reads per grab of the work counter
 };
 
 // A read's f, predecessors and used flags live in the wave's LDS area when it has at most CH_CAP
@@ -307,35 +308,42 @@ __device__ __forceinline__ bool chain_read(const ChainArgs &a, uint64_t r, uint6
 }
 
 __global__ void __launch_bounds__(64 * CH_WAVES) k_chain(ChainArgs a) {
-  // Every loop has a hard bound taken from the validated anchor count N of the read (a wave takes
-  // at most n_reads + 1 reads); a bound that is reached marks CH_GUARD and ends the work of the
-  // wave on that read, so a corrupt input can only produce an error, never a runaway loop.
+  // Every loop has a hard bound taken from the validated anchor count N of the read; a bound that is
+  // reached marks CH_GUARD and ends the work of the wave on that read, so a corrupt input can only
+  // produce an error, never a runaway loop.  Waves take `chunk` reads per grab of the work counter
+  // (device-scope atomics on one address serialise: one per read would cost more than the work).
   __shared__ int32_t sF[CH_WAVES][CH_CAP], sP[CH_WAVES][CH_CAP];
   __shared__ uint8_t sU[CH_WAVES][CH_CAP];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (uint64_t take = 0; take <= a.n_reads; ++take) {
+  uint32_t maxn = 0, big = 0;
+  for (uint64_t grab = 0; grab <= a.n_reads; ++grab) {
     unsigned long long t = 0;
-    if (lane == 0) t = atomicAdd(&a.ctl[CH_NEXT], 1ull);
-    const uint64_t r = uni((uint64_t)__shfl(t, 0));
-    if (r >= a.n_reads) break;
-    const uint64_t a0 = uni((uint64_t)a.aoff[r]);
-    const uint64_t a1 = uni((uint64_t)a.aoff[r + 1]);
-    if (a1 < a0 || a1 > a.na) {
-      if (lane == 0) { atomicOr(&a.ctl[CH_GUARD], 1ull); a.nch[r] = 0; a.nanc[r] = 0; }
-      continue;
+    if (lane == 0) t = atomicAdd(&a.ctl[CH_NEXT], (unsigned long long)a.chunk);
+    const uint64_t r0 = uni((uint64_t)__shfl(t, 0));
+    if (r0 >= a.n_reads) break;
+    const uint64_t r1 = r0 + a.chunk < a.n_reads ? r0 + a.chunk : a.n_reads;
+    for (uint64_t r = r0; r < r1; ++r) {
+      const uint64_t a0 = uni((uint64_t)a.aoff[r]);
+      const uint64_t a1 = uni((uint64_t)a.aoff[r + 1]);
+      if (a1 < a0 || a1 > a.na) {
+        if (lane == 0) { atomicOr(&a.ctl[CH_GUARD], 1ull); a.nch[r] = 0; a.nanc[r] = 0; }
+        continue;
+      }
+      const uint32_t N = (uint32_t)(a1 - a0);
+      if (N == 0) {
+        if (lane == 0) { a.nch[r] = 0; a.nanc[r] = 0; }
+        continue;
+      }
+      maxn = N > maxn ? N : maxn;
+      big += N > CH_CAP ? 1u : 0u;
+      const bool ok = N <= CH_CAP ? chain_read(a, r, a0, N, sF[wv], sP[wv], sU[wv], lane)
+                                  : chain_read(a, r, a0, N, a.F + a0, a.P + a0, a.U + a0, lane);
+      if (!ok && lane == 0) { atomicOr(&a.ctl[CH_GUARD], 2ull); a.nch[r] = 0; a.nanc[r] = 0; }
     }
-    const uint32_t N = (uint32_t)(a1 - a0);
-    if (N == 0) {
-      if (lane == 0) { a.nch[r] = 0; a.nanc[r] = 0; }
-      continue;
-    }
-    if (lane == 0) {
-      atomicMax(&a.ctl[CH_MAXN], (unsigned long long)N);
-      if (N > CH_CAP) atomicAdd(&a.ctl[CH_BIG], 1ull);
-    }
-    const bool ok = N <= CH_CAP ? chain_read(a, r, a0, N, sF[wv], sP[wv], sU[wv], lane)
-                                : chain_read(a, r, a0, N, a.F + a0, a.P + a0, a.U + a0, lane);
-    if (!ok && lane == 0) { atomicOr(&a.ctl[CH_GUARD], 2ull); a.nch[r] = 0; a.nanc[r] = 0; }
+  }
+  if (lane == 0 && maxn) {
+    atomicMax(&a.ctl[CH_MAXN], (unsigned long long)maxn);
+    if (big) atomicAdd(&a.ctl[CH_BIG], (unsigned long long)big);
   }
 }
 
@@ -478,6 +486,8 @@ extern "C" int mbw_chain(mbw_ctx *c, const mbw_result *res, uint64_t n_reads, co
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_chain, 64 * CH_WAVES, 0) != hipSuccess || per < 1)
       per = 4;
     const uint64_t grid = std::min<uint64_t>((n_reads + CH_WAVES - 1) / CH_WAVES, (uint64_t)per * c->n_cu);
+    // about 16 grabs per wave, at most 64 reads each, so that reads with many anchors still spread
+    ca.chunk = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(64, n_reads / (grid * CH_WAVES * 16)));
     k_chain<<<(unsigned)grid, 64 * CH_WAVES, 0, st>>>(ca);
     TRY(hipGetLastError());
   }
