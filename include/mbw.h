@@ -200,7 +200,11 @@ typedef struct {
   const mbw_piece_t *pieces;
 } mbw_result;
 
-/* Seed a batch of reads.
+/* Seed a batch of reads: for every read P, its (l,c)-SMEMs (Section 2.1 definitions; found with
+ * Algorithm 3, BatchFindSMEM, Section 2.5, with the k-mer shortcut), the second seeding round of
+ * Section 2.6 ((floor((j-i)/2), s+1)-SMEMs inside long rare SMEMs), and the reference positions of
+ * every seed with s <= max_occ by LF walks to the sampled SA (Algorithm 2, Section 2.4); for a
+ * bisulfite index the strand filter and optional refinement of Section 2.9.
  *   reads:   concatenated read bases, ASCII (A/C/G/T case-insensitive; anything else is a base
  *            that matches nothing), host or device pointer.
  *   lengths: n_reads x u32 read lengths (host or device), each < 65536; reads are stored back to
@@ -212,6 +216,34 @@ typedef struct {
  * mbw_seed on the same ctx.  Errors: MBW_E_INVAL, MBW_E_NOMEM, MBW_E_HIP. */
 int mbw_seed(mbw_ctx *ctx, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads,
              int min_seed_len, int max_occ, const mbw_seed_opts *opts, void *stream, mbw_result *out);
+
+/* Caller-owned buffers of mbw_seed_into (device memory, e.g. torch tensors), and the sizes the call
+ * needs, written back by it. */
+typedef struct {
+  void *workspace;              /* every temporary of the call is carved from here; 256-byte aligned */
+  uint64_t workspace_bytes;
+  mbw_seed_t *seeds;            /* result records */
+  uint64_t seeds_cap;
+  uint64_t *pos;                /* positions */
+  uint64_t pos_cap;
+  mbw_piece_t *pieces;          /* refined pieces (opts.bs_refine only; may be NULL otherwise) */
+  uint64_t pieces_cap;
+  uint64_t workspace_needed;    /* written back: work space bytes used, or at least needed */
+  uint64_t seeds_needed, pos_needed, pieces_needed;   /* written back once known */
+} mbw_seed_buffers;
+
+/* mbw_seed with caller-owned memory: computes exactly what mbw_seed computes (Algorithm 3 for the
+ * (l,c)-SMEMs of Section 2.5, the two seeding rounds of Section 2.6, Algorithm 2's locate of Section
+ * 2.4, the bisulfite filter and refinement of Section 2.9) but allocates no device memory: all work
+ * buffers come from bufs->workspace and the seeds, positions and pieces are written to the caller's
+ * buffers, which the returned mbw_result points to (valid while the caller keeps them).  The context
+ * must be the one whose index is meant; its own buffers are left untouched.
+ * A buffer that is too small makes the call return MBW_E_CAPACITY with the sizes learnt so far in
+ * bufs->*_needed (a work space shortfall reports at least the bytes asked for); enlarging those
+ * buffers and calling again converges (each retry gets further).  On success the *_needed fields
+ * hold the exact sizes used.  Errors: as mbw_seed, plus MBW_E_CAPACITY. */
+int mbw_seed_into(mbw_ctx *ctx, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads, int min_seed_len,
+                  int max_occ, const mbw_seed_opts *opts, void *stream, mbw_seed_buffers *bufs, mbw_result *out);
 
 /* Copy a result to host buffers (seeds: n_seeds records, pos: n_pos values; either may be NULL). */
 int mbw_result_download(mbw_ctx *ctx, const mbw_result *res, mbw_seed_t *seeds, uint64_t *pos);

@@ -40,7 +40,7 @@ EXPORTS = ["mbw_strerror", "mbw_last_error", "mbw_index_build", "mbw_index_save"
            "mbw_seed", "mbw_result_download", "mbw_pos_to_ref", "mbw_tune",
            "mbw_result_download_pieces", "mbw_serve_open", "mbw_serve_submit", "mbw_serve_wait", "mbw_serve_release", "mbw_serve_stats",
            "mbw_serve_close", "mbw_rescue_filter", "mbw_rescue_download", "mbw_debug_set_mem_limit", "mbw_chain",
-           "mbw_chain_download"]
+           "mbw_chain_download", "mbw_seed_into"]
 
 
 class MbwError(RuntimeError):
@@ -87,6 +87,13 @@ class RescueOpts(C.Structure):
 class RescueResult(C.Structure):
     _fields_ = [("n_cands", C.c_uint64), ("n_pass", C.c_uint64), ("hits", C.c_void_p), ("pass_", C.c_void_p),
                 ("ms_kernel", C.c_float), ("ms_total", C.c_float)]
+
+
+class SeedBuffers(C.Structure):
+    _fields_ = [("workspace", C.c_void_p), ("workspace_bytes", C.c_uint64), ("seeds", C.c_void_p),
+                ("seeds_cap", C.c_uint64), ("pos", C.c_void_p), ("pos_cap", C.c_uint64), ("pieces", C.c_void_p),
+                ("pieces_cap", C.c_uint64), ("workspace_needed", C.c_uint64), ("seeds_needed", C.c_uint64),
+                ("pos_needed", C.c_uint64), ("pieces_needed", C.c_uint64)]
 
 
 class ChainOpts(C.Structure):
@@ -145,6 +152,8 @@ def load_library():
     L.mbw_ctx_free.argtypes = [vp]
     L.mbw_ctx_free.restype = None
     L.mbw_seed.argtypes = [vp, vp, vp, u64, i32, i32, C.POINTER(SeedOpts), vp, C.POINTER(Result)]
+    L.mbw_seed_into.argtypes = [vp, vp, vp, u64, i32, i32, C.POINTER(SeedOpts), vp, C.POINTER(SeedBuffers),
+                                C.POINTER(Result)]
     L.mbw_result_download.argtypes = [vp, C.POINTER(Result), vp, vp]
     L.mbw_result_download_pieces.argtypes = [vp, C.POINTER(Result), vp]
     L.mbw_pos_to_ref.argtypes = [vp, u64, C.c_uint32, C.POINTER(C.c_int), C.POINTER(C.c_uint64)]
@@ -397,6 +406,50 @@ class Context:
         return SeedOutput(res.n_seeds, res.n_pos, res.seeds or 0, res.pos or 0, res.lines_smem, res.lines_locate,
                           res.steps, res.lf_steps, res.ms_smem, res.ms_locate, res.ms_total, res.n_smem_launches,
                           res.wave_iters, res.lane_iters, res.max_chain, res, self)
+
+    def seed_into(self, reads, lengths, workspace, seeds, pos, pieces=None, min_seed_len: int = 19, max_occ: int = 500,
+                  stream=None, entry: str = "mbw_seed_into", **kw):
+        """``mbw_seed_into``: the same result as :meth:`seed` in caller-owned device buffers (torch
+        uint8 tensors, or (pointer, bytes) pairs): ``workspace`` for every temporary, ``seeds``
+        (56-byte records), ``pos`` (uint64), ``pieces`` (24-byte records, bisulfite refinement).
+        Returns (SeedOutput, SeedBuffers with the ``*_needed`` sizes); an MbwError with code
+        MBW_E_CAPACITY carries the buffers as ``.buffers``."""
+        def span(x, item):
+            if x is None:
+                return None, 0
+            if isinstance(x, tuple):
+                return x[0], x[1] // item
+            return x.data_ptr(), x.numel() * x.element_size() // item
+        n = int(lengths.numel() if hasattr(lengths, "numel") else len(lengths))
+        if isinstance(lengths, np.ndarray):
+            lengths = np.ascontiguousarray(lengths, dtype=np.uint32)
+        if isinstance(reads, np.ndarray):
+            reads = np.ascontiguousarray(reads, dtype=np.uint8)
+        o = self._opts(kw)
+        wp, wb = span(workspace, 1)
+        sp, sc = span(seeds, SEED_DTYPE.itemsize)
+        pp, pc = span(pos, 8)
+        qp, qc = span(pieces, PIECE_DTYPE.itemsize)
+        b = SeedBuffers(wp, wb, sp, sc, pp, pc, qp, qc, 0, 0, 0, 0)
+        res = Result()
+        rc = getattr(self._lib, entry)(self._h, _ptr(reads) if n else None, _ptr(lengths) if n else None, n,
+                                       int(min_seed_len), int(max_occ), C.byref(o), _stream_handle(stream), C.byref(b),
+                                       C.byref(res))
+        if rc != MBW_OK:
+            err = MbwError(rc, self._lib.mbw_last_error().decode(errors="replace"))
+            err.buffers = b
+            raise err
+        return (SeedOutput(res.n_seeds, res.n_pos, res.seeds or 0, res.pos or 0, res.lines_smem, res.lines_locate,
+                           res.steps, res.lf_steps, res.ms_smem, res.ms_locate, res.ms_total, res.n_smem_launches,
+                           res.wave_iters, res.lane_iters, res.max_chain, res, self), b)
+
+    @staticmethod
+    def _opts(kw):
+        return SeedOpts(int(kw.get("min_occ", 1)), int(bool(kw.get("reseed", True))), int(kw.get("reseed_len", 38)),
+                        int(kw.get("reseed_occ", 10)), int(kw.get("bs_role", 0)), int(kw.get("kernel", KERNEL_COOP)),
+                        int(bool(kw.get("use_kmer", True))), int(kw.get("blocks_per_cu", 0)),
+                        int(not kw.get("stage", True)), int(bool(kw.get("unique_ext", True))), int(kw.get("seg_len", 0)),
+                        int(bool(kw.get("bs_refine", False))))
 
     def rescue(self, reads, lengths, cands, q: int = 7, min_hits: int = 10, bs_role: int = 0,
                stream=None) -> RescueOutput:

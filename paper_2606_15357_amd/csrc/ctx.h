@@ -17,7 +17,9 @@ struct mbw_ctx {
   const mbw_index *ix;
   int device;
   int n_cu;
-  struct Buf { void *p = nullptr; size_t bytes = 0; };   // grow-only device buffers (stream-ordered allocations)
+  // Device buffers: grow-only stream-ordered allocations, or (epoch != 0) carved for one call from a
+  // work space that the caller provides
+  struct Buf { void *p = nullptr; size_t bytes = 0; uint32_t epoch = 0; };
   // seeding
   Buf codes, ascii, lens, offs, raw, subq, keys0, keys1, vals0, vals1, flag, idx, seeds, npos, posoff, xrows, pos, pos2,
       keep, kidx, temp, ctl, pwords, pnmask, woffs, nwords, wread, q1, q2, bf0, bf1, bp0, bp1, bid0, bid1, bk0, bk1, q1s,
@@ -27,6 +29,11 @@ struct mbw_ctx {
   // chaining (its own buffers likewise)
   Buf ch_ctl, ch_cnt, ch_aoff, ch_slot, ch_cslot, ch_A, ch_As, ch_k2a, ch_k2b, ch_k1a, ch_k1b, ch_va, ch_vb, ch_F, ch_P,
       ch_U, ch_CH, ch_CA, ch_nch, ch_nanc, ch_choff, ch_anoff, ch_out, ch_outa;
+  // work space mode (mbw_seed_into and its variant on the static scratch array): every buffer of the
+  // call is carved from [arena, arena + arena_size); arena_need is the high-water mark asked for
+  uint8_t *arena = nullptr;
+  size_t arena_size = 0, arena_used = 0, arena_need = 0;
+  uint32_t epoch = 0;
   hipEvent_t ev[8] = {};
   // SMEM launches whose device time is still to be read: a start and an end event each, read once
   // the host has waited for the stream anyway (no wait of its own per launch)
@@ -61,6 +68,22 @@ extern std::atomic<unsigned long long> g_mbw_mem_limit;
 // refuses leaves the buffer as it was.
 static inline int grow(mbw_ctx *c, mbw_ctx::Buf &b, size_t bytes) {
   if (bytes == 0) bytes = 16;
+  if (c->arena) {
+    if (b.epoch == c->epoch && b.bytes >= bytes) return 0;
+    const size_t want = (bytes + 255) & ~(size_t)255;
+    if (c->arena_used + want > c->arena_size) {
+      if (c->arena_used + want > c->arena_need) c->arena_need = c->arena_used + want;
+      mbw_set_error("work space too small: this call needs at least " + std::to_string(c->arena_used + want) +
+                    " bytes of the " + std::to_string(c->arena_size) + " given");
+      return MBW_E_CAPACITY;
+    }
+    b.p = c->arena + c->arena_used;
+    b.bytes = want;
+    b.epoch = c->epoch;
+    c->arena_used += want;
+    if (c->arena_used > c->arena_need) c->arena_need = c->arena_used;
+    return 0;
+  }
   if (b.bytes >= bytes) return 0;
   size_t want = bytes + bytes / 2 + 256;
   if (const unsigned long long lim = g_mbw_mem_limit.load(std::memory_order_relaxed)) {
@@ -82,6 +105,36 @@ static inline int grow(mbw_ctx *c, mbw_ctx::Buf &b, size_t bytes) {
   return 0;
 }
 #define GROW(buf, bytes) do { int r_ = grow(c, buf, bytes); if (r_) return r_; } while (0)
+
+// A buffer that is no longer needed (work space mode: its space is simply not reused in this call).
+static inline void release(mbw_ctx *c, mbw_ctx::Buf &b, hipStream_t st) {
+  if (!c->arena && b.p) (void)hipFreeAsync(b.p, st);
+  b = mbw_ctx::Buf();
+}
+
+// For the duration of one work-space call: the context's own buffers are set aside (they stay
+// allocated for later calls) and every buffer of the call is carved from the caller's work space.
+struct ArenaScope {
+  mbw_ctx *c;
+  std::vector<mbw_ctx::Buf> saved;
+  ArenaScope(mbw_ctx *ctx, void *base, size_t bytes) : c(ctx) {
+    for (auto *b : c->buffers()) {
+      saved.push_back(*b);
+      if (b != &c->ctl) *b = mbw_ctx::Buf();
+    }
+    c->arena = (uint8_t *)base;
+    c->arena_size = bytes;
+    c->arena_used = 0;
+    c->arena_need = 0;
+    c->epoch = c->epoch + 1 ? c->epoch + 1 : 1;
+  }
+  ~ArenaScope() {
+    auto bufs = c->buffers();
+    for (size_t t = 0; t < bufs.size(); ++t) *bufs[t] = saved[t];
+    c->arena = nullptr;
+    c->arena_size = c->arena_used = 0;
+  }
+};
 
 static inline bool is_device_ptr(const void *p) {
   hipPointerAttribute_t a;

@@ -25,6 +25,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 #include <cstdio>
@@ -1411,8 +1412,11 @@ static int segment_queries(mbw_ctx *c, const Query *q, uint64_t n, uint32_t seg,
   return 0;
 }
 
-extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads, int min_seed_len,
-                        int max_occ, const mbw_seed_opts *opts, void *stream, mbw_result *out) {
+// The whole path of one call.  ob == nullptr: buffers are the context's own (grown as needed);
+// otherwise the context is in work space mode (ArenaScope) and the seeds, positions and pieces go to
+// the caller's buffers, whose required sizes are written back as they become known.
+static int seed_impl(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads, int min_seed_len,
+                     int max_occ, const mbw_seed_opts *opts, void *stream, mbw_seed_buffers *ob, mbw_result *out) {
   if (!c || !out) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
   memset(out, 0, sizeof(*out));
   if (min_seed_len < 1 || max_occ < 1) { mbw_set_error("min_seed_len and max_occ must be >= 1"); return MBW_E_INVAL; }
@@ -1523,12 +1527,6 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     R.pn = (const uint32_t *)c->pnmask.p;
     R.woff = woff;
   }
-  // SMEM rounds.  Per-wave output chunks leave up to one partly used chunk per wave of the grid.
-  const uint64_t chunk_slack = (uint64_t)c->n_cu * 64 * OUT_CHUNK;
-  uint64_t seed_cap = std::max<uint64_t>(1 << 16, n_reads * 6) + chunk_slack;
-  if (c->raw.bytes / sizeof(SeedRec) > seed_cap) seed_cap = c->raw.bytes / sizeof(SeedRec);
-  uint64_t subq_cap = std::max<uint64_t>(1 << 14, n_reads) + chunk_slack;
-  if (c->subq.bytes / sizeof(Query) > subq_cap) subq_cap = c->subq.bytes / sizeof(Query);
   SeedParams P;
   memset(&P, 0, sizeof(P));
   P.codes = (const uint8_t *)c->codes.p; P.offs = offs; P.queries = nullptr; P.n_queries = n_reads;
@@ -1571,6 +1569,21 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     r = segment_queries(c, qq + nshort1, nlong, seg_len, c->q1s, &nlong1, st);
     if (r) return r;
   }
+  // Seed and sub-query buffers.  Every wave of a round-1 launch holds one output chunk of each at a
+  // time, so up to one partly used chunk per wave and launch is left as slack.
+  uint64_t chunk_slack = 0;
+  if (coop)
+    for (int b = 0; b < 2; ++b) {
+      const uint64_t nqb = b == 0 ? nshort1 : nlong1;
+      if (!nqb) continue;
+      SeedParams Pg = P;
+      Pg.n_queries = nqb;
+      chunk_slack += (uint64_t)smem_grid(c, Pg, o, b == 0) * SMEM_WAVES * OUT_CHUNK;
+    }
+  uint64_t seed_cap = std::max<uint64_t>(1 << 16, n_reads * 6) + chunk_slack;
+  if (c->raw.bytes / sizeof(SeedRec) > seed_cap) seed_cap = c->raw.bytes / sizeof(SeedRec);
+  uint64_t subq_cap = std::max<uint64_t>(1 << 14, n_reads) + chunk_slack;
+  if (c->subq.bytes / sizeof(Query) > subq_cap) subq_cap = c->subq.bytes / sizeof(Query);
   unsigned long long n1 = 0, nq = 0, stats1[3] = {0, 0, 0};
   for (int attempt = 0;; ++attempt) {
     GROW(c->raw, seed_cap * sizeof(SeedRec));
@@ -1633,7 +1646,7 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
       int rr = grow(c, nb, (ntot + ntot / 2 + 1024) * sizeof(SeedRec));
       if (rr) return rr;
       TRY(hipMemcpyAsync(nb.p, c->raw.p, n1 * sizeof(SeedRec), hipMemcpyDeviceToDevice, st));
-      (void)hipFreeAsync(c->raw.p, st);
+      release(c, c->raw, st);
       c->raw = nb;
     }
   }
@@ -1665,11 +1678,21 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     FETCH({{flag + ns - 1, 0}, {idx + ns - 1, 0}}, v);
     nu = v[1] + v[0];
   }
-  GROW(c->seeds, (nu + 1) * sizeof(mbw_seed_t));
+  mbw_seed_t *seeds;
+  if (ob) {
+    ob->seeds_needed = nu;
+    if (nu > ob->seeds_cap) {
+      mbw_set_error("seed buffer too small: " + std::to_string(nu) + " records needed, " + std::to_string(ob->seeds_cap) + " given");
+      return MBW_E_CAPACITY;
+    }
+    seeds = ob->seeds;
+  } else {
+    GROW(c->seeds, (nu + 1) * sizeof(mbw_seed_t));
+    seeds = (mbw_seed_t *)c->seeds.p;
+  }
   GROW(c->npos, (nu + 2) * 8);
   GROW(c->posoff, (nu + 2) * 8);
   GROW(c->kpos, (nu + 1) * 8);
-  mbw_seed_t *seeds = (mbw_seed_t *)c->seeds.p;
   uint64_t *npos = (uint64_t *)c->npos.p, *posoff = (uint64_t *)c->posoff.p;
   if (ns) {
     k_seed_emit<<<grid_for(ns), 256, 0, st>>>((const SeedRec *)c->raw.p, dv.Current(), flag, idx, ns, (uint64_t)max_occ, seeds, npos,
@@ -1685,7 +1708,19 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     k_seed_posoff<<<grid_for(nu), 256, 0, st>>>(seeds, posoff, nu);
     TRY(hipGetLastError());
   }
-  GROW(c->pos, (n_pos + 1) * 8);
+  // positions: straight into the caller's buffer unless a bisulfite filter follows
+  uint64_t *posbuf;
+  if (ob && !o.bs_role) {
+    ob->pos_needed = n_pos;
+    if (n_pos > ob->pos_cap) {
+      mbw_set_error("position buffer too small: " + std::to_string(n_pos) + " needed, " + std::to_string(ob->pos_cap) + " given");
+      return MBW_E_CAPACITY;
+    }
+    posbuf = ob->pos;
+  } else {
+    GROW(c->pos, (n_pos + 1) * 8);
+    posbuf = (uint64_t *)c->pos.p;
+  }
   // locate
   uint32_t rmask = (ix->sa_sample & (ix->sa_sample - 1)) == 0 ? (uint32_t)(ix->sa_sample - 1) : 0u;
   int rshift = -1;
@@ -1694,40 +1729,53 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   if (n_pos) {
     if (!coop) {
       TRY(hipEventRecord(c->ev[3], st));
-      k_locate_plain<<<grid_for(nu), 256, 0, st>>>(v, seeds, nu, (uint64_t *)c->pos.p, rmask, rshift, ctl);
+      k_locate_plain<<<grid_for(nu), 256, 0, st>>>(v, seeds, nu, posbuf, rmask, rshift, ctl);
       TRY(hipGetLastError());
     } else {
       GROW(c->xrows, (n_pos + 1) * 8);
       k_expand_rows<<<grid_for((nu + 63) / 64 * 64 / 4, 256, 65536u), 256, 0, st>>>(seeds, (const uint64_t *)c->kpos.p, nu,
-                                                                                     (uint64_t *)c->xrows.p, (uint64_t *)c->pos.p);
+                                                                                     (uint64_t *)c->xrows.p, posbuf);
       TRY(hipGetLastError());
       const int grid = persistent_grid((const void *)k_locate_wave, 256, 0, c->n_cu, o.blocks_per_cu, n_pos, AUTO_ROWS_LOCATE);
       TRY(hipEventRecord(c->ev[3], st));
-      k_locate_wave<<<grid, 256, 0, st>>>(v, (const uint64_t *)c->xrows.p, n_pos, (uint64_t *)c->pos.p, rmask, rshift, ctl);
+      k_locate_wave<<<grid, 256, 0, st>>>(v, (const uint64_t *)c->xrows.p, n_pos, posbuf, rmask, rshift, ctl);
       TRY(hipGetLastError());
     }
   }
   TRY(hipEventRecord(c->ev[4], st));
   // bisulfite strand filter
-  const uint64_t *final_pos = (const uint64_t *)c->pos.p;
+  const uint64_t *final_pos = posbuf;
   if (o.bs_role && n_pos) {
     GROW(c->keep, (n_pos + 1) * 4);
     GROW(c->kidx, (n_pos + 1) * 8);
-    GROW(c->pos2, (n_pos + 1) * 8);
     uint32_t *keep = (uint32_t *)c->keep.p;
     uint64_t *kidx = (uint64_t *)c->kidx.p;
-    k_bs_mark<<<grid_for(n_pos + 1), 256, 0, st>>>((const uint64_t *)c->pos.p, n_pos, ix->len_r, o.bs_role, keep);
+    k_bs_mark<<<grid_for(n_pos + 1), 256, 0, st>>>(posbuf, n_pos, ix->len_r, o.bs_role, keep);
     TRY(hipGetLastError());
     r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, keep, kidx, n_pos + 1, st); });
     if (r) return r;
-    k_bs_compact<<<grid_for(n_pos), 256, 0, st>>>((const uint64_t *)c->pos.p, keep, kidx, n_pos, (uint64_t *)c->pos2.p);
+    uint64_t kept = 0;
+    FETCH({{kidx + n_pos, 1}}, &kept);
+    uint64_t *dst;
+    if (ob) {
+      ob->pos_needed = kept;
+      if (kept > ob->pos_cap) {
+        mbw_set_error("position buffer too small: " + std::to_string(kept) + " needed, " + std::to_string(ob->pos_cap) + " given");
+        return MBW_E_CAPACITY;
+      }
+      dst = ob->pos;
+    } else {
+      GROW(c->pos2, (kept + 1) * 8);
+      dst = (uint64_t *)c->pos2.p;
+    }
+    k_bs_compact<<<grid_for(n_pos), 256, 0, st>>>(posbuf, keep, kidx, n_pos, dst);
     TRY(hipGetLastError());
     k_bs_seeds<<<grid_for(nu), 256, 0, st>>>(seeds, nu, kidx);
     TRY(hipGetLastError());
-    uint64_t kept = 0;
-    FETCH({{kidx + n_pos, 1}}, &kept);
     n_pos = kept;
-    final_pos = (const uint64_t *)c->pos2.p;
+    final_pos = dst;
+  } else if (ob && o.bs_role) {
+    ob->pos_needed = 0;
   }
   // bisulfite refinement of every kept (seed, position) pair
   uint64_t n_pieces = 0;
@@ -1746,12 +1794,25 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
     r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, pc, po, n_pos + 1, st); });
     if (r) return r;
     FETCH({{po + n_pos, 1}}, &n_pieces);
-    GROW(c->pieces, (n_pieces + 1) * sizeof(mbw_piece_t));
+    mbw_piece_t *pdst;
+    if (ob) {
+      ob->pieces_needed = n_pieces;
+      if (n_pieces > ob->pieces_cap) {
+        mbw_set_error("piece buffer too small: " + std::to_string(n_pieces) + " needed, " + std::to_string(ob->pieces_cap) +
+                      " given");
+        return MBW_E_CAPACITY;
+      }
+      pdst = ob->pieces;
+    } else {
+      GROW(c->pieces, (n_pieces + 1) * sizeof(mbw_piece_t));
+      pdst = (mbw_piece_t *)c->pieces.p;
+    }
     if (n_pieces) {
       k_refine<<<grid_for(n_pos), 256, 0, st>>>(seeds, ps, final_pos, n_pos, dreads, offs, ix->orig, ix->len_r, o.bs_role,
-                                                min_seed_len, pc, po, (mbw_piece_t *)c->pieces.p);
+                                                min_seed_len, pc, po, pdst);
       TRY(hipGetLastError());
     }
+    out->pieces = pdst;
   }
   TRY(hipEventRecord(c->ev[5], st));
   {
@@ -1788,7 +1849,8 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
   out->lane_iters = c->host_ctl[C_LITER];
   out->max_chain = c->host_ctl[C_MAXCHAIN];
   out->n_pieces = n_pieces;
-  out->pieces = n_pieces ? (const mbw_piece_t *)c->pieces.p : nullptr;
+  if (!n_pieces) out->pieces = nullptr;
+  if (ob) ob->workspace_needed = c->arena_need;
   if (trace_on())
     fprintf(stderr, "{\"mbw\": \"seed\", \"reads\": %llu, \"seeds\": %llu, \"positions\": %llu, \"pieces\": %llu, "
             "\"smem_launches\": %d, \"ms_smem\": %.3f, \"ms_locate\": %.3f, \"ms_total\": %.3f, \"lines_smem\": %llu, "
@@ -1798,6 +1860,30 @@ extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
             (unsigned long long)out->lines_locate, (unsigned long long)out->wave_iters, (unsigned long long)out->lane_iters,
             (unsigned long long)out->max_chain);
   return MBW_OK;
+}
+
+extern "C" int mbw_seed(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads, int min_seed_len,
+                        int max_occ, const mbw_seed_opts *opts, void *stream, mbw_result *out) {
+  return seed_impl(c, reads, lengths, n_reads, min_seed_len, max_occ, opts, stream, nullptr, out);
+}
+
+static void clear_needed(mbw_seed_buffers *b) {
+  b->workspace_needed = b->seeds_needed = b->pos_needed = b->pieces_needed = 0;
+}
+
+extern "C" int mbw_seed_into(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads, int min_seed_len,
+                             int max_occ, const mbw_seed_opts *opts, void *stream, mbw_seed_buffers *bufs, mbw_result *out) {
+  if (!c || !bufs || !out) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
+  clear_needed(bufs);
+  if (!bufs->workspace || ((uintptr_t)bufs->workspace & 255)) {
+    mbw_set_error("the work space must be a device buffer aligned to 256 bytes"); return MBW_E_INVAL;
+  }
+  if ((bufs->seeds_cap && !bufs->seeds) || (bufs->pos_cap && !bufs->pos) || (bufs->pieces_cap && !bufs->pieces)) {
+    mbw_set_error("a result buffer with a capacity but no pointer"); return MBW_E_INVAL;
+  }
+  TRY(hipSetDevice(c->device));
+  ArenaScope scope(c, bufs->workspace, bufs->workspace_bytes);
+  return seed_impl(c, reads, lengths, n_reads, min_seed_len, max_occ, opts, stream, bufs, out);
 }
 
 extern "C" int mbw_result_download_pieces(mbw_ctx *c, const mbw_result *res, mbw_piece_t *pieces) {
