@@ -1883,7 +1883,9 @@ extern "C" int mbw_seed_into(mbw_ctx *c, const uint8_t *reads, const uint32_t *l
   }
   TRY(hipSetDevice(c->device));
   ArenaScope scope(c, bufs->workspace, bufs->workspace_bytes);
-  return seed_impl(c, reads, lengths, n_reads, min_seed_len, max_occ, opts, stream, bufs, out);
+  const int r = seed_impl(c, reads, lengths, n_reads, min_seed_len, max_occ, opts, stream, bufs, out);
+  bufs->workspace_needed = c->arena_need;   // also when the call stopped part way
+  return r;
 }
 
 extern "C" int mbw_result_download_pieces(mbw_ctx *c, const mbw_result *res, mbw_piece_t *pieces) {
