@@ -33,6 +33,7 @@ struct mbw_ctx {
   // call is carved from [arena, arena + arena_size); arena_need is the high-water mark asked for
   uint8_t *arena = nullptr;
   size_t arena_size = 0, arena_used = 0, arena_need = 0;
+  size_t arena_hint = 0;   // estimate of the whole call's need, reported when an allocation does not fit
   uint32_t epoch = 0;
   hipEvent_t ev[8] = {};
   // SMEM launches whose device time is still to be read: a start and an end event each, read once
@@ -73,6 +74,7 @@ static inline int grow(mbw_ctx *c, mbw_ctx::Buf &b, size_t bytes) {
     const size_t want = (bytes + 255) & ~(size_t)255;
     if (c->arena_used + want > c->arena_size) {
       if (c->arena_used + want > c->arena_need) c->arena_need = c->arena_used + want;
+      if (c->arena_hint > c->arena_need) c->arena_need = c->arena_hint;
       mbw_set_error("work space too small: this call needs at least " + std::to_string(c->arena_used + want) +
                     " bytes of the " + std::to_string(c->arena_size) + " given");
       return MBW_E_CAPACITY;
@@ -126,6 +128,7 @@ struct ArenaScope {
     c->arena_size = bytes;
     c->arena_used = 0;
     c->arena_need = 0;
+    c->arena_hint = 0;
     c->epoch = c->epoch + 1 ? c->epoch + 1 : 1;
   }
   ~ArenaScope() {

@@ -1412,6 +1412,29 @@ static int segment_queries(mbw_ctx *c, const Query *q, uint64_t n, uint32_t seg,
   return 0;
 }
 
+// A generous estimate of the work space one call takes, from its read count and bases (the seeding
+// result is assumed typical: 8 seeds and 64 positions per read; grids as the automatic sizing picks
+// them).  A work space call that runs short reports the larger of this and the exact need so far,
+// so that a caller who enlarges to the report usually needs one retry.
+static uint64_t ws_estimate(const mbw_ctx *c, uint64_t n, uint64_t bases, bool host_reads, const mbw_seed_opts &o) {
+  const uint64_t words = bases / 32 + n + 2;
+  uint64_t per_cu = 4;   // round-1 blocks per CU: as persistent_grid sizes them
+  if (o.blocks_per_cu > 0) per_cu = std::min<uint64_t>(4, (uint64_t)o.blocks_per_cu);
+  else if (o.blocks_per_cu == 0)
+    per_cu = std::min<uint64_t>(4, std::max<uint64_t>(1, (n + AUTO_QUERIES_R1 * (uint64_t)c->n_cu - 1) /
+                                                             (AUTO_QUERIES_R1 * (uint64_t)c->n_cu)));
+  const uint64_t slack = 2 * per_cu * (uint64_t)c->n_cu * SMEM_WAVES * OUT_CHUNK;
+  const uint64_t seeds = std::max<uint64_t>(1 << 16, 8 * n) + slack;
+  uint64_t b = 0;
+  b += n * (4 + 8 + 8 + 8 + 8 + 48 + 6 * 4 + 8 + 96);   // lengths, offsets, word counts, queries, bins, segments
+  b += host_reads ? bases + 16 : 0;
+  b += words * (8 + 4 + 4);                              // packed words, N masks, word owners
+  b += seeds * (sizeof(SeedRec) + sizeof(Query) + 16 + 8 + 8 + 24);   // seeds, sub-queries, sort, per-seed counts
+  b += 64 * n * (8 + 8 + 4 + 8 + 8 + 4 + 4 + 8);         // rows, positions, filter and refinement arrays
+  b += 16ull << 20;                                      // temporary storage of sorts and scans
+  return b;
+}
+
 // The whole path of one call.  ob == nullptr: buffers are the context's own (grown as needed);
 // otherwise the context is in work space mode (ArenaScope) and the seeds, positions and pieces go to
 // the caller's buffers, whose required sizes are written back as they become known.
@@ -1441,6 +1464,7 @@ static int seed_impl(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, 
   const mbw_index *ix = c->ix;
   const IndexView v = make_view(ix);
   unsigned long long *ctl = (unsigned long long *)c->ctl.p;
+  if (c->arena) c->arena_hint = ws_estimate(c, n_reads, 300 * n_reads, true, o);
   TRY(hipMemsetAsync(ctl, 0, C_COUNT * sizeof(unsigned long long), st));
   c->ms_smem = 0;
   c->n_smem_launches = 0;
@@ -1496,6 +1520,7 @@ static int seed_impl(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, 
     total = v[0]; maxlen = v[1]; totw = v[2]; lastf = v[3]; lastp = v[4];
   }
   if (maxlen > MBW_MAX_READ) { mbw_set_error("read longer than 65535 bases"); return MBW_E_INVAL; }
+  if (c->arena) c->arena_hint = ws_estimate(c, n_reads, total, !is_device_ptr(reads), o);
   // encode (plain kernel) or pack (wave kernels)
   const uint8_t *dreads = reads;
   if (!is_device_ptr(reads)) {

@@ -44,7 +44,7 @@ def seed_into_converging(ctx, reads, lengths, start=(1 << 20, 16, 16, 0), **kw):
             b = e.buffers
             grew = False
             if b.workspace_needed > ws_b:
-                ws_b = int(b.workspace_needed * 1.05) + 4096
+                ws_b = int(b.workspace_needed)
                 grew = True
             if b.seeds_needed > sc:
                 sc = int(b.seeds_needed)
@@ -102,13 +102,15 @@ def test_seed_into_equals_seed(small, where):
 
 
 def test_seed_into_capacity_recovery(small):
-    """From a 1 MiB work space and 16-record buffers: MBW_E_CAPACITY with larger needs each time,
-    then the same result as mbw_seed; a work space of exactly the reported size is enough."""
+    """From a 1 MiB work space and 16-record buffers: MBW_E_CAPACITY with larger needs each time
+    (the first one an estimate of the whole call), then after a few enlargements to exactly the
+    reported sizes the same result as mbw_seed; a work space of exactly the size used is enough and
+    one 4 KiB smaller is not."""
     ref, reads, exp, idx = small
     ctx = mbw.Context(idx)
     s0, p0 = ctx.seed(reads.seq, reads.lengths).download()
     out, b, tries, keep = seed_into_converging(ctx, reads.seq, reads.lengths)
-    assert tries >= 2
+    assert 2 <= tries <= 4
     s1, p1 = out.download()
     same(s1, p1, s0, p0)
     need = int(b.workspace_needed)
