@@ -1631,12 +1631,21 @@ static int seed_impl(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, 
     subq_cap = std::max<uint64_t>(subq_cap, nq + nq / 2 + 1024);
   }
   unsigned long long ntot = n1;
+  // Slot counts include the unused tails of per-wave output chunks, which depend on scheduling; in
+  // work space mode buffers sized by them take the (deterministic) slot capacity instead, so that a
+  // call needs the same work space every time.
+  const uint64_t nq_alloc = c->arena ? std::max<uint64_t>(nq, c->subq.bytes / sizeof(Query)) : nq;
   if (coop && o.reseed && nq > 0) {
     // round-2 queries by bin (unused chunk slots dropped)
-    GROW(c->q2, (nq + 1) * sizeof(Query));
-    GROW(c->bf0, (nq + 1) * 4); GROW(c->bf1, (nq + 1) * 4); GROW(c->bp0, (nq + 1) * 4); GROW(c->bp1, (nq + 1) * 4);
+    GROW(c->q2, (nq_alloc + 1) * sizeof(Query));
+    GROW(c->bf0, (nq_alloc + 1) * 4); GROW(c->bf1, (nq_alloc + 1) * 4); GROW(c->bp0, (nq_alloc + 1) * 4);
+    GROW(c->bp1, (nq_alloc + 1) * 4);
     uint32_t *fs = (uint32_t *)c->bf0.p, *fl = (uint32_t *)c->bf1.p, *ps = (uint32_t *)c->bp0.p, *pl = (uint32_t *)c->bp1.p;
     const Query *sq = (const Query *)c->subq.p;
+    if (c->arena) {
+      r = reserve_temp(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, fs, ps, nq_alloc, st); });
+      if (r) return r;
+    }
     k_query_bins<<<grid_for(nq), 256, 0, st>>>(sq, nq, o.no_stage ? 0 : 1, fs, fl);
     TRY(hipGetLastError());
     r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, fs, ps, nq, st); });
@@ -1677,12 +1686,21 @@ static int seed_impl(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, 
   }
   // sort by (read, qbeg, qend), dedup, counts
   const uint64_t ns = ntot;
-  GROW(c->keys0, ns * 8); GROW(c->keys1, ns * 8); GROW(c->vals0, ns * 4); GROW(c->vals1, ns * 4);
-  GROW(c->flag, ns * 4 + 8); GROW(c->idx, ns * 4 + 8);
+  const uint64_t ns_alloc = c->arena ? std::max<uint64_t>(ns, c->raw.bytes / sizeof(SeedRec)) : ns;
+  GROW(c->keys0, ns_alloc * 8); GROW(c->keys1, ns_alloc * 8); GROW(c->vals0, ns_alloc * 4); GROW(c->vals1, ns_alloc * 4);
+  GROW(c->flag, ns_alloc * 4 + 8); GROW(c->idx, ns_alloc * 4 + 8);
   hipcub::DoubleBuffer<uint64_t> dk((uint64_t *)c->keys0.p, (uint64_t *)c->keys1.p);
   hipcub::DoubleBuffer<uint32_t> dv((uint32_t *)c->vals0.p, (uint32_t *)c->vals1.p);
   uint32_t *flag = (uint32_t *)c->flag.p, *idx = (uint32_t *)c->idx.p;
   uint64_t nu = 0;
+  if (c->arena && ns) {   // temporary storage for the capacity, not the scheduling-dependent count
+    r = reserve_temp(c, [&](void *tp, size_t &tb) {
+      return hipcub::DeviceRadixSort::SortPairs(tp, tb, dk, dv, ns_alloc, 0, 64, st);
+    });
+    if (r) return r;
+    r = reserve_temp(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, flag, idx, ns_alloc, st); });
+    if (r) return r;
+  }
   if (ns) {
     int qb = 1;       // bits of an offset within a read (offsets run to the longest read's length)
     while ((1ull << qb) <= maxlen) ++qb;
