@@ -245,6 +245,19 @@ typedef struct {
 int mbw_seed_into(mbw_ctx *ctx, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads, int min_seed_len,
                   int max_occ, const mbw_seed_opts *opts, void *stream, mbw_seed_buffers *bufs, mbw_result *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): mbw_seed_into with the work space replaced by a static device
+ * array of 128 MiB that the library holds on each GPU it runs on until the process ends; the call
+ * allocates nothing (no hipMalloc, hipFree, pinned memory or library allocation).  reads and
+ * lengths must be in device memory; the seeds, positions and pieces go to the caller's buffers
+ * as for mbw_seed_into (bufs->workspace and workspace_bytes are ignored).  A batch whose work space
+ * does not fit in the 128 MiB (a few tens of thousands of 150-base reads) is refused with
+ * MBW_E_CAPACITY, a message saying so and the size it needs in bufs->workspace_needed.  Every call
+ * on one GPU shares that GPU's array: calls that overlap on a GPU (other threads, other streams)
+ * race and must be serialised by the caller.  Errors: as mbw_seed_into. */
+int mbw_seed_static(mbw_ctx *ctx, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads, int min_seed_len,
+                    int max_occ, const mbw_seed_opts *opts, void *stream, mbw_seed_buffers *bufs, mbw_result *out);
+
 /* Copy a result to host buffers (seeds: n_seeds records, pos: n_pos values; either may be NULL). */
 int mbw_result_download(mbw_ctx *ctx, const mbw_result *res, mbw_seed_t *seeds, uint64_t *pos);
 /* Copy the refined bisulfite pieces of a result (bs_refine) to host memory (n_pieces records). */

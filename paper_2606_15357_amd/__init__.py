@@ -40,7 +40,7 @@ EXPORTS = ["mbw_strerror", "mbw_last_error", "mbw_index_build", "mbw_index_save"
            "mbw_seed", "mbw_result_download", "mbw_pos_to_ref", "mbw_tune",
            "mbw_result_download_pieces", "mbw_serve_open", "mbw_serve_submit", "mbw_serve_wait", "mbw_serve_release", "mbw_serve_stats",
            "mbw_serve_close", "mbw_rescue_filter", "mbw_rescue_download", "mbw_debug_set_mem_limit", "mbw_chain",
-           "mbw_chain_download", "mbw_seed_into"]
+           "mbw_chain_download", "mbw_seed_into", "mbw_seed_static"]
 
 
 class MbwError(RuntimeError):
@@ -154,6 +154,7 @@ def load_library():
     L.mbw_seed.argtypes = [vp, vp, vp, u64, i32, i32, C.POINTER(SeedOpts), vp, C.POINTER(Result)]
     L.mbw_seed_into.argtypes = [vp, vp, vp, u64, i32, i32, C.POINTER(SeedOpts), vp, C.POINTER(SeedBuffers),
                                 C.POINTER(Result)]
+    L.mbw_seed_static.argtypes = L.mbw_seed_into.argtypes
     L.mbw_result_download.argtypes = [vp, C.POINTER(Result), vp, vp]
     L.mbw_result_download_pieces.argtypes = [vp, C.POINTER(Result), vp]
     L.mbw_pos_to_ref.argtypes = [vp, u64, C.c_uint32, C.POINTER(C.c_int), C.POINTER(C.c_uint64)]
@@ -442,6 +443,13 @@ class Context:
         return (SeedOutput(res.n_seeds, res.n_pos, res.seeds or 0, res.pos or 0, res.lines_smem, res.lines_locate,
                            res.steps, res.lf_steps, res.ms_smem, res.ms_locate, res.ms_total, res.n_smem_launches,
                            res.wave_iters, res.lane_iters, res.max_chain, res, self), b)
+
+    def seed_static(self, reads, lengths, seeds, pos, pieces=None, min_seed_len: int = 19, max_occ: int = 500,
+                    stream=None, **kw):
+        """``mbw_seed_static``: :meth:`seed_into` on the library's static device work space (no
+        allocation); ``reads`` and ``lengths`` must be device tensors."""
+        return self.seed_into(reads, lengths, None, seeds, pos, pieces, min_seed_len=min_seed_len, max_occ=max_occ,
+                              stream=stream, entry="mbw_seed_static", **kw)
 
     @staticmethod
     def _opts(kw):

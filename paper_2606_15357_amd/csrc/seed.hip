@@ -1185,6 +1185,8 @@ __global__ void k_refine(const mbw_seed_t *__restrict__ seeds, const uint32_t *_
 // context (struct mbw_ctx and its buffer helpers: ctx.h)
 static_assert(C_COUNT <= MBW_CTL_WORDS, "control block larger than the context's host copy");
 
+static int scratch_init(int device);
+
 extern "C" int mbw_ctx_create(const mbw_index *ix, mbw_ctx **out) {
   if (!ix || !out) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
   *out = nullptr;
@@ -1211,6 +1213,8 @@ extern "C" int mbw_ctx_create(const mbw_index *ix, mbw_ctx **out) {
     }
   }
   if (grow(c, c->ctl, C_COUNT * sizeof(unsigned long long))) { mbw_ctx_free(c); return MBW_E_NOMEM; }
+  // the device address of the static scratch array, looked up once for this device (it is current)
+  if (int rs = scratch_init(ix->device)) { mbw_ctx_free(c); return rs; }
   if (hipHostMalloc((void **)&c->hfetch, MBW_CTL_WORDS * sizeof(uint64_t), hipHostMallocCoherent) != hipSuccess ||
       hipHostGetDevicePointer((void **)&c->dfetch, c->hfetch, 0) != hipSuccess) {
     mbw_ctx_free(c);
@@ -1928,6 +1932,61 @@ extern "C" int mbw_seed_into(mbw_ctx *c, const uint8_t *reads, const uint32_t *l
   ArenaScope scope(c, bufs->workspace, bufs->workspace_bytes);
   const int r = seed_impl(c, reads, lengths, n_reads, min_seed_len, max_occ, opts, stream, bufs, out);
   bufs->workspace_needed = c->arena_need;   // also when the call stopped part way
+  return r;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Allocation-free seeding: the work space of mbw_seed_into becomes a file-scope device array of
+// MBW_SCRATCH_BYTES.  Each GPU that the library runs on holds its own copy until the process ends;
+// its device address is looked up once per device when a context is created on it (host code uses
+// that address, never the array's name).  Calls that overlap on one GPU share the array and race.
+#define MBW_SCRATCH_BYTES (128ull << 20)
+static __device__ __align__(256) uint8_t scratch[MBW_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[64];
+
+// with `device` current
+static int scratch_init(int device) {
+  if (device < 0 || device >= 64) { mbw_set_error("device ordinal out of range for the scratch table"); return MBW_E_INVAL; }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return MBW_OK;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    mbw_set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    return MBW_E_HIP;
+  }
+  g_scratch_ptr[device] = ptr;
+  return MBW_OK;
+}
+
+extern "C" int mbw_seed_static(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads, int min_seed_len,
+                               int max_occ, const mbw_seed_opts *opts, void *stream, mbw_seed_buffers *bufs, mbw_result *out) {
+  if (!c || !bufs || !out) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
+  clear_needed(bufs);
+  if (n_reads && (!reads || !lengths || !is_device_ptr(reads) || !is_device_ptr(lengths))) {
+    mbw_set_error("mbw_seed_static takes reads and lengths in device memory"); return MBW_E_INVAL;
+  }
+  if ((bufs->seeds_cap && !bufs->seeds) || (bufs->pos_cap && !bufs->pos) || (bufs->pieces_cap && !bufs->pieces)) {
+    mbw_set_error("a result buffer with a capacity but no pointer"); return MBW_E_INVAL;
+  }
+  TRY(hipSetDevice(c->device));
+  void *ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    ws = (c->device >= 0 && c->device < 64) ? g_scratch_ptr[c->device] : nullptr;
+  }
+  if (!ws) { mbw_set_error("no scratch address for this device (context not created through mbw_ctx_create)"); return MBW_E_HIP; }
+  int r;
+  {
+    ArenaScope scope(c, ws, MBW_SCRATCH_BYTES);
+    r = seed_impl(c, reads, lengths, n_reads, min_seed_len, max_occ, opts, stream, bufs, out);
+    bufs->workspace_needed = c->arena_need;
+  }
+  if (r == MBW_E_CAPACITY && bufs->workspace_needed > MBW_SCRATCH_BYTES)
+    mbw_set_error("batch too large for the allocation-free entry point: it needs at least " +
+                  std::to_string(bufs->workspace_needed) + " bytes of work space, the static array holds " +
+                  std::to_string(MBW_SCRATCH_BYTES) + " (use mbw_seed_into with a larger work space)");
   return r;
 }
 
