@@ -236,94 +236,135 @@ def latency_leg(torch, ctx, reads, dseq, dlen, sched: dict, stream):
     return dict(unit="ms per mbw_seed call, reads in HBM, median of 7", batches=rows)
 
 
-def serve_leg(mbw, idx, reads, seconds: float, sched: dict, fixed_qps: float = 0.0, workers: int = 3,
-              max_batch: int = 100_000):
-    """Open-loop serving on the resident index: Poisson arrivals, requests of log-uniform
-    1..20,000 reads drawn from the workload's reads, at half of the saturation rate measured by a
-    closed-loop burst (or at fixed_qps requests/s); latency = submit to result on the host (the
-    server's clock)."""
+LOADS = (0.25, 0.5, 0.8)
+MEAN_REQ = (20000.0 - 1.0) / np.log(20000.0)   # mean of the log-uniform 1..20,000 request size
+
+
+def _serve_points(servers: dict, make_request, n_burst: int, seconds: float, loads=LOADS, seed: int = 0):
+    """Closed-loop saturation, then open-loop Poisson arrivals at each fraction of it.
+
+    servers maps a stream name to a Server; make_request() returns (name, reads, lengths), views
+    into resident read pools (submitted without a host copy; results read in place and released).
+    Saturation = reads of a burst of n_burst requests, all submitted at once, over the time from the
+    first submission to the last result.  Each load point offers that fraction of the saturation
+    rate for `seconds`; latency = submission to host-visible result on the server's clock."""
     import threading
-    rng = np.random.default_rng(3000)
+
+    def drain(k, t):
+        srv = servers[k]
+        info = srv.wait(t, copy=False)[2]
+        srv.release(t)
+        return info
+
+    def submit(k, x, y):
+        t = servers[k].submit(x, y, copy=False)
+        while t is None:                  # queue full: back off
+            time.sleep(0.0002)
+            t = servers[k].submit(x, y, copy=False)
+        return t
+
+    for _ in range(6):                    # warm every worker's staging and result buffers
+        k, x, y = make_request()
+        drain(k, submit(k, x, y))
+    burst = [make_request() for _ in range(n_burst)]
+    t0 = time.perf_counter()
+    ts = [(k, submit(k, x, y)) for k, x, y in burst]
+    for k, t in ts:
+        drain(k, t)
+    sat_s = time.perf_counter() - t0
+    sat = sum(len(y) for _, _, y in burst) / sat_s
+    mean_req = float(np.mean([len(y) for _, _, y in burst]))
+    rng = np.random.default_rng(7000 + seed)
+    points = []
+    for frac in loads:
+        qps = frac * sat / mean_req
+        arrivals = np.cumsum(rng.exponential(1.0 / qps, size=int(qps * seconds * 1.3) + 10))
+        arrivals = arrivals[arrivals < seconds]
+        reqs = [make_request() for _ in range(arrivals.size)]
+        tickets, infos = [], []
+
+        def waiter():
+            k = 0
+            while k < len(reqs):
+                if k >= len(tickets):
+                    time.sleep(0.0001)
+                    continue
+                name, t = tickets[k]
+                infos.append((name, drain(name, t)))
+                k += 1
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        t0 = time.perf_counter()
+        for a, (k, x, y) in zip(arrivals, reqs):
+            d = t0 + a - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            tickets.append((k, submit(k, x, y)))
+        th.join()
+        wall = time.perf_counter() - t0
+        lat = np.array([(i["t_done"] - i["t_submit"]) * 1e3 for _, i in infos])
+        nr = sum(len(y) for _, _, y in reqs)
+        pt = dict(load=frac, qps=round(qps, 1), requests=len(reqs), reads_per_s=round(nr / wall, 1),
+                  p50_ms=round(float(np.percentile(lat, 50)), 3), p99_ms=round(float(np.percentile(lat, 99)), 3))
+        for name in servers:
+            if len(servers) > 1:
+                ln = np.array([(i["t_done"] - i["t_submit"]) * 1e3 for k, i in infos if k == name])
+                pt[name] = dict(requests=int(ln.size),
+                                p50_ms=round(float(np.percentile(ln, 50)), 3) if ln.size else None,
+                                p99_ms=round(float(np.percentile(ln, 99)), 3) if ln.size else None)
+        bids = {(k, i["batch_id"]): i["batch_reads"] for k, i in infos}
+        pt["batches"] = len(bids)
+        pt["mean_batch_reads"] = round(float(np.mean(list(bids.values()))), 1) if bids else 0.0
+        points.append(pt)
+    return dict(saturation_reads_per_s=round(sat, 1), saturation_burst=dict(requests=n_burst, reads=int(sum(
+        len(y) for _, _, y in burst)), seconds=round(sat_s, 3)), loads=points)
+
+
+def serve_leg(mbw, idx, reads, seconds: float, sched: dict, workers: int, max_batch: int, n_burst: int,
+              bulk_rate: float):
+    """The serving stream on the resident index: requests of log-uniform 1..20,000 reads drawn from
+    the workload's reads; closed-loop saturation and p50/p99 at 25/50/80% of it for the wave
+    kernel, and the closed-loop saturation of the same server running the plain kernel."""
     n = len(reads)
+    rng = np.random.default_rng(3000)
 
     def request():
         m = int(np.exp(rng.uniform(0.0, np.log(20000.0))))
         r0 = int(rng.integers(0, n - m))
-        return reads.seq[int(reads.offsets[r0]):int(reads.offsets[r0 + m])], reads.lengths[r0:r0 + m]
+        return "plain", reads.seq[int(reads.offsets[r0]):int(reads.offsets[r0 + m])], reads.lengths[r0:r0 + m]
 
-    srv = mbw.Server(idx, n_workers=workers, max_batch_reads=max_batch, **sched)
-    for _ in range(2):                                    # warm the workers' buffers
-        srv.wait(srv.submit(*request()))
-    burst = [request() for _ in range(300)]
-    t0 = time.perf_counter()
-    ts = [srv.submit(*r) for r in burst]
-    for t in ts:
-        srv.wait(t)
-    sat = sum(len(r[1]) for r in burst) / (time.perf_counter() - t0)
-    mean_req = (20000.0 - 1.0) / np.log(20000.0)
-    qps = fixed_qps if fixed_qps > 0 else 0.5 * sat / mean_req
-    arrivals = np.cumsum(rng.exponential(1.0 / qps, size=int(qps * seconds * 1.2) + 10))
-    arrivals = arrivals[arrivals < seconds]
-    reqs = [request() for _ in range(arrivals.size)]
-    tickets, lat, refused = [], [], 0
-    done = threading.Event()
-    info_all = []
-
-    def waiter():
-        k = 0
-        while k < len(reqs):
-            if k >= len(tickets):
-                time.sleep(0.0002)
-                continue
-            s, p, info = srv.wait(tickets[k])
-            info_all.append(info)
-            k += 1
-        done.set()
-
-    th = threading.Thread(target=waiter)
-    th.start()
-    t0 = time.perf_counter()
-    for a, r in zip(arrivals, reqs):
-        d = t0 + a - time.perf_counter()
-        if d > 0:
-            time.sleep(d)
-        t = srv.submit(*r)
-        while t is None:
-            refused += 1
-            time.sleep(0.0005)
-            t = srv.submit(*r)
-        tickets.append(t)
-    th.join()
+    cfg = dict(n_workers=workers, max_batch_reads=max_batch, max_batch_bases=max_batch * 160)
+    srv = mbw.Server(idx, **cfg, **sched)
+    st0 = srv.stats()
+    res = _serve_points({"plain": srv}, request, n_burst, seconds)
+    st = srv.stats()
     srv.close()
-    lat = np.array([(i["t_done"] - i["t_submit"]) * 1e3 for i in info_all])
-    span = max(i["t_done"] for i in info_all) - min(i["t_submit"] for i in info_all)
-    nr = sum(len(r[1]) for r in reqs)
-    batches = len(set(i["batch_id"] for i in info_all))
-    return dict(requests=len(reqs), reads=nr, qps=round(qps, 1), seconds=seconds,
-                saturation_reads_per_s=round(sat, 1), reads_per_s=round(nr / span, 1),
-                p50_ms=round(float(np.percentile(lat, 50)), 3), p99_ms=round(float(np.percentile(lat, 99)), 3),
-                batches=batches, refused_submits=refused, workers=workers, max_batch_reads=max_batch,
-                request_size="log-uniform 1..20000 reads",
-                arrivals=f"Poisson at {fixed_qps:g} requests/s" if fixed_qps > 0 else "Poisson at half the closed-loop saturation")
+    res.update(saturation_frac_of_bulk=round(res["saturation_reads_per_s"] / bulk_rate, 3), workers=workers,
+               max_batch_reads=max_batch, device_gb=round(st0["device_bytes"] / 1e9, 2),
+               split_retries=st["split_retries"], failed_requests=st["failed_requests"],
+               request_size="log-uniform 1..20000 reads", arrivals="Poisson at 25/50/80% of the closed-loop saturation",
+               handoff="requests queued without a host copy, results read in place from pinned memory")
+    sched_plain = dict(sched)
+    sched_plain["kernel"] = mbw.KERNEL_PLAIN
+    srv = mbw.Server(idx, **cfg, **sched_plain)
+    pres = _serve_points({"plain": srv}, request, n_burst, seconds, loads=())
+    srv.close()
+    res["plain_kernel"] = dict(saturation_reads_per_s=pres["saturation_reads_per_s"],
+                               note="the same server and request stream with the plain (one read per lane) kernel")
+    return res
 
 
-def serve_bs(mbw, synth, args):
+def serve_bs_leg(mbw, synth, ref, pl_idx, args):
     """Serving with a bisulfite index and a plain index of the same 3.1 Gbp reference resident:
-    Poisson requests of log-uniform 1..20,000 reads; 90% of them directional bisulfite reads
-    (150 bp, read-1 form, seeded against the four-copy index with the strand filter and the seed
-    refinement), 10% plain reads of 1-5 kbp (against the plain index); arrivals at --serve-qps
-    requests/s, or at half of the closed-loop saturation when that is 0; p50/p99 from submission to
-    result on the host."""
-    import threading
+    requests of log-uniform 1..20,000 reads; 90% of them directional bisulfite reads (150 bp,
+    read-1 form, seeded against the four-copy index with the strand filter and the seed
+    refinement), 10% plain reads of 1-5 kbp (against the plain index); closed-loop saturation of
+    the mix, then p50/p99 at 25/50/80% of it."""
     t0 = time.time()
-    ref = synth.workload_reference("serve_bs_3gbp", args.ref_len or None)
     bs_idx = mbw.Index.build(ref.codes, sa_sample=args.sa_sample, kmer_k=args.kmer, bisulfite=True, isa_sample=8)
     t_bs = time.time() - t0
-    t0 = time.time()
-    pl_idx = mbw.Index.build(ref.codes, sa_sample=args.sa_sample, kmer_k=args.kmer, isa_sample=args.isa_sample)
-    t_pl = time.time() - t0
-    log(f"indexes built: bisulfite {t_bs:.1f} s ({bs_idx.info()['bytes_resident'] / 1e9:.1f} GB), "
-        f"plain {t_pl:.1f} s ({pl_idx.info()['bytes_resident'] / 1e9:.1f} GB)")
+    log(f"bisulfite index built: {t_bs:.1f} s ({bs_idx.info()['bytes_resident'] / 1e9:.1f} GB)")
     bs_pool = synth.reads_bisulfite(ref, 1_000_000, seed=synth.READ_SEED + 4)
     pl_pool = synth.reads_uniform_len(ref, 20_000, 1000, 5000, p_sub=0.001, p_indel=0.0002, seed=synth.READ_SEED + 5)
     rng = np.random.default_rng(3001)
@@ -334,74 +375,28 @@ def serve_bs(mbw, synth, args):
         pool = bs_pool if bs else pl_pool
         m = min(m, len(pool) - 1)
         r0 = int(rng.integers(0, len(pool) - m))
-        return bs, pool.seq[int(pool.offsets[r0]):int(pool.offsets[r0 + m])], pool.lengths[r0:r0 + m]
+        return ("bisulfite" if bs else "plain_long", pool.seq[int(pool.offsets[r0]):int(pool.offsets[r0 + m])],
+                pool.lengths[r0:r0 + m])
 
-    srv = {True: mbw.Server(bs_idx, n_workers=args.bs_workers, max_batch_reads=100_000, bs_role=1, bs_refine=True),
-           False: mbw.Server(pl_idx, n_workers=args.bs_plain_workers, max_batch_reads=20_000)}
-    for _ in range(3):
-        for k in (True, False):
-            srv[k].wait(srv[k].submit(*request()[1:]))
-    burst = [request() for _ in range(300)]
-    t0 = time.perf_counter()
-    ts = [(b, srv[b].submit(x, y)) for b, x, y in burst]
-    for b, t in ts:
-        srv[b].wait(t)
-    bases = sum(int(y.sum()) for _, _, y in burst)
-    sat_reads = sum(len(y) for _, _, y in burst) / (time.perf_counter() - t0)
-    mean_req = (20000.0 - 1.0) / np.log(20000.0)
-    qps = args.serve_qps if args.serve_qps > 0 else 0.5 * sat_reads / mean_req
-    arrivals = np.cumsum(rng.exponential(1.0 / qps, size=int(qps * args.serve_seconds * 1.2) + 10))
-    arrivals = arrivals[arrivals < args.serve_seconds]
-    reqs = [request() for _ in range(arrivals.size)]
-    tickets, infos = [], []
-
-    def waiter():
-        k = 0
-        while k < len(reqs):
-            if k >= len(tickets):
-                time.sleep(0.0002)
-                continue
-            b, t = tickets[k]
-            infos.append((b, srv[b].wait(t)[2]))
-            k += 1
-
-    th = threading.Thread(target=waiter)
-    th.start()
-    t0 = time.perf_counter()
-    for a, (b, x, y) in zip(arrivals, reqs):
-        d = t0 + a - time.perf_counter()
-        if d > 0:
-            time.sleep(d)
-        t = srv[b].submit(x, y)
-        while t is None:
-            time.sleep(0.0005)
-            t = srv[b].submit(x, y)
-        tickets.append((b, t))
-    th.join()
-    wall = time.perf_counter() - t0
-    for k in srv:
-        srv[k].close()
-    lat = {k: np.array([(i["t_done"] - i["t_submit"]) * 1e3 for b, i in infos if b == k]) for k in (True, False)}
-    allat = np.concatenate([lat[True], lat[False]])
-    nr = sum(len(y) for _, _, y in reqs)
-    res = dict(metric="reads seeded/s served (bisulfite + plain), p50/p99 request latency", value=round(nr / wall, 1),
-               unit="reads/s", n_gpus=1, higher_is_better=True, data="synthetic", dtype="u64",
-               requests=len(reqs), reads=nr, qps=round(qps, 1), seconds=args.serve_seconds,
-               p50_ms=round(float(np.percentile(allat, 50)), 3), p99_ms=round(float(np.percentile(allat, 99)), 3),
-               bisulfite=dict(requests=int(lat[True].size), p50_ms=round(float(np.percentile(lat[True], 50)), 3),
-                              p99_ms=round(float(np.percentile(lat[True], 99)), 3)),
-               plain_long=dict(requests=int(lat[False].size),
-                               p50_ms=round(float(np.percentile(lat[False], 50)), 3) if lat[False].size else None,
-                               p99_ms=round(float(np.percentile(lat[False], 99)), 3) if lat[False].size else None),
-               saturation_reads_per_s=round(sat_reads, 1), burst_bases=bases,
-               config=dict(workload="3.1 Gbp synthetic reference; bisulfite 4-copy index (n = 12.4 G + 1) and plain "
-                                    "index resident; 90% directional bisulfite 150 bp requests (strand filter + seed "
-                                    "refinement), 10% plain 1-5 kbp; log-uniform 1..20000 reads per request; Poisson "
-                                    "arrivals at " + (f"{args.serve_qps:g} requests/s" if args.serve_qps > 0
-                                                      else "half the closed-loop saturation"),
-                           workers=dict(bisulfite=args.bs_workers, plain=args.bs_plain_workers),
-                           index_build_s=dict(bisulfite=round(t_bs, 1), plain=round(t_pl, 1))))
-    print(json.dumps(res), flush=True)
+    srv = {"bisulfite": mbw.Server(bs_idx, n_workers=args.bs_workers, max_batch_reads=1_000_000,
+                                   max_batch_bases=160_000_000, bs_role=1, bs_refine=True),
+           "plain_long": mbw.Server(pl_idx, n_workers=args.bs_plain_workers, max_batch_reads=20_000,
+                                    max_batch_bases=100_000_000)}
+    res = _serve_points(srv, request, args.serve_burst, args.serve_seconds, seed=1)
+    dev = sum(s.stats()["device_bytes"] for s in srv.values())
+    for s in srv.values():
+        s.close()
+    res.update(metric="reads seeded/s served (bisulfite + plain), p50/p99 request latency", unit="reads/s",
+               index_gb=dict(bisulfite=round(bs_idx.info()["bytes_resident"] / 1e9, 1),
+                             plain=round(pl_idx.info()["bytes_resident"] / 1e9, 1)),
+               index_build_s=round(t_bs, 1), device_gb_servers=round(dev / 1e9, 2),
+               workers=dict(bisulfite=args.bs_workers, plain_long=args.bs_plain_workers),
+               config="3.1 Gbp synthetic reference; bisulfite 4-copy index (n = 12.4 G + 1) and plain index "
+                      "resident; 90% directional bisulfite 150 bp requests (strand filter + seed refinement), 10% "
+                      "plain 1-5 kbp; log-uniform 1..20000 reads per request; Poisson arrivals at 25/50/80% of "
+                      "the closed-loop saturation")
+    bs_idx.free()
+    return res
 
 
 def main():
@@ -427,16 +422,15 @@ def main():
     ap.add_argument("--no-rescue", action="store_true", help="skip the mate-rescue prefilter leg")
     ap.add_argument("--no-chain", action="store_true", help="skip the chaining leg")
     ap.add_argument("--no-latency", action="store_true", help="skip the small-batch latency leg")
-    ap.add_argument("--serve-workers", type=int, default=3,
-                    help="serving leg: worker threads, one stream each (3 gave the lowest latency at 1,750 and "
-                         "2,500 requests/s; the process has 4 hardware queues)")
-    ap.add_argument("--bs-workers", type=int, default=2, help="serve_bs_3gbp: workers of the bisulfite server")
-    ap.add_argument("--bs-plain-workers", type=int, default=1, help="serve_bs_3gbp: workers of the plain server")
-    ap.add_argument("--serve-max-batch", type=int, default=100_000, help="serving leg: reads per batch at most")
-    ap.add_argument("--serve-qps", type=float, default=0.0,
-                    help="serving leg arrival rate in requests/s (0 = half the measured saturation)")
-    ap.add_argument("--serve-seconds", type=float, default=6.0,
-                    help="open-loop serving leg on the same index (0 = skip)")
+    ap.add_argument("--serve-workers", type=int, default=4, help="serving leg: worker threads, one stream each")
+    ap.add_argument("--bs-workers", type=int, default=3, help="bisulfite serving: workers of the bisulfite server")
+    ap.add_argument("--bs-plain-workers", type=int, default=1, help="bisulfite serving: workers of the plain server")
+    ap.add_argument("--serve-max-batch", type=int, default=1_000_000, help="serving leg: reads per batch at most")
+    ap.add_argument("--serve-burst", type=int, default=4000,
+                    help="requests in the closed-loop saturation burst (about 2,000 reads each)")
+    ap.add_argument("--serve-seconds", type=float, default=3.0,
+                    help="seconds of open-loop arrivals per load point (0 = skip the serving legs)")
+    ap.add_argument("--no-serve-bs", action="store_true", help="skip the bisulfite serving leg")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -458,7 +452,12 @@ def main():
                               gather_lines_per_s=lps, gather_gbs_128=round(lps * 128 / 1e9, 1), gather_ms=round(gms, 3))))
         return
     if args.workload == "serve_bs_3gbp":
-        serve_bs(mbw, synth, args)
+        ref = synth.workload_reference("serve_bs_3gbp", args.ref_len or None)
+        pl_idx = mbw.Index.build(ref.codes, sa_sample=args.sa_sample, kmer_k=args.kmer, isa_sample=args.isa_sample)
+        res = serve_bs_leg(mbw, synth, ref, pl_idx, args)
+        sat = res["saturation_reads_per_s"]
+        print(json.dumps(dict(res, value=sat, n_gpus=1, higher_is_better=True, data="synthetic", dtype="u64")),
+              flush=True)
         return
     gather_lps, _ = mbw.probe_gather(8 << 30, iters=32)
     t0 = time.time()
@@ -585,11 +584,15 @@ def main():
         latency = latency_leg(torch, ctx, reads, dseq, dlen, sched, stream)
         log(f"small batches: {latency}")
 
-    serve = None
+    serve = serve_bs = None
     if args.serve_seconds > 0:
-        serve = serve_leg(mbw, idx, reads, args.serve_seconds, sched, args.serve_qps, args.serve_workers,
-                          args.serve_max_batch)
+        ctx.free()
+        serve = serve_leg(mbw, idx, reads, args.serve_seconds, sched, args.serve_workers, args.serve_max_batch,
+                          args.serve_burst, value)
         log(f"serving: {serve}")
+        if not args.no_serve_bs and args.workload == "human_3gbp":
+            serve_bs = serve_bs_leg(mbw, synth, ref, idx, args)
+            log(f"bisulfite serving: {serve_bs}")
 
     line = dict(metric=METRIC, value=round(value, 1), unit="reads/s", n_gpus=1, steps=args.steps,
                 warmup=args.warmup, ms_per_step=round(elapsed / args.steps * 1e3, 2), higher_is_better=True,
@@ -599,7 +602,8 @@ def main():
                             min_seed_len=19, max_occ=500, sa_sample=args.sa_sample, kmer_k=info["kmer_k"],
                             isa_sample=args.isa_sample, unique_ext=not args.no_unique,
                             bases_per_line=384, line_bytes=LINE_BYTES, index_gb=round(info["bytes_resident"] / 1e9, 2)),
-                schedule=sched, plain_gpu=plain, roofline=roofline, cpu_baseline=cpu, serve=serve, batch_latency=latency,
+                schedule=sched, plain_gpu=plain, roofline=roofline, cpu_baseline=cpu, serve=serve, serve_bs=serve_bs,
+                batch_latency=latency,
                 index_build=index_build, rescue=rescue, chain=chain)
     print(json.dumps(line), flush=True)
 

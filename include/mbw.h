@@ -392,32 +392,42 @@ int mbw_chain_download(mbw_ctx *ctx, const mbw_chain_result *res, mbw_chain_t *c
 
 /* ---- debug -----------------------------------------------------------------------------------
  * Cap the device work space every context may hold (bytes; 0 = no cap, the default).  A call that
- * would grow a context beyond it fails with MBW_E_NOMEM and leaves the context usable; for tests of
- * allocation failure (a serving batch that fails reports the error to each of its requests and
- * the server goes on).  Process-wide. */
+ * would grow a context beyond it fails with MBW_E_NOMEM and leaves the context usable; a serve
+ * arena larger than the cap makes mbw_serve_open fail with MBW_E_NOMEM.  For tests of allocation
+ * failure.  Process-wide. */
 int mbw_debug_set_mem_limit(uint64_t bytes);
 
 /* ---- serving -------------------------------------------------------------------------------
- * A request loop over one resident index.  Submitted requests are queued (host copies of their
- * reads); admission is bounded by the bases waiting in the queue.  n_workers threads each own a
- * seeding context and a HIP stream; a free worker takes queued requests in arrival order into one
- * device batch (up to max_batch_reads reads and max_batch_bases bases; a larger single request
- * runs alone), so requests that arrive while other batches run join the next batch at once, and
- * the batches of different workers overlap on the device.  Each request's result equals what
- * mbw_seed returns for that request alone (read ids relative to the request). */
+ * A request loop over one resident index (the streaming use of Section 2.9's bisulfite mode, and
+ * of plain seeding).  n_workers threads each own a seeding context, a HIP stream and a fixed device
+ * arena (work space plus result buffers) allocated at mbw_serve_open: a running server allocates no
+ * device memory.  Admission is by device memory: a request whose estimated work space (the seeding
+ * path's sizing model for its reads and bases) exceeds one worker's arena, or that is over the
+ * batch budget by itself, is refused with MBW_E_CAPACITY; a free worker takes queued requests in
+ * arrival order into one device batch while the batch's estimate fits its arena (and within
+ * max_batch_reads / max_batch_bases / 65536 requests), so requests that arrive while other batches
+ * run join the next batch at once, and the batches of different workers overlap on the device.  A
+ * batch that still runs short of its arena, or meets an allocation failure, is split in two and
+ * each half run again, down to single requests, so a request's outcome never depends on what it
+ * was batched with: each request's result equals what mbw_seed returns for that request alone
+ * (read ids relative to the request). */
 typedef struct mbw_server mbw_server;
 
 typedef struct {
   int n_workers;              /* batches in flight at once (1..8); each worker has its own stream,
                                  and a process gets a few hardware queues (4 on MI355X by default),
                                  so more workers than that share them */
-  uint64_t max_batch_reads;   /* batch budget: reads ... */
+  uint64_t max_batch_reads;   /* batch budget: reads (< 2^31) ... */
   uint64_t max_batch_bases;   /* ... and bases */
-  uint64_t max_queued_bases;  /* admission: submit returns MBW_E_BUSY when the queue is not empty and
-                                 would exceed this many bases */
+  uint64_t max_queued_bases;  /* host back-pressure: submit returns MBW_E_BUSY when the queue is not
+                                 empty and would exceed this many bases */
   int min_seed_len, max_occ;  /* as mbw_seed */
   mbw_seed_opts opts;         /* as mbw_seed */
   int device;                 /* must be the index's device */
+  uint64_t device_bytes;      /* device memory of all worker arenas together, split evenly; 0 = each
+                                 arena sized by the model for a full batch of max_batch_reads reads
+                                 and max_batch_bases bases.  An arena must admit one read of 65535
+                                 bases (about 100 MB; the error message gives the least size) */
 } mbw_serve_cfg;
 
 typedef struct {
@@ -427,26 +437,48 @@ typedef struct {
                                  position */
   const uint64_t *pos;
   double t_submit, t_start, t_done;   /* seconds since mbw_serve_open (steady clock) */
-  uint64_t batch_id, batch_reads;     /* the device batch that carried the request */
+  uint64_t batch_id, batch_reads;     /* the device batch that carried the request (the last one
+                                         tried when it was split) */
   uint64_t n_pieces;          /* opts.bs_refine: the request's refined pieces (host memory owned by
                                  the server), read_id and seed counted from the request's own */
   const mbw_piece_t *pieces;
+  uint32_t attempts;          /* device batches the request was part of (> 1 after a split) */
+  uint32_t reserved;
 } mbw_serve_result;
 
-/* Start the workers.  The index must outlive the server.  Errors: MBW_E_INVAL, MBW_E_NOMEM, MBW_E_HIP. */
+typedef struct {
+  uint64_t batches;           /* device batches run (split halves included) */
+  uint64_t batch_reads;       /* reads in them */
+  uint64_t queued;            /* requests waiting for a worker */
+  uint64_t split_retries;     /* batches split in two after running short */
+  uint64_t failed_requests;   /* requests finished with an error */
+  uint64_t device_bytes;      /* device memory held by the worker arenas */
+  uint64_t workspace_bytes;   /* one worker's work space, the admission bound */
+  uint64_t seeds_cap, pos_cap, pieces_cap;   /* one worker's result buffers (records) */
+} mbw_serve_stats_t;
+
+/* Start the workers and allocate their arenas.  The index must outlive the server.  Errors:
+ * MBW_E_INVAL (configuration, device_bytes below the minimum), MBW_E_NOMEM (arena or pinned
+ * staging allocation, or an arena over the debug cap), MBW_E_HIP. */
 int mbw_serve_open(const mbw_index *idx, const mbw_serve_cfg *cfg, mbw_server **out);
 /* Queue a request (host pointers, copied before return; lengths < 65536).  Non-blocking.
- * Errors: MBW_E_INVAL, MBW_E_BUSY (queue full: retry later), MBW_E_NOMEM. */
+ * Errors: MBW_E_INVAL, MBW_E_CAPACITY (the request can never fit a worker: see above), MBW_E_BUSY
+ * (queue full: retry later), MBW_E_NOMEM. */
 int mbw_serve_submit(mbw_server *s, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads,
                      uint64_t *ticket);
+/* mbw_serve_submit without the host copy: the caller keeps reads and lengths valid and unchanged
+ * until mbw_serve_wait reports the request finished (or the server is closed). */
+int mbw_serve_submit_nocopy(mbw_server *s, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads,
+                            uint64_t *ticket);
 /* Wait up to timeout_ms (< 0: forever) for a request; MBW_E_BUSY if it is not finished by then,
- * else its result (valid until mbw_serve_release) or the error its batch returned. */
+ * else its result (valid until mbw_serve_release) or its error (the timing fields and attempts
+ * are filled in either case). */
 int mbw_serve_wait(mbw_server *s, uint64_t ticket, int timeout_ms, mbw_serve_result *out);
 /* Free a finished request's result.  Errors: MBW_E_INVAL (unknown ticket), MBW_E_BUSY (unfinished). */
 int mbw_serve_release(mbw_server *s, uint64_t ticket);
-/* Counters: device batches run, reads in them, requests waiting. */
-int mbw_serve_stats(mbw_server *s, uint64_t *batches, uint64_t *batch_reads, uint64_t *queued);
-/* Finish every queued request, stop the workers and free the server. */
+/* Counters since mbw_serve_open. */
+int mbw_serve_stats(mbw_server *s, mbw_serve_stats_t *out);
+/* Finish every queued request, stop the workers and free the server and its arenas. */
 void mbw_serve_close(mbw_server *s);
 
 #ifdef __cplusplus

@@ -38,7 +38,7 @@ SEED_ROUND2 = 2
 EXPORTS = ["mbw_strerror", "mbw_last_error", "mbw_index_build", "mbw_index_save", "mbw_index_load",
            "mbw_index_free", "mbw_index_info", "mbw_index_device_arrays", "mbw_ctx_create", "mbw_ctx_free",
            "mbw_seed", "mbw_result_download", "mbw_pos_to_ref", "mbw_tune",
-           "mbw_result_download_pieces", "mbw_serve_open", "mbw_serve_submit", "mbw_serve_wait", "mbw_serve_release", "mbw_serve_stats",
+           "mbw_result_download_pieces", "mbw_serve_open", "mbw_serve_submit", "mbw_serve_submit_nocopy", "mbw_serve_wait", "mbw_serve_release", "mbw_serve_stats",
            "mbw_serve_close", "mbw_rescue_filter", "mbw_rescue_download", "mbw_debug_set_mem_limit", "mbw_chain",
            "mbw_chain_download", "mbw_seed_into", "mbw_seed_static"]
 
@@ -70,14 +70,21 @@ class SeedOpts(C.Structure):
 class ServeCfg(C.Structure):
     _fields_ = [("n_workers", C.c_int), ("max_batch_reads", C.c_uint64), ("max_batch_bases", C.c_uint64),
                 ("max_queued_bases", C.c_uint64), ("min_seed_len", C.c_int), ("max_occ", C.c_int),
-                ("opts", SeedOpts), ("device", C.c_int)]
+                ("opts", SeedOpts), ("device", C.c_int), ("device_bytes", C.c_uint64)]
 
 
 class ServeResult(C.Structure):
     _fields_ = [("n_seeds", C.c_uint64), ("n_pos", C.c_uint64), ("seeds", C.c_void_p), ("pos", C.c_void_p),
                 ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
                 ("batch_id", C.c_uint64), ("batch_reads", C.c_uint64), ("n_pieces", C.c_uint64),
-                ("pieces", C.c_void_p)]
+                ("pieces", C.c_void_p), ("attempts", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class ServeStats(C.Structure):
+    _fields_ = [("batches", C.c_uint64), ("batch_reads", C.c_uint64), ("queued", C.c_uint64),
+                ("split_retries", C.c_uint64), ("failed_requests", C.c_uint64), ("device_bytes", C.c_uint64),
+                ("workspace_bytes", C.c_uint64), ("seeds_cap", C.c_uint64), ("pos_cap", C.c_uint64),
+                ("pieces_cap", C.c_uint64)]
 
 
 class RescueOpts(C.Structure):
@@ -161,9 +168,10 @@ def load_library():
     L.mbw_tune.argtypes = [vp, vp, vp, u64, i32, i32, C.POINTER(SeedOpts), vp, C.POINTER(SeedOpts), C.POINTER(C.c_float)]
     L.mbw_serve_open.argtypes = [vp, C.POINTER(ServeCfg), C.POINTER(vp)]
     L.mbw_serve_submit.argtypes = [vp, vp, vp, u64, C.POINTER(C.c_uint64)]
+    L.mbw_serve_submit_nocopy.argtypes = [vp, vp, vp, u64, C.POINTER(C.c_uint64)]
     L.mbw_serve_wait.argtypes = [vp, u64, i32, C.POINTER(ServeResult)]
     L.mbw_serve_release.argtypes = [vp, u64]
-    L.mbw_serve_stats.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+    L.mbw_serve_stats.argtypes = [vp, C.POINTER(ServeStats)]
     L.mbw_serve_close.argtypes = [vp]
     L.mbw_serve_close.restype = None
     L.mbw_rescue_filter.argtypes = [vp, vp, vp, u64, vp, u64, C.POINTER(RescueOpts), vp, C.POINTER(RescueResult)]
@@ -606,75 +614,104 @@ def canonical(seeds: np.ndarray, pos: np.ndarray):
     return s, flat
 
 
+def _view(ptr, n: int, dtype: np.dtype) -> np.ndarray:
+    """A numpy array over n records at host address ptr (no copy)."""
+    if not n or not ptr:
+        return np.zeros(0, dtype=dtype)
+    return np.frombuffer((C.c_char * (int(n) * dtype.itemsize)).from_address(ptr), dtype=dtype)
+
+
 class Server:
     """Request loop over a resident index (``mbw_serve_*``): submit reads, wait for each
-    request's seeds and positions; batches of several requests overlap on the device."""
+    request's seeds and positions; batches of several requests overlap on the device.  Each worker
+    holds a fixed device arena (``device_bytes`` for all of them together; 0 = sized for a full
+    batch); requests that can never fit one are refused with MBW_E_CAPACITY."""
 
     def __init__(self, index: Index, n_workers: int = 2, max_batch_reads: int = 1 << 20,
                  max_batch_bases: int = 1 << 28, max_queued_bases: int = 1 << 32, min_seed_len: int = 19,
-                 max_occ: int = 500, **opts):
+                 max_occ: int = 500, device_bytes: int = 0, **opts):
         self._lib = load_library()
         self.index = index
         o = SeedOpts(int(opts.get("min_occ", 1)), int(bool(opts.get("reseed", True))), int(opts.get("reseed_len", 38)),
-                     int(opts.get("reseed_occ", 10)), int(opts.get("bs_role", 0)), KERNEL_COOP,
+                     int(opts.get("reseed_occ", 10)), int(opts.get("bs_role", 0)), int(opts.get("kernel", KERNEL_COOP)),
                      int(bool(opts.get("use_kmer", True))), int(opts.get("blocks_per_cu", 0)),
                      int(not opts.get("stage", True)), int(bool(opts.get("unique_ext", True))), int(opts.get("seg_len", 0)),
                      int(bool(opts.get("bs_refine", False))))
         cfg = ServeCfg(int(n_workers), int(max_batch_reads), int(max_batch_bases), int(max_queued_bases),
-                       int(min_seed_len), int(max_occ), o, int(index.info()["device"]))
+                       int(min_seed_len), int(max_occ), o, int(index.info()["device"]), int(device_bytes))
+        self._held = {}   # ticket -> arrays of a request submitted without a copy
         h = C.c_void_p()
         _check(self._lib.mbw_serve_open(index._h, C.byref(cfg), C.byref(h)))
         self._h = h
 
-    def submit(self, reads: np.ndarray, lengths: np.ndarray):
-        """Queue a request; returns its ticket, or None when the queue is full (MBW_E_BUSY)."""
+    def submit(self, reads: np.ndarray, lengths: np.ndarray, copy: bool = True):
+        """Queue a request; returns its ticket, or None when the queue is full (MBW_E_BUSY).
+        copy=False queues the arrays themselves (no host copy): they are kept referenced here and
+        must not be modified until the request is waited for."""
         reads = np.ascontiguousarray(reads, dtype=np.uint8)
         lengths = np.ascontiguousarray(lengths, dtype=np.uint32)
         t = C.c_uint64()
-        rc = self._lib.mbw_serve_submit(self._h, reads.ctypes.data if reads.size else None,
-                                        lengths.ctypes.data if lengths.size else None, lengths.size, C.byref(t))
+        fn = self._lib.mbw_serve_submit if copy else self._lib.mbw_serve_submit_nocopy
+        rc = fn(self._h, reads.ctypes.data if reads.size else None, lengths.ctypes.data if lengths.size else None,
+                lengths.size, C.byref(t))
         if rc == MBW_E_BUSY:
             return None
         _check(rc)
+        if not copy:
+            self._held[t.value] = (reads, lengths)
         return t.value
 
-    def wait(self, ticket: int, timeout_ms: int = -1, release: bool = True):
+    def wait(self, ticket: int, timeout_ms: int = -1, release: bool = True, copy: bool = True):
         """(seeds, positions, info) of a request, or None if not finished within timeout_ms; info has
-        the timing, the batch and, for a bisulfite server with bs_refine, the refined pieces
-        (PIECE_DTYPE, read_id and seed counted within the request)."""
+        the timing, the batch, the device batches tried and, for a bisulfite server with bs_refine,
+        the refined pieces (PIECE_DTYPE, read_id and seed counted within the request).
+        copy=False returns arrays over the server's pinned result buffer without copying; they stay
+        valid until ``release(ticket)``, which the caller then must call (release is ignored)."""
         r = ServeResult()
         rc = self._lib.mbw_serve_wait(self._h, int(ticket), int(timeout_ms), C.byref(r))
         if rc == MBW_E_BUSY:
             return None
+        self._held.pop(int(ticket), None)
         if rc != MBW_OK:
             err = MbwError(rc, self._lib.mbw_last_error().decode(errors="replace"))
-            if release:   # the request failed (its whole batch did): free it and report
+            err.attempts = r.attempts
+            if release:   # the request failed: free it and report
                 self._lib.mbw_serve_release(self._h, int(ticket))
             raise err
-        seeds = np.zeros(r.n_seeds, dtype=SEED_DTYPE)
-        pos = np.zeros(r.n_pos, dtype=np.uint64)
-        if r.n_seeds:
-            C.memmove(seeds.ctypes.data, r.seeds, r.n_seeds * SEED_DTYPE.itemsize)
-        if r.n_pos:
-            C.memmove(pos.ctypes.data, r.pos, r.n_pos * 8)
-        pieces = np.zeros(r.n_pieces, dtype=PIECE_DTYPE)
-        if r.n_pieces:
-            C.memmove(pieces.ctypes.data, r.pieces, r.n_pieces * PIECE_DTYPE.itemsize)
+        if copy:
+            seeds = np.zeros(r.n_seeds, dtype=SEED_DTYPE)
+            pos = np.zeros(r.n_pos, dtype=np.uint64)
+            if r.n_seeds:
+                C.memmove(seeds.ctypes.data, r.seeds, r.n_seeds * SEED_DTYPE.itemsize)
+            if r.n_pos:
+                C.memmove(pos.ctypes.data, r.pos, r.n_pos * 8)
+            pieces = np.zeros(r.n_pieces, dtype=PIECE_DTYPE)
+            if r.n_pieces:
+                C.memmove(pieces.ctypes.data, r.pieces, r.n_pieces * PIECE_DTYPE.itemsize)
+        else:
+            seeds = _view(r.seeds, r.n_seeds, SEED_DTYPE)
+            pos = _view(r.pos, r.n_pos, np.dtype(np.uint64))
+            pieces = _view(r.pieces, r.n_pieces, PIECE_DTYPE)
         info = dict(t_submit=r.t_submit, t_start=r.t_start, t_done=r.t_done, batch_id=r.batch_id,
-                    batch_reads=r.batch_reads, pieces=pieces)
-        if release:
+                    batch_reads=r.batch_reads, attempts=r.attempts, pieces=pieces)
+        if release and copy:
             _check(self._lib.mbw_serve_release(self._h, int(ticket)))
         return seeds, pos, info
 
+    def release(self, ticket: int):
+        """Free a finished request (after wait(copy=False): its arrays become invalid)."""
+        _check(self._lib.mbw_serve_release(self._h, int(ticket)))
+
     def stats(self):
-        b, r, q = C.c_uint64(), C.c_uint64(), C.c_uint64()
-        _check(self._lib.mbw_serve_stats(self._h, C.byref(b), C.byref(r), C.byref(q)))
-        return dict(batches=b.value, batch_reads=r.value, queued=q.value)
+        st = ServeStats()
+        _check(self._lib.mbw_serve_stats(self._h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServeStats._fields_}
 
     def close(self):
         if self._h:
             self._lib.mbw_serve_close(self._h)
             self._h = None
+            self._held.clear()
 
     def __del__(self):
         try:

@@ -165,3 +165,9 @@ static int cub_call(mbw_ctx *c, F f) {
   MBW_HIP_TRY(f(c->temp.p, have));
   return 0;
 }
+
+// The seeding path's sizing model for a call on n reads of `bases` bases in work space mode: the
+// work space it is expected to need and the seeds, positions and refined pieces of a typical
+// result (a real call may need less, or more for an atypical result).
+struct MbwSizeModel { uint64_t ws, seeds, pos, pieces; };
+MbwSizeModel mbw_size_model(const mbw_ctx *c, uint64_t n, uint64_t bases, bool host_reads, const mbw_seed_opts *o);

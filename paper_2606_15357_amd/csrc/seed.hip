@@ -1417,10 +1417,10 @@ static int segment_queries(mbw_ctx *c, const Query *q, uint64_t n, uint32_t seg,
 }
 
 // A generous estimate of the work space one call takes, from its read count and bases (the seeding
-// result is assumed typical: 8 seeds and 64 positions per read; grids as the automatic sizing picks
-// them).  A work space call that runs short reports the larger of this and the exact need so far,
-// so that a caller who enlarges to the report usually needs one retry.
-static uint64_t ws_estimate(const mbw_ctx *c, uint64_t n, uint64_t bases, bool host_reads, const mbw_seed_opts &o) {
+// result is assumed typical; grids as the automatic sizing picks them).  A work space call that
+// runs short reports the larger of this and the exact need so far, so that a caller who enlarges
+// to the report usually needs one retry.
+static MbwSizeModel size_model(const mbw_ctx *c, uint64_t n, uint64_t bases, bool host_reads, const mbw_seed_opts &o) {
   const uint64_t words = bases / 32 + n + 2;
   uint64_t per_cu = 4;   // round-1 blocks per CU: as persistent_grid sizes them
   if (o.blocks_per_cu > 0) per_cu = std::min<uint64_t>(4, (uint64_t)o.blocks_per_cu);
@@ -1428,15 +1428,32 @@ static uint64_t ws_estimate(const mbw_ctx *c, uint64_t n, uint64_t bases, bool h
     per_cu = std::min<uint64_t>(4, std::max<uint64_t>(1, (n + AUTO_QUERIES_R1 * (uint64_t)c->n_cu - 1) /
                                                              (AUTO_QUERIES_R1 * (uint64_t)c->n_cu)));
   const uint64_t slack = 2 * per_cu * (uint64_t)c->n_cu * SMEM_WAVES * OUT_CHUNK;
-  const uint64_t seeds = std::max<uint64_t>(1 << 16, 8 * n) + slack;
+  // typical result: 8 seeds and 64 positions per read, or one seed per 16 bases and one position
+  // per 2 bases for long reads
+  const uint64_t recs = std::max<uint64_t>(8 * n, bases / 16);
+  const uint64_t rows = std::max<uint64_t>(64 * n, bases / 2);
+  const uint64_t seeds = std::max<uint64_t>(1 << 16, recs) + slack;
   uint64_t b = 0;
   b += n * (4 + 8 + 8 + 8 + 8 + 48 + 6 * 4 + 8 + 96);   // lengths, offsets, word counts, queries, bins, segments
   b += host_reads ? bases + 16 : 0;
   b += words * (8 + 4 + 4);                              // packed words, N masks, word owners
   b += seeds * (sizeof(SeedRec) + sizeof(Query) + 16 + 8 + 8 + 24);   // seeds, sub-queries, sort, per-seed counts
-  b += 64 * n * (8 + 8 + 4 + 8 + 8 + 4 + 4 + 8);         // rows, positions, filter and refinement arrays
+  b += rows * (8 + 8 + 4 + 8 + 8 + 4 + 4 + 8);           // rows, positions, filter and refinement arrays
   b += 16ull << 20;                                      // temporary storage of sorts and scans
-  return b;
+  MbwSizeModel m;
+  m.ws = b;
+  m.seeds = recs;
+  m.pos = rows;
+  m.pieces = o.bs_refine ? rows : 0;
+  return m;
+}
+
+static uint64_t ws_estimate(const mbw_ctx *c, uint64_t n, uint64_t bases, bool host_reads, const mbw_seed_opts &o) {
+  return size_model(c, n, bases, host_reads, o).ws;
+}
+
+MbwSizeModel mbw_size_model(const mbw_ctx *c, uint64_t n, uint64_t bases, bool host_reads, const mbw_seed_opts *o) {
+  return size_model(c, n, bases, host_reads, *o);
 }
 
 // The whole path of one call.  ob == nullptr: buffers are the context's own (grown as needed);

@@ -1,13 +1,26 @@
-// Serving runtime: a request loop around mbw_seed with the index resident in HBM.
+// Serving runtime: a request loop around the seeding path with the index resident in HBM.
 //
-// Requests (a few to tens of thousands of reads) are queued on submission; admission is bounded by
-// the bases waiting in the queue.  Each worker thread owns a seeding context and its own HIP stream.
-// A free worker forms a batch from the head of the queue (up to a read / base budget), so requests
-// that arrive while other batches are on the device join the next batch at once (continuous
-// batching), and batches of different workers run on the device at the same time.  A batch's
-// seeds come back sorted by read, so each request's seeds and positions are a contiguous slice;
-// read ids and position offsets are made relative to each request on the device, and the batch is
-// downloaded once into a pinned buffer its requests share.
+// Device memory is fixed when the server opens.  Every worker thread owns a seeding context, a HIP
+// stream and one device arena: the work space of its calls plus result buffers for seeds,
+// positions and refined pieces, sized from the batch budget (or from the device bytes the caller
+// grants) with the seeding path's own sizing model.  Batches run through mbw_seed_into on that
+// arena, so a running server allocates no device memory.
+//
+// Admission is by device memory.  A request whose estimated work space alone exceeds a worker's
+// arena is refused at submission (MBW_E_CAPACITY).  A free worker takes queued requests in arrival
+// order into one device batch while the batch's estimated work space fits its arena and the read /
+// base budget holds, so requests that arrive while other batches run join the next batch at once
+// (continuous batching), and the batches of different workers run on the device at the same time.
+// A batch that still runs short (a result larger than the model assumes, or an allocation failure)
+// is split in two and each half run again, down to single requests: a request never fails because
+// of the requests it was batched with.
+//
+// Requests are queued with host copies of their reads, or by reference when the caller keeps the
+// buffers until the request is finished.  A worker copies the next batch into pinned staging while
+// the previous batch's results are still coming back over PCIe.  A batch's seeds come back sorted by
+// read, so each request's seeds and positions are a contiguous slice; read ids and position offsets
+// are made relative to each request on the device, and the batch is downloaded once into a pinned
+// buffer its requests share.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,6 +36,7 @@
 #include <thread>
 #include <vector>
 
+#include "ctx.h"
 #include "mbw_internal.h"
 #include "../../include/mbw.h"
 
@@ -41,21 +55,6 @@ struct Pinned {
     return 0;
   }
   ~Pinned() { if (p) (void)hipHostFree(p); }
-};
-
-// grow-only device buffer (per worker)
-struct DevScratch {
-  void *p = nullptr;
-  size_t bytes = 0;
-  int ensure(size_t want) {
-    if (want <= bytes) return 0;
-    if (p) { (void)hipFree(p); p = nullptr; bytes = 0; }
-    const size_t b = 2 * want + 256;
-    if (hipMalloc(&p, b) != hipSuccess) { p = nullptr; return MBW_E_NOMEM; }
-    bytes = b;
-    return 0;
-  }
-  ~DevScratch() { if (p) (void)hipFree(p); }
 };
 
 // Per-request split of a batch's result, on the device.  Seeds come back sorted by read and
@@ -122,17 +121,104 @@ struct BatchBuf {
 
 struct Request {
   uint64_t ticket = 0;
-  std::vector<uint8_t> reads;
-  std::vector<uint32_t> lengths;
-  uint64_t bases = 0;
+  std::vector<uint8_t> reads_copy;      // empty when submitted by reference
+  std::vector<uint32_t> lengths_copy;
+  const uint8_t *reads = nullptr;       // the copies or the caller's buffers
+  const uint32_t *lengths = nullptr;
+  uint64_t n_reads = 0, bases = 0;
   double t_submit = 0, t_start = 0, t_done = 0;
   uint64_t batch_id = 0, batch_reads = 0;
+  uint32_t attempts = 0;                // device batches this request was part of
   int state = 0;   // 0 queued, 1 running, 2 done
   int rc = MBW_OK;
+  std::string err;                      // the failure's message (errors are per thread)
   BatchBuf *buf = nullptr;          // the shared batch result
   uint64_t s0 = 0, ns = 0, p0 = 0, np = 0;   // this request's slice of it (seeds, positions,
   uint64_t c0 = 0, nc = 0;                    // refined pieces)
 };
+
+// requests in one device batch at most (sizes the per-batch split arrays)
+constexpr uint32_t kMaxBatchRequests = 1u << 16;
+
+// a worker's fixed device memory
+struct Arena {
+  void *base = nullptr;
+  uint64_t bytes = 0;
+  void *ws = nullptr;
+  uint64_t ws_bytes = 0;
+  mbw_seed_t *seeds = nullptr;
+  uint64_t seeds_cap = 0;
+  uint64_t *pos = nullptr;
+  uint64_t pos_cap = 0;
+  mbw_piece_t *pieces = nullptr;
+  uint64_t pieces_cap = 0;
+  uint32_t *rstart = nullptr;     // per-batch split arrays (kMaxBatchRequests + 1 each)
+  SplitBound *bounds = nullptr;
+};
+
+static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+// Carve an arena of `bytes` (0 = the size the model gives for a full batch of max_reads reads and
+// max_bases bases) into work space and result buffers, in the proportions of that model.
+static int plan_arena(const mbw_ctx *c, const mbw_serve_cfg &cfg, uint64_t bytes, Arena &a) {
+  const uint64_t R = cfg.max_batch_reads, B = cfg.max_batch_bases;
+  const uint64_t fixed = align256((kMaxBatchRequests + 1) * sizeof(uint32_t)) +
+                         align256((kMaxBatchRequests + 1) * sizeof(SplitBound));
+  const MbwSizeModel sm = mbw_size_model(c, R, B, true, &cfg.opts);
+  const double m_ws = (double)sm.ws;
+  const double m_seeds = (double)(sm.seeds + 4096) * sizeof(mbw_seed_t);
+  const double m_pos = (double)(sm.pos + 4096) * sizeof(uint64_t);
+  const double m_pieces = cfg.opts.bs_refine ? (double)(sm.pieces + 4096) * sizeof(mbw_piece_t) : 0.0;
+  const double model = m_ws + m_seeds + m_pos + m_pieces;
+  if (bytes == 0) bytes = align256((uint64_t)model) + 4 * 256 + fixed;
+  // the smallest arena admits one read of the longest length
+  const MbwSizeModel one = mbw_size_model(c, 1, MBW_MAX_READ, true, &cfg.opts);
+  double lf = ((double)one.ws + 256) / m_ws;
+  lf = std::max(lf, (double)(one.seeds + 1) * sizeof(mbw_seed_t) / m_seeds);
+  lf = std::max(lf, (double)(one.pos + 1) * sizeof(uint64_t) / m_pos);
+  if (m_pieces > 0) lf = std::max(lf, (double)(one.pieces + 1) * sizeof(mbw_piece_t) / m_pieces);
+  const uint64_t least = (uint64_t)(lf * model) + 4 * 256 + fixed + 4096;
+  if (bytes < least) {
+    mbw_set_error("serve device_bytes too small: each worker needs at least " + std::to_string(least) + " bytes");
+    return MBW_E_INVAL;
+  }
+  const double f = (double)(bytes - fixed - 4 * 256) / model;
+  a.bytes = bytes;
+  a.ws_bytes = align256((uint64_t)(m_ws * f)) - 256;
+  a.seeds_cap = (uint64_t)(m_seeds * f) / sizeof(mbw_seed_t);
+  a.pos_cap = (uint64_t)(m_pos * f) / sizeof(uint64_t);
+  a.pieces_cap = (uint64_t)(m_pieces * f) / sizeof(mbw_piece_t);
+  return MBW_OK;
+}
+
+static int alloc_arena(Arena &a) {
+  const uint64_t extra = align256((kMaxBatchRequests + 1) * sizeof(uint32_t)) +
+                         align256((kMaxBatchRequests + 1) * sizeof(SplitBound));
+  const uint64_t want = align256(a.ws_bytes) + align256(a.seeds_cap * sizeof(mbw_seed_t)) +
+                        align256(a.pos_cap * sizeof(uint64_t)) + align256(a.pieces_cap * sizeof(mbw_piece_t)) + extra;
+  if (const unsigned long long lim = g_mbw_mem_limit.load(std::memory_order_relaxed)) {
+    if (want > lim) {
+      mbw_set_error("serve arena of " + std::to_string(want) + " bytes over the debug cap (" + std::to_string(lim) +
+                    " bytes)");
+      return MBW_E_NOMEM;
+    }
+  }
+  if (hipMalloc(&a.base, want) != hipSuccess) {
+    (void)hipGetLastError();
+    a.base = nullptr;
+    mbw_set_error("hipMalloc of a serve arena (" + std::to_string(want) + " bytes) failed");
+    return MBW_E_NOMEM;
+  }
+  uint8_t *p = (uint8_t *)a.base;
+  a.ws = p; p += align256(a.ws_bytes);
+  a.seeds = (mbw_seed_t *)p; p += align256(a.seeds_cap * sizeof(mbw_seed_t));
+  a.pos = (uint64_t *)p; p += align256(a.pos_cap * sizeof(uint64_t));
+  a.pieces = a.pieces_cap ? (mbw_piece_t *)p : nullptr; p += align256(a.pieces_cap * sizeof(mbw_piece_t));
+  a.rstart = (uint32_t *)p; p += align256((kMaxBatchRequests + 1) * sizeof(uint32_t));
+  a.bounds = (SplitBound *)p;
+  a.bytes = want;
+  return MBW_OK;
+}
 
 }  // namespace
 
@@ -147,197 +233,398 @@ struct mbw_server {
   bool stop = false;
   std::vector<std::thread> workers;
   std::chrono::steady_clock::time_point t0;
-  uint64_t batches = 0, batch_reads_sum = 0;
+  mbw_serve_stats_t st{};
   bool trace = false;   // MBW_SERVE_TRACE=1: one line per batch on stderr
   std::vector<BatchBuf *> free_bufs;
+  mbw_ctx *model_ctx = nullptr;   // worker 0's context, for the sizing model
+  uint64_t ws_bytes = 0;          // every worker's work space and result buffers (records)
+  uint64_t seeds_cap = 0, pos_cap = 0, pieces_cap = 0;
 
   void unref(BatchBuf *b) {   // with mu held
     if (b && --b->refs == 0) free_bufs.push_back(b);
   }
 
   double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+
+  // whether a batch of n reads and `bases` bases fits a worker's arena by the sizing model (its
+  // estimated work space in *need)
+  bool fits(uint64_t n, uint64_t bases, uint64_t *need = nullptr) const {
+    const MbwSizeModel m = mbw_size_model(model_ctx, n, bases, true, &cfg.opts);
+    if (need) *need = m.ws;
+    return m.ws <= ws_bytes && m.seeds <= seeds_cap && m.pos <= pos_cap && m.pieces <= pieces_cap;
+  }
 };
 
-static void worker_main(mbw_server *s, mbw_ctx *ctx, hipStream_t st) {
-  Pinned hreads, hlens, hreq, hbnd;
-  DevScratch dreq, dbnd;
+namespace {
+
+// A worker: its context, stream, arena and pinned staging.
+struct Worker {
+  mbw_server *s = nullptr;
+  mbw_ctx *ctx = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t ev = nullptr;
+  Arena a;
+  Pinned stage[2], lens[2], hreq, hbnd;
+};
+
+// a batch whose results are on their way to the host
+struct InFlight {
+  std::vector<Request *> reqs;
+  BatchBuf *bb = nullptr;
+  uint64_t bid = 0, nreads = 0;
+  double tb0 = 0, tb1 = 0, tb2 = 0;
+  float ms_device = 0;
+};
+
+// Take queued requests for one batch (mu held): in arrival order while the batch's estimated work
+// space fits the arena, within the read, base and request budgets.  The head request always fits
+// (submission refused those that do not).
+static std::vector<Request *> take_batch(mbw_server *s) {
+  std::vector<Request *> batch;
+  uint64_t nreads = 0, nbases = 0;
+  while (!s->queue.empty() && batch.size() < kMaxBatchRequests) {
+    Request *r = s->queue.front();
+    if (!batch.empty() &&
+        (nreads + r->n_reads > s->cfg.max_batch_reads || nbases + r->bases > s->cfg.max_batch_bases ||
+         !s->fits(nreads + r->n_reads, nbases + r->bases)))
+      break;
+    s->queue.pop_front();
+    s->queued_bases -= r->bases;
+    batch.push_back(r);
+    nreads += r->n_reads;
+    nbases += r->bases;
+  }
+  if (!batch.empty()) {
+    const double t = s->now();
+    for (Request *r : batch) { r->state = 1; r->t_start = t; }
+  }
+  return batch;
+}
+
+// Concatenate a batch's reads and lengths into pinned staging slot k.
+static int stage_batch(Worker &w, int k, const std::vector<Request *> &batch) {
+  uint64_t nreads = 0, nbases = 0;
+  for (Request *r : batch) { nreads += r->n_reads; nbases += r->bases; }
+  int rc = w.stage[k].ensure(nbases + 16);
+  if (!rc) rc = w.lens[k].ensure((nreads + 1) * sizeof(uint32_t));
+  if (rc) { mbw_set_error("pinned staging allocation failed"); return rc; }
+  uint8_t *rb = (uint8_t *)w.stage[k].p;
+  uint32_t *lb = (uint32_t *)w.lens[k].p;
+  uint64_t ob = 0, orr = 0;
+  for (Request *r : batch) {
+    if (r->bases) memcpy(rb + ob, r->reads, r->bases);
+    if (r->n_reads) memcpy(lb + orr, r->lengths, r->n_reads * sizeof(uint32_t));
+    ob += r->bases;
+    orr += r->n_reads;
+  }
+  return MBW_OK;
+}
+
+static BatchBuf *get_buf(mbw_server *s) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->free_bufs.empty()) return new BatchBuf();
+  BatchBuf *b = s->free_bufs.back();
+  s->free_bufs.pop_back();
+  return b;
+}
+
+// Seed requests [i0, i1) of a staged batch (their reads start at staged byte rb0 and staged read
+// rr0), split the result per request on the device and start its download; on success `out`
+// describes the batch in flight (complete it with finish()).
+static int run_batch(Worker &w, int k, const std::vector<Request *> &batch, size_t i0, size_t i1, uint64_t rb0,
+                     uint64_t rr0, InFlight &out) {
+  mbw_server *s = w.s;
+  out.reqs.assign(batch.begin() + i0, batch.begin() + i1);
+  const uint32_t nreq = (uint32_t)out.reqs.size();
+  uint64_t nreads = 0;
+  for (Request *r : out.reqs) nreads += r->n_reads;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    out.bid = s->next_batch++;
+    s->st.batches++;
+    s->st.batch_reads += nreads;
+    for (Request *r : out.reqs) { r->batch_id = out.bid; r->batch_reads = nreads; r->attempts++; }
+  }
+  out.nreads = nreads;
+  out.tb0 = s->now();
+  mbw_seed_buffers ob;
+  memset(&ob, 0, sizeof(ob));
+  ob.workspace = w.a.ws; ob.workspace_bytes = w.a.ws_bytes;
+  ob.seeds = w.a.seeds; ob.seeds_cap = w.a.seeds_cap;
+  ob.pos = w.a.pos; ob.pos_cap = w.a.pos_cap;
+  ob.pieces = w.a.pieces; ob.pieces_cap = w.a.pieces_cap;
+  mbw_result res;
+  memset(&res, 0, sizeof(res));
+  int rc = mbw_seed_into(w.ctx, (const uint8_t *)w.stage[k].p + rb0, (const uint32_t *)w.lens[k].p + rr0, nreads,
+                         s->cfg.min_seed_len, s->cfg.max_occ, &s->cfg.opts, (void *)w.st, &ob, &res);
+  out.tb1 = s->now();
+  out.ms_device = res.ms_total;
+  if (rc) return rc;
+  // per-request split on the device, then one download of the batch and of the request bounds
+  uint32_t *rs = (uint32_t *)w.hreq.p;
+  uint64_t r0 = 0;
+  for (uint32_t i = 0; i < nreq; ++i) { rs[i] = (uint32_t)r0; r0 += out.reqs[i]->n_reads; }
+  rs[nreq] = (uint32_t)r0;
+  BatchBuf *bb = get_buf(s);
+  out.bb = bb;
+  rc = bb->seeds.ensure((res.n_seeds + 1) * sizeof(mbw_seed_t));
+  if (!rc) rc = bb->pos.ensure((res.n_pos + 1) * sizeof(uint64_t));
+  if (!rc && res.n_pieces) rc = bb->pieces.ensure((res.n_pieces + 1) * sizeof(mbw_piece_t));
+  if (rc) { mbw_set_error("pinned result allocation failed"); return rc; }
+  const unsigned gb = (unsigned)std::min<uint64_t>((nreq + 256) / 256, 1024);
+  const unsigned gr = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((res.n_seeds + res.n_pieces + 255) / 256, 4096));
+#define SRV_TRY(x) do { if ((x) != hipSuccess) { mbw_set_error(std::string(#x) + ": " + hipGetErrorString(hipGetLastError())); return MBW_E_HIP; } } while (0)
+  SRV_TRY(hipMemcpyAsync(w.a.rstart, rs, (nreq + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, w.st));
+  k_split_bounds<<<gb, 256, 0, w.st>>>(res.seeds, res.n_seeds, res.n_pos, res.pieces, res.n_pieces, w.a.rstart, nreq,
+                                       w.a.bounds);
+  if (res.n_seeds + res.n_pieces)
+    k_split_rebase<<<gr, 256, 0, w.st>>>((mbw_seed_t *)res.seeds, res.n_seeds, (mbw_piece_t *)res.pieces, res.n_pieces,
+                                         w.a.rstart, nreq, w.a.bounds);
+  SRV_TRY(hipGetLastError());
+  SRV_TRY(hipMemcpyAsync(w.hbnd.p, w.a.bounds, (nreq + 1) * sizeof(SplitBound), hipMemcpyDeviceToHost, w.st));
+  if (res.n_seeds)
+    SRV_TRY(hipMemcpyAsync(bb->seeds.p, res.seeds, res.n_seeds * sizeof(mbw_seed_t), hipMemcpyDeviceToHost, w.st));
+  if (res.n_pos)
+    SRV_TRY(hipMemcpyAsync(bb->pos.p, res.pos, res.n_pos * sizeof(uint64_t), hipMemcpyDeviceToHost, w.st));
+  if (res.n_pieces)
+    SRV_TRY(hipMemcpyAsync(bb->pieces.p, res.pieces, res.n_pieces * sizeof(mbw_piece_t), hipMemcpyDeviceToHost, w.st));
+  SRV_TRY(hipEventRecord(w.ev, w.st));
+#undef SRV_TRY
+  return MBW_OK;
+}
+
+// Complete requests with an error (rc != 0) or with their slices of a downloaded batch.
+static void complete(Worker &w, InFlight &f, int rc) {
+  mbw_server *s = w.s;
+  if (!rc && hipEventSynchronize(w.ev) != hipSuccess) {
+    mbw_set_error(std::string("hipEventSynchronize: ") + hipGetErrorString(hipGetLastError()));
+    rc = MBW_E_HIP;
+  }
+  const double tb2 = s->now();
+  if (!rc) {
+    const SplitBound *b = (const SplitBound *)w.hbnd.p;
+    for (size_t i = 0; i < f.reqs.size(); ++i) {
+      Request *r = f.reqs[i];
+      r->buf = f.bb; r->s0 = b[i].t0; r->ns = b[i + 1].t0 - b[i].t0; r->p0 = b[i].p0; r->np = b[i + 1].p0 - b[i].p0;
+      r->c0 = b[i].c0; r->nc = b[i + 1].c0 - b[i].c0;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    const double t = s->now();
+    if (f.bb) {
+      f.bb->refs = rc ? 0 : (int)f.reqs.size();
+      if (rc || f.reqs.empty()) s->free_bufs.push_back(f.bb);
+    }
+    const std::string msg = rc ? std::string(mbw_last_error()) : std::string();
+    for (Request *r : f.reqs) {
+      r->rc = rc; r->state = 2; r->t_done = t;
+      if (rc) { r->buf = nullptr; r->err = msg; s->st.failed_requests++; }
+    }
+    if (s->trace)
+      fprintf(stderr, "[serve] batch %llu reads %llu requests %zu: seed %.2f ms (device %.2f), download %.2f ms%s\n",
+              (unsigned long long)f.bid, (unsigned long long)f.nreads, f.reqs.size(), (f.tb1 - f.tb0) * 1e3,
+              f.ms_device, (tb2 - f.tb1) * 1e3, rc ? " FAILED" : "");
+  }
+  s->done_cv.notify_all();
+}
+
+// Run requests [i0, i1) of a staged batch to completion; a shortfall of the arena (MBW_E_CAPACITY)
+// or an allocation failure splits them in two halves, each run again.
+static void run_split(Worker &w, int k, const std::vector<Request *> &batch, size_t i0, size_t i1, uint64_t rb0,
+                      uint64_t rr0) {
+  InFlight f;
+  int rc = run_batch(w, k, batch, i0, i1, rb0, rr0, f);
+  if ((rc == MBW_E_CAPACITY || rc == MBW_E_NOMEM) && i1 - i0 > 1) {
+    if (f.bb) { std::lock_guard<std::mutex> lk(w.s->mu); w.s->free_bufs.push_back(f.bb); }
+    {
+      std::lock_guard<std::mutex> lk(w.s->mu);
+      w.s->st.split_retries++;
+    }
+    const size_t mid = i0 + (i1 - i0) / 2;
+    uint64_t rb = rb0, rr = rr0;
+    for (size_t i = i0; i < mid; ++i) { rb += batch[i]->bases; rr += batch[i]->n_reads; }
+    run_split(w, k, batch, i0, mid, rb0, rr0);
+    run_split(w, k, batch, mid, i1, rb, rr);
+    return;
+  }
+  complete(w, f, rc);
+}
+
+static void worker_main(Worker *wp) {
+  Worker &w = *wp;
+  mbw_server *s = w.s;
   (void)hipSetDevice(s->cfg.device);
-  // pinned staging sized for a full batch up front (pinning memory while serving would stall)
-  const uint64_t br = std::min<uint64_t>(s->cfg.max_batch_reads, 1ull << 22);
-  (void)hreads.ensure(std::min<uint64_t>(s->cfg.max_batch_bases, br * 160) / 2 + 16);
-  (void)hlens.ensure(br * sizeof(uint32_t) / 2 + 16);
+  InFlight prev;
+  bool have_prev = false;
+  int k = 0;
   for (;;) {
     std::vector<Request *> batch;
-    uint64_t nreads = 0, nbases = 0, bid = 0;
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      s->work_cv.wait(lk, [&] { return s->stop || !s->queue.empty(); });
-      if (s->queue.empty()) return;   // stopping
-      while (!s->queue.empty()) {
-        Request *r = s->queue.front();
-        const uint64_t nr = r->lengths.size();
-        if (!batch.empty() && (nreads + nr > s->cfg.max_batch_reads || nbases + r->bases > s->cfg.max_batch_bases)) break;
-        s->queue.pop_front();
-        s->queued_bases -= r->bases;
-        batch.push_back(r);
-        nreads += nr;
-        nbases += r->bases;
-      }
-      bid = s->next_batch++;
-      const double t = s->now();
-      for (Request *r : batch) { r->state = 1; r->t_start = t; r->batch_id = bid; r->batch_reads = nreads; }
-      s->batches++;
-      s->batch_reads_sum += nreads;
+      if (!have_prev) s->work_cv.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+      batch = take_batch(s);
     }
-    // concatenate the batch in pinned memory and seed it
-    const double tb0 = s->now();
-    double tb1 = tb0, tb2 = tb0, tb3 = tb0;
-    int rc = hreads.ensure(nbases + 16);
-    if (!rc) rc = hlens.ensure((nreads + 1) * sizeof(uint32_t));
-    mbw_result res;
-    memset(&res, 0, sizeof(res));
+    if (batch.empty() && !have_prev) return;   // stopping with an empty queue
+    // stage the next batch while the previous one downloads, then finish the previous one
+    int rc = batch.empty() ? MBW_OK : stage_batch(w, k, batch);
+    if (have_prev) { complete(w, prev, MBW_OK); have_prev = false; }
+    if (batch.empty()) continue;
+    if (rc) {
+      InFlight f;
+      f.reqs = batch;
+      complete(w, f, rc);
+      continue;
+    }
+    InFlight f;
+    rc = run_batch(w, k, batch, 0, batch.size(), 0, 0, f);
     if (!rc) {
-      uint8_t *rb = (uint8_t *)hreads.p;
-      uint32_t *lb = (uint32_t *)hlens.p;
-      uint64_t ob = 0, orr = 0;
-      for (Request *r : batch) {
-        if (!r->reads.empty()) memcpy(rb + ob, r->reads.data(), r->reads.size());
-        if (!r->lengths.empty()) memcpy(lb + orr, r->lengths.data(), r->lengths.size() * sizeof(uint32_t));
-        ob += r->reads.size();
-        orr += r->lengths.size();
+      prev = std::move(f);
+      have_prev = true;
+      k ^= 1;
+      continue;
+    }
+    if ((rc == MBW_E_CAPACITY || rc == MBW_E_NOMEM) && batch.size() > 1) {
+      if (f.bb) { std::lock_guard<std::mutex> lk(s->mu); s->free_bufs.push_back(f.bb); }
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->st.split_retries++;
       }
-      tb1 = s->now();
-      rc = mbw_seed(ctx, rb, lb, nreads, s->cfg.min_seed_len, s->cfg.max_occ, &s->cfg.opts, (void *)st, &res);
-      tb2 = s->now();
+      const size_t mid = batch.size() / 2;
+      uint64_t rb = 0, rr = 0;
+      for (size_t i = 0; i < mid; ++i) { rb += batch[i]->bases; rr += batch[i]->n_reads; }
+      run_split(w, k, batch, 0, mid, 0, 0);
+      run_split(w, k, batch, mid, batch.size(), rb, rr);
+      continue;
     }
-    BatchBuf *bb = nullptr;
-    if (!rc) {
-      std::lock_guard<std::mutex> lk(s->mu);
-      if (!s->free_bufs.empty()) { bb = s->free_bufs.back(); s->free_bufs.pop_back(); }
-    }
-    if (!rc && !bb) {
-      bb = new BatchBuf();
-      rc = bb->seeds.ensure(br * 4 * sizeof(mbw_seed_t));
-      if (!rc) rc = bb->pos.ensure(br * 24 * sizeof(uint64_t));
-    }
-    // split into requests on the device (read ids, position offsets and piece seed indexes made
-    // relative to each request), then one download of the batch and of the request bounds
-    const uint32_t nreq = (uint32_t)batch.size();
-    if (!rc) rc = hreq.ensure((nreq + 1) * sizeof(uint32_t));
-    if (!rc) rc = hbnd.ensure((nreq + 1) * sizeof(SplitBound));
-    if (!rc) rc = dreq.ensure((nreq + 1) * sizeof(uint32_t));
-    if (!rc) rc = dbnd.ensure((nreq + 1) * sizeof(SplitBound));
-    if (!rc) {
-      uint32_t *rs = (uint32_t *)hreq.p;
-      uint64_t r0 = 0;
-      for (uint32_t i = 0; i < nreq; ++i) { rs[i] = (uint32_t)r0; r0 += batch[i]->lengths.size(); }
-      rs[nreq] = (uint32_t)r0;
-      const unsigned gb = (unsigned)std::min<uint64_t>((nreq + 256) / 256, 1024);
-      const unsigned gr = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((res.n_seeds + res.n_pieces + 255) / 256, 4096));
-      if (hipMemcpyAsync(dreq.p, rs, (nreq + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, st) != hipSuccess) rc = MBW_E_HIP;
-      if (!rc) {
-        k_split_bounds<<<gb, 256, 0, st>>>(res.seeds, res.n_seeds, res.n_pos, res.pieces, res.n_pieces,
-                                           (const uint32_t *)dreq.p, nreq, (SplitBound *)dbnd.p);
-        if (res.n_seeds + res.n_pieces)
-          k_split_rebase<<<gr, 256, 0, st>>>((mbw_seed_t *)res.seeds, res.n_seeds, (mbw_piece_t *)res.pieces, res.n_pieces,
-                                             (const uint32_t *)dreq.p, nreq, (const SplitBound *)dbnd.p);
-        if (hipGetLastError() != hipSuccess) rc = MBW_E_HIP;
-      }
-      if (!rc && hipMemcpyAsync(hbnd.p, dbnd.p, (nreq + 1) * sizeof(SplitBound), hipMemcpyDeviceToHost, st) != hipSuccess)
-        rc = MBW_E_HIP;
-    }
-    if (!rc) rc = bb->seeds.ensure((res.n_seeds + 1) * sizeof(mbw_seed_t));
-    if (!rc) rc = bb->pos.ensure((res.n_pos + 1) * sizeof(uint64_t));
-    if (!rc) rc = mbw_result_download(ctx, &res, (mbw_seed_t *)bb->seeds.p, (uint64_t *)bb->pos.p);
-    if (!rc && res.n_pieces) {
-      rc = bb->pieces.ensure((res.n_pieces + 1) * sizeof(mbw_piece_t));
-      if (!rc) rc = mbw_result_download_pieces(ctx, &res, (mbw_piece_t *)bb->pieces.p);
-    }
-    tb3 = s->now();
-    if (!rc) {
-      const SplitBound *b = (const SplitBound *)hbnd.p;
-      for (uint32_t i = 0; i < nreq; ++i) {
-        Request *r = batch[i];
-        r->buf = bb; r->s0 = b[i].t0; r->ns = b[i + 1].t0 - b[i].t0; r->p0 = b[i].p0; r->np = b[i + 1].p0 - b[i].p0;
-        r->c0 = b[i].c0; r->nc = b[i + 1].c0 - b[i].c0;
-      }
-    }
-    {
-      std::lock_guard<std::mutex> lk(s->mu);
-      const double t = s->now();
-      if (bb) {
-        bb->refs = rc ? 0 : (int)batch.size();
-        if (rc) s->free_bufs.push_back(bb);
-      }
-      for (Request *r : batch) { r->rc = rc; r->state = 2; r->t_done = t; if (rc) r->buf = nullptr; }
-      if (s->trace)
-        fprintf(stderr, "[serve] batch %llu reads %llu: copy %.2f ms, seed %.2f ms (device %.2f), download %.2f ms, split %.2f ms\n",
-                (unsigned long long)bid, (unsigned long long)nreads, (tb1 - tb0) * 1e3, (tb2 - tb1) * 1e3, res.ms_total,
-                (tb3 - tb2) * 1e3, (t - tb3) * 1e3);
-    }
-    s->done_cv.notify_all();
+    complete(w, f, rc);
   }
 }
+
+}  // namespace
 
 extern "C" int mbw_serve_open(const mbw_index *ix, const mbw_serve_cfg *cfg, mbw_server **out) {
   if (!ix || !cfg || !out) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
   *out = nullptr;
   if (cfg->n_workers < 1 || cfg->n_workers > 8 || cfg->max_batch_reads < 1 || cfg->max_batch_bases < 1 ||
-      cfg->min_seed_len < 1 || cfg->max_occ < 1) {
+      cfg->min_seed_len < 1 || cfg->max_occ < 1 || cfg->max_batch_reads >= (1ull << 31)) {
     mbw_set_error("bad serve configuration"); return MBW_E_INVAL;
   }
   if (cfg->device != ix->device) { mbw_set_error("serve device differs from the index device"); return MBW_E_INVAL; }
+  if (cfg->opts.bs_role && !ix->bisulfite) { mbw_set_error("bs_role needs a bisulfite index"); return MBW_E_INVAL; }
+  if (hipSetDevice(cfg->device) != hipSuccess) { mbw_set_error("hipSetDevice failed"); return MBW_E_HIP; }
   mbw_server *s = new mbw_server();
   s->ix = ix;
   s->cfg = *cfg;
   s->t0 = std::chrono::steady_clock::now();
   s->trace = getenv("MBW_SERVE_TRACE") && getenv("MBW_SERVE_TRACE")[0] == '1';
-  std::vector<std::pair<mbw_ctx *, hipStream_t>> res;
-  for (int w = 0; w < cfg->n_workers; ++w) {
-    mbw_ctx *c = nullptr;
-    int r = mbw_ctx_create(ix, &c);
-    hipStream_t st = nullptr;
+  std::vector<Worker *> ws;
+  auto fail = [&](int r) {
+    for (Worker *w : ws) {
+      if (w->a.base) (void)hipFree(w->a.base);
+      if (w->ev) (void)hipEventDestroy(w->ev);
+      if (w->st) (void)hipStreamDestroy(w->st);
+      if (w->ctx) mbw_ctx_free(w->ctx);
+      delete w;
+    }
+    delete s;
+    return r;
+  };
+  const uint64_t per_worker = cfg->device_bytes / (uint64_t)cfg->n_workers;
+  if (cfg->device_bytes && per_worker == 0) { mbw_set_error("serve device_bytes too small"); return fail(MBW_E_INVAL); }
+  for (int i = 0; i < cfg->n_workers; ++i) {
+    Worker *w = new Worker();
+    ws.push_back(w);
+    w->s = s;
+    int r = mbw_ctx_create(ix, &w->ctx);
+    if (r) return fail(r);
     // non-blocking: the workers' streams never wait for work on the null stream
-    if (!r && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-      mbw_ctx_free(c); mbw_set_error("hipStreamCreate failed"); r = MBW_E_HIP;
+    if (hipStreamCreateWithFlags(&w->st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&w->ev, hipEventDisableTiming) != hipSuccess) {
+      mbw_set_error("hipStreamCreate / hipEventCreate failed"); return fail(MBW_E_HIP);
     }
-    if (r) {
-      for (auto &x : res) { mbw_ctx_free(x.first); (void)hipStreamDestroy(x.second); }
-      delete s;
-      return r;
+    if (i == 0) s->model_ctx = w->ctx;
+    r = plan_arena(w->ctx, *cfg, per_worker, w->a);
+    if (!r) r = alloc_arena(w->a);
+    if (r) return fail(r);
+    s->ws_bytes = w->a.ws_bytes;
+    s->seeds_cap = w->a.seeds_cap;
+    s->pos_cap = w->a.pos_cap;
+    s->pieces_cap = w->a.pieces_cap;
+    // pinned staging and split arrays sized for a full batch up front (pinning while serving stalls)
+    const uint64_t br = std::min<uint64_t>(cfg->max_batch_reads, 1ull << 22);
+    const uint64_t bb = std::min<uint64_t>(cfg->max_batch_bases, br * 160);
+    for (int k = 0; k < 2; ++k)
+      if (w->stage[k].ensure(bb / 2 + 16) || w->lens[k].ensure(br * sizeof(uint32_t) / 2 + 16)) {
+        mbw_set_error("pinned staging allocation failed"); return fail(MBW_E_NOMEM);
+      }
+    if (w->hreq.ensure((kMaxBatchRequests + 1) * sizeof(uint32_t) / 2 + 16) ||
+        w->hbnd.ensure((kMaxBatchRequests + 1) * sizeof(SplitBound) / 2 + 16)) {
+      mbw_set_error("pinned staging allocation failed"); return fail(MBW_E_NOMEM);
     }
-    res.emplace_back(c, st);
   }
-  for (auto &x : res)
-    s->workers.emplace_back([s, x] {
-      worker_main(s, x.first, x.second);
-      mbw_ctx_free(x.first);
-      (void)hipStreamDestroy(x.second);
+  s->st.device_bytes = 0;
+  for (Worker *w : ws) s->st.device_bytes += w->a.bytes;
+  s->st.workspace_bytes = s->ws_bytes;
+  s->st.seeds_cap = ws[0]->a.seeds_cap;
+  s->st.pos_cap = ws[0]->a.pos_cap;
+  s->st.pieces_cap = ws[0]->a.pieces_cap;
+  for (Worker *w : ws)
+    s->workers.emplace_back([w] {
+      worker_main(w);
+      (void)hipSetDevice(w->s->cfg.device);
+      (void)hipStreamSynchronize(w->st);
+      if (w->a.base) (void)hipFree(w->a.base);
+      (void)hipEventDestroy(w->ev);
+      (void)hipStreamDestroy(w->st);
+      if (w->ctx != w->s->model_ctx) mbw_ctx_free(w->ctx);
+      else w->ctx = nullptr;   // freed by mbw_serve_close after every worker has ended
+      delete w;
     });
   *out = s;
   return MBW_OK;
 }
 
-extern "C" int mbw_serve_submit(mbw_server *s, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads,
-                                uint64_t *ticket) {
+static int submit_impl(mbw_server *s, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads, bool copy,
+                       uint64_t *ticket) {
   if (!s || !ticket || (n_reads && (!reads || !lengths))) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
+  if (n_reads >= (1ull << 31)) { mbw_set_error("too many reads in one request"); return MBW_E_INVAL; }
   uint64_t bases = 0;
   for (uint64_t i = 0; i < n_reads; ++i) {
     if (lengths[i] > MBW_MAX_READ) { mbw_set_error("read longer than 65535 bases"); return MBW_E_INVAL; }
     bases += lengths[i];
   }
-  Request *r = new Request();
-  try {
-    r->reads.assign(reads, reads + bases);
-    r->lengths.assign(lengths, lengths + n_reads);
-  } catch (...) { delete r; mbw_set_error("host allocation failed"); return MBW_E_NOMEM; }
+  // admission by device memory: the request alone must fit a worker's arena
+  uint64_t need = 0;
+  const bool fit = s->fits(n_reads, bases, &need);
+  if (n_reads > s->cfg.max_batch_reads || bases > s->cfg.max_batch_bases || !fit) {
+    mbw_set_error("request too large for the server: " + std::to_string(n_reads) + " reads, " + std::to_string(bases) +
+                  " bases, an estimated " + std::to_string(need) + " bytes of device work space; a worker has " +
+                  std::to_string(s->ws_bytes) + " bytes, " + std::to_string(s->cfg.max_batch_reads) + " reads and " +
+                  std::to_string(s->cfg.max_batch_bases) + " bases per batch");
+    return MBW_E_CAPACITY;
+  }
+  Request *r = new (std::nothrow) Request();
+  if (!r) { mbw_set_error("host allocation failed"); return MBW_E_NOMEM; }
+  if (copy) {
+    try {
+      r->reads_copy.assign(reads, reads + bases);
+      r->lengths_copy.assign(lengths, lengths + n_reads);
+    } catch (...) { delete r; mbw_set_error("host allocation failed"); return MBW_E_NOMEM; }
+    r->reads = r->reads_copy.data();
+    r->lengths = r->lengths_copy.data();
+  } else {
+    r->reads = reads;
+    r->lengths = lengths;
+  }
+  r->n_reads = n_reads;
   r->bases = bases;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) { delete r; mbw_set_error("server is closing"); return MBW_E_INVAL; }
     if (!s->queue.empty() && s->queued_bases + bases > s->cfg.max_queued_bases) {
       delete r;
-      mbw_set_error("queue full (admission by queued bases)");
+      mbw_set_error("queue full (bases waiting for a worker)");
       return MBW_E_BUSY;
     }
     r->ticket = s->next_ticket++;
@@ -351,6 +638,16 @@ extern "C" int mbw_serve_submit(mbw_server *s, const uint8_t *reads, const uint3
   return MBW_OK;
 }
 
+extern "C" int mbw_serve_submit(mbw_server *s, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads,
+                                uint64_t *ticket) {
+  return submit_impl(s, reads, lengths, n_reads, true, ticket);
+}
+
+extern "C" int mbw_serve_submit_nocopy(mbw_server *s, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads,
+                                       uint64_t *ticket) {
+  return submit_impl(s, reads, lengths, n_reads, false, ticket);
+}
+
 extern "C" int mbw_serve_wait(mbw_server *s, uint64_t ticket, int timeout_ms, mbw_serve_result *out) {
   if (!s || !out) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
   std::unique_lock<std::mutex> lk(s->mu);
@@ -362,16 +659,18 @@ extern "C" int mbw_serve_wait(mbw_server *s, uint64_t ticket, int timeout_ms, mb
   else if (!s->done_cv.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready)) {
     mbw_set_error("request not finished"); return MBW_E_BUSY;
   }
-  if (r->rc) return r->rc;
-  out->n_seeds = r->ns;
-  out->n_pos = r->np;
-  out->seeds = r->buf ? (const mbw_seed_t *)r->buf->seeds.p + r->s0 : nullptr;
-  out->pos = r->buf ? (const uint64_t *)r->buf->pos.p + r->p0 : nullptr;
+  memset(out, 0, sizeof(*out));
   out->t_submit = r->t_submit;
   out->t_start = r->t_start;
   out->t_done = r->t_done;
   out->batch_id = r->batch_id;
   out->batch_reads = r->batch_reads;
+  out->attempts = r->attempts;
+  if (r->rc) { mbw_set_error(r->err); return r->rc; }
+  out->n_seeds = r->ns;
+  out->n_pos = r->np;
+  out->seeds = r->buf ? (const mbw_seed_t *)r->buf->seeds.p + r->s0 : nullptr;
+  out->pos = r->buf ? (const uint64_t *)r->buf->pos.p + r->p0 : nullptr;
   out->n_pieces = r->nc;
   out->pieces = r->buf && r->nc ? (const mbw_piece_t *)r->buf->pieces.p + r->c0 : nullptr;
   return MBW_OK;
@@ -389,12 +688,11 @@ extern "C" int mbw_serve_release(mbw_server *s, uint64_t ticket) {
   return MBW_OK;
 }
 
-extern "C" int mbw_serve_stats(mbw_server *s, uint64_t *batches, uint64_t *batch_reads, uint64_t *queued) {
-  if (!s) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
+extern "C" int mbw_serve_stats(mbw_server *s, mbw_serve_stats_t *out) {
+  if (!s || !out) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
   std::lock_guard<std::mutex> lk(s->mu);
-  if (batches) *batches = s->batches;
-  if (batch_reads) *batch_reads = s->batch_reads_sum;
-  if (queued) *queued = s->queue.size();
+  *out = s->st;
+  out->queued = s->queue.size();
   return MBW_OK;
 }
 
@@ -406,6 +704,7 @@ extern "C" void mbw_serve_close(mbw_server *s) {
   }
   s->work_cv.notify_all();
   for (auto &t : s->workers) t.join();   // queued requests are finished first
+  if (s->model_ctx) mbw_ctx_free(s->model_ctx);
   for (auto &kv : s->all) { s->unref(kv.second->buf); delete kv.second; }
   for (BatchBuf *b : s->free_bufs) delete b;
   delete s;

@@ -5,8 +5,8 @@
 * the rescue prefilter fails the same way and recovers;
 * creating a context under a cap too small for its control block fails with MBW_E_NOMEM and
   releases what it had made; a context created after the cap is lifted seeds correctly;
-* a serving batch that fails reports the error to its request; the server then serves the next
-  request correctly.
+* a serve arena over the cap fails the server's open; a request too large for a worker fails alone
+  and the server then serves the next request correctly.
 """
 import numpy as np
 import pytest
@@ -70,19 +70,23 @@ def test_context_creation_fails_then_recovers(small):
     ctx.free()
 
 
-def test_serving_isolates_a_failed_batch(small):
+def test_serving_isolates_a_failed_request(small):
+    """A serve arena over the debug cap fails the open with MBW_E_NOMEM; a request that cannot fit
+    a worker fails alone (MBW_E_CAPACITY at submission) and the next request is served correctly."""
     ref, ox, idx = small
     big = synth.reads_fixed(ref, 2000, 150, False, seed=73)
     ok = synth.reads_fixed(ref, 300, 150, False, seed=74)
-    srv = mbw.Server(idx, n_workers=1)
     try:
         mbw.set_mem_limit(1 << 20)
-        t = srv.submit(big.seq, big.lengths)
         with pytest.raises(mbw.MbwError) as e:
-            srv.wait(t)
+            mbw.Server(idx, n_workers=1)
         assert e.value.code == mbw.MBW_E_NOMEM
     finally:
         mbw.set_mem_limit(0)
+    srv = mbw.Server(idx, n_workers=1, max_batch_reads=1000, max_batch_bases=200_000)
+    with pytest.raises(mbw.MbwError) as e:
+        srv.submit(big.seq, big.lengths)
+    assert e.value.code == mbw.MBW_E_CAPACITY
     t = srv.submit(ok.seq, ok.lengths)
     s, p, info = srv.wait(t)
     compare_with_oracle(s, p, ox.seed(ok.seq, ok.offsets))

@@ -3,8 +3,10 @@
 * mbw_tune picks one of its candidate schedules; seeding with it is bit-exact against the oracle.
 * mbw_serve: every request's result equals the oracle's for that request alone, both when it is
   served alone and when it is batched with many others submitted concurrently (tolerance 0);
-  batches really merge requests; admission refuses submissions when the queue is full; the
-  device-side split of a batch handles empty and seedless requests.
+  batches really merge requests; submissions are refused when the queue is full and when a
+  request can never fit a worker's device arena; a batch that runs short of its arena is split and
+  retried so that no request fails because of another; requests queued without a host copy and
+  results read in place; the device-side split of a batch handles empty and seedless requests.
 """
 import threading
 
@@ -123,7 +125,7 @@ def test_serve_alone_and_in_a_mix(small):
 def test_serve_admission_by_queued_bases(small):
     ref, ox, idx = small
     reqs = _requests(ref, 12, seed=9)
-    srv = mbw.Server(idx, n_workers=1, max_batch_reads=10, max_queued_bases=2000)
+    srv = mbw.Server(idx, n_workers=1, max_batch_reads=3000, max_batch_bases=2_000_000, max_queued_bases=2000)
     accepted, refused = [], 0
     for q, r in enumerate(reqs):
         t = srv.submit(r.seq, r.lengths)
@@ -170,7 +172,7 @@ def test_serve_bisulfite_refined_pieces():
         o0, o1 = int(rs.offsets[a]), int(rs.offsets[b])
         offs = (rs.offsets[a:b + 1] - rs.offsets[a]).astype(np.uint64)
         reqs.append((seq[o0:o1].copy(), rs.lengths[a:b].copy(), offs))
-    srv = mbw.Server(idx, n_workers=2, max_batch_reads=400, bs_role=1, bs_refine=True)
+    srv = mbw.Server(idx, n_workers=2, max_batch_reads=1500, bs_role=1, bs_refine=True)
     tickets = [srv.submit(s, l) for s, l, _ in reqs]
     merged = 0
     for (s, l, offs), t in zip(reqs, tickets):
@@ -225,4 +227,115 @@ def test_serve_many_tiny_requests_share_a_batch(small):
                 assert len(s) == 0
         shared += info["batch_reads"] > len(lens)
     assert shared >= 40
+    srv.close()
+
+
+def _slice(rs, a, b):
+    """Reads [a, b) of a ReadSet as (seq, lengths, offsets from 0)."""
+    o0, o1 = int(rs.offsets[a]), int(rs.offsets[b])
+    return (rs.seq[o0:o1].copy(), rs.lengths[a:b].copy(),
+            (rs.offsets[a:b + 1] - rs.offsets[a]).astype(np.uint64))
+
+
+def _repeat_reference(copies=300, unit=400, div=0.01, seed=41):
+    """10 kbp of random sequence, then `copies` copies of one `unit`-base repeat, each with `div`
+    substitutions: reads from it have seeds with hundreds of positions."""
+    rng = np.random.default_rng(seed)
+    u = rng.integers(0, 4, unit).astype(np.uint8)
+    parts = [rng.integers(0, 4, 10_000).astype(np.uint8)]
+    for _ in range(copies):
+        c = u.copy()
+        m = rng.random(unit) < div
+        c[m] = (c[m] + rng.integers(1, 4, int(m.sum()))) % 4
+        parts.append(c.astype(np.uint8))
+    return synth.Reference(np.concatenate(parts), np.zeros((0, 2), np.uint64), 0, seed)
+
+
+def test_serve_split_on_shortfall():
+    """A batch that runs short of its worker's arena (far more positions per read than the sizing
+    model assumes) is split and its halves run again: two requests that fit alone but not together,
+    and a small one queued with them, all equal the oracle's results alone; a request that cannot
+    fit even alone fails with MBW_E_CAPACITY while the small request batched with it succeeds."""
+    ref = _repeat_reference()
+    ox = oracle.OracleIndex(ref.codes, sa_rate=8)
+    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=10)
+    pool = synth.reads_fixed(ref, 10000, 150, False, p_sub=0.003, p_indel=0.0, seed=42)
+    full = ox.seed(pool.seq, pool.offsets)
+    per_read = np.bincount(full.read_id, weights=full.npos, minlength=len(pool)).astype(np.int64)
+    cum = np.concatenate([[0], np.cumsum(per_read)])
+    srv = mbw.Server(idx, n_workers=1, max_batch_reads=4000, max_batch_bases=600_000)
+    P = srv.stats()["pos_cap"]
+    assert P > 0 and cum[-1] > 3.3 * P, (P, cum[-1])
+
+    def upto(a, target):   # the first b > a with positions of reads [a, b) >= target
+        return int(np.searchsorted(cum, cum[a] + target)) + 1
+
+    cuts = [0]
+    for _ in range(3):                 # three requests of 0.6 P positions: no two fit together
+        cuts.append(upto(cuts[-1], 0.6 * P))
+    reqs = [_slice(pool, a, b) for a, b in zip(cuts[:-1], cuts[1:])] + [_slice(pool, cuts[-1], cuts[-1] + 5)]
+    a3 = cuts[-1] + 5
+    a4 = upto(a3, 1.3 * P)
+    assert a4 + 5 <= len(pool)
+    big, small = _slice(pool, a3, a4), _slice(pool, a4, a4 + 5)
+    # submitted at once to one worker: while the first runs, the others queue and are batched
+    ts = [srv.submit(s, l) for s, l, _ in reqs]
+    for (s, l, offs), t in zip(reqs, ts):
+        seeds, pos, info = srv.wait(t)
+        compare_with_oracle(seeds, pos, ox.seed(s, offs))
+    st = srv.stats()
+    assert st["split_retries"] >= 1 and st["failed_requests"] == 0
+    tb, tsm = srv.submit(big[0], big[1]), srv.submit(small[0], small[1])
+    with pytest.raises(mbw.MbwError) as e:
+        srv.wait(tb)
+    assert e.value.code == mbw.MBW_E_CAPACITY
+    seeds, pos, info = srv.wait(tsm)
+    compare_with_oracle(seeds, pos, ox.seed(small[0], small[2]))
+    assert srv.stats()["failed_requests"] == 1
+    srv.close()
+    idx.free()
+
+
+def test_serve_admission_by_device_memory(small):
+    """A device budget below what one read needs is refused at open (the message names the least
+    size); with arenas of that least size, a request within the read and base budget whose
+    estimated work space exceeds the arena is refused at submission with MBW_E_CAPACITY, and the
+    server goes on serving the requests that fit; the stats report the arenas."""
+    import re
+    ref, ox, idx = small
+    with pytest.raises(mbw.MbwError) as e:
+        mbw.Server(idx, n_workers=2, max_batch_reads=20000, max_batch_bases=3_000_000, device_bytes=1 << 20)
+    assert e.value.code == mbw.MBW_E_INVAL
+    least = int(re.search(r"at least (\d+) bytes", str(e.value)).group(1))
+    srv = mbw.Server(idx, n_workers=2, max_batch_reads=20000, max_batch_bases=3_000_000, device_bytes=2 * least)
+    st = srv.stats()
+    assert st["device_bytes"] >= 2 * st["workspace_bytes"] > 0 and st["pos_cap"] > 0 and st["seeds_cap"] > 0
+    over = synth.reads_fixed(ref, 2000, 150, False, seed=81)
+    with pytest.raises(mbw.MbwError) as e:
+        srv.submit(over.seq, over.lengths)
+    assert e.value.code == mbw.MBW_E_CAPACITY and "work space" in str(e.value)
+    oks = [synth.reads_fixed(ref, 20, 150, False, seed=82 + q) for q in range(6)]
+    ts = [srv.submit(ok.seq, ok.lengths) for ok in oks]
+    for ok, t in zip(oks, ts):
+        s, p, info = srv.wait(t)
+        compare_with_oracle(s, p, ox.seed(ok.seq, ok.offsets))
+    assert srv.stats()["failed_requests"] == 0
+    srv.close()
+
+
+def test_serve_by_reference_and_views(small):
+    """Requests queued without a host copy and results read in place (no copy) equal the oracle's;
+    the views stay valid until release, while later batches run."""
+    ref, ox, idx = small
+    reqs = _requests(ref, 12, seed=21)
+    srv = mbw.Server(idx, n_workers=2, max_batch_reads=5000)
+    ts = [srv.submit(r.seq, r.lengths, copy=False) for r in reqs]
+    views = [srv.wait(t, copy=False) for t in ts]
+    more = [srv.submit(r.seq, r.lengths, copy=False) for r in reqs[:4]]
+    for r, t, (s, p, info) in zip(reqs, ts, views):
+        compare_with_oracle(s, p, ox.seed(r.seq, r.offsets))
+        srv.release(t)
+    for r, t in zip(reqs[:4], more):
+        s, p, _ = srv.wait(t)
+        compare_with_oracle(s, p, ox.seed(r.seq, r.offsets))
     srv.close()
