@@ -111,6 +111,11 @@ int mbw_index_info(const mbw_index *idx, mbw_index_info_t *out);
  * ssa:   ceil(n/r) x u64, ssa[x/r] = S(x).
  * kmer:  4^k x 16 B packed (k:40 | k':40 | s:40 bits, little-endian), code = sum P[q]*4^q. */
 int mbw_index_device_arrays(const mbw_index *idx, const void **lines, const void **ssa, const void **kmer);
+/* Device pointer to the superblock table the kernels read (read-only view): for each of the
+ * n_superblocks superblocks of 2^sb_lines_log2 lines, 8 x u64: the counts of A, C, G, T in B
+ * before its first row (the $ row counted as A), then for c = A, C, G, T the sum of those counts
+ * over the symbols after c. */
+int mbw_index_superblock_table(const mbw_index *idx, const void **sbtab);
 
 /* ---- seeding ------------------------------------------------------------------------------ */
 typedef struct mbw_ctx mbw_ctx;

@@ -36,7 +36,7 @@ SEED_ROUND2 = 2
 
 # the symbols include/mbw.h declares
 EXPORTS = ["mbw_strerror", "mbw_last_error", "mbw_index_build", "mbw_index_save", "mbw_index_load",
-           "mbw_index_free", "mbw_index_info", "mbw_index_device_arrays", "mbw_ctx_create", "mbw_ctx_free",
+           "mbw_index_free", "mbw_index_info", "mbw_index_device_arrays", "mbw_index_superblock_table", "mbw_ctx_create", "mbw_ctx_free",
            "mbw_seed", "mbw_result_download", "mbw_pos_to_ref", "mbw_tune",
            "mbw_result_download_pieces", "mbw_serve_open", "mbw_serve_submit", "mbw_serve_submit_nocopy", "mbw_serve_wait", "mbw_serve_release", "mbw_serve_stats",
            "mbw_serve_close", "mbw_rescue_filter", "mbw_rescue_download", "mbw_debug_set_mem_limit", "mbw_chain",
@@ -155,6 +155,7 @@ def load_library():
     L.mbw_index_free.restype = None
     L.mbw_index_info.argtypes = [vp, C.POINTER(IndexInfo)]
     L.mbw_index_device_arrays.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]
+    L.mbw_index_superblock_table.argtypes = [vp, C.POINTER(vp)]
     L.mbw_ctx_create.argtypes = [vp, C.POINTER(vp)]
     L.mbw_ctx_free.argtypes = [vp]
     L.mbw_ctx_free.restype = None
@@ -285,6 +286,12 @@ class Index:
         a, b, c = C.c_void_p(), C.c_void_p(), C.c_void_p()
         _check(self._lib.mbw_index_device_arrays(self._h, C.byref(a), C.byref(b), C.byref(c)))
         return a.value, b.value, c.value
+
+    def superblock_table(self):
+        """Device pointer to the superblock table (n_superblocks x 8 u64)."""
+        a = C.c_void_p()
+        _check(self._lib.mbw_index_superblock_table(self._h, C.byref(a)))
+        return a.value
 
     def pos_to_ref(self, pos: int, length: int):
         s, p = C.c_int(), C.c_uint64()

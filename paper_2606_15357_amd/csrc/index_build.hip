@@ -741,6 +741,12 @@ extern "C" int mbw_index_device_arrays(const mbw_index *ix, const void **lines, 
   return MBW_OK;
 }
 
+extern "C" int mbw_index_superblock_table(const mbw_index *ix, const void **sbtab) {
+  if (!ix || !sbtab) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
+  *sbtab = ix->sbtab;
+  return MBW_OK;
+}
+
 extern "C" int mbw_pos_to_ref(const mbw_index *ix, uint64_t pos, uint32_t len, int *strand, uint64_t *ref_pos) {
   if (!ix || !strand || !ref_pos) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
   uint64_t half = (ix->n - 1) / 2;   // |R| (plain) or 2|R| (bisulfite)

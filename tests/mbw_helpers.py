@@ -89,3 +89,78 @@ def unpack_kmer(e):
     kr = (w0 >> 40) | ((w1 & 0xFFFF) << 24)
     s = w1 >> 16
     return k, kr, s
+
+
+_hip = None
+
+
+def device_to_host(ptr: int, nbytes: int) -> np.ndarray:
+    """Bytes of device memory at ptr (hipMemcpy, device to host)."""
+    import ctypes
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _hip.hipMemcpy.restype = ctypes.c_int
+    out = np.empty(max(int(nbytes), 1), np.uint8)
+    rc = _hip.hipMemcpy(out.ctypes.data, ctypes.c_void_p(int(ptr)), int(nbytes), 2)
+    assert rc == 0, f"hipMemcpy returned {rc}"
+    return out[:nbytes]
+
+
+def check_line_table(index, log=print):
+    """CPU check of a resident index's occurrence lines and superblock table against their
+    definitions, with numpy popcounts of the bit planes (none of the library's rank code):
+    rows past n are zero; each sub-checkpoint holds the A, C, G counts of the line's first 64b
+    rows; each line header holds the counts from its superblock's first row (zero at every
+    2^sb_lines_log2-line boundary); each superblock entry holds the A, C, G, T counts before it and
+    their suffix sums; and the totals over all n rows match C ($ counted as A)."""
+    info = index.info()
+    n, nl, sh, nsb = int(info["n"]), int(info["n_lines"]), int(info["sb_lines_log2"]), int(info["n_superblocks"])
+    Cc = [int(x) for x in info["C"]]
+    assert nsb == ((nl - 1) >> sh) + 1
+    lines_ptr = index.device_arrays()[0]
+    sbt = device_to_host(index.superblock_table(), nsb * 64).view(np.uint64).reshape(nsb, 8).astype(np.int64)
+    chunk = 1 << min(21, sh)            # chunks never straddle a superblock boundary
+    run = np.zeros(3, np.int64)         # A, C, G since the superblock's first row
+    total = np.zeros(4, np.int64)       # A, C, G, T before the chunk
+    full = np.uint64(0xFFFFFFFFFFFFFFFF)
+    for L0 in range(0, nl, chunk):
+        m = min(chunk, nl - L0)
+        if L0 % (1 << sh) == 0:
+            sb = L0 >> sh
+            run[:] = 0
+            assert np.array_equal(sbt[sb, :4], total), (sb, sbt[sb], total)
+            for c in range(4):
+                assert sbt[sb, 4 + c] == total[c + 1:].sum(), (sb, c)
+        raw = device_to_host(lines_ptr + L0 * 128, m * 128)
+        u32 = raw.view(np.uint32).reshape(m, 32)
+        u64 = raw.view(np.uint64).reshape(m, 16)
+        lo, hi = u64[:, 4::2], u64[:, 5::2]
+        first = np.arange(L0, L0 + m, dtype=np.int64)[:, None] * 384 + np.arange(6, dtype=np.int64)[None, :] * 64
+        nvalid = np.clip(n - first, 0, 64)
+        mask = np.where(nvalid >= 64, full,
+                        (np.uint64(1) << np.minimum(nvalid, 63).astype(np.uint64)) - np.uint64(1))
+        assert not np.any((lo | hi) & ~mask), "bits set in rows past n"
+        cA = np.bitwise_count(~lo & ~hi & mask).astype(np.int64)
+        cC = np.bitwise_count(lo & ~hi & mask).astype(np.int64)
+        cG = np.bitwise_count(~lo & hi & mask).astype(np.int64)
+        cT = np.bitwise_count(lo & hi & mask).astype(np.int64)
+        blk = np.stack([cA, cC, cG], axis=2)                    # lines x 6 blocks x 3
+        sub_exp = np.cumsum(blk, axis=1)[:, :5, :]
+        words = np.concatenate([u32[:, 3:4], u32[:, 4:8]], axis=1).astype(np.int64)
+        sub_got = np.stack([(words >> s) & 0x1FF for s in (0, 9, 18)], axis=2)
+        if not np.array_equal(sub_got, sub_exp):
+            bad = np.argwhere(sub_got != sub_exp)[0]
+            raise AssertionError(f"sub-checkpoint differs at line {L0 + bad[0]}, b={bad[1] + 1}")
+        per_line = blk.sum(axis=1)
+        head_exp = run[None, :] + np.cumsum(per_line, axis=0) - per_line
+        head_got = u32[:, 0:3].astype(np.int64)
+        if not np.array_equal(head_got, head_exp):
+            bad = np.argwhere(head_got != head_exp)[0]
+            raise AssertionError(f"line header differs at line {L0 + bad[0]}, symbol {bad[1]}")
+        run += per_line.sum(axis=0)
+        total += np.array([cA.sum(), cC.sum(), cG.sum(), cT.sum()])
+    want = np.array([Cc[2] - Cc[1] + 1, Cc[3] - Cc[2], Cc[4] - Cc[3], n - Cc[4]], np.int64)
+    assert np.array_equal(total, want), (total, want)
+    log(f"line table checked: {nl} lines, {nsb} superblocks of 2^{sh} lines")

@@ -16,7 +16,11 @@ position of the sampled reads must agree exactly:
   strand mirror (seeding revcomp(P) gives (k', k, s) and the mirrored positions).  The whole batch
   is chained (Section 2.6) and the chains of the sampled reads equal the chaining oracle's on the
   scan oracle's seeds.  The mate-rescue prefilter runs over 20,000,000 candidates of the same
-  batch; 1,200 sampled candidates must match the oracle exactly.
+  batch; 1,200 sampled candidates must match the oracle exactly.  The resident line table of the
+  index passes a CPU check from its definitions (check_line_table);
+* the same genome's four-copy bisulfite index: the line table check, wave and plain kernels
+  identical for read 1 and read 2 over 1,000,000 reads, and O3 on 60 sampled reads per role
+  (with the refined pieces of read 1).
 """
 import time
 
@@ -25,7 +29,7 @@ import pytest
 
 import oracle
 import synth
-from mbw_helpers import compare_with_oracle
+from mbw_helpers import check_line_table, compare_with_oracle
 
 mbw = pytest.importorskip("paper_2606_15357_amd")
 torch = pytest.importorskip("torch")
@@ -175,6 +179,8 @@ def test_human_3gbp_sampled_parity():
     idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=15)
     info = idx.info()
     log(f"GPU index in {time.time() - t0:.1f} s, n = {info['n']}")
+    assert info["n_superblocks"] == 2
+    check_line_table(idx, log)
     reads = synth.workload_reads("human_3gbp", ref)
     ctx = mbw.Context(idx)
     out, seeds, pos = gpu_seed_batch(ctx, reads, min_seed_len=19, max_occ=500)
@@ -260,6 +266,64 @@ def test_human_3gbp_sampled_parity():
         mine = flat[off[t]:off[t + 1]].astype(np.int64)
         mirrored = np.sort(two_r - mine - int(lens[q]))
         assert np.array_equal(mirrored, flat2[off2[q]:off2[q + 1]].astype(np.int64))
+    ctx.free()
+    idx.free()
+    log(f"done in {time.time() - t0:.1f} s")
+
+
+# ---------------------------------------------------------------------------------------------
+# 3.1 Gbp, bisulfite four-copy index
+
+def test_bisulfite_3gbp_sampled_parity():
+    """The four-copy bisulfite index of the 3.1 Gbp genome (n = 12.4 G + 1, four superblocks of
+    2^23 lines, so superblocks 2 and 3 and the copy-2/3 strand filter are used): the line table
+    passes the CPU check; 1,000,000 directional reads are seeded as read 1 (with the seed
+    refinement) and, reverse-complemented, as read 2; the wave and plain kernels give the same
+    arrays for the whole batch; on 60 sampled reads per role the seeds, occurrence counts and
+    positions equal the scan oracle's on the four-copy text, and for read 1 the refined pieces
+    equal the refinement oracle's on those seeds."""
+    t0 = time.time()
+    ref = synth.workload_reference("serve_bs_3gbp")
+    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=15, bisulfite=True, isa_sample=8)
+    info = idx.info()
+    log(f"bisulfite index in {time.time() - t0:.1f} s, n = {info['n']}, {info['n_superblocks']} superblocks")
+    assert info["n"] == 4 * len(ref) + 1 and info["n_superblocks"] == 4
+    check_line_table(idx, log)
+    log(f"line table checked ({time.time() - t0:.1f} s)")
+    r1 = synth.reads_bisulfite(ref, 1_000_000, seed=synth.READ_SEED + 40)
+    # read 2 of a directional library: the reverse complement of a read-1-form read
+    seq2 = np.frombuffer(r1.seq.tobytes().translate(COMP)[::-1], np.uint8).copy()
+    len2 = r1.lengths[::-1].copy()
+    off2 = np.concatenate([[0], np.cumsum(len2, dtype=np.uint64)]).astype(np.uint64)
+    r2 = synth.ReadSet(seq2, len2, off2, r1.tpos[::-1].copy(), r1.tstrand[::-1].copy())
+    ctx = mbw.Context(idx)
+    rng = np.random.default_rng(106)
+    for role, reads in ((1, r1), (2, r2)):
+        out, seeds, pos = gpu_seed_batch(ctx, reads, min_seed_len=19, max_occ=500, bs_role=role, bs_refine=role == 1)
+        pieces = out.download_pieces() if role == 1 else None
+        log(f"role {role}: {out.n_seeds} seeds, {out.n_pos} positions, {0 if pieces is None else len(pieces)} pieces "
+            f"({time.time() - t0:.1f} s)")
+        _, seeds_p, pos_p = gpu_seed_batch(ctx, reads, min_seed_len=19, max_occ=500, bs_role=role,
+                                           kernel=mbw.KERNEL_PLAIN)
+        assert same_arrays(seeds_p, pos_p, seeds, pos)
+        del seeds_p, pos_p
+        ids = np.sort(rng.choice(len(reads), 60, replace=False))
+        sub = reads.subset(ids)
+        s_gpu, p_gpu = sample_of(seeds, pos, ids)
+        exp = oracle.scan_seed(ref.codes, sub.seq, sub.offsets, bisulfite=True, bs_role=role, min_len=19, max_occ=500)
+        log(f"role {role} scan oracle: {len(exp)} seeds, {exp.pos.size} positions ({time.time() - t0:.1f} s)")
+        assert len(exp) > 60 and exp.pos.size > 60
+        compare_without_bounds(s_gpu, p_gpu, exp)
+        if role == 1:
+            m = np.isin(pieces["read_id"], ids)
+            got = pieces[m].copy()
+            got["read_id"] = np.searchsorted(ids, got["read_id"]).astype(np.uint32)
+            got = got[np.lexsort((got["pos"], got["qend"], got["qbeg"], got["read_id"]))]
+            want = oracle.bs_refine(ref.codes, sub.seq, sub.offsets, exp, 1, min_len=19)
+            assert len(got) == len(want) and len(want) > 0
+            for f in ("read_id", "qbeg", "qend", "pos"):
+                assert np.array_equal(got[f].astype(np.uint64), want[f].astype(np.uint64)), f
+        del seeds, pos, pieces
     ctx.free()
     idx.free()
     log(f"done in {time.time() - t0:.1f} s")
