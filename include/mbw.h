@@ -68,15 +68,31 @@ typedef struct {
  * mbw_index_free.  Blocking.  Errors: MBW_E_INVAL (len, options), MBW_E_NOMEM, MBW_E_HIP.      */
 int mbw_index_build(const uint8_t *ref, uint64_t len, const mbw_build_opts *opts, mbw_index **out);
 
-/* Write the resident index to `path` (versioned header + checksummed arrays), streamed through
- * 128 MiB of pinned host memory.  Blocking.  Errors: MBW_E_IO, MBW_E_NOMEM, MBW_E_HIP. */
+/* mbw_index_build from a FASTA file: R is the sequences of its records back to back (headers start
+ * with '>', a record's name is its header up to the first blank; line breaks and blanks inside
+ * sequences are dropped; every other character is a base, ambiguous ones drawn as for
+ * mbw_index_build).  The records are kept with the index (mbw_index_contig) and in its file.
+ * opts->ref_is_codes must be 0.  Errors: MBW_E_IO (open, read), MBW_E_FORMAT (no record, sequence
+ * before the first header, a record without sequence), and those of mbw_index_build. */
+int mbw_index_build_fasta(const char *fasta_path, const mbw_build_opts *opts, mbw_index **out);
+
+/* The records of the index's reference: an index built from memory has one, with an empty name,
+ * covering R; a FASTA build has the file's.  mbw_index_contig gives record i (name valid while the
+ * index lives; start and length in R coordinates); mbw_ref_to_contig maps a position of R (e.g.
+ * from mbw_pos_to_ref) to its record and the offset in it.  Errors: MBW_E_INVAL. */
+int mbw_index_contigs(const mbw_index *idx, uint64_t *n);
+int mbw_index_contig(const mbw_index *idx, uint64_t i, const char **name, uint64_t *start, uint64_t *len);
+int mbw_ref_to_contig(const mbw_index *idx, uint64_t ref_pos, uint64_t *contig, uint64_t *offset);
+
+/* Write the resident index to `path` (versioned header + checksummed arrays + the record table),
+ * streamed through 128 MiB of pinned host memory.  Blocking.  Errors: MBW_E_IO, MBW_E_NOMEM, MBW_E_HIP. */
 int mbw_index_save(const mbw_index *idx, const char *path);
 
 /* Read an index file written by mbw_index_save and make it resident on `device`, streamed
  * through 128 MiB of pinned host memory.  Before anything is allocated the header must pass the
  * builder's limits (n < 2^39, n = 2|R|+1 or 4|R|+1, primary < n, C non-decreasing with C[$] = 0,
  * C[A] = 1 and C[T] <= n, at most 8 superblocks, array sizes consistent) and the file size must
- * equal what the header states.
+ * equal what the header states; the record table must cover R exactly.
  * Errors: MBW_E_IO, MBW_E_FORMAT (magic, version, fields, sizes or checksum), MBW_E_NOMEM, MBW_E_HIP. */
 int mbw_index_load(const char *path, int device, mbw_index **out);
 

@@ -36,7 +36,7 @@ SEED_ROUND2 = 2
 
 # the symbols include/mbw.h declares
 EXPORTS = ["mbw_strerror", "mbw_last_error", "mbw_index_build", "mbw_index_save", "mbw_index_load",
-           "mbw_index_free", "mbw_index_info", "mbw_index_device_arrays", "mbw_index_superblock_table", "mbw_ctx_create", "mbw_ctx_free",
+           "mbw_index_free", "mbw_index_info", "mbw_index_device_arrays", "mbw_index_superblock_table", "mbw_index_build_fasta", "mbw_index_contigs", "mbw_index_contig", "mbw_ref_to_contig", "mbw_ctx_create", "mbw_ctx_free",
            "mbw_seed", "mbw_result_download", "mbw_pos_to_ref", "mbw_tune",
            "mbw_result_download_pieces", "mbw_serve_open", "mbw_serve_submit", "mbw_serve_submit_nocopy", "mbw_serve_wait", "mbw_serve_release", "mbw_serve_stats",
            "mbw_serve_close", "mbw_rescue_filter", "mbw_rescue_download", "mbw_debug_set_mem_limit", "mbw_chain",
@@ -156,6 +156,10 @@ def load_library():
     L.mbw_index_info.argtypes = [vp, C.POINTER(IndexInfo)]
     L.mbw_index_device_arrays.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]
     L.mbw_index_superblock_table.argtypes = [vp, C.POINTER(vp)]
+    L.mbw_index_build_fasta.argtypes = [C.c_char_p, C.POINTER(BuildOpts), C.POINTER(vp)]
+    L.mbw_index_contigs.argtypes = [vp, C.POINTER(C.c_uint64)]
+    L.mbw_index_contig.argtypes = [vp, u64, C.POINTER(C.c_char_p), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+    L.mbw_ref_to_contig.argtypes = [vp, u64, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
     L.mbw_ctx_create.argtypes = [vp, C.POINTER(vp)]
     L.mbw_ctx_free.argtypes = [vp]
     L.mbw_ctx_free.restype = None
@@ -264,6 +268,34 @@ class Index:
         h = C.c_void_p()
         _check(L.mbw_index_build(arr.ctypes.data if arr.size else None, arr.size, C.byref(o), C.byref(h)))
         return cls(h)
+
+    @classmethod
+    def build_fasta(cls, path: str, sa_sample: int = 8, kmer_k: int = 10, bisulfite: bool = False, device: int = 0,
+                    rng_seed: int = 0, isa_sample: int = 4, sb_lines_log2: int = 0):
+        """Build from a FASTA file (records back to back; see ``contigs``)."""
+        L = load_library()
+        o = BuildOpts(int(sa_sample), int(kmer_k), int(bool(bisulfite)), 0, int(rng_seed), int(device),
+                      int(isa_sample), int(sb_lines_log2))
+        h = C.c_void_p()
+        _check(L.mbw_index_build_fasta(path.encode(), C.byref(o), C.byref(h)))
+        return cls(h)
+
+    def contigs(self):
+        """[(name, start, length)] of the reference's records, start and length in R."""
+        n = C.c_uint64()
+        _check(self._lib.mbw_index_contigs(self._h, C.byref(n)))
+        out = []
+        for i in range(n.value):
+            nm, st, ln = C.c_char_p(), C.c_uint64(), C.c_uint64()
+            _check(self._lib.mbw_index_contig(self._h, i, C.byref(nm), C.byref(st), C.byref(ln)))
+            out.append((nm.value.decode(errors="replace"), st.value, ln.value))
+        return out
+
+    def ref_to_contig(self, ref_pos: int):
+        """(record index, offset in it) of a position of R."""
+        c, o = C.c_uint64(), C.c_uint64()
+        _check(self._lib.mbw_ref_to_contig(self._h, int(ref_pos), C.byref(c), C.byref(o)))
+        return c.value, o.value
 
     @classmethod
     def load(cls, path: str, device: int = 0):

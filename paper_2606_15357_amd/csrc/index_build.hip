@@ -20,6 +20,45 @@
 #include "mbw_internal.h"
 #include "../../include/mbw.h"
 
+// The records of a reference: R is their sequences back to back, record i at [start[i], start[i] +
+// len[i]).  An index built from memory has one record with an empty name.
+struct mbw_contigs {
+  std::vector<std::string> name;
+  std::vector<uint64_t> start, len;
+
+  // file form: u64 count, then per record u64 start, u64 length, u32 name bytes, the name
+  std::vector<uint8_t> serialize() const {
+    std::vector<uint8_t> b;
+    auto put = [&](const void *p, size_t k) { const uint8_t *q = (const uint8_t *)p; b.insert(b.end(), q, q + k); };
+    const uint64_t n = name.size();
+    put(&n, 8);
+    for (uint64_t i = 0; i < n; ++i) {
+      const uint32_t nl = (uint32_t)name[i].size();
+      put(&start[i], 8); put(&len[i], 8); put(&nl, 4); put(name[i].data(), nl);
+    }
+    while (b.size() % 8) b.push_back(0);
+    return b;
+  }
+  // parse and check against |R|: records back to back from 0, non-empty, covering R exactly
+  bool parse(const uint8_t *p, size_t bytes, uint64_t len_r) {
+    size_t o = 0;
+    auto get = [&](void *d, size_t k) { if (o + k > bytes) return false; memcpy(d, p + o, k); o += k; return true; };
+    uint64_t n = 0;
+    if (!get(&n, 8) || n == 0 || n > bytes / 20) return false;
+    uint64_t at = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+      uint64_t a, l; uint32_t nl;
+      if (!get(&a, 8) || !get(&l, 8) || !get(&nl, 4) || o + nl > bytes) return false;
+      if (a != at || l == 0) return false;
+      name.emplace_back((const char *)p + o, nl);
+      o += nl;
+      start.push_back(a); len.push_back(l);
+      at += l;
+    }
+    return at == len_r;
+  }
+};
+
 namespace {
 
 // ---------------------------------------------------------------------------------------------
@@ -468,6 +507,7 @@ extern "C" void mbw_index_free(mbw_index *ix) {
   if (ix->text) (void)hipFree(ix->text);
   if (ix->isa) (void)hipFree(ix->isa);
   if (ix->orig) (void)hipFree(ix->orig);
+  delete ix->contigs;
   (void)hipSetDevice(cur);
   delete ix;
 }
@@ -715,6 +755,14 @@ extern "C" int mbw_index_build(const uint8_t *ref, uint64_t len, const mbw_build
     return 0;
   }();
   (void)hipStreamDestroy(st);
+  if (!rc) {
+    try {
+      ix->contigs = new mbw_contigs();
+      ix->contigs->name.push_back("");
+      ix->contigs->start.push_back(0);
+      ix->contigs->len.push_back(len);
+    } catch (...) { mbw_set_error("host allocation failed"); rc = MBW_E_NOMEM; }
+  }
   if (rc) { mbw_index_free(ix); return rc; }
   *out = ix;
   return MBW_OK;
@@ -747,6 +795,109 @@ extern "C" int mbw_index_superblock_table(const mbw_index *ix, const void **sbta
   return MBW_OK;
 }
 
+extern "C" int mbw_index_contigs(const mbw_index *ix, uint64_t *n) {
+  if (!ix || !n) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
+  *n = ix->contigs ? ix->contigs->name.size() : 0;
+  return MBW_OK;
+}
+
+extern "C" int mbw_index_contig(const mbw_index *ix, uint64_t i, const char **name, uint64_t *start, uint64_t *len) {
+  if (!ix || !ix->contigs) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
+  if (i >= ix->contigs->name.size()) { mbw_set_error("record index out of range"); return MBW_E_INVAL; }
+  if (name) *name = ix->contigs->name[i].c_str();
+  if (start) *start = ix->contigs->start[i];
+  if (len) *len = ix->contigs->len[i];
+  return MBW_OK;
+}
+
+extern "C" int mbw_ref_to_contig(const mbw_index *ix, uint64_t ref_pos, uint64_t *contig, uint64_t *offset) {
+  if (!ix || !ix->contigs || !contig || !offset) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
+  if (ref_pos >= ix->len_r) { mbw_set_error("reference position out of range"); return MBW_E_INVAL; }
+  const std::vector<uint64_t> &st = ix->contigs->start;
+  const uint64_t i = (uint64_t)(std::upper_bound(st.begin(), st.end(), ref_pos) - st.begin()) - 1;
+  *contig = i;
+  *offset = ref_pos - st[i];
+  return MBW_OK;
+}
+
+// Read a FASTA file: records start with '>' (the name is the header up to the first white space);
+// sequence lines are concatenated with line breaks and blanks removed.
+static int read_fasta(const char *path, std::vector<uint8_t> &seq, mbw_contigs &ct) {
+  FILE *f = fopen(path, "rb");
+  if (!f) { mbw_set_error(std::string("cannot open ") + path); return MBW_E_IO; }
+  std::vector<char> buf(16u << 20);
+  enum { LINE_START, IN_HEADER_NAME, IN_HEADER_REST, IN_SEQ } state = LINE_START;
+  std::string name;
+  bool any = false;
+  int rc = MBW_OK;
+  auto close_record = [&]() -> bool {
+    if (!any) return true;
+    const uint64_t l = seq.size() - ct.start.back();
+    if (l == 0) { mbw_set_error("FASTA record '" + ct.name.back() + "' has no sequence"); return false; }
+    ct.len.push_back(l);
+    return true;
+  };
+  try {
+    for (;;) {
+      const size_t got = fread(buf.data(), 1, buf.size(), f);
+      if (got == 0) break;
+      for (size_t i = 0; i < got && !rc; ++i) {
+        const char ch = buf[i];
+        switch (state) {
+          case LINE_START:
+            if (ch == '>') {
+              if (!close_record()) { rc = MBW_E_FORMAT; break; }
+              any = true;
+              name.clear();
+              ct.start.push_back(seq.size());
+              state = IN_HEADER_NAME;
+              break;
+            }
+            state = IN_SEQ;
+            [[fallthrough]];   // the first character of a sequence line
+          case IN_SEQ:
+            if (ch == '\n') { state = LINE_START; break; }
+            if (ch == '\r' || ch == ' ' || ch == '\t') break;
+            if (!any) { mbw_set_error("FASTA sequence before the first '>' header"); rc = MBW_E_FORMAT; break; }
+            seq.push_back((uint8_t)ch);
+            break;
+          case IN_HEADER_NAME:
+            if (ch == '\n') { ct.name.push_back(name); state = LINE_START; }
+            else if (ch == ' ' || ch == '\t' || ch == '\r') { ct.name.push_back(name); state = IN_HEADER_REST; }
+            else name.push_back(ch);
+            break;
+          case IN_HEADER_REST:
+            if (ch == '\n') state = LINE_START;
+            break;
+        }
+      }
+      if (rc) break;
+    }
+    if (!rc && ferror(f)) { mbw_set_error(std::string("read failed: ") + path); rc = MBW_E_IO; }
+    if (!rc && state == IN_HEADER_NAME) ct.name.push_back(name);
+    if (!rc && !any) { mbw_set_error("no FASTA record in " + std::string(path)); rc = MBW_E_FORMAT; }
+    if (!rc && !close_record()) rc = MBW_E_FORMAT;
+  } catch (...) { mbw_set_error("host allocation failed"); rc = MBW_E_NOMEM; }
+  fclose(f);
+  return rc;
+}
+
+extern "C" int mbw_index_build_fasta(const char *fasta_path, const mbw_build_opts *opts, mbw_index **out) {
+  if (!out) { mbw_set_error("out is NULL"); return MBW_E_INVAL; }
+  *out = nullptr;
+  if (!fasta_path || !opts) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
+  if (opts->ref_is_codes) { mbw_set_error("a FASTA reference is ASCII (ref_is_codes must be 0)"); return MBW_E_INVAL; }
+  std::vector<uint8_t> seq;
+  mbw_contigs *ct = new (std::nothrow) mbw_contigs();
+  if (!ct) { mbw_set_error("host allocation failed"); return MBW_E_NOMEM; }
+  int rc = read_fasta(fasta_path, seq, *ct);
+  if (!rc) rc = mbw_index_build(seq.data(), seq.size(), opts, out);
+  if (rc) { delete ct; return rc; }
+  delete (*out)->contigs;
+  (*out)->contigs = ct;
+  return MBW_OK;
+}
+
 extern "C" int mbw_pos_to_ref(const mbw_index *ix, uint64_t pos, uint32_t len, int *strand, uint64_t *ref_pos) {
   if (!ix || !strand || !ref_pos) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
   uint64_t half = (ix->n - 1) / 2;   // |R| (plain) or 2|R| (bisulfite)
@@ -764,7 +915,7 @@ extern "C" int mbw_pos_to_ref(const mbw_index *ix, uint64_t pos, uint32_t len, i
 // ---------------------------------------------------------------------------------------------
 // index files: header (magic, version, fields, FNV-1a of header and of each array) + arrays
 static const uint64_t kMagic = 0x3158444e4957424dull;  // "MBWINDX1"
-static const uint32_t kVersion = 6;
+static const uint32_t kVersion = 7;
 
 struct FileHeader {
   uint64_t magic;
@@ -776,6 +927,7 @@ struct FileHeader {
   int32_t isa_sample, sb_shift;
   uint64_t n_text, n_isa, n_orig;
   uint64_t sum_lines, sum_ssa, sum_kmer, sum_text, sum_isa, sum_orig;
+  uint64_t contig_bytes, sum_contigs;   // the record table (its file form), after the arrays
   uint64_t sum_header;
 };
 
@@ -893,6 +1045,12 @@ extern "C" int mbw_index_save(const mbw_index *ix, const char *path) {
   if (!r) r = save_array(S, f, ix->isa, hd.n_isa * 8, &hd.sum_isa);
   if (!r) r = save_array(S, f, ix->orig, hd.n_orig * 8, &hd.sum_orig);
   if (!r) {
+    const std::vector<uint8_t> cb = ix->contigs->serialize();
+    hd.contig_bytes = cb.size();
+    hd.sum_contigs = fnv(cb.data(), cb.size());
+    if (fwrite(cb.data(), 1, cb.size(), f) != cb.size()) { mbw_set_error(std::string("write failed: ") + path); r = MBW_E_IO; }
+  }
+  if (!r) {
     hd.sum_header = fnv(&hd, offsetof(FileHeader, sum_header));
     if (fseek(f, 0, SEEK_SET) != 0 || fwrite(&hd, sizeof(hd), 1, f) != 1) {
       mbw_set_error(std::string("write failed: ") + path); r = MBW_E_IO;
@@ -924,11 +1082,13 @@ extern "C" int mbw_index_load(const char *path, int device, mbw_index **out) {
       hd.isa_sample < 0 || hd.isa_sample > 64 ||
       (hd.isa_sample ? (hd.n_isa != (hd.n - 1) / hd.isa_sample + 1 || hd.n_text != (hd.n - 1 + 31) / 32 + 4)
                      : (hd.n_isa != 0 || hd.n_text != 0)) ||
-      hd.n_orig != (hd.bisulfite ? (hd.len_r + 31) / 32 + 2 : 0)) {
+      hd.n_orig != (hd.bisulfite ? (hd.len_r + 31) / 32 + 2 : 0) || hd.contig_bytes < 8 ||
+      hd.contig_bytes > (1ull << 32) || hd.contig_bytes % 8) {
     fclose(f); mbw_set_error("bad magic, version or header fields"); return MBW_E_FORMAT;
   }
   const uint64_t kb = kmer_bytes(hd.kmer_k);
-  const uint64_t payload = hd.n_lines * MBW_LINE_BYTES + hd.n_ssa * 8 + kb + (hd.n_text + hd.n_isa + hd.n_orig) * 8;
+  const uint64_t payload =
+      hd.n_lines * MBW_LINE_BYTES + hd.n_ssa * 8 + kb + (hd.n_text + hd.n_isa + hd.n_orig) * 8 + hd.contig_bytes;
   // the file must hold exactly the arrays its header states (checked before any device allocation)
   if (fseeko(f, 0, SEEK_END) != 0) { fclose(f); mbw_set_error("cannot seek index file"); return MBW_E_IO; }
   const off_t fsize = ftello(f);
@@ -969,6 +1129,11 @@ extern "C" int mbw_index_load(const char *path, int device, mbw_index **out) {
     if ((r = place(&ix->text, hd.n_text * 8, hd.sum_text))) return r;
     if ((r = place(&ix->isa, hd.n_isa * 8, hd.sum_isa))) return r;
     if ((r = place(&ix->orig, hd.n_orig * 8, hd.sum_orig))) return r;
+    std::vector<uint8_t> cb(hd.contig_bytes);
+    if (fread(cb.data(), 1, cb.size(), f) != cb.size()) { mbw_set_error("truncated index file"); return MBW_E_FORMAT; }
+    if (fnv(cb.data(), cb.size()) != hd.sum_contigs) { mbw_set_error("index checksum mismatch"); return MBW_E_FORMAT; }
+    ix->contigs = new mbw_contigs();
+    if (!ix->contigs->parse(cb.data(), cb.size(), hd.len_r)) { mbw_set_error("bad record table"); return MBW_E_FORMAT; }
     ix->bytes = hd.n_lines * MBW_LINE_BYTES + hd.n_ssa * 8 + kb + sizeof(hd.sb) + (hd.n_text + hd.n_isa + hd.n_orig) * 8;
     return 0;
   }();

@@ -53,6 +53,7 @@ struct mbw_index {
   uint64_t n_orig;             // bisulfite indexes: the original reference, packed like the text
   uint64_t *orig;
   uint64_t bytes;
+  struct mbw_contigs *contigs; // host: the reference's records (names, start and length in R)
 };
 
 // Read-only view passed by value to kernels.

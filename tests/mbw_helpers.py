@@ -40,7 +40,7 @@ def compare_with_oracle(seeds, pos, ref_res, check_flags=True):
     assert np.array_equal(flat, ref_res.pos), "positions differ"
 
 
-HEADER = struct.Struct("<QII QQQQQ 5Q iiii 64Q ii QQQ QQQQQQ Q")
+HEADER = struct.Struct("<QII QQQQQ 5Q iiii 64Q ii QQQ QQQQQQ QQ Q")
 MAX_SB = 8
 
 
@@ -68,8 +68,17 @@ def read_index_file(path):
     isa = np.frombuffer(raw, dtype=np.uint64, count=n_isa, offset=off)
     off += 8 * n_isa
     orig = np.frombuffer(raw, dtype=np.uint64, count=n_orig, offset=off)
+    off += 8 * n_orig
+    contig_bytes = h[28 + 8 * MAX_SB]
+    blob = raw[off:off + contig_bytes]
+    contigs, o = [], 8
+    for _ in range(struct.unpack_from("<Q", blob, 0)[0]):
+        st, ln, nl = struct.unpack_from("<QQI", blob, o)
+        contigs.append((blob[o + 20:o + 20 + nl].decode(), st, ln))
+        o += 20 + nl
     return dict(n=n, len_r=len_r, primary=primary, n_lines=n_lines, C=C5, r=r, K=K, sb=sb, bis=bis, sb_shift=sb_shift,
-                lines=lines, ssa=ssa, kmer=kmer, bpl=bpl, isa_sample=isa_sample, text=text, isa=isa, orig=orig)
+                lines=lines, ssa=ssa, kmer=kmer, bpl=bpl, isa_sample=isa_sample, text=text, isa=isa, orig=orig,
+                contigs=contigs, size=len(raw), end=off + contig_bytes)
 
 
 def decode_bwt(idx):
