@@ -263,12 +263,15 @@ def _serve_points(servers: dict, make_request, n_burst: int, seconds: float, loa
             t = servers[k].submit(x, y, copy=False)
         return t
 
-    for _ in range(6):                    # warm every worker's staging and result buffers
-        k, x, y = make_request()
-        drain(k, submit(k, x, y))
+    # warm-up: a burst of the same shape, so that every worker's pinned staging and result buffers
+    # have grown to full batches before anything is timed
+    warm = [make_request() for _ in range(max(8, n_burst // 2))]
+    for k, t in [(k, submit(k, x, y)) for k, x, y in warm]:
+        drain(k, t)
     burst = [make_request() for _ in range(n_burst)]
     t0 = time.perf_counter()
     ts = [(k, submit(k, x, y)) for k, x, y in burst]
+    submit_s = time.perf_counter() - t0
     for k, t in ts:
         drain(k, t)
     sat_s = time.perf_counter() - t0
@@ -318,7 +321,7 @@ def _serve_points(servers: dict, make_request, n_burst: int, seconds: float, loa
         pt["mean_batch_reads"] = round(float(np.mean(list(bids.values()))), 1) if bids else 0.0
         points.append(pt)
     return dict(saturation_reads_per_s=round(sat, 1), saturation_burst=dict(requests=n_burst, reads=int(sum(
-        len(y) for _, _, y in burst)), seconds=round(sat_s, 3)), loads=points)
+        len(y) for _, _, y in burst)), seconds=round(sat_s, 3), submit_seconds=round(submit_s, 3)), loads=points)
 
 
 def serve_leg(mbw, idx, reads, seconds: float, sched: dict, workers: int, max_batch: int, n_burst: int,
@@ -426,7 +429,7 @@ def main():
     ap.add_argument("--bs-workers", type=int, default=3, help="bisulfite serving: workers of the bisulfite server")
     ap.add_argument("--bs-plain-workers", type=int, default=1, help="bisulfite serving: workers of the plain server")
     ap.add_argument("--serve-max-batch", type=int, default=1_000_000, help="serving leg: reads per batch at most")
-    ap.add_argument("--serve-burst", type=int, default=4000,
+    ap.add_argument("--serve-burst", type=int, default=12000,
                     help="requests in the closed-loop saturation burst (about 2,000 reads each)")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="seconds of open-loop arrivals per load point (0 = skip the serving legs)")

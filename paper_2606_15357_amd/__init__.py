@@ -666,8 +666,8 @@ class Server:
     holds a fixed device arena (``device_bytes`` for all of them together; 0 = sized for a full
     batch); requests that can never fit one are refused with MBW_E_CAPACITY."""
 
-    def __init__(self, index: Index, n_workers: int = 2, max_batch_reads: int = 1 << 20,
-                 max_batch_bases: int = 1 << 28, max_queued_bases: int = 1 << 32, min_seed_len: int = 19,
+    def __init__(self, index: Index, n_workers: int = 2, max_batch_reads: int = 1 << 18,
+                 max_batch_bases: int = 1 << 26, max_queued_bases: int = 1 << 32, min_seed_len: int = 19,
                  max_occ: int = 500, device_bytes: int = 0, **opts):
         self._lib = load_library()
         self.index = index

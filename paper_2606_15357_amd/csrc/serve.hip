@@ -46,10 +46,12 @@ namespace {
 struct Pinned {
   void *p = nullptr;
   size_t bytes = 0;
-  int ensure(size_t want) {
+  // grow to at least `want` bytes (to twice that unless exact: a buffer sized once for its largest
+  // use need not leave room)
+  int ensure(size_t want, bool exact = false) {
     if (want <= bytes) return 0;
     if (p) { (void)hipHostFree(p); p = nullptr; bytes = 0; }
-    const size_t b = 2 * want + 4096;
+    const size_t b = exact ? want : 2 * want + 4096;
     if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) { p = nullptr; return MBW_E_NOMEM; }
     bytes = b;
     return 0;
@@ -140,50 +142,58 @@ struct Request {
 // requests in one device batch at most (sizes the per-batch split arrays)
 constexpr uint32_t kMaxBatchRequests = 1u << 16;
 
-// a worker's fixed device memory
+// a worker's fixed device memory: one work space and two result slots (a batch's results are
+// downloaded from one slot while the next batch seeds into the other)
+struct ResultSlot {
+  mbw_seed_t *seeds = nullptr;
+  uint64_t *pos = nullptr;
+  mbw_piece_t *pieces = nullptr;
+  uint32_t *rstart = nullptr;     // per-batch split arrays (kMaxBatchRequests + 1 each)
+  SplitBound *bounds = nullptr;
+};
+
 struct Arena {
   void *base = nullptr;
   uint64_t bytes = 0;
   void *ws = nullptr;
   uint64_t ws_bytes = 0;
-  mbw_seed_t *seeds = nullptr;
-  uint64_t seeds_cap = 0;
-  uint64_t *pos = nullptr;
-  uint64_t pos_cap = 0;
-  mbw_piece_t *pieces = nullptr;
-  uint64_t pieces_cap = 0;
-  uint32_t *rstart = nullptr;     // per-batch split arrays (kMaxBatchRequests + 1 each)
-  SplitBound *bounds = nullptr;
+  uint64_t seeds_cap = 0, pos_cap = 0, pieces_cap = 0;   // records per slot
+  ResultSlot slot[2];
 };
 
 static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 
+static uint64_t slot_bytes(const Arena &a) {
+  return align256(a.seeds_cap * sizeof(mbw_seed_t)) + align256(a.pos_cap * sizeof(uint64_t)) +
+         align256(a.pieces_cap * sizeof(mbw_piece_t)) + align256((kMaxBatchRequests + 1) * sizeof(uint32_t)) +
+         align256((kMaxBatchRequests + 1) * sizeof(SplitBound));
+}
+
 // Carve an arena of `bytes` (0 = the size the model gives for a full batch of max_reads reads and
-// max_bases bases) into work space and result buffers, in the proportions of that model.
+// max_bases bases) into work space and two result slots, in the proportions of that model.
 static int plan_arena(const mbw_ctx *c, const mbw_serve_cfg &cfg, uint64_t bytes, Arena &a) {
   const uint64_t R = cfg.max_batch_reads, B = cfg.max_batch_bases;
-  const uint64_t fixed = align256((kMaxBatchRequests + 1) * sizeof(uint32_t)) +
-                         align256((kMaxBatchRequests + 1) * sizeof(SplitBound));
+  const uint64_t fixed = 2 * (align256((kMaxBatchRequests + 1) * sizeof(uint32_t)) +
+                              align256((kMaxBatchRequests + 1) * sizeof(SplitBound))) + 8 * 256;
   const MbwSizeModel sm = mbw_size_model(c, R, B, true, &cfg.opts);
   const double m_ws = (double)sm.ws;
   const double m_seeds = (double)(sm.seeds + 4096) * sizeof(mbw_seed_t);
   const double m_pos = (double)(sm.pos + 4096) * sizeof(uint64_t);
   const double m_pieces = cfg.opts.bs_refine ? (double)(sm.pieces + 4096) * sizeof(mbw_piece_t) : 0.0;
-  const double model = m_ws + m_seeds + m_pos + m_pieces;
-  if (bytes == 0) bytes = align256((uint64_t)model) + 4 * 256 + fixed;
+  const double model = m_ws + 2 * (m_seeds + m_pos + m_pieces);
+  if (bytes == 0) bytes = align256((uint64_t)model) + fixed;
   // the smallest arena admits one read of the longest length
   const MbwSizeModel one = mbw_size_model(c, 1, MBW_MAX_READ, true, &cfg.opts);
   double lf = ((double)one.ws + 256) / m_ws;
   lf = std::max(lf, (double)(one.seeds + 1) * sizeof(mbw_seed_t) / m_seeds);
   lf = std::max(lf, (double)(one.pos + 1) * sizeof(uint64_t) / m_pos);
   if (m_pieces > 0) lf = std::max(lf, (double)(one.pieces + 1) * sizeof(mbw_piece_t) / m_pieces);
-  const uint64_t least = (uint64_t)(lf * model) + 4 * 256 + fixed + 4096;
+  const uint64_t least = (uint64_t)(lf * model) + fixed + 4096;
   if (bytes < least) {
     mbw_set_error("serve device_bytes too small: each worker needs at least " + std::to_string(least) + " bytes");
     return MBW_E_INVAL;
   }
-  const double f = (double)(bytes - fixed - 4 * 256) / model;
-  a.bytes = bytes;
+  const double f = (double)(bytes - fixed) / model;
   a.ws_bytes = align256((uint64_t)(m_ws * f)) - 256;
   a.seeds_cap = (uint64_t)(m_seeds * f) / sizeof(mbw_seed_t);
   a.pos_cap = (uint64_t)(m_pos * f) / sizeof(uint64_t);
@@ -192,10 +202,7 @@ static int plan_arena(const mbw_ctx *c, const mbw_serve_cfg &cfg, uint64_t bytes
 }
 
 static int alloc_arena(Arena &a) {
-  const uint64_t extra = align256((kMaxBatchRequests + 1) * sizeof(uint32_t)) +
-                         align256((kMaxBatchRequests + 1) * sizeof(SplitBound));
-  const uint64_t want = align256(a.ws_bytes) + align256(a.seeds_cap * sizeof(mbw_seed_t)) +
-                        align256(a.pos_cap * sizeof(uint64_t)) + align256(a.pieces_cap * sizeof(mbw_piece_t)) + extra;
+  const uint64_t want = align256(a.ws_bytes) + 2 * slot_bytes(a);
   if (const unsigned long long lim = g_mbw_mem_limit.load(std::memory_order_relaxed)) {
     if (want > lim) {
       mbw_set_error("serve arena of " + std::to_string(want) + " bytes over the debug cap (" + std::to_string(lim) +
@@ -211,11 +218,13 @@ static int alloc_arena(Arena &a) {
   }
   uint8_t *p = (uint8_t *)a.base;
   a.ws = p; p += align256(a.ws_bytes);
-  a.seeds = (mbw_seed_t *)p; p += align256(a.seeds_cap * sizeof(mbw_seed_t));
-  a.pos = (uint64_t *)p; p += align256(a.pos_cap * sizeof(uint64_t));
-  a.pieces = a.pieces_cap ? (mbw_piece_t *)p : nullptr; p += align256(a.pieces_cap * sizeof(mbw_piece_t));
-  a.rstart = (uint32_t *)p; p += align256((kMaxBatchRequests + 1) * sizeof(uint32_t));
-  a.bounds = (SplitBound *)p;
+  for (ResultSlot &r : a.slot) {
+    r.seeds = (mbw_seed_t *)p; p += align256(a.seeds_cap * sizeof(mbw_seed_t));
+    r.pos = (uint64_t *)p; p += align256(a.pos_cap * sizeof(uint64_t));
+    r.pieces = a.pieces_cap ? (mbw_piece_t *)p : nullptr; p += align256(a.pieces_cap * sizeof(mbw_piece_t));
+    r.rstart = (uint32_t *)p; p += align256((kMaxBatchRequests + 1) * sizeof(uint32_t));
+    r.bounds = (SplitBound *)p; p += align256((kMaxBatchRequests + 1) * sizeof(SplitBound));
+  }
   a.bytes = want;
   return MBW_OK;
 }
@@ -257,23 +266,32 @@ struct mbw_server {
 
 namespace {
 
-// A worker: its context, stream, arena and pinned staging.
-struct Worker {
-  mbw_server *s = nullptr;
-  mbw_ctx *ctx = nullptr;
-  hipStream_t st = nullptr;
-  hipEvent_t ev = nullptr;
-  Arena a;
-  Pinned stage[2], lens[2], hreq, hbnd;
-};
-
 // a batch whose results are on their way to the host
 struct InFlight {
   std::vector<Request *> reqs;
   BatchBuf *bb = nullptr;
+  int slot = 0;
   uint64_t bid = 0, nreads = 0;
-  double tb0 = 0, tb1 = 0, tb2 = 0;
+  double tb0 = 0, tb1 = 0;
   float ms_device = 0;
+};
+
+// A worker: its context, compute stream, copy stream, arena and pinned staging.  Its finisher
+// thread completes the batches whose downloads it queues, so the worker seeds the next batch into
+// the other result slot meanwhile.
+struct Worker {
+  mbw_server *s = nullptr;
+  mbw_ctx *ctx = nullptr;
+  hipStream_t st = nullptr, cs = nullptr;
+  hipEvent_t ev_split[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr};
+  Arena a;
+  Pinned stage[2], lens[2], hreq, hbnd[2];
+  std::mutex fmu;
+  std::condition_variable fcv;
+  std::deque<InFlight> fq;         // batches downloading, in order
+  bool busy[2] = {false, false};   // result slot in use until its batch is completed
+  bool fstop = false;
+  std::thread finisher;
 };
 
 // Take queued requests for one batch (mu held): in arrival order while the batch's estimated work
@@ -301,7 +319,8 @@ static std::vector<Request *> take_batch(mbw_server *s) {
   return batch;
 }
 
-// Concatenate a batch's reads and lengths into pinned staging slot k.
+// Concatenate a batch's reads and lengths into pinned staging slot k.  A large batch is copied by
+// several threads (one thread's memcpy reaches about a third of the host's memory bandwidth).
 static int stage_batch(Worker &w, int k, const std::vector<Request *> &batch) {
   uint64_t nreads = 0, nbases = 0;
   for (Request *r : batch) { nreads += r->n_reads; nbases += r->bases; }
@@ -310,31 +329,74 @@ static int stage_batch(Worker &w, int k, const std::vector<Request *> &batch) {
   if (rc) { mbw_set_error("pinned staging allocation failed"); return rc; }
   uint8_t *rb = (uint8_t *)w.stage[k].p;
   uint32_t *lb = (uint32_t *)w.lens[k].p;
-  uint64_t ob = 0, orr = 0;
-  for (Request *r : batch) {
-    if (r->bases) memcpy(rb + ob, r->reads, r->bases);
-    if (r->n_reads) memcpy(lb + orr, r->lengths, r->n_reads * sizeof(uint32_t));
-    ob += r->bases;
-    orr += r->n_reads;
+  std::vector<uint64_t> ob(batch.size() + 1), orr(batch.size() + 1);
+  for (size_t i = 0; i < batch.size(); ++i) {
+    ob[i + 1] = ob[i] + batch[i]->bases;
+    orr[i + 1] = orr[i] + batch[i]->n_reads;
   }
+  auto copy = [&](size_t i0, size_t i1) {
+    for (size_t i = i0; i < i1; ++i) {
+      const Request *r = batch[i];
+      if (r->bases) memcpy(rb + ob[i], r->reads, r->bases);
+      if (r->n_reads) memcpy(lb + orr[i], r->lengths, r->n_reads * sizeof(uint32_t));
+    }
+  };
+  const size_t nt = nbases >= (32ull << 20) ? std::min<size_t>(4, batch.size()) : 1;
+  if (nt <= 1) { copy(0, batch.size()); return MBW_OK; }
+  // split the requests into nt runs of about equal bytes
+  std::vector<size_t> cut(nt + 1, batch.size());
+  cut[0] = 0;
+  for (size_t t = 1, i = 0; t < nt; ++t) {
+    const uint64_t want = nbases * t / nt;
+    while (i < batch.size() && ob[i] < want) ++i;
+    cut[t] = std::max(i, cut[t - 1]);
+  }
+  std::vector<std::thread> th;
+  try {
+    for (size_t t = 1; t < nt; ++t) th.emplace_back(copy, cut[t], cut[t + 1]);
+  } catch (...) {                 // no thread to be had: copy on this one
+    for (auto &x : th) x.join();
+    copy(0, batch.size());
+    return MBW_OK;
+  }
+  copy(0, cut[1]);
+  for (auto &x : th) x.join();
   return MBW_OK;
 }
 
-static BatchBuf *get_buf(mbw_server *s) {
-  std::lock_guard<std::mutex> lk(s->mu);
-  if (s->free_bufs.empty()) return new BatchBuf();
-  BatchBuf *b = s->free_bufs.back();
-  s->free_bufs.pop_back();
+// A batch result buffer from the pool, or a new one sized for the largest result an arena can
+// hold (pinning memory is slow: a buffer is never grown once it is in use).
+static BatchBuf *get_buf(mbw_server *s, int *rc) {
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!s->free_bufs.empty()) {
+      BatchBuf *b = s->free_bufs.back();
+      s->free_bufs.pop_back();
+      *rc = MBW_OK;
+      return b;
+    }
+  }
+  BatchBuf *b = new (std::nothrow) BatchBuf();
+  *rc = b ? b->seeds.ensure((s->seeds_cap + 1) * sizeof(mbw_seed_t), true) : MBW_E_NOMEM;
+  if (!*rc) *rc = b->pos.ensure((s->pos_cap + 1) * sizeof(uint64_t), true);
+  if (!*rc && s->pieces_cap) *rc = b->pieces.ensure((s->pieces_cap + 1) * sizeof(mbw_piece_t), true);
+  if (*rc) {   // a partly allocated buffer never enters the pool
+    delete b;
+    mbw_set_error("pinned result allocation failed");
+    return nullptr;
+  }
   return b;
 }
 
 // Seed requests [i0, i1) of a staged batch (their reads start at staged byte rb0 and staged read
-// rr0), split the result per request on the device and start its download; on success `out`
-// describes the batch in flight (complete it with finish()).
-static int run_batch(Worker &w, int k, const std::vector<Request *> &batch, size_t i0, size_t i1, uint64_t rb0,
-                     uint64_t rr0, InFlight &out) {
+// rr0) into result slot `slot`, split the result per request on the device and start its download
+// on the copy stream; on success `out` describes the batch in flight.
+static int run_batch(Worker &w, int k, int slot, const std::vector<Request *> &batch, size_t i0, size_t i1,
+                     uint64_t rb0, uint64_t rr0, InFlight &out) {
   mbw_server *s = w.s;
+  const ResultSlot &rs_ = w.a.slot[slot];
   out.reqs.assign(batch.begin() + i0, batch.begin() + i1);
+  out.slot = slot;
   const uint32_t nreq = (uint32_t)out.reqs.size();
   uint64_t nreads = 0;
   for (Request *r : out.reqs) nreads += r->n_reads;
@@ -350,9 +412,9 @@ static int run_batch(Worker &w, int k, const std::vector<Request *> &batch, size
   mbw_seed_buffers ob;
   memset(&ob, 0, sizeof(ob));
   ob.workspace = w.a.ws; ob.workspace_bytes = w.a.ws_bytes;
-  ob.seeds = w.a.seeds; ob.seeds_cap = w.a.seeds_cap;
-  ob.pos = w.a.pos; ob.pos_cap = w.a.pos_cap;
-  ob.pieces = w.a.pieces; ob.pieces_cap = w.a.pieces_cap;
+  ob.seeds = rs_.seeds; ob.seeds_cap = w.a.seeds_cap;
+  ob.pos = rs_.pos; ob.pos_cap = w.a.pos_cap;
+  ob.pieces = rs_.pieces; ob.pieces_cap = w.a.pieces_cap;
   mbw_result res;
   memset(&res, 0, sizeof(res));
   int rc = mbw_seed_into(w.ctx, (const uint8_t *)w.stage[k].p + rb0, (const uint32_t *)w.lens[k].p + rr0, nreads,
@@ -360,49 +422,51 @@ static int run_batch(Worker &w, int k, const std::vector<Request *> &batch, size
   out.tb1 = s->now();
   out.ms_device = res.ms_total;
   if (rc) return rc;
-  // per-request split on the device, then one download of the batch and of the request bounds
+  BatchBuf *bb = get_buf(s, &rc);
+  out.bb = bb;
+  if (rc) return rc;
+  // per-request split on the device, then the download of the batch and of the request bounds
   uint32_t *rs = (uint32_t *)w.hreq.p;
   uint64_t r0 = 0;
   for (uint32_t i = 0; i < nreq; ++i) { rs[i] = (uint32_t)r0; r0 += out.reqs[i]->n_reads; }
   rs[nreq] = (uint32_t)r0;
-  BatchBuf *bb = get_buf(s);
-  out.bb = bb;
-  rc = bb->seeds.ensure((res.n_seeds + 1) * sizeof(mbw_seed_t));
-  if (!rc) rc = bb->pos.ensure((res.n_pos + 1) * sizeof(uint64_t));
-  if (!rc && res.n_pieces) rc = bb->pieces.ensure((res.n_pieces + 1) * sizeof(mbw_piece_t));
-  if (rc) { mbw_set_error("pinned result allocation failed"); return rc; }
   const unsigned gb = (unsigned)std::min<uint64_t>((nreq + 256) / 256, 1024);
   const unsigned gr = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((res.n_seeds + res.n_pieces + 255) / 256, 4096));
 #define SRV_TRY(x) do { if ((x) != hipSuccess) { mbw_set_error(std::string(#x) + ": " + hipGetErrorString(hipGetLastError())); return MBW_E_HIP; } } while (0)
-  SRV_TRY(hipMemcpyAsync(w.a.rstart, rs, (nreq + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, w.st));
-  k_split_bounds<<<gb, 256, 0, w.st>>>(res.seeds, res.n_seeds, res.n_pos, res.pieces, res.n_pieces, w.a.rstart, nreq,
-                                       w.a.bounds);
+  SRV_TRY(hipMemcpyAsync(rs_.rstart, rs, (nreq + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, w.st));
+  k_split_bounds<<<gb, 256, 0, w.st>>>(res.seeds, res.n_seeds, res.n_pos, res.pieces, res.n_pieces, rs_.rstart, nreq,
+                                       rs_.bounds);
   if (res.n_seeds + res.n_pieces)
     k_split_rebase<<<gr, 256, 0, w.st>>>((mbw_seed_t *)res.seeds, res.n_seeds, (mbw_piece_t *)res.pieces, res.n_pieces,
-                                         w.a.rstart, nreq, w.a.bounds);
+                                         rs_.rstart, nreq, rs_.bounds);
   SRV_TRY(hipGetLastError());
-  SRV_TRY(hipMemcpyAsync(w.hbnd.p, w.a.bounds, (nreq + 1) * sizeof(SplitBound), hipMemcpyDeviceToHost, w.st));
+  // hreq is rewritten by the next batch: the copy of it above must have been taken first
+  SRV_TRY(hipEventRecord(w.ev_split[slot], w.st));
+  SRV_TRY(hipStreamWaitEvent(w.cs, w.ev_split[slot], 0));
+  SRV_TRY(hipMemcpyAsync(w.hbnd[slot].p, rs_.bounds, (nreq + 1) * sizeof(SplitBound), hipMemcpyDeviceToHost, w.cs));
   if (res.n_seeds)
-    SRV_TRY(hipMemcpyAsync(bb->seeds.p, res.seeds, res.n_seeds * sizeof(mbw_seed_t), hipMemcpyDeviceToHost, w.st));
+    SRV_TRY(hipMemcpyAsync(bb->seeds.p, res.seeds, res.n_seeds * sizeof(mbw_seed_t), hipMemcpyDeviceToHost, w.cs));
   if (res.n_pos)
-    SRV_TRY(hipMemcpyAsync(bb->pos.p, res.pos, res.n_pos * sizeof(uint64_t), hipMemcpyDeviceToHost, w.st));
+    SRV_TRY(hipMemcpyAsync(bb->pos.p, res.pos, res.n_pos * sizeof(uint64_t), hipMemcpyDeviceToHost, w.cs));
   if (res.n_pieces)
-    SRV_TRY(hipMemcpyAsync(bb->pieces.p, res.pieces, res.n_pieces * sizeof(mbw_piece_t), hipMemcpyDeviceToHost, w.st));
-  SRV_TRY(hipEventRecord(w.ev, w.st));
+    SRV_TRY(hipMemcpyAsync(bb->pieces.p, res.pieces, res.n_pieces * sizeof(mbw_piece_t), hipMemcpyDeviceToHost, w.cs));
+  SRV_TRY(hipEventRecord(w.ev_done[slot], w.cs));
+  SRV_TRY(hipEventSynchronize(w.ev_split[slot]));
 #undef SRV_TRY
   return MBW_OK;
 }
 
-// Complete requests with an error (rc != 0) or with their slices of a downloaded batch.
+// Complete requests with an error (rc != 0) or with their slices of a downloaded batch (after its
+// download has finished).
 static void complete(Worker &w, InFlight &f, int rc) {
   mbw_server *s = w.s;
-  if (!rc && hipEventSynchronize(w.ev) != hipSuccess) {
+  if (!rc && hipEventSynchronize(w.ev_done[f.slot]) != hipSuccess) {
     mbw_set_error(std::string("hipEventSynchronize: ") + hipGetErrorString(hipGetLastError()));
     rc = MBW_E_HIP;
   }
   const double tb2 = s->now();
   if (!rc) {
-    const SplitBound *b = (const SplitBound *)w.hbnd.p;
+    const SplitBound *b = (const SplitBound *)w.hbnd[f.slot].p;
     for (size_t i = 0; i < f.reqs.size(); ++i) {
       Request *r = f.reqs[i];
       r->buf = f.bb; r->s0 = b[i].t0; r->ns = b[i + 1].t0 - b[i].t0; r->p0 = b[i].p0; r->np = b[i + 1].p0 - b[i].p0;
@@ -429,14 +493,67 @@ static void complete(Worker &w, InFlight &f, int rc) {
   s->done_cv.notify_all();
 }
 
-// Run requests [i0, i1) of a staged batch to completion; a shortfall of the arena (MBW_E_CAPACITY)
-// or an allocation failure splits them in two halves, each run again.
-static void run_split(Worker &w, int k, const std::vector<Request *> &batch, size_t i0, size_t i1, uint64_t rb0,
-                      uint64_t rr0) {
+// the finisher: completes downloaded batches in order and frees their result slots
+static void finisher_main(Worker *wp) {
+  Worker &w = *wp;
+  (void)hipSetDevice(w.s->cfg.device);
+  for (;;) {
+    InFlight f;
+    {
+      std::unique_lock<std::mutex> lk(w.fmu);
+      w.fcv.wait(lk, [&] { return w.fstop || !w.fq.empty(); });
+      if (w.fq.empty()) return;
+      f = std::move(w.fq.front());
+      w.fq.pop_front();
+    }
+    complete(w, f, MBW_OK);
+    {
+      std::lock_guard<std::mutex> lk(w.fmu);
+      w.busy[f.slot] = false;
+    }
+    w.fcv.notify_all();
+  }
+}
+
+// wait until result slot `slot` is free, and claim it
+static void claim_slot(Worker &w, int slot) {
+  std::unique_lock<std::mutex> lk(w.fmu);
+  w.fcv.wait(lk, [&] { return !w.busy[slot]; });
+  w.busy[slot] = true;
+}
+
+static void release_slot(Worker &w, int slot) {
+  {
+    std::lock_guard<std::mutex> lk(w.fmu);
+    w.busy[slot] = false;
+  }
+  w.fcv.notify_all();
+}
+
+static void hand_to_finisher(Worker &w, InFlight &&f) {
+  {
+    std::lock_guard<std::mutex> lk(w.fmu);
+    w.fq.push_back(std::move(f));
+  }
+  w.fcv.notify_all();
+}
+
+// Run requests [i0, i1) of a staged batch; a shortfall of the arena (MBW_E_CAPACITY) or an
+// allocation failure splits them in two halves, each run again.  `slot` alternates between the two
+// result slots over the runs of one worker.
+static void run_split(Worker &w, int k, int &slot, const std::vector<Request *> &batch, size_t i0, size_t i1,
+                      uint64_t rb0, uint64_t rr0) {
   InFlight f;
-  int rc = run_batch(w, k, batch, i0, i1, rb0, rr0, f);
+  claim_slot(w, slot);
+  int rc = run_batch(w, k, slot, batch, i0, i1, rb0, rr0, f);
+  if (!rc) {
+    hand_to_finisher(w, std::move(f));
+    slot ^= 1;
+    return;
+  }
+  release_slot(w, slot);
+  if (f.bb) { std::lock_guard<std::mutex> lk(w.s->mu); w.s->free_bufs.push_back(f.bb); f.bb = nullptr; }
   if ((rc == MBW_E_CAPACITY || rc == MBW_E_NOMEM) && i1 - i0 > 1) {
-    if (f.bb) { std::lock_guard<std::mutex> lk(w.s->mu); w.s->free_bufs.push_back(f.bb); }
     {
       std::lock_guard<std::mutex> lk(w.s->mu);
       w.s->st.split_retries++;
@@ -444,8 +561,8 @@ static void run_split(Worker &w, int k, const std::vector<Request *> &batch, siz
     const size_t mid = i0 + (i1 - i0) / 2;
     uint64_t rb = rb0, rr = rr0;
     for (size_t i = i0; i < mid; ++i) { rb += batch[i]->bases; rr += batch[i]->n_reads; }
-    run_split(w, k, batch, i0, mid, rb0, rr0);
-    run_split(w, k, batch, mid, i1, rb, rr);
+    run_split(w, k, slot, batch, i0, mid, rb0, rr0);
+    run_split(w, k, slot, batch, mid, i1, rb, rr);
     return;
   }
   complete(w, f, rc);
@@ -455,50 +572,31 @@ static void worker_main(Worker *wp) {
   Worker &w = *wp;
   mbw_server *s = w.s;
   (void)hipSetDevice(s->cfg.device);
-  InFlight prev;
-  bool have_prev = false;
-  int k = 0;
+  int k = 0, slot = 0;
   for (;;) {
     std::vector<Request *> batch;
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      if (!have_prev) s->work_cv.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+      s->work_cv.wait(lk, [&] { return s->stop || !s->queue.empty(); });
       batch = take_batch(s);
     }
-    if (batch.empty() && !have_prev) return;   // stopping with an empty queue
-    // stage the next batch while the previous one downloads, then finish the previous one
-    int rc = batch.empty() ? MBW_OK : stage_batch(w, k, batch);
-    if (have_prev) { complete(w, prev, MBW_OK); have_prev = false; }
-    if (batch.empty()) continue;
+    if (batch.empty()) break;   // stopping with an empty queue
+    const int rc = stage_batch(w, k, batch);
     if (rc) {
       InFlight f;
       f.reqs = batch;
       complete(w, f, rc);
       continue;
     }
-    InFlight f;
-    rc = run_batch(w, k, batch, 0, batch.size(), 0, 0, f);
-    if (!rc) {
-      prev = std::move(f);
-      have_prev = true;
-      k ^= 1;
-      continue;
-    }
-    if ((rc == MBW_E_CAPACITY || rc == MBW_E_NOMEM) && batch.size() > 1) {
-      if (f.bb) { std::lock_guard<std::mutex> lk(s->mu); s->free_bufs.push_back(f.bb); }
-      {
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->st.split_retries++;
-      }
-      const size_t mid = batch.size() / 2;
-      uint64_t rb = 0, rr = 0;
-      for (size_t i = 0; i < mid; ++i) { rb += batch[i]->bases; rr += batch[i]->n_reads; }
-      run_split(w, k, batch, 0, mid, 0, 0);
-      run_split(w, k, batch, mid, batch.size(), rb, rr);
-      continue;
-    }
-    complete(w, f, rc);
+    run_split(w, k, slot, batch, 0, batch.size(), 0, 0);
+    k ^= 1;
   }
+  {   // let the finisher drain and stop
+    std::lock_guard<std::mutex> lk(w.fmu);
+    w.fstop = true;
+  }
+  w.fcv.notify_all();
+  w.finisher.join();
 }
 
 }  // namespace
@@ -519,11 +617,18 @@ extern "C" int mbw_serve_open(const mbw_index *ix, const mbw_serve_cfg *cfg, mbw
   s->t0 = std::chrono::steady_clock::now();
   s->trace = getenv("MBW_SERVE_TRACE") && getenv("MBW_SERVE_TRACE")[0] == '1';
   std::vector<Worker *> ws;
+  auto destroy = [](Worker *w) {
+    if (w->a.base) (void)hipFree(w->a.base);
+    for (int k = 0; k < 2; ++k) {
+      if (w->ev_split[k]) (void)hipEventDestroy(w->ev_split[k]);
+      if (w->ev_done[k]) (void)hipEventDestroy(w->ev_done[k]);
+    }
+    if (w->st) (void)hipStreamDestroy(w->st);
+    if (w->cs) (void)hipStreamDestroy(w->cs);
+  };
   auto fail = [&](int r) {
     for (Worker *w : ws) {
-      if (w->a.base) (void)hipFree(w->a.base);
-      if (w->ev) (void)hipEventDestroy(w->ev);
-      if (w->st) (void)hipStreamDestroy(w->st);
+      destroy(w);
       if (w->ctx) mbw_ctx_free(w->ctx);
       delete w;
     }
@@ -539,10 +644,12 @@ extern "C" int mbw_serve_open(const mbw_index *ix, const mbw_serve_cfg *cfg, mbw
     int r = mbw_ctx_create(ix, &w->ctx);
     if (r) return fail(r);
     // non-blocking: the workers' streams never wait for work on the null stream
-    if (hipStreamCreateWithFlags(&w->st, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&w->ev, hipEventDisableTiming) != hipSuccess) {
-      mbw_set_error("hipStreamCreate / hipEventCreate failed"); return fail(MBW_E_HIP);
-    }
+    bool ok = hipStreamCreateWithFlags(&w->st, hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&w->cs, hipStreamNonBlocking) == hipSuccess;
+    for (int k = 0; k < 2 && ok; ++k)
+      ok = hipEventCreateWithFlags(&w->ev_split[k], hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&w->ev_done[k], hipEventDisableTiming) == hipSuccess;
+    if (!ok) { mbw_set_error("hipStreamCreate / hipEventCreate failed"); return fail(MBW_E_HIP); }
     if (i == 0) s->model_ctx = w->ctx;
     r = plan_arena(w->ctx, *cfg, per_worker, w->a);
     if (!r) r = alloc_arena(w->a);
@@ -558,8 +665,9 @@ extern "C" int mbw_serve_open(const mbw_index *ix, const mbw_serve_cfg *cfg, mbw
       if (w->stage[k].ensure(bb / 2 + 16) || w->lens[k].ensure(br * sizeof(uint32_t) / 2 + 16)) {
         mbw_set_error("pinned staging allocation failed"); return fail(MBW_E_NOMEM);
       }
-    if (w->hreq.ensure((kMaxBatchRequests + 1) * sizeof(uint32_t) / 2 + 16) ||
-        w->hbnd.ensure((kMaxBatchRequests + 1) * sizeof(SplitBound) / 2 + 16)) {
+    if (w->hreq.ensure((kMaxBatchRequests + 1) * sizeof(uint32_t), true) ||
+        w->hbnd[0].ensure((kMaxBatchRequests + 1) * sizeof(SplitBound), true) ||
+        w->hbnd[1].ensure((kMaxBatchRequests + 1) * sizeof(SplitBound), true)) {
       mbw_set_error("pinned staging allocation failed"); return fail(MBW_E_NOMEM);
     }
   }
@@ -569,18 +677,49 @@ extern "C" int mbw_serve_open(const mbw_index *ix, const mbw_serve_cfg *cfg, mbw
   s->st.seeds_cap = ws[0]->a.seeds_cap;
   s->st.pos_cap = ws[0]->a.pos_cap;
   s->st.pieces_cap = ws[0]->a.pieces_cap;
-  for (Worker *w : ws)
-    s->workers.emplace_back([w] {
-      worker_main(w);
-      (void)hipSetDevice(w->s->cfg.device);
-      (void)hipStreamSynchronize(w->st);
-      if (w->a.base) (void)hipFree(w->a.base);
-      (void)hipEventDestroy(w->ev);
-      (void)hipStreamDestroy(w->st);
-      if (w->ctx != w->s->model_ctx) mbw_ctx_free(w->ctx);
-      else w->ctx = nullptr;   // freed by mbw_serve_close after every worker has ended
-      delete w;
-    });
+  size_t started = 0;
+  try {
+    for (; started < ws.size(); ++started) {
+      Worker *w = ws[started];
+      w->finisher = std::thread(finisher_main, w);
+      try {
+        s->workers.emplace_back([w, destroy] {
+          worker_main(w);   // returns once its finisher has completed every batch
+          (void)hipSetDevice(w->s->cfg.device);
+          (void)hipStreamSynchronize(w->st);
+          (void)hipStreamSynchronize(w->cs);
+          destroy(w);
+          if (w->ctx != w->s->model_ctx) mbw_ctx_free(w->ctx);
+          else w->ctx = nullptr;   // freed by mbw_serve_close after every worker has ended
+          delete w;
+        });
+      } catch (...) {   // no worker thread: stop this worker's finisher
+        {
+          std::lock_guard<std::mutex> lk(w->fmu);
+          w->fstop = true;
+        }
+        w->fcv.notify_all();
+        w->finisher.join();
+        throw;
+      }
+    }
+  } catch (...) {   // out of threads: stop what started (its workers free themselves), free the rest
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->stop = true;
+    }
+    s->work_cv.notify_all();
+    for (auto &t : s->workers) t.join();
+    for (size_t i = s->workers.size(); i < ws.size(); ++i) {
+      destroy(ws[i]);
+      if (ws[i]->ctx && ws[i]->ctx != s->model_ctx) mbw_ctx_free(ws[i]->ctx);
+      delete ws[i];
+    }
+    if (s->model_ctx) mbw_ctx_free(s->model_ctx);
+    delete s;
+    mbw_set_error("cannot start serve threads");
+    return MBW_E_NOMEM;
+  }
   *out = s;
   return MBW_OK;
 }
