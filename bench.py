@@ -339,10 +339,12 @@ def serve_leg(mbw, idx, reads, seconds: float, sched: dict, workers: int, max_ba
 
     cfg = dict(n_workers=workers, max_batch_reads=max_batch, max_batch_bases=max_batch * 160)
     srv = mbw.Server(idx, **cfg, **sched)
-    st0 = srv.stats()
-    res = _serve_points({"plain": srv}, request, n_burst, seconds)
-    st = srv.stats()
-    srv.close()
+    try:
+        st0 = srv.stats()
+        res = _serve_points({"plain": srv}, request, n_burst, seconds)
+        st = srv.stats()
+    finally:
+        srv.close()
     res.update(saturation_frac_of_bulk=round(res["saturation_reads_per_s"] / bulk_rate, 3), workers=workers,
                max_batch_reads=max_batch, device_gb=round(st0["device_bytes"] / 1e9, 2),
                split_retries=st["split_retries"], failed_requests=st["failed_requests"],
@@ -351,8 +353,10 @@ def serve_leg(mbw, idx, reads, seconds: float, sched: dict, workers: int, max_ba
     sched_plain = dict(sched)
     sched_plain["kernel"] = mbw.KERNEL_PLAIN
     srv = mbw.Server(idx, **cfg, **sched_plain)
-    pres = _serve_points({"plain": srv}, request, n_burst, seconds, loads=())
-    srv.close()
+    try:
+        pres = _serve_points({"plain": srv}, request, n_burst, seconds, loads=())
+    finally:
+        srv.close()
     res["plain_kernel"] = dict(saturation_reads_per_s=pres["saturation_reads_per_s"],
                                note="the same server and request stream with the plain (one read per lane) kernel")
     return res
@@ -381,14 +385,19 @@ def serve_bs_leg(mbw, synth, ref, pl_idx, args):
         return ("bisulfite" if bs else "plain_long", pool.seq[int(pool.offsets[r0]):int(pool.offsets[r0 + m])],
                 pool.lengths[r0:r0 + m])
 
-    srv = {"bisulfite": mbw.Server(bs_idx, n_workers=args.bs_workers, max_batch_reads=1_000_000,
-                                   max_batch_bases=160_000_000, bs_role=1, bs_refine=True),
-           "plain_long": mbw.Server(pl_idx, n_workers=args.bs_plain_workers, max_batch_reads=20_000,
-                                    max_batch_bases=100_000_000)}
-    res = _serve_points(srv, request, args.serve_burst, args.serve_seconds, seed=1)
-    dev = sum(s.stats()["device_bytes"] for s in srv.values())
-    for s in srv.values():
-        s.close()
+    srv = {}
+    try:
+        srv["bisulfite"] = mbw.Server(bs_idx, n_workers=args.bs_workers, max_batch_reads=1_000_000,
+                                      max_batch_bases=160_000_000, bs_role=1, bs_refine=True)
+        srv["plain_long"] = mbw.Server(pl_idx, n_workers=args.bs_plain_workers, max_batch_reads=20_000,
+                                       max_batch_bases=100_000_000)
+        res = _serve_points(srv, request, args.serve_burst, args.serve_seconds, seed=1)
+        dev = sum(s.stats()["device_bytes"] for s in srv.values())
+    finally:
+        for s in srv.values():
+            s.close()
+        if "res" not in locals():
+            bs_idx.free()
     res.update(metric="reads seeded/s served (bisulfite + plain), p50/p99 request latency", unit="reads/s",
                index_gb=dict(bisulfite=round(bs_idx.info()["bytes_resident"] / 1e9, 1),
                              plain=round(pl_idx.info()["bytes_resident"] / 1e9, 1)),
@@ -422,6 +431,8 @@ def main():
     ap.add_argument("--no-unique", action="store_true", help="extend unique matches base by base")
     ap.add_argument("--probe", action="store_true", help="only run the copy and random-gather probes")
     ap.add_argument("--no-tune", action="store_true", help="default schedule instead of the autotuned one")
+    ap.add_argument("--sched", default="", help="a fixed schedule as JSON (keyword arguments of Context.seed, e.g. "
+                                                "the autotuner's pick of an earlier run) instead of tuning")
     ap.add_argument("--no-rescue", action="store_true", help="skip the mate-rescue prefilter leg")
     ap.add_argument("--no-chain", action="store_true", help="skip the chaining leg")
     ap.add_argument("--no-latency", action="store_true", help="skip the small-batch latency leg")
@@ -489,7 +500,10 @@ def main():
     ctx = mbw.Context(idx)
     stream = torch.cuda.current_stream()
     sched = dict(unique_ext=not args.no_unique)
-    if not args.no_tune:
+    if args.sched:
+        sched = json.loads(args.sched)
+        log(f"fixed schedule: {sched}")
+    elif not args.no_tune:
         t0 = time.time()
         m = min(n_reads, 4_000_000)
         best = ctx.tune(dseq[: int(reads.offsets[m])], dlen[:m], stream=stream)

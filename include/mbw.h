@@ -96,6 +96,9 @@ int mbw_index_save(const mbw_index *idx, const char *path);
  * Errors: MBW_E_IO, MBW_E_FORMAT (magic, version, fields, sizes or checksum), MBW_E_NOMEM, MBW_E_HIP. */
 int mbw_index_load(const char *path, int device, mbw_index **out);
 
+/* Release the index.  Contexts and servers keep the index they were created on: an index freed
+ * while any of them is alive is released when the last of them is freed or closed (device memory
+ * is never freed under a kernel that reads it). */
 void mbw_index_free(mbw_index *idx);
 
 typedef struct {
@@ -137,7 +140,8 @@ int mbw_index_superblock_table(const mbw_index *idx, const void **sbtab);
 typedef struct mbw_ctx mbw_ctx;
 
 /* A context owns the device work space and result buffers for one stream of mbw_seed calls.
- * Contexts are not thread-safe; use one per host thread / stream.  The index must outlive it.
+ * Contexts are not thread-safe; use one per host thread / stream.  A context keeps its index alive
+ * until it is freed.
  * mbw_ctx_free waits for all work on the context's device (so it is safe after a call that failed
  * part way, and the caller's last stream need not exist any more), frees the work space on a
  * stream of the context's own and trims the device's memory pool. */
@@ -171,6 +175,9 @@ typedef struct {
                          (wave kernels; same results); 0 = 256, minimum 32 */
   int bs_refine;      /* bisulfite only (needs bs_role): refine every kept (seed, position) pair
                          as in Section 2.9 into mbw_result.pieces */
+  int wave_chunk;     /* reads (queries) a wave of the SMEM kernels takes from the work queue at a
+                         time (wave kernels; same results): 0 = automatic (as many as leave every
+                         wave of the grid about 8 takes, at most 256), else 1..256 */
 } mbw_seed_opts;
 
 
@@ -285,10 +292,11 @@ int mbw_result_download(mbw_ctx *ctx, const mbw_result *res, mbw_seed_t *seeds, 
 int mbw_result_download_pieces(mbw_ctx *ctx, const mbw_result *res, mbw_piece_t *pieces);
 
 /* Autotuner for the wave kernels: runs mbw_seed on this batch with candidate schedules (length
- * binning on or off, segment lengths 128/256/1024, persistent blocks per CU sized by the work, at
- * the occupancy limit or 2, unique-match extension on or off), each once untimed and once timed,
- * and writes the fastest to *best (other fields copied from *base, or the defaults when base is NULL) and its
- * device time to *best_ms.  Every candidate yields the same seeds.  Blocking; uses ctx's buffers
+ * binning on or off, segment lengths 128/256/1024, persistent blocks per CU, i.e. the waves each
+ * CU keeps in flight, sized by the work, at the occupancy limit or 2, unique-match extension on or
+ * off), each once untimed and once timed, then with the best of those the reads a wave takes from
+ * the work queue at a time (16, 64, 256 against automatic), and writes the fastest to *best (other
+ * fields copied from *base, or the defaults when base is NULL) and its device time to *best_ms.  Every candidate yields the same seeds.  Blocking; uses ctx's buffers
  * (its last result is overwritten).  Errors: as mbw_seed. */
 int mbw_tune(mbw_ctx *ctx, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads, int min_seed_len,
              int max_occ, const mbw_seed_opts *base, void *stream, mbw_seed_opts *best, float *best_ms);
@@ -478,7 +486,7 @@ typedef struct {
   uint64_t seeds_cap, pos_cap, pieces_cap;   /* one worker's result buffers (records) */
 } mbw_serve_stats_t;
 
-/* Start the workers and allocate their arenas.  The index must outlive the server.  Errors:
+/* Start the workers and allocate their arenas.  The server keeps the index alive until it closes.  Errors:
  * MBW_E_INVAL (configuration, device_bytes below the minimum), MBW_E_NOMEM (arena or pinned
  * staging allocation, or an arena over the debug cap), MBW_E_HIP. */
 int mbw_serve_open(const mbw_index *idx, const mbw_serve_cfg *cfg, mbw_server **out);

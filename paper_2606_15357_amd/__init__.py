@@ -9,7 +9,9 @@ handed to the library) and ``stream`` may be a ``torch.cuda.Stream``.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import weakref
 import hashlib
 import json
 import os
@@ -64,7 +66,8 @@ class IndexInfo(C.Structure):
 class SeedOpts(C.Structure):
     _fields_ = [("min_occ", C.c_int), ("reseed", C.c_int), ("reseed_len", C.c_int), ("reseed_occ", C.c_int),
                 ("bs_role", C.c_int), ("kernel", C.c_int), ("use_kmer", C.c_int), ("blocks_per_cu", C.c_int),
-                ("no_stage", C.c_int), ("unique_ext", C.c_int), ("seg_len", C.c_int), ("bs_refine", C.c_int)]
+                ("no_stage", C.c_int), ("unique_ext", C.c_int), ("seg_len", C.c_int), ("bs_refine", C.c_int),
+                ("wave_chunk", C.c_int)]
 
 
 class ServeCfg(C.Structure):
@@ -435,7 +438,8 @@ class Context:
     def seed(self, reads, lengths, min_seed_len: int = 19, max_occ: int = 500, min_occ: int = 1,
              reseed: bool = True, reseed_len: int = 38, reseed_occ: int = 10, bs_role: int = 0,
              kernel: int = KERNEL_COOP, use_kmer: bool = True, blocks_per_cu: int = 0, stage: bool = True,
-             unique_ext: bool = True, seg_len: int = 0, bs_refine: bool = False, stream=None) -> SeedOutput:
+             unique_ext: bool = True, seg_len: int = 0, bs_refine: bool = False, wave_chunk: int = 0,
+             stream=None) -> SeedOutput:
         """``reads``: concatenated ASCII (numpy uint8 on the host or a torch uint8 CUDA tensor);
         ``lengths``: uint32 per read (numpy or torch)."""
         n = int(lengths.numel() if hasattr(lengths, "numel") else len(lengths))
@@ -445,7 +449,7 @@ class Context:
             reads = np.ascontiguousarray(reads, dtype=np.uint8)
         o = SeedOpts(int(min_occ), int(bool(reseed)), int(reseed_len), int(reseed_occ), int(bs_role), int(kernel),
                      int(bool(use_kmer)), int(blocks_per_cu), int(not stage), int(bool(unique_ext)), int(seg_len),
-                     int(bool(bs_refine)))
+                     int(bool(bs_refine)), int(wave_chunk))
         res = Result()
         rp = _ptr(reads) if n else None
         lp = _ptr(lengths) if n else None
@@ -504,7 +508,7 @@ class Context:
                         int(kw.get("reseed_occ", 10)), int(kw.get("bs_role", 0)), int(kw.get("kernel", KERNEL_COOP)),
                         int(bool(kw.get("use_kmer", True))), int(kw.get("blocks_per_cu", 0)),
                         int(not kw.get("stage", True)), int(bool(kw.get("unique_ext", True))), int(kw.get("seg_len", 0)),
-                        int(bool(kw.get("bs_refine", False))))
+                        int(bool(kw.get("bs_refine", False))), int(kw.get("wave_chunk", 0)))
 
     def rescue(self, reads, lengths, cands, q: int = 7, min_hits: int = 10, bs_role: int = 0,
                stream=None) -> RescueOutput:
@@ -564,7 +568,7 @@ class Context:
                                   int(min_seed_len), int(max_occ), C.byref(b), _stream_handle(stream), C.byref(best),
                                   C.byref(ms)))
         res = dict(stage=not best.no_stage, seg_len=best.seg_len, blocks_per_cu=best.blocks_per_cu,
-                   unique_ext=bool(best.unique_ext), ms=ms.value)
+                   unique_ext=bool(best.unique_ext), wave_chunk=best.wave_chunk, ms=ms.value)
         if cache:
             stored = _read_json(cache)
             stored[key] = res
@@ -660,6 +664,20 @@ def _view(ptr, n: int, dtype: np.dtype) -> np.ndarray:
     return np.frombuffer((C.c_char * (int(n) * dtype.itemsize)).from_address(ptr), dtype=dtype)
 
 
+_live_servers = weakref.WeakSet()
+
+
+@atexit.register
+def _close_servers():
+    """Servers still open when the interpreter exits are closed first (their workers finish the
+    queued requests), so that no worker thread is left running while the process tears down."""
+    for srv in list(_live_servers):
+        try:
+            srv.close()
+        except Exception:
+            pass
+
+
 class Server:
     """Request loop over a resident index (``mbw_serve_*``): submit reads, wait for each
     request's seeds and positions; batches of several requests overlap on the device.  Each worker
@@ -675,13 +693,14 @@ class Server:
                      int(opts.get("reseed_occ", 10)), int(opts.get("bs_role", 0)), int(opts.get("kernel", KERNEL_COOP)),
                      int(bool(opts.get("use_kmer", True))), int(opts.get("blocks_per_cu", 0)),
                      int(not opts.get("stage", True)), int(bool(opts.get("unique_ext", True))), int(opts.get("seg_len", 0)),
-                     int(bool(opts.get("bs_refine", False))))
+                     int(bool(opts.get("bs_refine", False))), int(opts.get("wave_chunk", 0)))
         cfg = ServeCfg(int(n_workers), int(max_batch_reads), int(max_batch_bases), int(max_queued_bases),
                        int(min_seed_len), int(max_occ), o, int(index.info()["device"]), int(device_bytes))
         self._held = {}   # ticket -> arrays of a request submitted without a copy
         h = C.c_void_p()
         _check(self._lib.mbw_serve_open(index._h, C.byref(cfg), C.byref(h)))
         self._h = h
+        _live_servers.add(self)
 
     def submit(self, reads: np.ndarray, lengths: np.ndarray, copy: bool = True):
         """Queue a request; returns its ticket, or None when the queue is full (MBW_E_BUSY).

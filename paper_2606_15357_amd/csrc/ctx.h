@@ -100,6 +100,7 @@ static inline int grow(mbw_ctx *c, mbw_ctx::Buf &b, size_t bytes) {
   hipError_t e = hipMallocAsync(&b.p, want, c->cur);
   if (e != hipSuccess) {
     b.p = nullptr;
+    (void)hipGetLastError();   // the failure is reported here: later launch checks must not see it
     mbw_set_error(std::string("hipMalloc(") + std::to_string(want) + "): " + hipGetErrorString(e));
     return MBW_E_NOMEM;
   }

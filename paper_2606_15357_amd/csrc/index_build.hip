@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -495,8 +496,9 @@ extern "C" const char *mbw_strerror(int code) {
   }
 }
 
-extern "C" void mbw_index_free(mbw_index *ix) {
-  if (!ix) return;
+static std::mutex g_index_mu;   // guards users / free_pending of every index
+
+static void index_destroy(mbw_index *ix) {
   int cur = 0;
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(ix->device);
@@ -510,6 +512,30 @@ extern "C" void mbw_index_free(mbw_index *ix) {
   delete ix->contigs;
   (void)hipSetDevice(cur);
   delete ix;
+}
+
+void mbw_index_retain(const mbw_index *ix) {
+  std::lock_guard<std::mutex> lk(g_index_mu);
+  ++const_cast<mbw_index *>(ix)->users;
+}
+
+void mbw_index_release(const mbw_index *ix) {
+  mbw_index *m = const_cast<mbw_index *>(ix);
+  bool last = false;
+  {
+    std::lock_guard<std::mutex> lk(g_index_mu);
+    last = --m->users == 0 && m->free_pending;
+  }
+  if (last) index_destroy(m);
+}
+
+extern "C" void mbw_index_free(mbw_index *ix) {
+  if (!ix) return;
+  {
+    std::lock_guard<std::mutex> lk(g_index_mu);
+    if (ix->users > 0) { ix->free_pending = true; return; }
+  }
+  index_destroy(ix);
 }
 
 static int build_kmer_table(mbw_index *ix, hipStream_t st) {

@@ -54,7 +54,14 @@ struct mbw_index {
   uint64_t *orig;
   uint64_t bytes;
   struct mbw_contigs *contigs; // host: the reference's records (names, start and length in R)
+  int users;                   // contexts and servers using the index (mbw_index_retain)
+  bool free_pending;           // mbw_index_free came while it was in use: freed by the last release
 };
+
+// An index stays allocated while contexts or servers use it: they retain it when created and
+// release it when freed; mbw_index_free on an index in use defers the free to the last release.
+void mbw_index_retain(const mbw_index *ix);
+void mbw_index_release(const mbw_index *ix);
 
 // Read-only view passed by value to kernels.
 struct IndexView {

@@ -1193,9 +1193,10 @@ extern "C" int mbw_ctx_create(const mbw_index *ix, mbw_ctx **out) {
   TRY(hipSetDevice(ix->device));
   mbw_ctx *c = new mbw_ctx();
   c->ix = ix;
+  mbw_index_retain(ix);   // released by mbw_ctx_free, also on the failure paths below
   c->device = ix->device;
   hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, ix->device) != hipSuccess) { delete c; mbw_set_error("hipGetDeviceProperties failed"); return MBW_E_HIP; }
+  if (hipGetDeviceProperties(&prop, ix->device) != hipSuccess) { mbw_ctx_free(c); mbw_set_error("hipGetDeviceProperties failed"); return MBW_E_HIP; }
   c->n_cu = prop.multiProcessorCount;
   if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess) {
     c->own = nullptr; mbw_ctx_free(c); mbw_set_error("hipStreamCreate failed"); return MBW_E_HIP;
@@ -1244,7 +1245,9 @@ extern "C" void mbw_ctx_free(mbw_ctx *c) {
   for (int t = 0; t < 8; ++t) if (c->ev[t]) (void)hipEventDestroy(c->ev[t]);
   for (int t = 0; t < 2 * mbw_ctx::kLaunchSlots; ++t) if (c->lev[t]) (void)hipEventDestroy(c->lev[t]);
   if (c->hfetch) (void)hipHostFree(c->hfetch);
+  const mbw_index *ix = c->ix;
   delete c;
+  if (ix) mbw_index_release(ix);
 }
 
 // Persistent grid: blocks per CU as requested (> 0), the occupancy limit (< 0), or (0) sized by
@@ -1326,7 +1329,8 @@ static int run_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const ReadWor
   const int grid = o.kernel == MBW_KERNEL_PLAIN ? 0 : smem_grid(c, P, o, staged);
   // at least ~8 grabs per wave of the persistent grid, so that long queries (queued longest
   // first) spread over the whole chip
-  {
+  if (o.wave_chunk > 0) P.chunk = (uint32_t)std::min(WORK_CHUNK, o.wave_chunk);
+  else {
     const uint64_t waves = (uint64_t)std::max(grid, 1) * SMEM_WAVES;
     uint64_t ch = P.n_queries / (waves * 8);
     P.chunk = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(WORK_CHUNK, ch));
@@ -1473,6 +1477,7 @@ static int seed_impl(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, 
     o.min_occ = 1; o.reseed = 1; o.reseed_len = 38; o.reseed_occ = 10; o.use_kmer = 1; o.unique_ext = 1;
   }
   if (o.min_occ < 1) { mbw_set_error("min_occ must be >= 1"); return MBW_E_INVAL; }
+  if (o.wave_chunk < 0 || o.wave_chunk > WORK_CHUNK) { mbw_set_error("wave_chunk must be in [0,256]"); return MBW_E_INVAL; }
   if (o.bs_role && !c->ix->bisulfite) { mbw_set_error("bs_role needs a bisulfite index"); return MBW_E_INVAL; }
   if (o.bs_refine && (!o.bs_role || !c->ix->orig)) {
     mbw_set_error("bs_refine needs bs_role and a bisulfite index"); return MBW_E_INVAL;
@@ -2048,6 +2053,19 @@ extern "C" int mbw_tune(mbw_ctx *c, const uint8_t *reads, const uint32_t *length
           if (r) return r;
           if (!have || res.ms_total < bt) { bt = res.ms_total; *best = o; have = true; }
         }
+  // then the reads each wave takes from the work queue at a time, with the rest of the best schedule
+  const int chunk_opts[3] = {16, 64, 256};
+  const mbw_seed_opts grid_best = *best;
+  for (int ch = 0; ch < 3; ++ch) {
+    mbw_seed_opts o = grid_best;
+    o.wave_chunk = chunk_opts[ch];
+    mbw_result res;
+    int r = mbw_seed(c, reads, lengths, n_reads, min_seed_len, max_occ, &o, stream, &res);
+    if (r) return r;
+    r = mbw_seed(c, reads, lengths, n_reads, min_seed_len, max_occ, &o, stream, &res);
+    if (r) return r;
+    if (res.ms_total < bt) { bt = res.ms_total; *best = o; }
+  }
   *best_ms = bt;
   return MBW_OK;
 }

@@ -52,7 +52,11 @@ struct Pinned {
     if (want <= bytes) return 0;
     if (p) { (void)hipHostFree(p); p = nullptr; bytes = 0; }
     const size_t b = exact ? want : 2 * want + 4096;
-    if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) { p = nullptr; return MBW_E_NOMEM; }
+    if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();   // reported by the return code: later launch checks must not see it
+      p = nullptr;
+      return MBW_E_NOMEM;
+    }
     bytes = b;
     return 0;
   }
@@ -119,7 +123,10 @@ __global__ void k_split_rebase(mbw_seed_t *__restrict__ sd, uint64_t ns, mbw_pie
 struct BatchBuf {
   Pinned seeds, pos, pieces;
   int refs = 0;
+  size_t bytes() const { return seeds.bytes + pos.bytes + pieces.bytes; }
 };
+
+static void pool_put(mbw_server *s, BatchBuf *b);
 
 struct Request {
   uint64_t ticket = 0;
@@ -249,8 +256,8 @@ struct mbw_server {
   uint64_t ws_bytes = 0;          // every worker's work space and result buffers (records)
   uint64_t seeds_cap = 0, pos_cap = 0, pieces_cap = 0;
 
-  void unref(BatchBuf *b) {   // with mu held
-    if (b && --b->refs == 0) free_bufs.push_back(b);
+  void unref(BatchBuf *b) {   // with mu held: drop a request's reference to its batch result
+    if (b && --b->refs == 0) pool_put(this, b);
   }
 
   double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
@@ -364,28 +371,56 @@ static int stage_batch(Worker &w, int k, const std::vector<Request *> &batch) {
   return MBW_OK;
 }
 
-// A batch result buffer from the pool, or a new one sized for the largest result an arena can
-// hold (pinning memory is slow: a buffer is never grown once it is in use).
-static BatchBuf *get_buf(mbw_server *s, int *rc) {
+// A pinned buffer for a batch result of ns seeds, np positions and nc pieces: a pooled one that
+// holds it if there is one (the smallest such), else the largest pooled one grown to it (rounded up
+// to 64 MiB per array, so that few batches grow it again), else a new one.  Pinning host memory is
+// slow, so buffers are kept for reuse; the pool holds at most 2 per worker.
+static BatchBuf *get_buf(mbw_server *s, uint64_t ns, uint64_t np, uint64_t nc, int *rc) {
+  const size_t want_s = (ns + 1) * sizeof(mbw_seed_t), want_p = (np + 1) * sizeof(uint64_t),
+               want_c = nc ? (nc + 1) * sizeof(mbw_piece_t) : 0;
+  auto fits = [&](const BatchBuf *b) {
+    return b->seeds.bytes >= want_s && b->pos.bytes >= want_p && b->pieces.bytes >= want_c;
+  };
+  BatchBuf *b = nullptr;
   {
     std::lock_guard<std::mutex> lk(s->mu);
-    if (!s->free_bufs.empty()) {
-      BatchBuf *b = s->free_bufs.back();
-      s->free_bufs.pop_back();
-      *rc = MBW_OK;
-      return b;
+    size_t pick = s->free_bufs.size();
+    for (size_t i = 0; i < s->free_bufs.size(); ++i) {
+      const BatchBuf *x = s->free_bufs[i];
+      if (fits(x) ? (pick == s->free_bufs.size() || !fits(s->free_bufs[pick]) || x->bytes() < s->free_bufs[pick]->bytes())
+                  : (pick == s->free_bufs.size() || (!fits(s->free_bufs[pick]) && x->bytes() > s->free_bufs[pick]->bytes())))
+        pick = i;
+    }
+    if (pick < s->free_bufs.size()) {
+      b = s->free_bufs[pick];
+      s->free_bufs.erase(s->free_bufs.begin() + pick);
     }
   }
-  BatchBuf *b = new (std::nothrow) BatchBuf();
-  *rc = b ? b->seeds.ensure((s->seeds_cap + 1) * sizeof(mbw_seed_t), true) : MBW_E_NOMEM;
-  if (!*rc) *rc = b->pos.ensure((s->pos_cap + 1) * sizeof(uint64_t), true);
-  if (!*rc && s->pieces_cap) *rc = b->pieces.ensure((s->pieces_cap + 1) * sizeof(mbw_piece_t), true);
-  if (*rc) {   // a partly allocated buffer never enters the pool
+  if (!b) b = new (std::nothrow) BatchBuf();
+  if (!b) { mbw_set_error("host allocation failed"); *rc = MBW_E_NOMEM; return nullptr; }
+  const size_t g = 64ull << 20;
+  auto up = [&](size_t x) { return x ? (x + g - 1) / g * g : 0; };
+  *rc = b->seeds.ensure(up(want_s), true);
+  if (!*rc) *rc = b->pos.ensure(up(want_p), true);
+  if (!*rc && want_c) *rc = b->pieces.ensure(up(want_c), true);
+  if (*rc) {   // a buffer that could not grow is dropped, not pooled
     delete b;
     mbw_set_error("pinned result allocation failed");
     return nullptr;
   }
   return b;
+}
+
+// Return a buffer to the pool (mu held); beyond 2 per worker the smallest is freed.
+static void pool_put(mbw_server *s, BatchBuf *b) {
+  s->free_bufs.push_back(b);
+  if (s->free_bufs.size() > 2 * (size_t)s->cfg.n_workers) {
+    size_t m = 0;
+    for (size_t i = 1; i < s->free_bufs.size(); ++i)
+      if (s->free_bufs[i]->bytes() < s->free_bufs[m]->bytes()) m = i;
+    delete s->free_bufs[m];
+    s->free_bufs.erase(s->free_bufs.begin() + m);
+  }
 }
 
 // Seed requests [i0, i1) of a staged batch (their reads start at staged byte rb0 and staged read
@@ -422,7 +457,7 @@ static int run_batch(Worker &w, int k, int slot, const std::vector<Request *> &b
   out.tb1 = s->now();
   out.ms_device = res.ms_total;
   if (rc) return rc;
-  BatchBuf *bb = get_buf(s, &rc);
+  BatchBuf *bb = get_buf(s, res.n_seeds, res.n_pos, res.n_pieces, &rc);
   out.bb = bb;
   if (rc) return rc;
   // per-request split on the device, then the download of the batch and of the request bounds
@@ -478,7 +513,7 @@ static void complete(Worker &w, InFlight &f, int rc) {
     const double t = s->now();
     if (f.bb) {
       f.bb->refs = rc ? 0 : (int)f.reqs.size();
-      if (rc || f.reqs.empty()) s->free_bufs.push_back(f.bb);
+      if (rc || f.reqs.empty()) pool_put(s, f.bb);
     }
     const std::string msg = rc ? std::string(mbw_last_error()) : std::string();
     for (Request *r : f.reqs) {
@@ -552,7 +587,7 @@ static void run_split(Worker &w, int k, int &slot, const std::vector<Request *> 
     return;
   }
   release_slot(w, slot);
-  if (f.bb) { std::lock_guard<std::mutex> lk(w.s->mu); w.s->free_bufs.push_back(f.bb); f.bb = nullptr; }
+  if (f.bb) { std::lock_guard<std::mutex> lk(w.s->mu); pool_put(w.s, f.bb); f.bb = nullptr; }
   if ((rc == MBW_E_CAPACITY || rc == MBW_E_NOMEM) && i1 - i0 > 1) {
     {
       std::lock_guard<std::mutex> lk(w.s->mu);
@@ -613,6 +648,7 @@ extern "C" int mbw_serve_open(const mbw_index *ix, const mbw_serve_cfg *cfg, mbw
   if (hipSetDevice(cfg->device) != hipSuccess) { mbw_set_error("hipSetDevice failed"); return MBW_E_HIP; }
   mbw_server *s = new mbw_server();
   s->ix = ix;
+  mbw_index_retain(ix);   // released by mbw_serve_close (or below when the open fails)
   s->cfg = *cfg;
   s->t0 = std::chrono::steady_clock::now();
   s->trace = getenv("MBW_SERVE_TRACE") && getenv("MBW_SERVE_TRACE")[0] == '1';
@@ -632,6 +668,7 @@ extern "C" int mbw_serve_open(const mbw_index *ix, const mbw_serve_cfg *cfg, mbw
       if (w->ctx) mbw_ctx_free(w->ctx);
       delete w;
     }
+    mbw_index_release(ix);
     delete s;
     return r;
   };
@@ -716,6 +753,7 @@ extern "C" int mbw_serve_open(const mbw_index *ix, const mbw_serve_cfg *cfg, mbw
       delete ws[i];
     }
     if (s->model_ctx) mbw_ctx_free(s->model_ctx);
+    mbw_index_release(ix);
     delete s;
     mbw_set_error("cannot start serve threads");
     return MBW_E_NOMEM;
@@ -846,5 +884,7 @@ extern "C" void mbw_serve_close(mbw_server *s) {
   if (s->model_ctx) mbw_ctx_free(s->model_ctx);
   for (auto &kv : s->all) { s->unref(kv.second->buf); delete kv.second; }
   for (BatchBuf *b : s->free_bufs) delete b;
+  const mbw_index *ix = s->ix;
   delete s;
+  mbw_index_release(ix);
 }

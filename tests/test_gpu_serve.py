@@ -54,6 +54,7 @@ def test_tune_picks_a_valid_schedule(small):
     ctx = mbw.Context(idx)
     best = ctx.tune(reads.seq, reads.lengths)
     assert best["seg_len"] in (128, 256, 1024) and best["blocks_per_cu"] in (0, -1, 2) and best["ms"] > 0
+    assert best["wave_chunk"] in (0, 16, 64, 256)
     ms = best.pop("ms")
     assert best.pop("cached") is False
     out = ctx.seed(reads.seq, reads.lengths, **best)
