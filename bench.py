@@ -561,15 +561,21 @@ def main():
     smem_bytes = lines_smem * LINE_BYTES
     achieved = smem_bytes / (ms_smem * 1e-3) / 1e9
     traffic = traffic_from_profile("smem", smem_bytes / max(launches, 1))
+    loc_traffic = traffic_from_profile("locate", 0)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                     kernel="k_smem_wave<staged> (both SMEM rounds)", launches_per_step=launches,
                     avg_launch_ms=round(ms_smem / max(launches, 1), 3),
                     bytes_per_launch=round(smem_bytes / max(launches, 1)),
                     lines_per_read=round(lines_smem / n_reads, 1),
-                    locate=dict(achieved=round(lines_loc * LINE_BYTES / (ms_loc * 1e-3) / 1e9, 1),
-                                lines_per_read=round(lines_loc / n_reads, 1)),
-                    whole_path=round((lines_smem + lines_loc) * LINE_BYTES / (elapsed / args.steps) / 1e9, 1),
+                    locate=dict(line_accesses_per_read=round(lines_loc / n_reads, 1),
+                                line_access_gbs=round(lines_loc * LINE_BYTES / (ms_loc * 1e-3) / 1e9, 1),
+                                hbm_gbs=round(loc_traffic / (ms_loc * 1e-3) / 1e9, 1) if loc_traffic else None,
+                                note="line_access_gbs counts every 128-byte line access of the walks, L2 hits "
+                                     "included (neighbouring rows of one seed share lines), so it is not an HBM "
+                                     "rate; hbm_gbs is the counter-measured traffic over the kernel time"),
+                    whole_path_hbm_gbs=round((traffic * launches + loc_traffic) / (elapsed / args.steps) / 1e9, 1)
+                    if traffic and loc_traffic else None,
                     random_line_ceiling=dict(lines_per_s=round(gather_lps), gbs=round(gather_lps * LINE_BYTES / 1e9, 1),
                                              probe="one lane x 16 B per random 128-B line, 4 dependent chains per lane, 8 GiB buffer"),
                     frac_of_measured_ceiling=round(lines_smem / (ms_smem * 1e-3) / gather_lps, 3))
