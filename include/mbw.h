@@ -177,7 +177,9 @@ typedef struct {
                          as in Section 2.9 into mbw_result.pieces */
   int wave_chunk;     /* reads (queries) a wave of the SMEM kernels takes from the work queue at a
                          time (wave kernels; same results): 0 = automatic (as many as leave every
-                         wave of the grid about 8 takes, at most 256), else 1..256 */
+                         wave of the grid about 8 takes, at most 256), else 1..256 fixed (a fixed
+                         size leaves waves of the grid idle on a batch of fewer than that many reads
+                         per wave) */
 } mbw_seed_opts;
 
 
