@@ -25,7 +25,6 @@
 // anchor can reach min_score or displace the last kept chain (a chain never scores above f of its
 // end), so a read with many anchors does not pay for chains it cannot keep.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <cstring>
 
@@ -34,6 +33,7 @@
 
 #include "ctx.h"
 #include "mbw_internal.h"
+#include "prim.h"
 #include "../../include/mbw.h"
 
 #define TRY(call) MBW_HIP_TRY(call)
@@ -430,28 +430,28 @@ extern "C" int mbw_chain(mbw_ctx *c, const mbw_result *res, uint64_t n_reads, co
   const uint32_t *order = va;   // anchor indices in (read, x, y, w) order
   if (na > 1) {
     // (y, w), then (read, x): both stable, so the anchors end up in (read, x, y, w) order
-    hipcub::DoubleBuffer<uint32_t> kb2(k2a, k2b), vb2(va, vb);
-    r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceRadixSort::SortPairs(tp, tb, kb2, vb2, na, 0, 32, st); });
+    prim::dbuf<uint32_t> kb2(k2a, k2b), vb2(va, vb);
+    r = prim_call(c, [&](void *tp, size_t &tb) { return prim::sort_pairs(tp, tb, kb2, vb2, na, 0, 32, st); });
     if (r) return r;
-    k_ch_gather_k1<<<grid_for(na), 256, 0, st>>>(k1a, vb2.Current(), na, k1b);
+    k_ch_gather_k1<<<grid_for(na), 256, 0, st>>>(k1a, vb2.current(), na, k1b);
     TRY(hipGetLastError());
-    hipcub::DoubleBuffer<uint64_t> kb1(k1b, k1a);
-    hipcub::DoubleBuffer<uint32_t> vb1(vb2.Current(), vb2.Alternate());
-    r = cub_call(c, [&](void *tp, size_t &tb) {
-      return hipcub::DeviceRadixSort::SortPairs(tp, tb, kb1, vb1, na, 0, xb + rb, st);
+    prim::dbuf<uint64_t> kb1(k1b, k1a);
+    prim::dbuf<uint32_t> vb1(vb2.current(), vb2.alternate());
+    r = prim_call(c, [&](void *tp, size_t &tb) {
+      return prim::sort_pairs(tp, tb, kb1, vb1, na, 0, xb + rb, st);
     });
     if (r) return r;
-    order = vb1.Current();
+    order = vb1.current();
   }
   if (na) {
     k_ch_gather_anchors<<<grid_for(na), 256, 0, st>>>(A, order, na, As);   // one anchor: va[0] = 0 from the anchor kernel
     TRY(hipGetLastError());
   }
-  r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, cnt, aoff, n_reads + 1, st); });
+  r = prim_call(c, [&](void *tp, size_t &tb) { return prim::exclusive_sum(tp, tb, cnt, aoff, n_reads + 1, st); });
   if (r) return r;
   k_ch_slots<<<grid_for(n_reads + 1), 256, 0, st>>>(cnt, n_reads, (uint32_t)o.max_chains, slot);
   TRY(hipGetLastError());
-  r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, slot, cslot, n_reads + 1, st); });
+  r = prim_call(c, [&](void *tp, size_t &tb) { return prim::exclusive_sum(tp, tb, slot, cslot, n_reads + 1, st); });
   if (r) return r;
   {
     // the per-read ranges must tile the anchors exactly before the chaining kernel relies on them
@@ -492,9 +492,9 @@ extern "C" int mbw_chain(mbw_ctx *c, const mbw_result *res, uint64_t n_reads, co
     TRY(hipGetLastError());
   }
   TRY(hipEventRecord(c->ev[2], st));
-  r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, nch, choff, n_reads + 1, st); });
+  r = prim_call(c, [&](void *tp, size_t &tb) { return prim::exclusive_sum(tp, tb, nch, choff, n_reads + 1, st); });
   if (r) return r;
-  r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, nanc, anoff, n_reads + 1, st); });
+  r = prim_call(c, [&](void *tp, size_t &tb) { return prim::exclusive_sum(tp, tb, nanc, anoff, n_reads + 1, st); });
   if (r) return r;
   uint64_t h[5] = {0, 0, 0, 0, 0};
   TRY(hipMemcpyAsync(&h[3], ctl + CH_MAXN, 16, hipMemcpyDeviceToHost, st));

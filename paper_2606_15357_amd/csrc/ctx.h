@@ -146,7 +146,7 @@ static inline bool is_device_ptr(const void *p) {
   return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
 }
 
-// Make the temporary buffer large enough for f (a hipcub call of the size it captures) without
+// Make the temporary buffer large enough for f (a device-wide rocPRIM call of the size it captures) without
 // running it: a later call on fewer items then needs no larger buffer.
 template <class F>
 static int reserve_temp(mbw_ctx *c, F f) {
@@ -156,9 +156,9 @@ static int reserve_temp(mbw_ctx *c, F f) {
   return 0;
 }
 
-// run a hipcub device-wide algorithm with the context's temporary buffer
+// run a device-wide rocPRIM algorithm with the context's temporary buffer
 template <class F>
-static int cub_call(mbw_ctx *c, F f) {
+static int prim_call(mbw_ctx *c, F f) {
   size_t tb = 0;
   MBW_HIP_TRY(f((void *)nullptr, tb));
   GROW(c->temp, tb);

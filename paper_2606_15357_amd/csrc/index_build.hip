@@ -8,7 +8,6 @@
 // the next 21 symbols until every group is a single suffix.  $ is unique, so a key that reaches
 // the end of T is unique and needs no further refinement.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cstdio>
@@ -19,6 +18,7 @@
 #include <vector>
 
 #include "mbw_internal.h"
+#include "prim.h"
 #include "../../include/mbw.h"
 
 // The records of a reference: R is their sequences back to back, record i at [start[i], start[i] +
@@ -397,19 +397,19 @@ int sort_chunk(const uint64_t *Tw, uint64_t m, uint64_t n, uint32_t blo, uint32_
   if (got != M) { mbw_set_error("suffix bucket selection count mismatch"); return MBW_E_HIP; }
   k_keys<<<grid_for(M), 256, 0, st>>>(Tw, m, sa0, M, 0, key0);
   TRY(hipGetLastError());
-  hipcub::DoubleBuffer<uint64_t> dk(key0, key1), dv(sa0, sa1);
+  prim::dbuf<uint64_t> dk(key0, key1), dv(sa0, sa1);
   size_t tb = 0;
-  TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, dk, dv, M, 0, 63, st));
+  TRY(prim::sort_pairs(nullptr, tb, dk, dv, M, 0, 63, st));
   TRY(tmp.ensure(tb));
-  TRY(hipcub::DeviceRadixSort::SortPairs(tmp.b.p, tb, dk, dv, M, 0, 63, st));
-  uint64_t *sa = dv.Current();
-  uint64_t *key = dk.Current();
+  TRY(prim::sort_pairs(tmp.b.p, tb, dk, dv, M, 0, 63, st));
+  uint64_t *sa = dv.current();
+  uint64_t *key = dk.current();
   k_init_bounds<<<grid_for(M + 1), 256, 0, st>>>(key, M, bnd, idx /*as seed*/);
   TRY(hipGetLastError());
   tb = 0;
-  TRY(hipcub::DeviceScan::InclusiveScan(nullptr, tb, idx, grp, hipcub::Max(), M, st));
+  TRY(prim::inclusive_max(nullptr, tb, idx, grp, M, st));
   TRY(tmp.ensure(tb));
-  TRY(hipcub::DeviceScan::InclusiveScan(tmp.b.p, tb, idx, grp, hipcub::Max(), M, st));
+  TRY(prim::inclusive_max(tmp.b.p, tb, idx, grp, M, st));
   uint64_t MU = M;   // candidates of this round: all rows in the first, then the last round's unresolved list
   for (uint64_t round = 1;; ++round) {
     if (round > n / 21 + 4) { mbw_set_error("suffix refinement did not converge"); return MBW_E_HIP; }
@@ -418,9 +418,9 @@ int sort_chunk(const uint64_t *Tw, uint64_t m, uint64_t n, uint32_t blo, uint32_
     else k_mark_unres_list<<<grid_for(MU), 256, 0, st>>>(bnd, prev, MU, flag);
     TRY(hipGetLastError());
     tb = 0;
-    TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, flag, idx, MU, st));
+    TRY(prim::exclusive_sum(nullptr, tb, flag, idx, MU, st));
     TRY(tmp.ensure(tb));
-    TRY(hipcub::DeviceScan::ExclusiveSum(tmp.b.p, tb, flag, idx, MU, st));
+    TRY(prim::exclusive_sum(tmp.b.p, tb, flag, idx, MU, st));
     uint32_t lastf = 0, lasti = 0;
     TRY(hipMemcpyAsync(&lastf, flag + MU - 1, 4, hipMemcpyDeviceToHost, st));
     TRY(hipMemcpyAsync(&lasti, idx + MU - 1, 4, hipMemcpyDeviceToHost, st));
@@ -438,24 +438,24 @@ int sort_chunk(const uint64_t *Tw, uint64_t m, uint64_t n, uint32_t blo, uint32_
     k_u_keys<<<grid_for(MU), 256, 0, st>>>(Tw, m, sa, u_slot, MU, d, tmp_nk /*nk*/, iota0);
     TRY(hipGetLastError());
     // stable LSD: by next key, then by group start
-    hipcub::DoubleBuffer<uint64_t> k1(tmp_nk, nk1);
-    hipcub::DoubleBuffer<uint32_t> v1(iota0, iota1);
+    prim::dbuf<uint64_t> k1(tmp_nk, nk1);
+    prim::dbuf<uint32_t> v1(iota0, iota1);
     tb = 0;
-    TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, k1, v1, MU, 0, 63, st));
+    TRY(prim::sort_pairs(nullptr, tb, k1, v1, MU, 0, 63, st));
     TRY(tmp.ensure(tb));
-    TRY(hipcub::DeviceRadixSort::SortPairs(tmp.b.p, tb, k1, v1, MU, 0, 63, st));
-    uint64_t *nk = (k1.Current() == tmp_nk) ? tmp_nk : nk1;   // sorted keys (unused below)
+    TRY(prim::sort_pairs(tmp.b.p, tb, k1, v1, MU, 0, 63, st));
+    uint64_t *nk = (k1.current() == tmp_nk) ? tmp_nk : nk1;   // sorted keys (unused below)
     (void)nk;
-    uint32_t *perm1 = v1.Current();
+    uint32_t *perm1 = v1.current();
     uint32_t *perm_alt = (perm1 == iota0) ? iota1 : iota0;
     k_gather_u32<<<grid_for(MU), 256, 0, st>>>(u_gid, perm1, MU, gid1);
     TRY(hipGetLastError());
-    hipcub::DoubleBuffer<uint32_t> k2(gid1, gscan), v2(perm1, perm_alt);
+    prim::dbuf<uint32_t> k2(gid1, gscan), v2(perm1, perm_alt);
     tb = 0;
-    TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, k2, v2, MU, 0, 32, st));
+    TRY(prim::sort_pairs(nullptr, tb, k2, v2, MU, 0, 32, st));
     TRY(tmp.ensure(tb));
-    TRY(hipcub::DeviceRadixSort::SortPairs(tmp.b.p, tb, k2, v2, MU, 0, 32, st));
-    uint32_t *perm = v2.Current();
+    TRY(prim::sort_pairs(tmp.b.p, tb, k2, v2, MU, 0, 32, st));
+    uint32_t *perm = v2.current();
     // the unsorted next keys of this round are needed by index: recompute into nk1
     k_u_keys<<<grid_for(MU), 256, 0, st>>>(Tw, m, sa, u_slot, MU, d, nk1, gscan /*scratch iota*/);
     TRY(hipGetLastError());
@@ -464,9 +464,9 @@ int sort_chunk(const uint64_t *Tw, uint64_t m, uint64_t n, uint32_t blo, uint32_
     k_apply_scatter<<<grid_for(MU), 256, 0, st>>>(sa, bnd, u_slot, tmp_sa, tmp_nk, MU, gseed);
     TRY(hipGetLastError());
     tb = 0;
-    TRY(hipcub::DeviceScan::InclusiveScan(nullptr, tb, gseed, gscan, hipcub::Max(), MU, st));
+    TRY(prim::inclusive_max(nullptr, tb, gseed, gscan, MU, st));
     TRY(tmp.ensure(tb));
-    TRY(hipcub::DeviceScan::InclusiveScan(tmp.b.p, tb, gseed, gscan, hipcub::Max(), MU, st));
+    TRY(prim::inclusive_max(tmp.b.p, tb, gseed, gscan, MU, st));
     k_apply_groups<<<grid_for(MU), 256, 0, st>>>(grp, u_slot, gscan, MU);
     TRY(hipGetLastError());
   }
@@ -585,9 +585,9 @@ static int build_lines(mbw_index *ix, const uint8_t *B, hipStream_t st) {
   Temp tmp;
   for (int a = 0; a < 4; ++a) {
     size_t tb = 0;
-    TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt.p + a * nl, pre.p + a * nl, nl, st));
+    TRY(prim::exclusive_sum(nullptr, tb, cnt.p + a * nl, pre.p + a * nl, nl, st));
     TRY(tmp.ensure(tb));
-    TRY(hipcub::DeviceScan::ExclusiveSum(tmp.b.p, tb, cnt.p + a * nl, pre.p + a * nl, nl, st));
+    TRY(prim::exclusive_sum(tmp.b.p, tb, cnt.p + a * nl, pre.p + a * nl, nl, st));
   }
   uint64_t tot[4], last[4];
   for (int a = 0; a < 4; ++a) {

@@ -16,7 +16,6 @@
 // The work per candidate is O(|P| + |W| + matching pairs) rather than the O(|P| |W|) of testing
 // every diagonal; the pass list is a device-wide selection of candidates with max >= min_hits.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cstring>
@@ -24,6 +23,7 @@
 
 #include "ctx.h"
 #include "mbw_internal.h"
+#include "prim.h"
 #include "../../include/mbw.h"
 
 #define TRY(call) MBW_HIP_TRY(call)
@@ -340,7 +340,7 @@ extern "C" int mbw_rescue_filter(mbw_ctx *c, const uint8_t *reads, const uint32_
   uint64_t *wide = (uint64_t *)c->rc_wide.p, *offs = (uint64_t *)c->rc_offs.p;
   k_rc_widen<<<rc_grid(n_reads + 1), 256, 0, st>>>(dlen, n_reads, wide, ctl);
   TRY(hipGetLastError());
-  int r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, wide, offs, n_reads + 1, st); });
+  int r = prim_call(c, [&](void *tp, size_t &tb) { return prim::exclusive_sum(tp, tb, wide, offs, n_reads + 1, st); });
   if (r) return r;
   // candidates
   const mbw_rescue_cand_t *dc = cands;
@@ -396,9 +396,8 @@ extern "C" int mbw_rescue_filter(mbw_ctx *c, const uint8_t *reads, const uint32_
   TRY(hipGetLastError());
   TRY(hipEventRecord(c->ev[2], st));
   uint32_t *nsel = (uint32_t *)(ctl + RC_NSEL);
-  r = cub_call(c, [&](void *tp, size_t &tb) {
-    return hipcub::DeviceSelect::Flagged(tp, tb, hipcub::CountingInputIterator<uint32_t>(0), A.flags,
-                                         (uint32_t *)c->rc_pass.p, nsel, n_cands, st);
+  r = prim_call(c, [&](void *tp, size_t &tb) {
+    return prim::flagged_indices(tp, tb, A.flags, (uint32_t *)c->rc_pass.p, nsel, n_cands, st);
   });
   if (r) return r;
   TRY(hipMemcpyAsync(h, ctl, sizeof(h), hipMemcpyDeviceToHost, st));

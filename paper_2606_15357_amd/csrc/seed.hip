@@ -21,7 +21,6 @@
 //   * plain (the baseline): one thread runs the serial algorithm for one read (round 2 inline) and
 //     one thread locates one seed; ranks read their line straight from global memory.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cstring>
@@ -33,6 +32,7 @@
 
 #include "ctx.h"
 #include "mbw_internal.h"
+#include "prim.h"
 #include "../../include/mbw.h"
 
 #define TRY(call) MBW_HIP_TRY(call)
@@ -1409,7 +1409,7 @@ static int segment_queries(mbw_ctx *c, const Query *q, uint64_t n, uint32_t seg,
   uint32_t *cnt = (uint32_t *)c->sc0.p, *off = (uint32_t *)c->sc1.p;
   k_seg_count<<<grid_for(n), 256, 0, st>>>(q, n, seg, cnt);
   TRY(hipGetLastError());
-  int r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, cnt, off, n, st); });
+  int r = prim_call(c, [&](void *tp, size_t &tb) { return prim::exclusive_sum(tp, tb, cnt, off, n, st); });
   if (r) return r;
   uint64_t tail[2] = {0, 0};
   FETCH({{cnt + n - 1, 0}, {off + n - 1, 0}}, tail);
@@ -1513,7 +1513,7 @@ static int seed_impl(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, 
   k_widen<<<grid_for(n_reads + 1, 256, 1024u), 256, 0, st>>>(dlen, n_reads, wide, ctl + C_MAXLEN);
   TRY(hipGetLastError());
   uint64_t *offs = (uint64_t *)c->offs.p;
-  int r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, wide, offs, n_reads + 1, st); });
+  int r = prim_call(c, [&](void *tp, size_t &tb) { return prim::exclusive_sum(tp, tb, wide, offs, n_reads + 1, st); });
   if (r) return r;
   const bool coop = o.kernel != MBW_KERNEL_PLAIN;
   // wave kernels: packed-word offsets and the LDS-staging bins follow from the offsets alone, so
@@ -1526,7 +1526,7 @@ static int seed_impl(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, 
     nwd = (uint64_t *)c->nwords.p; woff = (uint64_t *)c->woffs.p;
     k_read_words<<<grid_for(n_reads + 1), 256, 0, st>>>(offs, n_reads, nwd);
     TRY(hipGetLastError());
-    r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, nwd, woff, n_reads + 1, st); });
+    r = prim_call(c, [&](void *tp, size_t &tb) { return prim::exclusive_sum(tp, tb, nwd, woff, n_reads + 1, st); });
     if (r) return r;
     GROW(c->q1, (n_reads + 1) * sizeof(Query));
     GROW(c->bf0, (n_reads + 1) * 4); GROW(c->bp0, (n_reads + 1) * 4);
@@ -1535,7 +1535,7 @@ static int seed_impl(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, 
     flag1 = (uint32_t *)c->bf0.p; pos1 = (uint32_t *)c->bp0.p;
     k_read_bins<<<grid_for(n_reads), 256, 0, st>>>(offs, n_reads, o.no_stage ? 0 : 1, flag1);
     TRY(hipGetLastError());
-    r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, flag1, pos1, n_reads, st); });
+    r = prim_call(c, [&](void *tp, size_t &tb) { return prim::exclusive_sum(tp, tb, flag1, pos1, n_reads, st); });
     if (r) return r;
   }
   uint64_t total = 0, totw = 0, maxlen = 0, lastf = 0, lastp = 0;
@@ -1603,11 +1603,11 @@ static int seed_impl(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, 
     TRY(hipGetLastError());
     const uint32_t *long_ids = ids + nshort1;
     if (nlong > 1) {
-      hipcub::DoubleBuffer<uint32_t> bk((uint32_t *)c->bk0.p, (uint32_t *)c->bk1.p);
-      hipcub::DoubleBuffer<uint32_t> bv(ids + nshort1, (uint32_t *)c->bid1.p);
-      r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceRadixSort::SortPairs(tp, tb, bk, bv, nlong, 0, 16, st); });
+      prim::dbuf<uint32_t> bk((uint32_t *)c->bk0.p, (uint32_t *)c->bk1.p);
+      prim::dbuf<uint32_t> bv(ids + nshort1, (uint32_t *)c->bid1.p);
+      r = prim_call(c, [&](void *tp, size_t &tb) { return prim::sort_pairs(tp, tb, bk, bv, nlong, 0, 16, st); });
       if (r) return r;
-      long_ids = bv.Current();
+      long_ids = bv.current();
     }
     Query *qq = (Query *)c->q1.p;
     if (nshort1)
@@ -1669,14 +1669,14 @@ static int seed_impl(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, 
     uint32_t *fs = (uint32_t *)c->bf0.p, *fl = (uint32_t *)c->bf1.p, *ps = (uint32_t *)c->bp0.p, *pl = (uint32_t *)c->bp1.p;
     const Query *sq = (const Query *)c->subq.p;
     if (c->arena) {
-      r = reserve_temp(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, fs, ps, nq_alloc, st); });
+      r = reserve_temp(c, [&](void *tp, size_t &tb) { return prim::exclusive_sum(tp, tb, fs, ps, nq_alloc, st); });
       if (r) return r;
     }
     k_query_bins<<<grid_for(nq), 256, 0, st>>>(sq, nq, o.no_stage ? 0 : 1, fs, fl);
     TRY(hipGetLastError());
-    r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, fs, ps, nq, st); });
+    r = prim_call(c, [&](void *tp, size_t &tb) { return prim::exclusive_sum(tp, tb, fs, ps, nq, st); });
     if (r) return r;
-    r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, fl, pl, nq, st); });
+    r = prim_call(c, [&](void *tp, size_t &tb) { return prim::exclusive_sum(tp, tb, fl, pl, nq, st); });
     if (r) return r;
     uint64_t tail[4] = {0, 0, 0, 0};
     FETCH({{fs + nq - 1, 0}, {ps + nq - 1, 0}, {fl + nq - 1, 0}, {pl + nq - 1, 0}}, tail);
@@ -1715,16 +1715,16 @@ static int seed_impl(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, 
   const uint64_t ns_alloc = c->arena ? std::max<uint64_t>(ns, c->raw.bytes / sizeof(SeedRec)) : ns;
   GROW(c->keys0, ns_alloc * 8); GROW(c->keys1, ns_alloc * 8); GROW(c->vals0, ns_alloc * 4); GROW(c->vals1, ns_alloc * 4);
   GROW(c->flag, ns_alloc * 4 + 8); GROW(c->idx, ns_alloc * 4 + 8);
-  hipcub::DoubleBuffer<uint64_t> dk((uint64_t *)c->keys0.p, (uint64_t *)c->keys1.p);
-  hipcub::DoubleBuffer<uint32_t> dv((uint32_t *)c->vals0.p, (uint32_t *)c->vals1.p);
+  prim::dbuf<uint64_t> dk((uint64_t *)c->keys0.p, (uint64_t *)c->keys1.p);
+  prim::dbuf<uint32_t> dv((uint32_t *)c->vals0.p, (uint32_t *)c->vals1.p);
   uint32_t *flag = (uint32_t *)c->flag.p, *idx = (uint32_t *)c->idx.p;
   uint64_t nu = 0;
   if (c->arena && ns) {   // temporary storage for the capacity, not the scheduling-dependent count
     r = reserve_temp(c, [&](void *tp, size_t &tb) {
-      return hipcub::DeviceRadixSort::SortPairs(tp, tb, dk, dv, ns_alloc, 0, 64, st);
+      return prim::sort_pairs(tp, tb, dk, dv, ns_alloc, 0, 64, st);
     });
     if (r) return r;
-    r = reserve_temp(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, flag, idx, ns_alloc, st); });
+    r = reserve_temp(c, [&](void *tp, size_t &tb) { return prim::exclusive_sum(tp, tb, flag, idx, ns_alloc, st); });
     if (r) return r;
   }
   if (ns) {
@@ -1736,12 +1736,12 @@ static int seed_impl(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, 
     int hibit = 2 * qb + 1;   // every key < (n_reads + 1) << 2 qb
     while (hibit < 64 && (1ull << (hibit - 2 * qb)) <= n_reads) ++hibit;
     if (ns > 1) {
-      r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceRadixSort::SortPairs(tp, tb, dk, dv, ns, 0, hibit, st); });
+      r = prim_call(c, [&](void *tp, size_t &tb) { return prim::sort_pairs(tp, tb, dk, dv, ns, 0, hibit, st); });
       if (r) return r;
     }
-    k_dedup_mark<<<grid_for(ns), 256, 0, st>>>(dk.Current(), ns, n_reads, qb, flag);
+    k_dedup_mark<<<grid_for(ns), 256, 0, st>>>(dk.current(), ns, n_reads, qb, flag);
     TRY(hipGetLastError());
-    r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, flag, idx, ns, st); });
+    r = prim_call(c, [&](void *tp, size_t &tb) { return prim::exclusive_sum(tp, tb, flag, idx, ns, st); });
     if (r) return r;
     uint64_t v[2];
     FETCH({{flag + ns - 1, 0}, {idx + ns - 1, 0}}, v);
@@ -1764,14 +1764,14 @@ static int seed_impl(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, 
   GROW(c->kpos, (nu + 1) * 8);
   uint64_t *npos = (uint64_t *)c->npos.p, *posoff = (uint64_t *)c->posoff.p;
   if (ns) {
-    k_seed_emit<<<grid_for(ns), 256, 0, st>>>((const SeedRec *)c->raw.p, dv.Current(), flag, idx, ns, (uint64_t)max_occ, seeds, npos,
+    k_seed_emit<<<grid_for(ns), 256, 0, st>>>((const SeedRec *)c->raw.p, dv.current(), flag, idx, ns, (uint64_t)max_occ, seeds, npos,
                                               (uint64_t *)c->kpos.p);
     TRY(hipGetLastError());
   }
   uint64_t n_pos = 0;
   if (nu) {
     TRY(hipMemsetAsync(npos + nu, 0, 8, st));
-    r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, npos, posoff, nu + 1, st); });
+    r = prim_call(c, [&](void *tp, size_t &tb) { return prim::exclusive_sum(tp, tb, npos, posoff, nu + 1, st); });
     if (r) return r;
     FETCH({{posoff + nu, 1}}, &n_pos);
     k_seed_posoff<<<grid_for(nu), 256, 0, st>>>(seeds, posoff, nu);
@@ -1821,7 +1821,7 @@ static int seed_impl(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, 
     uint64_t *kidx = (uint64_t *)c->kidx.p;
     k_bs_mark<<<grid_for(n_pos + 1), 256, 0, st>>>(posbuf, n_pos, ix->len_r, o.bs_role, keep);
     TRY(hipGetLastError());
-    r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, keep, kidx, n_pos + 1, st); });
+    r = prim_call(c, [&](void *tp, size_t &tb) { return prim::exclusive_sum(tp, tb, keep, kidx, n_pos + 1, st); });
     if (r) return r;
     uint64_t kept = 0;
     FETCH({{kidx + n_pos, 1}}, &kept);
@@ -1860,7 +1860,7 @@ static int seed_impl(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, 
                                               min_seed_len, pc, nullptr, nullptr);
     TRY(hipGetLastError());
     TRY(hipMemsetAsync(pc + n_pos, 0, 4, st));
-    r = cub_call(c, [&](void *tp, size_t &tb) { return hipcub::DeviceScan::ExclusiveSum(tp, tb, pc, po, n_pos + 1, st); });
+    r = prim_call(c, [&](void *tp, size_t &tb) { return prim::exclusive_sum(tp, tb, pc, po, n_pos + 1, st); });
     if (r) return r;
     FETCH({{po + n_pos, 1}}, &n_pieces);
     mbw_piece_t *pdst;
