@@ -445,8 +445,10 @@ def main():
     ap.add_argument("--no-chain", action="store_true", help="skip the chaining leg")
     ap.add_argument("--no-latency", action="store_true", help="skip the small-batch latency leg")
     ap.add_argument("--serve-workers", type=int, default=4, help="serving leg: worker threads, one stream each")
-    ap.add_argument("--bs-workers", type=int, default=3, help="bisulfite serving: workers of the bisulfite server")
-    ap.add_argument("--bs-plain-workers", type=int, default=1, help="bisulfite serving: workers of the plain server")
+    ap.add_argument("--bs-workers", type=int, default=2, help="bisulfite serving: workers of the bisulfite server")
+    ap.add_argument("--bs-plain-workers", type=int, default=2,
+                    help="bisulfite serving: workers of the plain server (2 + 2 saturate at 11.5 M reads/s of the mix, "
+                         "3 + 1 at 6.9 M: the 1-5 kbp requests carry most of the bases)")
     ap.add_argument("--serve-max-batch", type=int, default=1_000_000, help="serving leg: reads per batch at most")
     ap.add_argument("--serve-burst", type=int, default=12000,
                     help="requests in the closed-loop saturation burst (about 2,000 reads each)")
