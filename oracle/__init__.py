@@ -376,3 +376,37 @@ def chain(res: SeedResult, seg_len: int, max_gap: int = 5000, max_pred: int = 50
     for q in ptrs:
         L.orc_free_ptr(q)
     return chains, anchors
+
+
+# ---- reference text from ASCII (Section 2.1: bases other than A, C, G, T become random bases) ----
+_SM_GAMMA = 0x9E3779B97F4A7C15
+_SM_MASK = (1 << 64) - 1
+
+
+def splitmix64(seed: int, n: int) -> np.ndarray:
+    """The first n outputs of SplitMix64 (Steele, Lea and Flood, 2014) with state `seed`: the state
+    advances by the golden-ratio increment 0x9E3779B97F4A7C15, and each output is the state after
+    the step through the variant-13 mixer (xor-shift 30, multiply, xor-shift 27, multiply,
+    xor-shift 31)."""
+    with np.errstate(over="ignore"):
+        z = (np.uint64(seed & _SM_MASK) + np.arange(1, n + 1, dtype=np.uint64) * np.uint64(_SM_GAMMA))
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def codes_from_ascii(ref: bytes | np.ndarray, rng_seed: int = 0) -> np.ndarray:
+    """Reference codes 0..3 from ASCII: A, C, G, T in either case are 0, 1, 2, 3; any other byte at
+    position i becomes the low two bits of output i of SplitMix64 seeded with rng_seed (the reading
+    S5 of the random replacement)."""
+    a = np.frombuffer(bytes(ref), np.uint8) if not isinstance(ref, np.ndarray) else ref.astype(np.uint8)
+    table = np.full(256, 255, np.uint8)
+    for ch, v in zip(b"ACGT", range(4)):
+        table[ch] = v
+        table[ch + 32] = v
+    codes = table[a]
+    amb = np.nonzero(codes == 255)[0]
+    if amb.size:
+        draws = splitmix64(rng_seed, int(amb.max()) + 1)
+        codes[amb] = (draws[amb] & np.uint64(3)).astype(np.uint8)
+    return codes

@@ -106,3 +106,43 @@ def test_fasta_refusals(tmp_path, content, code):
     with pytest.raises(mbw.MbwError) as e:
         mbw.Index.build_fasta(p, sa_sample=8, kmer_k=4)
     assert e.value.code == getattr(mbw, code)
+
+
+def test_ambiguous_reference_bases_follow_the_oracle(tmp_path):
+    """Reading S5: bases other than A, C, G, T (N runs, IUPAC codes, one in a hundred) become the
+    low two bits of SplitMix64 output i at reference position i, seeded with rng_seed; the GPU
+    index (from memory and from FASTA) has the oracle's BWT, C and primary row for the converted
+    reference, and seeding on it equals the oracle's."""
+    import tempfile
+    from mbw_helpers import decode_bwt
+    rng = np.random.default_rng(17)
+    n = 60_000
+    ascii_ = ACGT[rng.integers(0, 4, n)].copy()
+    amb = rng.choice(n, n // 100, replace=False)
+    ascii_[amb] = np.frombuffer(b"NRYKMSWBDHV", np.uint8)[rng.integers(0, 11, amb.size)]
+    ascii_[1000:1040] = ord("N")
+    seed = 1234567
+    codes = oracle.codes_from_ascii(ascii_.tobytes(), seed)
+    ox = oracle.OracleIndex(codes, sa_rate=8)
+    fa = str(tmp_path / "amb.fa")
+    with open(fa, "wb") as f:
+        f.write(b">amb\n")
+        for a in range(0, n, 70):
+            f.write(ascii_[a:a + 70].tobytes() + b"\n")
+    for idx in (mbw.Index.build(ascii_.tobytes(), sa_sample=8, kmer_k=8, rng_seed=seed),
+                mbw.Index.build_fasta(fa, sa_sample=8, kmer_k=8, rng_seed=seed)):
+        info = idx.info()
+        assert info["n"] == ox.n and info["primary"] == ox.primary
+        assert [int(x) for x in info["C"]] == [int(x) for x in ox.C()[:5]]
+        with tempfile.TemporaryDirectory() as d:
+            p = os.path.join(d, "amb.mbw")
+            idx.save(p)
+            fidx = read_index_file(p)
+        B = ox.bwt().astype(np.int64) - 1
+        B[ox.primary] = 0
+        assert np.array_equal(decode_bwt(fidx), B.astype(np.uint8))
+        ref = synth.Reference(codes, np.zeros((0, 2), np.uint64), 0, 0)
+        reads = synth.reads_fixed(ref, 1500, 150, False, p_sub=0.01, p_indel=0.001, seed=18)
+        out, s, p = gpu_seed(idx, reads)
+        compare_with_oracle(s, p, ox.seed(reads.seq, reads.offsets))
+        idx.free()
