@@ -369,6 +369,55 @@ def serve_leg(mbw, idx, reads, seconds: float, sched: dict, workers: int, max_ba
     return res
 
 
+def workload_leg(mbw, torch, synth, name: str, args, steps: int = 3):
+    """Another workload of the same path, measured in the same way as the headline: its own index
+    (100 Mbp mixed genome), reads resident in HBM, autotuned schedule, `steps` timed calls of the
+    wave path after one warm-up, and one call of the plain kernel."""
+    t0 = time.time()
+    wl = synth.WORKLOADS[name]
+    ref = synth.workload_reference(name)
+    idx = mbw.Index.build(ref.codes, sa_sample=args.sa_sample, kmer_k=args.kmer, isa_sample=args.isa_sample)
+    reads = synth.workload_reads(name, ref)
+    dev = torch.device("cuda:0")
+    dseq = torch.from_numpy(reads.seq).to(dev)
+    dlen = torch.from_numpy(reads.lengths.view(np.int32)).to(dev)
+    stream = torch.cuda.current_stream()
+    ctx = mbw.Context(idx)
+    try:
+        best = ctx.tune(dseq, dlen, stream=stream)
+        best.pop("ms")
+        best.pop("cached", None)
+
+        def step(kernel):
+            return ctx.seed(dseq, dlen, min_seed_len=19, max_occ=500, kernel=kernel, stream=stream, **best)
+
+        step(mbw.KERNEL_COOP)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        outs = [step(mbw.KERNEL_COOP) for _ in range(steps)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        o = outs[-1]
+        step(mbw.KERNEL_PLAIN)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        po = step(mbw.KERNEL_PLAIN)
+        torch.cuda.synchronize()
+        pel = time.perf_counter() - t2
+        res = dict(workload=wl["desc"], reads=len(reads), bases=int(reads.lengths.sum()),
+                   value=round(len(reads) * steps / el, 1), unit="reads/s", ms_per_step=round(el / steps * 1e3, 2),
+                   plain_kernel=round(len(reads) / pel, 1), same_result=bool(po.n_seeds == o.n_seeds and po.n_pos == o.n_pos),
+                   seeds=int(o.n_seeds), positions=int(o.n_pos), schedule=best, kmer_k=idx.info()["kmer_k"],
+                   lines_per_read=round(o.lines_smem / len(reads), 1),
+                   lane_use=round(o.lane_iters / max(1, 64 * o.wave_iters), 3),
+                   note="index lines of a 100 Mbp genome largely fit the 256 MB last-level cache: no HBM roofline",
+                   leg_seconds=round(time.time() - t0, 1))
+    finally:
+        ctx.free()
+        idx.free()
+    return res
+
+
 def serve_bs_leg(mbw, synth, ref, pl_idx, args):
     """Serving with a bisulfite index and a plain index of the same 3.1 Gbp reference resident:
     requests of log-uniform 1..20,000 reads; 90% of them directional bisulfite reads (150 bp,
@@ -455,6 +504,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="seconds of open-loop arrivals per load point (0 = skip the serving legs)")
     ap.add_argument("--no-serve-bs", action="store_true", help="skip the bisulfite serving leg")
+    ap.add_argument("--no-other-workloads", action="store_true",
+                    help="skip the 100 Mbp workloads (paired reads, lognormal read lengths)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -617,6 +668,13 @@ def main():
         latency = latency_leg(torch, ctx, reads, dseq, dlen, sched, stream)
         log(f"small batches: {latency}")
 
+    others = None
+    if not args.no_other_workloads and args.workload == "human_3gbp":
+        others = {}
+        for name in ("paired_100mbp", "lognormal_100mbp"):
+            others[name] = workload_leg(mbw, torch, synth, name, args)
+            log(f"{name}: {others[name]}")
+
     serve = serve_bs = None
     if args.serve_seconds > 0:
         ctx.free()
@@ -636,7 +694,7 @@ def main():
                             isa_sample=args.isa_sample, unique_ext=not args.no_unique,
                             bases_per_line=384, line_bytes=LINE_BYTES, index_gb=round(info["bytes_resident"] / 1e9, 2)),
                 schedule=sched, plain_gpu=plain, roofline=roofline, cpu_baseline=cpu, serve=serve, serve_bs=serve_bs,
-                batch_latency=latency,
+                batch_latency=latency, other_workloads=others,
                 index_build=index_build, rescue=rescue, chain=chain)
     print(json.dumps(line), flush=True)
 
