@@ -586,6 +586,10 @@ static void run_split(Worker &w, int k, int &slot, const std::vector<Request *> 
     slot ^= 1;
     return;
   }
+  // a failure after the downloads were queued must not hand the buffer or the slot on while a
+  // copy may still write them
+  (void)hipStreamSynchronize(w.cs);
+  (void)hipStreamSynchronize(w.st);
   release_slot(w, slot);
   if (f.bb) { std::lock_guard<std::mutex> lk(w.s->mu); pool_put(w.s, f.bb); f.bb = nullptr; }
   if ((rc == MBW_E_CAPACITY || rc == MBW_E_NOMEM) && i1 - i0 > 1) {
