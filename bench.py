@@ -484,7 +484,9 @@ def main():
     ap.add_argument("--cpu-pairs", type=int, default=250_000)
     ap.add_argument("--cpu-window", type=int, default=16_000_000)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--isa-sample", type=int, default=4, help="inverse-SA sampling step (0 = no unique-match path)")
+    ap.add_argument("--isa-sample", type=int, default=1,
+                    help="inverse-SA sampling step (0 = no unique-match path; 1 keeps every entry: 49.6 GB at 3.1 Gbp, "
+                         "2 %% faster seeding than step 4, which needs 12.4 GB)")
     ap.add_argument("--no-unique", action="store_true", help="extend unique matches base by base")
     ap.add_argument("--probe", action="store_true", help="only run the copy and random-gather probes")
     ap.add_argument("--no-tune", action="store_true", help="default schedule instead of the autotuned one")
