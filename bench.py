@@ -74,9 +74,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel: str, launches_bytes: float):
+def traffic_from_profile(kernel: str, launches_bytes: float, isa_sample: int):
     """HBM bytes per launch of `kernel` from the committed counter summary, if it was taken on the
-    current kernel sources (else None)."""
+    current kernel sources with the same inverse-SA sampling step (else None)."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -84,7 +84,7 @@ def traffic_from_profile(kernel: str, launches_bytes: float):
         d = json.load(open(p))
     except Exception:
         return None
-    if d.get("source_hash") != kernel_source_hash():
+    if d.get("source_hash") != kernel_source_hash() or d.get("isa_sample") != isa_sample:
         return None
     k = d.get("kernels", {}).get(kernel)
     if not k:
@@ -623,8 +623,8 @@ def main():
     # roofline of the dominant kernel (SMEM): algorithmic 128-byte lines over its event time
     smem_bytes = lines_smem * LINE_BYTES
     achieved = smem_bytes / (ms_smem * 1e-3) / 1e9
-    traffic = traffic_from_profile("smem", smem_bytes / max(launches, 1))
-    loc_traffic = traffic_from_profile("locate", 0)
+    traffic = traffic_from_profile("smem", smem_bytes / max(launches, 1), args.isa_sample)
+    loc_traffic = traffic_from_profile("locate", 0, args.isa_sample)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                     kernel="k_smem_wave<staged> (both SMEM rounds)", launches_per_step=launches,

@@ -30,12 +30,14 @@ def test_comment_edits_keep_the_key_and_code_edits_change_it():
     assert bench.strip_comments(code) != bench.strip_comments(changed)
 
 
-def test_traffic_is_null_for_another_source_hash(tmp_path, monkeypatch):
+def test_traffic_is_null_for_another_source_hash_or_index(tmp_path, monkeypatch):
     (tmp_path / "profiles").mkdir()
     (tmp_path / "profiles" / "traffic.json").write_text(
-        '{"source_hash": "0000000000000000", "kernels": {"smem": {"hbm_bytes_per_launch": 5.0}}}')
+        '{"source_hash": "0000000000000000", "isa_sample": 1, "kernels": {"smem": {"hbm_bytes_per_launch": 5.0}}}')
     monkeypatch.setattr(bench, "ROOT", tmp_path)
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "1111111111111111")
-    assert bench.traffic_from_profile("smem", 1.0) is None
+    assert bench.traffic_from_profile("smem", 1.0, 1) is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0000000000000000")
-    assert bench.traffic_from_profile("smem", 1.0) == 5.0
+    assert bench.traffic_from_profile("smem", 1.0, 1) == 5.0
+    # counters taken with another inverse-SA step describe another index
+    assert bench.traffic_from_profile("smem", 1.0, 4) is None
