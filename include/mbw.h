@@ -180,6 +180,15 @@ typedef struct {
                          wave of the grid about 8 takes, at most 256), else 1..256 fixed (a fixed
                          size leaves waves of the grid idle on a batch of fewer than that many reads
                          per wave) */
+  int unique_defer;   /* with unique_ext, for reads staged in LDS (round 1): 1 = a lane whose forward
+                         extension reaches s = 1 hands the match to a task list and takes the next
+                         read; a continuation kernel finishes the listed matches against the text
+                         and lists their reads for another pass, and the passes alternate until
+                         every read is done (same results; the SMEM kernel runs without the
+                         unique-match stages, about a third fewer vector instructions, but the
+                         passes serialise the continuation work that the lanes otherwise overlap
+                         with extension, and each pass costs the host two waits: slower on the
+                         150 bp reads measured); 0 = the lane finishes the match itself */
 } mbw_seed_opts;
 
 

@@ -67,7 +67,7 @@ class SeedOpts(C.Structure):
     _fields_ = [("min_occ", C.c_int), ("reseed", C.c_int), ("reseed_len", C.c_int), ("reseed_occ", C.c_int),
                 ("bs_role", C.c_int), ("kernel", C.c_int), ("use_kmer", C.c_int), ("blocks_per_cu", C.c_int),
                 ("no_stage", C.c_int), ("unique_ext", C.c_int), ("seg_len", C.c_int), ("bs_refine", C.c_int),
-                ("wave_chunk", C.c_int)]
+                ("wave_chunk", C.c_int), ("unique_defer", C.c_int)]
 
 
 class ServeCfg(C.Structure):
@@ -439,7 +439,7 @@ class Context:
              reseed: bool = True, reseed_len: int = 38, reseed_occ: int = 10, bs_role: int = 0,
              kernel: int = KERNEL_COOP, use_kmer: bool = True, blocks_per_cu: int = 0, stage: bool = True,
              unique_ext: bool = True, seg_len: int = 0, bs_refine: bool = False, wave_chunk: int = 0,
-             stream=None) -> SeedOutput:
+             unique_defer: int = 0, stream=None) -> SeedOutput:
         """``reads``: concatenated ASCII (numpy uint8 on the host or a torch uint8 CUDA tensor);
         ``lengths``: uint32 per read (numpy or torch)."""
         n = int(lengths.numel() if hasattr(lengths, "numel") else len(lengths))
@@ -449,7 +449,7 @@ class Context:
             reads = np.ascontiguousarray(reads, dtype=np.uint8)
         o = SeedOpts(int(min_occ), int(bool(reseed)), int(reseed_len), int(reseed_occ), int(bs_role), int(kernel),
                      int(bool(use_kmer)), int(blocks_per_cu), int(not stage), int(bool(unique_ext)), int(seg_len),
-                     int(bool(bs_refine)), int(wave_chunk))
+                     int(bool(bs_refine)), int(wave_chunk), int(unique_defer))
         res = Result()
         rp = _ptr(reads) if n else None
         lp = _ptr(lengths) if n else None
@@ -508,7 +508,8 @@ class Context:
                         int(kw.get("reseed_occ", 10)), int(kw.get("bs_role", 0)), int(kw.get("kernel", KERNEL_COOP)),
                         int(bool(kw.get("use_kmer", True))), int(kw.get("blocks_per_cu", 0)),
                         int(not kw.get("stage", True)), int(bool(kw.get("unique_ext", True))), int(kw.get("seg_len", 0)),
-                        int(bool(kw.get("bs_refine", False))), int(kw.get("wave_chunk", 0)))
+                        int(bool(kw.get("bs_refine", False))), int(kw.get("wave_chunk", 0)),
+                        int(kw.get("unique_defer", 0)))
 
     def rescue(self, reads, lengths, cands, q: int = 7, min_hits: int = 10, bs_role: int = 0,
                stream=None) -> RescueOutput:
@@ -693,7 +694,8 @@ class Server:
                      int(opts.get("reseed_occ", 10)), int(opts.get("bs_role", 0)), int(opts.get("kernel", KERNEL_COOP)),
                      int(bool(opts.get("use_kmer", True))), int(opts.get("blocks_per_cu", 0)),
                      int(not opts.get("stage", True)), int(bool(opts.get("unique_ext", True))), int(opts.get("seg_len", 0)),
-                     int(bool(opts.get("bs_refine", False))), int(opts.get("wave_chunk", 0)))
+                     int(bool(opts.get("bs_refine", False))), int(opts.get("wave_chunk", 0)),
+                     int(opts.get("unique_defer", 0)))
         cfg = ServeCfg(int(n_workers), int(max_batch_reads), int(max_batch_bases), int(max_queued_bases),
                        int(min_seed_len), int(max_occ), o, int(index.info()["device"]), int(device_bytes))
         self._held = {}   # ticket -> arrays of a request submitted without a copy

@@ -23,7 +23,7 @@ struct mbw_ctx {
   // seeding
   Buf codes, ascii, lens, offs, raw, subq, keys0, keys1, vals0, vals1, flag, idx, seeds, npos, posoff, xrows, pos, pos2,
       keep, kidx, temp, ctl, pwords, pnmask, woffs, nwords, wread, q1, q2, bf0, bf1, bp0, bp1, bid0, bid1, bk0, bk1, q1s,
-      q2s, sc0, sc1, pseed, pcnt, ppoff, pieces, kpos;
+      q2s, sc0, sc1, pseed, pcnt, ppoff, pieces, kpos, utask, ures;
   // mate-rescue prefilter (its own buffers, so that it leaves the last seeding result intact)
   Buf rc_lens, rc_wide, rc_offs, rc_ascii, rc_cand, rc_ctl, rc_hits, rc_flags, rc_pass;
   // chaining (its own buffers likewise)
@@ -41,7 +41,7 @@ struct mbw_ctx {
   static const int kLaunchSlots = 8;
   hipEvent_t lev[2 * kLaunchSlots] = {};
   int n_pending = 0;
-  struct LaunchNote { int round, staged, grid; uint64_t queries; uint32_t chunk; };
+  struct LaunchNote { int round, staged, kind, grid; uint64_t queries; uint32_t chunk; };
   LaunchNote pending[kLaunchSlots];
   hipStream_t cur = nullptr;   // stream of the current / last call
   hipStream_t own = nullptr;   // the context's own stream: frees its buffers when it is destroyed
@@ -55,7 +55,7 @@ struct mbw_ctx {
     return {&codes, &ascii, &lens, &offs, &raw, &subq, &keys0, &keys1, &vals0, &vals1, &flag, &idx, &seeds, &npos,
             &posoff, &xrows, &pos, &pos2, &keep, &kidx, &temp, &ctl, &pwords, &pnmask, &woffs, &nwords, &wread, &q1,
             &q2, &bf0, &bf1, &bp0, &bp1, &bid0, &bid1, &bk0, &bk1, &q1s, &q2s, &sc0, &sc1, &pseed, &pcnt, &ppoff,
-            &pieces, &kpos, &rc_lens, &rc_wide, &rc_offs, &rc_ascii, &rc_cand, &rc_ctl, &rc_hits, &rc_flags, &rc_pass,
+            &pieces, &kpos, &utask, &ures, &rc_lens, &rc_wide, &rc_offs, &rc_ascii, &rc_cand, &rc_ctl, &rc_hits, &rc_flags, &rc_pass,
             &ch_ctl, &ch_cnt, &ch_aoff, &ch_slot, &ch_cslot, &ch_A, &ch_As, &ch_k2a, &ch_k2b, &ch_k1a, &ch_k1b, &ch_va,
             &ch_vb, &ch_F, &ch_P, &ch_U, &ch_CH, &ch_CA, &ch_nch, &ch_nanc, &ch_choff, &ch_anoff, &ch_out, &ch_outa};
   }

@@ -46,6 +46,12 @@ namespace {
 // cannot be extended to the left (SEG_CHECK: one backward step decides).
 #define SEG_CHECK 1u
 struct Query { uint32_t read_id, qbeg, qend, l, c, rlen, woff_lo, woff_hi, send, flags, pad0, pad1; };   // 48 bytes
+// A query resumed after a unique match that a continuation pass finished: the lane starts in stage 3
+// at the match [pad0, pad1) instead of stage 1 at qbeg.
+#define Q_RESUME 2u
+// A unique match handed from the SMEM kernel to the continuation kernel: the query (its record's
+// first eight words), the match P[i, j) with interval (k, kr) and s = 1.
+struct UTask { uint32_t read_id, qbeg, qend, l, c, rlen, woff_lo, woff_hi, i, j, pad0, pad1; uint64_t k, kr; };   // 64 bytes
 #define INVALID_READ 0xFFFFFFFFu   // unused slot of a per-wave output chunk
 // pos: the text position of the SMEM when the unique-match path found it (s = 1), else NO_POS
 #define NO_POS 0xFFFFFFFFFFFFFFFFull
@@ -54,6 +60,7 @@ struct SeedRec { uint32_t read_id, qbeg, qend, flags; uint64_t k, kr, s, pos; };
 // control block (device): counters shared by the kernels of one call
 enum { C_WORK = 0, C_NSEEDS = 1, C_NSUBQ = 2, C_LINES = 3, C_STEPS = 4, C_KMER = 5, C_LFSTEPS = 6, C_SAREADS = 7,
        C_LINES_LOC = 8, C_WORK2 = 9, C_MAXLEN = 10, C_ERR = 11, C_WITER = 12, C_LITER = 13, C_MAXCHAIN = 14,
+       C_PASSQ = 15,   // slots of the task or resume list a continuation pass writes
        C_COUNT = 16 };
 
 struct SeedParams {
@@ -74,6 +81,12 @@ struct SeedParams {
   Query *__restrict__ subq;
   uint64_t subq_cap;
   unsigned long long *__restrict__ ctl;
+  // unique-match continuations (round 1, staged reads): the SMEM kernel writes tasks, the
+  // continuation kernel reads them (n_queries of them) and writes the queries to resume
+  UTask *__restrict__ tasks;
+  uint64_t task_cap;
+  Query *__restrict__ resume;
+  uint64_t resume_cap;
 };
 
 struct ReadWords {
@@ -328,6 +341,14 @@ __device__ __forceinline__ void wave_stat(unsigned long long *dst, uint64_t v, b
 // kernel also from the reverse-complement row k', in step) until a sampled row is reached
 // (Algorithm 2; the second walk gives the mirror of p), 5 = text comparison, 6 = inverse-SA sample
 // read, 7 = LF walk to k'.  The seed carries p to locate, which does not walk it again.
+//
+// Deferred unique matches (DEFER; staged reads, round 1).  A wave runs the code of every state any
+// of its lanes is in, so stages 4-7 in the same loop as the extensions make every iteration pay for
+// them.  With DEFER the kernel runs the extension loop alone: a lane whose forward extension
+// reaches s = 1 writes the match and its query to a task list and takes the next query; the
+// continuation kernel (k_unique_wave) runs stages 4-7 for every task, reports the SMEM and lists
+// the query for another pass of this kernel, which resumes it in stage 3 after the match.  Passes
+// alternate until no query is left; the SMEMs are the same.
 #define STAGE_WORDS 5   // staged reads of up to 160 bases
 #define SOLO_STEPS 1024 // extension steps the tail loop takes in one iteration
 #define SMEM_WAVES 4    // waves per block
@@ -342,8 +363,9 @@ typedef __attribute__((address_space(3))) void lds_void;
 // Records that arrive in the memory phase (query records, k-mer entries, staged read words) are
 // loaded straight into LDS (global_load_lds: lane L's bytes land at base + size * L), so they
 // occupy no registers while the wave waits.
-template <bool STAGED, bool UNIQ>
+template <bool STAGED, bool UNIQ, bool DEFER = false>
 __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_per_eu(4))) k_smem_wave(IndexView ix, SeedParams P, ReadWords R) {
+  static_assert(!DEFER || (STAGED && !UNIQ), "deferred unique matches: staged kernel without the in-lane path");
   constexpr bool SEG = !STAGED;
   // the unique path's first walk follows both rows of the match in the staged kernel only: in the
   // unstaged one the second row's state made the compiler spill four times as many scalar
@@ -402,6 +424,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
   uint32_t chain = 0, max_chain = 0;   // iterations of the current query; longest so far
   uint64_t cb = 0, ce = 0;
   WaveOut wout = {0, 0, 0, 0};
+  uint64_t tkb = 0, tke = 0;      // DEFER: the wave's current chunk of the task list
   for (;;) {
     // ---- idle lanes take a query (its record is loaded in this iteration's memory phase)
     const bool want = st == ST_IDLE;
@@ -418,6 +441,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
     int act = ACT_DONE, a = 0;
     uint32_t code = 0;
     bool em = false;
+    bool dfr = false;             // DEFER: the match reached s = 1; it goes to the task list
     Emit e;
     e.i = 0; e.j = 0; e.k = 0; e.kr = 0; e.s = 0;
     if (st == ST_ACTIVE && --budget == 0) { atomicOr(&P.ctl[C_ERR], 1ull); st = ST_IDLE; }
@@ -452,6 +476,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
           const bool qe = j == (int)qend;
           a = qe ? 4 : base_at(j);
           if (UNIQ && !qe && P.uniq && s == 1) { u = 4; wrow = k; wrow2 = kr; wcnt = 0; continue; }
+          if (DEFER && !qe && s == 1) { dfr = true; act = ACT_DONE; break; }
           if (a > 3) {                                  // end of the query, or a non-ACGT base: SMEM [i, j)
             if (SEG && segchk && i == (int)qbeg) { segchk = false; u = 8; continue; }
             em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s;
@@ -528,7 +553,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
             else { kr = nx; k = ny; j += 1; }
             s = ns;
             act = ACT_SKIP;
-            if (sbwd ? ((u == 1 && j < i) || (u == 3 && j <= i)) : (j == (int)qend || (UNIQ && P.uniq && s == 1))) go = false;
+            if (sbwd ? ((u == 1 && j < i) || (u == 3 && j <= i)) : (j == (int)qend || (((UNIQ && P.uniq) || DEFER) && s == 1))) go = false;
             else {
               a = base_at(j);
               if (a > 3) go = false;
@@ -700,6 +725,10 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
     if ((STAGED && st_mem == ST_STAGE) || (!STAGED && st_mem == ST_REC && st == ST_ACTIVE)) {
       u = 1; i = (int)qbeg; j = (int)(qbeg + l - 1);
       k = 0; kr = 0; s = ix.n; fresh = true;
+      if (DEFER) {                                      // a query resumed after its unique match
+        const uint4 q2 = sq[wv][2][lane];
+        if (q2.y & Q_RESUME) { u = 3; i = (int)q2.z; j = (int)q2.w; }
+      }
       {
         const uint64_t b = 8ull * (qend - qbeg) * (qend - qbeg) + 64;
         budget = b > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)b;
@@ -707,14 +736,220 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
       st = ST_ACTIVE;
     }
     wave_emit(P, lane, em, q_read_id(), e, wout, q_rlen(), q_wo(), tpl);
+    if (DEFER && __ballot(dfr)) {                       // the query's record is still in LDS
+      const uint64_t ts = wave_slot(dfr, tkb, tke, &P.ctl[C_PASSQ], lane);
+      if (dfr && ts < P.task_cap) {
+        const uint4 q0 = sq[wv][0][lane], q1 = sq[wv][1][lane];
+        UTask t;
+        t.read_id = q0.x; t.qbeg = q0.y; t.qend = q0.z; t.l = q0.w;
+        t.c = q1.x; t.rlen = q1.y; t.woff_lo = q1.z; t.woff_hi = q1.w;
+        t.i = (uint32_t)i; t.j = (uint32_t)j; t.pad0 = 0; t.pad1 = 0; t.k = k; t.kr = kr;
+        P.tasks[ts] = t;
+      }
+    }
   }
   wave_close(P, lane, wout);
+  if (DEFER)                                            // the unused tail of the wave's task chunk
+    for (uint64_t t = tkb + lane; t < tke; t += 64)
+      if (t < P.task_cap) P.tasks[t].read_id = INVALID_READ;
   // n_iter and n_busy are per wave (the same in every lane); the rest are per lane
   if ((threadIdx.x & 63) == 0 && n_iter) { atomicAdd(&P.ctl[C_WITER], (unsigned long long)n_iter); atomicAdd(&P.ctl[C_LITER], (unsigned long long)n_busy); }
   wave_stat(&P.ctl[C_MAXCHAIN], max_chain, true);
   wave_stat(&P.ctl[C_LINES], (uint64_t)n_lines + n_kmer);
   wave_stat(&P.ctl[C_STEPS], n_steps);
   wave_stat(&P.ctl[C_KMER], n_kmer);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Continuation kernel of deferred unique matches (persistent; one task per lane at a time).
+//
+// A task is a match P[i, j) with s = 1 found by forward extension.  Its lane walks LF from both
+// rows of the match (k and the reverse-complement row kr) until one reaches a sampled SA row
+// (stage 4), reads that sample (5: the occurrence p, or its mirror from the second walk), compares
+// the read with the packed text 64 bases at a time from P[j] on (6), reads the inverse-SA sample at
+// or after the mirrored position of the extended match and walks LF to it (7: k'), then reports the
+// SMEM [i, j') with (k, k', 1) and its position, and lists the query for the next pass of the SMEM
+// kernel unless j' is the query's end.  The read's packed words come from global memory.
+#define UNIQ_WAVES 4
+#define AUTO_TASKS 4000   // automatic grid sizing: tasks per block and CU
+
+__global__ void __launch_bounds__(64 * UNIQ_WAVES) k_unique_wave(IndexView ix, SeedParams P, ReadWords R) {
+  __shared__ uint64_t sbt[MBW_MAX_SB * 8];
+  __shared__ uint64_t scb[4];
+  __shared__ uint64_t stp[UNIQ_WAVES][64];   // text position of P[i] (read when a seed is written)
+  for (int t = threadIdx.x; t < 8 * ix.n_sb; t += blockDim.x) sbt[t] = ix.sbtab[t];
+  if (threadIdx.x < 4) scb[threadIdx.x] = ix.Cb[threadIdx.x];
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t sbm = (1u << ix.sb_shift) - 1;
+  const uint64_t tm = ix.n - 1;   // text length without $
+  uint64_t *tpl = &stp[wv][lane];
+  int st = ST_IDLE;
+  uint32_t ti = 0;                // task being loaded
+  uint32_t read_id = 0, qbeg = 0, qend = 0, l = 0, c = 1, rlen = 0;
+  uint64_t wo = 0;                // first packed word of the read
+  int i = 0, j = 0, u = 0;
+  uint64_t k = 0, wrow = 0, wrow2 = 0;
+  bool wmir = false;
+  uint32_t wcnt = 0, budget = 0;
+  uint32_t n_lines = 0;
+  uint64_t n_iter = 0, n_busy = 0;
+  uint64_t cb = 0, ce = 0, rb = 0, re = 0;
+  WaveOut wout = {0, 0, 0, 0};
+  for (;;) {
+    const bool want = st == ST_IDLE;
+    if (__ballot(want)) {
+      const uint64_t t = wave_take(want, cb, ce, &P.ctl[C_WORK], P.n_queries, lane, P.chunk);
+      if (want) { if (t == ~0ull) st = ST_DRAINED; else { ti = (uint32_t)t; st = ST_REC; } }
+    }
+    if (__ballot(st != ST_DRAINED) == 0) break;
+    ++n_iter;
+    n_busy += __popcll(__ballot(st != ST_DRAINED && st != ST_IDLE));
+    int act = ACT_DONE;
+    bool em = false, rs = false;
+    Emit e;
+    e.i = 0; e.j = 0; e.k = 0; e.kr = 0; e.s = 0;
+    if (st == ST_ACTIVE && --budget == 0) { atomicOr(&P.ctl[C_ERR], 1ull); st = ST_IDLE; }
+    if (st == ST_ACTIVE) {
+      if (u == 4) {
+        const bool s1 = (wrow & P.rmask) == 0, s2 = (wrow2 & P.rmask) == 0;
+        if (s1 || s2) { wmir = !s1; if (!s1) wrow = wrow2; act = ACT_SSA; }
+        else act = ACT_LF;
+      } else if (u == 5) act = ACT_TEXT;
+      else if (u == 6) act = ACT_ISA;
+      else if (wcnt > 0) act = ACT_LF;
+      else {                                            // u == 7, at k': the SMEM [i, j) with (k, k', 1)
+        em = true; e.i = (uint32_t)i; e.j = (uint32_t)j; e.k = k; e.kr = wrow; e.s = 1 | KNOWN_POS;
+        rs = j != (int)qend;
+        st = ST_IDLE;
+      }
+    }
+    const bool lfa = act == ACT_LF;
+    const bool lf2 = lfa && u == 4;                      // both rows of the match
+    const uint64_t x1 = wrow, x2 = lf2 ? wrow2 : wrow;
+    const uint32_t L1 = line_of(x1), L2 = line_of(x2);
+    const int o1 = (int)(x1 - (uint64_t)L1 * MBW_BPL), o2 = (int)(x2 - (uint64_t)L2 * MBW_BPL);
+    const bool two = lf2 && L1 != L2;
+    const bool blk2 = lf2 && (two || (o1 >> 6) != (o2 >> 6));
+    // ---- the memory phase
+    const uint4 z4 = make_uint4(0, 0, 0, 0);
+    const uint4 *l1p = ix.lines + (uint64_t)L1 * MBW_LINE_U4, *l2p = ix.lines + (uint64_t)L2 * MBW_LINE_U4;
+    uint4 h0a = z4, h1a = z4, ba = z4, h0b = z4, h1b = z4, bb = z4;
+    if (lfa) { h0a = l1p[0]; h1a = l1p[1]; ba = l1p[2 + (o1 >> 6)]; }
+    if (two) { h0b = l2p[0]; h1b = l2p[1]; }
+    if (blk2) bb = l2p[2 + (o2 >> 6)];
+    const uint64_t tq = (act == ACT_TEXT ? *tpl : 0ull) + (uint64_t)(j - i);
+    const bool txt = act == ACT_TEXT && tq < tm;
+    uint64_t a0 = 0, a1 = 0, a2 = 0;
+    uint32_t n0 = 0, n1 = 0, n2 = 0;
+    if (txt) {
+      const uint4 *tw = (const uint4 *)(ix.text + ((tq >> 5) & ~1ull));
+      h0b = tw[0]; h1b = tw[1];
+      // read bases j .. j+63 (the packed batch ends with two spare words)
+      const uint64_t w0 = wo + (uint64_t)(j >> 5);
+      a0 = R.pw[w0]; a1 = R.pw[w0 + 1]; a2 = R.pw[w0 + 2];
+      n0 = R.pn[w0]; n1 = R.pn[w0 + 1]; n2 = R.pn[w0 + 2];
+    }
+    uint64_t mval = 0;
+    if (act == ACT_SSA) mval = ix.ssa[wrow >> P.rshift];
+    if (act == ACT_ISA) mval = ix.isa[wrow];
+    const int st_mem = st;
+    uint4 t0 = z4, t1 = z4, t2 = z4, t3 = z4;
+    if (st_mem == ST_REC) {
+      const uint4 *tp = (const uint4 *)(P.tasks + ti);
+      t0 = tp[0]; t1 = tp[1]; t2 = tp[2]; t3 = tp[3];
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    // ---- compute
+    if (lfa) {                                          // LF of the walked row(s); the $ row maps to row 0
+      const int cx = bwt_from_block(ba, o1);
+      if (!two) { h0b = h0a; h1b = h1a; }
+      if (!blk2) bb = ba;
+      const uint32_t sb1 = 8 * (L1 >> ix.sb_shift);
+      uint64_t E1, G1;
+      rank_eg(h0a, h1a, ba, L1 & sbm, o1, cx, sym_masks(cx), sbt[sb1 + cx], sbt[sb1 + 4 + cx], E1, G1);
+      wrow = x1 == ix.primary ? 0ull : scb[cx] + E1 - ((cx == 0 && x1 > ix.primary) ? 1ull : 0ull);
+      if (lf2) {
+        const int cx2 = bwt_from_block(bb, o2);
+        const uint32_t sb2 = 8 * (L2 >> ix.sb_shift);
+        uint64_t E2, G2;
+        rank_eg(h0b, h1b, bb, L2 & sbm, o2, cx2, sym_masks(cx2), sbt[sb2 + cx2], sbt[sb2 + 4 + cx2], E2, G2);
+        wrow2 = x2 == ix.primary ? 0ull : scb[cx2] + E2 - ((cx2 == 0 && x2 > ix.primary) ? 1ull : 0ull);
+        ++wcnt;
+        n_lines += two ? 2 : 1;
+      } else {
+        --wcnt;
+        ++n_lines;
+      }
+    }
+    if (act == ACT_SSA) {                               // the occurrence: p = S(row) + steps (mod n)
+      uint64_t pp = mval + wcnt;
+      if (pp >= ix.n) pp -= ix.n;
+      if (wmir) pp = tm - pp - (uint64_t)(j - i);       // the mirror of the reverse-complement match
+      *tpl = pp;
+      u = 5;
+      ++n_lines;
+    }
+    if (act == ACT_TEXT) {                              // compare up to 64 bases of read and text
+      const int lim0 = min(64, (int)qend - j);
+      int first = 0;
+      if (txt) {
+        const uint64_t wv0 = ((uint64_t)h0b.y << 32) | h0b.x, wv1 = ((uint64_t)h0b.w << 32) | h0b.z;
+        const uint64_t wv2 = ((uint64_t)h1b.y << 32) | h1b.x, wv3 = ((uint64_t)h1b.w << 32) | h1b.z;
+        const int off = 2 * (int)(tq - 32 * ((tq >> 5) & ~1ull));   // bit offset of tq in the window, 0..126
+        const int sh = off & 63;
+        const uint64_t lo = off < 64 ? wv0 : wv1, mid = off < 64 ? wv1 : wv2, hi = off < 64 ? wv2 : wv3;
+        const uint64_t tt0 = sh ? (lo >> sh) | (mid << (64 - sh)) : lo;
+        const uint64_t tt1 = sh ? (mid >> sh) | (hi << (64 - sh)) : mid;
+        const int rb2 = j & 31;
+        const uint64_t r0 = rb2 ? (a0 >> (2 * rb2)) | (a1 << (64 - 2 * rb2)) : a0;
+        const uint64_t r1 = rb2 ? (a1 >> (2 * rb2)) | (a2 << (64 - 2 * rb2)) : a1;
+        const uint64_t nb = (((uint64_t)n2 << 32 | n1) << (32 - rb2)) | ((uint64_t)n0 >> rb2);
+        const uint64_t d0 = r0 ^ tt0, d1 = r1 ^ tt1;
+        const uint64_t f0 = (d0 | (d0 >> 1)) & 0x5555555555555555ull, f1 = (d1 | (d1 >> 1)) & 0x5555555555555555ull;
+        const int mm = f0 ? (__ffsll((long long)f0) - 1) >> 1 : (f1 ? 32 + ((__ffsll((long long)f1) - 1) >> 1) : 64);
+        const int nf = nb ? __ffsll((long long)nb) - 1 : 64;
+        const uint64_t left = tm - tq;                  // text symbols before the $
+        first = min(min(mm, nf), min(lim0, left < 64 ? (int)left : 64));
+        n_lines += ((((tq >> 5) & ~1ull) & 15) == 14) ? 2 : 1;
+      }
+      j += first;
+      if (!(first == 64 && j < (int)qend)) {            // end of the match: k' from the mirror position
+        const uint64_t pm = tm - *tpl - (uint64_t)(j - i);
+        const uint64_t q = ((pm >> P.rishift) + ((pm & ((1ull << P.rishift) - 1)) ? 1 : 0)) << P.rishift;
+        if (q >= tm) { wrow = 0; wcnt = (uint32_t)(tm - pm); u = 7; }   // row 0 holds the suffix at tm ($)
+        else { wrow = q >> P.rishift; wcnt = (uint32_t)(q - pm); u = 6; }
+      }
+    }
+    if (act == ACT_ISA) { wrow = mval; u = 7; ++n_lines; }
+    if (st_mem == ST_REC) {
+      read_id = t0.x; qbeg = t0.y; qend = t0.z; l = t0.w;
+      c = t1.x; rlen = t1.y; wo = ((uint64_t)t1.w << 32) | t1.z;
+      i = (int)t2.x; j = (int)t2.y;
+      k = ((uint64_t)t3.y << 32) | t3.x;
+      wrow = k; wrow2 = ((uint64_t)t3.w << 32) | t3.z;
+      wcnt = 0; u = 4;
+      const uint64_t b = 8ull * (qend - qbeg) * (qend - qbeg) + 64;
+      budget = b > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)b;
+      st = read_id == INVALID_READ ? ST_IDLE : ST_ACTIVE;
+    }
+    wave_emit(P, lane, em, read_id, e, wout, rlen, wo, tpl);
+    if (__ballot(rs)) {                                 // the rest of the query: another pass
+      const uint64_t rsl = wave_slot(rs, rb, re, &P.ctl[C_PASSQ], lane);
+      if (rs && rsl < P.resume_cap) {
+        Query q;
+        q.read_id = read_id; q.qbeg = qbeg; q.qend = qend; q.l = l; q.c = c; q.rlen = rlen;
+        q.woff_lo = (uint32_t)wo; q.woff_hi = (uint32_t)(wo >> 32); q.send = qend; q.flags = Q_RESUME;
+        q.pad0 = (uint32_t)i; q.pad1 = (uint32_t)j;
+        P.resume[rsl] = q;
+      }
+    }
+  }
+  wave_close(P, lane, wout);
+  for (uint64_t t = rb + lane; t < re; t += 64)
+    if (t < P.resume_cap) P.resume[t].read_id = INVALID_READ;
+  if ((threadIdx.x & 63) == 0 && n_iter) { atomicAdd(&P.ctl[C_WITER], (unsigned long long)n_iter); atomicAdd(&P.ctl[C_LITER], (unsigned long long)n_busy); }
+  wave_stat(&P.ctl[C_LINES], (uint64_t)n_lines);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1273,23 +1508,32 @@ static int persistent_grid(const void *kern, int block, size_t lds, int n_cu, in
 #define AUTO_QUERIES_R2 4000
 #define AUTO_ROWS_LOCATE 24000
 
-template <bool STAGED, bool UNIQ>
+template <bool STAGED, bool UNIQ, bool DEFER = false>
 static int wave_grid(mbw_ctx *c, const SeedParams &P, const mbw_seed_opts &o) {
-  return persistent_grid((const void *)k_smem_wave<STAGED, UNIQ>, 64 * SMEM_WAVES, 0, c->n_cu, o.blocks_per_cu,
+  return persistent_grid((const void *)k_smem_wave<STAGED, UNIQ, DEFER>, 64 * SMEM_WAVES, 0, c->n_cu, o.blocks_per_cu,
                          P.n_queries, P.round == 1 ? AUTO_QUERIES_R1 : AUTO_QUERIES_R2);
 }
 
-static int smem_grid(mbw_ctx *c, const SeedParams &P, const mbw_seed_opts &o, bool staged) {
+// kinds of SMEM-stage launch: the SMEM kernel, with deferred unique matches, the continuation kernel
+enum { L_SMEM = 0, L_DEFER = 1, L_UNIQUE = 2 };
+
+static int smem_grid(mbw_ctx *c, const SeedParams &P, const mbw_seed_opts &o, bool staged, int kind = L_SMEM) {
+  if (kind == L_UNIQUE)
+    return persistent_grid((const void *)k_unique_wave, 64 * UNIQ_WAVES, 0, c->n_cu, o.blocks_per_cu, P.n_queries,
+                           AUTO_TASKS);
+  if (kind == L_DEFER) return wave_grid<true, false, true>(c, P, o);
   const bool uniq = P.uniq && P.round == 1;
   if (staged) return uniq ? wave_grid<true, true>(c, P, o) : wave_grid<true, false>(c, P, o);
   return uniq ? wave_grid<false, true>(c, P, o) : wave_grid<false, false>(c, P, o);
 }
 
 static int launch_smem(const IndexView &v, SeedParams &P, const ReadWords &R, const mbw_seed_opts &o, bool staged,
-                       int grid, hipStream_t st) {
+                       int grid, hipStream_t st, int kind) {
   const bool uniq = P.uniq && P.round == 1;
   const int bs = 64 * SMEM_WAVES;
-  if (o.kernel == MBW_KERNEL_PLAIN) k_smem_plain<<<grid_for(P.n_queries, 256), 256, 0, st>>>(v, P);
+  if (kind == L_UNIQUE) k_unique_wave<<<grid, 64 * UNIQ_WAVES, 0, st>>>(v, P, R);
+  else if (kind == L_DEFER) k_smem_wave<true, false, true><<<grid, bs, 0, st>>>(v, P, R);
+  else if (o.kernel == MBW_KERNEL_PLAIN) k_smem_plain<<<grid_for(P.n_queries, 256), 256, 0, st>>>(v, P);
   else if (staged) {
     if (uniq) k_smem_wave<true, true><<<grid, bs, 0, st>>>(v, P, R);
     else k_smem_wave<true, false><<<grid, bs, 0, st>>>(v, P, R);
@@ -1316,22 +1560,24 @@ static int flush_launch_times(mbw_ctx *c) {
     c->ms_smem += ms;
     const mbw_ctx::LaunchNote &n = c->pending[t];
     if (trace_on())
-      fprintf(stderr, "{\"mbw\": \"smem_launch\", \"round\": %d, \"staged\": %d, \"queries\": %llu, \"blocks\": %d, "
-              "\"chunk\": %u, \"ms\": %.3f}\n", n.round, n.staged, (unsigned long long)n.queries, n.grid, n.chunk, ms);
+      fprintf(stderr, "{\"mbw\": \"smem_launch\", \"round\": %d, \"staged\": %d, \"kind\": \"%s\", \"queries\": %llu, "
+              "\"blocks\": %d, \"chunk\": %u, \"ms\": %.3f}\n", n.round, n.staged,
+              n.kind == L_UNIQUE ? "unique" : (n.kind == L_DEFER ? "defer" : "smem"), (unsigned long long)n.queries, n.grid,
+              n.chunk, ms);
   }
   c->n_pending = 0;
   return 0;
 }
 
 static int run_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const ReadWords &R, const mbw_seed_opts &o, bool staged,
-                    hipStream_t st) {
+                    hipStream_t st, int kind = L_SMEM) {
   if (P.n_queries == 0) return 0;
-  const int grid = o.kernel == MBW_KERNEL_PLAIN ? 0 : smem_grid(c, P, o, staged);
+  const int grid = (o.kernel == MBW_KERNEL_PLAIN && kind == L_SMEM) ? 0 : smem_grid(c, P, o, staged, kind);
   // at least ~8 grabs per wave of the persistent grid, so that long queries (queued longest
   // first) spread over the whole chip
   if (o.wave_chunk > 0) P.chunk = (uint32_t)std::min(WORK_CHUNK, o.wave_chunk);
   else {
-    const uint64_t waves = (uint64_t)std::max(grid, 1) * SMEM_WAVES;
+    const uint64_t waves = (uint64_t)std::max(grid, 1) * (kind == L_UNIQUE ? UNIQ_WAVES : SMEM_WAVES);
     uint64_t ch = P.n_queries / (waves * 8);
     P.chunk = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(WORK_CHUNK, ch));
   }
@@ -1341,31 +1587,12 @@ static int run_smem(mbw_ctx *c, const IndexView &v, SeedParams &P, const ReadWor
     if (r) return r;
   }
   const int slot = c->n_pending++;
-  c->pending[slot] = {P.round, (int)staged, grid, P.n_queries, P.chunk};
+  c->pending[slot] = {P.round, (int)staged, kind, grid, P.n_queries, P.chunk};
   TRY(hipEventRecord(c->lev[2 * slot], st));
-  int r = launch_smem(v, P, R, o, staged, grid, st);
+  int r = launch_smem(v, P, R, o, staged, grid, st, kind);
   if (r) return r;
   TRY(hipEventRecord(c->lev[2 * slot + 1], st));
   c->n_smem_launches++;
-  return 0;
-}
-
-// one seeding round: the staged kernel over qs[0, ns), the unstaged one over ql[0, nl); each launch
-// starts its own work counter
-static int run_binned(mbw_ctx *c, const IndexView &v, SeedParams &P, const ReadWords &R, const mbw_seed_opts &o,
-                      const Query *qs, uint64_t ns, const Query *ql, uint64_t nl, hipStream_t st) {
-  if (ns) {
-    TRY(hipMemsetAsync(P.ctl + C_WORK, 0, 8, st));
-    P.queries = qs; P.n_queries = ns;
-    int r = run_smem(c, v, P, R, o, true, st);
-    if (r) return r;
-  }
-  if (nl) {
-    TRY(hipMemsetAsync(P.ctl + C_WORK, 0, 8, st));
-    P.queries = ql; P.n_queries = nl;
-    int r = run_smem(c, v, P, R, o, false, st);
-    if (r) return r;
-  }
   return 0;
 }
 
@@ -1393,6 +1620,91 @@ static int fetch(mbw_ctx *c, hipStream_t st, std::initializer_list<FetchItem> it
   return flush_launch_times(c);
 }
 #define FETCH(...) do { int r_ = fetch(c, st, __VA_ARGS__); if (r_) return r_; } while (0)
+
+// zero two counters of the control block
+__global__ void k_ctl_zero(unsigned long long *ctl, int a, int b) {
+  if (threadIdx.x == 0) { ctl[a] = 0; ctl[b] = 0; }
+}
+
+// Slots a pass of the deferred unique-match path may need beyond its valid entries: one partly
+// used output chunk per wave of the largest grid.
+static uint64_t defer_slack(const mbw_ctx *c) {
+  int per = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_smem_wave<true, false, true>, 64 * SMEM_WAVES, 0) !=
+          hipSuccess || per < 1)
+    per = 4;
+  int per_u = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_u, (const void *)k_unique_wave, 64 * UNIQ_WAVES, 0) != hipSuccess ||
+      per_u < 1)
+    per_u = 8;
+  const uint64_t waves = (uint64_t)c->n_cu * std::max(per * SMEM_WAVES, per_u * UNIQ_WAVES);
+  return waves * OUT_CHUNK;
+}
+
+#define DEFER_SLACK_PASSES 4         // passes whose partly used output chunks the first sizing allows for
+
+// Round 1 of the staged bin with deferred unique matches: the SMEM kernel over the queries writes
+// the unique matches it reaches to the task list, the continuation kernel finishes them and lists
+// the queries that go on; the two alternate until no query is left.  Every pass advances each of
+// its queries past at least one SMEM end, so a read of at most STAGE_MAX bases needs at most
+// STAGE_MAX + 1 passes.
+static int run_deferred(mbw_ctx *c, const IndexView &v, SeedParams &P, const ReadWords &R, const mbw_seed_opts &o,
+                        const Query *qs, uint64_t ns, hipStream_t st) {
+  const uint64_t cap = ns + defer_slack(c);
+  GROW(c->utask, cap * sizeof(UTask));
+  GROW(c->ures, cap * sizeof(Query));
+  const Query *q = qs;
+  uint64_t nq = ns;
+  for (int pass = 0;; ++pass) {
+    if (pass > STAGE_MAX + 1) { mbw_set_error("internal: unique-match passes did not end"); return MBW_E_INVAL; }
+    k_ctl_zero<<<1, 64, 0, st>>>(P.ctl, C_WORK, C_PASSQ);
+    TRY(hipGetLastError());
+    SeedParams Pd = P;
+    Pd.queries = q; Pd.n_queries = nq; Pd.tasks = (UTask *)c->utask.p; Pd.task_cap = cap;
+    int r = run_smem(c, v, Pd, R, o, true, st, L_DEFER);
+    if (r) return r;
+    uint64_t nt = 0;
+    FETCH({{P.ctl + C_PASSQ, 1}}, &nt);
+    if (nt > cap) { mbw_set_error("internal: task list overflow"); return MBW_E_INVAL; }
+    if (!nt) break;
+    k_ctl_zero<<<1, 64, 0, st>>>(P.ctl, C_WORK, C_PASSQ);
+    TRY(hipGetLastError());
+    SeedParams Pu = P;
+    Pu.tasks = (UTask *)c->utask.p; Pu.n_queries = nt; Pu.resume = (Query *)c->ures.p; Pu.resume_cap = cap;
+    r = run_smem(c, v, Pu, R, o, true, st, L_UNIQUE);
+    if (r) return r;
+    uint64_t nr = 0;
+    FETCH({{P.ctl + C_PASSQ, 1}}, &nr);
+    if (nr > cap) { mbw_set_error("internal: resume list overflow"); return MBW_E_INVAL; }
+    if (!nr) break;
+    q = (const Query *)c->ures.p;
+    nq = nr;
+  }
+  return 0;
+}
+
+// one seeding round: the staged kernel over qs[0, ns), the unstaged one over ql[0, nl); each launch
+// starts its own work counter
+static int run_binned(mbw_ctx *c, const IndexView &v, SeedParams &P, const ReadWords &R, const mbw_seed_opts &o,
+                      const Query *qs, uint64_t ns, const Query *ql, uint64_t nl, hipStream_t st, bool defer = false) {
+  if (ns && defer) {
+    int r = run_deferred(c, v, P, R, o, qs, ns, st);
+    if (r) return r;
+  } else if (ns) {
+    TRY(hipMemsetAsync(P.ctl + C_WORK, 0, 8, st));
+    P.queries = qs; P.n_queries = ns;
+    int r = run_smem(c, v, P, R, o, true, st);
+    if (r) return r;
+  }
+  if (nl) {
+    TRY(hipMemsetAsync(P.ctl + C_WORK, 0, 8, st));
+    P.queries = ql; P.n_queries = nl;
+    int r = run_smem(c, v, P, R, o, false, st);
+    if (r) return r;
+  }
+  return 0;
+}
+
 
 // round 2 starts from round 1's seed count and line statistics again on a retry
 __global__ void k_ctl_restore(unsigned long long *ctl, unsigned long long n1, unsigned long long l0, unsigned long long l1,
@@ -1444,6 +1756,9 @@ static MbwSizeModel size_model(const mbw_ctx *c, uint64_t n, uint64_t bases, boo
   b += seeds * (sizeof(SeedRec) + sizeof(Query) + 16 + 8 + 8 + 24);   // seeds, sub-queries, sort, per-seed counts
   b += rows * (8 + 8 + 4 + 8 + 8 + 4 + 4 + 8);           // rows, positions, filter and refinement arrays
   b += 16ull << 20;                                      // temporary storage of sorts and scans
+  if (o.unique_defer == 1)                               // task and resume lists, output chunks of the passes
+    b += (n + defer_slack(c)) * (sizeof(UTask) + sizeof(Query)) +
+         DEFER_SLACK_PASSES * defer_slack(c) * (sizeof(SeedRec) + sizeof(Query) + 16 + 8 + 8 + 24);
   MbwSizeModel m;
   m.ws = b;
   m.seeds = recs;
@@ -1478,6 +1793,7 @@ static int seed_impl(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, 
   }
   if (o.min_occ < 1) { mbw_set_error("min_occ must be >= 1"); return MBW_E_INVAL; }
   if (o.wave_chunk < 0 || o.wave_chunk > WORK_CHUNK) { mbw_set_error("wave_chunk must be in [0,256]"); return MBW_E_INVAL; }
+  if (o.unique_defer < 0 || o.unique_defer > 1) { mbw_set_error("unique_defer must be 0 or 1"); return MBW_E_INVAL; }
   if (o.bs_role && !c->ix->bisulfite) { mbw_set_error("bs_role needs a bisulfite index"); return MBW_E_INVAL; }
   if (o.bs_refine && (!o.bs_role || !c->ix->orig)) {
     mbw_set_error("bs_refine needs bs_role and a bisulfite index"); return MBW_E_INVAL;
@@ -1631,6 +1947,10 @@ static int seed_impl(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, 
       Pg.n_queries = nqb;
       chunk_slack += (uint64_t)smem_grid(c, Pg, o, b == 0) * SMEM_WAVES * OUT_CHUNK;
     }
+  // Deferred unique matches (staged reads, round 1), when asked for: every pass may leave partly
+  // used output chunks (the first few passes carry nearly all the work)
+  const bool defer = coop && P.uniq && nshort1 > 0 && o.unique_defer == 1;
+  if (defer) chunk_slack += DEFER_SLACK_PASSES * defer_slack(c);
   uint64_t seed_cap = std::max<uint64_t>(1 << 16, n_reads * 6) + chunk_slack;
   if (c->raw.bytes / sizeof(SeedRec) > seed_cap) seed_cap = c->raw.bytes / sizeof(SeedRec);
   uint64_t subq_cap = std::max<uint64_t>(1 << 14, n_reads) + chunk_slack;
@@ -1643,7 +1963,7 @@ static int seed_impl(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, 
     subq_cap = c->subq.bytes / sizeof(Query);
     P.seeds = (SeedRec *)c->raw.p; P.seed_cap = seed_cap; P.subq = (Query *)c->subq.p; P.subq_cap = subq_cap;
     TRY(hipMemsetAsync(ctl, 0, 8 * sizeof(unsigned long long), st));
-    if (coop) r = run_binned(c, v, P, R, o, q1, nshort1, (const Query *)c->q1s.p, nlong1, st);
+    if (coop) r = run_binned(c, v, P, R, o, q1, nshort1, (const Query *)c->q1s.p, nlong1, st, defer);
     else r = run_smem(c, v, P, R, o, false, st);
     if (r) return r;
     {

@@ -4,7 +4,9 @@ The SMEM set, each interval and each position set are fixed by the reads and the
 result must not depend on how the work is scheduled.  On ragged reads (20-700 bases, N runs) over
 the 1 Mbp genome, bit-exact in canonical order:
   * length binning on / off x persistent blocks per CU (sized by the work, occupancy limit, 2,
-    1) x segment length (32, default) x unique-match path on / off, against the oracle;
+    1) x segment length (32, default) x unique-match path on / off, against the oracle; the unique
+    matches of staged reads finished in alternating continuation passes, under several grids and
+    work chunks;
   * the same call twice (determinism, byte for byte);
   * the batch split at arbitrary points (read ids offset), against the whole batch;
   * the reads in shuffled order (seeds mapped back through the permutation).
@@ -58,6 +60,13 @@ def test_every_schedule_matches_the_oracle(setup):
         out = ctx.seed(reads.seq, reads.lengths, wave_chunk=chunk)
         s, p = out.download()
         compare_with_oracle(s, p, exp)
+    for bpc, chunk, seg in itertools.product((0, -1, 1), (0, 1, 64), (32, 0)):
+        out = ctx.seed(reads.seq, reads.lengths, unique_defer=1, blocks_per_cu=bpc, wave_chunk=chunk, seg_len=seg)
+        s, p = out.download()
+        compare_with_oracle(s, p, exp)
+    for bad in (-1, 2):
+        with pytest.raises(mbw.MbwError):
+            ctx.seed(reads.seq, reads.lengths, unique_defer=bad)
     with pytest.raises(mbw.MbwError):
         ctx.seed(reads.seq, reads.lengths, wave_chunk=257)
     ctx.free()

@@ -152,16 +152,21 @@ def cfg0():
     return ref, reads, ox, exp
 
 
-@pytest.mark.parametrize("kernel,K,ri,uniq", [(0, 10, 4, True), (0, 10, 4, False), (0, 0, 1, True), (1, 0, 4, True),
-                                              (0, 12, 8, True), (0, 12, 0, True), (0, 14, 4, True), (1, 14, 4, True),
-                                              (0, 15, 4, True)])
-def test_small_workload_parity(cfg0, kernel, K, ri, uniq):
+@pytest.mark.parametrize("kernel,K,ri,uniq,defer", [(0, 10, 4, True, 0), (0, 10, 4, False, 0), (0, 0, 1, True, 0),
+                                                    (1, 0, 4, True, 0), (0, 12, 8, True, 0), (0, 12, 0, True, 0),
+                                                    (0, 14, 4, True, 0), (1, 14, 4, True, 0), (0, 15, 4, True, 0),
+                                                    (0, 10, 4, True, 1), (0, 0, 1, True, 1), (0, 12, 8, True, 1),
+                                                    (0, 15, 1, True, 1)])
+def test_small_workload_parity(cfg0, kernel, K, ri, uniq, defer):
     """1 Mbp + repeat family reference, 10,000 x 150 bp reads, (19,1)-SMEMs with re-seeding,
     max_occ 500: every seed, interval and position equals the oracle's, with and without the
-    direct extension of unique matches (inverse-SA samples every ri text positions)."""
+    direct extension of unique matches (inverse-SA samples every ri text positions), and with the
+    unique matches finished in the lane (defer 0) or by the continuation kernel in alternating
+    passes (defer 1)."""
     ref, reads, ox, exp = cfg0
     idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=K, isa_sample=ri)
-    out, seeds, pos = gpu_seed(idx, reads, min_seed_len=19, max_occ=500, kernel=kernel, unique_ext=uniq)
+    out, seeds, pos = gpu_seed(idx, reads, min_seed_len=19, max_occ=500, kernel=kernel, unique_ext=uniq,
+                               unique_defer=defer)
     compare_with_oracle(seeds, pos, exp)
     assert out.n_seeds == len(exp)
     idx.free()
@@ -399,9 +404,10 @@ def test_bisulfite_refinement():
 # relative to a superblock, the superblock table, lines on both sides of a boundary) that the
 # 3.1 Gbp indexes need, checked against the definition oracle with every field compared
 
-@pytest.mark.parametrize("kernel,K,ri,uniq", [(0, 10, 4, True), (0, 10, 4, False), (0, 0, 1, True), (1, 10, 4, True),
-                                              (0, 15, 4, True), (1, 0, 0, True)])
-def test_multi_superblock_parity(cfg0, kernel, K, ri, uniq):
+@pytest.mark.parametrize("kernel,K,ri,uniq,defer", [(0, 10, 4, True, 0), (0, 10, 4, False, 0), (0, 0, 1, True, 0),
+                                                    (1, 10, 4, True, 0), (0, 15, 4, True, 0), (1, 0, 0, True, 0),
+                                                    (0, 15, 1, True, 1), (0, 10, 4, True, 1)])
+def test_multi_superblock_parity(cfg0, kernel, K, ri, uniq, defer):
     """The 1 Mbp workload on an index with 2^10 lines (393,216 rows) per superblock, so that its
     2,080,001 rows span 6 superblocks: every seed, ds-interval (k, k', s) and position of all
     10,000 reads equals O1's, with and without the unique-match path."""
@@ -409,7 +415,8 @@ def test_multi_superblock_parity(cfg0, kernel, K, ri, uniq):
     idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=K, isa_sample=ri, sb_lines_log2=10)
     info = idx.info()
     assert info["sb_lines_log2"] == 10 and info["n_superblocks"] == 6
-    out, seeds, pos = gpu_seed(idx, reads, min_seed_len=19, max_occ=500, kernel=kernel, unique_ext=uniq)
+    out, seeds, pos = gpu_seed(idx, reads, min_seed_len=19, max_occ=500, kernel=kernel, unique_ext=uniq,
+                               unique_defer=defer)
     compare_with_oracle(seeds, pos, exp)
     # seeds whose intervals lie wholly past the first superblock (k and k + s above 393,216)
     assert np.sum(seeds["k"] > 393_216 * 2) > 1000
