@@ -154,7 +154,10 @@ __global__ void __launch_bounds__(PACK_BLOCK) k_pack_words(const uint8_t *__rest
                                                            const uint64_t *__restrict__ offs, const uint64_t *__restrict__ woff,
                                                            const uint32_t *__restrict__ wread, uint64_t totw, int role,
                                                            uint64_t *__restrict__ pw, uint32_t *__restrict__ pn) {
-  __shared__ uint32_t buf[PACK_BLOCK * 8 + 16];         // the range (<= 32 * PACK_BLOCK + 3 bytes) + reads past it
+  // the range (<= 32 * PACK_BLOCK + 30 bytes from a 16-byte boundary) in 32-bit words, one pad word
+  // after every 8 (word i at i + i / 8), so that the 32 words that a thread converts, 8 words after its
+  // neighbour's, fall in distinct banks
+  __shared__ uint32_t buf[(PACK_BLOCK * 8 + 16) * 9 / 8 + 4];
   __shared__ uint64_t range[2];
   const uint64_t w0 = (uint64_t)blockIdx.x * PACK_BLOCK;
   if (w0 >= totw) return;
@@ -166,19 +169,26 @@ __global__ void __launch_bounds__(PACK_BLOCK) k_pack_words(const uint8_t *__rest
   }
   __syncthreads();
   const uint64_t b0 = range[0], b1 = range[1];
-  const uint64_t a0 = b0 & ~3ull;                       // first aligned dword of the range
-  const uint32_t ndw = (uint32_t)((b1 - a0 + 3) >> 2);  // <= 8 * PACK_BLOCK + 1
-  const bool aligned = (((uintptr_t)ascii) & 3) == 0;
-  for (uint32_t t = threadIdx.x; t < ndw; t += PACK_BLOCK) {
-    const uint64_t byte = a0 + 4ull * t;
-    uint32_t v;
-    if (aligned && byte + 4 <= total) v = *(const uint32_t *)(ascii + byte);
-    else {
-      v = 0;
-      for (int q = 0; q < 4; ++q)
-        if (byte + q < total) v |= (uint32_t)ascii[byte + q] << (8 * q);
+  const uint64_t a0 = b0 & ~15ull;                      // first 16-byte boundary of the range
+  const uint32_t nq = (uint32_t)((b1 - a0 + 15) >> 4);  // 16-byte pieces, <= 2 * PACK_BLOCK + 2
+  const bool aligned = (((uintptr_t)ascii) & 15) == 0;
+  auto pad = [](uint32_t i) { return i + (i >> 3); };
+  for (uint32_t t = threadIdx.x; t < nq; t += PACK_BLOCK) {
+    const uint64_t byte = a0 + 16ull * t;
+    uint32_t v[4];
+    if (aligned && byte + 16 <= total) {
+      const uint4 x = *(const uint4 *)(ascii + byte);
+      v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        v[u] = 0;
+        for (int q = 0; q < 4; ++q)
+          if (byte + 4 * u + q < total) v[u] |= (uint32_t)ascii[byte + 4 * u + q] << (8 * q);
+      }
     }
-    buf[t] = v;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) buf[pad(4 * t + u)] = v[u];
   }
   __syncthreads();
   const uint64_t w = w0 + threadIdx.x;
@@ -192,7 +202,7 @@ __global__ void __launch_bounds__(PACK_BLOCK) k_pack_words(const uint8_t *__rest
 #pragma unroll
   for (int q = 0; q < 8; ++q) {                        // four bases per step, no branches
     const uint32_t bo = boff + 4 * q, sh = (bo & 3) * 8;
-    const uint32_t lo = buf[bo >> 2], hi = buf[(bo >> 2) + 1];
+    const uint32_t lo = buf[pad(bo >> 2)], hi = buf[pad((bo >> 2) + 1)];
     const uint32_t d = sh ? (lo >> sh) | (hi << (32 - sh)) : lo;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -1185,19 +1195,25 @@ __global__ void k_seed_posoff(mbw_seed_t *__restrict__ out, const uint64_t *__re
     out[t].pos_off = off[t];
 }
 
-// start row of every (seed, occurrence) pair: X[pos_off + i] = k + i.  A wave takes 64 seeds; a
-// seed with few rows is written by its own lane (neighbouring lanes write neighbouring runs), a
-// seed with many by all lanes of the wave (coalesced).  A seed whose position the unique-match
-// path already found gets it written to the output and NO_POS in X (locate skips it).
+// start row of every (seed, occurrence) pair: X[pos_off + i] = k + i, with pos_off (the exclusive
+// sum of the seeds' position counts) also stored in the seed.  A wave takes 64 seeds; a seed with
+// few rows is written by its own lane (neighbouring lanes write neighbouring runs), a seed with many
+// by all lanes of the wave (coalesced).  A seed whose position the unique-match path already found
+// gets it written to the output and NO_POS in X (locate skips it).
 #define EXPAND_LANE_MAX 8
-__global__ void __launch_bounds__(256) k_expand_rows(const mbw_seed_t *__restrict__ seeds, const uint64_t *__restrict__ kpos,
-                                                     uint64_t ns, uint64_t *__restrict__ X, uint64_t *__restrict__ pos) {
+__global__ void __launch_bounds__(256) k_expand_rows(mbw_seed_t *__restrict__ seeds, const uint64_t *__restrict__ posoff,
+                                                     const uint64_t *__restrict__ kpos, uint64_t ns, uint64_t *__restrict__ X,
+                                                     uint64_t *__restrict__ pos) {
   const int lane = threadIdx.x & 63;
   const uint64_t nwave = (uint64_t)gridDim.x * (blockDim.x >> 6);
   for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64; base < ns; base += nwave * 64) {
     uint64_t k = 0, off = 0, kp = NO_POS;
     uint32_t np = 0;
-    if (base + lane < ns) { const mbw_seed_t sd = seeds[base + lane]; k = sd.k; off = sd.pos_off; np = sd.npos; kp = kpos[base + lane]; }
+    if (base + lane < ns) {
+      const uint64_t t = base + lane;
+      k = seeds[t].k; np = seeds[t].npos; off = posoff[t]; kp = kpos[t];
+      seeds[t].pos_off = off;
+    }
     const bool mine = np <= EXPAND_LANE_MAX;
     if (mine && np == 1 && kp != NO_POS) { X[off] = NO_POS; pos[off] = kp; }
     else if (mine)
@@ -2094,8 +2110,10 @@ static int seed_impl(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, 
     r = prim_call(c, [&](void *tp, size_t &tb) { return prim::exclusive_sum(tp, tb, npos, posoff, nu + 1, st); });
     if (r) return r;
     FETCH({{posoff + nu, 1}}, &n_pos);
-    k_seed_posoff<<<grid_for(nu), 256, 0, st>>>(seeds, posoff, nu);
-    TRY(hipGetLastError());
+    if (!coop || !n_pos) {   // the wave path stores the offsets while it expands the rows
+      k_seed_posoff<<<grid_for(nu), 256, 0, st>>>(seeds, posoff, nu);
+      TRY(hipGetLastError());
+    }
   }
   // positions: straight into the caller's buffer unless a bisulfite filter follows
   uint64_t *posbuf;
@@ -2122,8 +2140,8 @@ static int seed_impl(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, 
       TRY(hipGetLastError());
     } else {
       GROW(c->xrows, (n_pos + 1) * 8);
-      k_expand_rows<<<grid_for((nu + 63) / 64 * 64 / 4, 256, 65536u), 256, 0, st>>>(seeds, (const uint64_t *)c->kpos.p, nu,
-                                                                                     (uint64_t *)c->xrows.p, posbuf);
+      k_expand_rows<<<grid_for((nu + 63) / 64 * 64 / 4, 256, 65536u), 256, 0, st>>>(seeds, posoff, (const uint64_t *)c->kpos.p,
+                                                                                     nu, (uint64_t *)c->xrows.p, posbuf);
       TRY(hipGetLastError());
       const int grid = persistent_grid((const void *)k_locate_wave, 256, 0, c->n_cu, o.blocks_per_cu, n_pos, AUTO_ROWS_LOCATE);
       TRY(hipEventRecord(c->ev[3], st));
