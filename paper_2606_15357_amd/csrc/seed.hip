@@ -27,6 +27,7 @@
 #include <mutex>
 #include <string>
 #include <vector>
+#include <type_traits>
 #include <cstdio>
 #include <cstdlib>
 
@@ -418,17 +419,20 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
   };
   const uint64_t tm = ix.n - 1;   // text length without $
   uint32_t qbeg = 0, qend = 0, l = 0, c = 1, segend = 0;
-  bool segchk = false;            // the SMEM starting at qbeg still needs its left check (stage 8)
+  uint32_t segchk = 0;            // 1: the SMEM starting at qbeg still needs its left check (stage 8)
   int u = 0, i = 0, j = 0;
   uint64_t k = 0, kr = 0, s = 0;
   uint32_t budget = 0;            // iteration guard of the current query (a corrupt index cannot loop forever)
   uint64_t wrow = 0;              // unique path: walk row (or sample index)
   uint64_t wrow2 = 0;             // unique path, first walk: the row of the reverse-complement match
-  bool wmir = false;              // the occurrence was found by the reverse-complement walk
+  // (wcnt's top bit: the occurrence was found by the reverse-complement walk)
   __shared__ uint64_t stp[SMEM_WAVES][64];   // unique path: text position of P[i] (rarely read: kept in LDS)
   uint64_t *tpl = &stp[wv][lane];
   uint32_t wcnt = 0;              // unique path: LF steps taken (stage 4) or still to take (stage 7)
-  bool fresh = false;
+  constexpr uint32_t WMIR = 1u << 31;
+  // 1: the interval is (0, 0, n) and the k-mer shortcut is still to try (an integer except in the
+  // staged kernel with the unique-match path, where a lane mask measured faster)
+  typename std::conditional<STAGED && UNIQ, bool, uint32_t>::type fresh = 0;
   uint32_t n_lines = 0, n_steps = 0, n_kmer = 0;   // per lane (well below 2^32 per launch)
   uint64_t n_iter = 0, n_busy = 0;                 // per wave
   uint32_t chain = 0, max_chain = 0;   // iterations of the current query; longest so far
@@ -460,7 +464,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
         if ((UNIQ || SEG) && u >= 4) {                  // unique path (4-7), segment left check (8)
           if (UNIQ && u == 4) {   // walk both rows of the match until one reaches a sampled row
             const bool s1 = (wrow & P.rmask) == 0, s2 = DUAL && (wrow2 & P.rmask) == 0;
-            if (s1 || s2) { wmir = !s1; if (!s1) wrow = wrow2; act = ACT_SSA; break; }
+            if (s1 || s2) { if (!s1) { wrow = wrow2; wcnt |= WMIR; } act = ACT_SSA; break; }
             if (!DUAL && wrow == ix.primary) { wrow = 0; ++wcnt; continue; }   // LF of the $ row is row 0
             act = ACT_LF; break;
           }
@@ -468,10 +472,10 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
           if (UNIQ && u == 6) { act = ACT_ISA; break; }
           if (UNIQ && u == 7) {
             if (wcnt > 0) { act = ACT_LF; break; }
-            if (SEG && segchk && i == (int)qbeg) { segchk = false; kr = wrow; s = 1; u = 8; continue; }
+            if (SEG && segchk != 0 && i == (int)qbeg) { segchk = 0; kr = wrow; s = 1; u = 8; continue; }
             em = true; e.i = i; e.j = j; e.k = k; e.kr = wrow; e.s = 1 | KNOWN_POS;
             if (j == (int)qend) { act = ACT_DONE; break; }
-            u = 3; k = 0; kr = 0; s = ix.n; fresh = true;
+            u = 3; k = 0; kr = 0; s = ix.n; fresh = 1;
             continue;
           }
           // u == 8: left check of a segment's first SMEM [qbeg, j) with interval (k, kr, s)
@@ -479,7 +483,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
           if (a <= 3) { act = ACT_BWD; break; }
           em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s;   // P[i-1] matches nothing
           if (j == (int)qend) { act = ACT_DONE; break; }
-          u = 3; k = 0; kr = 0; s = ix.n; fresh = true;
+          u = 3; k = 0; kr = 0; s = ix.n; fresh = 1;
           continue;
         }
         if (u == 2) {
@@ -488,33 +492,33 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
           if (UNIQ && !qe && P.uniq && s == 1) { u = 4; wrow = k; wrow2 = kr; wcnt = 0; continue; }
           if (DEFER && !qe && s == 1) { dfr = true; act = ACT_DONE; break; }
           if (a > 3) {                                  // end of the query, or a non-ACGT base: SMEM [i, j)
-            if (SEG && segchk && i == (int)qbeg) { segchk = false; u = 8; continue; }
+            if (SEG && segchk != 0 && i == (int)qbeg) { segchk = 0; u = 8; continue; }
             em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s;
             if (qe) { act = ACT_DONE; break; }
-            u = 3; k = 0; kr = 0; s = ix.n; fresh = true;
+            u = 3; k = 0; kr = 0; s = ix.n; fresh = 1;
             continue;
           }
           act = ACT_FWD; break;
         }
-        if (u == 1 && j < i) { u = 2; j = i + (int)l; fresh = false; continue; }
+        if (u == 1 && j < i) { u = 2; j = i + (int)l; fresh = 0; continue; }
         if (u == 3 && j <= i) {
           if (SEG && j + 1 >= (int)segend) { act = ACT_DONE; break; }   // the next start belongs to the next segment
-          u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; continue;
+          u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = 1; continue;
         }
-        if (fresh && K > 0 && j - K + 1 >= (u == 1 ? i : i + 1)) {
+        if (fresh != 0 && K > 0 && j - K + 1 >= (u == 1 ? i : i + 1)) {
           // k-mer P[j-K+1 .. j] from the packed read: its code is the bit field 2(j-K+1) .. 2(j+1)
           const int a0 = j - K + 1, w = a0 >> 5, b0 = a0 & 31;
           uint64_t bits = word_at(w) >> (2 * b0);
           uint32_t nbits = nbits_at(w) >> b0;
           if (b0 + K > 32) { bits |= word_at(w + 1) << (64 - 2 * b0); nbits |= nbits_at(w + 1) << (32 - b0); }
-          fresh = false;
+          fresh = 0;
           if ((nbits & ((1u << K) - 1)) == 0) { code = (uint32_t)(bits & ((1ull << (2 * K)) - 1)); act = ACT_KMER; break; }
         }
-        fresh = false;
+        fresh = 0;
         a = base_at(j);
         if (a > 3) {                                    // BackStep fails on a non-ACGT base
           if (j + (int)l < (int)qend && (!SEG || j + 1 < (int)segend)) {
-            u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; continue;
+            u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = 1; continue;
           }
           act = ACT_DONE; break;
         }
@@ -657,25 +661,25 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
         if (SEG && u == 8) {                              // left check: report unless P[i-1, j) occurs c times
           if (ns < c) { em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s; }
           if (j == (int)qend) st = ST_IDLE;
-          else { u = 3; k = 0; kr = 0; s = ix.n; fresh = true; }
+          else { u = 3; k = 0; kr = 0; s = ix.n; fresh = 1; }
         } else if (ns >= c) {
           if (bwd) { k = nx; kr = ny; s = ns; j -= 1; }
           else { kr = nx; k = ny; s = ns; j += 1; }
         } else if (bwd) {                                 // BackStep failure: jump past j
-          if (j + (int)l < (int)qend && (!SEG || j + 1 < (int)segend)) { u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = true; }
+          if (j + (int)l < (int)qend && (!SEG || j + 1 < (int)segend)) { u = 1; i = j + 1; j = j + (int)l; k = 0; kr = 0; s = ix.n; fresh = 1; }
           else st = ST_IDLE;
-        } else if (SEG && segchk && i == (int)qbeg) {    // forward failure at a segment's first SMEM
-          segchk = false; u = 8;
+        } else if (SEG && segchk != 0 && i == (int)qbeg) {   // forward failure at a segment's first SMEM
+          segchk = 0; u = 8;
         } else {                                          // forward failure: report, then stage 3 from j
           em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s;
-          u = 3; k = 0; kr = 0; s = ix.n; fresh = true;
+          u = 3; k = 0; kr = 0; s = ix.n; fresh = 1;
         }
       }
     }
     if (UNIQ && act == ACT_SSA) {                       // the occurrence: p = S(row) + steps (mod n)
-      uint64_t pp = mval + wcnt;
+      uint64_t pp = mval + (wcnt & ~WMIR);
       if (pp >= ix.n) pp -= ix.n;
-      if (DUAL && wmir) pp = tm - pp - (uint64_t)(j - i);   // the mirror of the reverse-complement match
+      if (DUAL && (wcnt & WMIR)) pp = tm - pp - (uint64_t)(j - i);   // the mirror of the reverse-complement match
       *tpl = pp;
       u = 5;
       ++n_lines;
@@ -726,7 +730,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
       const uint32_t read_id = q0.x, rlen = q1.y;
       qbeg = q0.y; qend = q0.z; l = q0.w; c = q1.x;
       if (!STAGED) wo = ((uint64_t)q1.w << 32) | q1.z;
-      segend = q2.x; segchk = SEG && (q2.y & SEG_CHECK) != 0;
+      segend = q2.x; segchk = (SEG && (q2.y & SEG_CHECK) != 0) ? 1u : 0u;
       nw = (rlen + 31) >> 5;
       // Algorithm 3 queues a string only if l - 1 < |P|
       const bool work = read_id != INVALID_READ && l >= 1 && l - 1 < qend - qbeg && (!STAGED || nw <= STAGE_WORDS);
@@ -734,7 +738,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
     }
     if ((STAGED && st_mem == ST_STAGE) || (!STAGED && st_mem == ST_REC && st == ST_ACTIVE)) {
       u = 1; i = (int)qbeg; j = (int)(qbeg + l - 1);
-      k = 0; kr = 0; s = ix.n; fresh = true;
+      k = 0; kr = 0; s = ix.n; fresh = 1;
       if (DEFER) {                                      // a query resumed after its unique match
         const uint4 q2 = sq[wv][2][lane];
         if (q2.y & Q_RESUME) { u = 3; i = (int)q2.z; j = (int)q2.w; }
