@@ -42,7 +42,8 @@ EXPORTS = ["mbw_strerror", "mbw_last_error", "mbw_index_build", "mbw_index_save"
            "mbw_seed", "mbw_result_download", "mbw_pos_to_ref", "mbw_tune",
            "mbw_result_download_pieces", "mbw_serve_open", "mbw_serve_submit", "mbw_serve_submit_nocopy", "mbw_serve_wait", "mbw_serve_release", "mbw_serve_stats",
            "mbw_serve_close", "mbw_rescue_filter", "mbw_rescue_download", "mbw_debug_set_mem_limit", "mbw_chain",
-           "mbw_chain_download", "mbw_seed_into", "mbw_seed_static"]
+           "mbw_chain_download", "mbw_seed_into", "mbw_seed_static", "mbw_graph_create", "mbw_graph_info",
+           "mbw_graph_seed", "mbw_graph_free"]
 
 
 class MbwError(RuntimeError):
@@ -61,6 +62,11 @@ class IndexInfo(C.Structure):
                 ("bytes_resident", C.c_uint64), ("C", C.c_uint64 * 5), ("bases_per_line", C.c_int),
                 ("line_bytes", C.c_int), ("sa_sample", C.c_int), ("kmer_k", C.c_int), ("bisulfite", C.c_int),
                 ("device", C.c_int), ("isa_sample", C.c_int), ("sb_lines_log2", C.c_int), ("n_superblocks", C.c_int)]
+
+
+class GraphPlan(C.Structure):
+    _fields_ = [("max_reads", C.c_uint64), ("max_bases", C.c_uint64), ("max_seeds", C.c_uint64),
+                ("max_subqueries", C.c_uint64), ("max_positions", C.c_uint64)]
 
 
 class SeedOpts(C.Structure):
@@ -187,6 +193,11 @@ def load_library():
     L.mbw_debug_set_mem_limit.argtypes = [u64]
     L.mbw_chain.argtypes = [vp, C.POINTER(Result), u64, C.POINTER(ChainOpts), vp, C.POINTER(ChainResult)]
     L.mbw_chain_download.argtypes = [vp, C.POINTER(ChainResult), vp, vp]
+    L.mbw_graph_create.argtypes = [vp, C.POINTER(GraphPlan), i32, i32, C.POINTER(SeedOpts), C.POINTER(vp)]
+    L.mbw_graph_info.argtypes = [vp, C.POINTER(GraphPlan)]
+    L.mbw_graph_seed.argtypes = [vp, vp, vp, u64, vp, C.POINTER(Result)]
+    L.mbw_graph_free.argtypes = [vp]
+    L.mbw_graph_free.restype = None
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
@@ -425,6 +436,45 @@ class RescueOutput:
         return hits, passed
 
 
+class Graph:
+    """A captured seeding graph (``mbw_graph_*``) of a context; results point into its buffers until
+    its next call."""
+
+    def __init__(self, ctx, h):
+        self._ctx = ctx
+        self._lib = ctx._lib
+        self._h = h
+
+    def plan(self) -> dict:
+        p = GraphPlan()
+        _check(self._lib.mbw_graph_info(self._h, C.byref(p)))
+        return {f: int(getattr(p, f)) for f, _ in GraphPlan._fields_}
+
+    def seed(self, reads, lengths, stream=None) -> "SeedOutput":
+        n = int(lengths.numel() if hasattr(lengths, "numel") else len(lengths))
+        if isinstance(lengths, np.ndarray):
+            lengths = np.ascontiguousarray(lengths, dtype=np.uint32)
+        if isinstance(reads, np.ndarray):
+            reads = np.ascontiguousarray(reads, dtype=np.uint8)
+        res = Result()
+        _check(self._lib.mbw_graph_seed(self._h, _ptr(reads) if n else None, _ptr(lengths) if n else None, n,
+                                        _stream_handle(stream), C.byref(res)))
+        return SeedOutput(res.n_seeds, res.n_pos, res.seeds or 0, res.pos or 0, res.lines_smem, res.lines_locate,
+                          res.steps, res.lf_steps, res.ms_smem, res.ms_locate, res.ms_total, res.n_smem_launches,
+                          res.wave_iters, res.lane_iters, res.max_chain, res, self._ctx)
+
+    def free(self):
+        if self._h:
+            self._lib.mbw_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
 class Context:
     """Work space for a stream of ``mbw_seed`` / ``mbw_rescue_filter`` calls against one index."""
 
@@ -544,6 +594,16 @@ class Context:
                                    C.byref(res)))
         return ChainOutput(res.n_chains, res.n_anchors, res.n_input_anchors, res.ms_kernel, res.ms_total,
                            res.max_read_anchors, res.reads_over_lds, res, self)
+
+    def graph(self, max_reads: int, max_bases: int = 0, max_seeds: int = 0, max_subqueries: int = 0,
+              max_positions: int = 0, min_seed_len: int = 19, max_occ: int = 500, **kw) -> "Graph":
+        """``mbw_graph_create``: the seeding path captured once as a HIP graph for batches of at most
+        ``max_reads`` reads of at most 160 bases (options as for :meth:`seed`)."""
+        plan = GraphPlan(int(max_reads), int(max_bases), int(max_seeds), int(max_subqueries), int(max_positions))
+        h = C.c_void_p()
+        _check(self._lib.mbw_graph_create(self._h, C.byref(plan), int(min_seed_len), int(max_occ),
+                                          C.byref(self._opts(kw)), C.byref(h)))
+        return Graph(self, h)
 
     def tune(self, reads, lengths, min_seed_len: int = 19, max_occ: int = 500, stream=None, cache=None,
              **base) -> dict:

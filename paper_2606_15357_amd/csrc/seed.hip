@@ -88,6 +88,8 @@ struct SeedParams {
   uint64_t task_cap;
   Query *__restrict__ resume;
   uint64_t resume_cap;
+  // captured graphs: the query count on the device (at most n_queries, which sized the grid)
+  const unsigned long long *__restrict__ nq_dev;
 };
 
 struct ReadWords {
@@ -149,12 +151,18 @@ __global__ void k_word_owner(const uint64_t *__restrict__ woff, uint64_t n, uint
 // one thread per packed word: 32 ASCII bases -> 2-bit codes + N bits (bisulfite conversion as in
 // k_encode; the code of an ACGT byte is its bits 1-2 with the Gray-code swap of G and T).  The words of a block cover one contiguous byte range of the reads (reads are stored
 // back to back and split into words in order), which the block first copies into LDS with
-// coalesced 4-byte loads (byte loads at the ends of the buffer).
+// coalesced 16-byte loads (byte loads at the ends of the buffer).
 #define PACK_BLOCK 256
 __global__ void __launch_bounds__(PACK_BLOCK) k_pack_words(const uint8_t *__restrict__ ascii, uint64_t total,
                                                            const uint64_t *__restrict__ offs, const uint64_t *__restrict__ woff,
                                                            const uint32_t *__restrict__ wread, uint64_t totw, int role,
-                                                           uint64_t *__restrict__ pw, uint32_t *__restrict__ pn) {
+                                                           uint64_t *__restrict__ pw, uint32_t *__restrict__ pn,
+                                                           const uint64_t *__restrict__ total_p = nullptr,
+                                                           const uint64_t *__restrict__ totw_p = nullptr) {
+  // total_p / totw_p (captured graphs): the batch's bytes and words on the device, at most the
+  // capacities total / totw that the grid was sized for
+  if (total_p) total = min(total, *total_p);
+  if (totw_p) totw = min(totw, *totw_p);
   // the range (<= 32 * PACK_BLOCK + 30 bytes from a 16-byte boundary) in 32-bit words, one pad word
   // after every 8 (word i at i + i / 8), so that the 32 words that a thread converts, 8 words after its
   // neighbour's, fall in distinct banks
@@ -418,6 +426,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
     return ((nbits_at(w) >> b) & 1) ? 4 : (int)((word_at(w) >> (2 * b)) & 3);
   };
   const uint64_t tm = ix.n - 1;   // text length without $
+  const uint64_t nq_total = P.nq_dev ? min(P.n_queries, (uint64_t)*P.nq_dev) : P.n_queries;
   uint32_t qbeg = 0, qend = 0, l = 0, c = 1, segend = 0;
   uint32_t segchk = 0;            // 1: the SMEM starting at qbeg still needs its left check (stage 8)
   int u = 0, i = 0, j = 0;
@@ -443,7 +452,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
     // ---- idle lanes take a query (its record is loaded in this iteration's memory phase)
     const bool want = st == ST_IDLE;
     if (__ballot(want)) {
-      const uint64_t t = wave_take(want, cb, ce, &P.ctl[C_WORK], P.n_queries, lane, P.chunk);
+      const uint64_t t = wave_take(want, cb, ce, &P.ctl[C_WORK], nq_total, lane, P.chunk);
       if (want) { if (t == ~0ull) st = ST_DRAINED; else { qi = (uint32_t)t; st = ST_REC; } }
     }
     if (__ballot(st != ST_DRAINED) == 0) break;
@@ -995,7 +1004,7 @@ __global__ void k_read_partition(const uint64_t *__restrict__ offs, const uint32
 __global__ void k_make_queries(const uint32_t *__restrict__ ids, uint64_t n, const uint64_t *__restrict__ offs,
                                const uint64_t *__restrict__ woff, uint32_t l, uint32_t c, Query *__restrict__ q) {
   for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < n; t += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t r = ids[t];
+    const uint32_t r = ids ? ids[t] : (uint32_t)t;   // no ids: every read, in order
     const uint32_t len = (uint32_t)(offs[r + 1] - offs[r]);
     const uint64_t wo = woff[r];
     Query x;
@@ -1160,12 +1169,15 @@ __global__ void __launch_bounds__(256) k_smem_plain(IndexView ix, SeedParams P) 
 // sort key (read, qbeg, qend); unused slots (read_id INVALID_READ) get key n_reads << 32, after all
 // sort key (read, qbeg, qend) with qb bits for each offset (qb = bit length of the longest read);
 // unused slots sort last as n_reads << 2 qb
+// ns_p (captured graphs): the records written, on the device; slots from there to the capacity ns
+// sort last like unused ones
 __global__ void k_seed_keys(const SeedRec *__restrict__ raw, uint64_t ns, uint64_t n_reads, int qb, uint64_t *__restrict__ key,
-                            uint32_t *__restrict__ val) {
+                            uint32_t *__restrict__ val, const unsigned long long *__restrict__ ns_p = nullptr) {
+  const uint64_t nv = ns_p ? min(ns, (uint64_t)*ns_p) : ns;
   for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < ns; t += (uint64_t)gridDim.x * blockDim.x) {
-    SeedRec r = raw[t];
-    key[t] = r.read_id == INVALID_READ ? (n_reads << (2 * qb))
-                                       : (((uint64_t)r.read_id << (2 * qb)) | ((uint64_t)r.qbeg << qb) | (uint64_t)r.qend);
+    const uint32_t rid = t < nv ? raw[t].read_id : INVALID_READ;
+    key[t] = rid == INVALID_READ ? (n_reads << (2 * qb))
+                                 : (((uint64_t)rid << (2 * qb)) | ((uint64_t)raw[t].qbeg << qb) | (uint64_t)raw[t].qend);
     val[t] = (uint32_t)t;
   }
 }
@@ -1205,9 +1217,13 @@ __global__ void k_seed_posoff(mbw_seed_t *__restrict__ out, const uint64_t *__re
 // by all lanes of the wave (coalesced).  A seed whose position the unique-match path already found
 // gets it written to the output and NO_POS in X (locate skips it).
 #define EXPAND_LANE_MAX 8
+// nu_p / xcap (captured graphs): the seed count on the device, at most ns; rows and positions are
+// written only below xcap
 __global__ void __launch_bounds__(256) k_expand_rows(mbw_seed_t *__restrict__ seeds, const uint64_t *__restrict__ posoff,
                                                      const uint64_t *__restrict__ kpos, uint64_t ns, uint64_t *__restrict__ X,
-                                                     uint64_t *__restrict__ pos) {
+                                                     uint64_t *__restrict__ pos, const uint32_t *__restrict__ nu_p = nullptr,
+                                                     uint64_t xcap = ~0ull) {
+  if (nu_p) ns = min(ns, (uint64_t)*nu_p);
   const int lane = threadIdx.x & 63;
   const uint64_t nwave = (uint64_t)gridDim.x * (blockDim.x >> 6);
   for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64; base < ns; base += nwave * 64) {
@@ -1218,6 +1234,7 @@ __global__ void __launch_bounds__(256) k_expand_rows(mbw_seed_t *__restrict__ se
       k = seeds[t].k; np = seeds[t].npos; off = posoff[t]; kp = kpos[t];
       seeds[t].pos_off = off;
     }
+    if (off + np > xcap) np = 0;
     const bool mine = np <= EXPAND_LANE_MAX;
     if (mine && np == 1 && kp != NO_POS) { X[off] = NO_POS; pos[off] = kp; }
     else if (mine)
@@ -1279,7 +1296,9 @@ __global__ void __launch_bounds__(256) k_locate_plain(IndexView ix, const mbw_se
 // lane's next walk (taken one walk ahead, so a finished lane continues at once).
 __global__ void __launch_bounds__(256) k_locate_wave(IndexView ix, const uint64_t *__restrict__ X, uint64_t n_pos,
                                                      uint64_t *__restrict__ pos, uint32_t rmask, int rshift,
-                                                     unsigned long long *__restrict__ ctl) {
+                                                     unsigned long long *__restrict__ ctl,
+                                                     const uint64_t *__restrict__ np_p = nullptr) {
+  if (np_p) n_pos = min(n_pos, *np_p);   // captured graphs: the row count on the device
   __shared__ uint64_t sbt[MBW_MAX_SB * 8];
   for (int t = threadIdx.x; t < 8 * ix.n_sb; t += blockDim.x) sbt[t] = ix.sbtab[t];
   __syncthreads();
@@ -2422,3 +2441,348 @@ extern "C" int mbw_result_download(mbw_ctx *c, const mbw_result *res, mbw_seed_t
   TRY(hipStreamSynchronize(c->cur));
   return MBW_OK;
 }
+
+// ---------------------------------------------------------------------------------------------
+// Captured graphs (mbw_graph_*).  The seeding path of a batch of reads that fit the LDS staging area
+// is recorded once as a HIP graph over buffers sized by a plan (reads, bases, seeds, sub-queries and
+// positions at most) and replayed for every batch.  Nothing in it needs the host: every count the
+// eager path waits for (bases, packed words, seeds, sub-queries, unique seeds, positions) stays on
+// the device, the kernels that consume one read it there, and grids, sorts and scans span the
+// plan's capacities (unused slots sort last and hold nothing).  The host copies the batch in,
+// launches the graph and waits once, for the counts, which it checks against the plan.
+namespace {
+
+// zero the control block and the lengths of the plan's unused reads (the replayed batch may be
+// smaller than the plan), and the flag past the last seed slot (the unique-seed scan reads it)
+__global__ void k_graph_prep(uint32_t *__restrict__ lens, uint64_t N, const uint64_t *__restrict__ nreads,
+                             unsigned long long *__restrict__ ctl, uint32_t *__restrict__ flag_end) {
+  const uint64_t n = *nreads;
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < N; t += (uint64_t)gridDim.x * blockDim.x)
+    if (t >= n) lens[t] = 0;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x < C_COUNT) ctl[threadIdx.x] = 0;
+    if (threadIdx.x == 0) *flag_end = 0;
+  }
+}
+
+__global__ void k_fill_u64(uint64_t *__restrict__ p, uint64_t n, uint64_t v) {
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < n; t += (uint64_t)gridDim.x * blockDim.x) p[t] = v;
+}
+
+// the counts the host checks after a replay, into pinned host memory: the control block, the
+// unique seeds and the positions
+__global__ void k_graph_counts(const unsigned long long *__restrict__ ctl, const uint32_t *__restrict__ nu,
+                               const uint64_t *__restrict__ npos, uint64_t *__restrict__ out) {
+  const int t = threadIdx.x;
+  if (t < C_COUNT) out[t] = ctl[t];
+  if (t == C_COUNT) out[t] = *nu;
+  if (t == C_COUNT + 1) out[t] = *npos;
+  __threadfence_system();
+}
+
+}  // namespace
+
+struct mbw_graph {
+  mbw_ctx *ctx = nullptr;
+  const mbw_index *ix = nullptr;    // kept alive while the graph exists (its kernels read it)
+  int device = 0;
+  uint64_t N = 0, B = 0, W = 0, S = 0, Q = 0, X = 0;
+  int reseed = 0, launches = 0;
+  std::vector<void *> dev;          // device allocations
+  uint8_t *reads = nullptr;
+  uint32_t *lens = nullptr;
+  uint64_t *nreads = nullptr;
+  mbw_seed_t *seeds = nullptr;
+  uint64_t *pos = nullptr;
+  uint64_t *hio = nullptr, *dio = nullptr;   // pinned host words: [0] read count in; counts out from [1]
+  uint32_t *hlens = nullptr;        // pinned host copy of a batch's lengths given on the device
+  hipStream_t cs = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+static void graph_destroy(mbw_graph *g) {
+  if (!g) return;
+  (void)hipSetDevice(g->device);
+  if (g->cs) (void)hipStreamSynchronize(g->cs);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  for (void *p : g->dev) (void)hipFree(p);
+  if (g->hio) (void)hipHostFree(g->hio);
+  if (g->hlens) (void)hipHostFree(g->hlens);
+  if (g->ev0) (void)hipEventDestroy(g->ev0);
+  if (g->ev1) (void)hipEventDestroy(g->ev1);
+  if (g->cs) (void)hipStreamDestroy(g->cs);
+  if (g->ix) mbw_index_release(g->ix);
+  delete g;
+}
+
+// one device allocation of the graph
+template <class T>
+static int graph_alloc(mbw_graph *g, T *&p, uint64_t count) {
+  void *q = nullptr;
+  if (hipMalloc(&q, std::max<uint64_t>(count, 1) * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    mbw_set_error("graph: device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    return MBW_E_NOMEM;
+  }
+  g->dev.push_back(q);
+  p = (T *)q;
+  return 0;
+}
+#define GALLOC(p, n) do { int r_ = graph_alloc(g, p, n); if (r_) { graph_destroy(g); return r_; } } while (0)
+#define GTRY(call) do { hipError_t e_ = (call); if (e_ != hipSuccess) {                              \
+    mbw_set_error(std::string("graph: ") + #call + ": " + hipGetErrorString(e_));                   \
+    hipGraph_t dummy_ = nullptr; if (capturing) (void)hipStreamEndCapture(g->cs, &dummy_);           \
+    if (dummy_) (void)hipGraphDestroy(dummy_);                                                        \
+    graph_destroy(g); return e_ == hipErrorOutOfMemory ? MBW_E_NOMEM : MBW_E_HIP; } } while (0)
+
+extern "C" int mbw_graph_create(mbw_ctx *c, const mbw_graph_plan *plan, int min_seed_len, int max_occ,
+                                const mbw_seed_opts *opts, mbw_graph **out) {
+  if (!c || !plan || !out) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
+  *out = nullptr;
+  if (min_seed_len < 1 || max_occ < 1) { mbw_set_error("min_seed_len and max_occ must be >= 1"); return MBW_E_INVAL; }
+  mbw_seed_opts o;
+  if (opts) o = *opts;
+  else {
+    memset(&o, 0, sizeof(o));
+    o.min_occ = 1; o.reseed = 1; o.reseed_len = 38; o.reseed_occ = 10; o.use_kmer = 1; o.unique_ext = 1;
+  }
+  if (o.min_occ < 1) { mbw_set_error("min_occ must be >= 1"); return MBW_E_INVAL; }
+  if (o.kernel != MBW_KERNEL_COOP || o.no_stage || o.bs_role || o.bs_refine || o.unique_defer) {
+    mbw_set_error("graph: the wave kernels with LDS staging only (no plain kernel, no_stage, bisulfite or unique_defer)");
+    return MBW_E_INVAL;
+  }
+  if (o.wave_chunk < 0 || o.wave_chunk > WORK_CHUNK) { mbw_set_error("wave_chunk must be in [0,256]"); return MBW_E_INVAL; }
+  const uint64_t N = plan->max_reads;
+  if (N < 1 || N >= (1ull << 31)) { mbw_set_error("graph: max_reads must be in [1, 2^31)"); return MBW_E_INVAL; }
+  const uint64_t B = plan->max_bases ? plan->max_bases : N * STAGE_MAX;
+  if (B > N * STAGE_MAX) { mbw_set_error("graph: max_bases above max_reads x 160"); return MBW_E_INVAL; }
+  TRY(hipSetDevice(c->device));
+  const mbw_index *ix = c->ix;
+  const IndexView v = make_view(ix);
+  mbw_graph *g = new mbw_graph;
+  g->ctx = c;
+  g->device = c->device;
+  g->ix = ix;
+  mbw_index_retain(ix);
+  g->N = N; g->B = B;
+  g->W = B / 32 + N + 2;                      // packed words: each read adds at most one partial word
+  g->reseed = o.reseed;
+  // seeding parameters, as the eager path sets them
+  SeedParams P;
+  memset(&P, 0, sizeof(P));
+  P.n_queries = N;
+  P.l = min_seed_len; P.c = o.min_occ; P.reseed = o.reseed; P.reseed_len = o.reseed_len; P.reseed_occ = o.reseed_occ;
+  P.round = 1; P.use_kmer = o.use_kmer;
+  {
+    auto pow2 = [](int x) { return x > 0 && (x & (x - 1)) == 0; };
+    auto lg = [](int x) { int t = 0; while ((1 << t) < x) ++t; return t; };
+    P.uniq = (o.unique_ext && ix->text && ix->isa && pow2(ix->sa_sample) && pow2(ix->isa_sample)) ? 1 : 0;
+    P.rmask = (uint32_t)(ix->sa_sample - 1);
+    P.rshift = pow2(ix->sa_sample) ? lg(ix->sa_sample) : 0;
+    P.rishift = pow2(ix->isa_sample) ? lg(ix->isa_sample) : 0;
+  }
+  const int grid1 = P.uniq ? wave_grid<true, true>(c, P, o) : wave_grid<true, false>(c, P, o);
+  // capacities: seeds and sub-queries as the plan gives them, else 8 seeds and 2 sub-queries per read,
+  // plus one output chunk per wave of each launch that writes them
+  SeedParams P2 = P;
+  P2.round = 2; P2.uniq = 0;
+  const uint64_t slack1 = (uint64_t)grid1 * SMEM_WAVES * OUT_CHUNK;
+  g->Q = (plan->max_subqueries ? plan->max_subqueries : 2 * N) + slack1;
+  P2.n_queries = g->Q;
+  const int grid2 = wave_grid<true, false>(c, P2, o);
+  g->S = (plan->max_seeds ? plan->max_seeds : 8 * N) + slack1 + (o.reseed ? (uint64_t)grid2 * SMEM_WAVES * OUT_CHUNK : 0);
+  g->X = plan->max_positions ? plan->max_positions : 64 * N;
+  if (g->S >= (1ull << 32) - 2) { mbw_set_error("graph: too many seeds for one plan"); graph_destroy(g); return MBW_E_INVAL; }
+  const uint64_t S = g->S, Q = g->Q, X = g->X, W = g->W;
+  // device buffers
+  uint64_t *wide, *offs, *nwords, *woff, *pw, *keys0, *keys1, *npos, *posoff, *kpos, *xrows;
+  uint32_t *wread, *pn, *vals0, *vals1, *flag, *idx;
+  Query *q1, *subq;
+  SeedRec *raw;
+  unsigned long long *ctl;
+  GALLOC(g->reads, B + 64);
+  GALLOC(g->lens, N + 1);
+  GALLOC(g->nreads, 1);
+  GALLOC(wide, N + 1); GALLOC(offs, N + 1); GALLOC(nwords, N + 1); GALLOC(woff, N + 1);
+  GALLOC(wread, W); GALLOC(pw, W + 2); GALLOC(pn, W + 2);
+  GALLOC(q1, N); GALLOC(raw, S); GALLOC(subq, Q);
+  GALLOC(keys0, S); GALLOC(keys1, S); GALLOC(vals0, S); GALLOC(vals1, S); GALLOC(flag, S + 1); GALLOC(idx, S + 1);
+  GALLOC(g->seeds, S); GALLOC(npos, S + 1); GALLOC(posoff, S + 1); GALLOC(kpos, S + 1);
+  GALLOC(xrows, X + 1); GALLOC(g->pos, X + 1);
+  GALLOC(ctl, C_COUNT);
+  if (hipHostMalloc((void **)&g->hio, 64 * sizeof(uint64_t), hipHostMallocCoherent) != hipSuccess ||
+      hipHostGetDevicePointer((void **)&g->dio, g->hio, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    mbw_set_error("graph: pinned host allocation failed");
+    graph_destroy(g);
+    return MBW_E_NOMEM;
+  }
+  int qb = 1;                                   // bits of an offset within a read of at most 160 bases
+  while ((1ull << qb) <= STAGE_MAX) ++qb;
+  int hibit = 2 * qb + 1;
+  while (hibit < 64 && (1ull << (hibit - 2 * qb)) <= N) ++hibit;
+  // temporary storage: the largest any sort or scan of the graph asks for
+  prim::dbuf<uint64_t> dk(keys0, keys1);
+  prim::dbuf<uint32_t> dv(vals0, vals1);
+  size_t tb = 0, t1 = 0;
+  bool capturing = false;
+  GTRY(prim::exclusive_sum((void *)nullptr, t1, wide, offs, N + 1, (hipStream_t)0)); tb = std::max(tb, t1);
+  GTRY(prim::sort_pairs((void *)nullptr, t1, dk, dv, S, 0, hibit, (hipStream_t)0)); tb = std::max(tb, t1);
+  GTRY(prim::exclusive_sum((void *)nullptr, t1, flag, idx, S + 1, (hipStream_t)0)); tb = std::max(tb, t1);
+  GTRY(prim::exclusive_sum((void *)nullptr, t1, npos, posoff, S + 1, (hipStream_t)0)); tb = std::max(tb, t1);
+  uint8_t *temp;
+  GALLOC(temp, tb + 256);
+  GTRY(hipStreamCreateWithFlags(&g->cs, hipStreamNonBlocking));
+  GTRY(hipEventCreate(&g->ev0));
+  GTRY(hipEventCreate(&g->ev1));
+  ReadWords R;
+  R.pw = pw; R.pn = pn; R.woff = woff;
+  P.queries = q1; P.seeds = raw; P.seed_cap = S; P.subq = subq; P.subq_cap = Q; P.ctl = ctl;
+  P2.queries = subq; P2.seeds = raw; P2.seed_cap = S; P2.subq = nullptr; P2.subq_cap = 0; P2.ctl = ctl;
+  P2.nq_dev = ctl + C_NSUBQ;
+  auto chunk_for = [&](int grid, uint64_t n) {
+    if (o.wave_chunk > 0) return (uint32_t)std::min(WORK_CHUNK, o.wave_chunk);
+    const uint64_t waves = (uint64_t)std::max(grid, 1) * SMEM_WAVES;
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(WORK_CHUNK, n / (waves * 8)));
+  };
+  P.chunk = chunk_for(grid1, N);
+  P2.chunk = chunk_for(grid2, 2 * N);
+  uint32_t rmask = (ix->sa_sample & (ix->sa_sample - 1)) == 0 ? (uint32_t)(ix->sa_sample - 1) : 0u;
+  int rshift = -1;
+  if ((ix->sa_sample & (ix->sa_sample - 1)) == 0) { rshift = 0; while ((1 << rshift) < ix->sa_sample) ++rshift; }
+  const int gridL = persistent_grid((const void *)k_locate_wave, 256, 0, c->n_cu, o.blocks_per_cu, X, AUTO_ROWS_LOCATE);
+  const int bs = 64 * SMEM_WAVES;
+  hipStream_t st = g->cs;
+  GTRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  capturing = true;
+  size_t have = tb + 256;
+  k_graph_prep<<<grid_for(N), 256, 0, st>>>(g->lens, N, g->nreads, ctl, flag + S);
+  k_widen<<<grid_for(N + 1, 256, 1024u), 256, 0, st>>>(g->lens, N, wide, ctl + C_MAXLEN);
+  GTRY(prim::exclusive_sum((void *)temp, have, wide, offs, N + 1, st));
+  k_read_words<<<grid_for(N + 1), 256, 0, st>>>(offs, N, nwords);
+  have = tb + 256;
+  GTRY(prim::exclusive_sum((void *)temp, have, nwords, woff, N + 1, st));
+  k_word_owner<<<grid_for(N), 256, 0, st>>>(woff, N, wread);
+  k_pack_words<<<(unsigned)((W + PACK_BLOCK - 1) / PACK_BLOCK), PACK_BLOCK, 0, st>>>(g->reads, B, offs, woff, wread, W, 0, pw, pn,
+                                                                                       offs + N, woff + N);
+  k_make_queries<<<grid_for(N), 256, 0, st>>>(nullptr, N, offs, woff, (uint32_t)min_seed_len, (uint32_t)o.min_occ, q1);
+  k_ctl_zero<<<1, 64, 0, st>>>(ctl, C_WORK, C_WORK);
+  if (P.uniq) k_smem_wave<true, true><<<grid1, bs, 0, st>>>(v, P, R);
+  else k_smem_wave<true, false><<<grid1, bs, 0, st>>>(v, P, R);
+  g->launches = 1;
+  if (o.reseed) {
+    k_ctl_zero<<<1, 64, 0, st>>>(ctl, C_WORK, C_WORK);
+    k_smem_wave<true, false><<<grid2, bs, 0, st>>>(v, P2, R);
+    g->launches = 2;
+  }
+  k_seed_keys<<<grid_for(S), 256, 0, st>>>(raw, S, N, qb, keys0, vals0, ctl + C_NSEEDS);
+  have = tb + 256;
+  GTRY(prim::sort_pairs((void *)temp, have, dk, dv, S, 0, hibit, st));
+  k_dedup_mark<<<grid_for(S), 256, 0, st>>>(dk.current(), S, N, qb, flag);
+  have = tb + 256;
+  GTRY(prim::exclusive_sum((void *)temp, have, flag, idx, S + 1, st));
+  k_fill_u64<<<grid_for(S + 1), 256, 0, st>>>(npos, S + 1, 0);
+  k_seed_emit<<<grid_for(S), 256, 0, st>>>(raw, dv.current(), flag, idx, S, (uint64_t)max_occ, g->seeds, npos, kpos);
+  have = tb + 256;
+  GTRY(prim::exclusive_sum((void *)temp, have, npos, posoff, S + 1, st));
+  k_expand_rows<<<grid_for((S + 63) / 64 * 64 / 4, 256, 65536u), 256, 0, st>>>(g->seeds, posoff, kpos, S, xrows, g->pos,
+                                                                                 idx + S, X);
+  k_locate_wave<<<gridL, 256, 0, st>>>(v, xrows, X, g->pos, rmask, rshift, ctl, posoff + S);
+  k_graph_counts<<<1, 64, 0, st>>>(ctl, idx + S, posoff + S, g->dio + 1);
+  GTRY(hipGetLastError());
+  capturing = false;
+  GTRY(hipStreamEndCapture(st, &g->graph));
+  GTRY(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+  *out = g;
+  return MBW_OK;
+}
+#undef GALLOC
+
+extern "C" int mbw_graph_info(const mbw_graph *g, mbw_graph_plan *plan) {
+  if (!g || !plan) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
+  memset(plan, 0, sizeof(*plan));
+  plan->max_reads = g->N; plan->max_bases = g->B; plan->max_seeds = g->S; plan->max_subqueries = g->Q;
+  plan->max_positions = g->X;
+  return MBW_OK;
+}
+
+extern "C" int mbw_graph_seed(mbw_graph *g, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads, void *stream,
+                              mbw_result *out) {
+  if (!g || !out) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
+  memset(out, 0, sizeof(*out));
+  if (n_reads > g->N) { mbw_set_error("graph: " + std::to_string(n_reads) + " reads, the plan holds " + std::to_string(g->N)); return MBW_E_INVAL; }
+  if (n_reads > 0 && (!reads || !lengths)) { mbw_set_error("NULL reads or lengths"); return MBW_E_INVAL; }
+  TRY(hipSetDevice(g->device));
+  hipStream_t st = (hipStream_t)stream;
+  g->ctx->cur = st;
+  // the lengths on the host, checked against the plan before anything reaches the graph
+  const uint32_t *hl = lengths;
+  if (n_reads && is_device_ptr(lengths)) {
+    if (!g->hlens && hipHostMalloc((void **)&g->hlens, g->N * sizeof(uint32_t), 0) != hipSuccess) {
+      (void)hipGetLastError();
+      g->hlens = nullptr;
+      mbw_set_error("graph: pinned host allocation failed");
+      return MBW_E_NOMEM;
+    }
+    TRY(hipMemcpyAsync(g->hlens, lengths, n_reads * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    TRY(hipStreamSynchronize(st));
+    hl = g->hlens;
+  }
+  uint64_t total = 0;
+  for (uint64_t r = 0; r < n_reads; ++r) {
+    if (hl[r] > STAGE_MAX) {
+      mbw_set_error("graph: read " + std::to_string(r) + " has " + std::to_string(hl[r]) + " bases; a graph takes reads of at most 160");
+      return MBW_E_INVAL;
+    }
+    total += hl[r];
+  }
+  if (total > g->B) {
+    mbw_set_error("graph: " + std::to_string(total) + " bases, the plan holds " + std::to_string(g->B));
+    return MBW_E_INVAL;
+  }
+  // the batch into the graph's input buffers, its read count into the device word the graph reads
+  if (n_reads) {
+    TRY(hipMemcpyAsync(g->lens, lengths, n_reads * sizeof(uint32_t), hipMemcpyDefault, st));
+    if (total) TRY(hipMemcpyAsync(g->reads, reads, total, hipMemcpyDefault, st));
+  }
+  g->hio[0] = n_reads;
+  TRY(hipMemcpyAsync(g->nreads, g->hio, sizeof(uint64_t), hipMemcpyHostToDevice, st));
+  TRY(hipEventRecord(g->ev0, st));
+  TRY(hipGraphLaunch(g->exec, st));
+  TRY(hipEventRecord(g->ev1, st));
+  TRY(hipStreamSynchronize(st));
+  uint64_t cnt[C_COUNT + 2];
+  for (int t = 0; t < C_COUNT + 2; ++t) cnt[t] = ((volatile uint64_t *)g->hio)[1 + t];
+  if (cnt[C_ERR]) {
+    mbw_set_error("kernel guard tripped (" + std::to_string(cnt[C_ERR]) + "): corrupt index or internal error");
+    return MBW_E_HIP;
+  }
+  const uint64_t nu = cnt[C_COUNT], n_pos = cnt[C_COUNT + 1];
+  if (cnt[C_NSEEDS] > g->S || cnt[C_NSUBQ] > g->Q || n_pos > g->X) {
+    mbw_set_error("graph: the batch needs " + std::to_string(cnt[C_NSEEDS]) + " seed slots, " + std::to_string(cnt[C_NSUBQ]) +
+                  " sub-query slots and " + std::to_string(n_pos) + " positions; the plan holds " + std::to_string(g->S) + ", " +
+                  std::to_string(g->Q) + " and " + std::to_string(g->X) + " (seed it with mbw_seed, or use a larger plan)");
+    return MBW_E_CAPACITY;
+  }
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, g->ev0, g->ev1);
+  out->n_seeds = nu;
+  out->n_pos = n_pos;
+  out->seeds = g->seeds;
+  out->pos = g->pos;
+  out->lines_smem = cnt[C_LINES];
+  out->lines_locate = cnt[C_LINES_LOC];
+  out->steps = cnt[C_STEPS];
+  out->lf_steps = cnt[C_LFSTEPS];
+  out->ms_total = ms;
+  out->n_smem_launches = g->launches;
+  out->wave_iters = cnt[C_WITER];
+  out->lane_iters = cnt[C_LITER];
+  out->max_chain = cnt[C_MAXCHAIN];
+  return MBW_OK;
+}
+
+extern "C" void mbw_graph_free(mbw_graph *g) { graph_destroy(g); }

@@ -1,0 +1,139 @@
+"""Captured graphs (mbw_graph_*): the seeding path recorded once as a HIP graph and replayed.
+
+Every replay must give exactly the seeds and positions of an eager mbw_seed call with the same
+options (and so the oracle's): the whole 1 Mbp workload, then one graph replayed on batches of
+other sizes, lengths (1-160 bases, N runs) and an empty one, each twice with eager calls and
+synchronisations in between (a replayed graph must not depend on state the first replay left
+behind), from host and from device memory; plans too small and inputs outside the plan are
+refused with the documented codes and leave the graph usable.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from mbw_helpers import compare_with_oracle
+
+mbw = pytest.importorskip("paper_2606_15357_amd")
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def same(a, b):
+    sa, pa = a.download()
+    sb, pb = b.download()
+    assert sa.size == sb.size and pa.size == pb.size
+    for f in sa.dtype.names:
+        if f != "reserved":
+            assert np.array_equal(sa[f], sb[f]), f
+    assert np.array_equal(pa, pb)
+    return sa, pa
+
+
+def subset(reads, ids):
+    ids = np.asarray(ids, dtype=np.int64)
+    lens = reads.lengths[ids]
+    offs = np.zeros(len(ids) + 1, dtype=np.uint64)
+    np.cumsum(lens, out=offs[1:])
+    seq = np.concatenate([reads.seq[int(reads.offsets[r]):int(reads.offsets[r + 1])] for r in ids]) if len(ids) else \
+        np.zeros(0, np.uint8)
+    return synth.ReadSet(seq, lens.astype(np.uint32), offs, reads.tpos[ids], reads.tstrand[ids])
+
+
+@pytest.fixture(scope="module")
+def small():
+    ref = synth.workload_reference("small_1mbp")
+    reads = synth.workload_reads("small_1mbp", ref)
+    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=10)
+    yield ref, reads, idx
+    idx.free()
+
+
+@pytest.mark.parametrize("kw", [{}, dict(unique_ext=False), dict(reseed=False), dict(use_kmer=False),
+                                dict(blocks_per_cu=-1, wave_chunk=64)])
+def test_graph_equals_seed_and_oracle(small, kw):
+    """10,000 x 150 bp reads of the 1 Mbp workload: a graph's replay equals mbw_seed array for array
+    and the oracle, under several seeding options."""
+    ref, reads, idx = small
+    ctx = mbw.Context(idx)
+    base = ctx.seed(reads.seq, reads.lengths, **kw)
+    g = ctx.graph(len(reads), **kw)
+    out = g.seed(reads.seq, reads.lengths)
+    s, p = same(out, base)
+    if kw.get("reseed", True):
+        ox = oracle.OracleIndex(ref.codes, sa_rate=8)
+        compare_with_oracle(s, p, ox.seed(reads.seq, reads.offsets, min_len=19, max_occ=500))
+    assert out.ms_total > 0 and out.n_smem_launches == (1 if kw.get("reseed") is False else 2)
+    g.free()
+    ctx.free()
+
+
+def test_graph_replays(small):
+    """One graph (plan: 4,000 reads) replayed on batches of different sizes and lengths, host and
+    device inputs, each twice with eager calls in between; every replay equals the eager result."""
+    ref, reads, idx = small
+    rag = synth.reads_uniform_len(ref, 3000, 1, 160, seed=91)
+    seq = rag.seq.copy()
+    rng = np.random.default_rng(92)
+    for r in range(0, len(rag), 7):
+        a, n = int(rag.offsets[r]), int(rag.lengths[r])
+        if n > 40:
+            seq[a + 20:a + 20 + int(rng.integers(1, 6))] = ord("N")
+    rag = synth.ReadSet(seq, rag.lengths, rag.offsets, rag.tpos, rag.tstrand)
+    batches = [subset(reads, range(4000)), subset(reads, range(4000, 4001)), subset(reads, []),
+               subset(reads, rng.permutation(10000)[:2500]), rag, subset(reads, range(9000, 10000))]
+    ctx = mbw.Context(idx)
+    g = ctx.graph(4000)
+    plan = g.plan()
+    assert plan["max_reads"] == 4000 and plan["max_bases"] == 4000 * 160
+    for b in batches:
+        for rep in range(2):
+            eager = ctx.seed(b.seq, b.lengths)
+            ref_s, ref_p = eager.download()
+            torch.cuda.synchronize()
+            if rep == 0:
+                out = g.seed(b.seq, b.lengths)
+            else:
+                dseq = torch.from_numpy(b.seq.copy() if b.seq.size else np.zeros(1, np.uint8)).to(DEV)
+                dlen = torch.from_numpy(b.lengths.view(np.int32).copy()).to(DEV)
+                out = g.seed(dseq, dlen)
+            s, p = out.download()
+            assert s.size == ref_s.size and p.size == ref_p.size
+            for f in s.dtype.names:
+                if f != "reserved":
+                    assert np.array_equal(s[f], ref_s[f]), f
+            assert np.array_equal(p, ref_p)
+    g.free()
+    ctx.free()
+
+
+def test_graph_refusals(small):
+    ref, reads, idx = small
+    ctx = mbw.Context(idx)
+    g = ctx.graph(100, max_positions=50)
+    with pytest.raises(mbw.MbwError) as e:          # more reads than the plan
+        g.seed(reads.seq[: int(reads.offsets[101])], reads.lengths[:101])
+    assert e.value.code == mbw.MBW_E_INVAL
+    long_read = np.frombuffer(b"ACGT" * 50, dtype=np.uint8)
+    with pytest.raises(mbw.MbwError) as e:          # a read of 200 bases
+        g.seed(long_read, np.array([200], np.uint32))
+    assert e.value.code == mbw.MBW_E_INVAL
+    with pytest.raises(mbw.MbwError) as e:          # positions beyond the plan
+        g.seed(reads.seq[: int(reads.offsets[100])], reads.lengths[:100])
+    assert e.value.code == mbw.MBW_E_CAPACITY and "positions" in str(e.value)
+    one = subset(reads, [0])                        # the graph still serves a batch that fits
+    out = g.seed(one.seq, one.lengths)
+    base = ctx.seed(one.seq, one.lengths)
+    if base.n_pos <= 50:
+        same(out, base)
+    g.free()
+    for kw in (dict(kernel=mbw.KERNEL_PLAIN), dict(stage=False), dict(unique_defer=1)):
+        with pytest.raises(mbw.MbwError) as e:
+            ctx.graph(10, **kw)
+        assert e.value.code == mbw.MBW_E_INVAL
+    with pytest.raises(mbw.MbwError):
+        ctx.graph(0)
+    ctx.free()
