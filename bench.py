@@ -211,7 +211,7 @@ def chain_cpu_baseline(res, seg_len: int, sample: str):
                        f"{chains.size} chains, {dt:.1f} s on one thread")
 
 
-def latency_leg(torch, ctx, reads, dseq, dlen, sched: dict, stream):
+def latency_leg(mbw, torch, ctx, reads, dseq, dlen, sched: dict, stream):
     """Per-call time of small batches (reads already in HBM): persistent grids sized by the work
     (blocks_per_cu = 0) against grids at the occupancy limit (-1)."""
     rows = []
@@ -234,8 +234,29 @@ def latency_leg(torch, ctx, reads, dseq, dlen, sched: dict, stream):
                 torch.cuda.synchronize()
                 ts.append(time.perf_counter() - t0)
             row[name] = round(float(np.median(ts)) * 1e3, 3)
+        # the same batch through a captured graph planned for it (work-sized grids; the lengths
+        # come from the host, which checks them against the plan, the reads from HBM)
+        gkw = dict(unique_ext=sched.get("unique_ext", True), blocks_per_cu=0, wave_chunk=0)
+        g = ctx.graph(n, max_bases=nb, max_positions=max(64 * n, 16384), min_seed_len=19, max_occ=500, **gkw)
+        hl = reads.lengths[:n]
+        try:
+            for _ in range(2):
+                g.seed(dseq[:nb], hl, stream=stream)
+            ts = []
+            for _ in range(7):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                g.seed(dseq[:nb], hl, stream=stream)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            row["graph_ms"] = round(float(np.median(ts)) * 1e3, 3)
+        except mbw.MbwError as e:            # a batch beyond its plan: no figure
+            row["graph_ms"] = None
+            log(f"graph leg at {n} reads: {e}")
+        g.free()
         rows.append(row)
-    return dict(unit="ms per mbw_seed call, reads in HBM, median of 7", batches=rows)
+    return dict(unit="ms per mbw_seed call (graph_ms: per mbw_graph_seed call on a graph planned for the batch), "
+                     "reads in HBM, median of 7", batches=rows)
 
 
 LOADS = (0.25, 0.5, 0.8)
@@ -667,7 +688,7 @@ def main():
 
     latency = None
     if not args.no_latency:
-        latency = latency_leg(torch, ctx, reads, dseq, dlen, sched, stream)
+        latency = latency_leg(mbw, torch, ctx, reads, dseq, dlen, sched, stream)
         log(f"small batches: {latency}")
 
     others = None

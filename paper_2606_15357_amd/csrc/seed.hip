@@ -1218,7 +1218,8 @@ __global__ void k_seed_posoff(mbw_seed_t *__restrict__ out, const uint64_t *__re
 // gets it written to the output and NO_POS in X (locate skips it).
 #define EXPAND_LANE_MAX 8
 // nu_p / xcap (captured graphs): the seed count on the device, at most ns; rows and positions are
-// written only below xcap
+// written only below xcap, and every row below it is written (NO_POS for a seed cut off by it), so
+// that locate never reads a row that was not set
 __global__ void __launch_bounds__(256) k_expand_rows(mbw_seed_t *__restrict__ seeds, const uint64_t *__restrict__ posoff,
                                                      const uint64_t *__restrict__ kpos, uint64_t ns, uint64_t *__restrict__ X,
                                                      uint64_t *__restrict__ pos, const uint32_t *__restrict__ nu_p = nullptr,
@@ -1234,7 +1235,10 @@ __global__ void __launch_bounds__(256) k_expand_rows(mbw_seed_t *__restrict__ se
       k = seeds[t].k; np = seeds[t].npos; off = posoff[t]; kp = kpos[t];
       seeds[t].pos_off = off;
     }
-    if (off + np > xcap) np = 0;
+    if (off + np > xcap) {          // past the capacity: rows below it that the seed would have
+      for (uint64_t q = off; q < xcap; ++q) X[q] = NO_POS;   // started are marked for locate to skip
+      np = 0;
+    }
     const bool mine = np <= EXPAND_LANE_MAX;
     if (mine && np == 1 && kp != NO_POS) { X[off] = NO_POS; pos[off] = kp; }
     else if (mine)
@@ -2465,6 +2469,21 @@ __global__ void k_graph_prep(uint32_t *__restrict__ lens, uint64_t N, const uint
   }
 }
 
+// the re-seeding queries that round 1 wrote (its list has unused slots of per-wave chunks, and
+// nothing past the count on the device), flagged and moved to the front of q2 in order, so that
+// round 2 runs only real queries; qp[n] is their number
+__global__ void k_graph_qflags(const Query *__restrict__ q, uint64_t n, const unsigned long long *__restrict__ count,
+                               uint64_t *__restrict__ qf) {
+  const uint64_t m = min(n, (uint64_t)*count);
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t <= n; t += (uint64_t)gridDim.x * blockDim.x)
+    qf[t] = (t < m && q[t].read_id != INVALID_READ) ? 1u : 0u;
+}
+__global__ void k_graph_qcompact(const Query *__restrict__ q, const uint64_t *__restrict__ qf, const uint64_t *__restrict__ qp,
+                                 uint64_t n, Query *__restrict__ q2) {
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < n; t += (uint64_t)gridDim.x * blockDim.x)
+    if (qf[t]) q2[qp[t]] = q[t];
+}
+
 __global__ void k_fill_u64(uint64_t *__restrict__ p, uint64_t n, uint64_t v) {
   for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < n; t += (uint64_t)gridDim.x * blockDim.x) p[t] = v;
 }
@@ -2598,9 +2617,9 @@ extern "C" int mbw_graph_create(mbw_ctx *c, const mbw_graph_plan *plan, int min_
   if (g->S >= (1ull << 32) - 2) { mbw_set_error("graph: too many seeds for one plan"); graph_destroy(g); return MBW_E_INVAL; }
   const uint64_t S = g->S, Q = g->Q, X = g->X, W = g->W;
   // device buffers
-  uint64_t *wide, *offs, *nwords, *woff, *pw, *keys0, *keys1, *npos, *posoff, *kpos, *xrows;
+  uint64_t *wide, *offs, *nwords, *woff, *pw, *keys0, *keys1, *npos, *posoff, *kpos, *xrows, *qf, *qp;
   uint32_t *wread, *pn, *vals0, *vals1, *flag, *idx;
-  Query *q1, *subq;
+  Query *q1, *subq, *q2;
   SeedRec *raw;
   unsigned long long *ctl;
   GALLOC(g->reads, B + 64);
@@ -2608,11 +2627,13 @@ extern "C" int mbw_graph_create(mbw_ctx *c, const mbw_graph_plan *plan, int min_
   GALLOC(g->nreads, 1);
   GALLOC(wide, N + 1); GALLOC(offs, N + 1); GALLOC(nwords, N + 1); GALLOC(woff, N + 1);
   GALLOC(wread, W); GALLOC(pw, W + 2); GALLOC(pn, W + 2);
-  GALLOC(q1, N); GALLOC(raw, S); GALLOC(subq, Q);
+  GALLOC(q1, N); GALLOC(raw, S); GALLOC(subq, Q); GALLOC(q2, Q); GALLOC(qf, Q + 1); GALLOC(qp, Q + 1);
   GALLOC(keys0, S); GALLOC(keys1, S); GALLOC(vals0, S); GALLOC(vals1, S); GALLOC(flag, S + 1); GALLOC(idx, S + 1);
   GALLOC(g->seeds, S); GALLOC(npos, S + 1); GALLOC(posoff, S + 1); GALLOC(kpos, S + 1);
   GALLOC(xrows, X + 1); GALLOC(g->pos, X + 1);
   GALLOC(ctl, C_COUNT);
+  bool capturing = false;
+  GTRY(hipMemset(xrows, 0xff, (X + 1) * sizeof(uint64_t)));   // every row starts as NO_POS
   if (hipHostMalloc((void **)&g->hio, 64 * sizeof(uint64_t), hipHostMallocCoherent) != hipSuccess ||
       hipHostGetDevicePointer((void **)&g->dio, g->hio, 0) != hipSuccess) {
     (void)hipGetLastError();
@@ -2628,11 +2649,11 @@ extern "C" int mbw_graph_create(mbw_ctx *c, const mbw_graph_plan *plan, int min_
   prim::dbuf<uint64_t> dk(keys0, keys1);
   prim::dbuf<uint32_t> dv(vals0, vals1);
   size_t tb = 0, t1 = 0;
-  bool capturing = false;
   GTRY(prim::exclusive_sum((void *)nullptr, t1, wide, offs, N + 1, (hipStream_t)0)); tb = std::max(tb, t1);
   GTRY(prim::sort_pairs((void *)nullptr, t1, dk, dv, S, 0, hibit, (hipStream_t)0)); tb = std::max(tb, t1);
   GTRY(prim::exclusive_sum((void *)nullptr, t1, flag, idx, S + 1, (hipStream_t)0)); tb = std::max(tb, t1);
   GTRY(prim::exclusive_sum((void *)nullptr, t1, npos, posoff, S + 1, (hipStream_t)0)); tb = std::max(tb, t1);
+  GTRY(prim::exclusive_sum((void *)nullptr, t1, qf, qp, Q + 1, (hipStream_t)0)); tb = std::max(tb, t1);
   uint8_t *temp;
   GALLOC(temp, tb + 256);
   GTRY(hipStreamCreateWithFlags(&g->cs, hipStreamNonBlocking));
@@ -2641,8 +2662,8 @@ extern "C" int mbw_graph_create(mbw_ctx *c, const mbw_graph_plan *plan, int min_
   ReadWords R;
   R.pw = pw; R.pn = pn; R.woff = woff;
   P.queries = q1; P.seeds = raw; P.seed_cap = S; P.subq = subq; P.subq_cap = Q; P.ctl = ctl;
-  P2.queries = subq; P2.seeds = raw; P2.seed_cap = S; P2.subq = nullptr; P2.subq_cap = 0; P2.ctl = ctl;
-  P2.nq_dev = ctl + C_NSUBQ;
+  P2.queries = q2; P2.seeds = raw; P2.seed_cap = S; P2.subq = nullptr; P2.subq_cap = 0; P2.ctl = ctl;
+  P2.nq_dev = (const unsigned long long *)(qp + Q);
   auto chunk_for = [&](int grid, uint64_t n) {
     if (o.wave_chunk > 0) return (uint32_t)std::min(WORK_CHUNK, o.wave_chunk);
     const uint64_t waves = (uint64_t)std::max(grid, 1) * SMEM_WAVES;
@@ -2674,6 +2695,10 @@ extern "C" int mbw_graph_create(mbw_ctx *c, const mbw_graph_plan *plan, int min_
   else k_smem_wave<true, false><<<grid1, bs, 0, st>>>(v, P, R);
   g->launches = 1;
   if (o.reseed) {
+    k_graph_qflags<<<grid_for(Q + 1), 256, 0, st>>>(subq, Q, ctl + C_NSUBQ, qf);
+    have = tb + 256;
+    GTRY(prim::exclusive_sum((void *)temp, have, qf, qp, Q + 1, st));
+    k_graph_qcompact<<<grid_for(Q), 256, 0, st>>>(subq, qf, qp, Q, q2);
     k_ctl_zero<<<1, 64, 0, st>>>(ctl, C_WORK, C_WORK);
     k_smem_wave<true, false><<<grid2, bs, 0, st>>>(v, P2, R);
     g->launches = 2;
