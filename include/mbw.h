@@ -299,8 +299,9 @@ int mbw_seed_static(mbw_ctx *ctx, const uint8_t *reads, const uint32_t *lengths,
 
 /* ---- captured graphs -------------------------------------------------------------------- */
 /* The seeding path of mbw_seed (Algorithm 3 of Section 2.5 in both rounds of Section 2.6, then
- * Algorithm 2 of Section 2.4) for batches of reads of at most 160 bases, recorded once as a HIP graph
- * over device buffers sized by a plan and replayed for every batch: each call copies the batch in,
+ * Algorithm 2 of Section 2.4), recorded once as a HIP graph over device buffers sized by a plan and
+ * replayed for every batch, with the same length bins as mbw_seed (reads of at most 160 bases
+ * staged in LDS; longer ones, when the plan allows them, in segments): each call copies the batch in,
  * launches the graph and waits once (mbw_seed waits for every intermediate count).  Same seeds and
  * positions as mbw_seed with the same options.  Sorts and scans span the plan's capacities, so a
  * plan much larger than its batches costs time.  A graph belongs to one context, is freed before
@@ -308,26 +309,30 @@ int mbw_seed_static(mbw_ctx *ctx, const uint8_t *reads, const uint32_t *lengths,
 typedef struct mbw_graph mbw_graph;
 typedef struct {
   uint64_t max_reads;       /* reads per batch at most (>= 1, < 2^31) */
-  uint64_t max_bases;       /* bases per batch at most; 0 = 160 per read (the most a read may have) */
+  uint64_t max_bases;       /* bases per batch at most; 0 = max_read_len per read */
   uint64_t max_seeds;       /* seed records before duplicates are dropped; 0 = 8 per read (output
                                slack of the kernels' per-wave chunks is added) */
   uint64_t max_subqueries;  /* re-seeding queries; 0 = 2 per read (plus the same slack) */
   uint64_t max_positions;   /* positions; 0 = 64 per read */
+  uint64_t max_read_len;    /* longest read; 0 = 160 (the staged bin only); at most 65535.  Longer
+                               reads add the unstaged bin: segments of seg_len bases, at most
+                               max_bases / seg + max_reads in round 1 and max_subqueries +
+                               4 max_bases / seg in round 2 */
 } mbw_graph_plan;
 /* Allocate the plan's buffers on the context's device (mbw_graph_info reports the capacities with
- * slack) and capture the graph.  opts as for mbw_seed; the wave kernels with LDS staging only: the
- * plain kernel, no_stage, bisulfite roles and unique_defer are refused (MBW_E_INVAL).  Errors:
+ * slack) and capture the graph.  opts as for mbw_seed; the wave kernels with LDS staging: the plain
+ * kernel, no_stage, bisulfite roles and unique_defer are refused (MBW_E_INVAL).  Errors:
  * MBW_E_INVAL, MBW_E_NOMEM, MBW_E_HIP (capture or instantiation failed). */
 int mbw_graph_create(mbw_ctx *ctx, const mbw_graph_plan *plan, int min_seed_len, int max_occ,
                      const mbw_seed_opts *opts, mbw_graph **out);
-int mbw_graph_info(const mbw_graph *g, mbw_graph_plan *plan);
+int mbw_graph_info(const mbw_graph *g, mbw_graph_plan *plan);   /* capacities, slack included */
 /* Seed one batch (reads and lengths on the host or the device, as for mbw_seed) on `stream`;
  * blocking.  The result points into the graph's buffers and stays valid until the graph's next
  * call or mbw_graph_free; mbw_result_download with the graph's context copies it out.  ms_total is
  * the graph's device time (ms_smem and ms_locate are not split out).  Errors: MBW_E_INVAL (more
- * reads or bases than the plan, a read longer than 160 bases), MBW_E_CAPACITY (the batch needs more
- * seed, sub-query or position slots than the plan holds: the message gives the counts; seed it with
- * mbw_seed or a larger plan), MBW_E_HIP. */
+ * reads or bases than the plan, a read longer than its max_read_len), MBW_E_CAPACITY (the batch
+ * needs more seed, sub-query, segment or position slots than the plan holds: the message gives the
+ * counts; seed it with mbw_seed or a larger plan), MBW_E_HIP. */
 int mbw_graph_seed(mbw_graph *g, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads, void *stream,
                    mbw_result *out);
 void mbw_graph_free(mbw_graph *g);

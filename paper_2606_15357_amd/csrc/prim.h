@@ -36,6 +36,18 @@ inline hipError_t sort_pairs(void *tmp, size_t &bytes, dbuf<K> &k, dbuf<V> &v, s
   return rocprim::radix_sort_pairs(tmp, bytes, k, v, n, (unsigned)b0, (unsigned)b1, st);
 }
 
+// the same sort through rocPRIM's merge-based path at every size.  Above 2^20 items the default
+// dispatch takes the onesweep path, which resets its histogram and look-back states with
+// hipMemsetAsync; a captured graph must not record memset operations (they are not reliable when
+// the graph is replayed), and the merge-based path issues none.
+template <class K, class V>
+inline hipError_t sort_pairs_merge(void *tmp, size_t &bytes, dbuf<K> &k, dbuf<V> &v, size_t n, int b0, int b1,
+                                   hipStream_t st) {
+  using cfg = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config, rocprim::default_config,
+                                         ~size_t(0)>;
+  return rocprim::radix_sort_pairs<cfg>(tmp, bytes, k, v, n, (unsigned)b0, (unsigned)b1, st);
+}
+
 // the indices i < n with flags[i] != 0, ascending, into out; their number into *count (device)
 template <class F, class O, class C>
 inline hipError_t flagged_indices(void *tmp, size_t &bytes, F flags, O out, C count, size_t n, hipStream_t st) {

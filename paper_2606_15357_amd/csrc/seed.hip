@@ -1002,7 +1002,9 @@ __global__ void k_read_partition(const uint64_t *__restrict__ offs, const uint32
 
 // round-1 query records of reads ids[0..n)
 __global__ void k_make_queries(const uint32_t *__restrict__ ids, uint64_t n, const uint64_t *__restrict__ offs,
-                               const uint64_t *__restrict__ woff, uint32_t l, uint32_t c, Query *__restrict__ q) {
+                               const uint64_t *__restrict__ woff, uint32_t l, uint32_t c, Query *__restrict__ q,
+                               const uint64_t *__restrict__ n_p = nullptr) {
+  if (n_p) n = min(n, *n_p);   // captured graphs: the count on the device
   for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < n; t += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t r = ids ? ids[t] : (uint32_t)t;   // no ids: every read, in order
     const uint32_t len = (uint32_t)(offs[r + 1] - offs[r]);
@@ -2453,7 +2455,9 @@ extern "C" int mbw_result_download(mbw_ctx *c, const mbw_result *res, mbw_seed_t
 // eager path waits for (bases, packed words, seeds, sub-queries, unique seeds, positions) stays on
 // the device, the kernels that consume one read it there, and grids, sorts and scans span the
 // plan's capacities (unused slots sort last and hold nothing).  The host copies the batch in,
-// launches the graph and waits once, for the counts, which it checks against the plan.
+// launches the graph and waits once, for the counts, which it checks against the plan.  The graph
+// records no memset operation: clearing is done by kernels, and the sorts take rocPRIM's
+// merge-based path, whose resets are kernels too.
 namespace {
 
 // zero the control block and the lengths of the plan's unused reads (the replayed batch may be
@@ -2469,19 +2473,81 @@ __global__ void k_graph_prep(uint32_t *__restrict__ lens, uint64_t N, const uint
   }
 }
 
-// the re-seeding queries that round 1 wrote (its list has unused slots of per-wave chunks, and
-// nothing past the count on the device), flagged and moved to the front of q2 in order, so that
-// round 2 runs only real queries; qp[n] is their number
-__global__ void k_graph_qflags(const Query *__restrict__ q, uint64_t n, const unsigned long long *__restrict__ count,
-                               uint64_t *__restrict__ qf) {
-  const uint64_t m = min(n, (uint64_t)*count);
-  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t <= n; t += (uint64_t)gridDim.x * blockDim.x)
-    qf[t] = (t < m && q[t].read_id != INVALID_READ) ? 1u : 0u;
+// Length bins with the counts on the device.  Reads: flag 1 for those staged in LDS (the plan's
+// unused reads have length 0 and count as staged); fs[N] = 0 so that a scan over N + 1 ends in the
+// count.
+__global__ void k_graph_rflags(const uint64_t *__restrict__ offs, uint64_t N, uint64_t *__restrict__ fs) {
+  for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r <= N; r += (uint64_t)gridDim.x * blockDim.x)
+    fs[r] = (r < N && offs[r + 1] - offs[r] <= STAGE_MAX) ? 1u : 0u;
 }
-__global__ void k_graph_qcompact(const Query *__restrict__ q, const uint64_t *__restrict__ qf, const uint64_t *__restrict__ qp,
-                                 uint64_t n, Query *__restrict__ q2) {
-  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < n; t += (uint64_t)gridDim.x * blockDim.x)
-    if (qf[t]) q2[qp[t]] = q[t];
+// staged read ids in order; the others with sort keys that put the longest first (slots past the
+// last of them keep the filler key, which sorts after every length); nlong = N - staged
+__global__ void k_graph_rsplit(const uint64_t *__restrict__ offs, uint64_t N, const uint64_t *__restrict__ fs,
+                               const uint64_t *__restrict__ ps, uint32_t *__restrict__ ids_s, uint32_t *__restrict__ lkey,
+                               uint32_t *__restrict__ lid, uint64_t *__restrict__ nlong) {
+  for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < N; r += (uint64_t)gridDim.x * blockDim.x) {
+    if (fs[r]) ids_s[ps[r]] = (uint32_t)r;
+    else {
+      const uint64_t t = r - ps[r];
+      lid[t] = (uint32_t)r;
+      lkey[t] = 65535u - (uint32_t)(offs[r + 1] - offs[r]);
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *nlong = N - ps[N];
+}
+// Re-seeding queries that round 1 wrote (its list has unused slots of per-wave chunks, and nothing
+// past the count on the device), flagged by bin; [n] = 0
+__global__ void k_graph_qflags(const Query *__restrict__ q, uint64_t n, const unsigned long long *__restrict__ count,
+                               uint64_t *__restrict__ fs, uint64_t *__restrict__ fl) {
+  const uint64_t m = min(n, (uint64_t)*count);
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t <= n; t += (uint64_t)gridDim.x * blockDim.x) {
+    const bool valid = t < m && q[t].read_id != INVALID_READ;
+    const bool sh = valid && q[t].rlen <= STAGE_MAX;
+    fs[t] = (valid && sh) ? 1u : 0u;
+    fl[t] = (valid && !sh) ? 1u : 0u;
+  }
+}
+// ... moved to the front of their bin's list, in order
+__global__ void k_graph_qsplit(const Query *__restrict__ q, const uint64_t *__restrict__ fs, const uint64_t *__restrict__ ps,
+                               const uint64_t *__restrict__ fl, const uint64_t *__restrict__ pl, uint64_t n,
+                               Query *__restrict__ qs, Query *__restrict__ ql) {
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < n; t += (uint64_t)gridDim.x * blockDim.x) {
+    if (fs[t]) qs[ps[t]] = q[t];
+    else if (fl[t]) ql[pl[t]] = q[t];
+  }
+}
+// segments of the first *count queries (as k_seg_count / k_seg_write); [n] = 0; segments at or past
+// cap are not written (the host reports the shortfall from the count)
+__global__ void k_graph_segcount(const Query *__restrict__ q, uint64_t n, const uint64_t *__restrict__ count, uint32_t seg,
+                                 uint64_t *__restrict__ cnt) {
+  const uint64_t m = min(n, *count);
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t <= n; t += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t k = 0;
+    if (t < m) {
+      const uint32_t len = q[t].qend > q[t].qbeg ? q[t].qend - q[t].qbeg : 0u;
+      k = len > seg ? (len + seg - 1) / seg : 1u;
+    }
+    cnt[t] = k;
+  }
+}
+__global__ void k_graph_segwrite(const Query *__restrict__ q, uint64_t n, const uint64_t *__restrict__ count, uint32_t seg,
+                                 const uint64_t *__restrict__ cnt, const uint64_t *__restrict__ off, uint64_t cap,
+                                 Query *__restrict__ out) {
+  const uint64_t m = min(n, *count);
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < m; t += (uint64_t)gridDim.x * blockDim.x) {
+    const Query x = q[t];
+    const uint64_t k = cnt[t];
+    for (uint64_t g = 0; g < k && off[t] + g < cap; ++g) {
+      Query y = x;
+      y.qbeg = x.qbeg + (uint32_t)g * seg;
+      y.send = g + 1 < k ? y.qbeg + seg : x.send;
+      y.flags = g > 0 ? (x.flags | SEG_CHECK) : x.flags;
+      out[off[t] + g] = y;
+    }
+  }
+}
+__global__ void k_fill_u32(uint32_t *__restrict__ p, uint64_t n, uint32_t v) {
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < n; t += (uint64_t)gridDim.x * blockDim.x) p[t] = v;
 }
 
 __global__ void k_fill_u64(uint64_t *__restrict__ p, uint64_t n, uint64_t v) {
@@ -2491,11 +2557,14 @@ __global__ void k_fill_u64(uint64_t *__restrict__ p, uint64_t n, uint64_t v) {
 // the counts the host checks after a replay, into pinned host memory: the control block, the
 // unique seeds and the positions
 __global__ void k_graph_counts(const unsigned long long *__restrict__ ctl, const uint32_t *__restrict__ nu,
-                               const uint64_t *__restrict__ npos, uint64_t *__restrict__ out) {
+                               const uint64_t *__restrict__ npos, uint64_t *__restrict__ out,
+                               const uint64_t *__restrict__ seg1, const uint64_t *__restrict__ seg2) {
   const int t = threadIdx.x;
   if (t < C_COUNT) out[t] = ctl[t];
   if (t == C_COUNT) out[t] = *nu;
   if (t == C_COUNT + 1) out[t] = *npos;
+  if (t == C_COUNT + 2) out[t] = seg1 ? *seg1 : 0;   // segments of the long reads and of their sub-queries
+  if (t == C_COUNT + 3) out[t] = seg2 ? *seg2 : 0;
   __threadfence_system();
 }
 
@@ -2505,8 +2574,9 @@ struct mbw_graph {
   mbw_ctx *ctx = nullptr;
   const mbw_index *ix = nullptr;    // kept alive while the graph exists (its kernels read it)
   int device = 0;
-  uint64_t N = 0, B = 0, W = 0, S = 0, Q = 0, X = 0;
+  uint64_t N = 0, B = 0, L = 0, W = 0, S = 0, Q = 0, X = 0, QS1 = 0, QS2 = 0;
   int reseed = 0, launches = 0;
+  const uint64_t *seg_counts[2] = {nullptr, nullptr};
   std::vector<void *> dev;          // device allocations
   uint8_t *reads = nullptr;
   uint32_t *lens = nullptr;
@@ -2576,8 +2646,12 @@ extern "C" int mbw_graph_create(mbw_ctx *c, const mbw_graph_plan *plan, int min_
   if (o.wave_chunk < 0 || o.wave_chunk > WORK_CHUNK) { mbw_set_error("wave_chunk must be in [0,256]"); return MBW_E_INVAL; }
   const uint64_t N = plan->max_reads;
   if (N < 1 || N >= (1ull << 31)) { mbw_set_error("graph: max_reads must be in [1, 2^31)"); return MBW_E_INVAL; }
-  const uint64_t B = plan->max_bases ? plan->max_bases : N * STAGE_MAX;
-  if (B > N * STAGE_MAX) { mbw_set_error("graph: max_bases above max_reads x 160"); return MBW_E_INVAL; }
+  const uint64_t L = plan->max_read_len ? plan->max_read_len : STAGE_MAX;
+  if (L > MBW_MAX_READ) { mbw_set_error("graph: max_read_len above 65535"); return MBW_E_INVAL; }
+  const uint64_t B = plan->max_bases ? plan->max_bases : N * L;
+  if (B > N * L) { mbw_set_error("graph: max_bases above max_reads x max_read_len"); return MBW_E_INVAL; }
+  const bool binned = L > STAGE_MAX;          // reads too long for LDS staging: the unstaged bin, in segments
+  const uint32_t seg = o.seg_len > 0 ? (uint32_t)std::max(32, o.seg_len) : 256u;
   TRY(hipSetDevice(c->device));
   const mbw_index *ix = c->ix;
   const IndexView v = make_view(ix);
@@ -2586,13 +2660,12 @@ extern "C" int mbw_graph_create(mbw_ctx *c, const mbw_graph_plan *plan, int min_
   g->device = c->device;
   g->ix = ix;
   mbw_index_retain(ix);
-  g->N = N; g->B = B;
+  g->N = N; g->B = B; g->L = L;
   g->W = B / 32 + N + 2;                      // packed words: each read adds at most one partial word
   g->reseed = o.reseed;
   // seeding parameters, as the eager path sets them
   SeedParams P;
   memset(&P, 0, sizeof(P));
-  P.n_queries = N;
   P.l = min_seed_len; P.c = o.min_occ; P.reseed = o.reseed; P.reseed_len = o.reseed_len; P.reseed_occ = o.reseed_occ;
   P.round = 1; P.use_kmer = o.use_kmer;
   {
@@ -2603,23 +2676,34 @@ extern "C" int mbw_graph_create(mbw_ctx *c, const mbw_graph_plan *plan, int min_
     P.rshift = pow2(ix->sa_sample) ? lg(ix->sa_sample) : 0;
     P.rishift = pow2(ix->isa_sample) ? lg(ix->isa_sample) : 0;
   }
-  const int grid1 = P.uniq ? wave_grid<true, true>(c, P, o) : wave_grid<true, false>(c, P, o);
-  // capacities: seeds and sub-queries as the plan gives them, else 8 seeds and 2 sub-queries per read,
-  // plus one output chunk per wave of each launch that writes them
-  SeedParams P2 = P;
-  P2.round = 2; P2.uniq = 0;
-  const uint64_t slack1 = (uint64_t)grid1 * SMEM_WAVES * OUT_CHUNK;
+  // capacities and grids.  Every launch that writes seeds or re-seeding queries leaves at most one
+  // partly used output chunk per wave, which the seed and sub-query capacities add.
+  const uint64_t QS1 = binned ? B / seg + N + 1 : 0;   // segments of the long reads
+  SeedParams P1s = P, P1l = P;
+  P1s.n_queries = N;
+  P1l.n_queries = QS1;
+  const int g1s = P.uniq ? wave_grid<true, true>(c, P1s, o) : wave_grid<true, false>(c, P1s, o);
+  const int g1l = binned ? (P.uniq ? wave_grid<false, true>(c, P1l, o) : wave_grid<false, false>(c, P1l, o)) : 0;
+  const uint64_t slack1 = (uint64_t)(g1s + g1l) * SMEM_WAVES * OUT_CHUNK;
   g->Q = (plan->max_subqueries ? plan->max_subqueries : 2 * N) + slack1;
-  P2.n_queries = g->Q;
-  const int grid2 = wave_grid<true, false>(c, P2, o);
-  g->S = (plan->max_seeds ? plan->max_seeds : 8 * N) + slack1 + (o.reseed ? (uint64_t)grid2 * SMEM_WAVES * OUT_CHUNK : 0);
+  const uint64_t Q = g->Q;
+  const uint64_t QS2 = binned ? Q + 4 * (B / seg) + 1 : 0;   // segments of the long reads' sub-queries
+  SeedParams P2s = P, P2l = P;
+  P2s.round = P2l.round = 2; P2s.uniq = P2l.uniq = 0;
+  P2s.n_queries = Q;
+  P2l.n_queries = QS2;
+  const int g2s = wave_grid<true, false>(c, P2s, o);
+  const int g2l = binned ? wave_grid<false, false>(c, P2l, o) : 0;
+  g->S = (plan->max_seeds ? plan->max_seeds : 8 * N) + slack1 + (o.reseed ? (uint64_t)(g2s + g2l) * SMEM_WAVES * OUT_CHUNK : 0);
   g->X = plan->max_positions ? plan->max_positions : 64 * N;
+  g->QS1 = QS1; g->QS2 = QS2;
   if (g->S >= (1ull << 32) - 2) { mbw_set_error("graph: too many seeds for one plan"); graph_destroy(g); return MBW_E_INVAL; }
-  const uint64_t S = g->S, Q = g->Q, X = g->X, W = g->W;
+  const uint64_t S = g->S, X = g->X, W = g->W;
   // device buffers
-  uint64_t *wide, *offs, *nwords, *woff, *pw, *keys0, *keys1, *npos, *posoff, *kpos, *xrows, *qf, *qp;
+  uint64_t *wide, *offs, *nwords, *woff, *pw, *keys0, *keys1, *npos, *posoff, *kpos, *xrows;
+  uint64_t *f2s, *p2s, *f2l, *p2l;
   uint32_t *wread, *pn, *vals0, *vals1, *flag, *idx;
-  Query *q1, *subq, *q2;
+  Query *q1, *subq, *q2s;
   SeedRec *raw;
   unsigned long long *ctl;
   GALLOC(g->reads, B + 64);
@@ -2627,11 +2711,24 @@ extern "C" int mbw_graph_create(mbw_ctx *c, const mbw_graph_plan *plan, int min_
   GALLOC(g->nreads, 1);
   GALLOC(wide, N + 1); GALLOC(offs, N + 1); GALLOC(nwords, N + 1); GALLOC(woff, N + 1);
   GALLOC(wread, W); GALLOC(pw, W + 2); GALLOC(pn, W + 2);
-  GALLOC(q1, N); GALLOC(raw, S); GALLOC(subq, Q); GALLOC(q2, Q); GALLOC(qf, Q + 1); GALLOC(qp, Q + 1);
+  GALLOC(q1, N); GALLOC(raw, S); GALLOC(subq, Q); GALLOC(q2s, Q);
+  GALLOC(f2s, Q + 1); GALLOC(p2s, Q + 1); GALLOC(f2l, Q + 1); GALLOC(p2l, Q + 1);
   GALLOC(keys0, S); GALLOC(keys1, S); GALLOC(vals0, S); GALLOC(vals1, S); GALLOC(flag, S + 1); GALLOC(idx, S + 1);
   GALLOC(g->seeds, S); GALLOC(npos, S + 1); GALLOC(posoff, S + 1); GALLOC(kpos, S + 1);
   GALLOC(xrows, X + 1); GALLOC(g->pos, X + 1);
   GALLOC(ctl, C_COUNT);
+  // the unstaged bin
+  uint64_t *fs1 = nullptr, *ps1 = nullptr, *nlong = nullptr, *c1 = nullptr, *o1 = nullptr, *c2 = nullptr, *o2 = nullptr;
+  uint32_t *ids_s = nullptr, *lk0 = nullptr, *lk1 = nullptr, *li0 = nullptr, *li1 = nullptr;
+  Query *ql = nullptr, *q1seg = nullptr, *q2l = nullptr, *q2seg = nullptr;
+  if (binned) {
+    GALLOC(fs1, N + 1); GALLOC(ps1, N + 1); GALLOC(nlong, 1);
+    GALLOC(ids_s, N); GALLOC(lk0, N); GALLOC(lk1, N); GALLOC(li0, N); GALLOC(li1, N);
+    GALLOC(ql, N); GALLOC(c1, N + 1); GALLOC(o1, N + 1); GALLOC(q1seg, QS1);
+    GALLOC(q2l, Q); GALLOC(c2, Q + 1); GALLOC(o2, Q + 1); GALLOC(q2seg, QS2);
+  }
+  g->seg_counts[0] = o1 ? o1 + N : nullptr;
+  g->seg_counts[1] = o2 ? o2 + Q : nullptr;
   bool capturing = false;
   GTRY(hipMemset(xrows, 0xff, (X + 1) * sizeof(uint64_t)));   // every row starts as NO_POS
   if (hipHostMalloc((void **)&g->hio, 64 * sizeof(uint64_t), hipHostMallocCoherent) != hipSuccess ||
@@ -2641,19 +2738,23 @@ extern "C" int mbw_graph_create(mbw_ctx *c, const mbw_graph_plan *plan, int min_
     graph_destroy(g);
     return MBW_E_NOMEM;
   }
-  int qb = 1;                                   // bits of an offset within a read of at most 160 bases
-  while ((1ull << qb) <= STAGE_MAX) ++qb;
+  int qb = 1;                                   // bits of an offset within a read of at most L bases
+  while ((1ull << qb) <= L) ++qb;
   int hibit = 2 * qb + 1;
   while (hibit < 64 && (1ull << (hibit - 2 * qb)) <= N) ++hibit;
   // temporary storage: the largest any sort or scan of the graph asks for
   prim::dbuf<uint64_t> dk(keys0, keys1);
   prim::dbuf<uint32_t> dv(vals0, vals1);
+  prim::dbuf<uint32_t> dlk(lk0, lk1), dli(li0, li1);
   size_t tb = 0, t1 = 0;
   GTRY(prim::exclusive_sum((void *)nullptr, t1, wide, offs, N + 1, (hipStream_t)0)); tb = std::max(tb, t1);
-  GTRY(prim::sort_pairs((void *)nullptr, t1, dk, dv, S, 0, hibit, (hipStream_t)0)); tb = std::max(tb, t1);
+  GTRY(prim::sort_pairs_merge((void *)nullptr, t1, dk, dv, S, 0, hibit, (hipStream_t)0)); tb = std::max(tb, t1);
   GTRY(prim::exclusive_sum((void *)nullptr, t1, flag, idx, S + 1, (hipStream_t)0)); tb = std::max(tb, t1);
   GTRY(prim::exclusive_sum((void *)nullptr, t1, npos, posoff, S + 1, (hipStream_t)0)); tb = std::max(tb, t1);
-  GTRY(prim::exclusive_sum((void *)nullptr, t1, qf, qp, Q + 1, (hipStream_t)0)); tb = std::max(tb, t1);
+  GTRY(prim::exclusive_sum((void *)nullptr, t1, f2s, p2s, Q + 1, (hipStream_t)0)); tb = std::max(tb, t1);
+  if (binned) {
+    GTRY(prim::sort_pairs_merge((void *)nullptr, t1, dlk, dli, N, 0, 17, (hipStream_t)0)); tb = std::max(tb, t1);
+  }
   uint8_t *temp;
   GALLOC(temp, tb + 256);
   GTRY(hipStreamCreateWithFlags(&g->cs, hipStreamNonBlocking));
@@ -2661,16 +2762,26 @@ extern "C" int mbw_graph_create(mbw_ctx *c, const mbw_graph_plan *plan, int min_
   GTRY(hipEventCreate(&g->ev1));
   ReadWords R;
   R.pw = pw; R.pn = pn; R.woff = woff;
-  P.queries = q1; P.seeds = raw; P.seed_cap = S; P.subq = subq; P.subq_cap = Q; P.ctl = ctl;
-  P2.queries = q2; P2.seeds = raw; P2.seed_cap = S; P2.subq = nullptr; P2.subq_cap = 0; P2.ctl = ctl;
-  P2.nq_dev = (const unsigned long long *)(qp + Q);
+  for (SeedParams *pp : {&P1s, &P1l}) {
+    pp->seeds = raw; pp->seed_cap = S; pp->subq = subq; pp->subq_cap = Q; pp->ctl = ctl;
+  }
+  for (SeedParams *pp : {&P2s, &P2l}) {
+    pp->seeds = raw; pp->seed_cap = S; pp->subq = nullptr; pp->subq_cap = 0; pp->ctl = ctl;
+  }
+  P1s.queries = q1; P1s.nq_dev = binned ? (const unsigned long long *)(ps1 + N) : nullptr;
+  P1l.queries = q1seg; P1l.nq_dev = binned ? (const unsigned long long *)(o1 + N) : nullptr;
+  P2s.queries = q2s; P2s.nq_dev = (const unsigned long long *)(p2s + Q);
+  P2l.queries = q2seg; P2l.nq_dev = binned ? (const unsigned long long *)(o2 + Q) : nullptr;
   auto chunk_for = [&](int grid, uint64_t n) {
     if (o.wave_chunk > 0) return (uint32_t)std::min(WORK_CHUNK, o.wave_chunk);
     const uint64_t waves = (uint64_t)std::max(grid, 1) * SMEM_WAVES;
     return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(WORK_CHUNK, n / (waves * 8)));
   };
-  P.chunk = chunk_for(grid1, N);
-  P2.chunk = chunk_for(grid2, 2 * N);
+  // expected counts (the plan's reads, about 1.5 sub-queries per read) set the automatic takes
+  P1s.chunk = chunk_for(g1s, N);
+  P1l.chunk = chunk_for(g1l, B / seg);
+  P2s.chunk = chunk_for(g2s, 2 * N);
+  P2l.chunk = chunk_for(g2l, B / seg);
   uint32_t rmask = (ix->sa_sample & (ix->sa_sample - 1)) == 0 ? (uint32_t)(ix->sa_sample - 1) : 0u;
   int rshift = -1;
   if ((ix->sa_sample & (ix->sa_sample - 1)) == 0) { rshift = 0; while ((1 << rshift) < ix->sa_sample) ++rshift; }
@@ -2680,6 +2791,7 @@ extern "C" int mbw_graph_create(mbw_ctx *c, const mbw_graph_plan *plan, int min_
   GTRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   capturing = true;
   size_t have = tb + 256;
+  // lengths -> offsets, packed words (as the eager path)
   k_graph_prep<<<grid_for(N), 256, 0, st>>>(g->lens, N, g->nreads, ctl, flag + S);
   k_widen<<<grid_for(N + 1, 256, 1024u), 256, 0, st>>>(g->lens, N, wide, ctl + C_MAXLEN);
   GTRY(prim::exclusive_sum((void *)temp, have, wide, offs, N + 1, st));
@@ -2689,23 +2801,61 @@ extern "C" int mbw_graph_create(mbw_ctx *c, const mbw_graph_plan *plan, int min_
   k_word_owner<<<grid_for(N), 256, 0, st>>>(woff, N, wread);
   k_pack_words<<<(unsigned)((W + PACK_BLOCK - 1) / PACK_BLOCK), PACK_BLOCK, 0, st>>>(g->reads, B, offs, woff, wread, W, 0, pw, pn,
                                                                                        offs + N, woff + N);
-  k_make_queries<<<grid_for(N), 256, 0, st>>>(nullptr, N, offs, woff, (uint32_t)min_seed_len, (uint32_t)o.min_occ, q1);
-  k_ctl_zero<<<1, 64, 0, st>>>(ctl, C_WORK, C_WORK);
-  if (P.uniq) k_smem_wave<true, true><<<grid1, bs, 0, st>>>(v, P, R);
-  else k_smem_wave<true, false><<<grid1, bs, 0, st>>>(v, P, R);
-  g->launches = 1;
-  if (o.reseed) {
-    k_graph_qflags<<<grid_for(Q + 1), 256, 0, st>>>(subq, Q, ctl + C_NSUBQ, qf);
+  // round 1: the staged bin in read order, the other reads longest first and in segments
+  if (!binned) {
+    k_make_queries<<<grid_for(N), 256, 0, st>>>(nullptr, N, offs, woff, (uint32_t)min_seed_len, (uint32_t)o.min_occ, q1);
+  } else {
+    k_graph_rflags<<<grid_for(N + 1), 256, 0, st>>>(offs, N, fs1);
     have = tb + 256;
-    GTRY(prim::exclusive_sum((void *)temp, have, qf, qp, Q + 1, st));
-    k_graph_qcompact<<<grid_for(Q), 256, 0, st>>>(subq, qf, qp, Q, q2);
-    k_ctl_zero<<<1, 64, 0, st>>>(ctl, C_WORK, C_WORK);
-    k_smem_wave<true, false><<<grid2, bs, 0, st>>>(v, P2, R);
-    g->launches = 2;
+    GTRY(prim::exclusive_sum((void *)temp, have, fs1, ps1, N + 1, st));
+    k_fill_u32<<<grid_for(N), 256, 0, st>>>(lk0, N, 0x10000u);
+    k_graph_rsplit<<<grid_for(N), 256, 0, st>>>(offs, N, fs1, ps1, ids_s, lk0, li0, nlong);
+    have = tb + 256;
+    GTRY(prim::sort_pairs_merge((void *)temp, have, dlk, dli, N, 0, 17, st));
+    k_make_queries<<<grid_for(N), 256, 0, st>>>(ids_s, N, offs, woff, (uint32_t)min_seed_len, (uint32_t)o.min_occ, q1,
+                                                ps1 + N);
+    k_make_queries<<<grid_for(N), 256, 0, st>>>(dli.current(), N, offs, woff, (uint32_t)min_seed_len, (uint32_t)o.min_occ,
+                                                ql, nlong);
+    k_graph_segcount<<<grid_for(N + 1), 256, 0, st>>>(ql, N, nlong, seg, c1);
+    have = tb + 256;
+    GTRY(prim::exclusive_sum((void *)temp, have, c1, o1, N + 1, st));
+    k_graph_segwrite<<<grid_for(N), 256, 0, st>>>(ql, N, nlong, seg, c1, o1, QS1, q1seg);
   }
+  k_ctl_zero<<<1, 64, 0, st>>>(ctl, C_WORK, C_WORK);
+  if (P.uniq) k_smem_wave<true, true><<<g1s, bs, 0, st>>>(v, P1s, R);
+  else k_smem_wave<true, false><<<g1s, bs, 0, st>>>(v, P1s, R);
+  g->launches = 1;
+  if (binned) {
+    k_ctl_zero<<<1, 64, 0, st>>>(ctl, C_WORK, C_WORK);
+    if (P.uniq) k_smem_wave<false, true><<<g1l, bs, 0, st>>>(v, P1l, R);
+    else k_smem_wave<false, false><<<g1l, bs, 0, st>>>(v, P1l, R);
+    ++g->launches;
+  }
+  // round 2: the re-seeding queries by bin, compacted, the long ones in segments
+  if (o.reseed) {
+    k_graph_qflags<<<grid_for(Q + 1), 256, 0, st>>>(subq, Q, ctl + C_NSUBQ, f2s, f2l);
+    have = tb + 256;
+    GTRY(prim::exclusive_sum((void *)temp, have, f2s, p2s, Q + 1, st));
+    have = tb + 256;
+    GTRY(prim::exclusive_sum((void *)temp, have, f2l, p2l, Q + 1, st));
+    k_graph_qsplit<<<grid_for(Q), 256, 0, st>>>(subq, f2s, p2s, f2l, p2l, Q, q2s, binned ? q2l : q2s);
+    k_ctl_zero<<<1, 64, 0, st>>>(ctl, C_WORK, C_WORK);
+    k_smem_wave<true, false><<<g2s, bs, 0, st>>>(v, P2s, R);
+    ++g->launches;
+    if (binned) {
+      k_graph_segcount<<<grid_for(Q + 1), 256, 0, st>>>(q2l, Q, p2l + Q, seg, c2);
+      have = tb + 256;
+      GTRY(prim::exclusive_sum((void *)temp, have, c2, o2, Q + 1, st));
+      k_graph_segwrite<<<grid_for(Q), 256, 0, st>>>(q2l, Q, p2l + Q, seg, c2, o2, QS2, q2seg);
+      k_ctl_zero<<<1, 64, 0, st>>>(ctl, C_WORK, C_WORK);
+      k_smem_wave<false, false><<<g2l, bs, 0, st>>>(v, P2l, R);
+      ++g->launches;
+    }
+  }
+  // sort by (read, qbeg, qend), dedup, counts, rows, locate (as the eager path, over capacities)
   k_seed_keys<<<grid_for(S), 256, 0, st>>>(raw, S, N, qb, keys0, vals0, ctl + C_NSEEDS);
   have = tb + 256;
-  GTRY(prim::sort_pairs((void *)temp, have, dk, dv, S, 0, hibit, st));
+  GTRY(prim::sort_pairs_merge((void *)temp, have, dk, dv, S, 0, hibit, st));
   k_dedup_mark<<<grid_for(S), 256, 0, st>>>(dk.current(), S, N, qb, flag);
   have = tb + 256;
   GTRY(prim::exclusive_sum((void *)temp, have, flag, idx, S + 1, st));
@@ -2716,7 +2866,7 @@ extern "C" int mbw_graph_create(mbw_ctx *c, const mbw_graph_plan *plan, int min_
   k_expand_rows<<<grid_for((S + 63) / 64 * 64 / 4, 256, 65536u), 256, 0, st>>>(g->seeds, posoff, kpos, S, xrows, g->pos,
                                                                                  idx + S, X);
   k_locate_wave<<<gridL, 256, 0, st>>>(v, xrows, X, g->pos, rmask, rshift, ctl, posoff + S);
-  k_graph_counts<<<1, 64, 0, st>>>(ctl, idx + S, posoff + S, g->dio + 1);
+  k_graph_counts<<<1, 64, 0, st>>>(ctl, idx + S, posoff + S, g->dio + 1, g->seg_counts[0], g->seg_counts[1]);
   GTRY(hipGetLastError());
   capturing = false;
   GTRY(hipStreamEndCapture(st, &g->graph));
@@ -2730,7 +2880,7 @@ extern "C" int mbw_graph_info(const mbw_graph *g, mbw_graph_plan *plan) {
   if (!g || !plan) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
   memset(plan, 0, sizeof(*plan));
   plan->max_reads = g->N; plan->max_bases = g->B; plan->max_seeds = g->S; plan->max_subqueries = g->Q;
-  plan->max_positions = g->X;
+  plan->max_positions = g->X; plan->max_read_len = g->L;
   return MBW_OK;
 }
 
@@ -2758,8 +2908,9 @@ extern "C" int mbw_graph_seed(mbw_graph *g, const uint8_t *reads, const uint32_t
   }
   uint64_t total = 0;
   for (uint64_t r = 0; r < n_reads; ++r) {
-    if (hl[r] > STAGE_MAX) {
-      mbw_set_error("graph: read " + std::to_string(r) + " has " + std::to_string(hl[r]) + " bases; a graph takes reads of at most 160");
+    if (hl[r] > g->L) {
+      mbw_set_error("graph: read " + std::to_string(r) + " has " + std::to_string(hl[r]) + " bases, the plan's reads at most " +
+                    std::to_string(g->L));
       return MBW_E_INVAL;
     }
     total += hl[r];
@@ -2779,17 +2930,19 @@ extern "C" int mbw_graph_seed(mbw_graph *g, const uint8_t *reads, const uint32_t
   TRY(hipGraphLaunch(g->exec, st));
   TRY(hipEventRecord(g->ev1, st));
   TRY(hipStreamSynchronize(st));
-  uint64_t cnt[C_COUNT + 2];
-  for (int t = 0; t < C_COUNT + 2; ++t) cnt[t] = ((volatile uint64_t *)g->hio)[1 + t];
+  uint64_t cnt[C_COUNT + 4];
+  for (int t = 0; t < C_COUNT + 4; ++t) cnt[t] = ((volatile uint64_t *)g->hio)[1 + t];
   if (cnt[C_ERR]) {
     mbw_set_error("kernel guard tripped (" + std::to_string(cnt[C_ERR]) + "): corrupt index or internal error");
     return MBW_E_HIP;
   }
   const uint64_t nu = cnt[C_COUNT], n_pos = cnt[C_COUNT + 1];
-  if (cnt[C_NSEEDS] > g->S || cnt[C_NSUBQ] > g->Q || n_pos > g->X) {
+  if (cnt[C_NSEEDS] > g->S || cnt[C_NSUBQ] > g->Q || n_pos > g->X || cnt[C_COUNT + 2] > g->QS1 || cnt[C_COUNT + 3] > g->QS2) {
     mbw_set_error("graph: the batch needs " + std::to_string(cnt[C_NSEEDS]) + " seed slots, " + std::to_string(cnt[C_NSUBQ]) +
-                  " sub-query slots and " + std::to_string(n_pos) + " positions; the plan holds " + std::to_string(g->S) + ", " +
-                  std::to_string(g->Q) + " and " + std::to_string(g->X) + " (seed it with mbw_seed, or use a larger plan)");
+                  " sub-query slots, " + std::to_string(n_pos) + " positions and " + std::to_string(cnt[C_COUNT + 2]) + " + " +
+                  std::to_string(cnt[C_COUNT + 3]) + " segments; the plan holds " + std::to_string(g->S) + ", " +
+                  std::to_string(g->Q) + ", " + std::to_string(g->X) + " and " + std::to_string(g->QS1) + " + " +
+                  std::to_string(g->QS2) + " (seed it with mbw_seed, or use a larger plan)");
     return MBW_E_CAPACITY;
   }
   float ms = 0;

@@ -137,3 +137,67 @@ def test_graph_refusals(small):
     with pytest.raises(mbw.MbwError):
         ctx.graph(0)
     ctx.free()
+
+
+@pytest.fixture(scope="module")
+def ragged(small):
+    """3,000 reads of 20-700 bases with N runs (both length bins, segments) and the oracle's result."""
+    ref, _, idx = small
+    rs = synth.reads_uniform_len(ref, 3000, 20, 700, seed=61)
+    seq = rs.seq.copy()
+    rng = np.random.default_rng(62)
+    for r in range(0, len(rs), 9):
+        a, n = int(rs.offsets[r]), int(rs.lengths[r])
+        if n > 60:
+            seq[a + 30:a + 30 + int(rng.integers(1, 8))] = ord("N")
+    rs = synth.ReadSet(seq, rs.lengths, rs.offsets, rs.tpos, rs.tstrand)
+    ox = oracle.OracleIndex(ref.codes, sa_rate=8)
+    return rs, ox.seed(rs.seq, rs.offsets, min_len=19, max_occ=500)
+
+
+@pytest.mark.parametrize("kw", [{}, dict(seg_len=32), dict(unique_ext=False, seg_len=100)])
+def test_graph_length_bins(small, ragged, kw):
+    """Reads of 20-700 bases: a plan with max_read_len 700 runs the staged bin and the long reads in
+    segments (both rounds) inside the graph; equal to mbw_seed and the oracle."""
+    ref, _, idx = small
+    rs, exp = ragged
+    ctx = mbw.Context(idx)
+    g = ctx.graph(len(rs), max_read_len=700, **kw)
+    plan = g.plan()
+    assert plan["max_read_len"] == 700 and plan["max_bases"] == len(rs) * 700
+    out = g.seed(rs.seq, rs.lengths)
+    s, p = same(out, ctx.seed(rs.seq, rs.lengths, **kw))
+    compare_with_oracle(s, p, exp)
+    assert out.n_smem_launches == 4
+    g.free()
+    ctx.free()
+
+
+def test_graph_length_bins_replays(small, ragged):
+    """One binned graph (above a million seed slots) replayed on batches of only short reads, only
+    long reads, a mix and an empty batch, twice each with eager calls in between; every replay
+    equals mbw_seed.  A read longer than
+    the plan's max_read_len is refused."""
+    ref, reads, idx = small
+    rs, _ = ragged
+    longs = np.flatnonzero(rs.lengths > 160)
+    shorts = np.flatnonzero(rs.lengths <= 160)
+    batches = [subset(rs, longs[:800]), subset(rs, shorts), subset(rs, np.sort(np.concatenate([longs[800:1200],
+               shorts[:300]]))), subset(rs, []), subset(reads, range(2000))]
+    ctx = mbw.Context(idx)
+    g = ctx.graph(2000, max_read_len=700)
+    # more seed slots than rocPRIM's merge-sort limit (2^20): the graph's sorts must still avoid the
+    # onesweep path, whose resets are memsets, on every replay
+    assert g.plan()["max_seeds"] > 1 << 20
+    for b in batches:
+        for rep in range(2):
+            eager = ctx.seed(b.seq, b.lengths)
+            torch.cuda.synchronize()
+            out = g.seed(b.seq, b.lengths)
+            same(out, eager)
+    too_long = np.frombuffer(b"ACGT" * 200, dtype=np.uint8)
+    with pytest.raises(mbw.MbwError) as e:
+        g.seed(too_long, np.array([800], np.uint32))
+    assert e.value.code == mbw.MBW_E_INVAL
+    g.free()
+    ctx.free()
