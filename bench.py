@@ -425,8 +425,32 @@ def workload_leg(mbw, torch, synth, name: str, args, steps: int = 3):
         po = step(mbw.KERNEL_PLAIN)
         torch.cuda.synchronize()
         pel = time.perf_counter() - t2
+        # the same batch through a captured graph planned for it (the tuned schedule where a graph takes
+        # it; capacities from this batch's counts with room to spare)
+        graph = None
+        gkw = {k: v for k, v in best.items() if k in ("unique_ext", "seg_len", "blocks_per_cu", "wave_chunk")}
+        g = ctx.graph(len(reads), max_bases=int(reads.lengths.sum()), max_read_len=int(reads.lengths.max()),
+                      max_seeds=2 * int(o.n_seeds) + 1024, max_positions=2 * int(o.n_pos) + 1024, min_seed_len=19,
+                      max_occ=500, **gkw)
+        try:
+            hl = reads.lengths
+            go = g.seed(dseq, hl, stream=stream)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            for _ in range(steps):
+                go = g.seed(dseq, hl, stream=stream)
+            torch.cuda.synchronize()
+            gel = time.perf_counter() - t3
+            graph = dict(value=round(len(reads) * steps / gel, 1), ms_per_step=round(gel / steps * 1e3, 2),
+                         same_counts=bool(go.n_seeds == o.n_seeds and go.n_pos == o.n_pos),
+                         launches=int(go.n_smem_launches),
+                         note="mbw_graph_seed: the whole call replayed from one captured graph (length bins, "
+                              "segments), one host wait per call; sorts and scans span the plan's capacities")
+        finally:
+            g.free()
         res = dict(workload=wl["desc"], reads=len(reads), bases=int(reads.lengths.sum()),
                    value=round(len(reads) * steps / el, 1), unit="reads/s", ms_per_step=round(el / steps * 1e3, 2),
+                   graph=graph,
                    plain_kernel=round(len(reads) / pel, 1), same_result=bool(po.n_seeds == o.n_seeds and po.n_pos == o.n_pos),
                    seeds=int(o.n_seeds), positions=int(o.n_pos), schedule=best, kmer_k=idx.info()["kmer_k"],
                    lines_per_read=round(o.lines_smem / len(reads), 1),
