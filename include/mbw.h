@@ -318,10 +318,12 @@ typedef struct {
                                reads add the unstaged bin: segments of seg_len bases, at most
                                max_bases / seg + max_reads in round 1 and max_subqueries +
                                4 max_bases / seg in round 2 */
+  uint64_t max_pieces;      /* bs_refine: refined pieces; 0 = max_positions */
 } mbw_graph_plan;
 /* Allocate the plan's buffers on the context's device (mbw_graph_info reports the capacities with
- * slack) and capture the graph.  opts as for mbw_seed; the wave kernels with LDS staging: the plain
- * kernel, no_stage, bisulfite roles and unique_defer are refused (MBW_E_INVAL).  Errors:
+ * slack) and capture the graph.  opts as for mbw_seed, bisulfite roles and refinement included
+ * (the strand filter and the refinement run inside the graph); the plain kernel, no_stage and
+ * unique_defer are refused (MBW_E_INVAL).  Errors:
  * MBW_E_INVAL, MBW_E_NOMEM, MBW_E_HIP (capture or instantiation failed). */
 int mbw_graph_create(mbw_ctx *ctx, const mbw_graph_plan *plan, int min_seed_len, int max_occ,
                      const mbw_seed_opts *opts, mbw_graph **out);
@@ -331,7 +333,7 @@ int mbw_graph_info(const mbw_graph *g, mbw_graph_plan *plan);   /* capacities, s
  * call or mbw_graph_free; mbw_result_download with the graph's context copies it out.  ms_total is
  * the graph's device time (ms_smem and ms_locate are not split out).  Errors: MBW_E_INVAL (more
  * reads or bases than the plan, a read longer than its max_read_len), MBW_E_CAPACITY (the batch
- * needs more seed, sub-query, segment or position slots than the plan holds: the message gives the
+ * needs more seed, sub-query, segment, position or piece slots than the plan holds: the message gives the
  * counts; seed it with mbw_seed or a larger plan), MBW_E_HIP. */
 int mbw_graph_seed(mbw_graph *g, const uint8_t *reads, const uint32_t *lengths, uint64_t n_reads, void *stream,
                    mbw_result *out);

@@ -66,7 +66,8 @@ class IndexInfo(C.Structure):
 
 class GraphPlan(C.Structure):
     _fields_ = [("max_reads", C.c_uint64), ("max_bases", C.c_uint64), ("max_seeds", C.c_uint64),
-                ("max_subqueries", C.c_uint64), ("max_positions", C.c_uint64), ("max_read_len", C.c_uint64)]
+                ("max_subqueries", C.c_uint64), ("max_positions", C.c_uint64), ("max_read_len", C.c_uint64),
+                ("max_pieces", C.c_uint64)]
 
 
 class SeedOpts(C.Structure):
@@ -596,12 +597,12 @@ class Context:
                            res.max_read_anchors, res.reads_over_lds, res, self)
 
     def graph(self, max_reads: int, max_bases: int = 0, max_seeds: int = 0, max_subqueries: int = 0,
-              max_positions: int = 0, max_read_len: int = 0, min_seed_len: int = 19, max_occ: int = 500,
-              **kw) -> "Graph":
+              max_positions: int = 0, max_read_len: int = 0, max_pieces: int = 0, min_seed_len: int = 19,
+              max_occ: int = 500, **kw) -> "Graph":
         """``mbw_graph_create``: the seeding path captured once as a HIP graph for batches of at most
         ``max_reads`` reads of at most ``max_read_len`` bases (0: 160; options as for :meth:`seed`)."""
         plan = GraphPlan(int(max_reads), int(max_bases), int(max_seeds), int(max_subqueries), int(max_positions),
-                         int(max_read_len))
+                         int(max_read_len), int(max_pieces))
         h = C.c_void_p()
         _check(self._lib.mbw_graph_create(self._h, C.byref(plan), int(min_seed_len), int(max_occ),
                                           C.byref(self._opts(kw)), C.byref(h)))

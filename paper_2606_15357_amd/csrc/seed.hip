@@ -1371,9 +1371,13 @@ __global__ void __launch_bounds__(256) k_locate_wave(IndexView ix, const uint64_
 
 // ---------------------------------------------------------------------------------------------
 // bisulfite strand filter (Section 2.9): segment = pos / |R| of T over the four copies
-__global__ void k_bs_mark(const uint64_t *__restrict__ pos, uint64_t np, uint64_t len_r, int role, uint32_t *__restrict__ keep) {
+// np_p (captured graphs): the positions on the device, at most the capacity np; slots from there
+// to np are not kept
+__global__ void k_bs_mark(const uint64_t *__restrict__ pos, uint64_t np, uint64_t len_r, int role, uint32_t *__restrict__ keep,
+                          const uint64_t *__restrict__ np_p = nullptr) {
+  const uint64_t nv = np_p ? min(np, *np_p) : np;
   for (uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; w <= np; w += (uint64_t)gridDim.x * blockDim.x) {
-    if (w == np) { keep[w] = 0; continue; }
+    if (w >= nv) { keep[w] = 0; continue; }
     const uint64_t seg = pos[w] / len_r;
     keep[w] = (role == 1) ? (seg == 0 || seg == 2) : (seg == 1 || seg == 3);
   }
@@ -1385,9 +1389,13 @@ __global__ void k_bs_compact(const uint64_t *__restrict__ pos, const uint32_t *_
     if (keep[w]) out[kidx[w]] = pos[w];
 }
 
-__global__ void k_bs_seeds(mbw_seed_t *__restrict__ seeds, uint64_t ns, const uint64_t *__restrict__ kidx) {
+// ns_p / cap (captured graphs): the seed count on the device; position offsets clamped to the
+// position capacity (past it the result is refused anyway)
+__global__ void k_bs_seeds(mbw_seed_t *__restrict__ seeds, uint64_t ns, const uint64_t *__restrict__ kidx,
+                           const uint32_t *__restrict__ ns_p = nullptr, uint64_t cap = ~0ull) {
+  if (ns_p) ns = min(ns, (uint64_t)*ns_p);
   for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < ns; t += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t a = seeds[t].pos_off, b = a + seeds[t].npos;
+    const uint64_t a = min(seeds[t].pos_off, cap), b = min(seeds[t].pos_off + seeds[t].npos, cap);
     seeds[t].pos_off = kidx[a];
     seeds[t].npos = (uint32_t)(kidx[b] - kidx[a]);
   }
@@ -1400,7 +1408,9 @@ __global__ void k_bs_seeds(mbw_seed_t *__restrict__ seeds, uint64_t ns, const ui
 // least min_len bases are kept with their own text positions
 
 // the seed of every kept position
-__global__ void __launch_bounds__(256) k_pos_seed(const mbw_seed_t *__restrict__ seeds, uint64_t ns, uint32_t *__restrict__ ps) {
+__global__ void __launch_bounds__(256) k_pos_seed(const mbw_seed_t *__restrict__ seeds, uint64_t ns, uint32_t *__restrict__ ps,
+                                                  const uint32_t *__restrict__ ns_p = nullptr, uint64_t cap = ~0ull) {
+  if (ns_p) ns = min(ns, (uint64_t)*ns_p);   // captured graphs: the seed count on the device; ps holds cap
   const int lane = threadIdx.x & 63;
   const uint64_t nwave = (uint64_t)gridDim.x * (blockDim.x >> 6);
   for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64; base < ns; base += nwave * 64) {
@@ -1411,7 +1421,7 @@ __global__ void __launch_bounds__(256) k_pos_seed(const mbw_seed_t *__restrict__
     for (int t = 0; t < cnt; ++t) {
       const uint64_t ot = __shfl(off, t);
       const uint32_t nt = (uint32_t)__shfl((int)np, t);
-      for (uint32_t q = (uint32_t)lane; q < nt; q += 64) ps[ot + q] = (uint32_t)(base + t);
+      for (uint32_t q = (uint32_t)lane; q < nt && ot + q < cap; q += 64) ps[ot + q] = (uint32_t)(base + t);
     }
   }
 }
@@ -1431,7 +1441,9 @@ __global__ void k_refine(const mbw_seed_t *__restrict__ seeds, const uint32_t *_
                          const uint64_t *__restrict__ pos, uint64_t np, const uint8_t *__restrict__ ascii,
                          const uint64_t *__restrict__ offs, const uint64_t *__restrict__ orig, uint64_t L, int role,
                          int min_len, uint32_t *__restrict__ cnt, const uint64_t *__restrict__ poff,
-                         mbw_piece_t *__restrict__ out) {
+                         mbw_piece_t *__restrict__ out, const uint64_t *__restrict__ np_p = nullptr,
+                         uint64_t pcap = ~0ull) {
+  if (np_p) np = min(np, *np_p);   // captured graphs: the positions on the device; pieces written below pcap
   const uint32_t bad = role == 1 ? 'C' : 'G';          // read base that cannot face ...
   const int over = role == 1 ? 3 : 0;                  // ... this original reference base
   for (uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; w < np; w += (uint64_t)gridDim.x * blockDim.x) {
@@ -1445,7 +1457,7 @@ __global__ void k_refine(const mbw_seed_t *__restrict__ seeds, const uint32_t *_
       if (!cut) cut = ((uint32_t)P[i] & 0xDFu) == bad && orig_base(orig, L, p + (i - sd.qbeg)) == over;
       if (cut) {
         if (i - start >= (uint32_t)min_len) {
-          if (out) {
+          if (out && poff[w] + c < pcap) {
             mbw_piece_t x;
             x.read_id = sd.read_id; x.qbeg = start; x.qend = i; x.seed = t; x.pos = p + (start - sd.qbeg);
             out[poff[w] + c] = x;
@@ -2558,13 +2570,16 @@ __global__ void k_fill_u64(uint64_t *__restrict__ p, uint64_t n, uint64_t v) {
 // unique seeds and the positions
 __global__ void k_graph_counts(const unsigned long long *__restrict__ ctl, const uint32_t *__restrict__ nu,
                                const uint64_t *__restrict__ npos, uint64_t *__restrict__ out,
-                               const uint64_t *__restrict__ seg1, const uint64_t *__restrict__ seg2) {
+                               const uint64_t *__restrict__ seg1, const uint64_t *__restrict__ seg2,
+                               const uint64_t *__restrict__ kept, const uint64_t *__restrict__ pieces) {
   const int t = threadIdx.x;
   if (t < C_COUNT) out[t] = ctl[t];
   if (t == C_COUNT) out[t] = *nu;
   if (t == C_COUNT + 1) out[t] = *npos;
   if (t == C_COUNT + 2) out[t] = seg1 ? *seg1 : 0;   // segments of the long reads and of their sub-queries
   if (t == C_COUNT + 3) out[t] = seg2 ? *seg2 : 0;
+  if (t == C_COUNT + 4) out[t] = kept ? *kept : 0;       // bisulfite: positions kept by the strand filter
+  if (t == C_COUNT + 5) out[t] = pieces ? *pieces : 0;   // ... and refined pieces
   __threadfence_system();
 }
 
@@ -2574,8 +2589,10 @@ struct mbw_graph {
   mbw_ctx *ctx = nullptr;
   const mbw_index *ix = nullptr;    // kept alive while the graph exists (its kernels read it)
   int device = 0;
-  uint64_t N = 0, B = 0, L = 0, W = 0, S = 0, Q = 0, X = 0, QS1 = 0, QS2 = 0;
-  int reseed = 0, launches = 0;
+  uint64_t N = 0, B = 0, L = 0, W = 0, S = 0, Q = 0, X = 0, QS1 = 0, QS2 = 0, PC = 0;
+  int reseed = 0, launches = 0, bs_role = 0, refine = 0;
+  uint64_t *pos_kept = nullptr;     // bisulfite: the positions the strand filter keeps
+  mbw_piece_t *pieces = nullptr;
   const uint64_t *seg_counts[2] = {nullptr, nullptr};
   std::vector<void *> dev;          // device allocations
   uint8_t *reads = nullptr;
@@ -2639,9 +2656,14 @@ extern "C" int mbw_graph_create(mbw_ctx *c, const mbw_graph_plan *plan, int min_
     o.min_occ = 1; o.reseed = 1; o.reseed_len = 38; o.reseed_occ = 10; o.use_kmer = 1; o.unique_ext = 1;
   }
   if (o.min_occ < 1) { mbw_set_error("min_occ must be >= 1"); return MBW_E_INVAL; }
-  if (o.kernel != MBW_KERNEL_COOP || o.no_stage || o.bs_role || o.bs_refine || o.unique_defer) {
-    mbw_set_error("graph: the wave kernels with LDS staging only (no plain kernel, no_stage, bisulfite or unique_defer)");
+  if (o.kernel != MBW_KERNEL_COOP || o.no_stage || o.unique_defer) {
+    mbw_set_error("graph: the wave kernels with LDS staging only (no plain kernel, no_stage or unique_defer)");
     return MBW_E_INVAL;
+  }
+  if (o.bs_role < 0 || o.bs_role > 2) { mbw_set_error("bs_role must be 0, 1 or 2"); return MBW_E_INVAL; }
+  if (o.bs_role && !c->ix->bisulfite) { mbw_set_error("bs_role needs a bisulfite index"); return MBW_E_INVAL; }
+  if (o.bs_refine && (!o.bs_role || !c->ix->orig)) {
+    mbw_set_error("bs_refine needs bs_role and a bisulfite index"); return MBW_E_INVAL;
   }
   if (o.wave_chunk < 0 || o.wave_chunk > WORK_CHUNK) { mbw_set_error("wave_chunk must be in [0,256]"); return MBW_E_INVAL; }
   const uint64_t N = plan->max_reads;
@@ -2697,6 +2719,8 @@ extern "C" int mbw_graph_create(mbw_ctx *c, const mbw_graph_plan *plan, int min_
   g->S = (plan->max_seeds ? plan->max_seeds : 8 * N) + slack1 + (o.reseed ? (uint64_t)(g2s + g2l) * SMEM_WAVES * OUT_CHUNK : 0);
   g->X = plan->max_positions ? plan->max_positions : 64 * N;
   g->QS1 = QS1; g->QS2 = QS2;
+  g->bs_role = o.bs_role; g->refine = o.bs_refine;
+  g->PC = o.bs_refine ? (plan->max_pieces ? plan->max_pieces : g->X) : 0;
   if (g->S >= (1ull << 32) - 2) { mbw_set_error("graph: too many seeds for one plan"); graph_destroy(g); return MBW_E_INVAL; }
   const uint64_t S = g->S, X = g->X, W = g->W;
   // device buffers
@@ -2727,6 +2751,12 @@ extern "C" int mbw_graph_create(mbw_ctx *c, const mbw_graph_plan *plan, int min_
     GALLOC(ql, N); GALLOC(c1, N + 1); GALLOC(o1, N + 1); GALLOC(q1seg, QS1);
     GALLOC(q2l, Q); GALLOC(c2, Q + 1); GALLOC(o2, Q + 1); GALLOC(q2seg, QS2);
   }
+  // bisulfite strand filter and refinement
+  uint32_t *keep = nullptr, *ps = nullptr, *pc = nullptr;
+  uint64_t *kidx = nullptr, *po = nullptr;
+  const uint64_t PC = g->PC;
+  if (o.bs_role) { GALLOC(keep, X + 1); GALLOC(kidx, X + 1); GALLOC(g->pos_kept, X + 1); }
+  if (o.bs_refine) { GALLOC(ps, X + 1); GALLOC(pc, X + 1); GALLOC(po, X + 1); GALLOC(g->pieces, PC); }
   g->seg_counts[0] = o1 ? o1 + N : nullptr;
   g->seg_counts[1] = o2 ? o2 + Q : nullptr;
   bool capturing = false;
@@ -2755,6 +2785,8 @@ extern "C" int mbw_graph_create(mbw_ctx *c, const mbw_graph_plan *plan, int min_
   if (binned) {
     GTRY(prim::sort_pairs_merge((void *)nullptr, t1, dlk, dli, N, 0, 17, (hipStream_t)0)); tb = std::max(tb, t1);
   }
+  if (o.bs_role) { GTRY(prim::exclusive_sum((void *)nullptr, t1, keep, kidx, X + 1, (hipStream_t)0)); tb = std::max(tb, t1); }
+  if (o.bs_refine) { GTRY(prim::exclusive_sum((void *)nullptr, t1, pc, po, X + 1, (hipStream_t)0)); tb = std::max(tb, t1); }
   uint8_t *temp;
   GALLOC(temp, tb + 256);
   GTRY(hipStreamCreateWithFlags(&g->cs, hipStreamNonBlocking));
@@ -2799,8 +2831,8 @@ extern "C" int mbw_graph_create(mbw_ctx *c, const mbw_graph_plan *plan, int min_
   have = tb + 256;
   GTRY(prim::exclusive_sum((void *)temp, have, nwords, woff, N + 1, st));
   k_word_owner<<<grid_for(N), 256, 0, st>>>(woff, N, wread);
-  k_pack_words<<<(unsigned)((W + PACK_BLOCK - 1) / PACK_BLOCK), PACK_BLOCK, 0, st>>>(g->reads, B, offs, woff, wread, W, 0, pw, pn,
-                                                                                       offs + N, woff + N);
+  k_pack_words<<<(unsigned)((W + PACK_BLOCK - 1) / PACK_BLOCK), PACK_BLOCK, 0, st>>>(g->reads, B, offs, woff, wread, W,
+                                                                                       o.bs_role, pw, pn, offs + N, woff + N);
   // round 1: the staged bin in read order, the other reads longest first and in segments
   if (!binned) {
     k_make_queries<<<grid_for(N), 256, 0, st>>>(nullptr, N, offs, woff, (uint32_t)min_seed_len, (uint32_t)o.min_occ, q1);
@@ -2866,7 +2898,27 @@ extern "C" int mbw_graph_create(mbw_ctx *c, const mbw_graph_plan *plan, int min_
   k_expand_rows<<<grid_for((S + 63) / 64 * 64 / 4, 256, 65536u), 256, 0, st>>>(g->seeds, posoff, kpos, S, xrows, g->pos,
                                                                                  idx + S, X);
   k_locate_wave<<<gridL, 256, 0, st>>>(v, xrows, X, g->pos, rmask, rshift, ctl, posoff + S);
-  k_graph_counts<<<1, 64, 0, st>>>(ctl, idx + S, posoff + S, g->dio + 1, g->seg_counts[0], g->seg_counts[1]);
+  // bisulfite: the strand filter on the positions, then the refinement of every kept pair (as the
+  // eager path, over the position capacity)
+  if (o.bs_role) {
+    k_bs_mark<<<grid_for(X + 1), 256, 0, st>>>(g->pos, X, ix->len_r, o.bs_role, keep, posoff + S);
+    have = tb + 256;
+    GTRY(prim::exclusive_sum((void *)temp, have, keep, kidx, X + 1, st));
+    k_bs_compact<<<grid_for(X), 256, 0, st>>>(g->pos, keep, kidx, X, g->pos_kept);
+    k_bs_seeds<<<grid_for(S), 256, 0, st>>>(g->seeds, S, kidx, idx + S, X);
+  }
+  if (o.bs_refine) {
+    k_pos_seed<<<grid_for((S + 63) / 64 * 64 / 4, 256, 65536u), 256, 0, st>>>(g->seeds, S, ps, idx + S, X);
+    k_fill_u32<<<grid_for(X + 1), 256, 0, st>>>(pc, X + 1, 0u);
+    k_refine<<<grid_for(X), 256, 0, st>>>(g->seeds, ps, g->pos_kept, X, g->reads, offs, ix->orig, ix->len_r, o.bs_role,
+                                          min_seed_len, pc, nullptr, nullptr, kidx + X);
+    have = tb + 256;
+    GTRY(prim::exclusive_sum((void *)temp, have, pc, po, X + 1, st));
+    k_refine<<<grid_for(X), 256, 0, st>>>(g->seeds, ps, g->pos_kept, X, g->reads, offs, ix->orig, ix->len_r, o.bs_role,
+                                          min_seed_len, pc, po, g->pieces, kidx + X, PC);
+  }
+  k_graph_counts<<<1, 64, 0, st>>>(ctl, idx + S, posoff + S, g->dio + 1, g->seg_counts[0], g->seg_counts[1],
+                                   o.bs_role ? kidx + X : nullptr, o.bs_refine ? po + X : nullptr);
   GTRY(hipGetLastError());
   capturing = false;
   GTRY(hipStreamEndCapture(st, &g->graph));
@@ -2880,7 +2932,7 @@ extern "C" int mbw_graph_info(const mbw_graph *g, mbw_graph_plan *plan) {
   if (!g || !plan) { mbw_set_error("NULL argument"); return MBW_E_INVAL; }
   memset(plan, 0, sizeof(*plan));
   plan->max_reads = g->N; plan->max_bases = g->B; plan->max_seeds = g->S; plan->max_subqueries = g->Q;
-  plan->max_positions = g->X; plan->max_read_len = g->L;
+  plan->max_positions = g->X; plan->max_read_len = g->L; plan->max_pieces = g->PC;
   return MBW_OK;
 }
 
@@ -2930,8 +2982,8 @@ extern "C" int mbw_graph_seed(mbw_graph *g, const uint8_t *reads, const uint32_t
   TRY(hipGraphLaunch(g->exec, st));
   TRY(hipEventRecord(g->ev1, st));
   TRY(hipStreamSynchronize(st));
-  uint64_t cnt[C_COUNT + 4];
-  for (int t = 0; t < C_COUNT + 4; ++t) cnt[t] = ((volatile uint64_t *)g->hio)[1 + t];
+  uint64_t cnt[C_COUNT + 6];
+  for (int t = 0; t < C_COUNT + 6; ++t) cnt[t] = ((volatile uint64_t *)g->hio)[1 + t];
   if (cnt[C_ERR]) {
     mbw_set_error("kernel guard tripped (" + std::to_string(cnt[C_ERR]) + "): corrupt index or internal error");
     return MBW_E_HIP;
@@ -2945,12 +2997,19 @@ extern "C" int mbw_graph_seed(mbw_graph *g, const uint8_t *reads, const uint32_t
                   std::to_string(g->QS2) + " (seed it with mbw_seed, or use a larger plan)");
     return MBW_E_CAPACITY;
   }
+  if (g->refine && cnt[C_COUNT + 5] > g->PC) {
+    mbw_set_error("graph: the batch needs " + std::to_string(cnt[C_COUNT + 5]) + " refined pieces; the plan holds " +
+                  std::to_string(g->PC) + " (seed it with mbw_seed, or use a larger plan)");
+    return MBW_E_CAPACITY;
+  }
   float ms = 0;
   (void)hipEventElapsedTime(&ms, g->ev0, g->ev1);
   out->n_seeds = nu;
-  out->n_pos = n_pos;
+  out->n_pos = g->bs_role ? cnt[C_COUNT + 4] : n_pos;
   out->seeds = g->seeds;
-  out->pos = g->pos;
+  out->pos = g->bs_role ? g->pos_kept : g->pos;
+  out->n_pieces = g->refine ? cnt[C_COUNT + 5] : 0;
+  out->pieces = g->refine ? g->pieces : nullptr;
   out->lines_smem = cnt[C_LINES];
   out->lines_locate = cnt[C_LINES_LOC];
   out->steps = cnt[C_STEPS];

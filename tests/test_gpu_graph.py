@@ -201,3 +201,45 @@ def test_graph_length_bins_replays(small, ragged):
     assert e.value.code == mbw.MBW_E_INVAL
     g.free()
     ctx.free()
+
+
+def test_graph_bisulfite_filter_and_refinement():
+    """A 200 kbp four-copy bisulfite index, 2,000 directional reads in read-1 form and their read-2
+    image with planted C/G changes: for both roles, a graph with the strand filter and the seed
+    refinement gives the seeds, kept positions and pieces of mbw_seed (and the oracle's), replayed
+    twice on different batches with eager calls in between."""
+    ref = synth.reference(0, 200_000, 31)
+    idx = mbw.Index.build(ref.codes, sa_sample=8, kmer_k=10, bisulfite=True)
+    ox = oracle.OracleIndex(ref.codes, bisulfite=True, sa_rate=8)
+    rs = synth.reads_bisulfite(ref, 2000, seed=5)
+    seq2 = rs.seq.copy()
+    comp = bytes.maketrans(b"ACGT", b"TGCA")
+    for r in range(len(rs)):
+        a, b = int(rs.offsets[r]), int(rs.offsets[r + 1])
+        seq2[a:b] = np.frombuffer(rs.seq[a:b].tobytes().translate(comp)[::-1], np.uint8)
+    rng = np.random.default_rng(4)
+    for s_ in (rs.seq, seq2):
+        hit = rng.integers(0, s_.size, s_.size // 200)
+        s_[hit] = np.where(rng.random(hit.size) < 0.5, ord("C"), ord("G"))
+    ctx = mbw.Context(idx)
+    for role, seq in ((1, rs.seq), (2, seq2)):
+        full = synth.ReadSet(seq, rs.lengths, rs.offsets, rs.tpos, rs.tstrand)
+        for refine in (False, True):
+            g = ctx.graph(len(rs), bs_role=role, bs_refine=refine)
+            for b in (full, subset(full, range(0, 2000, 3))):
+                for rep in range(2):
+                    eager = ctx.seed(b.seq, b.lengths, bs_role=role, bs_refine=refine)
+                    e_p = eager.download_pieces() if refine else None
+                    torch.cuda.synchronize()
+                    out = g.seed(b.seq, b.lengths)
+                    s, p = same(out, eager)
+                    if refine:
+                        got = out.download_pieces()
+                        assert got.size == e_p.size > 0
+                        for f in got.dtype.names:
+                            assert np.array_equal(got[f], e_p[f]), f
+                    if b is full and rep == 0 and not refine:
+                        compare_with_oracle(s, p, ox.seed(b.seq, b.offsets, bs_role=role))
+            g.free()
+    ctx.free()
+    idx.free()
