@@ -452,6 +452,8 @@ class Graph:
         return {f: int(getattr(p, f)) for f, _ in GraphPlan._fields_}
 
     def seed(self, reads, lengths, stream=None) -> "SeedOutput":
+        if not self._h:
+            raise MbwError(MBW_E_INVAL, "graph already freed")
         n = int(lengths.numel() if hasattr(lengths, "numel") else len(lengths))
         if isinstance(lengths, np.ndarray):
             lengths = np.ascontiguousarray(lengths, dtype=np.uint32)
@@ -485,6 +487,7 @@ class Context:
         h = C.c_void_p()
         _check(self._lib.mbw_ctx_create(index._h, C.byref(h)))
         self._h = h
+        self._graphs = weakref.WeakSet()   # graphs of this context: freed before it
 
     def seed(self, reads, lengths, min_seed_len: int = 19, max_occ: int = 500, min_occ: int = 1,
              reseed: bool = True, reseed_len: int = 38, reseed_occ: int = 10, bs_role: int = 0,
@@ -606,7 +609,9 @@ class Context:
         h = C.c_void_p()
         _check(self._lib.mbw_graph_create(self._h, C.byref(plan), int(min_seed_len), int(max_occ),
                                           C.byref(self._opts(kw)), C.byref(h)))
-        return Graph(self, h)
+        g = Graph(self, h)
+        self._graphs.add(g)
+        return g
 
     def tune(self, reads, lengths, min_seed_len: int = 19, max_occ: int = 500, stream=None, cache=None,
              **base) -> dict:
@@ -657,6 +662,8 @@ class Context:
 
     def free(self):
         if self._h:
+            for g in list(self._graphs):   # a graph is freed before its context
+                g.free()
             self._lib.mbw_ctx_free(self._h)
             self._h = None
 
