@@ -196,6 +196,18 @@ def test_human_3gbp_sampled_parity():
     assert same_arrays(seeds_p, pos_p, seeds, pos)
     del seeds_p, pos_p
     log(f"plain kernel: same {out.n_seeds} seeds and {out.n_pos} positions ({time.time() - t0:.1f} s)")
+    # a captured graph planned for 20,000 reads returns the eager call's arrays on the first 20,000,
+    # replayed twice
+    sub20 = reads.subset(np.arange(20_000))
+    e20 = ctx.seed(sub20.seq, sub20.lengths, min_seed_len=19, max_occ=500)
+    es, ep = e20.download()
+    g20 = ctx.graph(20_000, min_seed_len=19, max_occ=500)
+    for _ in range(2):
+        gs, gp = g20.seed(sub20.seq, sub20.lengths).download()
+        assert same_arrays(gs, gp, es, ep)
+    g20.free()
+    del sub20, es, ep, gs, gp
+    log(f"captured graph: same arrays on 20,000 reads ({time.time() - t0:.1f} s)")
     # mate-rescue prefilter over the whole batch (a true-mate and a decoy window per pair, device
     # inputs, as the benchmark runs it); the oracle recomputes 1,200 sampled candidates
     cands, decoy = synth.rescue_candidates(reads, len(ref), decoys=True, seed=104)
