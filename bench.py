@@ -513,6 +513,16 @@ def serve_bs_leg(mbw, synth, ref, pl_idx, args):
     return res
 
 
+def gather_sweep(mbw):
+    """Random 128-byte lines per second of the gather probe at 1-8 waves per SIMD and with the full
+    grid ("full"): the rate depends on the number of requests in flight."""
+    out = {}
+    for w in (1, 2, 3, 4, 5, 6, 8, 0):
+        lps, _ = mbw.probe_gather(8 << 30, iters=32, waves_per_simd=w)
+        out["full" if w == 0 else str(w)] = round(lps)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -570,8 +580,10 @@ def main():
     if args.probe:
         ms = mbw.probe_copy(1 << 30)
         lps, gms = mbw.probe_gather(8 << 30, iters=32)
+        sweep = gather_sweep(mbw)
         print(json.dumps(dict(copy_bytes=1 << 30, copy_ms=round(ms, 3), copy_gbs=round(2 * (1 << 30) / ms / 1e6, 1),
-                              gather_lines_per_s=lps, gather_gbs_128=round(lps * 128 / 1e9, 1), gather_ms=round(gms, 3))))
+                              gather_lines_per_s=lps, gather_gbs_128=round(lps * 128 / 1e9, 1), gather_ms=round(gms, 3),
+                              gather_by_waves_per_simd=sweep)))
         return
     if args.workload == "serve_bs_3gbp":
         ref = synth.workload_reference("serve_bs_3gbp", args.ref_len or None)
@@ -581,7 +593,8 @@ def main():
         print(json.dumps(dict(res, value=sat, n_gpus=1, higher_is_better=True, data="synthetic", dtype="u64")),
               flush=True)
         return
-    gather_lps, _ = mbw.probe_gather(8 << 30, iters=32)
+    gather_by_waves = gather_sweep(mbw)
+    gather_lps = max(gather_by_waves.values())
     t0 = time.time()
     wl = synth.WORKLOADS[args.workload]
     args.ref_len = args.ref_len or wl["ref_len"]
@@ -685,7 +698,9 @@ def main():
                     whole_path_hbm_gbs=round((traffic * launches + loc_traffic) / (elapsed / args.steps) / 1e9, 1)
                     if traffic and loc_traffic else None,
                     random_line_ceiling=dict(lines_per_s=round(gather_lps), gbs=round(gather_lps * LINE_BYTES / 1e9, 1),
-                                             probe="one lane x 16 B per random 128-B line, 4 dependent chains per lane, 8 GiB buffer"),
+                                             by_waves_per_simd=gather_by_waves,
+                                             probe="one lane x 16 B per random 128-B line, 4 dependent chains per lane, "
+                                                   "8 GiB buffer; the best of 1-8 waves per SIMD and the full grid"),
                     frac_of_measured_ceiling=round(lines_smem / (ms_smem * 1e-3) / gather_lps, 3))
 
     cpu = None

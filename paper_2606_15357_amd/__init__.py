@@ -692,7 +692,7 @@ def _probe_library():
             raise ImportError(f"{path} is missing: build it with `python -m paper_2606_15357_amd.build`")
         P = C.CDLL(path)
         P.mbwprobe_copy.argtypes = [C.c_int, C.c_uint64, C.POINTER(C.c_float)]
-        P.mbwprobe_gather.argtypes = [C.c_int, C.c_uint64, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_float)]
+        P.mbwprobe_gather.argtypes = [C.c_int, C.c_uint64, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_float)]
         P.mbwprobe_last_error.restype = C.c_char_p
         _probe = P
     return _probe
@@ -710,11 +710,13 @@ def probe_copy(nbytes: int = 1 << 30, device: int = 0) -> float:
     return ms.value
 
 
-def probe_gather(nbytes: int = 16 << 30, iters: int = 64, device: int = 0):
+def probe_gather(nbytes: int = 16 << 30, iters: int = 64, waves_per_simd: int = 0, device: int = 0):
     """Random 128-byte lines served per second over a power-of-two buffer of at most `nbytes` (one
-    lane per line, four dependent chains per lane)."""
+    lane per line, four dependent chains per lane); `waves_per_simd` 1..8 launches that many blocks
+    of 256 threads per CU (0: 8,192 blocks), with the same number of fetches in every setting."""
     lps, ms = C.c_double(), C.c_float()
-    _probe_check(_probe_library().mbwprobe_gather(int(device), int(nbytes), int(iters), C.byref(lps), C.byref(ms)))
+    _probe_check(_probe_library().mbwprobe_gather(int(device), int(nbytes), int(iters), int(waves_per_simd),
+                                                  C.byref(lps), C.byref(ms)))
     return lps.value, ms.value
 
 

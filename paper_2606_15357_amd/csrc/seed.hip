@@ -438,6 +438,18 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
   __shared__ uint64_t stp[SMEM_WAVES][64];   // unique path: text position of P[i] (rarely read: kept in LDS)
   uint64_t *tpl = &stp[wv][lane];
   uint32_t wcnt = 0;              // unique path: LF steps taken (stage 4) or still to take (stage 7)
+  // this iteration's SMEM (at most one per lane) waits in LDS, in the parts of the lane's query
+  // record that were copied to registers when it was loaded: k, k' in the third word, i, j and the
+  // low half of s in the first (after the read id), the high half of s in the second
+  bool em = false;
+  auto put_emit = [&](int ei, int ej, uint64_t ek, uint64_t ekr, uint64_t es) {
+    em = true;
+    sq[wv][2][lane] = make_uint4((uint32_t)ek, (uint32_t)(ek >> 32), (uint32_t)ekr, (uint32_t)(ekr >> 32));
+    sq[wv][0][lane].y = (uint32_t)ei;
+    sq[wv][0][lane].z = (uint32_t)ej;
+    sq[wv][0][lane].w = (uint32_t)es;
+    sq[wv][1][lane].x = (uint32_t)(es >> 32);
+  };
   constexpr uint32_t WMIR = 1u << 31;
   // 1: the interval is (0, 0, n) and the k-mer shortcut is still to try (an integer except in the
   // staged kernel with the unique-match path, where a lane mask measured faster)
@@ -463,10 +475,8 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
     // ---- active lanes: stage transitions up to the next memory action
     int act = ACT_DONE, a = 0;
     uint32_t code = 0;
-    bool em = false;
+    em = false;
     bool dfr = false;             // DEFER: the match reached s = 1; it goes to the task list
-    Emit e;
-    e.i = 0; e.j = 0; e.k = 0; e.kr = 0; e.s = 0;
     if (st == ST_ACTIVE && --budget == 0) { atomicOr(&P.ctl[C_ERR], 1ull); st = ST_IDLE; }
     if (st == ST_ACTIVE) {
       for (;;) {
@@ -482,7 +492,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
           if (UNIQ && u == 7) {
             if (wcnt > 0) { act = ACT_LF; break; }
             if (SEG && segchk != 0 && i == (int)qbeg) { segchk = 0; kr = wrow; s = 1; u = 8; continue; }
-            em = true; e.i = i; e.j = j; e.k = k; e.kr = wrow; e.s = 1 | KNOWN_POS;
+            put_emit(i, j, k, wrow, 1 | KNOWN_POS);
             if (j == (int)qend) { act = ACT_DONE; break; }
             u = 3; k = 0; kr = 0; s = ix.n; fresh = 1;
             continue;
@@ -490,7 +500,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
           // u == 8: left check of a segment's first SMEM [qbeg, j) with interval (k, kr, s)
           a = base_at(i - 1);
           if (a <= 3) { act = ACT_BWD; break; }
-          em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s;   // P[i-1] matches nothing
+          put_emit(i, j, k, kr, s);   // P[i-1] matches nothing
           if (j == (int)qend) { act = ACT_DONE; break; }
           u = 3; k = 0; kr = 0; s = ix.n; fresh = 1;
           continue;
@@ -502,7 +512,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
           if (DEFER && !qe && s == 1) { dfr = true; act = ACT_DONE; break; }
           if (a > 3) {                                  // end of the query, or a non-ACGT base: SMEM [i, j)
             if (SEG && segchk != 0 && i == (int)qbeg) { segchk = 0; u = 8; continue; }
-            em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s;
+            put_emit(i, j, k, kr, s);
             if (qe) { act = ACT_DONE; break; }
             u = 3; k = 0; kr = 0; s = ix.n; fresh = 1;
             continue;
@@ -668,7 +678,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
         n_lines += two ? 2 : 1;
         ++n_steps;
         if (SEG && u == 8) {                              // left check: report unless P[i-1, j) occurs c times
-          if (ns < c) { em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s; }
+          if (ns < c) put_emit(i, j, k, kr, s);
           if (j == (int)qend) st = ST_IDLE;
           else { u = 3; k = 0; kr = 0; s = ix.n; fresh = 1; }
         } else if (ns >= c) {
@@ -680,7 +690,7 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
         } else if (SEG && segchk != 0 && i == (int)qbeg) {   // forward failure at a segment's first SMEM
           segchk = 0; u = 8;
         } else {                                          // forward failure: report, then stage 3 from j
-          em = true; e.i = i; e.j = j; e.k = k; e.kr = kr; e.s = s;
+          put_emit(i, j, k, kr, s);
           u = 3; k = 0; kr = 0; s = ix.n; fresh = 1;
         }
       }
@@ -758,14 +768,22 @@ __global__ void __launch_bounds__(64 * SMEM_WAVES) __attribute__((amdgpu_waves_p
       }
       st = ST_ACTIVE;
     }
-    wave_emit(P, lane, em, q_read_id(), e, wout, q_rlen(), q_wo(), tpl);
-    if (DEFER && __ballot(dfr)) {                       // the query's record is still in LDS
+    {
+      Emit e = {0, 0, 0, 0, 0};
+      if (em) {
+        const uint4 r0 = sq[wv][0][lane], r2 = sq[wv][2][lane];
+        e.i = r0.y; e.j = r0.z; e.s = ((uint64_t)sq[wv][1][lane].x << 32) | r0.w;
+        e.k = ((uint64_t)r2.y << 32) | r2.x; e.kr = ((uint64_t)r2.w << 32) | r2.z;
+      }
+      wave_emit(P, lane, em, q_read_id(), e, wout, q_rlen(), q_wo(), tpl);
+    }
+    if (DEFER && __ballot(dfr)) {                       // its read id, length and word offset are still in LDS
       const uint64_t ts = wave_slot(dfr, tkb, tke, &P.ctl[C_PASSQ], lane);
       if (dfr && ts < P.task_cap) {
         const uint4 q0 = sq[wv][0][lane], q1 = sq[wv][1][lane];
         UTask t;
-        t.read_id = q0.x; t.qbeg = q0.y; t.qend = q0.z; t.l = q0.w;
-        t.c = q1.x; t.rlen = q1.y; t.woff_lo = q1.z; t.woff_hi = q1.w;
+        t.read_id = q0.x; t.qbeg = qbeg; t.qend = qend; t.l = l;
+        t.c = c; t.rlen = q1.y; t.woff_lo = q1.z; t.woff_hi = q1.w;
         t.i = (uint32_t)i; t.j = (uint32_t)j; t.pad0 = 0; t.pad1 = 0; t.k = k; t.kr = kr;
         P.tasks[ts] = t;
       }
@@ -1547,13 +1565,14 @@ extern "C" void mbw_ctx_free(mbw_ctx *c) {
 // is bound by its longest chains of dependent loads: more waves per SIMD only slow each one
 // (they share the SIMD) and add same-address atomics on the work counter, which serialise.
 static int persistent_grid(const void *kern, int block, size_t lds, int n_cu, int per_cu_req, uint64_t work,
-                           uint64_t per_block) {
+                           uint64_t per_block, int auto_max = 0) {
   int per = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, block, lds) != hipSuccess || per < 1) per = 4;
   int want = per_cu_req;
   if (want == 0) {
     const uint64_t unit = per_block * (uint64_t)n_cu;
-    want = (int)std::min<uint64_t>((uint64_t)per, std::max<uint64_t>(1, (work + unit - 1) / unit));
+    const int cap = auto_max > 0 ? std::min(per, auto_max) : per;
+    want = (int)std::min<uint64_t>((uint64_t)cap, std::max<uint64_t>(1, (work + unit - 1) / unit));
   }
   if (want > 0 && want < per) per = want;
   return per * n_cu;
@@ -1564,6 +1583,10 @@ static int persistent_grid(const void *kern, int block, size_t lds, int n_cu, in
 #define AUTO_QUERIES_R1 1200
 #define AUTO_QUERIES_R2 4000
 #define AUTO_ROWS_LOCATE 24000
+// ... and at most 4 locate blocks (4 waves per SIMD) per CU: on the 3.1 Gbp index the random line
+// reads of the walks complete faster with 4 waves per SIMD than with the 8 the registers allow
+// (36.7 ms against 43.5 ms for 442 M rows; 5, 6 and 8 waves: 39.4, 41.4, 43.2 ms)
+#define AUTO_LOCATE_MAX_PER_CU 4
 
 template <bool STAGED, bool UNIQ, bool DEFER = false>
 static int wave_grid(mbw_ctx *c, const SeedParams &P, const mbw_seed_opts &o) {
@@ -2184,7 +2207,8 @@ static int seed_impl(mbw_ctx *c, const uint8_t *reads, const uint32_t *lengths, 
       k_expand_rows<<<grid_for((nu + 63) / 64 * 64 / 4, 256, 65536u), 256, 0, st>>>(seeds, posoff, (const uint64_t *)c->kpos.p,
                                                                                      nu, (uint64_t *)c->xrows.p, posbuf);
       TRY(hipGetLastError());
-      const int grid = persistent_grid((const void *)k_locate_wave, 256, 0, c->n_cu, o.blocks_per_cu, n_pos, AUTO_ROWS_LOCATE);
+      const int grid = persistent_grid((const void *)k_locate_wave, 256, 0, c->n_cu, o.blocks_per_cu, n_pos, AUTO_ROWS_LOCATE,
+                                     AUTO_LOCATE_MAX_PER_CU);
       TRY(hipEventRecord(c->ev[3], st));
       k_locate_wave<<<grid, 256, 0, st>>>(v, (const uint64_t *)c->xrows.p, n_pos, posbuf, rmask, rshift, ctl);
       TRY(hipGetLastError());
@@ -2817,7 +2841,8 @@ extern "C" int mbw_graph_create(mbw_ctx *c, const mbw_graph_plan *plan, int min_
   uint32_t rmask = (ix->sa_sample & (ix->sa_sample - 1)) == 0 ? (uint32_t)(ix->sa_sample - 1) : 0u;
   int rshift = -1;
   if ((ix->sa_sample & (ix->sa_sample - 1)) == 0) { rshift = 0; while ((1 << rshift) < ix->sa_sample) ++rshift; }
-  const int gridL = persistent_grid((const void *)k_locate_wave, 256, 0, c->n_cu, o.blocks_per_cu, X, AUTO_ROWS_LOCATE);
+  const int gridL = persistent_grid((const void *)k_locate_wave, 256, 0, c->n_cu, o.blocks_per_cu, X, AUTO_ROWS_LOCATE,
+                                     AUTO_LOCATE_MAX_PER_CU);
   const int bs = 64 * SMEM_WAVES;
   hipStream_t st = g->cs;
   GTRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));

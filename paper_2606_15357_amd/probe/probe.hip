@@ -7,10 +7,14 @@
 // mbwprobe_last_error()):
 //   int mbwprobe_copy(int device, uint64_t bytes, float *ms)
 //       streams `bytes` bytes (>= 4096) from one buffer to another once; *ms = kernel time.
-//   int mbwprobe_gather(int device, uint64_t bytes, int iters, double *lines_per_s, float *ms)
+//   int mbwprobe_gather(int device, uint64_t bytes, int iters, int waves_per_simd, double *lines_per_s,
+//                       float *ms)
 //       every lane follows four chains of random 128-byte lines (16 bytes read per line) over the
 //       largest power-of-two number of lines that fits in `bytes` (>= 1 MiB), `iters` dependent
-//       fetches per chain; *lines_per_s = random lines served per second.
+//       fetches per chain; *lines_per_s = random lines served per second.  waves_per_simd 0: 8,192
+//       blocks of 256 threads (as many waves as the CUs hold); 1..8: that many blocks per CU, i.e.
+//       that many waves per SIMD, each lane taking 8192 / (blocks) times `iters` fetches per chain so
+//       that every setting makes the same number of fetches.
 // Both allocate and free their own device memory.
 #include <hip/hip_runtime.h>
 
@@ -84,13 +88,26 @@ extern "C" int mbwprobe_copy(int device, uint64_t bytes, float *ms) {
   return rc;
 }
 
-extern "C" int mbwprobe_gather(int device, uint64_t bytes, int iters, double *lines_per_s, float *ms) {
-  if (!lines_per_s || !ms || bytes < (1u << 20) || iters < 1) { set_error("bad probe arguments"); return -1; }
+extern "C" int mbwprobe_gather(int device, uint64_t bytes, int iters, int waves_per_simd, double *lines_per_s,
+                               float *ms) {
+  if (!lines_per_s || !ms || bytes < (1u << 20) || iters < 1 || waves_per_simd < 0 || waves_per_simd > 8) {
+    set_error("bad probe arguments");
+    return -1;
+  }
   TRY(hipSetDevice(device));
   uint64_t nlines = 1;                                   // a power of two, at most bytes / 128 and 2^32
   while (nlines * 2 <= bytes / 128 && nlines < (1ull << 32)) nlines *= 2;
   const uint32_t mask = (uint32_t)(nlines - 1);
-  const int grid = 8192, block = 256;
+  const int block = 256;
+  int grid = 8192;
+  if (waves_per_simd > 0) {
+    int n_cu = 0;
+    TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device));
+    grid = std::max(1, n_cu) * waves_per_simd;
+    const int64_t it = (int64_t)iters * 8192 / grid;
+    if (it > (1 << 24)) { set_error("bad probe arguments"); return -1; }
+    iters = (int)std::max<int64_t>(1, it);
+  }
   uint4 *buf = nullptr;
   uint64_t *out = nullptr;
   TRY(hipMalloc((void **)&buf, nlines * 128));
