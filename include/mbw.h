@@ -165,7 +165,8 @@ typedef struct {
                          most the occupancy limit), -1 the occupancy limit, 0 sized per launch by
                          its work (about one block per CU per 1,200 round-1 queries, 4,000
                          round-2 queries or 24,000 positions to locate, up to the occupancy
-                         limit: small batches run faster on fewer waves) */
+                         limit, and up to 4 blocks for locate: small batches run faster on fewer
+                         waves, and locate on large ones with 4 waves per SIMD rather than 8) */
   int no_stage;       /* 1: do not stage reads of <= 160 bases in LDS */
   int unique_ext;     /* 1: when the index holds the text and inverse-SA samples, a forward
                          extension whose interval has s = 1 continues by comparing the read with
