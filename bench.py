@@ -74,9 +74,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel: str, launches_bytes: float, isa_sample: int):
-    """HBM bytes per launch of `kernel` from the committed counter summary, if it was taken on the
-    current kernel sources with the same inverse-SA sampling step (else None)."""
+def profile_entry(kernel: str, isa_sample: int):
+    """The committed counter summary's entry for `kernel`, if it was taken on the current kernel
+    sources with the same inverse-SA sampling step (else None)."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -86,10 +86,30 @@ def traffic_from_profile(kernel: str, launches_bytes: float, isa_sample: int):
         return None
     if d.get("source_hash") != kernel_source_hash() or d.get("isa_sample") != isa_sample:
         return None
-    k = d.get("kernels", {}).get(kernel)
-    if not k:
+    return d.get("kernels", {}).get(kernel) or None
+
+
+def traffic_from_profile(kernel: str, launches_bytes: float, isa_sample: int):
+    """HBM bytes per launch of `kernel` from the committed counter summary (see profile_entry)."""
+    k = profile_entry(kernel, isa_sample)
+    return k.get("hbm_bytes_per_launch") if k else None
+
+
+def transactions(smem_entry, loc_entry, ms_smem_step: float, ms_loc: float, ceiling_lps: float):
+    """L2 hit rates and HBM read-request rates (one request moves a 128-byte line) of the SMEM
+    rounds and locate from the committed counter summary, over this run's kernel times, against the
+    random-gather probe's rate; None without a matching summary."""
+    if not smem_entry or not loc_entry or "l2" not in smem_entry or "l2" not in loc_entry:
         return None
-    return k.get("hbm_bytes_per_launch")
+    sreq = sum(smem_entry["l2"]["hbm_read_requests_by_round"])
+    lreq = loc_entry["l2"]["hbm_read_requests_per_launch"]
+    s_ps, l_ps = sreq / (ms_smem_step * 1e-3), lreq / (ms_loc * 1e-3)
+    return dict(smem=dict(l2_hit_rate_by_round=smem_entry["l2"]["hit_rate_by_round"], hbm_read_requests_per_step=sreq,
+                          requests_per_s=round(s_ps), frac_of_probe=round(s_ps / ceiling_lps, 3)),
+                locate=dict(l2_hit_rate=loc_entry["l2"]["hit_rate"], hbm_read_requests_per_launch=lreq,
+                            requests_per_s=round(l_ps), frac_of_probe=round(l_ps / ceiling_lps, 3)),
+                source="profiles/traffic.json (rocprofv3 TCC counters of one step); rates over this run's kernel "
+                       "times; frac_of_probe against random_line_ceiling.lines_per_s")
 
 
 def cpu_baseline(workload: str, ref_codes, n_pairs: int, window: int, threads: int):
@@ -701,7 +721,9 @@ def main():
                                              by_waves_per_simd=gather_by_waves,
                                              probe="one lane x 16 B per random 128-B line, 4 dependent chains per lane, "
                                                    "8 GiB buffer; the best of 1-8 waves per SIMD and the full grid"),
-                    frac_of_measured_ceiling=round(lines_smem / (ms_smem * 1e-3) / gather_lps, 3))
+                    frac_of_measured_ceiling=round(lines_smem / (ms_smem * 1e-3) / gather_lps, 3),
+                    transactions=transactions(profile_entry("smem", args.isa_sample),
+                                              profile_entry("locate", args.isa_sample), ms_smem, ms_loc, gather_lps))
 
     cpu = None
     if not args.no_cpu:
