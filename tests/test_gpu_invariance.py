@@ -56,6 +56,10 @@ def test_every_schedule_matches_the_oracle(setup):
         out = ctx.seed(reads.seq, reads.lengths, stage=stage, blocks_per_cu=bpc, seg_len=seg, unique_ext=uniq)
         s, p = out.download()
         compare_with_oracle(s, p, exp)
+    for bpc in (4, 8):   # locate's automatic cap, and its occupancy limit (the SMEM kernel stops at 4)
+        out = ctx.seed(reads.seq, reads.lengths, blocks_per_cu=bpc)
+        s, p = out.download()
+        compare_with_oracle(s, p, exp)
     for chunk in (1, 7, 64, 256):
         out = ctx.seed(reads.seq, reads.lengths, wave_chunk=chunk)
         s, p = out.download()
